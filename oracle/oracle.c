@@ -1,0 +1,219 @@
+/*
+ * FP64 CPU oracle for the octree gravity force path -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * call this file.  It shares no code, header or constant with the HIP library.
+ * Every loop is plain, in a fixed order, in double precision, with no blocking
+ * or vector intrinsics; the outer loop over target particles may run on
+ * several OpenMP threads (each target's sum is still taken in list order).
+ *
+ * Units: G = 1.  Softening is Plummer's: a source of mass m at y acts on a
+ * target at x with
+ *     acceleration  m (y - x) (|y - x|^2 + eps^2)^(-3/2)
+ *     potential    -m (|y - x|^2 + eps^2)^(-1/2).
+ * The paper only says that particle-particle interactions use a
+ * gravitational softening length (Sec. 3.4, description of the r_b slot);
+ * the Plummer form is the reading taken here.
+ *
+ *   oracle_direct      O(N^2) direct summation over all j != i (Sec. 2: the
+ *                      brute-force method the tree replaces).
+ *   oracle_list_force  the same sums over a group's interaction list, where
+ *                      index e < n is particle e and index e >= n is cell
+ *                      e - n acting as a virtual particle of mass M_c at its
+ *                      centre of mass (monopole, Sec. 2; unified particle/cell
+ *                      index space, Sec. 3.2).  The target's own entry is
+ *                      skipped (self pair excluded).  Optionally each cell
+ *                      entry also carries a symmetric tensor Qt (6 numbers per
+ *                      (group, cell) pair) whose quadrupole-form field is added:
+ *                          phi_Q = -1/2 d^T Qt d r^-5,
+ *                          a_Q   = Qt d r^-5 - 5/2 (d^T Qt d) d r^-7,
+ *                      with d = x - COM_c and r^2 = |d|^2 + eps^2.  This is the
+ *                      quadrupole term of the multipole expansion the paper
+ *                      names (orders up to p = 3, Sec. 2), softened like the
+ *                      monopole.
+ *
+ * Build: gcc -O2 -fopenmp -shared -fPIC oracle.c -o liboracle.so -lm
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+
+/* one softened source acting on one target: adds to a[3] and *phi */
+static void pair_monopole(const double x[3], const double y[3], double m, double eps2,
+                          double a[3], double *phi)
+{
+    double dx = y[0] - x[0];
+    double dy = y[1] - x[1];
+    double dz = y[2] - x[2];
+    double r2 = dx * dx + dy * dy + dz * dz + eps2;
+    double r = sqrt(r2);
+    double inv_r = 1.0 / r;
+    double inv_r3 = inv_r / r2;
+    a[0] += m * dx * inv_r3;
+    a[1] += m * dy * inv_r3;
+    a[2] += m * dz * inv_r3;
+    *phi -= m * inv_r;
+}
+
+/* quadrupole-form field of tensor q = (xx, yy, zz, xy, xz, yz) centred at c */
+static void pair_quadrupole(const double x[3], const double c[3], const double q[6], double eps2,
+                            double a[3], double *phi)
+{
+    double d[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps2;
+    double inv_r2 = 1.0 / r2;
+    double inv_r = sqrt(inv_r2);
+    double inv_r5 = inv_r * inv_r2 * inv_r2;
+    double inv_r7 = inv_r5 * inv_r2;
+    /* Qd */
+    double qd[3];
+    qd[0] = q[0] * d[0] + q[3] * d[1] + q[4] * d[2];
+    qd[1] = q[3] * d[0] + q[1] * d[1] + q[5] * d[2];
+    qd[2] = q[4] * d[0] + q[5] * d[1] + q[2] * d[2];
+    double dqd = d[0] * qd[0] + d[1] * qd[1] + d[2] * qd[2];
+    for (int k = 0; k < 3; k++)
+        a[k] += qd[k] * inv_r5 - 2.5 * dqd * d[k] * inv_r7;
+    *phi += -0.5 * dqd * inv_r5;
+}
+
+/*
+ * Direct sum.  pos[n][3], mass[n]; targets tgt[n_tgt] (NULL = all particles,
+ * then n_tgt must equal n).  Writes acc[n_tgt][3], pot[n_tgt].
+ */
+void oracle_direct(int64_t n, const double *pos, const double *mass, double eps,
+                   int64_t n_tgt, const int64_t *tgt, double *acc, double *pot)
+{
+    double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < n_tgt; t++) {
+        int64_t i = tgt ? tgt[t] : t;
+        double a[3] = {0.0, 0.0, 0.0};
+        double phi = 0.0;
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i)
+                continue;
+            pair_monopole(&pos[3 * i], &pos[3 * j], mass[j], eps2, a, &phi);
+        }
+        acc[3 * t + 0] = a[0];
+        acc[3 * t + 1] = a[1];
+        acc[3 * t + 2] = a[2];
+        pot[t] = phi;
+    }
+}
+
+/* group containing particle i: largest g with group_off[g] <= i */
+static int64_t find_group(int64_t n_groups, const int64_t *group_off, int64_t i)
+{
+    int64_t lo = 0, hi = n_groups - 1;
+    while (lo < hi) {
+        int64_t mid = (lo + hi + 1) / 2;
+        if (group_off[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+/*
+ * List force.  Particles pos[n][3], mass[n]; groups are the ranges
+ * [group_off[g], group_off[g+1]) of particle indices; group g's list is
+ * list_idx[list_off[g] .. list_off[g+1]).  Cells: cell_com[n_cells][3],
+ * cell_mass[n_cells].  Optional quadrupole-form tensors: the first
+ * n_cellent[g] entries of a group's list are its cells and the k-th of them
+ * uses quad[(pair_off[g] + k) * 6 ...]; pass quad = NULL for monopole only.
+ * Targets tgt[n_tgt] (NULL = all particles).  Returns 0, or -1 if an index
+ * is out of range or a cell tensor is requested for a particle entry.
+ */
+int oracle_list_force(int64_t n, const double *pos, const double *mass,
+                      int64_t n_groups, const int64_t *group_off,
+                      const int64_t *list_off, const int64_t *list_idx,
+                      int64_t n_cells, const double *cell_com, const double *cell_mass,
+                      const int64_t *n_cellent, const int64_t *pair_off, const double *quad,
+                      double eps, int64_t n_tgt, const int64_t *tgt,
+                      double *acc, double *pot)
+{
+    double eps2 = eps * eps;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
+    for (int64_t t = 0; t < n_tgt; t++) {
+        int64_t i = tgt ? tgt[t] : t;
+        int64_t g = find_group(n_groups, group_off, i);
+        double a[3] = {0.0, 0.0, 0.0};
+        double phi = 0.0;
+        for (int64_t k = list_off[g]; k < list_off[g + 1]; k++) {
+            int64_t e = list_idx[k];
+            int64_t kk = k - list_off[g];
+            if (e < 0 || e >= n + n_cells) {
+                bad = 1;
+                continue;
+            }
+            if (e < n) {
+                if (quad && kk < n_cellent[g])
+                    bad = 1;
+                if (e == i)
+                    continue;
+                pair_monopole(&pos[3 * i], &pos[3 * e], mass[e], eps2, a, &phi);
+            } else {
+                int64_t c = e - n;
+                pair_monopole(&pos[3 * i], &cell_com[3 * c], cell_mass[c], eps2, a, &phi);
+                if (quad) {
+                    if (kk >= n_cellent[g]) {
+                        bad = 1;
+                        continue;
+                    }
+                    pair_quadrupole(&pos[3 * i], &cell_com[3 * c], &quad[6 * (pair_off[g] + kk)],
+                                    eps2, a, &phi);
+                }
+            }
+        }
+        acc[3 * t + 0] = a[0];
+        acc[3 * t + 1] = a[1];
+        acc[3 * t + 2] = a[2];
+        pot[t] = phi;
+    }
+    return bad ? -1 : 0;
+}
+
+/*
+ * Exact field of a set of sources at arbitrary points: for each target point
+ * x[t], sum over sources src_idx[src_off[t] .. src_off[t+1]) of the softened
+ * monopole field (no self exclusion: the targets are points, not particles).
+ * Used to compute the exact field of a cell's particles (the truth the
+ * learned correction is fitted to).
+ */
+void oracle_point_field(int64_t n_pts, const double *x, const int64_t *src_off,
+                        const int64_t *src_idx, const double *pos, const double *mass,
+                        double eps, double *acc, double *pot)
+{
+    double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t t = 0; t < n_pts; t++) {
+        double a[3] = {0.0, 0.0, 0.0};
+        double phi = 0.0;
+        for (int64_t k = src_off[t]; k < src_off[t + 1]; k++) {
+            int64_t j = src_idx[k];
+            pair_monopole(&x[3 * t], &pos[3 * j], mass[j], eps2, a, &phi);
+        }
+        acc[3 * t + 0] = a[0];
+        acc[3 * t + 1] = a[1];
+        acc[3 * t + 2] = a[2];
+        pot[t] = phi;
+    }
+}
+
+/* quadrupole-form field alone at points (used to test it against -grad phi) */
+void oracle_quad_field(int64_t n_pts, const double *x, const double *centre, const double *quad,
+                       double eps, double *acc, double *pot)
+{
+    double eps2 = eps * eps;
+    for (int64_t t = 0; t < n_pts; t++) {
+        double a[3] = {0.0, 0.0, 0.0};
+        double phi = 0.0;
+        pair_quadrupole(&x[3 * t], &centre[3 * t], &quad[6 * t], eps2, a, &phi);
+        acc[3 * t + 0] = a[0];
+        acc[3 * t + 1] = a[1];
+        acc[3 * t + 2] = a[2];
+        pot[t] = phi;
+    }
+}

@@ -1,0 +1,94 @@
+"""Pins of the FP64 list force (oracle_list_force) and its quadrupole-form term.
+
+* a cell entry whose moments are one particle's is that particle;
+* a monopole at the centre of mass approximates a cell with an error that
+  falls as (l/D)^2 (no dipole about the COM); adding the textbook quadrupole
+  Q = 3S - tr(S) I makes it fall as (l/D)^3 -- this fixes the sign and the
+  form of the quadrupole term;
+* the quadrupole-form acceleration is minus the gradient of its potential;
+* malformed lists are rejected.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as omlp
+
+
+def _cluster(seed, n=40, size=0.1):
+    rng = np.random.default_rng(seed)
+    p = rng.uniform(-size / 2, size / 2, (n, 3)) * np.array([1.0, 0.6, 0.3])
+    m = rng.uniform(0.5, 1.5, n)
+    com = (m[:, None] * p).sum(0) / m.sum()
+    r = p - com
+    S = (m[:, None, None] * r[:, :, None] * r[:, None, :]).sum(0)
+    return p, m, com, m.sum(), np.array([S[0, 0], S[1, 1], S[2, 2], S[0, 1], S[0, 2], S[1, 2]])
+
+
+def test_cell_entry_equals_particle():
+    rng = np.random.default_rng(1)
+    pos = rng.normal(size=(10, 3))
+    m = rng.uniform(0.5, 1.5, 10)
+    # one group of all particles; list: particles 0..8 and particle 9 as a cell
+    go = [0, 10]
+    a_ref, p_ref = oracle.list_force(pos, m, go, [0, 10], np.arange(10), np.zeros((0, 3)), [], 0.01)
+    a, p = oracle.list_force(pos, m, go, [0, 10], list(range(9)) + [10], pos[9:10], m[9:10], 0.01)
+    # target 9 sees itself as a cell at distance 0: remove that row
+    np.testing.assert_allclose(a[:9], a_ref[:9], rtol=1e-14)
+    np.testing.assert_allclose(p[:9], p_ref[:9], rtol=1e-14)
+
+
+def _monopole_and_quad_errors(D, direction, eps=0.0):
+    p, m, com, M, S6 = _cluster(3)
+    x = com + D * direction
+    a_ex, _ = oracle.point_field(x[None], [0, len(m)], np.arange(len(m)), p, m, eps)
+    # monopole through the list sum: one target particle of zero mass, one cell entry
+    pos = np.vstack([x[None], p])
+    mass = np.concatenate([[0.0], m])
+    a_mono, _ = oracle.list_force(pos, mass, [0, 1, 1 + len(m)], [0, 1, 1], [1 + len(m)],
+                                  com[None], [M], eps, tgt=[0])
+    Q = omlp.exact_quadrupole(S6[None])
+    a_mq, _ = oracle.list_force(pos, mass, [0, 1, 1 + len(m)], [0, 1, 1], [1 + len(m)],
+                                com[None], [M], eps, tgt=[0], n_cellent=[1, 0], quad=Q)
+    n = np.linalg.norm(a_ex)
+    return np.linalg.norm(a_mono - a_ex) / n, np.linalg.norm(a_mq - a_ex) / n
+
+
+@pytest.mark.parametrize("direction", [np.array([1.0, 0, 0]), np.array([0.3, -0.5, 0.81])])
+def test_multipole_convergence_orders(direction):
+    direction = direction / np.linalg.norm(direction)
+    e1m, e1q = _monopole_and_quad_errors(1.0, direction)
+    e2m, e2q = _monopole_and_quad_errors(2.0, direction)
+    # monopole error ~ D^-2 relative; with the quadrupole ~ D^-3
+    assert e1m / e2m == pytest.approx(4.0, rel=0.08)
+    assert e1q / e2q == pytest.approx(8.0, rel=0.12)
+    assert e1q < 0.2 * e1m
+
+
+def test_quad_field_is_minus_gradient():
+    rng = np.random.default_rng(5)
+    c = np.zeros(3)
+    q = rng.normal(size=6)
+    q[2] = -q[0] - q[1]
+    for eps in (0.0, 0.3):
+        x = rng.normal(size=3) * 2
+        a, _ = oracle.quad_field(x[None], c[None], q[None], eps)
+        h = 1e-5
+        grad = np.zeros(3)
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = h
+            _, pp = oracle.quad_field((x + e)[None], c[None], q[None], eps)
+            _, pm = oracle.quad_field((x - e)[None], c[None], q[None], eps)
+            grad[k] = (pp[0] - pm[0]) / (2 * h)
+        np.testing.assert_allclose(a[0], -grad, rtol=1e-7, atol=1e-12)
+
+
+def test_bad_lists_rejected():
+    pos = np.zeros((2, 3))
+    pos[1, 0] = 1
+    with pytest.raises(ValueError):
+        oracle.list_force(pos, [1, 1], [0, 2], [0, 1], [5], np.zeros((1, 3)), [1.0], 0.1)
+    with pytest.raises(ValueError):   # particle entry where a cell tensor is promised
+        oracle.list_force(pos, [1, 1], [0, 2], [0, 2], [0, 1], np.zeros((1, 3)), [1.0], 0.1,
+                          n_cellent=[1], quad=np.zeros((1, 6)))
