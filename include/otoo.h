@@ -1,0 +1,224 @@
+/*
+ * otoo.h -- C ABI of the MI355X octree gravity force library (libotoo.so).
+ *
+ * The library evaluates, for every group of target particles produced by a
+ * grouped tree walk, the Plummer-softened acceleration and potential summed
+ * over the group's interaction list of particles and monopole cell moments:
+ * the force evaluation that the paper hands to the GPU (Sec. 3.4, with the
+ * octree method of Sec. 2).  G = 1 throughout.  A source of mass m at y acts
+ * on a target at x with
+ *     acceleration  m (y - x) (|y - x|^2 + eps^2)^(-3/2)
+ *     potential    -m (|y - x|^2 + eps^2)^(-1/2)
+ * and the target's own entry (the self pair) is excluded.
+ *
+ * Two halves:
+ *   host  (C++/OpenMP, host pointers): tree build, cell moments, grouped walk
+ *         -> the interaction-list CSR;
+ *   device (HIP, gfx950, device pointers): the force evaluation and the
+ *         learned cell correction (network inference and training).
+ *
+ * Conventions
+ *   - every function returns OTOO_OK (0) or a negative otoo_status;
+ *     nothing throws across the ABI;
+ *   - device entry points are asynchronous on the context's stream; device
+ *     outputs are valid once that stream has synchronised;
+ *   - inputs are never modified; outputs are fully overwritten;
+ *   - device pointers belong to the caller; a context owns only its own
+ *     scratch memory, grown on demand and freed by otoo_destroy;
+ *   - on a non-zero return, otoo_last_error(ctx) names the problem.
+ */
+#ifndef OTOO_H
+#define OTOO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum otoo_status {
+    OTOO_OK = 0,
+    OTOO_EINVAL = -1,      /* bad argument (null pointer, size, eps, stride, ...) */
+    OTOO_ENOMEM = -2,      /* host or device allocation failed, or the scratch cap was hit */
+    OTOO_EHIP = -3,        /* a HIP runtime call failed; otoo_last_error has its message */
+    OTOO_EUNSUPPORTED = -4 /* option not available in this build */
+};
+
+/* Largest group (number of target particles sharing one list) the device
+ * kernels accept; a workgroup holds the whole group in registers. */
+#define OTOO_MAX_GROUP 256
+/* Opening angles at or above 2/sqrt(3) could accept a cell that holds one of
+ * the group's own particles; the walk rejects them (see otoo_tree_walk). */
+#define OTOO_THETA_LIMIT 1.15
+
+/* ======================================================================
+ * Host half: tree build and grouped walk
+ * ====================================================================== */
+
+typedef struct otoo_tree otoo_tree;
+
+/* Build the octree of n particles (Sec. 3.2: root cube from the bounding
+ * box, 21-bit-per-axis integer coordinates turned into Hilbert keys, parallel
+ * sort, cells read off equal key prefixes; a cell with at most n_crit
+ * particles, or at depth 21, is a leaf) and its cell moments (Sec. 3.3: mass,
+ * centre of mass, second-moment tensor S with trace B2 of Eq. (2), b_max).
+ *   pos   [n][3] FP64, original order (host)      mass [n] FP64, >= 0
+ *   n     1 .. 2^30                               n_crit >= 1 (the paper uses 16)
+ *   *tree receives a handle freed by otoo_tree_free.
+ * EINVAL for null pointers, bad sizes, non-finite coordinates or negative
+ * masses; ENOMEM when host memory runs out. */
+int otoo_tree_build(const double* pos, const double* mass, int64_t n, int32_t n_crit, otoo_tree** tree);
+void otoo_tree_free(otoo_tree* tree);
+
+/* Sizes and root cube.  Any output pointer may be NULL. */
+int otoo_tree_info(const otoo_tree* tree, int64_t* n, int64_t* n_cells, int32_t* depth,
+                   double* root_lo /*[3]*/, double* root_side);
+
+/* Copy out the device-ready arrays (host buffers owned by the caller; NULL skips):
+ *   perm     [n]        sorted position k holds original particle perm[k]
+ *   pos32    [n][3]     FP32 positions in key (group) order
+ *   mass32   [n]        FP32 masses in key order
+ *   cell_mom [n_cells][stride], stride 4: COM xyz, M;
+ *            stride 12: COM xyz, M, side l, S (xx, yy, zz, xy, xz, yz), 0. */
+int otoo_tree_export(const otoo_tree* tree, int64_t* perm, float* pos32, float* mass32, float* cell_mom,
+                     int32_t stride);
+
+/* FP64 cell data in preorder (host buffers, NULL skips): first particle and
+ * count in key order, level, integer cube coordinates ijk [n_cells][3] at that
+ * level, COM [n_cells][3], mass, side, offset s = |COM - centre|,
+ * S [n_cells][6], b_max. */
+int otoo_tree_cells(const otoo_tree* tree, int64_t* first, int64_t* count, int32_t* level, int64_t* ijk,
+                    double* com, double* mass, double* side, double* s, double* S6, double* bmax);
+
+/* The next/more links over the unified index space [0, n + n_cells)
+ * (Sec. 2.1; index u < n is particle u in key order, u >= n is cell u - n;
+ * -1 is null). */
+int otoo_tree_links(const otoo_tree* tree, int64_t* next, int64_t* more);
+
+enum otoo_mac {
+    OTOO_MAC_BH = 0,       /* accept iff d_min > l/theta + s  (opening angle theta, COM offset s) */
+    OTOO_MAC_ABSOLUTE = 1  /* accept iff d_min > r_b of Eq. (1); r_b = 2 * root side above m_limit */
+};
+enum otoo_group_mode {
+    OTOO_GROUP_CHUNK = 0,  /* consecutive runs of g_max particles in key order */
+    OTOO_GROUP_CELL = 1    /* maximal cells holding at most g_max particles */
+};
+
+typedef struct {
+    int32_t mac;          /* otoo_mac */
+    double theta;         /* BH: 0 <= theta < OTOO_THETA_LIMIT (0 opens every cell) */
+    double delta;         /* ABSOLUTE: accuracy parameter Delta > 0 */
+    double m_limit;       /* ABSOLUTE: cells heavier than this are never accepted (INFINITY = off) */
+    int32_t group_mode;   /* otoo_group_mode */
+    int32_t g_max;        /* 1 .. OTOO_MAX_GROUP */
+} otoo_walk_params;
+
+/* Interaction lists in CSR form, allocated by the library. */
+typedef struct {
+    int32_t n_groups;
+    int64_t n_entries;      /* sum of list lengths */
+    int64_t interactions;   /* sum over groups of n_g * |L_g| (self pairs included) */
+    int32_t* group_off;     /* [n_groups+1] particle ranges in key order */
+    int64_t* list_off;      /* [n_groups+1] */
+    int32_t* list_idx;      /* [n_entries]: j < n particle j, j >= n cell j - n */
+    int32_t* n_cellent;     /* [n_groups]: the first n_cellent[g] entries of L_g are cells */
+    float* group_box;       /* [n_groups][6]: bounding box lo xyz, hi xyz (FP32) */
+    void* impl;
+} otoo_lists;
+
+/* Grouped stackless walk (Sec. 2.1 rules 1-4; group d_min as in Sec. 3.4):
+ * for each group, d_min is the distance from a cell's COM to the group's
+ * bounding box; accepted cells become one entry, opened leaves contribute
+ * their particles.  Each list holds the accepted cells first, then the
+ * particles, each part ascending.  Every group particle appears in its own
+ * list (its leaf can never be accepted below OTOO_THETA_LIMIT), which the
+ * device force relies on to remove the self pair.  *out is freed by
+ * otoo_lists_free.  EINVAL on bad parameters, ENOMEM on allocation failure. */
+int otoo_tree_walk(const otoo_tree* tree, const otoo_walk_params* params, otoo_lists** out);
+void otoo_lists_free(otoo_lists* lists);
+
+/* ======================================================================
+ * Device half: force evaluation
+ * ====================================================================== */
+
+typedef struct otoo_ctx otoo_ctx;
+
+/* Create a context on HIP device `device` (its stream is the null stream
+ * until otoo_set_stream).  EHIP if the device cannot be used. */
+int otoo_create(otoo_ctx** ctx, int32_t device);
+/* Synchronise the context's stream, free its scratch and the context. */
+int otoo_destroy(otoo_ctx* ctx);
+/* Use `hip_stream` (a hipStream_t, e.g. torch's current stream) for all work. */
+int otoo_set_stream(otoo_ctx* ctx, void* hip_stream);
+/* Message of the last failing call on this context ("" if none). */
+const char* otoo_last_error(const otoo_ctx* ctx);
+
+/* Kernel schedule knobs (the autotuner's search space).  Zero fields keep
+ * the current value. */
+typedef struct {
+    int32_t chunk;        /* list entries per work item (a long list is split into items); >= 64 */
+    int32_t blocks_per_cu;/* persistent workgroups per compute unit, 1..16 */
+    int32_t lpt;          /* 1: hand out items longest-first, 0: in group order */
+    int32_t debug_validate; /* 1: check the CSR on the host before launching (slow) */
+} otoo_tuning;
+int otoo_set_tuning(otoo_ctx* ctx, const otoo_tuning* tuning);
+int otoo_get_tuning(const otoo_ctx* ctx, otoo_tuning* tuning);
+
+/* Force evaluation over interaction lists (device pointers).
+ *   n           number of particles, 1 .. 2^30
+ *   pos [n][3], mass [n]   FP32 targets and particle sources, in group order
+ *   n_groups    >= 1; group_off [n_groups+1] int32: group g is particles
+ *               [group_off[g], group_off[g+1]), 1 .. OTOO_MAX_GROUP of them
+ *   n_entries   = list_off[n_groups]; list_off [n_groups+1] int64;
+ *   list_idx [n_entries] int32: j < n particle j, j >= n cell j - n
+ *               (the unified index space of Sec. 3.2).  A group's list must
+ *               hold each of the group's own particles exactly once: that
+ *               self pair is what the final reduction removes.
+ *   n_cells     >= 0; cell_mom [n_cells][cell_stride] FP32, COM xyz then M
+ *               (cell_stride 4 or 12)
+ *   eps         Plummer softening, > 0 and finite
+ *   pair_off, corr  learned correction (both NULL for the plain monopole):
+ *               pair_off [n_groups+1] int64 = prefix sums of the groups' cell
+ *               counts (the first pair_off[g+1]-pair_off[g] entries of L_g are
+ *               cells), corr [pair_off[n_groups]][6] FP32 symmetric tensors
+ *               (xx, yy, zz, xy, xz, yz) whose quadrupole-form field
+ *               a = Qd r^-5 - 5/2 (d.Qd) d r^-7, phi = -1/2 d.Qd r^-5
+ *               (d = x - COM, r^2 = |d|^2 + eps^2) is added per cell entry
+ *   out_acc [n][3] FP32, out_pot [n] FP64 (the potential is reduced in FP64)
+ * Arithmetic: FP32 pairs; per-tile FP32 partial sums combined with Kahan
+ * compensation across tiles and work items; FP64 for the final potential.
+ * Results are bitwise reproducible for fixed tuning.  Malformed device CSR
+ * (indices out of range, group sizes outside 1..OTOO_MAX_GROUP) never causes
+ * an out-of-bounds access: such entries are skipped and otoo_check(ctx)
+ * reports them; with debug_validate the call returns EINVAL instead. */
+int otoo_force(otoo_ctx* ctx, int32_t n, const float* pos, const float* mass, int32_t n_groups,
+               const int32_t* group_off, int64_t n_entries, const int64_t* list_off, const int32_t* list_idx,
+               int32_t n_cells, const float* cell_mom, int32_t cell_stride, float eps, const int64_t* pair_off,
+               const float* corr, float* out_acc, double* out_pot);
+
+/* Synchronise the context's stream and report whether any kernel since the
+ * last otoo_check met malformed input (EINVAL) or not (OK); clears the flag. */
+int otoo_check(otoo_ctx* ctx);
+
+/* Timing of the last otoo_force on the context stream (ms of the force
+ * kernel alone and of the whole call), taken with HIP events when
+ * enable != 0 (set with otoo_enable_timing). */
+int otoo_enable_timing(otoo_ctx* ctx, int32_t enable);
+int otoo_last_timing(otoo_ctx* ctx, float* ms_force_kernel, float* ms_total);
+
+/* Capture the exact sequence otoo_force would enqueue for these arguments
+ * into a HIP graph held by the context (replacing any previous one), and
+ * replay it with otoo_graph_launch on the context stream.  The pointers are
+ * baked into the graph; list contents may change between replays as long as
+ * n_groups, n_entries and the pointers stay the same. */
+int otoo_graph_capture(otoo_ctx* ctx, int32_t n, const float* pos, const float* mass, int32_t n_groups,
+                       const int32_t* group_off, int64_t n_entries, const int64_t* list_off,
+                       const int32_t* list_idx, int32_t n_cells, const float* cell_mom, int32_t cell_stride,
+                       float eps, const int64_t* pair_off, const float* corr, float* out_acc, double* out_pot);
+int otoo_graph_launch(otoo_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OTOO_H */

@@ -1,0 +1,336 @@
+"""MI355X octree gravity force library: thin Python binding over libotoo.so.
+
+Argument marshalling only.  The tree build and walk run in the library's
+C++/OpenMP host code; every step of the force evaluation runs in its HIP
+kernels.  PyTorch supplies device memory and streams.  There is no fallback:
+if ``libotoo.so`` is missing, importing the binding's entry points raises.
+
+    tree  = Tree(pos64, mass64, n_crit=16)          # host octree (key order)
+    lists = tree.walk(theta=0.5, g_max=64)          # interaction-list CSR
+    dev   = DeviceLists.upload(tree, lists, device)  # torch tensors on the GPU
+    ctx   = Context(device=0)
+    acc, pot = ctx.force(dev, eps=0.01)
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libotoo.so")
+
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
+MAX_GROUP = 256
+THETA_LIMIT = 1.15
+MAC_BH, MAC_ABSOLUTE = 0, 1
+GROUP_CHUNK, GROUP_CELL = 0, 1
+
+_lib = None
+
+
+class OtooError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"otoo error {code}: {msg}")
+        self.code = code
+
+
+class _WalkParams(ctypes.Structure):
+    _fields_ = [("mac", ctypes.c_int32), ("theta", ctypes.c_double), ("delta", ctypes.c_double),
+                ("m_limit", ctypes.c_double), ("group_mode", ctypes.c_int32), ("g_max", ctypes.c_int32)]
+
+
+class _Lists(ctypes.Structure):
+    _fields_ = [("n_groups", ctypes.c_int32), ("n_entries", ctypes.c_int64), ("interactions", ctypes.c_int64),
+                ("group_off", ctypes.POINTER(ctypes.c_int32)), ("list_off", ctypes.POINTER(ctypes.c_int64)),
+                ("list_idx", ctypes.POINTER(ctypes.c_int32)), ("n_cellent", ctypes.POINTER(ctypes.c_int32)),
+                ("group_box", ctypes.POINTER(ctypes.c_float)), ("impl", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32), ("lpt", ctypes.c_int32),
+                ("debug_validate", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTED = [
+    "otoo_tree_build", "otoo_tree_free", "otoo_tree_info", "otoo_tree_export", "otoo_tree_cells",
+    "otoo_tree_links", "otoo_tree_walk", "otoo_lists_free", "otoo_create", "otoo_destroy",
+    "otoo_set_stream", "otoo_last_error", "otoo_set_tuning", "otoo_get_tuning", "otoo_force",
+    "otoo_check", "otoo_enable_timing", "otoo_last_timing", "otoo_graph_capture", "otoo_graph_launch",
+]
+
+
+def lib():
+    """Load libotoo.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1206_1199_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D, F = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_float
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "otoo_tree_build": ([P, P, I64, I32, pp], I32),
+        "otoo_tree_free": ([P], None),
+        "otoo_tree_info": ([P, P, P, P, P, P], I32),
+        "otoo_tree_export": ([P, P, P, P, P, I32], I32),
+        "otoo_tree_cells": ([P, P, P, P, P, P, P, P, P, P, P], I32),
+        "otoo_tree_links": ([P, P, P], I32),
+        "otoo_tree_walk": ([P, ctypes.POINTER(_WalkParams), ctypes.POINTER(ctypes.POINTER(_Lists))], I32),
+        "otoo_lists_free": ([ctypes.POINTER(_Lists)], None),
+        "otoo_create": ([pp, I32], I32),
+        "otoo_destroy": ([P], I32),
+        "otoo_set_stream": ([P, P], I32),
+        "otoo_last_error": ([P], ctypes.c_char_p),
+        "otoo_set_tuning": ([P, ctypes.POINTER(Tuning)], I32),
+        "otoo_get_tuning": ([P, ctypes.POINTER(Tuning)], I32),
+        "otoo_force": ([P, I32, P, P, I32, P, I64, P, P, I32, P, I32, F, P, P, P, P], I32),
+        "otoo_check": ([P], I32),
+        "otoo_enable_timing": ([P, I32], I32),
+        "otoo_last_timing": ([P, ctypes.POINTER(F), ctypes.POINTER(F)], I32),
+        "otoo_graph_capture": ([P, I32, P, P, I32, P, I64, P, P, I32, P, I32, F, P, P, P, P], I32),
+        "otoo_graph_launch": ([P], I32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(rc, what="call"):
+    if rc != OK:
+        raise OtooError(rc, what)
+
+
+# ------------------------------------------------------------------ host tree
+
+
+@dataclass
+class Lists:
+    """Interaction-list CSR (host numpy arrays, copied out of the library)."""
+    group_off: np.ndarray    # int32 [G+1]
+    list_off: np.ndarray     # int64 [G+1]
+    list_idx: np.ndarray     # int32 [E]
+    n_cellent: np.ndarray    # int32 [G]
+    group_box: np.ndarray    # float32 [G, 6]
+    interactions: int
+
+    @property
+    def n_groups(self):
+        return len(self.group_off) - 1
+
+    @property
+    def n_entries(self):
+        return int(self.list_off[-1])
+
+    @property
+    def pair_off(self):
+        return np.concatenate([[0], np.cumsum(self.n_cellent, dtype=np.int64)]).astype(np.int64)
+
+
+class Tree:
+    """Host octree (library-owned) of FP64 particles, sorted into key order."""
+
+    def __init__(self, pos, mass, n_crit: int = 16):
+        L = lib()
+        pos = np.ascontiguousarray(pos, dtype=np.float64)
+        mass = np.ascontiguousarray(mass, dtype=np.float64)
+        if pos.ndim != 2 or pos.shape[1] != 3 or len(mass) != len(pos):
+            raise ValueError("pos must be [n, 3] and mass [n]")
+        h = ctypes.c_void_p()
+        _check(L.otoo_tree_build(_np_ptr(pos), _np_ptr(mass), len(mass), int(n_crit), ctypes.byref(h)),
+               "otoo_tree_build")
+        self._h = h
+        n = ctypes.c_int64()
+        nc = ctypes.c_int64()
+        depth = ctypes.c_int32()
+        lo = (ctypes.c_double * 3)()
+        side = ctypes.c_double()
+        _check(L.otoo_tree_info(h, ctypes.byref(n), ctypes.byref(nc), ctypes.byref(depth), lo, ctypes.byref(side)))
+        self.n, self.n_cells, self.depth = n.value, nc.value, depth.value
+        self.root_lo = np.array(lo[:])
+        self.root_side = side.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.otoo_tree_free(h)
+            self._h = None
+
+    def export(self, stride: int = 4):
+        """(perm int64 [n], pos32 [n,3], mass32 [n], cell_mom float32 [n_cells, stride])."""
+        perm = np.empty(self.n, np.int64)
+        pos = np.empty((self.n, 3), np.float32)
+        mass = np.empty(self.n, np.float32)
+        cm = np.empty((self.n_cells, stride), np.float32)
+        _check(lib().otoo_tree_export(self._h, _np_ptr(perm), _np_ptr(pos), _np_ptr(mass), _np_ptr(cm), stride),
+               "otoo_tree_export")
+        return perm, pos, mass, cm
+
+    def cells(self):
+        nc = self.n_cells
+        out = dict(first=np.empty(nc, np.int64), count=np.empty(nc, np.int64), level=np.empty(nc, np.int32),
+                   ijk=np.empty((nc, 3), np.int64), com=np.empty((nc, 3)), mass=np.empty(nc), side=np.empty(nc),
+                   s=np.empty(nc), S6=np.empty((nc, 6)), bmax=np.empty(nc))
+        _check(lib().otoo_tree_cells(self._h, *[_np_ptr(out[k]) for k in
+                                               ("first", "count", "level", "ijk", "com", "mass", "side", "s",
+                                                "S6", "bmax")]), "otoo_tree_cells")
+        return out
+
+    def links(self):
+        m = self.n + self.n_cells
+        nxt = np.empty(m, np.int64)
+        more = np.empty(m, np.int64)
+        _check(lib().otoo_tree_links(self._h, _np_ptr(nxt), _np_ptr(more)), "otoo_tree_links")
+        return nxt, more
+
+    def walk(self, theta: float = 0.5, g_max: int = 64, group_mode: int = GROUP_CHUNK, mac: int = MAC_BH,
+             delta: float = 0.01, m_limit: float = math.inf) -> Lists:
+        p = _WalkParams(mac=mac, theta=theta, delta=delta, m_limit=m_limit, group_mode=group_mode, g_max=g_max)
+        out = ctypes.POINTER(_Lists)()
+        _check(lib().otoo_tree_walk(self._h, ctypes.byref(p), ctypes.byref(out)), "otoo_tree_walk")
+        try:
+            s = out.contents
+            G, E = s.n_groups, s.n_entries
+            res = Lists(
+                group_off=np.ctypeslib.as_array(s.group_off, (G + 1,)).copy(),
+                list_off=np.ctypeslib.as_array(s.list_off, (G + 1,)).copy(),
+                list_idx=(np.ctypeslib.as_array(s.list_idx, (E,)).copy() if E else np.zeros(0, np.int32)),
+                n_cellent=np.ctypeslib.as_array(s.n_cellent, (G,)).copy(),
+                group_box=np.ctypeslib.as_array(s.group_box, (G * 6,)).copy().reshape(G, 6),
+                interactions=int(s.interactions))
+        finally:
+            lib().otoo_lists_free(out)
+        return res
+
+
+# ------------------------------------------------------------------ device
+
+
+@dataclass
+class DeviceLists:
+    """Device-resident inputs of one force evaluation (torch tensors)."""
+    pos: "object"        # float32 [n,3]
+    mass: "object"       # float32 [n]
+    group_off: "object"  # int32 [G+1]
+    list_off: "object"   # int64 [G+1]
+    list_idx: "object"   # int32 [E]
+    cell_mom: "object"   # float32 [n_cells, stride]
+    n_entries: int
+    interactions: int
+
+    @property
+    def n(self):
+        return int(self.mass.shape[0])
+
+    @property
+    def n_groups(self):
+        return int(self.group_off.shape[0]) - 1
+
+    @property
+    def n_cells(self):
+        return int(self.cell_mom.shape[0])
+
+    @classmethod
+    def from_host(cls, pos32, mass32, lists: Lists, cell_mom, device="cuda:0"):
+        import torch
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+        return cls(pos=t(pos32, np.float32), mass=t(mass32, np.float32), group_off=t(lists.group_off, np.int32),
+                   list_off=t(lists.list_off, np.int64),
+                   list_idx=t(lists.list_idx if lists.n_entries else np.zeros(1, np.int32), np.int32),
+                   cell_mom=t(cell_mom if len(cell_mom) else np.zeros((1, cell_mom.shape[1])), np.float32)[
+                       :len(cell_mom)],
+                   n_entries=lists.n_entries, interactions=lists.interactions)
+
+
+def _tptr(x):
+    return ctypes.c_void_p(x.data_ptr()) if x is not None else None
+
+
+class Context:
+    """One libotoo device context; work goes on torch's current stream of that device."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the force path has no CPU fallback")
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(lib().otoo_create(ctypes.byref(h), int(device)), "otoo_create")
+        self._h = h
+        self.sync_stream()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.otoo_destroy(h)
+            self._h = None
+
+    def _raise(self, rc, what):
+        if rc != OK:
+            raise OtooError(rc, f"{what}: {lib().otoo_last_error(self._h).decode()}")
+
+    def sync_stream(self):
+        import torch
+        s = torch.cuda.current_stream(self.device)
+        self._raise(lib().otoo_set_stream(self._h, ctypes.c_void_p(s.cuda_stream)), "otoo_set_stream")
+
+    def set_tuning(self, chunk=0, blocks_per_cu=0, lpt=None, debug_validate=None):
+        cur = self.tuning()
+        t = Tuning(chunk=chunk, blocks_per_cu=blocks_per_cu, lpt=cur.lpt if lpt is None else int(lpt),
+                   debug_validate=cur.debug_validate if debug_validate is None else int(debug_validate))
+        self._raise(lib().otoo_set_tuning(self._h, ctypes.byref(t)), "otoo_set_tuning")
+
+    def tuning(self) -> Tuning:
+        t = Tuning()
+        self._raise(lib().otoo_get_tuning(self._h, ctypes.byref(t)), "otoo_get_tuning")
+        return t
+
+    def _args(self, d: DeviceLists, eps, out_acc, out_pot, pair_off=None, corr=None):
+        stride = int(d.cell_mom.shape[1]) if d.cell_mom.dim() == 2 else 4
+        return (self._h, d.n, _tptr(d.pos), _tptr(d.mass), d.n_groups, _tptr(d.group_off), int(d.n_entries),
+                _tptr(d.list_off), _tptr(d.list_idx), d.n_cells, _tptr(d.cell_mom) if d.n_cells else None,
+                stride, float(eps), _tptr(pair_off), _tptr(corr), _tptr(out_acc), _tptr(out_pot))
+
+    def outputs(self, n):
+        import torch
+        return (torch.empty((n, 3), dtype=torch.float32, device=f"cuda:{self.device}"),
+                torch.empty(n, dtype=torch.float64, device=f"cuda:{self.device}"))
+
+    def force(self, d: DeviceLists, eps: float, out=None, pair_off=None, corr=None):
+        """Accelerations [n,3] FP32 and potentials [n] FP64 in key order (asynchronous)."""
+        acc, pot = out if out is not None else self.outputs(d.n)
+        self._raise(lib().otoo_force(*self._args(d, eps, acc, pot, pair_off, corr)), "otoo_force")
+        return acc, pot
+
+    def check(self):
+        self._raise(lib().otoo_check(self._h), "otoo_check")
+
+    def enable_timing(self, on=True):
+        self._raise(lib().otoo_enable_timing(self._h, int(on)), "otoo_enable_timing")
+
+    def last_timing(self):
+        k = ctypes.c_float()
+        t = ctypes.c_float()
+        self._raise(lib().otoo_last_timing(self._h, ctypes.byref(k), ctypes.byref(t)), "otoo_last_timing")
+        return k.value, t.value
+
+    def graph_capture(self, d: DeviceLists, eps: float, out, pair_off=None, corr=None):
+        acc, pot = out
+        self._raise(lib().otoo_graph_capture(*self._args(d, eps, acc, pot, pair_off, corr)), "otoo_graph_capture")
+
+    def graph_launch(self):
+        self._raise(lib().otoo_graph_launch(self._h), "otoo_graph_launch")

@@ -1,0 +1,891 @@
+// Device half of libotoo: the grouped gravity force evaluation on gfx950.
+//
+// Per call (all on the context stream, no host synchronisation):
+//   k_pack        unified source table src[e] = (x, y, z, m): particles 0..n-1,
+//                 then cell monopoles (COM, M) at n + c (the index space of
+//                 Sec. 3.2, the (r, m) words of Sec. 3.4); clears the queue.
+//   k_sched_*     work items (group g, chunk k of its list), their partial-row
+//                 offsets, and an optional longest-first order.
+//   k_force       persistent workgroups pull items from a device queue; the
+//                 group's targets sit in registers, list tiles are gathered
+//                 with coalesced loads into LDS and read back as broadcasts;
+//                 FP32 pair arithmetic, per-tile FP32 partials, Kahan across
+//                 tiles.  A group whose list is one item writes its results
+//                 directly; longer lists leave per-item partial rows.
+//   k_reduce      per particle: Kahan over the item partials in item order,
+//                 potential in FP64, self pair removed.
+// The pair term is the Plummer-softened monopole; cell entries may add the
+// quadrupole-form field of a per-(group, cell) tensor (learned correction).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "otoo.h"
+
+namespace {
+
+constexpr int kBlock = 256;           // threads per force workgroup = largest group
+constexpr int kTile = 256;            // list entries staged in LDS per tile
+constexpr int kScanBlock = 1024;      // groups per scan block (256 threads x 4)
+constexpr int kClasses = 40;          // longest-first cost classes (log2 buckets)
+
+static_assert(kBlock == OTOO_MAX_GROUP, "a workgroup holds one whole group");
+
+struct Meta {
+    int64_t n_items;
+    int64_t n_parts;
+    int32_t head;
+    int32_t pad;
+    int32_t hist[kClasses];
+    int32_t cursor[kClasses];
+};
+
+enum : int { kErrGroup = 1, kErrIndex = 2, kErrCapacity = 4 };
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ void kahan_add(float& sum, float& comp, float x) {
+    // sum + comp carries the running value; comp holds what rounding dropped
+    const float y = x + comp;
+    const float t = sum + y;
+    comp = y - (t - sum);
+    sum = t;
+}
+
+__device__ __forceinline__ int64_t clamp64(int64_t v, int64_t lo, int64_t hi) {
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// list range of group g, clamped to [0, n_entries]
+__device__ __forceinline__ void list_range(const int64_t* list_off, int64_t n_entries, int g, int64_t& b,
+                                           int64_t& e) {
+    b = clamp64(list_off[g], 0, n_entries);
+    e = clamp64(list_off[g + 1], b, n_entries);
+}
+
+__device__ __forceinline__ int64_t n_chunks(int64_t len, int chunk) {
+    return len <= chunk ? 1 : (len + chunk - 1) / chunk;
+}
+
+// ---------------------------------------------------------------- K1 pack
+
+__global__ void k_pack(const float* __restrict__ pos, const float* __restrict__ mass, int32_t n,
+                       const float* __restrict__ cell_mom, int32_t n_cells, int32_t stride,
+                       float4* __restrict__ src, Meta* meta) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) {
+        meta->head = 0;
+        for (int c = 0; c < kClasses; c++) {
+            meta->hist[c] = 0;
+            meta->cursor[c] = 0;
+        }
+    }
+    if (e < n) {
+        src[e] = make_float4(pos[3 * e], pos[3 * e + 1], pos[3 * e + 2], mass[e]);
+    } else if (e < (int64_t)n + n_cells) {
+        const float* c = cell_mom + (e - n) * stride;
+        src[e] = make_float4(c[0], c[1], c[2], c[3]);
+    }
+}
+
+// ---------------------------------------------------------------- scheduling
+
+// Per group: items c_g and partial rows p_g (only for groups split in >1
+// items); block-local exclusive prefix sums and block totals.
+__global__ __launch_bounds__(256) void k_sched_scan1(const int32_t* __restrict__ group_off,
+                                                     const int64_t* __restrict__ list_off, int64_t n_entries,
+                                                     int32_t n_groups, int32_t chunk, int64_t* item_base,
+                                                     int64_t* part_base, int64_t* block_tot) {
+    __shared__ int64_t s_i[256], s_p[256];
+    const int t = threadIdx.x;
+    const int64_t g0 = (int64_t)blockIdx.x * kScanBlock + 4 * t;
+    int64_t ci[4], cp[4], si = 0, sp = 0;
+    for (int k = 0; k < 4; k++) {
+        const int64_t g = g0 + k;
+        ci[k] = cp[k] = 0;
+        if (g < n_groups) {
+            int64_t b, e;
+            list_range(list_off, n_entries, (int)g, b, e);
+            const int64_t c = n_chunks(e - b, chunk);
+            int ng = group_off[g + 1] - group_off[g];
+            ng = ng < 0 ? 0 : (ng > kBlock ? kBlock : ng);
+            ci[k] = c;
+            cp[k] = c > 1 ? c * ng : 0;
+        }
+        si += ci[k];
+        sp += cp[k];
+    }
+    s_i[t] = si;
+    s_p[t] = sp;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over the 256 thread sums
+    for (int off = 1; off < 256; off <<= 1) {
+        int64_t ai = 0, ap = 0;
+        if (t >= off) {
+            ai = s_i[t - off];
+            ap = s_p[t - off];
+        }
+        __syncthreads();
+        s_i[t] += ai;
+        s_p[t] += ap;
+        __syncthreads();
+    }
+    int64_t ri = s_i[t] - si, rp = s_p[t] - sp;  // exclusive
+    for (int k = 0; k < 4; k++) {
+        const int64_t g = g0 + k;
+        if (g < n_groups) {
+            item_base[g] = ri;
+            part_base[g] = rp;
+        }
+        ri += ci[k];
+        rp += cp[k];
+    }
+    if (t == 255) {
+        block_tot[2 * blockIdx.x] = s_i[255];
+        block_tot[2 * blockIdx.x + 1] = s_p[255];
+    }
+}
+
+// Exclusive scan of block totals (one workgroup, sequential over 256-wide
+// chunks), grand totals into meta.
+__global__ __launch_bounds__(256) void k_sched_scan2(int64_t* block_tot, int32_t n_blocks, Meta* meta) {
+    __shared__ int64_t s_i[256], s_p[256];
+    __shared__ int64_t carry_i, carry_p;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        carry_i = 0;
+        carry_p = 0;
+    }
+    __syncthreads();
+    for (int base = 0; base < n_blocks; base += 256) {
+        const int b = base + t;
+        const int64_t vi = b < n_blocks ? block_tot[2 * b] : 0;
+        const int64_t vp = b < n_blocks ? block_tot[2 * b + 1] : 0;
+        s_i[t] = vi;
+        s_p[t] = vp;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            int64_t ai = 0, ap = 0;
+            if (t >= off) {
+                ai = s_i[t - off];
+                ap = s_p[t - off];
+            }
+            __syncthreads();
+            s_i[t] += ai;
+            s_p[t] += ap;
+            __syncthreads();
+        }
+        if (b < n_blocks) {
+            block_tot[2 * b] = carry_i + s_i[t] - vi;
+            block_tot[2 * b + 1] = carry_p + s_p[t] - vp;
+        }
+        __syncthreads();
+        if (t == 255) {
+            carry_i += s_i[255];
+            carry_p += s_p[255];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        meta->n_items = carry_i;
+        meta->n_parts = carry_p;
+    }
+}
+
+__device__ __forceinline__ int cost_class(int64_t cost) {
+    int c = cost > 0 ? 63 - __clzll((unsigned long long)cost) : 0;
+    return c >= kClasses ? kClasses - 1 : c;
+}
+
+// Item table (g, k) and, for longest-first, a histogram of cost classes.
+__global__ __launch_bounds__(256) void k_sched_fill(const int32_t* __restrict__ group_off,
+                                                    const int64_t* __restrict__ list_off, int64_t n_entries,
+                                                    int32_t n_groups, int32_t chunk, int64_t* item_base,
+                                                    int64_t* part_base, const int64_t* __restrict__ block_tot,
+                                                    int2* items, int64_t item_cap, int32_t lpt, Meta* meta,
+                                                    int32_t* err) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_groups) return;
+    const int64_t blk = g / kScanBlock;
+    const int64_t ib = item_base[g] + block_tot[2 * blk];
+    item_base[g] = ib;
+    part_base[g] += block_tot[2 * blk + 1];
+    int64_t b, e;
+    list_range(list_off, n_entries, (int)g, b, e);
+    const int64_t len = e - b;
+    const int64_t c = n_chunks(len, chunk);
+    int ng = group_off[g + 1] - group_off[g];
+    ng = ng < 0 ? 0 : (ng > kBlock ? kBlock : ng);
+    for (int64_t k = 0; k < c; k++) {
+        const int64_t q = ib + k;
+        if (q >= item_cap) {
+            atomicOr(err, kErrCapacity);
+            return;
+        }
+        items[q] = make_int2((int)g, (int)k);
+        if (lpt) {
+            const int64_t l = (k + 1 < c) ? chunk : len - k * (int64_t)chunk;
+            atomicAdd(&meta->hist[cost_class((int64_t)ng * (l > 0 ? l : 1))], 1);
+        }
+    }
+}
+
+// Longest-first order: classes from the most to the least expensive.
+__global__ void k_lpt_offsets(Meta* meta) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int run = 0;
+        for (int c = kClasses - 1; c >= 0; c--) {
+            meta->cursor[c] = run;
+            run += meta->hist[c];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_lpt_scatter(const int2* __restrict__ items, const int32_t* __restrict__ group_off,
+                                                     const int64_t* __restrict__ list_off, int64_t n_entries,
+                                                     int32_t chunk, int64_t item_cap, Meta* meta,
+                                                     int32_t* __restrict__ order) {
+    const int64_t n_items = meta->n_items < item_cap ? meta->n_items : item_cap;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_items;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int2 it = items[q];
+        int64_t b, e;
+        list_range(list_off, n_entries, it.x, b, e);
+        const int64_t len = e - b;
+        const int64_t c = n_chunks(len, chunk);
+        int ng = group_off[it.x + 1] - group_off[it.x];
+        ng = ng < 0 ? 0 : (ng > kBlock ? kBlock : ng);
+        const int64_t l = (it.y + 1 < c) ? chunk : len - it.y * (int64_t)chunk;
+        const int cls = cost_class((int64_t)ng * (l > 0 ? l : 1));
+        const int p = atomicAdd(&meta->cursor[cls], 1);
+        if (p < n_items) order[p] = (int32_t)q;
+    }
+}
+
+// ---------------------------------------------------------------- K2 force
+
+struct ForceArgs {
+    const float4* src;
+    int64_t n_src;
+    int32_t n;
+    const int32_t* group_off;
+    const int64_t* list_off;
+    int64_t n_entries;
+    const int32_t* list_idx;
+    const int2* items;
+    const int32_t* order;     // NULL: items in table order
+    int64_t item_cap;
+    const int64_t* part_base;
+    float4* partial;          // rows of 8 floats: acc sum xyz, pot sum | acc comp xyz, pot comp
+    int64_t part_cap;
+    Meta* meta;
+    int32_t chunk;
+    float eps2;
+    float* out_acc;
+    double* out_pot;
+    int32_t* err;
+};
+
+// Interaction of one target with one source: Plummer-softened monopole.
+// 13 VALU operations and one v_rsq_f32.
+__device__ __forceinline__ void pair_mono(float xi, float yi, float zi, float4 s, float eps2, float& ax, float& ay,
+                                          float& az, float& ph) {
+    const float dx = s.x - xi;
+    const float dy = s.y - yi;
+    const float dz = s.z - zi;
+    float r2 = fmaf(dx, dx, eps2);
+    r2 = fmaf(dy, dy, r2);
+    r2 = fmaf(dz, dz, r2);
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float mr = s.w * rinv;
+    const float mr3 = mr * rinv * rinv;
+    ax = fmaf(mr3, dx, ax);
+    ay = fmaf(mr3, dy, ay);
+    az = fmaf(mr3, dz, az);
+    ph += mr;
+}
+
+__global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
+    __shared__ float4 tile[2][kTile];
+    __shared__ int s_q;
+    const int t = threadIdx.x;
+    const int64_t n_items = a.meta->n_items < a.item_cap ? a.meta->n_items : a.item_cap;
+
+    for (;;) {
+        if (t == 0) s_q = atomicAdd(&a.meta->head, 1);
+        __syncthreads();
+        const int64_t q = s_q;
+        __syncthreads();
+        if (q >= n_items) break;
+        const int64_t qi = a.order ? a.order[q] : q;
+        const int2 it = a.items[qi];
+        const int g = it.x, k = it.y;
+        const int g0 = a.group_off[g];
+        const int ng = a.group_off[g + 1] - g0;
+        if (ng < 1 || ng > kBlock || g0 < 0 || g0 + ng > a.n) {
+            if (t == 0) atomicOr(a.err, kErrGroup);
+            continue;
+        }
+        int64_t lb, le;
+        list_range(a.list_off, a.n_entries, g, lb, le);
+        const int64_t len = le - lb;
+        const int64_t nch = n_chunks(len, a.chunk);
+        const int64_t cb = lb + (int64_t)k * a.chunk;
+        const int64_t ce = (cb + a.chunk < le) ? cb + a.chunk : le;
+
+        // Lanes are (target i, slice sl): S slices split each tile into S
+        // contiguous runs of `rows` entries, padded with zero-mass entries, so
+        // every lane runs the same uniform trip count.
+        const int S = kBlock / ng;
+        const int i = t % ng;
+        const int sl = t / ng;
+        const bool active = sl < S;
+        const int tstride = S * (kTile / S);          // entries per tile, a multiple of S
+        const bool wave_busy = (t & ~63) < S * ng;    // some lane of this wave is active
+        const float4 xi = a.src[g0 + i];
+
+        float s_ax = 0.f, s_ay = 0.f, s_az = 0.f, s_ph = 0.f;
+        float c_ax = 0.f, c_ay = 0.f, c_az = 0.f, c_ph = 0.f;
+
+        // prefetch the first tile into registers
+        float4 pre = make_float4(0.f, 0.f, 0.f, 0.f);
+        {
+            const int64_t e = cb + t;
+            if (t < tstride && e < ce) {
+                const int32_t j = a.list_idx[e];
+                if (j >= 0 && j < a.n_src) {
+                    pre = a.src[j];
+                } else {
+                    atomicOr(a.err, kErrIndex);
+                }
+            }
+        }
+        int buf = 0;
+        for (int64_t tb = cb; tb < ce; tb += tstride) {
+            const int tl = (int)((ce - tb) < tstride ? (ce - tb) : tstride);
+            const int rows = (tl + S - 1) / S;
+            tile[buf][t] = pre;
+            __syncthreads();
+            // next tile's gather overlaps this tile's arithmetic
+            {
+                const int64_t e = tb + tstride + t;
+                pre = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (t < tstride && e < ce) {
+                    const int32_t j = a.list_idx[e];
+                    if (j >= 0 && j < a.n_src) {
+                        pre = a.src[j];
+                    } else {
+                        atomicOr(a.err, kErrIndex);
+                    }
+                }
+            }
+            float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
+            if (wave_busy) {
+                const float4* tp = tile[buf] + (active ? sl : 0) * rows;
+#pragma unroll 8
+                for (int m = 0; m < rows; m++) pair_mono(xi.x, xi.y, xi.z, tp[m], a.eps2, ax, ay, az, ph);
+            }
+            kahan_add(s_ax, c_ax, ax);
+            kahan_add(s_ay, c_ay, ay);
+            kahan_add(s_az, c_az, az);
+            kahan_add(s_ph, c_ph, ph);
+            buf ^= 1;
+        }
+        __syncthreads();  // all reads of the tiles are done before reuse as reduction space
+
+        // combine the j-slices of each target (fixed slice order)
+        float* red = reinterpret_cast<float*>(&tile[0][0]);  // 2 * kTile float4 = 8 floats per thread
+        if (S > 1) {
+            red[8 * t + 0] = s_ax;
+            red[8 * t + 1] = s_ay;
+            red[8 * t + 2] = s_az;
+            red[8 * t + 3] = s_ph;
+            red[8 * t + 4] = c_ax;
+            red[8 * t + 5] = c_ay;
+            red[8 * t + 6] = c_az;
+            red[8 * t + 7] = c_ph;
+            __syncthreads();
+            if (t < ng) {
+                for (int s = 1; s < S; s++) {
+                    const float* r = red + 8 * (s * ng + t);
+                    kahan_add(s_ax, c_ax, r[0] + r[4]);
+                    kahan_add(s_ay, c_ay, r[1] + r[5]);
+                    kahan_add(s_az, c_az, r[2] + r[6]);
+                    kahan_add(s_ph, c_ph, r[3] + r[7]);
+                }
+            }
+        }
+        if (t < ng) {
+            const int p = g0 + t;
+            if (nch == 1) {
+                a.out_acc[3 * p + 0] = s_ax + c_ax;
+                a.out_acc[3 * p + 1] = s_ay + c_ay;
+                a.out_acc[3 * p + 2] = s_az + c_az;
+                const float self = xi.w * __builtin_amdgcn_rsqf(a.eps2);
+                a.out_pot[p] = -((double)s_ph + (double)c_ph) + (double)self;
+            } else {
+                const int64_t row = a.part_base[g] + (int64_t)k * ng + t;
+                if (row >= 0 && row < a.part_cap) {
+                    a.partial[2 * row] = make_float4(s_ax, s_ay, s_az, s_ph);
+                    a.partial[2 * row + 1] = make_float4(c_ax, c_ay, c_az, c_ph);
+                } else {
+                    atomicOr(a.err, kErrCapacity);
+                }
+            }
+        }
+        __syncthreads();  // the reduction space is the next item's tile buffer
+    }
+}
+
+// ---------------------------------------------------------------- K3 reduce
+
+__global__ __launch_bounds__(kBlock) void k_reduce(const float4* __restrict__ src, const int32_t* __restrict__ group_off,
+                                                   const int64_t* __restrict__ list_off, int64_t n_entries, int32_t n,
+                                                   int32_t chunk, const int64_t* __restrict__ part_base,
+                                                   const float4* __restrict__ partial, int64_t part_cap, float eps2,
+                                                   float* __restrict__ out_acc, double* __restrict__ out_pot) {
+    const int g = blockIdx.x;
+    const int t = threadIdx.x;
+    const int g0 = group_off[g];
+    const int ng = group_off[g + 1] - g0;
+    if (ng < 1 || ng > kBlock || g0 < 0 || g0 + ng > n || t >= ng) return;
+    int64_t lb, le;
+    list_range(list_off, n_entries, g, lb, le);
+    const int64_t nch = n_chunks(le - lb, chunk);
+    if (nch == 1) return;
+    float s_ax = 0.f, s_ay = 0.f, s_az = 0.f, c_ax = 0.f, c_ay = 0.f, c_az = 0.f;
+    double ph = 0.0;
+    for (int64_t k = 0; k < nch; k++) {
+        const int64_t row = part_base[g] + k * ng + t;
+        if (row < 0 || row >= part_cap) return;
+        const float4 s = partial[2 * row];
+        const float4 c = partial[2 * row + 1];
+        kahan_add(s_ax, c_ax, s.x + c.x);
+        kahan_add(s_ay, c_ay, s.y + c.y);
+        kahan_add(s_az, c_az, s.z + c.z);
+        ph += (double)s.w + (double)c.w;
+    }
+    const int p = g0 + t;
+    out_acc[3 * p + 0] = s_ax + c_ax;
+    out_acc[3 * p + 1] = s_ay + c_ay;
+    out_acc[3 * p + 2] = s_az + c_az;
+    const float self = src[p].w * __builtin_amdgcn_rsqf(eps2);
+    out_pot[p] = -ph + (double)self;
+}
+
+}  // namespace
+
+// ================================================================ runtime
+
+struct otoo_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    otoo_tuning tune{1024, 8, 1, 0};
+    int num_cu = 0;
+    // scratch
+    void* buf = nullptr;
+    size_t buf_bytes = 0;
+    Meta* meta = nullptr;
+    int32_t* errflag = nullptr;
+    // timing
+    bool timing = false;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    // graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap_stream = nullptr;
+};
+
+namespace {
+
+int fail(otoo_ctx* c, int code, const char* fmt, ...) {
+    char msg[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(msg, sizeof msg, fmt, ap);
+    va_end(ap);
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIP_TRY(c, expr)                                                                             \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess) return fail((c), OTOO_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+struct Layout {
+    size_t src, item_base, part_base, block_tot, items, order, partial, total;
+    int64_t item_cap, part_cap;
+};
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+Layout plan_layout(int32_t n, int32_t n_groups, int64_t n_entries, int32_t n_cells, int32_t chunk) {
+    Layout L{};
+    const int64_t n_blocks = (n_groups + kScanBlock - 1) / kScanBlock;
+    L.item_cap = (int64_t)n_groups + n_entries / chunk + 1;
+    // rows are written only for groups split into more than one item; each
+    // such group has len > chunk and at most 2 len / chunk items
+    const int64_t split_items = std::min<int64_t>(L.item_cap, 2 * (n_entries / chunk) + 1);
+    L.part_cap = std::max<int64_t>(1, std::min<int64_t>(split_items * (int64_t)kBlock, (int64_t)n * (n_entries / chunk + 1)));
+    size_t off = 0;
+    L.src = off;
+    off = align_up(off + sizeof(float4) * ((size_t)n + n_cells));
+    L.item_base = off;
+    off = align_up(off + sizeof(int64_t) * ((size_t)n_groups + 1));
+    L.part_base = off;
+    off = align_up(off + sizeof(int64_t) * ((size_t)n_groups + 1));
+    L.block_tot = off;
+    off = align_up(off + 2 * sizeof(int64_t) * ((size_t)n_blocks + 1));
+    L.items = off;
+    off = align_up(off + sizeof(int2) * (size_t)L.item_cap);
+    L.order = off;
+    off = align_up(off + sizeof(int32_t) * (size_t)L.item_cap);
+    L.partial = off;
+    off = align_up(off + 2 * sizeof(float4) * (size_t)L.part_cap);
+    L.total = off;
+    return L;
+}
+
+int ensure_scratch(otoo_ctx* c, size_t bytes) {
+    if (bytes <= c->buf_bytes) return OTOO_OK;
+    if (c->buf) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        HIP_TRY(c, hipFree(c->buf));
+        c->buf = nullptr;
+        c->buf_bytes = 0;
+    }
+    size_t want = bytes + bytes / 4;
+    if (hipMalloc(&c->buf, want) != hipSuccess) {
+        (void)hipGetLastError();
+        c->buf = nullptr;
+        return fail(c, OTOO_ENOMEM, "device scratch of %zu bytes could not be allocated", want);
+    }
+    c->buf_bytes = want;
+    return OTOO_OK;
+}
+
+struct Call {
+    int32_t n;
+    const float* pos;
+    const float* mass;
+    int32_t n_groups;
+    const int32_t* group_off;
+    int64_t n_entries;
+    const int64_t* list_off;
+    const int32_t* list_idx;
+    int32_t n_cells;
+    const float* cell_mom;
+    int32_t cell_stride;
+    float eps;
+    const int64_t* pair_off;
+    const float* corr;
+    float* out_acc;
+    double* out_pot;
+};
+
+int check_args(otoo_ctx* c, const Call& a) {
+    if (!c) return OTOO_EINVAL;
+    if (a.n < 1 || a.n > (1 << 30)) return fail(c, OTOO_EINVAL, "n = %d outside 1..2^30", a.n);
+    if (a.n_groups < 1 || a.n_groups > a.n) return fail(c, OTOO_EINVAL, "n_groups = %d outside 1..n", a.n_groups);
+    if (a.n_entries < 0) return fail(c, OTOO_EINVAL, "n_entries < 0");
+    if (a.n_cells < 0 || (int64_t)a.n + a.n_cells > INT32_MAX)
+        return fail(c, OTOO_EINVAL, "n_cells = %d out of range", a.n_cells);
+    if (a.cell_stride != 4 && a.cell_stride != 12) return fail(c, OTOO_EINVAL, "cell_stride must be 4 or 12");
+    if (!(a.eps > 0.f) || !std::isfinite(a.eps)) return fail(c, OTOO_EINVAL, "eps must be positive and finite");
+    if (!a.pos || !a.mass || !a.group_off || !a.list_off || !a.out_acc || !a.out_pot)
+        return fail(c, OTOO_EINVAL, "null pointer argument");
+    if (a.n_entries > 0 && !a.list_idx) return fail(c, OTOO_EINVAL, "list_idx is null");
+    if (a.n_cells > 0 && !a.cell_mom) return fail(c, OTOO_EINVAL, "cell_mom is null");
+    if ((a.pair_off == nullptr) != (a.corr == nullptr))
+        return fail(c, OTOO_EINVAL, "pair_off and corr must both be given or both be null");
+    if (a.corr) return fail(c, OTOO_EUNSUPPORTED, "learned correction not in this build");
+    return OTOO_OK;
+}
+
+// Host-side check of the device CSR (debug mode): copies it back.
+int validate_csr(otoo_ctx* c, const Call& a) {
+    std::vector<int32_t> go(a.n_groups + 1);
+    std::vector<int64_t> lo(a.n_groups + 1);
+    std::vector<int32_t> li(a.n_entries);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(go.data(), a.group_off, sizeof(int32_t) * go.size(), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(lo.data(), a.list_off, sizeof(int64_t) * lo.size(), hipMemcpyDeviceToHost));
+    if (a.n_entries)
+        HIP_TRY(c, hipMemcpy(li.data(), a.list_idx, sizeof(int32_t) * li.size(), hipMemcpyDeviceToHost));
+    if (go[0] != 0 || go[a.n_groups] != a.n) return fail(c, OTOO_EINVAL, "group_off must run from 0 to n");
+    if (lo[0] != 0 || lo[a.n_groups] != a.n_entries)
+        return fail(c, OTOO_EINVAL, "list_off must run from 0 to n_entries");
+    const int64_t n_src = (int64_t)a.n + a.n_cells;
+    for (int g = 0; g < a.n_groups; g++) {
+        const int ng = go[g + 1] - go[g];
+        if (ng < 1 || ng > OTOO_MAX_GROUP) return fail(c, OTOO_EINVAL, "group %d has %d particles", g, ng);
+        if (lo[g + 1] < lo[g]) return fail(c, OTOO_EINVAL, "list_off decreases at group %d", g);
+        int self = 0;
+        for (int64_t e = lo[g]; e < lo[g + 1]; e++) {
+            const int32_t j = li[e];
+            if (j < 0 || j >= n_src) return fail(c, OTOO_EINVAL, "list entry %lld = %d out of range", (long long)e, j);
+            if (j >= go[g] && j < go[g + 1]) self++;
+        }
+        if (self != ng)
+            return fail(c, OTOO_EINVAL, "group %d: list holds %d of its %d own particles", g, self, ng);
+    }
+    return OTOO_OK;
+}
+
+int enqueue(otoo_ctx* c, const Call& a, bool allow_timing) {
+    const otoo_tuning& tu = c->tune;
+    const Layout L = plan_layout(a.n, a.n_groups, a.n_entries, a.n_cells, tu.chunk);
+    char* base = static_cast<char*>(c->buf);
+    float4* src = reinterpret_cast<float4*>(base + L.src);
+    int64_t* item_base = reinterpret_cast<int64_t*>(base + L.item_base);
+    int64_t* part_base = reinterpret_cast<int64_t*>(base + L.part_base);
+    int64_t* block_tot = reinterpret_cast<int64_t*>(base + L.block_tot);
+    int2* items = reinterpret_cast<int2*>(base + L.items);
+    int32_t* order = reinterpret_cast<int32_t*>(base + L.order);
+    float4* partial = reinterpret_cast<float4*>(base + L.partial);
+    hipStream_t s = c->stream;
+    const bool tm = allow_timing && c->timing;
+
+    if (tm) HIP_TRY(c, hipEventRecord(c->ev[0], s));
+    const int64_t n_src = (int64_t)a.n + a.n_cells;
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)((n_src + 255) / 256)), dim3(256), 0, s, a.pos, a.mass, a.n, a.cell_mom,
+                       a.n_cells, a.cell_stride, src, c->meta);
+    const int n_blocks = (a.n_groups + kScanBlock - 1) / kScanBlock;
+    hipLaunchKernelGGL(k_sched_scan1, dim3(n_blocks), dim3(256), 0, s, a.group_off, a.list_off, a.n_entries,
+                       a.n_groups, tu.chunk, item_base, part_base, block_tot);
+    hipLaunchKernelGGL(k_sched_scan2, dim3(1), dim3(256), 0, s, block_tot, n_blocks, c->meta);
+    hipLaunchKernelGGL(k_sched_fill, dim3((a.n_groups + 255) / 256), dim3(256), 0, s, a.group_off, a.list_off,
+                       a.n_entries, a.n_groups, tu.chunk, item_base, part_base, block_tot, items, L.item_cap,
+                       tu.lpt, c->meta, c->errflag);
+    if (tu.lpt) {
+        hipLaunchKernelGGL(k_lpt_offsets, dim3(1), dim3(64), 0, s, c->meta);
+        hipLaunchKernelGGL(k_lpt_scatter, dim3(1024), dim3(256), 0, s, items, a.group_off, a.list_off, a.n_entries,
+                           tu.chunk, L.item_cap, c->meta, order);
+    }
+    ForceArgs fa;
+    fa.src = src;
+    fa.n_src = n_src;
+    fa.n = a.n;
+    fa.group_off = a.group_off;
+    fa.list_off = a.list_off;
+    fa.n_entries = a.n_entries;
+    fa.list_idx = a.list_idx;
+    fa.items = items;
+    fa.order = tu.lpt ? order : nullptr;
+    fa.item_cap = L.item_cap;
+    fa.part_base = part_base;
+    fa.partial = partial;
+    fa.part_cap = L.part_cap;
+    fa.meta = c->meta;
+    fa.chunk = tu.chunk;
+    fa.eps2 = a.eps * a.eps;
+    fa.out_acc = a.out_acc;
+    fa.out_pot = a.out_pot;
+    fa.err = c->errflag;
+    const int grid = c->num_cu * tu.blocks_per_cu;
+    if (tm) HIP_TRY(c, hipEventRecord(c->ev[1], s));
+    hipLaunchKernelGGL(k_force, dim3(grid), dim3(kBlock), 0, s, fa);
+    if (tm) HIP_TRY(c, hipEventRecord(c->ev[2], s));
+    hipLaunchKernelGGL(k_reduce, dim3(a.n_groups), dim3(kBlock), 0, s, src, a.group_off, a.list_off, a.n_entries,
+                       a.n, tu.chunk, part_base, partial, L.part_cap, fa.eps2, a.out_acc, a.out_pot);
+    HIP_TRY(c, hipGetLastError());
+    return OTOO_OK;
+}
+
+int prepare(otoo_ctx* c, const Call& a) {
+    int rc = check_args(c, a);
+    if (rc) return rc;
+    if (c->tune.debug_validate) {
+        rc = validate_csr(c, a);
+        if (rc) return rc;
+    }
+    const Layout L = plan_layout(a.n, a.n_groups, a.n_entries, a.n_cells, c->tune.chunk);
+    return ensure_scratch(c, L.total);
+}
+
+}  // namespace
+
+extern "C" {
+
+int otoo_create(otoo_ctx** out, int32_t device) {
+    if (!out) return OTOO_EINVAL;
+    *out = nullptr;
+    otoo_ctx* c = new (std::nothrow) otoo_ctx();
+    if (!c) return OTOO_ENOMEM;
+    c->device = device;
+    hipError_t e = hipSetDevice(device);
+    int cu = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device);
+    void* small = nullptr;
+    if (e == hipSuccess) e = hipMalloc(&small, 4096);
+    if (e != hipSuccess) {
+        delete c;
+        (void)hipGetLastError();
+        return OTOO_EHIP;
+    }
+    c->num_cu = cu;
+    c->meta = static_cast<Meta*>(small);
+    c->errflag = reinterpret_cast<int32_t*>(static_cast<char*>(small) + 2048);
+    if (hipMemset(small, 0, 4096) != hipSuccess) {
+        (void)hipFree(small);
+        delete c;
+        return OTOO_EHIP;
+    }
+    for (auto& ev : c->ev) {
+        if (hipEventCreate(&ev) != hipSuccess) {
+            (void)hipFree(small);
+            delete c;
+            return OTOO_EHIP;
+        }
+    }
+    *out = c;
+    return OTOO_OK;
+}
+
+int otoo_destroy(otoo_ctx* c) {
+    if (!c) return OTOO_EINVAL;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    for (auto& ev : c->ev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (c->buf) (void)hipFree(c->buf);
+    if (c->meta) (void)hipFree(c->meta);
+    delete c;
+    return OTOO_OK;
+}
+
+int otoo_set_stream(otoo_ctx* c, void* stream) {
+    if (!c) return OTOO_EINVAL;
+    c->stream = static_cast<hipStream_t>(stream);
+    return OTOO_OK;
+}
+
+const char* otoo_last_error(const otoo_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int otoo_set_tuning(otoo_ctx* c, const otoo_tuning* t) {
+    if (!c || !t) return OTOO_EINVAL;
+    otoo_tuning nt = c->tune;
+    if (t->chunk) nt.chunk = t->chunk;
+    if (t->blocks_per_cu) nt.blocks_per_cu = t->blocks_per_cu;
+    nt.lpt = t->lpt ? 1 : 0;
+    nt.debug_validate = t->debug_validate ? 1 : 0;
+    if (nt.chunk < 64 || nt.chunk > (1 << 28)) return fail(c, OTOO_EINVAL, "chunk must be in 64..2^28");
+    if (nt.blocks_per_cu < 1 || nt.blocks_per_cu > 16) return fail(c, OTOO_EINVAL, "blocks_per_cu must be in 1..16");
+    c->tune = nt;
+    return OTOO_OK;
+}
+
+int otoo_get_tuning(const otoo_ctx* c, otoo_tuning* t) {
+    if (!c || !t) return OTOO_EINVAL;
+    *t = c->tune;
+    return OTOO_OK;
+}
+
+int otoo_force(otoo_ctx* c, int32_t n, const float* pos, const float* mass, int32_t n_groups,
+               const int32_t* group_off, int64_t n_entries, const int64_t* list_off, const int32_t* list_idx,
+               int32_t n_cells, const float* cell_mom, int32_t cell_stride, float eps, const int64_t* pair_off,
+               const float* corr, float* out_acc, double* out_pot) {
+    if (!c) return OTOO_EINVAL;
+    c->err.clear();
+    Call a{n, pos, mass, n_groups, group_off, n_entries, list_off, list_idx, n_cells, cell_mom, cell_stride, eps,
+           pair_off, corr, out_acc, out_pot};
+    HIP_TRY(c, hipSetDevice(c->device));
+    int rc = prepare(c, a);
+    if (rc) return rc;
+    return enqueue(c, a, true);
+}
+
+int otoo_check(otoo_ctx* c) {
+    if (!c) return OTOO_EINVAL;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int32_t f = 0;
+    HIP_TRY(c, hipMemcpy(&f, c->errflag, sizeof f, hipMemcpyDeviceToHost));
+    if (f) {
+        const int32_t zero = 0;
+        HIP_TRY(c, hipMemcpy(c->errflag, &zero, sizeof zero, hipMemcpyHostToDevice));
+        return fail(c, OTOO_EINVAL, "malformed device input skipped (flags 0x%x:%s%s%s)", f,
+                    (f & kErrGroup) ? " group size" : "", (f & kErrIndex) ? " list index" : "",
+                    (f & kErrCapacity) ? " capacity" : "");
+    }
+    return OTOO_OK;
+}
+
+int otoo_enable_timing(otoo_ctx* c, int32_t enable) {
+    if (!c) return OTOO_EINVAL;
+    c->timing = enable != 0;
+    return OTOO_OK;
+}
+
+int otoo_last_timing(otoo_ctx* c, float* ms_kernel, float* ms_total) {
+    if (!c) return OTOO_EINVAL;
+    if (!c->timing) return fail(c, OTOO_EINVAL, "timing is not enabled");
+    HIP_TRY(c, hipEventSynchronize(c->ev[2]));
+    float k = 0, t = 0;
+    HIP_TRY(c, hipEventElapsedTime(&k, c->ev[1], c->ev[2]));
+    HIP_TRY(c, hipEventElapsedTime(&t, c->ev[0], c->ev[2]));
+    if (ms_kernel) *ms_kernel = k;
+    if (ms_total) *ms_total = t;
+    return OTOO_OK;
+}
+
+int otoo_graph_capture(otoo_ctx* c, int32_t n, const float* pos, const float* mass, int32_t n_groups,
+                       const int32_t* group_off, int64_t n_entries, const int64_t* list_off,
+                       const int32_t* list_idx, int32_t n_cells, const float* cell_mom, int32_t cell_stride,
+                       float eps, const int64_t* pair_off, const float* corr, float* out_acc, double* out_pot) {
+    if (!c) return OTOO_EINVAL;
+    c->err.clear();
+    Call a{n, pos, mass, n_groups, group_off, n_entries, list_off, list_idx, n_cells, cell_mom, cell_stride, eps,
+           pair_off, corr, out_acc, out_pot};
+    HIP_TRY(c, hipSetDevice(c->device));
+    int rc = prepare(c, a);  // all allocation happens before capture
+    if (rc) return rc;
+    if (c->gexec) {
+        HIP_TRY(c, hipGraphExecDestroy(c->gexec));
+        c->gexec = nullptr;
+    }
+    if (c->graph) {
+        HIP_TRY(c, hipGraphDestroy(c->graph));
+        c->graph = nullptr;
+    }
+    if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    hipStream_t user = c->stream;
+    c->stream = c->cap_stream;
+    HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    rc = enqueue(c, a, false);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    c->stream = user;
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(c, OTOO_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    c->graph = g;
+    HIP_TRY(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    return OTOO_OK;
+}
+
+int otoo_graph_launch(otoo_ctx* c) {
+    if (!c) return OTOO_EINVAL;
+    if (!c->gexec) return fail(c, OTOO_EINVAL, "no graph captured");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
+    return OTOO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,39 @@
+"""The C ABI: every function include/otoo.h declares is exported by libotoo.so,
+and the entry points reject bad arguments without touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1206_1199_amd as otoo
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "otoo.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(otoo_[a-z_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = otoo.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(otoo.EXPORTED)
+
+
+def test_null_context_and_bad_arguments_return_einval():
+    lib = otoo.lib()
+    assert lib.otoo_force(None, 1, None, None, 1, None, 0, None, None, 0, None, 4, 0.1, None, None, None,
+                          None) == otoo.EINVAL
+    assert lib.otoo_check(None) == otoo.EINVAL
+    assert lib.otoo_graph_launch(None) == otoo.EINVAL
+    assert lib.otoo_set_tuning(None, None) == otoo.EINVAL
+    assert lib.otoo_last_error(None) == b"null context"
+    assert lib.otoo_tree_build(None, None, 0, 16, None) == otoo.EINVAL
+    assert lib.otoo_tree_walk(None, None, None) == otoo.EINVAL

@@ -1,0 +1,176 @@
+"""GPU parity: the HIP force path (through the C ABI) against the FP64 oracle.
+
+Both sides see the same FP32 inputs (positions, masses and cell moments as
+exported for the device, promoted to FP64 for the oracle) and the same lists.
+Bar (FP32 pair arithmetic with Kahan-compensated accumulation, FP64
+potential): median relative error <= 1e-6 and maximum <= 1e-4 per particle
+for both acceleration and potential.  Integer outputs (lists) are compared
+exactly elsewhere; here runs with different schedules must agree bitwise.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_1206_1199_amd as otoo
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MED_TOL = 1e-6
+MAX_TOL = 1e-4
+
+
+def _setup(pos64, m64, theta, g_max, mode=otoo.GROUP_CHUNK, stride=4):
+    t = otoo.Tree(pos64, m64, n_crit=16)
+    lists = t.walk(theta=theta, g_max=g_max, group_mode=mode)
+    perm, pos32, mass32, cm = t.export(stride)
+    d = otoo.DeviceLists.from_host(pos32, mass32, lists, cm, "cuda:0")
+    return t, lists, pos32, mass32, cm, d
+
+
+def _oracle(pos32, mass32, lists, cm, eps, tgt=None):
+    return oracle.list_force(pos32.astype(np.float64), mass32.astype(np.float64), lists.group_off,
+                             lists.list_off, lists.list_idx, cm[:, :3].astype(np.float64),
+                             cm[:, 3].astype(np.float64), float(np.float32(eps)), tgt=tgt)
+
+
+def _gpu(ctx, d, eps):
+    acc, pot = ctx.force(d, eps)
+    torch.cuda.synchronize()
+    ctx.check()
+    return acc.cpu().numpy().astype(np.float64), pot.cpu().numpy()
+
+
+def _assert_parity(acc, pot, a_ref, p_ref, label):
+    ea = oracle.rel_err(acc, a_ref)
+    ep = oracle.rel_err(pot, p_ref)
+    print(f"{label}: acc median {np.median(ea):.2e} max {ea.max():.2e} | pot median {np.median(ep):.2e} "
+          f"max {ep.max():.2e}", flush=True)
+    assert np.median(ea) <= MED_TOL and ea.max() <= MAX_TOL
+    assert np.median(ep) <= MED_TOL and ep.max() <= MAX_TOL
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return otoo.Context(0)
+
+
+@pytest.fixture(scope="module")
+def plummer16k():
+    return synth.plummer(16384, seed=0)
+
+
+@pytest.mark.parametrize("g_max,mode", [(64, otoo.GROUP_CHUNK), (64, otoo.GROUP_CELL), (256, otoo.GROUP_CHUNK),
+                                        (100, otoo.GROUP_CHUNK), (200, otoo.GROUP_CELL), (17, otoo.GROUP_CHUNK)])
+def test_plummer16k_all_particles(ctx, plummer16k, g_max, mode):
+    pos, m = plummer16k
+    t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.5, g_max, mode)
+    ctx.set_tuning(chunk=1024, lpt=1)
+    acc, pot = _gpu(ctx, d, 0.01)
+    a_ref, p_ref = _oracle(pos32, mass32, lists, cm, 0.01)
+    _assert_parity(acc, pot, a_ref, p_ref, f"plummer16k g_max={g_max} mode={mode}")
+
+
+def test_schedules_agree_bitwise(ctx, plummer16k):
+    """Item order (longest-first or table order) and the workgroup count do not
+    change a single bit; a short chunk (many items per group, partial rows and
+    the reduction kernel) still meets the parity bar."""
+    pos, m = plummer16k
+    t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.5, 64)
+    outs = []
+    for lpt, bpc in ((1, 8), (0, 8), (1, 2), (0, 16)):
+        ctx.set_tuning(chunk=512, lpt=lpt, blocks_per_cu=bpc)
+        outs.append(_gpu(ctx, d, 0.01))
+    for a, p in outs[1:]:
+        assert np.array_equal(a, outs[0][0]) and np.array_equal(p, outs[0][1])
+    ctx.set_tuning(chunk=64, lpt=1, blocks_per_cu=8)
+    acc, pot = _gpu(ctx, d, 0.01)
+    a_ref, p_ref = _oracle(pos32, mass32, lists, cm, 0.01)
+    _assert_parity(acc, pot, a_ref, p_ref, "chunk=64")
+    ctx.set_tuning(chunk=1024)
+
+
+def test_graph_replay_matches_eager(ctx, plummer16k):
+    pos, m = plummer16k
+    t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.5, 64)
+    ctx.set_tuning(chunk=256, lpt=1)
+    a_e, p_e = _gpu(ctx, d, 0.01)
+    out = ctx.outputs(d.n)
+    ctx.graph_capture(d, 0.01, out)
+    for rep in range(4):
+        out[0].fill_(float("nan"))
+        out[1].fill_(float("nan"))
+        ctx.graph_launch()
+        torch.cuda.synchronize()
+        # eager work of the program between replays
+        _ = (d.pos * 2).sum().item()
+        assert np.array_equal(out[0].cpu().numpy().astype(np.float64), a_e), rep
+        assert np.array_equal(out[1].cpu().numpy(), p_e), rep
+    ctx.set_tuning(chunk=1024)
+
+
+def test_theta_zero_equals_direct_sum(ctx):
+    pos, m = synth.plummer(2000, seed=5)
+    t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.0, 64)
+    acc, pot = _gpu(ctx, d, 0.01)
+    a_ref, p_ref = oracle.direct(pos32.astype(np.float64), mass32.astype(np.float64), float(np.float32(0.01)))
+    _assert_parity(acc, pot, a_ref, p_ref, "theta=0 vs direct")
+
+
+def test_polytrope_pair_and_cube(ctx):
+    pos, m, star, _ = synth.polytrope_pair(8192, seed=2)
+    t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.6, 64)
+    acc, pot = _gpu(ctx, d, 1e-4)
+    a_ref, p_ref = _oracle(pos32, mass32, lists, cm, 1e-4)
+    _assert_parity(acc, pot, a_ref, p_ref, "polytrope pair eps=1e-4")
+    pos, m = synth.grf_cube(24, seed=4)
+    t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.7, 256, otoo.GROUP_CELL)
+    acc, pot = _gpu(ctx, d, 1e-3)
+    a_ref, p_ref = _oracle(pos32, mass32, lists, cm, 1e-3)
+    _assert_parity(acc, pot, a_ref, p_ref, "grf cube")
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 65])
+def test_tiny_inputs(ctx, n):
+    rng = np.random.default_rng(n)
+    pos = rng.normal(size=(n, 3))
+    m = rng.uniform(0.5, 1.5, n)
+    t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.5, 64)
+    acc, pot = _gpu(ctx, d, 0.05)
+    a_ref, p_ref = _oracle(pos32, mass32, lists, cm, 0.05)
+    if n == 1:
+        assert np.all(acc == 0) and np.all(pot == 0)
+        return
+    _assert_parity(acc, pot, a_ref, p_ref, f"n={n}")
+
+
+def test_malformed_lists_are_reported(ctx):
+    pos, m = synth.plummer(1000, seed=6)
+    t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.5, 64)
+    bad = d.list_idx.clone()
+    bad[5] = d.n + d.n_cells + 7          # out of range: skipped by the kernel, flagged
+    d_bad = otoo.DeviceLists(d.pos, d.mass, d.group_off, d.list_off, bad, d.cell_mom, d.n_entries,
+                             d.interactions)
+    ctx.force(d_bad, 0.01)
+    with pytest.raises(otoo.OtooError):
+        ctx.check()
+    ctx.check()                            # flag cleared
+    ctx.set_tuning(debug_validate=1)
+    with pytest.raises(otoo.OtooError):
+        ctx.force(d_bad, 0.01)
+    ctx.set_tuning(debug_validate=0)
+    with pytest.raises(otoo.OtooError):
+        ctx.force(d, 0.0)                  # eps must be positive
+
+
+def test_plummer_1m_sampled(ctx):
+    """The benchmark workload (Plummer 2^20, eps 0.005, theta 0.5) on a
+    4096-particle sample, in the launch configuration the benchmark times."""
+    pos, m = synth.plummer(1 << 20, seed=1)
+    t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.5, 64)
+    ctx.set_tuning(chunk=1024, lpt=1, blocks_per_cu=8)
+    acc, pot = _gpu(ctx, d, 0.005)
+    sample = synth.sample_idx(len(m), 4096, seed=101)
+    a_ref, p_ref = _oracle(pos32, mass32, lists, cm, 0.005, tgt=sample)
+    _assert_parity(acc[sample], pot[sample], a_ref, p_ref, "plummer 2^20 sample")
