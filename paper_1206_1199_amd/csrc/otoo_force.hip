@@ -204,37 +204,45 @@ __device__ __forceinline__ int cost_class(int64_t cost) {
     return c >= kClasses ? kClasses - 1 : c;
 }
 
-// Item table (g, k) and, for longest-first, a histogram of cost classes.
+// Item table (g, k) and, for longest-first, a histogram of cost classes
+// (counted in LDS, one global atomic per class per workgroup).
 __global__ __launch_bounds__(256) void k_sched_fill(const int32_t* __restrict__ group_off,
                                                     const int64_t* __restrict__ list_off, int64_t n_entries,
                                                     int32_t n_groups, int32_t chunk, int64_t* item_base,
                                                     int64_t* part_base, const int64_t* __restrict__ block_tot,
                                                     int2* items, int64_t item_cap, int32_t lpt, Meta* meta,
                                                     int32_t* err) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n_groups) return;
-    const int64_t blk = g / kScanBlock;
-    const int64_t ib = item_base[g] + block_tot[2 * blk];
-    item_base[g] = ib;
-    part_base[g] += block_tot[2 * blk + 1];
-    int64_t b, e;
-    list_range(list_off, n_entries, (int)g, b, e);
-    const int64_t len = e - b;
-    const int64_t c = n_chunks(len, chunk);
-    int ng = group_off[g + 1] - group_off[g];
-    ng = ng < 0 ? 0 : (ng > kBlock ? kBlock : ng);
-    for (int64_t k = 0; k < c; k++) {
-        const int64_t q = ib + k;
-        if (q >= item_cap) {
-            atomicOr(err, kErrCapacity);
-            return;
-        }
-        items[q] = make_int2((int)g, (int)k);
-        if (lpt) {
-            const int64_t l = (k + 1 < c) ? chunk : len - k * (int64_t)chunk;
-            atomicAdd(&meta->hist[cost_class((int64_t)ng * (l > 0 ? l : 1))], 1);
+    __shared__ int hist[kClasses];
+    const int t = threadIdx.x;
+    if (t < kClasses) hist[t] = 0;
+    __syncthreads();
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + t;
+    if (g < n_groups) {
+        const int64_t blk = g / kScanBlock;
+        const int64_t ib = item_base[g] + block_tot[2 * blk];
+        item_base[g] = ib;
+        part_base[g] += block_tot[2 * blk + 1];
+        int64_t b, e;
+        list_range(list_off, n_entries, (int)g, b, e);
+        const int64_t len = e - b;
+        const int64_t c = n_chunks(len, chunk);
+        int ng = group_off[g + 1] - group_off[g];
+        ng = ng < 0 ? 0 : (ng > kBlock ? kBlock : ng);
+        for (int64_t k = 0; k < c; k++) {
+            const int64_t q = ib + k;
+            if (q >= item_cap) {
+                atomicOr(err, kErrCapacity);
+                break;
+            }
+            items[q] = make_int2((int)g, (int)k);
+            if (lpt) {
+                const int64_t l = (k + 1 < c) ? chunk : len - k * (int64_t)chunk;
+                atomicAdd(&hist[cost_class((int64_t)ng * (l > 0 ? l : 1))], 1);
+            }
         }
     }
+    __syncthreads();
+    if (lpt && t < kClasses && hist[t]) atomicAdd(&meta->hist[t], hist[t]);
 }
 
 // Longest-first order: classes from the most to the least expensive.
@@ -248,23 +256,44 @@ __global__ void k_lpt_offsets(Meta* meta) {
     }
 }
 
+__device__ __forceinline__ int item_class(const int2 it, const int32_t* group_off, const int64_t* list_off,
+                                          int64_t n_entries, int32_t chunk) {
+    int64_t b, e;
+    list_range(list_off, n_entries, it.x, b, e);
+    const int64_t len = e - b;
+    const int64_t c = n_chunks(len, chunk);
+    int ng = group_off[it.x + 1] - group_off[it.x];
+    ng = ng < 0 ? 0 : (ng > kBlock ? kBlock : ng);
+    const int64_t l = (it.y + 1 < c) ? chunk : len - it.y * (int64_t)chunk;
+    return cost_class((int64_t)ng * (l > 0 ? l : 1));
+}
+
+// Scatter items into class order.  Each workgroup takes a contiguous range of
+// items, ranks them per class in LDS and reserves its slots with one global
+// atomic per class.
 __global__ __launch_bounds__(256) void k_lpt_scatter(const int2* __restrict__ items, const int32_t* __restrict__ group_off,
                                                      const int64_t* __restrict__ list_off, int64_t n_entries,
                                                      int32_t chunk, int64_t item_cap, Meta* meta,
                                                      int32_t* __restrict__ order) {
+    __shared__ int cnt[kClasses], base[kClasses], rank[kClasses];
+    const int t = threadIdx.x;
     const int64_t n_items = meta->n_items < item_cap ? meta->n_items : item_cap;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_items;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int2 it = items[q];
-        int64_t b, e;
-        list_range(list_off, n_entries, it.x, b, e);
-        const int64_t len = e - b;
-        const int64_t c = n_chunks(len, chunk);
-        int ng = group_off[it.x + 1] - group_off[it.x];
-        ng = ng < 0 ? 0 : (ng > kBlock ? kBlock : ng);
-        const int64_t l = (it.y + 1 < c) ? chunk : len - it.y * (int64_t)chunk;
-        const int cls = cost_class((int64_t)ng * (l > 0 ? l : 1));
-        const int p = atomicAdd(&meta->cursor[cls], 1);
+    const int64_t per = (n_items + gridDim.x - 1) / gridDim.x;
+    const int64_t q0 = (int64_t)blockIdx.x * per;
+    const int64_t q1 = (q0 + per < n_items) ? q0 + per : n_items;
+    if (t < kClasses) {
+        cnt[t] = 0;
+        rank[t] = 0;
+    }
+    __syncthreads();
+    for (int64_t q = q0 + t; q < q1; q += blockDim.x)
+        atomicAdd(&cnt[item_class(items[q], group_off, list_off, n_entries, chunk)], 1);
+    __syncthreads();
+    if (t < kClasses) base[t] = cnt[t] ? atomicAdd(&meta->cursor[t], cnt[t]) : 0;
+    __syncthreads();
+    for (int64_t q = q0 + t; q < q1; q += blockDim.x) {
+        const int cls = item_class(items[q], group_off, list_off, n_entries, chunk);
+        const int p = base[cls] + atomicAdd(&rank[cls], 1);
         if (p < n_items) order[p] = (int32_t)q;
     }
 }
@@ -446,24 +475,37 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
 
 // ---------------------------------------------------------------- K3 reduce
 
-__global__ __launch_bounds__(kBlock) void k_reduce(const float4* __restrict__ src, const int32_t* __restrict__ group_off,
-                                                   const int64_t* __restrict__ list_off, int64_t n_entries, int32_t n,
-                                                   int32_t chunk, const int64_t* __restrict__ part_base,
-                                                   const float4* __restrict__ partial, int64_t part_cap, float eps2,
-                                                   float* __restrict__ out_acc, double* __restrict__ out_pot) {
-    const int g = blockIdx.x;
-    const int t = threadIdx.x;
+// One thread per particle of a group whose list was split into several
+// items: Kahan over the item partials in item order (acceleration, FP32) and
+// an FP64 sum for the potential, then the self pair is removed.
+__global__ __launch_bounds__(256) void k_reduce(const float4* __restrict__ src, const int32_t* __restrict__ group_off,
+                                                int32_t n_groups, const int64_t* __restrict__ list_off,
+                                                int64_t n_entries, int32_t n, int32_t chunk,
+                                                const int64_t* __restrict__ part_base,
+                                                const float4* __restrict__ partial, int64_t part_cap, float eps2,
+                                                float* __restrict__ out_acc, double* __restrict__ out_pot) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    // group of particle p: last g with group_off[g] <= p
+    int lo = 0, hi = n_groups - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (group_off[mid] <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    const int g = lo;
     const int g0 = group_off[g];
     const int ng = group_off[g + 1] - g0;
-    if (ng < 1 || ng > kBlock || g0 < 0 || g0 + ng > n || t >= ng) return;
+    if (ng < 1 || ng > kBlock || g0 < 0 || g0 + ng > n || p < g0 || p >= g0 + ng) return;
     int64_t lb, le;
     list_range(list_off, n_entries, g, lb, le);
     const int64_t nch = n_chunks(le - lb, chunk);
     if (nch == 1) return;
+    const int i = p - g0;
     float s_ax = 0.f, s_ay = 0.f, s_az = 0.f, c_ax = 0.f, c_ay = 0.f, c_az = 0.f;
     double ph = 0.0;
     for (int64_t k = 0; k < nch; k++) {
-        const int64_t row = part_base[g] + k * ng + t;
+        const int64_t row = part_base[g] + k * ng + i;
         if (row < 0 || row >= part_cap) return;
         const float4 s = partial[2 * row];
         const float4 c = partial[2 * row + 1];
@@ -472,7 +514,6 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const float4* __restrict__ sr
         kahan_add(s_az, c_az, s.z + c.z);
         ph += (double)s.w + (double)c.w;
     }
-    const int p = g0 + t;
     out_acc[3 * p + 0] = s_ax + c_ax;
     out_acc[3 * p + 1] = s_ay + c_ay;
     out_acc[3 * p + 2] = s_az + c_az;
@@ -696,8 +737,9 @@ int enqueue(otoo_ctx* c, const Call& a, bool allow_timing) {
     if (tm) HIP_TRY(c, hipEventRecord(c->ev[1], s));
     hipLaunchKernelGGL(k_force, dim3(grid), dim3(kBlock), 0, s, fa);
     if (tm) HIP_TRY(c, hipEventRecord(c->ev[2], s));
-    hipLaunchKernelGGL(k_reduce, dim3(a.n_groups), dim3(kBlock), 0, s, src, a.group_off, a.list_off, a.n_entries,
-                       a.n, tu.chunk, part_base, partial, L.part_cap, fa.eps2, a.out_acc, a.out_pot);
+    hipLaunchKernelGGL(k_reduce, dim3((a.n + 255) / 256), dim3(256), 0, s, src, a.group_off, a.n_groups,
+                       a.list_off, a.n_entries, a.n, tu.chunk, part_base, partial, L.part_cap, fa.eps2,
+                       a.out_acc, a.out_pot);
     HIP_TRY(c, hipGetLastError());
     return OTOO_OK;
 }
