@@ -177,13 +177,21 @@ int otoo_get_tuning(const otoo_ctx* ctx, otoo_tuning* tuning);
  *   n_cells     >= 0; cell_mom [n_cells][cell_stride] FP32, COM xyz then M
  *               (cell_stride 4 or 12)
  *   eps         Plummer softening, > 0 and finite
- *   pair_off, corr  learned correction (both NULL for the plain monopole):
- *               pair_off [n_groups+1] int64 = prefix sums of the groups' cell
- *               counts (the first pair_off[g+1]-pair_off[g] entries of L_g are
- *               cells), corr [pair_off[n_groups]][6] FP32 symmetric tensors
- *               (xx, yy, zz, xy, xz, yz) whose quadrupole-form field
- *               a = Qd r^-5 - 5/2 (d.Qd) d r^-7, phi = -1/2 d.Qd r^-5
- *               (d = x - COM, r^2 = |d|^2 + eps^2) is added per cell entry
+ *   n_pairs, pair_off, corr  cell correction (n_pairs = 0 and both pointers
+ *               NULL for the plain monopole): pair_off [n_groups+1] int64 =
+ *               prefix sums of the groups' cell counts (the first
+ *               pair_off[g+1]-pair_off[g] entries of L_g are cells),
+ *               n_pairs = pair_off[n_groups], corr [n_pairs][6] FP32 symmetric
+ *               tensors Q (xx, yy, zz, xy, xz, yz), one per (group, cell) pair,
+ *               whose quadrupole-form field
+ *                   a = Qd r^-5 - 5/2 (d.Qd) d r^-7,  phi = -1/2 d.Qd r^-5
+ *               (d = x - COM, r^2 = |d|^2 + eps^2) is added through a
+ *               first-order local expansion about the centre c_g of the
+ *               group's bounding box: a_i += A_g + J_g (x_i - c_g),
+ *               phi_i += Phi_g - A_g.(x_i - c_g), with A_g, J_g (the Jacobian)
+ *               and Phi_g summed over the group's cells at c_g.  The tensors
+ *               come from otoo_quad_exact (the textbook quadrupole of each
+ *               cell) or otoo_mlp_infer (the learned effective tensor).
  *   out_acc [n][3] FP32, out_pot [n] FP64 (the potential is reduced in FP64)
  * Arithmetic: FP32 pairs; per-tile FP32 partial sums combined with Kahan
  * compensation across tiles and work items; FP64 for the final potential.
@@ -193,8 +201,20 @@ int otoo_get_tuning(const otoo_ctx* ctx, otoo_tuning* tuning);
  * reports them; with debug_validate the call returns EINVAL instead. */
 int otoo_force(otoo_ctx* ctx, int32_t n, const float* pos, const float* mass, int32_t n_groups,
                const int32_t* group_off, int64_t n_entries, const int64_t* list_off, const int32_t* list_idx,
-               int32_t n_cells, const float* cell_mom, int32_t cell_stride, float eps, const int64_t* pair_off,
-               const float* corr, float* out_acc, double* out_pot);
+               int32_t n_cells, const float* cell_mom, int32_t cell_stride, float eps, int64_t n_pairs,
+               const int64_t* pair_off, const float* corr, float* out_acc, double* out_pot);
+
+/* Textbook quadrupole tensor of every (group, cell) pair (the p = 2 term of
+ * the multipole expansion the paper names in Sec. 2 but does not use):
+ * corr[pair_off[g] + k] = 3 S_c - tr(S_c) I for the k-th cell entry c of
+ * group g's list, from the second-moment tensor S in cell_mom (cell_stride 12,
+ * as exported by otoo_tree_export).  Device pointers; corr [n_pairs][6]
+ * (xx, yy, zz, xy, xz, yz) is written; asynchronous on the context stream.
+ * Entries that are not cells give a zero tensor and are flagged for
+ * otoo_check. */
+int otoo_quad_exact(otoo_ctx* ctx, int32_t n, int32_t n_groups, int64_t n_entries, const int64_t* list_off,
+                    const int32_t* list_idx, int64_t n_pairs, const int64_t* pair_off, int32_t n_cells,
+                    const float* cell_mom, int32_t cell_stride, float* corr);
 
 /* Synchronise the context's stream and report whether any kernel since the
  * last otoo_check met malformed input (EINVAL) or not (OK); clears the flag. */
@@ -214,7 +234,8 @@ int otoo_last_timing(otoo_ctx* ctx, float* ms_force_kernel, float* ms_total);
 int otoo_graph_capture(otoo_ctx* ctx, int32_t n, const float* pos, const float* mass, int32_t n_groups,
                        const int32_t* group_off, int64_t n_entries, const int64_t* list_off,
                        const int32_t* list_idx, int32_t n_cells, const float* cell_mom, int32_t cell_stride,
-                       float eps, const int64_t* pair_off, const float* corr, float* out_acc, double* out_pot);
+                       float eps, int64_t n_pairs, const int64_t* pair_off, const float* corr, float* out_acc,
+                       double* out_pot);
 int otoo_graph_launch(otoo_ctx* ctx);
 
 #ifdef __cplusplus

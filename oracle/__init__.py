@@ -58,6 +58,10 @@ def _load():
         lib.oracle_point_field.restype = None
         lib.oracle_quad_field.argtypes = [I, P, P, P, D, P, P]
         lib.oracle_quad_field.restype = None
+        lib.oracle_list_force_expanded.argtypes = [I, P, P, I, P, P, P, I, P, P, P, P, P, D, I, P, P, P]
+        lib.oracle_list_force_expanded.restype = ctypes.c_int
+        lib.oracle_quad_jacobian.argtypes = [I, P, P, P, D, P, P, P]
+        lib.oracle_quad_jacobian.restype = None
         _lib = lib
     return _lib
 
@@ -89,8 +93,13 @@ def direct(pos, mass, eps, tgt=None):
 
 
 def list_force(pos, mass, group_off, list_off, list_idx, cell_com, cell_mass, eps,
-               tgt=None, n_cellent=None, quad=None):
-    """Interaction-list sums (see oracle.c).  Returns (acc[T,3], pot[T])."""
+               tgt=None, n_cellent=None, quad=None, expanded=False):
+    """Interaction-list sums (see oracle.c).  Returns (acc[T,3], pot[T]).
+
+    With ``quad`` (one tensor per (group, cell) pair) the cells also act
+    through the quadrupole form, per target (``expanded=False``) or through a
+    first-order local expansion about the group's box centre (``expanded=True``).
+    """
     lib = _load()
     pos = _f64(pos)
     mass = _f64(mass)
@@ -111,9 +120,10 @@ def list_force(pos, mass, group_off, list_off, list_idx, cell_com, cell_mass, ep
             raise ValueError("quad must hold one tensor per (group, cell) pair")
     acc = np.empty((nt, 3))
     pot = np.empty(nt)
-    rc = lib.oracle_list_force(n, _ptr(pos), _ptr(mass), len(go) - 1, _ptr(go), _ptr(lo), _ptr(li),
-                               len(cm), _ptr(cc), _ptr(cm), _ptr(nce), _ptr(po), _ptr(qd),
-                               float(eps), nt, _ptr(tg), _ptr(acc), _ptr(pot))
+    fn = lib.oracle_list_force_expanded if (expanded and quad is not None) else lib.oracle_list_force
+    rc = fn(n, _ptr(pos), _ptr(mass), len(go) - 1, _ptr(go), _ptr(lo), _ptr(li),
+            len(cm), _ptr(cc), _ptr(cm), _ptr(nce), _ptr(po), _ptr(qd),
+            float(eps), nt, _ptr(tg), _ptr(acc), _ptr(pot))
     if rc != 0:
         raise ValueError("list entry out of range or cell/particle order violated")
     return acc, pot
@@ -144,6 +154,19 @@ def quad_field(x, centre, quad, eps):
     pot = np.empty(len(x))
     lib.oracle_quad_field(len(x), _ptr(x), _ptr(c), _ptr(q), float(eps), _ptr(acc), _ptr(pot))
     return acc, pot
+
+
+def quad_jacobian(x, centre, quad, eps):
+    """Quadrupole-form field, its Jacobian [T,6] (xx,yy,zz,xy,xz,yz) and potential at points."""
+    lib = _load()
+    x = _f64(x).reshape(-1, 3)
+    c = _f64(centre).reshape(-1, 3)
+    q = _f64(quad).reshape(-1, 6)
+    acc = np.empty((len(x), 3))
+    jac = np.empty((len(x), 6))
+    pot = np.empty(len(x))
+    lib.oracle_quad_jacobian(len(x), _ptr(x), _ptr(c), _ptr(q), float(eps), _ptr(acc), _ptr(jac), _ptr(pot))
+    return acc, jac, pot
 
 
 def rel_err(a, ref):

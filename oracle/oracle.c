@@ -77,6 +77,41 @@ static void pair_quadrupole(const double x[3], const double c[3], const double q
 }
 
 /*
+ * Quadrupole-form field of tensor q centred at c, at point x: acceleration
+ * a, potential phi and the Jacobian J_ab = d a_a / d x_b (symmetric, stored
+ * xx, yy, zz, xy, xz, yz).  With d = x - c, u = d.Qd, r^2 = |d|^2 + eps^2:
+ *   a    = Qd r^-5 - 5/2 u d r^-7
+ *   J_ab = Q_ab r^-5 - 5 r^-7 ((Qd)_a d_b + (Qd)_b d_a) - 5/2 u delta_ab r^-7
+ *          + 35/2 u d_a d_b r^-9
+ *   phi  = -1/2 u r^-5
+ */
+static void quad_field_jacobian(const double x[3], const double c[3], const double q[6], double eps2,
+                                double a[3], double J[6], double *phi)
+{
+    double d[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps2;
+    double inv_r2 = 1.0 / r2;
+    double inv_r = sqrt(inv_r2);
+    double r5 = inv_r * inv_r2 * inv_r2;
+    double r7 = r5 * inv_r2;
+    double r9 = r7 * inv_r2;
+    double Q[3][3] = {{q[0], q[3], q[4]}, {q[3], q[1], q[5]}, {q[4], q[5], q[2]}};
+    double qd[3];
+    for (int k = 0; k < 3; k++)
+        qd[k] = Q[k][0] * d[0] + Q[k][1] * d[1] + Q[k][2] * d[2];
+    double u = d[0] * qd[0] + d[1] * qd[1] + d[2] * qd[2];
+    for (int k = 0; k < 3; k++)
+        a[k] = qd[k] * r5 - 2.5 * u * d[k] * r7;
+    static const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+    for (int m = 0; m < 6; m++) {
+        int p = ia[m], r = ib[m];
+        J[m] = Q[p][r] * r5 - 5.0 * r7 * (qd[p] * d[r] + qd[r] * d[p]) - (p == r ? 2.5 * u * r7 : 0.0) +
+               17.5 * u * d[p] * d[r] * r9;
+    }
+    *phi = -0.5 * u * r5;
+}
+
+/*
  * Direct sum.  pos[n][3], mass[n]; targets tgt[n_tgt] (NULL = all particles,
  * then n_tgt must equal n).  Writes acc[n_tgt][3], pot[n_tgt].
  */
@@ -173,6 +208,78 @@ int oracle_list_force(int64_t n, const double *pos, const double *mass,
         pot[t] = phi;
     }
     return bad ? -1 : 0;
+}
+
+/*
+ * List force whose cell tensors act through a first-order local expansion
+ * about the centre c_g of group g's bounding box (the form the device
+ * applies): with A_g = sum_c a_Q(c_g), J_g = sum_c J_Q(c_g) and
+ * Phi_g = sum_c phi_Q(c_g) over the group's cell entries,
+ *     a_i   += A_g + J_g (x_i - c_g)
+ *     phi_i += Phi_g - A_g . (x_i - c_g)
+ * on top of the monopole list sums of oracle_list_force.  Arguments as for
+ * oracle_list_force with quad required.  Returns 0 or -1 (malformed lists).
+ */
+int oracle_list_force_expanded(int64_t n, const double *pos, const double *mass,
+                               int64_t n_groups, const int64_t *group_off,
+                               const int64_t *list_off, const int64_t *list_idx,
+                               int64_t n_cells, const double *cell_com, const double *cell_mass,
+                               const int64_t *n_cellent, const int64_t *pair_off, const double *quad,
+                               double eps, int64_t n_tgt, const int64_t *tgt,
+                               double *acc, double *pot)
+{
+    int rc = oracle_list_force(n, pos, mass, n_groups, group_off, list_off, list_idx, n_cells, cell_com,
+                               cell_mass, NULL, NULL, NULL, eps, n_tgt, tgt, acc, pot);
+    if (rc)
+        return rc;
+    double eps2 = eps * eps;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
+    for (int64_t t = 0; t < n_tgt; t++) {
+        int64_t i = tgt ? tgt[t] : t;
+        int64_t g = find_group(n_groups, group_off, i);
+        double lo[3], hi[3], cg[3];
+        for (int k = 0; k < 3; k++)
+            lo[k] = hi[k] = pos[3 * group_off[g] + k];
+        for (int64_t p = group_off[g]; p < group_off[g + 1]; p++)
+            for (int k = 0; k < 3; k++) {
+                double v = pos[3 * p + k];
+                lo[k] = v < lo[k] ? v : lo[k];
+                hi[k] = v > hi[k] ? v : hi[k];
+            }
+        for (int k = 0; k < 3; k++)
+            cg[k] = 0.5 * (lo[k] + hi[k]);
+        double A[3] = {0, 0, 0}, J[6] = {0, 0, 0, 0, 0, 0}, Phi = 0.0;
+        for (int64_t kk = 0; kk < n_cellent[g]; kk++) {
+            int64_t e = list_idx[list_off[g] + kk];
+            if (e < n || e >= n + n_cells) {
+                bad = 1;
+                continue;
+            }
+            double a1[3], J1[6], p1;
+            quad_field_jacobian(cg, &cell_com[3 * (e - n)], &quad[6 * (pair_off[g] + kk)], eps2, a1, J1, &p1);
+            for (int k = 0; k < 3; k++)
+                A[k] += a1[k];
+            for (int k = 0; k < 6; k++)
+                J[k] += J1[k];
+            Phi += p1;
+        }
+        double dl[3] = {pos[3 * i] - cg[0], pos[3 * i + 1] - cg[1], pos[3 * i + 2] - cg[2]};
+        acc[3 * t + 0] += A[0] + J[0] * dl[0] + J[3] * dl[1] + J[4] * dl[2];
+        acc[3 * t + 1] += A[1] + J[3] * dl[0] + J[1] * dl[1] + J[5] * dl[2];
+        acc[3 * t + 2] += A[2] + J[4] * dl[0] + J[5] * dl[1] + J[2] * dl[2];
+        pot[t] += Phi - (A[0] * dl[0] + A[1] * dl[1] + A[2] * dl[2]);
+    }
+    return bad ? -1 : 0;
+}
+
+/* quadrupole-form field with its Jacobian at points (pins the Jacobian) */
+void oracle_quad_jacobian(int64_t n_pts, const double *x, const double *centre, const double *quad,
+                          double eps, double *acc, double *jac, double *pot)
+{
+    double eps2 = eps * eps;
+    for (int64_t t = 0; t < n_pts; t++)
+        quad_field_jacobian(&x[3 * t], &centre[3 * t], &quad[6 * t], eps2, &acc[3 * t], &jac[6 * t], &pot[t]);
 }
 
 /*

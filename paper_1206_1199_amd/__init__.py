@@ -63,6 +63,7 @@ EXPORTED = [
     "otoo_tree_links", "otoo_tree_walk", "otoo_lists_free", "otoo_create", "otoo_destroy",
     "otoo_set_stream", "otoo_last_error", "otoo_set_tuning", "otoo_get_tuning", "otoo_force",
     "otoo_check", "otoo_enable_timing", "otoo_last_timing", "otoo_graph_capture", "otoo_graph_launch",
+    "otoo_quad_exact",
 ]
 
 
@@ -91,11 +92,12 @@ def lib():
         "otoo_last_error": ([P], ctypes.c_char_p),
         "otoo_set_tuning": ([P, ctypes.POINTER(Tuning)], I32),
         "otoo_get_tuning": ([P, ctypes.POINTER(Tuning)], I32),
-        "otoo_force": ([P, I32, P, P, I32, P, I64, P, P, I32, P, I32, F, P, P, P, P], I32),
+        "otoo_force": ([P, I32, P, P, I32, P, I64, P, P, I32, P, I32, F, I64, P, P, P, P], I32),
+        "otoo_quad_exact": ([P, I32, I32, I64, P, P, I64, P, I32, P, I32, P], I32),
         "otoo_check": ([P], I32),
         "otoo_enable_timing": ([P, I32], I32),
         "otoo_last_timing": ([P, ctypes.POINTER(F), ctypes.POINTER(F)], I32),
-        "otoo_graph_capture": ([P, I32, P, P, I32, P, I64, P, P, I32, P, I32, F, P, P, P, P], I32),
+        "otoo_graph_capture": ([P, I32, P, P, I32, P, I64, P, P, I32, P, I32, F, I64, P, P, P, P], I32),
         "otoo_graph_launch": ([P], I32),
     }
     for name, (args, res) in sig.items():
@@ -229,6 +231,7 @@ class DeviceLists:
     list_off: "object"   # int64 [G+1]
     list_idx: "object"   # int32 [E]
     cell_mom: "object"   # float32 [n_cells, stride]
+    pair_off: "object"   # int64 [G+1]: prefix sums of the groups' cell counts
     n_entries: int
     interactions: int
 
@@ -244,15 +247,19 @@ class DeviceLists:
     def n_cells(self):
         return int(self.cell_mom.shape[0])
 
+    @property
+    def n_pairs(self):
+        return int(self.pair_off[-1].item())
+
     @classmethod
     def from_host(cls, pos32, mass32, lists: Lists, cell_mom, device="cuda:0"):
         import torch
         t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+        cm = cell_mom if len(cell_mom) else np.zeros((1, cell_mom.shape[1]), np.float32)
         return cls(pos=t(pos32, np.float32), mass=t(mass32, np.float32), group_off=t(lists.group_off, np.int32),
                    list_off=t(lists.list_off, np.int64),
                    list_idx=t(lists.list_idx if lists.n_entries else np.zeros(1, np.int32), np.int32),
-                   cell_mom=t(cell_mom if len(cell_mom) else np.zeros((1, cell_mom.shape[1])), np.float32)[
-                       :len(cell_mom)],
+                   cell_mom=t(cm, np.float32)[:len(cell_mom)], pair_off=t(lists.pair_off, np.int64),
                    n_entries=lists.n_entries, interactions=lists.interactions)
 
 
@@ -299,22 +306,43 @@ class Context:
         self._raise(lib().otoo_get_tuning(self._h, ctypes.byref(t)), "otoo_get_tuning")
         return t
 
-    def _args(self, d: DeviceLists, eps, out_acc, out_pot, pair_off=None, corr=None):
+    def _args(self, d: DeviceLists, eps, out_acc, out_pot, corr=None):
         stride = int(d.cell_mom.shape[1]) if d.cell_mom.dim() == 2 else 4
+        n_pairs = int(corr.shape[0]) if corr is not None else 0
         return (self._h, d.n, _tptr(d.pos), _tptr(d.mass), d.n_groups, _tptr(d.group_off), int(d.n_entries),
                 _tptr(d.list_off), _tptr(d.list_idx), d.n_cells, _tptr(d.cell_mom) if d.n_cells else None,
-                stride, float(eps), _tptr(pair_off), _tptr(corr), _tptr(out_acc), _tptr(out_pot))
+                stride, float(eps), n_pairs, _tptr(d.pair_off) if corr is not None else None, _tptr(corr),
+                _tptr(out_acc), _tptr(out_pot))
 
     def outputs(self, n):
         import torch
         return (torch.empty((n, 3), dtype=torch.float32, device=f"cuda:{self.device}"),
                 torch.empty(n, dtype=torch.float64, device=f"cuda:{self.device}"))
 
-    def force(self, d: DeviceLists, eps: float, out=None, pair_off=None, corr=None):
-        """Accelerations [n,3] FP32 and potentials [n] FP64 in key order (asynchronous)."""
+    def force(self, d: DeviceLists, eps: float, out=None, corr=None):
+        """Accelerations [n,3] FP32 and potentials [n] FP64 in key order (asynchronous).
+
+        ``corr``: optional float32 tensor [n_pairs, 6] of per-(group, cell)
+        tensors applied through the group local expansion.
+        """
         acc, pot = out if out is not None else self.outputs(d.n)
-        self._raise(lib().otoo_force(*self._args(d, eps, acc, pot, pair_off, corr)), "otoo_force")
+        self._raise(lib().otoo_force(*self._args(d, eps, acc, pot, corr)), "otoo_force")
         return acc, pot
+
+    def quad_exact(self, d: DeviceLists, out=None):
+        """Textbook quadrupole 3S - tr(S) I of each (group, cell) pair: float32 [n_pairs, 6]."""
+        import torch
+        if d.cell_mom.shape[1] != 12:
+            raise ValueError("cell moments with stride 12 (second-moment tensor) are required")
+        n_pairs = d.n_pairs
+        corr = out if out is not None else torch.empty((max(n_pairs, 1), 6), dtype=torch.float32,
+                                                       device=f"cuda:{self.device}")[:n_pairs]
+        self._raise(lib().otoo_quad_exact(self._h, d.n, d.n_groups, int(d.n_entries), _tptr(d.list_off),
+                                          _tptr(d.list_idx), n_pairs, _tptr(d.pair_off), d.n_cells,
+                                          _tptr(d.cell_mom) if d.n_cells else None, int(d.cell_mom.shape[1]),
+                                          _tptr(corr)),
+                    "otoo_quad_exact")
+        return corr
 
     def check(self):
         self._raise(lib().otoo_check(self._h), "otoo_check")
@@ -328,9 +356,9 @@ class Context:
         self._raise(lib().otoo_last_timing(self._h, ctypes.byref(k), ctypes.byref(t)), "otoo_last_timing")
         return k.value, t.value
 
-    def graph_capture(self, d: DeviceLists, eps: float, out, pair_off=None, corr=None):
+    def graph_capture(self, d: DeviceLists, eps: float, out, corr=None):
         acc, pot = out
-        self._raise(lib().otoo_graph_capture(*self._args(d, eps, acc, pot, pair_off, corr)), "otoo_graph_capture")
+        self._raise(lib().otoo_graph_capture(*self._args(d, eps, acc, pot, corr)), "otoo_graph_capture")
 
     def graph_launch(self):
         self._raise(lib().otoo_graph_launch(self._h), "otoo_graph_launch")

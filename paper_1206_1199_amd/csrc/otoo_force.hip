@@ -298,6 +298,159 @@ __global__ __launch_bounds__(256) void k_lpt_scatter(const int2* __restrict__ it
     }
 }
 
+// ---------------------------------------------------------------- cell correction
+
+// Quadrupole-form field of tensor Q (xx, yy, zz, xy, xz, yz) about COM at
+// the point whose offset from the COM is d: acceleration, Jacobian (same
+// component order) and potential, accumulated into f[10] =
+// {ax, ay, az, phi, Jxx, Jyy, Jzz, Jxy, Jxz, Jyz}.  With u = d.Qd and
+// r^2 = |d|^2 + eps^2:
+//   a = Qd r^-5 - 5/2 u d r^-7,  phi = -1/2 u r^-5,
+//   J_ab = Q_ab r^-5 - 5 r^-7 ((Qd)_a d_b + (Qd)_b d_a) - 5/2 u delta_ab r^-7 + 35/2 u d_a d_b r^-9
+__device__ __forceinline__ void quad_expand_add(float dx, float dy, float dz, const float* q, float eps2,
+                                                float* f) {
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float ri2 = ri * ri;
+    const float r5 = ri * ri2 * ri2;
+    const float r7 = r5 * ri2;
+    const float r9 = r7 * ri2;
+    const float qx = q[0] * dx + q[3] * dy + q[4] * dz;
+    const float qy = q[3] * dx + q[1] * dy + q[5] * dz;
+    const float qz = q[4] * dx + q[5] * dy + q[2] * dz;
+    const float u = dx * qx + dy * qy + dz * qz;
+    const float c7 = 2.5f * u * r7;
+    f[0] += qx * r5 - c7 * dx;
+    f[1] += qy * r5 - c7 * dy;
+    f[2] += qz * r5 - c7 * dz;
+    f[3] += -0.5f * u * r5;
+    const float c9 = 17.5f * u * r9;
+    const float f7 = 5.0f * r7;
+    f[4] += q[0] * r5 - f7 * 2.f * qx * dx - c7 + c9 * dx * dx;
+    f[5] += q[1] * r5 - f7 * 2.f * qy * dy - c7 + c9 * dy * dy;
+    f[6] += q[2] * r5 - f7 * 2.f * qz * dz - c7 + c9 * dz * dz;
+    f[7] += q[3] * r5 - f7 * (qx * dy + qy * dx) + c9 * dx * dy;
+    f[8] += q[4] * r5 - f7 * (qx * dz + qz * dx) + c9 * dx * dz;
+    f[9] += q[5] * r5 - f7 * (qy * dz + qz * dy) + c9 * dy * dz;
+}
+
+constexpr int kCorrStride = 16;   // floats per group: A xyz, Phi, J (6), centre xyz, pad
+
+// One workgroup per group: bounding-box centre c_g of the group's particles,
+// then the sums over the group's cell entries of the quadrupole-form field,
+// Jacobian and potential at c_g (fixed summation order: strided per thread,
+// then a fixed tree in LDS).
+__global__ __launch_bounds__(256) void k_corr_expand(const float4* __restrict__ src, int32_t n, int64_t n_src,
+                                                     const int32_t* __restrict__ group_off,
+                                                     const int64_t* __restrict__ list_off, int64_t n_entries,
+                                                     const int32_t* __restrict__ list_idx,
+                                                     const int64_t* __restrict__ pair_off, int64_t n_pairs,
+                                                     const float* __restrict__ corr, float eps2,
+                                                     float* __restrict__ gcorr, int32_t* err) {
+    __shared__ float red[10][256];
+    __shared__ float box[6][256];
+    const int g = blockIdx.x;
+    const int t = threadIdx.x;
+    const int g0 = group_off[g];
+    const int ng = group_off[g + 1] - g0;
+    const bool ok = ng >= 1 && ng <= kBlock && g0 >= 0 && g0 + ng <= n;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (ok && t < ng) {
+        const float4 p = src[g0 + t];
+        lo[0] = hi[0] = p.x;
+        lo[1] = hi[1] = p.y;
+        lo[2] = hi[2] = p.z;
+    }
+    for (int k = 0; k < 3; k++) {
+        box[k][t] = lo[k];
+        box[3 + k][t] = hi[k];
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int k = 0; k < 3; k++) {
+                box[k][t] = fminf(box[k][t], box[k][t + w]);
+                box[3 + k][t] = fmaxf(box[3 + k][t], box[3 + k][t + w]);
+            }
+        __syncthreads();
+    }
+    const float cx = 0.5f * (box[0][0] + box[3][0]);
+    const float cy = 0.5f * (box[1][0] + box[4][0]);
+    const float cz = 0.5f * (box[2][0] + box[5][0]);
+    float f[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (ok) {
+        int64_t lb, le;
+        list_range(list_off, n_entries, g, lb, le);
+        const int64_t p0 = clamp64(pair_off[g], 0, n_pairs);
+        const int64_t p1 = clamp64(pair_off[g + 1], p0, n_pairs);
+        const int64_t nce = (p1 - p0) < (le - lb) ? (p1 - p0) : (le - lb);
+        for (int64_t k = t; k < nce; k += 256) {
+            const int32_t j = list_idx[lb + k];
+            if (j < n || j >= n_src) {
+                atomicOr(err, kErrIndex);
+                continue;
+            }
+            const float4 cm = src[j];
+            quad_expand_add(cx - cm.x, cy - cm.y, cz - cm.z, corr + 6 * (p0 + k), eps2, f);
+        }
+    } else if (t == 0) {
+        atomicOr(err, kErrGroup);
+    }
+    for (int k = 0; k < 10; k++) red[k][t] = f[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int k = 0; k < 10; k++) red[k][t] += red[k][t + w];
+        __syncthreads();
+    }
+    if (t < 10) gcorr[(int64_t)kCorrStride * g + t] = red[t][0];
+    if (t == 10) gcorr[(int64_t)kCorrStride * g + 10] = cx;
+    if (t == 11) gcorr[(int64_t)kCorrStride * g + 11] = cy;
+    if (t == 12) gcorr[(int64_t)kCorrStride * g + 12] = cz;
+}
+
+// Textbook quadrupole of each accepted cell, Q = 3 S - tr(S) I from the
+// cell's second-moment tensor S, written per (group, cell) pair.
+__global__ __launch_bounds__(256) void k_quad_exact(int32_t n, int32_t n_groups, const int64_t* __restrict__ list_off,
+                                                    int64_t n_entries, const int32_t* __restrict__ list_idx,
+                                                    const int64_t* __restrict__ pair_off, int64_t n_pairs,
+                                                    int32_t n_cells, const float* __restrict__ cell_mom,
+                                                    float* __restrict__ corr, int32_t* err) {
+    const int g = blockIdx.x;
+    int64_t lb, le;
+    list_range(list_off, n_entries, g, lb, le);
+    const int64_t p0 = clamp64(pair_off[g], 0, n_pairs);
+    const int64_t p1 = clamp64(pair_off[g + 1], p0, n_pairs);
+    const int64_t nce = (p1 - p0) < (le - lb) ? (p1 - p0) : (le - lb);
+    for (int64_t k = threadIdx.x; k < nce; k += blockDim.x) {
+        const int64_t c = (int64_t)list_idx[lb + k] - n;
+        float* q = corr + 6 * (p0 + k);
+        if (c < 0 || c >= n_cells) {
+            atomicOr(err, kErrIndex);
+            for (int m = 0; m < 6; m++) q[m] = 0.f;
+            continue;
+        }
+        const float* S = cell_mom + 12 * c + 5;
+        const float tr = S[0] + S[1] + S[2];
+        q[0] = 3.f * S[0] - tr;
+        q[1] = 3.f * S[1] - tr;
+        q[2] = 3.f * S[2] - tr;
+        q[3] = 3.f * S[3];
+        q[4] = 3.f * S[4];
+        q[5] = 3.f * S[5];
+    }
+}
+
+// Local expansion of group g's cell correction applied at particle position x.
+__device__ __forceinline__ void apply_corr(const float* __restrict__ gc, float x, float y, float z, float& ax,
+                                           float& ay, float& az, double& phi) {
+    const float dx = x - gc[10], dy = y - gc[11], dz = z - gc[12];
+    ax += gc[0] + gc[4] * dx + gc[7] * dy + gc[8] * dz;
+    ay += gc[1] + gc[7] * dx + gc[5] * dy + gc[9] * dz;
+    az += gc[2] + gc[8] * dx + gc[9] * dy + gc[6] * dz;
+    phi += (double)gc[3] - (double)(gc[0] * dx + gc[1] * dy + gc[2] * dz);
+}
+
 // ---------------------------------------------------------------- K2 force
 
 struct ForceArgs {
@@ -317,6 +470,7 @@ struct ForceArgs {
     Meta* meta;
     int32_t chunk;
     float eps2;
+    const float* gcorr;       // per-group correction expansion (NULL: plain monopole)
     float* out_acc;
     double* out_pot;
     int32_t* err;
@@ -454,11 +608,14 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
         if (t < ng) {
             const int p = g0 + t;
             if (nch == 1) {
-                a.out_acc[3 * p + 0] = s_ax + c_ax;
-                a.out_acc[3 * p + 1] = s_ay + c_ay;
-                a.out_acc[3 * p + 2] = s_az + c_az;
+                float ax = s_ax + c_ax, ay = s_ay + c_ay, az = s_az + c_az;
                 const float self = xi.w * __builtin_amdgcn_rsqf(a.eps2);
-                a.out_pot[p] = -((double)s_ph + (double)c_ph) + (double)self;
+                double phi = -((double)s_ph + (double)c_ph) + (double)self;
+                if (a.gcorr) apply_corr(a.gcorr + (int64_t)kCorrStride * g, xi.x, xi.y, xi.z, ax, ay, az, phi);
+                a.out_acc[3 * p + 0] = ax;
+                a.out_acc[3 * p + 1] = ay;
+                a.out_acc[3 * p + 2] = az;
+                a.out_pot[p] = phi;
             } else {
                 const int64_t row = a.part_base[g] + (int64_t)k * ng + t;
                 if (row >= 0 && row < a.part_cap) {
@@ -483,7 +640,8 @@ __global__ __launch_bounds__(256) void k_reduce(const float4* __restrict__ src, 
                                                 int64_t n_entries, int32_t n, int32_t chunk,
                                                 const int64_t* __restrict__ part_base,
                                                 const float4* __restrict__ partial, int64_t part_cap, float eps2,
-                                                float* __restrict__ out_acc, double* __restrict__ out_pot) {
+                                                const float* __restrict__ gcorr, float* __restrict__ out_acc,
+                                                double* __restrict__ out_pot) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     // group of particle p: last g with group_off[g] <= p
@@ -514,11 +672,15 @@ __global__ __launch_bounds__(256) void k_reduce(const float4* __restrict__ src, 
         kahan_add(s_az, c_az, s.z + c.z);
         ph += (double)s.w + (double)c.w;
     }
-    out_acc[3 * p + 0] = s_ax + c_ax;
-    out_acc[3 * p + 1] = s_ay + c_ay;
-    out_acc[3 * p + 2] = s_az + c_az;
-    const float self = src[p].w * __builtin_amdgcn_rsqf(eps2);
-    out_pot[p] = -ph + (double)self;
+    const float4 xp = src[p];
+    float ax = s_ax + c_ax, ay = s_ay + c_ay, az = s_az + c_az;
+    const float self = xp.w * __builtin_amdgcn_rsqf(eps2);
+    double phi = -ph + (double)self;
+    if (gcorr) apply_corr(gcorr + (int64_t)kCorrStride * g, xp.x, xp.y, xp.z, ax, ay, az, phi);
+    out_acc[3 * p + 0] = ax;
+    out_acc[3 * p + 1] = ay;
+    out_acc[3 * p + 2] = az;
+    out_pot[p] = phi;
 }
 
 }  // namespace
@@ -564,7 +726,7 @@ int fail(otoo_ctx* c, int code, const char* fmt, ...) {
     } while (0)
 
 struct Layout {
-    size_t src, item_base, part_base, block_tot, items, order, partial, total;
+    size_t src, item_base, part_base, block_tot, items, order, partial, gcorr, total;
     int64_t item_cap, part_cap;
 };
 
@@ -593,6 +755,8 @@ Layout plan_layout(int32_t n, int32_t n_groups, int64_t n_entries, int32_t n_cel
     off = align_up(off + sizeof(int32_t) * (size_t)L.item_cap);
     L.partial = off;
     off = align_up(off + 2 * sizeof(float4) * (size_t)L.part_cap);
+    L.gcorr = off;
+    off = align_up(off + sizeof(float) * kCorrStride * ((size_t)n_groups + 1));
     L.total = off;
     return L;
 }
@@ -628,6 +792,7 @@ struct Call {
     const float* cell_mom;
     int32_t cell_stride;
     float eps;
+    int64_t n_pairs;
     const int64_t* pair_off;
     const float* corr;
     float* out_acc;
@@ -649,7 +814,8 @@ int check_args(otoo_ctx* c, const Call& a) {
     if (a.n_cells > 0 && !a.cell_mom) return fail(c, OTOO_EINVAL, "cell_mom is null");
     if ((a.pair_off == nullptr) != (a.corr == nullptr))
         return fail(c, OTOO_EINVAL, "pair_off and corr must both be given or both be null");
-    if (a.corr) return fail(c, OTOO_EUNSUPPORTED, "learned correction not in this build");
+    if (a.n_pairs < 0 || (a.n_pairs > 0 && !a.corr) || (a.corr && a.n_pairs > a.n_entries))
+        return fail(c, OTOO_EINVAL, "n_pairs = %lld inconsistent with corr / n_entries", (long long)a.n_pairs);
     return OTOO_OK;
 }
 
@@ -694,6 +860,7 @@ int enqueue(otoo_ctx* c, const Call& a, bool allow_timing) {
     int2* items = reinterpret_cast<int2*>(base + L.items);
     int32_t* order = reinterpret_cast<int32_t*>(base + L.order);
     float4* partial = reinterpret_cast<float4*>(base + L.partial);
+    float* gcorr = a.corr ? reinterpret_cast<float*>(base + L.gcorr) : nullptr;
     hipStream_t s = c->stream;
     const bool tm = allow_timing && c->timing;
 
@@ -713,6 +880,10 @@ int enqueue(otoo_ctx* c, const Call& a, bool allow_timing) {
         hipLaunchKernelGGL(k_lpt_scatter, dim3(1024), dim3(256), 0, s, items, a.group_off, a.list_off, a.n_entries,
                            tu.chunk, L.item_cap, c->meta, order);
     }
+    if (gcorr)
+        hipLaunchKernelGGL(k_corr_expand, dim3(a.n_groups), dim3(256), 0, s, src, a.n, n_src, a.group_off,
+                           a.list_off, a.n_entries, a.list_idx, a.pair_off, a.n_pairs, a.corr, a.eps * a.eps,
+                           gcorr, c->errflag);
     ForceArgs fa;
     fa.src = src;
     fa.n_src = n_src;
@@ -730,6 +901,7 @@ int enqueue(otoo_ctx* c, const Call& a, bool allow_timing) {
     fa.meta = c->meta;
     fa.chunk = tu.chunk;
     fa.eps2 = a.eps * a.eps;
+    fa.gcorr = gcorr;
     fa.out_acc = a.out_acc;
     fa.out_pot = a.out_pot;
     fa.err = c->errflag;
@@ -738,7 +910,7 @@ int enqueue(otoo_ctx* c, const Call& a, bool allow_timing) {
     hipLaunchKernelGGL(k_force, dim3(grid), dim3(kBlock), 0, s, fa);
     if (tm) HIP_TRY(c, hipEventRecord(c->ev[2], s));
     hipLaunchKernelGGL(k_reduce, dim3((a.n + 255) / 256), dim3(256), 0, s, src, a.group_off, a.n_groups,
-                       a.list_off, a.n_entries, a.n, tu.chunk, part_base, partial, L.part_cap, fa.eps2,
+                       a.list_off, a.n_entries, a.n, tu.chunk, part_base, partial, L.part_cap, fa.eps2, gcorr,
                        a.out_acc, a.out_pot);
     HIP_TRY(c, hipGetLastError());
     return OTOO_OK;
@@ -838,16 +1010,34 @@ int otoo_get_tuning(const otoo_ctx* c, otoo_tuning* t) {
 
 int otoo_force(otoo_ctx* c, int32_t n, const float* pos, const float* mass, int32_t n_groups,
                const int32_t* group_off, int64_t n_entries, const int64_t* list_off, const int32_t* list_idx,
-               int32_t n_cells, const float* cell_mom, int32_t cell_stride, float eps, const int64_t* pair_off,
-               const float* corr, float* out_acc, double* out_pot) {
+               int32_t n_cells, const float* cell_mom, int32_t cell_stride, float eps, int64_t n_pairs,
+               const int64_t* pair_off, const float* corr, float* out_acc, double* out_pot) {
     if (!c) return OTOO_EINVAL;
     c->err.clear();
     Call a{n, pos, mass, n_groups, group_off, n_entries, list_off, list_idx, n_cells, cell_mom, cell_stride, eps,
-           pair_off, corr, out_acc, out_pot};
+           n_pairs, pair_off, corr, out_acc, out_pot};
     HIP_TRY(c, hipSetDevice(c->device));
     int rc = prepare(c, a);
     if (rc) return rc;
     return enqueue(c, a, true);
+}
+
+int otoo_quad_exact(otoo_ctx* c, int32_t n, int32_t n_groups, int64_t n_entries, const int64_t* list_off,
+                    const int32_t* list_idx, int64_t n_pairs, const int64_t* pair_off, int32_t n_cells,
+                    const float* cell_mom, int32_t cell_stride, float* corr) {
+    if (!c) return OTOO_EINVAL;
+    c->err.clear();
+    if (n < 1 || n_groups < 1 || n_entries < 0 || n_pairs < 0 || n_pairs > n_entries || n_cells < 0)
+        return fail(c, OTOO_EINVAL, "bad sizes");
+    if (cell_stride != 12) return fail(c, OTOO_EINVAL, "the quadrupole needs cell moments of stride 12");
+    if (!list_off || !pair_off || (n_entries && !list_idx) || (n_cells && !cell_mom) || (n_pairs && !corr))
+        return fail(c, OTOO_EINVAL, "null pointer argument");
+    if (n_pairs == 0) return OTOO_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipLaunchKernelGGL(k_quad_exact, dim3(n_groups), dim3(256), 0, c->stream, n, n_groups, list_off, n_entries,
+                       list_idx, pair_off, n_pairs, n_cells, cell_mom, corr, c->errflag);
+    HIP_TRY(c, hipGetLastError());
+    return OTOO_OK;
 }
 
 int otoo_check(otoo_ctx* c) {
@@ -887,11 +1077,12 @@ int otoo_last_timing(otoo_ctx* c, float* ms_kernel, float* ms_total) {
 int otoo_graph_capture(otoo_ctx* c, int32_t n, const float* pos, const float* mass, int32_t n_groups,
                        const int32_t* group_off, int64_t n_entries, const int64_t* list_off,
                        const int32_t* list_idx, int32_t n_cells, const float* cell_mom, int32_t cell_stride,
-                       float eps, const int64_t* pair_off, const float* corr, float* out_acc, double* out_pot) {
+                       float eps, int64_t n_pairs, const int64_t* pair_off, const float* corr, float* out_acc,
+                       double* out_pot) {
     if (!c) return OTOO_EINVAL;
     c->err.clear();
     Call a{n, pos, mass, n_groups, group_off, n_entries, list_off, list_idx, n_cells, cell_mom, cell_stride, eps,
-           pair_off, corr, out_acc, out_pot};
+           n_pairs, pair_off, corr, out_acc, out_pot};
     HIP_TRY(c, hipSetDevice(c->device));
     int rc = prepare(c, a);  // all allocation happens before capture
     if (rc) return rc;

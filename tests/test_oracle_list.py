@@ -92,3 +92,62 @@ def test_bad_lists_rejected():
     with pytest.raises(ValueError):   # particle entry where a cell tensor is promised
         oracle.list_force(pos, [1, 1], [0, 2], [0, 2], [0, 1], np.zeros((1, 3)), [1.0], 0.1,
                           n_cellent=[1], quad=np.zeros((1, 6)))
+
+
+def test_quad_jacobian_is_derivative_of_field():
+    rng = np.random.default_rng(12)
+    q = rng.normal(size=6)
+    c = np.zeros(3)
+    for eps in (0.0, 0.2):
+        x = rng.normal(size=3) * 2
+        a, J, p = oracle.quad_jacobian(x[None], c[None], q[None], eps)
+        a2, p2 = oracle.quad_field(x[None], c[None], q[None], eps)
+        np.testing.assert_allclose(a, a2, rtol=1e-13)
+        np.testing.assert_allclose(p, p2, rtol=1e-13)
+        h = 1e-5
+        Jfd = np.zeros((3, 3))
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = h
+            ap, _ = oracle.quad_field((x + e)[None], c[None], q[None], eps)
+            am, _ = oracle.quad_field((x - e)[None], c[None], q[None], eps)
+            Jfd[:, k] = (ap[0] - am[0]) / (2 * h)
+        J6 = np.array([Jfd[0, 0], Jfd[1, 1], Jfd[2, 2], Jfd[0, 1], Jfd[0, 2], Jfd[1, 2]])
+        np.testing.assert_allclose(J[0], J6, rtol=1e-6, atol=1e-9 * np.abs(J6).max())
+        np.testing.assert_allclose(Jfd, Jfd.T, atol=1e-6 * np.abs(Jfd).max())
+
+
+def _expanded_vs_exact(spread):
+    # one group of 10 targets near the origin, cells far away carrying tensors
+    rng = np.random.default_rng(13)
+    tg = rng.uniform(-spread, spread, (10, 3))
+    com = np.array([[3.0, 0.5, -0.2], [-2.0, 2.5, 1.0]])
+    pos = np.vstack([tg])
+    m = np.full(10, 1e-3)
+    q = rng.normal(size=(2, 6)) * 0.1
+    args = (pos, m, [0, 10], [0, 12], [10, 11] + list(range(10)), com, [1.0, 2.0], 0.01)
+    a_ex, p_ex = oracle.list_force(*args, n_cellent=[2], quad=q)
+    a_lx, p_lx = oracle.list_force(*args, n_cellent=[2], quad=q, expanded=True)
+    a_mo, p_mo = oracle.list_force(*args)
+    return (np.abs(a_lx - a_ex).max(), np.abs(p_lx - p_ex).max(),
+            np.abs(a_ex - a_mo).max())
+
+
+def test_local_expansion_is_second_order():
+    d1, p1, corr1 = _expanded_vs_exact(0.2)
+    d2, p2, corr2 = _expanded_vs_exact(0.1)
+    assert d1 < 0.05 * corr1
+    assert d1 / d2 == pytest.approx(4.0, rel=0.15)
+    assert p1 / p2 == pytest.approx(4.0, rel=0.15)
+
+
+def test_local_expansion_zero_tensor_is_monopole():
+    rng = np.random.default_rng(14)
+    pos = rng.normal(size=(20, 3))
+    m = rng.uniform(0.5, 1.5, 20)
+    args = (pos, m, [0, 10, 20], [0, 11, 22], [20] + list(range(10)) + [20] + list(range(10, 20)),
+            np.array([[5.0, 5.0, 5.0]]), [3.0], 0.05)
+    a0, p0 = oracle.list_force(*args)
+    a1, p1 = oracle.list_force(*args, n_cellent=[1, 1], quad=np.zeros((2, 6)), expanded=True)
+    np.testing.assert_array_equal(a0, a1)
+    np.testing.assert_array_equal(p0, p1)
