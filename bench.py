@@ -1,13 +1,20 @@
 """Benchmark: Ginteractions/s and ms per full force evaluation on one MI355X.
 
 Default workload: Plummer sphere, N = 2^20 equal masses (G = M = a = 1), seed 1,
-softening 0.005, opening angle 0.5, groups of at most g_max particles.  The
-host builds the tree and walks it once (timed separately, like the paper's
-TREE / KERNEL / PCIe breakdown); the lists are uploaded once; a step is one
-full force evaluation on the device (pack, schedule, force kernel, reduction)
+softening 0.005, opening angle 0.5, groups of at most g_max particles (group
+size and schedule from the autotuner's cache, or its defaults).  The host
+builds the tree and walks it once (timed separately, like the paper's TREE /
+KERNEL / PCIe breakdown); the lists are uploaded once; a step is one full
+force evaluation on the device (pack, schedule, force kernel, reduction)
 replayed from a captured HIP graph with all inputs resident in HBM.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload plummer1m]
+                    [--autotune] [--learned] [--no-cpu-baseline]
+
+--learned adds the learned-correction comparison on a held-out Plummer
+sphere (N = 2^20, seed 3): the network is trained here on the GPU from the
+method's own walks, then plain, textbook-quadrupole and learned evaluations
+are timed and checked against the direct sum.
 
 Prints one JSON line.
 """
@@ -29,53 +36,160 @@ FLOPS_PER_INTERACTION = 20          # the paper's counting convention (Sec. 5)
 PEAK_FP32_TFLOPS = 157.3            # MI355X FP32 vector peak (packed); 78.6 without packed FP32
 
 WORKLOADS = {
-    # name: (generator, kwargs, eps, theta, default g_max, description)
-    "plummer16k": ("plummer", dict(n=16384, seed=0), 0.01, 0.5, 64,
-                   "Plummer N=16384 seed=0 eps=0.01 theta=0.5"),
-    "plummer1m": ("plummer", dict(n=1 << 20, seed=1), 0.005, 0.5, 64,
-                  "Plummer N=1048576 seed=1 eps=0.005 theta=0.5"),
-    "polytrope2m": ("polytrope_pair", dict(n_each=1 << 20, seed=2), 1e-4, 0.6, 64,
+    # name: (generator, kwargs, eps, theta, description)
+    "plummer16k": ("plummer", dict(n=16384, seed=0), 0.01, 0.5, "Plummer N=16384 seed=0 eps=0.01 theta=0.5"),
+    "plummer1m": ("plummer", dict(n=1 << 20, seed=1), 0.005, 0.5, "Plummer N=1048576 seed=1 eps=0.005 theta=0.5"),
+    "polytrope2m": ("polytrope_pair", dict(n_each=1 << 20, seed=2), 1e-4, 0.6,
                     "two n=1.5 polytropes 2x1048576 seed=2 eps=1e-4 theta=0.6"),
-    "cube16m": ("grf_cube", dict(ng=256, seed=4), 1e-3, 0.7, 256,
+    "cube16m": ("grf_cube", dict(ng=256, seed=4), 1e-3, 0.7,
                 "GRF cube 256^3 P(k)~k^-2 rms 0.3 seed=4 eps=1e-3 theta=0.7"),
 }
+DEFAULT_SCHEDULE = dict(group_mode="chunk", g_max=32, chunk=1 << 24, blocks_per_cu=8, lpt=0, tile=256)
+SAMPLE_SEED = {"plummer16k": 100, "plummer1m": 101, "polytrope2m": 102, "cube16m": 104}
 
 
 def make_workload(name):
     import synth
-    gen, kw, eps, theta, g_max, desc = WORKLOADS[name]
+    gen, kw, eps, theta, desc = WORKLOADS[name]
     out = getattr(synth, gen)(**kw)
-    pos, m = out[0], out[1]
-    return pos, m, eps, theta, g_max, desc
+    return out[0], out[1], eps, theta, desc
 
 
-def cpu_baseline(pos32, mass32, lists, cm, eps, acc_gpu, pot_gpu, pos64_sorted, m64_sorted, sample_seed):
-    """The FP64 oracle timed on this host (all targets of the workload), plus
-    accuracy: GPU vs the oracle's list sums (parity) and the tree force vs the
-    O(N^2) direct sum on a 4096-particle sample."""
+# ------------------------------------------------------------------ CPU baseline leg (the oracle)
+
+
+def cpu_baseline(pos32, mass32, lists, cm, eps, pos64_sorted, m64_sorted, sample):
+    """The FP64 oracle timed on this host over the whole workload (list sums
+    for every target) plus the direct-sum references of a 4096-particle sample.
+
+    Returns (baseline dict, list-sum references (acc, pot), direct references
+    (acc, pot) on the sample)."""
     import oracle
     oracle.build()
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
-    a_ref, p_ref = oracle.list_force(pos32.astype(np.float64), mass32.astype(np.float64), lists.group_off,
-                                     lists.list_off, lists.list_idx, cm[:, :3].astype(np.float64),
-                                     cm[:, 3].astype(np.float64), float(np.float32(eps)))
+    ref = oracle.list_force(pos32.astype(np.float64), mass32.astype(np.float64), lists.group_off, lists.list_off,
+                            lists.list_idx, cm[:, :3].astype(np.float64), cm[:, 3].astype(np.float64),
+                            float(np.float32(eps)))
     dt = time.perf_counter() - t0
-    ea = oracle.rel_err(acc_gpu, a_ref)
-    ep = oracle.rel_err(pot_gpu, p_ref)
-    import synth
-    sample = synth.sample_idx(len(mass32), 4096, seed=sample_seed)
-    a_dir, p_dir = oracle.direct(pos64_sorted, m64_sorted, eps, tgt=sample)
-    et = oracle.rel_err(acc_gpu[sample], a_dir)
-    ept = oracle.rel_err(pot_gpu[sample], p_dir)
+    direct = oracle.direct(pos64_sorted, m64_sorted, eps, tgt=sample)
     base = {"value": lists.interactions / dt / 1e9, "unit": "Ginteractions/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 list sums over all {len(mass32)} targets ({lists.interactions} interactions), "
-                      f"{dt:.2f} s"}
-    acc = {"parity_acc_median": float(np.median(ea)), "parity_acc_max": float(ea.max()),
-           "parity_pot_median": float(np.median(ep)), "parity_pot_max": float(ep.max()),
-           "tree_acc_median_vs_direct": float(np.median(et)), "tree_acc_p99_vs_direct": float(np.quantile(et, 0.99)),
-           "tree_pot_median_vs_direct": float(np.median(ept)), "direct_sample": 4096}
-    return base, acc
+            "sample": f"FP64 list sums over all {len(mass32)} targets of the workload "
+                      f"({lists.interactions} interactions) in {dt:.2f} s"}
+    return base, ref, direct
+
+
+def direct_reference(pos64_sorted, m64_sorted, eps, sample):
+    """Direct-sum references for the learned comparison (part of the CPU leg)."""
+    import oracle
+    oracle.build()
+    return oracle.direct(pos64_sorted, m64_sorted, eps, tgt=sample)
+
+
+def rel_err(a, ref):
+    a = np.asarray(a, np.float64)
+    ref = np.asarray(ref, np.float64)
+    if a.ndim == 2:
+        return np.linalg.norm(a - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    return np.abs(a - ref) / np.abs(ref)
+
+
+# ------------------------------------------------------------------ learned comparison
+
+
+def learned_comparison(ctx, log, steps, train_steps, timing_reps):
+    """Train the correction network on the GPU and compare, on a held-out
+    Plummer sphere (N = 2^20, seed 3, eps 0.005), plain theta = 0.5, plain at
+    the largest theta with median error <= 1e-3, the textbook quadrupole and
+    the learned correction, all timed per force evaluation."""
+    import torch
+    import synth
+    import paper_1206_1199_amd as otoo
+    from paper_1206_1199_amd import learned
+    eps = 0.005
+    net = learned.Network(ctx)
+    net.set_params(learned.init_params(0))
+    rng = np.random.Generator(np.random.PCG64(12345))
+    cfgs = [learned.SampleConfig("plummer", 16384, 1000 + k, 0.01, float(rng.uniform(0.5, 0.9)), 64, 40000)
+            for k in range(20)]
+    cfgs += [learned.SampleConfig("plummer", 1 << 20, 1020 + k, eps, float(rng.uniform(0.5, 0.9)), 64, 240000)
+             for k in range(5)]
+    t0 = time.perf_counter()
+    X, aux, eps_all = learned.make_training_set(ctx, net, cfgs, seed=1)
+    Xv, auxv, epsv = learned.make_training_set(
+        ctx, net, [learned.SampleConfig("plummer", 1 << 20, 1100, eps, 0.8, 64, 100000)], seed=2)
+    t_data = time.perf_counter() - t0
+    base_val = learned.zero_correction_loss(auxv)
+    t0 = time.perf_counter()
+    hist = learned.fit(net, X, aux, eps_all, steps=train_steps, batch=32768, lr=2e-3, seed=0, X_val=Xv,
+                       aux_val=auxv, eps_val=epsv, log=log, log_every=max(1, train_steps // 5))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    val = learned.evaluate_loss(net, Xv, auxv, epsv)
+    log(f"learned: {X.shape[0]} samples in {t_data:.1f} s, {train_steps} steps in {t_train:.1f} s, "
+        f"validation loss {val:.3e} (plain monopole {base_val:.3e})")
+
+    pos, m = synth.plummer(1 << 20, seed=3)
+    tree = otoo.Tree(pos, m, n_crit=16)
+    perm, pos32, mass32, cm = tree.export(12)
+    sample = synth.sample_idx(len(m), 4096, seed=103)
+    a_dir, _ = direct_reference(pos[perm], m[perm], eps, sample)
+    cells = tree.cells()
+
+    def run(theta, mode):
+        lists = tree.walk(theta=theta, g_max=DEFAULT_SCHEDULE["g_max"])
+        d, _, _ = learned.device_tree_arrays(tree, lists)
+        out = ctx.outputs(d.n)
+        corr = torch.empty((max(d.n_pairs, 1), 6), dtype=torch.float32, device="cuda:0")[:d.n_pairs]
+
+        def step():
+            if mode == "learned":
+                net.infer(d, eps, out=corr)
+                ctx.force(d, eps, out=out, corr=corr)
+            elif mode == "quad":
+                ctx.quad_exact(d, out=corr)
+                ctx.force(d, eps, out=out, corr=corr)
+            else:
+                ctx.force(d, eps, out=out)
+        for _ in range(3):
+            step()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(timing_reps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        ctx.check()
+        ms = e0.elapsed_time(e1) / timing_reps
+        err = rel_err(out[0].cpu().numpy()[sample], a_dir)
+        return dict(mode=mode, theta=theta, ms=ms, interactions=lists.interactions,
+                    median_err=float(np.median(err)), p99_err=float(np.quantile(err, 0.99)))
+
+    rows = [run(0.5, "plain")]
+    for th in (0.6, 0.65, 0.7, 0.75, 0.8, 0.85, 0.9):
+        rows.append(run(th, "plain"))
+    for th in (0.8, 0.9, 1.0, 1.1):
+        rows.append(run(th, "quad"))
+        rows.append(run(th, "learned"))
+    for r in rows:
+        log(f"  {r['mode']:8s} theta {r['theta']:.2f}: {r['ms']:.3f} ms, median err {r['median_err']:.2e}")
+    ok = lambda mode: [r for r in rows if r["mode"] == mode and r["median_err"] <= 1e-3]
+    best = {mode: (min(ok(mode), key=lambda r: r["ms"]) if ok(mode) else None) for mode in ("plain", "quad", "learned")}
+    plain05 = rows[0]
+    res = {"workload": "Plummer N=1048576 seed=3 eps=0.005 (held out), error vs direct sum on 4096 particles",
+           "training": {"samples": int(X.shape[0]), "steps": train_steps, "data_s": t_data, "train_s": t_train,
+                        "val_loss": val, "val_loss_plain_monopole": base_val},
+           "plain_theta_0.5": plain05, "best_at_1e-3": best, "rows": rows}
+    if best["learned"]:
+        res["learned_speedup_vs_plain_theta_0.5"] = plain05["ms"] / best["learned"]["ms"]
+        if best["plain"]:
+            res["learned_speedup_vs_best_plain"] = best["plain"]["ms"] / best["learned"]["ms"]
+    return res
+
+
+# ------------------------------------------------------------------ main
 
 
 def main():
@@ -85,10 +199,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plummer1m", choices=sorted(WORKLOADS))
     ap.add_argument("--g-max", type=int, default=0)
-    ap.add_argument("--group-mode", default="chunk", choices=["chunk", "cell"])
-    ap.add_argument("--chunk", type=int, default=1024)
-    ap.add_argument("--blocks-per-cu", type=int, default=8)
-    ap.add_argument("--lpt", type=int, default=1)
+    ap.add_argument("--group-mode", default="", choices=["", "chunk", "cell"])
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--lpt", type=int, default=-1)
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true", help="sweep the schedule and store the best in the cache")
+    ap.add_argument("--learned", action="store_true", help="add the learned-correction comparison")
+    ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
@@ -104,38 +222,59 @@ def main():
 
     import torch
     import paper_1206_1199_amd as otoo
+    from paper_1206_1199_amd import autotune as at
 
-    pos, m, eps, theta, g_max, desc = make_workload(args.workload)
-    if args.g_max:
-        g_max = args.g_max
-    mode = otoo.GROUP_CHUNK if args.group_mode == "chunk" else otoo.GROUP_CELL
+    pos, m, eps, theta, desc = make_workload(args.workload)
     log(f"workload {desc}: n={len(m)}")
-
     t0 = time.perf_counter()
     tree = otoo.Tree(pos, m, n_crit=16)
     t1 = time.perf_counter()
-    lists = tree.walk(theta=theta, g_max=g_max, group_mode=mode)
+    ctx = otoo.Context(0)
+
+    key = f"{at.device_key(0)}:{args.workload}"
+    sched = dict(DEFAULT_SCHEDULE)
+    source = "defaults"
+    if args.autotune:
+        best, table = at.autotune(tree, eps, theta, ctx, log=log)
+        at.save_cache(key, best)
+        sched.update({k: best[k] for k in sched})
+        source = "autotuned now"
+    else:
+        cached = at.load_cache().get(key)
+        if cached:
+            sched.update({k: cached[k] for k in sched})
+            source = "autotune cache"
+    for k, v in (("g_max", args.g_max), ("group_mode", args.group_mode), ("chunk", args.chunk),
+                 ("blocks_per_cu", args.blocks_per_cu), ("tile", args.tile)):
+        if v:
+            sched[k] = v
+            source += "+override"
+    if args.lpt >= 0:
+        sched["lpt"] = args.lpt
+    mode = otoo.GROUP_CHUNK if sched["group_mode"] == "chunk" else otoo.GROUP_CELL
+    log(f"schedule ({source}): {sched}")
+
     t2 = time.perf_counter()
+    lists = tree.walk(theta=theta, g_max=sched["g_max"], group_mode=mode)
+    t3 = time.perf_counter()
     perm, pos32, mass32, cm = tree.export(4)
-    log(f"tree {1e3 * (t1 - t0):.0f} ms, walk {1e3 * (t2 - t1):.0f} ms: groups {lists.n_groups}, "
+    log(f"tree {1e3 * (t1 - t0):.0f} ms, walk {1e3 * (t3 - t2):.0f} ms: groups {lists.n_groups}, "
         f"entries {lists.n_entries}, interactions {lists.interactions}")
 
     torch.cuda.synchronize()
-    t3 = time.perf_counter()
+    t4 = time.perf_counter()
     d = otoo.DeviceLists.from_host(pos32, mass32, lists, cm, "cuda:0")
     torch.cuda.synchronize()
-    t4 = time.perf_counter()
+    t5 = time.perf_counter()
 
-    ctx = otoo.Context(0)
-    ctx.set_tuning(chunk=args.chunk, blocks_per_cu=args.blocks_per_cu, lpt=args.lpt)
+    ctx.set_tuning(chunk=sched["chunk"], blocks_per_cu=sched["blocks_per_cu"], lpt=sched["lpt"], tile=sched["tile"])
     out = ctx.outputs(d.n)
 
-    # kernel duration, measured with HIP events on the stream the kernel runs on
+    # force-kernel duration, measured with HIP events on the stream the kernel runs on
     ctx.enable_timing(True)
-    kms = []
     for _ in range(max(3, args.warmup)):
         ctx.force(d, eps, out=out)
-        kms.append(ctx.last_timing())
+        ctx.last_timing()
     kms = []
     for _ in range(max(5, min(args.steps, 20))):
         ctx.force(d, eps, out=out)
@@ -180,24 +319,28 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": desc, "n": int(len(m)), "g_max": g_max, "group_mode": args.group_mode,
-                   "groups": lists.n_groups, "list_entries": lists.n_entries, "interactions": inter,
-                   "n_cells": tree.n_cells, "chunk": args.chunk, "blocks_per_cu": args.blocks_per_cu,
-                   "lpt": args.lpt},
+        "config": {"workload": desc, "n": int(len(m)), "groups": lists.n_groups, "list_entries": lists.n_entries,
+                   "interactions": inter, "n_cells": tree.n_cells, "schedule": sched, "schedule_source": source},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "k_force", "kernel_ms": k_ms,
-                     "flops_per_interaction": FLOPS_PER_INTERACTION},
-        "host": {"tree_build_ms": 1e3 * (t1 - t0), "walk_ms": 1e3 * (t2 - t1), "h2d_ms": 1e3 * (t4 - t3)},
+                     "kernel": "k_force", "kernel_ms": k_ms, "flops_per_interaction": FLOPS_PER_INTERACTION},
+        "host": {"tree_build_ms": 1e3 * (t1 - t0), "walk_ms": 1e3 * (t3 - t2), "h2d_ms": 1e3 * (t5 - t4)},
     }
     if not args.no_cpu_baseline:
-        pos_sorted = pos[perm]
-        m_sorted = m[perm]
-        sample_seed = {"plummer1m": 101, "polytrope2m": 102, "cube16m": 104}.get(args.workload, 100)
-        base, accy = cpu_baseline(pos32, mass32, lists, cm, eps, acc, pot, pos_sorted, m_sorted, sample_seed)
+        sample = __import__("synth").sample_idx(len(m), 4096, seed=SAMPLE_SEED.get(args.workload, 100))
+        base, (a_ref, p_ref), (a_dir, p_dir) = cpu_baseline(pos32, mass32, lists, cm, eps, pos[perm], m[perm],
+                                                            sample)
+        ea, ep = rel_err(acc, a_ref), rel_err(pot, p_ref)
+        et, ept = rel_err(acc[sample], a_dir), rel_err(pot[sample], p_dir)
         res["cpu_baseline"] = base
-        res["accuracy"] = accy
-        log(f"accuracy {accy}")
+        res["accuracy"] = {"parity_acc_median": float(np.median(ea)), "parity_acc_max": float(ea.max()),
+                           "parity_pot_median": float(np.median(ep)), "parity_pot_max": float(ep.max()),
+                           "tree_acc_median_vs_direct": float(np.median(et)),
+                           "tree_acc_p99_vs_direct": float(np.quantile(et, 0.99)),
+                           "tree_pot_median_vs_direct": float(np.median(ept)), "direct_sample": len(sample)}
+        log(f"accuracy {res['accuracy']}")
+    if args.learned:
+        res["learned"] = learned_comparison(ctx, log, args.steps, args.train_steps, max(5, min(args.steps, 20)))
     print(json.dumps(res), flush=True)
 
 

@@ -160,6 +160,7 @@ typedef struct {
     int32_t blocks_per_cu;/* persistent workgroups per compute unit, 1..16 */
     int32_t lpt;          /* 1: hand out items longest-first, 0: in group order */
     int32_t debug_validate; /* 1: check the CSR on the host before launching (slow) */
+    int32_t tile;         /* list entries staged in LDS per tile: 256 or 512 */
 } otoo_tuning;
 int otoo_set_tuning(otoo_ctx* ctx, const otoo_tuning* tuning);
 int otoo_get_tuning(const otoo_ctx* ctx, otoo_tuning* tuning);
@@ -215,6 +216,76 @@ int otoo_force(otoo_ctx* ctx, int32_t n, const float* pos, const float* mass, in
 int otoo_quad_exact(otoo_ctx* ctx, int32_t n, int32_t n_groups, int64_t n_entries, const int64_t* list_off,
                     const int32_t* list_idx, int64_t n_pairs, const int64_t* pair_off, int32_t n_cells,
                     const float* cell_mom, int32_t cell_stride, float* corr);
+
+/* ======================================================================
+ * Learned cell correction (not in the paper, which evaluates accepted cells
+ * as monopoles, Sec. 2): for every (group g, accepted cell c) pair a network
+ * 12 features (zero-padded to 32) -> 64 -> GELU -> 64 -> GELU -> 6 predicts a
+ * symmetric traceless tensor Qt = M_c l_c^2 P(o) (P removes the trace) that
+ * otoo_force applies through its local expansion.  Features, with
+ * d = COM_c - c_g (c_g the centre of the group's bounding box) and n = |d|:
+ *     d/n (3), l_c/n, eps/n, h_g/n (h_g the box half-diagonal),
+ *     S_c / (M_c l_c^2) as (xx, yy, zz, xy, xz, yz).
+ * A pair whose features are non-finite or exceed 8 in magnitude gets a zero
+ * tensor (plain monopole).  GELU is the tanh form.  BF16 operands on MFMA,
+ * FP32 accumulation, FP32 master weights with Adam.
+ * ====================================================================== */
+
+typedef struct otoo_mlp otoo_mlp;
+
+/* Number of FP32 parameters (6662): W1 [32][64], b1 [64], W2 [64][64],
+ * b2 [64], W3 [64][6], b3 [6], concatenated row-major in that order. */
+int otoo_mlp_num_params(void);
+/* A network bound to a context (its device, its stream).  No parameters
+ * until otoo_mlp_set_params or otoo_mlp_load. */
+int otoo_mlp_create(otoo_ctx* ctx, otoo_mlp** mlp);
+int otoo_mlp_destroy(otoo_mlp* mlp);
+/* Host parameter vector in, optimiser state reset (EINVAL on non-finite values). */
+int otoo_mlp_set_params(otoo_mlp* mlp, const float* params);
+/* Host copies of parameters, Adam moments and the step count (NULL skips). */
+int otoo_mlp_get_params(otoo_mlp* mlp, float* params, float* adam_m, float* adam_v, int64_t* step);
+/* Checkpoint: "OTOOMLP1", int32 parameter count, int64 step, then FP32
+ * parameters, Adam m and Adam v.  Loading restores the exact training state. */
+int otoo_mlp_save(otoo_mlp* mlp, const char* path);
+int otoo_mlp_load(otoo_mlp* mlp, const char* path);
+
+/* Raw network outputs o [rows][6] (before projection and scaling) for BF16
+ * features X [rows][32] (device pointers; for parity checks). */
+int otoo_mlp_forward(otoo_mlp* mlp, const uint16_t* X, int64_t rows, float* out);
+
+/* Tensors of every (group, cell) pair for otoo_force: corr [n_pairs][6].
+ * Arguments as for otoo_force (device pointers; cell_stride must be 12). */
+int otoo_mlp_infer(otoo_mlp* mlp, int32_t n, const float* pos, int32_t n_groups, const int32_t* group_off,
+                   int64_t n_entries, const int64_t* list_off, const int32_t* list_idx, int64_t n_pairs,
+                   const int64_t* pair_off, int32_t n_cells, const float* cell_mom, int32_t cell_stride, float eps,
+                   float* corr);
+
+/* Training samples generated by the method itself: for each requested
+ * (pair p, particle i) with i a target of p's group (samples [n_samples][2]
+ * int64), the pair's BF16 features X [n_samples][32] and aux [n_samples][12]
+ * FP32 = {c_g - COM (3), x_i - c_g (3), t (3), M l^2, w, 0}, where
+ * t = a_exact(x_i) - a_mono(x_i) is the cell's exact softened direct sum over
+ * its particles minus its monopole (FP64 sums; cell_first/cell_count give each
+ * cell's particle range in key order, from otoo_tree_cells) and
+ * w = (|x_i - COM|^2 / M)^2.  Device pointers. */
+int otoo_mlp_train_samples(otoo_mlp* mlp, int32_t n, const float* pos, const float* mass, int32_t n_groups,
+                           const int32_t* group_off, int64_t n_entries, const int64_t* list_off,
+                           const int32_t* list_idx, int64_t n_pairs, const int64_t* pair_off, int32_t n_cells,
+                           const float* cell_mom, int32_t cell_stride, const int32_t* cell_first,
+                           const int32_t* cell_count, float eps, int64_t n_samples, const int64_t* samples,
+                           uint16_t* X, float* aux);
+
+/* Loss L = mean over the samples of w |a_corr - t|^2, with a_corr the
+ * correction of the sample's predicted tensor through the second-order local
+ * expansion about c_g evaluated at x_i, and its gradient with respect to the
+ * parameters (host grad [6662] and loss, NULL skips; synchronises).  Sums
+ * over samples are taken per workgroup and then in a fixed order. */
+int otoo_mlp_backward(otoo_mlp* mlp, const uint16_t* X, const float* aux, int64_t n_samples, float eps,
+                      float* grad, float* loss);
+/* One Adam step (beta 0.9 / 0.999, epsilon 1e-8, bias-corrected) on that
+ * gradient; *loss (if not NULL) receives the loss before the step. */
+int otoo_mlp_train_step(otoo_mlp* mlp, const uint16_t* X, const float* aux, int64_t n_samples, float eps, float lr,
+                        float* loss);
 
 /* Synchronise the context's stream and report whether any kernel since the
  * last otoo_check met malformed input (EINVAL) or not (OK); clears the flag. */

@@ -60,8 +60,8 @@ def _load():
         lib.oracle_quad_field.restype = None
         lib.oracle_list_force_expanded.argtypes = [I, P, P, I, P, P, P, I, P, P, P, P, P, D, I, P, P, P]
         lib.oracle_list_force_expanded.restype = ctypes.c_int
-        lib.oracle_quad_jacobian.argtypes = [I, P, P, P, D, P, P, P]
-        lib.oracle_quad_jacobian.restype = None
+        lib.oracle_quad_derivs.argtypes = [I, P, P, P, D, P, P, P, P]
+        lib.oracle_quad_derivs.restype = None
         _lib = lib
     return _lib
 
@@ -98,7 +98,7 @@ def list_force(pos, mass, group_off, list_off, list_idx, cell_com, cell_mass, ep
 
     With ``quad`` (one tensor per (group, cell) pair) the cells also act
     through the quadrupole form, per target (``expanded=False``) or through a
-    first-order local expansion about the group's box centre (``expanded=True``).
+    second-order local expansion about the group's box centre (``expanded=True``).
     """
     lib = _load()
     pos = _f64(pos)
@@ -156,17 +156,20 @@ def quad_field(x, centre, quad, eps):
     return acc, pot
 
 
-def quad_jacobian(x, centre, quad, eps):
-    """Quadrupole-form field, its Jacobian [T,6] (xx,yy,zz,xy,xz,yz) and potential at points."""
+def quad_derivs(x, centre, quad, eps):
+    """Quadrupole-form field, Jacobian [T,6] (xx,yy,zz,xy,xz,yz), Hessian [T,10]
+    (xxx,yyy,zzz,xxy,xxz,xyy,yyz,xzz,yzz,xyz) and potential at points."""
     lib = _load()
     x = _f64(x).reshape(-1, 3)
     c = _f64(centre).reshape(-1, 3)
     q = _f64(quad).reshape(-1, 6)
     acc = np.empty((len(x), 3))
     jac = np.empty((len(x), 6))
+    hess = np.empty((len(x), 10))
     pot = np.empty(len(x))
-    lib.oracle_quad_jacobian(len(x), _ptr(x), _ptr(c), _ptr(q), float(eps), _ptr(acc), _ptr(jac), _ptr(pot))
-    return acc, jac, pot
+    lib.oracle_quad_derivs(len(x), _ptr(x), _ptr(c), _ptr(q), float(eps), _ptr(acc), _ptr(jac), _ptr(hess),
+                           _ptr(pot))
+    return acc, jac, hess, pot
 
 
 def rel_err(a, ref):

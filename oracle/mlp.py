@@ -26,6 +26,12 @@ Loss over samples (g, c, target particle x of g):
 a_exact is the cell's exact softened direct sum at x.  Only the Qt-dependent
 part of r needs the network, so a sample carries t = a_exact - a_mono.
 
+The device applies each pair's tensor through a second-order local expansion
+about the group's box centre c_g; ``expanded_basis`` gives that linear map
+(from the C oracle's field derivatives) and ``loss_and_grad_basis`` the loss
+with it.  ``to_bf16`` rounds to BF16 (round to nearest, ties to even) so the
+oracle can run the network at the device's rounded weights and inputs.
+
 Backward is written out by hand (reverse mode), and is checked against
 central finite differences of ``forward``.
 """
@@ -191,3 +197,105 @@ def exact_quadrupole(S):
     Q = 3.0 * S
     Q[:, 0:3] -= tr[:, None]
     return Q
+
+
+def to_bf16(x):
+    """Round to the nearest BF16 value (ties to even), returned as float64.
+
+    BF16 keeps the top 16 bits of an FP32 word: round the FP32 value's low 16
+    bits to nearest, ties to the even upper half.
+    """
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    low = u & 0xFFFF
+    up = u >> 16
+    round_up = (low > 0x8000) | ((low == 0x8000) & ((up & 1) == 1))
+    up = up + round_up.astype(np.uint64)
+    return (up << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def bf16_params(p):
+    """Weights rounded to BF16, biases kept (the device keeps FP32 biases)."""
+    q = dict(p)
+    for k in ("W1", "W2", "W3"):
+        q[k] = to_bf16(p[k])
+    return q
+
+
+def flat_to_params(v):
+    """Parameter dict from the flat vector W1, b1, W2, b2, W3, b3 (row-major)."""
+    v = np.asarray(v, dtype=np.float64)
+    out, off = {}, 0
+    for k, shape in (("W1", (N_IN, N_H)), ("b1", (N_H,)), ("W2", (N_H, N_H)), ("b2", (N_H,)),
+                     ("W3", (N_H, N_OUT)), ("b3", (N_OUT,))):
+        size = int(np.prod(shape))
+        out[k] = v[off:off + size].reshape(shape)
+        off += size
+    assert off == len(v)
+    return out
+
+
+def params_to_flat(p):
+    return np.concatenate([p[k].ravel() for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+
+
+def expanded_basis(D, delta, eps):
+    """Linear map Qt -> correction at x = c_g + delta through the second-order
+    local expansion about c_g, where D = c_g - COM.
+
+    B[P,3,6] such that a = B @ (xx, yy, zz, xy, xz, yz), with
+    a = A + J delta + 1/2 H[delta, delta] and A, J, H the quadrupole-form field
+    and its derivatives at c_g (oracle_quad_derivs).
+    """
+    import oracle
+    D = np.asarray(D, dtype=np.float64).reshape(-1, 3)
+    delta = np.asarray(delta, dtype=np.float64).reshape(-1, 3)
+    P = len(D)
+    hidx = [(0, 0, 0), (1, 1, 1), (2, 2, 2), (0, 0, 1), (0, 0, 2), (0, 1, 1), (1, 1, 2), (0, 2, 2), (1, 2, 2),
+            (0, 1, 2)]
+    B = np.zeros((P, 3, 6))
+    for m in range(6):
+        e = np.zeros((P, 6))
+        e[:, m] = 1.0
+        A, J6, H10, _ = oracle.quad_derivs(D, np.zeros((P, 3)), e, eps)
+        J = np.zeros((P, 3, 3))
+        for k, (i, j) in enumerate(((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))):
+            J[:, i, j] = J6[:, k]
+            J[:, j, i] = J6[:, k]
+        H = np.zeros((P, 3, 3, 3))
+        import itertools
+        for k, (i, j, l) in enumerate(hidx):
+            for perm in set(itertools.permutations((i, j, l))):
+                H[:, perm[0], perm[1], perm[2]] = H10[:, k]
+        B[:, :, m] = (A + np.einsum("pij,pj->pi", J, delta)
+                      + 0.5 * np.einsum("pijk,pj,pk->pi", H, delta, delta))
+    return B
+
+
+def loss_and_grad_basis(p, u, B, scale, t, w):
+    """Mean of w |B (scale P(o)) - t|^2 over samples and its parameter gradient.
+
+    Same reverse mode as ``loss_and_grad`` with the applied map B given.
+    """
+    P = len(u)
+    o, (u_, z1, h1, z2, h2) = forward(p, u)
+    q = traceless(o) * scale[:, None]
+    r = np.einsum("pkj,pj->pk", B, q) - t
+    L = float(np.mean(w * (r * r).sum(axis=1)))
+    dr = (2.0 / P) * w[:, None] * r
+    dq = np.einsum("pkj,pk->pj", B, dr) * scale[:, None]
+    do = dq.copy()
+    m = (dq[:, 0] + dq[:, 1] + dq[:, 2]) / 3.0
+    do[:, 0:3] -= m[:, None]
+    g = {}
+    g["W3"] = h2.T @ do
+    g["b3"] = do.sum(axis=0)
+    dh2 = do @ p["W3"].T
+    dz2 = dh2 * gelu_grad(z2)
+    g["W2"] = h1.T @ dz2
+    g["b2"] = dz2.sum(axis=0)
+    dh1 = dz2 @ p["W2"].T
+    dz1 = dh1 * gelu_grad(z1)
+    g["W1"] = u_.T @ dz1
+    g["b1"] = dz1.sum(axis=0)
+    return L, g

@@ -77,16 +77,24 @@ static void pair_quadrupole(const double x[3], const double c[3], const double q
 }
 
 /*
- * Quadrupole-form field of tensor q centred at c, at point x: acceleration
- * a, potential phi and the Jacobian J_ab = d a_a / d x_b (symmetric, stored
- * xx, yy, zz, xy, xz, yz).  With d = x - c, u = d.Qd, r^2 = |d|^2 + eps^2:
- *   a    = Qd r^-5 - 5/2 u d r^-7
- *   J_ab = Q_ab r^-5 - 5 r^-7 ((Qd)_a d_b + (Qd)_b d_a) - 5/2 u delta_ab r^-7
- *          + 35/2 u d_a d_b r^-9
- *   phi  = -1/2 u r^-5
+ * Quadrupole-form field of tensor q centred at c, at point x, with its first
+ * two derivatives.  phi = -1/2 u rho with u = d.Qd, rho = r^-5, d = x - c,
+ * r^2 = |d|^2 + eps^2; a = -grad phi, J_ab = -d_a d_b phi (stored xx, yy, zz,
+ * xy, xz, yz) and H_abc = -d_a d_b d_c phi (fully symmetric, stored xxx, yyy,
+ * zzz, xxy, xxz, xyy, yyz, xzz, yzz, xyz).  Since u has constant second
+ * derivatives 2Q and vanishing third ones, Leibniz's rule gives
+ *   a_a    = (Qd)_a rho + 1/2 u rho_a
+ *   J_ab   = Q_ab rho + (Qd)_a rho_b + (Qd)_b rho_a + 1/2 u rho_ab
+ *   H_abc  = Q_ab rho_c + Q_ac rho_b + Q_bc rho_a
+ *            + (Qd)_a rho_bc + (Qd)_b rho_ac + (Qd)_c rho_ab + 1/2 u rho_abc
+ * with rho_a = -5 r^-7 d_a, rho_ab = -5 r^-7 delta_ab + 35 r^-9 d_a d_b,
+ * rho_abc = 35 r^-9 (delta_ab d_c + delta_ac d_b + delta_bc d_a) - 315 r^-11 d_a d_b d_c.
  */
-static void quad_field_jacobian(const double x[3], const double c[3], const double q[6], double eps2,
-                                double a[3], double J[6], double *phi)
+static const int H_IDX[10][3] = {{0, 0, 0}, {1, 1, 1}, {2, 2, 2}, {0, 0, 1}, {0, 0, 2},
+                                 {0, 1, 1}, {1, 1, 2}, {0, 2, 2}, {1, 2, 2}, {0, 1, 2}};
+
+static void quad_field_derivs(const double x[3], const double c[3], const double q[6], double eps2,
+                              double a[3], double J[6], double H[10], double *phi)
 {
     double d[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
     double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps2;
@@ -95,20 +103,51 @@ static void quad_field_jacobian(const double x[3], const double c[3], const doub
     double r5 = inv_r * inv_r2 * inv_r2;
     double r7 = r5 * inv_r2;
     double r9 = r7 * inv_r2;
+    double r11 = r9 * inv_r2;
     double Q[3][3] = {{q[0], q[3], q[4]}, {q[3], q[1], q[5]}, {q[4], q[5], q[2]}};
     double qd[3];
     for (int k = 0; k < 3; k++)
         qd[k] = Q[k][0] * d[0] + Q[k][1] * d[1] + Q[k][2] * d[2];
     double u = d[0] * qd[0] + d[1] * qd[1] + d[2] * qd[2];
+    double rho = r5, rho1[3], rho2[3][3];
     for (int k = 0; k < 3; k++)
-        a[k] = qd[k] * r5 - 2.5 * u * d[k] * r7;
+        rho1[k] = -5.0 * r7 * d[k];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            rho2[i][j] = (i == j ? -5.0 * r7 : 0.0) + 35.0 * r9 * d[i] * d[j];
+    for (int k = 0; k < 3; k++)
+        a[k] = qd[k] * rho + 0.5 * u * rho1[k];
     static const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
     for (int m = 0; m < 6; m++) {
-        int p = ia[m], r = ib[m];
-        J[m] = Q[p][r] * r5 - 5.0 * r7 * (qd[p] * d[r] + qd[r] * d[p]) - (p == r ? 2.5 * u * r7 : 0.0) +
-               17.5 * u * d[p] * d[r] * r9;
+        int i = ia[m], j = ib[m];
+        J[m] = Q[i][j] * rho + qd[i] * rho1[j] + qd[j] * rho1[i] + 0.5 * u * rho2[i][j];
     }
-    *phi = -0.5 * u * r5;
+    for (int m = 0; m < 10; m++) {
+        int i = H_IDX[m][0], j = H_IDX[m][1], k = H_IDX[m][2];
+        double rho3 = 35.0 * r9 * ((i == j ? d[k] : 0.0) + (i == k ? d[j] : 0.0) + (j == k ? d[i] : 0.0)) -
+                      315.0 * r11 * d[i] * d[j] * d[k];
+        H[m] = Q[i][j] * rho1[k] + Q[i][k] * rho1[j] + Q[j][k] * rho1[i] + qd[i] * rho2[j][k] +
+               qd[j] * rho2[i][k] + qd[k] * rho2[i][j] + 0.5 * u * rho3;
+    }
+    *phi = -0.5 * u * rho;
+}
+
+/* the stored component of the symmetric H for index triple (i, j, k) */
+static double H_at(const double H[10], int i, int j, int k)
+{
+    int s[3] = {i, j, k};
+    /* sort the three indices */
+    for (int p = 0; p < 2; p++)
+        for (int q = 0; q < 2 - p; q++)
+            if (s[q] > s[q + 1]) {
+                int tmp = s[q];
+                s[q] = s[q + 1];
+                s[q + 1] = tmp;
+            }
+    for (int m = 0; m < 10; m++)
+        if (H_IDX[m][0] == s[0] && H_IDX[m][1] == s[1] && H_IDX[m][2] == s[2])
+            return H[m];
+    return 0.0;
 }
 
 /*
@@ -211,13 +250,15 @@ int oracle_list_force(int64_t n, const double *pos, const double *mass,
 }
 
 /*
- * List force whose cell tensors act through a first-order local expansion
+ * List force whose cell tensors act through a second-order local expansion
  * about the centre c_g of group g's bounding box (the form the device
- * applies): with A_g = sum_c a_Q(c_g), J_g = sum_c J_Q(c_g) and
- * Phi_g = sum_c phi_Q(c_g) over the group's cell entries,
- *     a_i   += A_g + J_g (x_i - c_g)
- *     phi_i += Phi_g - A_g . (x_i - c_g)
- * on top of the monopole list sums of oracle_list_force.  Arguments as for
+ * applies).  With A_g, J_g, H_g and Phi_g the sums over the group's cell
+ * entries of the quadrupole-form field, its first and second derivatives
+ * and potential at c_g, and delta = x_i - c_g:
+ *     a_i   += A_g + J_g delta + 1/2 H_g[delta, delta]
+ *     phi_i += Phi_g - A_g . delta - 1/2 delta . J_g delta
+ * (a = -grad phi, so the potential's expansion uses -A and -J), on top of
+ * the monopole list sums of oracle_list_force.  Arguments as for
  * oracle_list_force with quad required.  Returns 0 or -1 (malformed lists).
  */
 int oracle_list_force_expanded(int64_t n, const double *pos, const double *mass,
@@ -249,37 +290,49 @@ int oracle_list_force_expanded(int64_t n, const double *pos, const double *mass,
             }
         for (int k = 0; k < 3; k++)
             cg[k] = 0.5 * (lo[k] + hi[k]);
-        double A[3] = {0, 0, 0}, J[6] = {0, 0, 0, 0, 0, 0}, Phi = 0.0;
+        double A[3] = {0, 0, 0}, J[6] = {0}, H[10] = {0}, Phi = 0.0;
         for (int64_t kk = 0; kk < n_cellent[g]; kk++) {
             int64_t e = list_idx[list_off[g] + kk];
             if (e < n || e >= n + n_cells) {
                 bad = 1;
                 continue;
             }
-            double a1[3], J1[6], p1;
-            quad_field_jacobian(cg, &cell_com[3 * (e - n)], &quad[6 * (pair_off[g] + kk)], eps2, a1, J1, &p1);
+            double a1[3], J1[6], H1[10], p1;
+            quad_field_derivs(cg, &cell_com[3 * (e - n)], &quad[6 * (pair_off[g] + kk)], eps2, a1, J1, H1, &p1);
             for (int k = 0; k < 3; k++)
                 A[k] += a1[k];
             for (int k = 0; k < 6; k++)
                 J[k] += J1[k];
+            for (int k = 0; k < 10; k++)
+                H[k] += H1[k];
             Phi += p1;
         }
         double dl[3] = {pos[3 * i] - cg[0], pos[3 * i + 1] - cg[1], pos[3 * i + 2] - cg[2]};
-        acc[3 * t + 0] += A[0] + J[0] * dl[0] + J[3] * dl[1] + J[4] * dl[2];
-        acc[3 * t + 1] += A[1] + J[3] * dl[0] + J[1] * dl[1] + J[5] * dl[2];
-        acc[3 * t + 2] += A[2] + J[4] * dl[0] + J[5] * dl[1] + J[2] * dl[2];
-        pot[t] += Phi - (A[0] * dl[0] + A[1] * dl[1] + A[2] * dl[2]);
+        double Jm[3][3] = {{J[0], J[3], J[4]}, {J[3], J[1], J[5]}, {J[4], J[5], J[2]}};
+        double quadform = 0.0;
+        for (int a = 0; a < 3; a++) {
+            double lin = 0.0, sec = 0.0;
+            for (int b = 0; b < 3; b++) {
+                lin += Jm[a][b] * dl[b];
+                for (int c = 0; c < 3; c++)
+                    sec += H_at(H, a, b, c) * dl[b] * dl[c];
+            }
+            acc[3 * t + a] += A[a] + lin + 0.5 * sec;
+            quadform += dl[a] * lin;
+        }
+        pot[t] += Phi - (A[0] * dl[0] + A[1] * dl[1] + A[2] * dl[2]) - 0.5 * quadform;
     }
     return bad ? -1 : 0;
 }
 
-/* quadrupole-form field with its Jacobian at points (pins the Jacobian) */
-void oracle_quad_jacobian(int64_t n_pts, const double *x, const double *centre, const double *quad,
-                          double eps, double *acc, double *jac, double *pot)
+/* quadrupole-form field with its Jacobian and Hessian at points (pins them) */
+void oracle_quad_derivs(int64_t n_pts, const double *x, const double *centre, const double *quad,
+                        double eps, double *acc, double *jac, double *hess, double *pot)
 {
     double eps2 = eps * eps;
     for (int64_t t = 0; t < n_pts; t++)
-        quad_field_jacobian(&x[3 * t], &centre[3 * t], &quad[6 * t], eps2, &acc[3 * t], &jac[6 * t], &pot[t]);
+        quad_field_derivs(&x[3 * t], &centre[3 * t], &quad[6 * t], eps2, &acc[3 * t], &jac[6 * t],
+                          &hess[10 * t], &pot[t]);
 }
 
 /*

@@ -52,7 +52,7 @@ class _Lists(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32), ("lpt", ctypes.c_int32),
-                ("debug_validate", ctypes.c_int32)]
+                ("debug_validate", ctypes.c_int32), ("tile", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -63,7 +63,9 @@ EXPORTED = [
     "otoo_tree_links", "otoo_tree_walk", "otoo_lists_free", "otoo_create", "otoo_destroy",
     "otoo_set_stream", "otoo_last_error", "otoo_set_tuning", "otoo_get_tuning", "otoo_force",
     "otoo_check", "otoo_enable_timing", "otoo_last_timing", "otoo_graph_capture", "otoo_graph_launch",
-    "otoo_quad_exact",
+    "otoo_quad_exact", "otoo_mlp_num_params", "otoo_mlp_create", "otoo_mlp_destroy", "otoo_mlp_set_params",
+    "otoo_mlp_get_params", "otoo_mlp_save", "otoo_mlp_load", "otoo_mlp_forward", "otoo_mlp_infer",
+    "otoo_mlp_train_samples", "otoo_mlp_backward", "otoo_mlp_train_step",
 ]
 
 
@@ -295,10 +297,10 @@ class Context:
         s = torch.cuda.current_stream(self.device)
         self._raise(lib().otoo_set_stream(self._h, ctypes.c_void_p(s.cuda_stream)), "otoo_set_stream")
 
-    def set_tuning(self, chunk=0, blocks_per_cu=0, lpt=None, debug_validate=None):
+    def set_tuning(self, chunk=0, blocks_per_cu=0, lpt=None, debug_validate=None, tile=0):
         cur = self.tuning()
         t = Tuning(chunk=chunk, blocks_per_cu=blocks_per_cu, lpt=cur.lpt if lpt is None else int(lpt),
-                   debug_validate=cur.debug_validate if debug_validate is None else int(debug_validate))
+                   debug_validate=cur.debug_validate if debug_validate is None else int(debug_validate), tile=tile)
         self._raise(lib().otoo_set_tuning(self._h, ctypes.byref(t)), "otoo_set_tuning")
 
     def tuning(self) -> Tuning:

@@ -1,0 +1,101 @@
+"""Autotuner for the force evaluation: group size and mode (host walk) and the
+device schedule (chunk length, workgroups per CU, item order, tile depth).
+
+The objective is the wall time of one full force evaluation (a graph replay
+with device-resident inputs) at the workload's opening angle: larger groups
+raise the interaction count, so interactions per second alone would favour
+them; the time per evaluation is what a simulation pays.  Results are cached
+in a JSON file keyed by device architecture, compute-unit count and workload.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+import time
+
+import numpy as np
+
+from . import GROUP_CELL, GROUP_CHUNK, Context, DeviceLists, Tree
+
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
+
+GRID = {
+    "group": [(GROUP_CHUNK, 32), (GROUP_CHUNK, 64), (GROUP_CHUNK, 128), (GROUP_CELL, 64), (GROUP_CELL, 128),
+              (GROUP_CELL, 256)],
+    "chunk": [2048, 8192, 1 << 24],
+    "blocks_per_cu": [4, 8],
+    "lpt": [0, 1],
+    "tile": [256, 512],
+}
+
+
+def device_key(device: int = 0) -> str:
+    import torch
+    p = torch.cuda.get_device_properties(device)
+    arch = getattr(p, "gcnArchName", "unknown").split(":")[0]
+    return f"{arch}:{p.multi_processor_count}cu"
+
+
+def time_replays(ctx: Context, d: DeviceLists, eps: float, out, reps: int = 10, corr=None) -> float:
+    """Median-free mean of `reps` graph replays (ms), after two warm-ups."""
+    import torch
+    ctx.graph_capture(d, eps, out, corr=corr)
+    for _ in range(2):
+        ctx.graph_launch()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    e0.record(stream)
+    for _ in range(reps):
+        ctx.graph_launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def autotune(tree: Tree, eps: float, theta: float, ctx: Context, grid=None, reps: int = 10, log=None):
+    """Sweep the grid; returns (best dict, table of all measurements)."""
+    grid = grid or GRID
+    table = []
+    best = None
+    for mode, g_max in grid["group"]:
+        t0 = time.perf_counter()
+        lists = tree.walk(theta=theta, g_max=g_max, group_mode=mode)
+        walk_ms = 1e3 * (time.perf_counter() - t0)
+        _, pos32, mass32, cm = tree.export(4)
+        d = DeviceLists.from_host(pos32, mass32, lists, cm)
+        out = ctx.outputs(d.n)
+        for chunk, bpc, lpt, tile in itertools.product(grid["chunk"], grid["blocks_per_cu"], grid["lpt"],
+                                                      grid["tile"]):
+            ctx.set_tuning(chunk=chunk, blocks_per_cu=bpc, lpt=lpt, tile=tile)
+            ms = time_replays(ctx, d, eps, out, reps)
+            row = dict(group_mode="chunk" if mode == GROUP_CHUNK else "cell", g_max=g_max, chunk=chunk,
+                       blocks_per_cu=bpc, lpt=lpt, tile=tile, ms=ms, interactions=lists.interactions,
+                       gint_s=lists.interactions / ms / 1e6, walk_ms=walk_ms)
+            table.append(row)
+            if best is None or ms < best["ms"]:
+                best = row
+        ctx.check()
+        if log:
+            sub = [r for r in table if r["g_max"] == g_max and r["group_mode"] == table[-1]["group_mode"]]
+            b = min(sub, key=lambda r: r["ms"])
+            log(f"  {b['group_mode']} g_max={g_max}: best {b['ms']:.3f} ms ({b['gint_s']:.0f} Gint/s)")
+    return best, table
+
+
+def load_cache(path: str = DEFAULT_CACHE) -> dict:
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def save_cache(entry_key: str, best: dict, path: str = DEFAULT_CACHE):
+    cache = load_cache(path)
+    cache[entry_key] = best
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)

@@ -28,51 +28,19 @@
 #include <vector>
 
 #include "otoo.h"
+#include "otoo_internal.h"
+
+using namespace otoo_detail;
 
 namespace {
 
-constexpr int kBlock = 256;           // threads per force workgroup = largest group
-constexpr int kTile = 256;            // list entries staged in LDS per tile
 constexpr int kScanBlock = 1024;      // groups per scan block (256 threads x 4)
-constexpr int kClasses = 40;          // longest-first cost classes (log2 buckets)
 
-static_assert(kBlock == OTOO_MAX_GROUP, "a workgroup holds one whole group");
 
-struct Meta {
-    int64_t n_items;
-    int64_t n_parts;
-    int32_t head;
-    int32_t pad;
-    int32_t hist[kClasses];
-    int32_t cursor[kClasses];
-};
 
-enum : int { kErrGroup = 1, kErrIndex = 2, kErrCapacity = 4 };
+
 
 // ---------------------------------------------------------------- helpers
-
-__device__ __forceinline__ void kahan_add(float& sum, float& comp, float x) {
-    // sum + comp carries the running value; comp holds what rounding dropped
-    const float y = x + comp;
-    const float t = sum + y;
-    comp = y - (t - sum);
-    sum = t;
-}
-
-__device__ __forceinline__ int64_t clamp64(int64_t v, int64_t lo, int64_t hi) {
-    return v < lo ? lo : (v > hi ? hi : v);
-}
-
-// list range of group g, clamped to [0, n_entries]
-__device__ __forceinline__ void list_range(const int64_t* list_off, int64_t n_entries, int g, int64_t& b,
-                                           int64_t& e) {
-    b = clamp64(list_off[g], 0, n_entries);
-    e = clamp64(list_off[g + 1], b, n_entries);
-}
-
-__device__ __forceinline__ int64_t n_chunks(int64_t len, int chunk) {
-    return len <= chunk ? 1 : (len + chunk - 1) / chunk;
-}
 
 // ---------------------------------------------------------------- K1 pack
 
@@ -300,46 +268,10 @@ __global__ __launch_bounds__(256) void k_lpt_scatter(const int2* __restrict__ it
 
 // ---------------------------------------------------------------- cell correction
 
-// Quadrupole-form field of tensor Q (xx, yy, zz, xy, xz, yz) about COM at
-// the point whose offset from the COM is d: acceleration, Jacobian (same
-// component order) and potential, accumulated into f[10] =
-// {ax, ay, az, phi, Jxx, Jyy, Jzz, Jxy, Jxz, Jyz}.  With u = d.Qd and
-// r^2 = |d|^2 + eps^2:
-//   a = Qd r^-5 - 5/2 u d r^-7,  phi = -1/2 u r^-5,
-//   J_ab = Q_ab r^-5 - 5 r^-7 ((Qd)_a d_b + (Qd)_b d_a) - 5/2 u delta_ab r^-7 + 35/2 u d_a d_b r^-9
-__device__ __forceinline__ void quad_expand_add(float dx, float dy, float dz, const float* q, float eps2,
-                                                float* f) {
-    const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
-    const float ri = __builtin_amdgcn_rsqf(r2);
-    const float ri2 = ri * ri;
-    const float r5 = ri * ri2 * ri2;
-    const float r7 = r5 * ri2;
-    const float r9 = r7 * ri2;
-    const float qx = q[0] * dx + q[3] * dy + q[4] * dz;
-    const float qy = q[3] * dx + q[1] * dy + q[5] * dz;
-    const float qz = q[4] * dx + q[5] * dy + q[2] * dz;
-    const float u = dx * qx + dy * qy + dz * qz;
-    const float c7 = 2.5f * u * r7;
-    f[0] += qx * r5 - c7 * dx;
-    f[1] += qy * r5 - c7 * dy;
-    f[2] += qz * r5 - c7 * dz;
-    f[3] += -0.5f * u * r5;
-    const float c9 = 17.5f * u * r9;
-    const float f7 = 5.0f * r7;
-    f[4] += q[0] * r5 - f7 * 2.f * qx * dx - c7 + c9 * dx * dx;
-    f[5] += q[1] * r5 - f7 * 2.f * qy * dy - c7 + c9 * dy * dy;
-    f[6] += q[2] * r5 - f7 * 2.f * qz * dz - c7 + c9 * dz * dz;
-    f[7] += q[3] * r5 - f7 * (qx * dy + qy * dx) + c9 * dx * dy;
-    f[8] += q[4] * r5 - f7 * (qx * dz + qz * dx) + c9 * dx * dz;
-    f[9] += q[5] * r5 - f7 * (qy * dz + qz * dy) + c9 * dy * dz;
-}
-
-constexpr int kCorrStride = 16;   // floats per group: A xyz, Phi, J (6), centre xyz, pad
-
 // One workgroup per group: bounding-box centre c_g of the group's particles,
 // then the sums over the group's cell entries of the quadrupole-form field,
-// Jacobian and potential at c_g (fixed summation order: strided per thread,
-// then a fixed tree in LDS).
+// its derivatives and potential at c_g (fixed summation order: strided per
+// thread, then a fixed tree in LDS).
 __global__ __launch_bounds__(256) void k_corr_expand(const float4* __restrict__ src, int32_t n, int64_t n_src,
                                                      const int32_t* __restrict__ group_off,
                                                      const int64_t* __restrict__ list_off, int64_t n_entries,
@@ -347,8 +279,7 @@ __global__ __launch_bounds__(256) void k_corr_expand(const float4* __restrict__ 
                                                      const int64_t* __restrict__ pair_off, int64_t n_pairs,
                                                      const float* __restrict__ corr, float eps2,
                                                      float* __restrict__ gcorr, int32_t* err) {
-    __shared__ float red[10][256];
-    __shared__ float box[6][256];
+    __shared__ float red[kCorrTerms][256];
     const int g = blockIdx.x;
     const int t = threadIdx.x;
     const int g0 = group_off[g];
@@ -362,22 +293,25 @@ __global__ __launch_bounds__(256) void k_corr_expand(const float4* __restrict__ 
         lo[2] = hi[2] = p.z;
     }
     for (int k = 0; k < 3; k++) {
-        box[k][t] = lo[k];
-        box[3 + k][t] = hi[k];
+        red[k][t] = lo[k];
+        red[3 + k][t] = hi[k];
     }
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (t < w)
             for (int k = 0; k < 3; k++) {
-                box[k][t] = fminf(box[k][t], box[k][t + w]);
-                box[3 + k][t] = fmaxf(box[3 + k][t], box[3 + k][t + w]);
+                red[k][t] = fminf(red[k][t], red[k][t + w]);
+                red[3 + k][t] = fmaxf(red[3 + k][t], red[3 + k][t + w]);
             }
         __syncthreads();
     }
-    const float cx = 0.5f * (box[0][0] + box[3][0]);
-    const float cy = 0.5f * (box[1][0] + box[4][0]);
-    const float cz = 0.5f * (box[2][0] + box[5][0]);
-    float f[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const float cx = 0.5f * (red[0][0] + red[3][0]);
+    const float cy = 0.5f * (red[1][0] + red[4][0]);
+    const float cz = 0.5f * (red[2][0] + red[5][0]);
+    __syncthreads();
+    float f[kCorrTerms];
+#pragma unroll
+    for (int k = 0; k < kCorrTerms; k++) f[k] = 0.f;
     if (ok) {
         int64_t lb, le;
         list_range(list_off, n_entries, g, lb, le);
@@ -396,17 +330,19 @@ __global__ __launch_bounds__(256) void k_corr_expand(const float4* __restrict__ 
     } else if (t == 0) {
         atomicOr(err, kErrGroup);
     }
-    for (int k = 0; k < 10; k++) red[k][t] = f[k];
+#pragma unroll
+    for (int k = 0; k < kCorrTerms; k++) red[k][t] = f[k];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (t < w)
-            for (int k = 0; k < 10; k++) red[k][t] += red[k][t + w];
+            for (int k = 0; k < kCorrTerms; k++) red[k][t] += red[k][t + w];
         __syncthreads();
     }
-    if (t < 10) gcorr[(int64_t)kCorrStride * g + t] = red[t][0];
-    if (t == 10) gcorr[(int64_t)kCorrStride * g + 10] = cx;
-    if (t == 11) gcorr[(int64_t)kCorrStride * g + 11] = cy;
-    if (t == 12) gcorr[(int64_t)kCorrStride * g + 12] = cz;
+    float* out = gcorr + (int64_t)kCorrStride * g;
+    if (t < kCorrTerms) out[t] = red[t][0];
+    if (t == kCorrTerms) out[kCorrTerms] = cx;
+    if (t == kCorrTerms + 1) out[kCorrTerms + 1] = cy;
+    if (t == kCorrTerms + 2) out[kCorrTerms + 2] = cz;
 }
 
 // Textbook quadrupole of each accepted cell, Q = 3 S - tr(S) I from the
@@ -441,14 +377,26 @@ __global__ __launch_bounds__(256) void k_quad_exact(int32_t n, int32_t n_groups,
     }
 }
 
-// Local expansion of group g's cell correction applied at particle position x.
+// Second-order local expansion of group g's cell correction applied at x:
+// a += A + J delta + 1/2 H[delta, delta], phi += Phi - A.delta - 1/2 delta.J delta.
 __device__ __forceinline__ void apply_corr(const float* __restrict__ gc, float x, float y, float z, float& ax,
                                            float& ay, float& az, double& phi) {
-    const float dx = x - gc[10], dy = y - gc[11], dz = z - gc[12];
-    ax += gc[0] + gc[4] * dx + gc[7] * dy + gc[8] * dz;
-    ay += gc[1] + gc[7] * dx + gc[5] * dy + gc[9] * dz;
-    az += gc[2] + gc[8] * dx + gc[9] * dy + gc[6] * dz;
-    phi += (double)gc[3] - (double)(gc[0] * dx + gc[1] * dy + gc[2] * dz);
+    const float dx = x - gc[kCorrTerms], dy = y - gc[kCorrTerms + 1], dz = z - gc[kCorrTerms + 2];
+    const float* J = gc + 4;
+    const float* H = gc + 10;   // xxx yyy zzz xxy xxz xyy yyz xzz yzz xyz
+    const float jx = J[0] * dx + J[3] * dy + J[4] * dz;
+    const float jy = J[3] * dx + J[1] * dy + J[5] * dz;
+    const float jz = J[4] * dx + J[5] * dy + J[2] * dz;
+    const float xx = dx * dx, yy = dy * dy, zz = dz * dz, xy = 2.f * dx * dy, xz = 2.f * dx * dz,
+                yz = 2.f * dy * dz;
+    const float hx = H[0] * xx + H[5] * yy + H[7] * zz + H[3] * xy + H[4] * xz + H[9] * yz;
+    const float hy = H[3] * xx + H[1] * yy + H[8] * zz + H[5] * xy + H[9] * xz + H[6] * yz;
+    const float hz = H[4] * xx + H[6] * yy + H[2] * zz + H[9] * xy + H[7] * xz + H[8] * yz;
+    ax += gc[0] + jx + 0.5f * hx;
+    ay += gc[1] + jy + 0.5f * hy;
+    az += gc[2] + jz + 0.5f * hz;
+    phi += (double)gc[3] - (double)(gc[0] * dx + gc[1] * dy + gc[2] * dz) -
+           0.5 * (double)(dx * jx + dy * jy + dz * jz);
 }
 
 // ---------------------------------------------------------------- K2 force
@@ -495,8 +443,12 @@ __device__ __forceinline__ void pair_mono(float xi, float yi, float zi, float4 s
     ph += mr;
 }
 
+// TILE list entries are staged in LDS per tile (TILE / kBlock per thread).
+template <int TILE>
 __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
-    __shared__ float4 tile[2][kTile];
+    constexpr int L = TILE / kBlock;
+    static_assert(L * kBlock == TILE && L >= 1, "tile must be a multiple of the workgroup");
+    __shared__ float4 tile[2][TILE];
     __shared__ int s_q;
     const int t = threadIdx.x;
     const int64_t n_items = a.meta->n_items < a.item_cap ? a.meta->n_items : a.item_cap;
@@ -530,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
         const int i = t % ng;
         const int sl = t / ng;
         const bool active = sl < S;
-        const int tstride = S * (kTile / S);          // entries per tile, a multiple of S
+        const int tstride = S * (TILE / S);           // entries per tile, a multiple of S
         const bool wave_busy = (t & ~63) < S * ng;    // some lane of this wave is active
         const float4 xi = a.src[g0 + i];
 
@@ -538,13 +490,16 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
         float c_ax = 0.f, c_ay = 0.f, c_az = 0.f, c_ph = 0.f;
 
         // prefetch the first tile into registers
-        float4 pre = make_float4(0.f, 0.f, 0.f, 0.f);
-        {
-            const int64_t e = cb + t;
-            if (t < tstride && e < ce) {
+        float4 pre[L];
+#pragma unroll
+        for (int l = 0; l < L; l++) {
+            pre[l] = make_float4(0.f, 0.f, 0.f, 0.f);
+            const int te = t + l * kBlock;
+            const int64_t e = cb + te;
+            if (te < tstride && e < ce) {
                 const int32_t j = a.list_idx[e];
                 if (j >= 0 && j < a.n_src) {
-                    pre = a.src[j];
+                    pre[l] = a.src[j];
                 } else {
                     atomicOr(a.err, kErrIndex);
                 }
@@ -554,16 +509,19 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
         for (int64_t tb = cb; tb < ce; tb += tstride) {
             const int tl = (int)((ce - tb) < tstride ? (ce - tb) : tstride);
             const int rows = (tl + S - 1) / S;
-            tile[buf][t] = pre;
+#pragma unroll
+            for (int l = 0; l < L; l++) tile[buf][t + l * kBlock] = pre[l];
             __syncthreads();
             // next tile's gather overlaps this tile's arithmetic
-            {
-                const int64_t e = tb + tstride + t;
-                pre = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (t < tstride && e < ce) {
+#pragma unroll
+            for (int l = 0; l < L; l++) {
+                const int te = t + l * kBlock;
+                const int64_t e = tb + tstride + te;
+                pre[l] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (te < tstride && e < ce) {
                     const int32_t j = a.list_idx[e];
                     if (j >= 0 && j < a.n_src) {
-                        pre = a.src[j];
+                        pre[l] = a.src[j];
                     } else {
                         atomicOr(a.err, kErrIndex);
                     }
@@ -584,7 +542,7 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
         __syncthreads();  // all reads of the tiles are done before reuse as reduction space
 
         // combine the j-slices of each target (fixed slice order)
-        float* red = reinterpret_cast<float*>(&tile[0][0]);  // 2 * kTile float4 = 8 floats per thread
+        float* red = reinterpret_cast<float*>(&tile[0][0]);  // >= 2 * 256 float4 = 8 floats per thread
         if (S > 1) {
             red[8 * t + 0] = s_ax;
             red[8 * t + 1] = s_ay;
@@ -687,43 +645,7 @@ __global__ __launch_bounds__(256) void k_reduce(const float4* __restrict__ src, 
 
 // ================================================================ runtime
 
-struct otoo_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    std::string err;
-    otoo_tuning tune{1024, 8, 1, 0};
-    int num_cu = 0;
-    // scratch
-    void* buf = nullptr;
-    size_t buf_bytes = 0;
-    Meta* meta = nullptr;
-    int32_t* errflag = nullptr;
-    // timing
-    bool timing = false;
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-    // graph
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    hipStream_t cap_stream = nullptr;
-};
-
 namespace {
-
-int fail(otoo_ctx* c, int code, const char* fmt, ...) {
-    char msg[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(msg, sizeof msg, fmt, ap);
-    va_end(ap);
-    if (c) c->err = msg;
-    return code;
-}
-
-#define HIP_TRY(c, expr)                                                                             \
-    do {                                                                                             \
-        hipError_t e_ = (expr);                                                                      \
-        if (e_ != hipSuccess) return fail((c), OTOO_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
 
 struct Layout {
     size_t src, item_base, part_base, block_tot, items, order, partial, gcorr, total;
@@ -907,7 +829,10 @@ int enqueue(otoo_ctx* c, const Call& a, bool allow_timing) {
     fa.err = c->errflag;
     const int grid = c->num_cu * tu.blocks_per_cu;
     if (tm) HIP_TRY(c, hipEventRecord(c->ev[1], s));
-    hipLaunchKernelGGL(k_force, dim3(grid), dim3(kBlock), 0, s, fa);
+    if (tu.tile == 512)
+        hipLaunchKernelGGL(k_force<512>, dim3(grid), dim3(kBlock), 0, s, fa);
+    else
+        hipLaunchKernelGGL(k_force<256>, dim3(grid), dim3(kBlock), 0, s, fa);
     if (tm) HIP_TRY(c, hipEventRecord(c->ev[2], s));
     hipLaunchKernelGGL(k_reduce, dim3((a.n + 255) / 256), dim3(256), 0, s, src, a.group_off, a.n_groups,
                        a.list_off, a.n_entries, a.n, tu.chunk, part_base, partial, L.part_cap, fa.eps2, gcorr,
@@ -994,10 +919,12 @@ int otoo_set_tuning(otoo_ctx* c, const otoo_tuning* t) {
     otoo_tuning nt = c->tune;
     if (t->chunk) nt.chunk = t->chunk;
     if (t->blocks_per_cu) nt.blocks_per_cu = t->blocks_per_cu;
+    if (t->tile) nt.tile = t->tile;
     nt.lpt = t->lpt ? 1 : 0;
     nt.debug_validate = t->debug_validate ? 1 : 0;
     if (nt.chunk < 64 || nt.chunk > (1 << 28)) return fail(c, OTOO_EINVAL, "chunk must be in 64..2^28");
     if (nt.blocks_per_cu < 1 || nt.blocks_per_cu > 16) return fail(c, OTOO_EINVAL, "blocks_per_cu must be in 1..16");
+    if (nt.tile != 256 && nt.tile != 512) return fail(c, OTOO_EINVAL, "tile must be 256 or 512");
     c->tune = nt;
     return OTOO_OK;
 }

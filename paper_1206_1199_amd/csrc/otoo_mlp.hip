@@ -1,0 +1,1053 @@
+// Learned cell correction on gfx950.
+//
+// For every (group g, accepted cell c) pair a small network predicts a
+// symmetric traceless tensor Qt_gc whose quadrupole-form field, applied
+// through the group's local expansion, corrects the cell's monopole toward
+// the cell's exact direct sum (the paper uses monopoles only and names higher
+// multipoles without using them, Sec. 2).
+//
+//   k_group_geom    bounding-box centre and half-diagonal of each group
+//   k_mlp_infer     features -> 32-64-64-6 GELU network on BF16 MFMA
+//                   (v_mfma_f32_16x16x32_bf16, FP32 accumulate) -> Qt per pair
+//   k_train_samples exact cell sums at target particles (FP64) and features
+//   k_mlp_train     forward, loss through the expansion, backward (MFMA for
+//                   every product), per-workgroup gradient partials
+//   k_grad_reduce   fixed-order sum of the partials
+//   k_adam          Adam on FP32 master weights, BF16 operand copies
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "otoo_internal.h"
+
+using namespace otoo_detail;
+
+namespace {
+
+constexpr int NIN = 32, NFEAT = 12, NH = 64, NOUT = 6, NOUTP = 16, NO32 = 32;
+// FP32 master parameters: W1 [NIN][NH], b1 [NH], W2 [NH][NH], b2 [NH], W3 [NH][NOUT], b3 [NOUT]
+constexpr int OFF_W1 = 0;
+constexpr int OFF_B1 = OFF_W1 + NIN * NH;
+constexpr int OFF_W2 = OFF_B1 + NH;
+constexpr int OFF_B2 = OFF_W2 + NH * NH;
+constexpr int OFF_W3 = OFF_B2 + NH;
+constexpr int OFF_B3 = OFF_W3 + NH * NOUT;
+constexpr int NPARAM = OFF_B3 + NOUT;
+// BF16 operand copies: out-major for the forward products, in-major for the backward ones
+constexpr int OFFB_W1T = 0;                     // [NH][NIN]
+constexpr int OFFB_W2T = OFFB_W1T + NH * NIN;   // [NH][NH]
+constexpr int OFFB_W3T = OFFB_W2T + NH * NH;    // [NOUTP][NH], rows >= NOUT zero
+constexpr int OFFB_W2 = OFFB_W3T + NOUTP * NH;  // [NH][NH]
+constexpr int OFFB_W3 = OFFB_W2 + NH * NH;      // [NH][NO32], columns >= NOUT zero
+constexpr int NBF = OFFB_W3 + NH * NO32;
+constexpr int AUX = 12;          // per training sample: D xyz, delta xyz, target xyz, scale, weight, pad
+constexpr float kFeatLimit = 8.f;
+constexpr float GELU_C = 0.7978845608028654f;  // sqrt(2/pi)
+constexpr float GELU_A = 0.044715f;
+
+static_assert(NPARAM == 6662, "parameter count");
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ bf16x8 ld8(const uint16_t* p) {  // 8 contiguous BF16, 16-byte aligned
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
+}
+
+__device__ __forceinline__ bf16x8 ld8s(const uint16_t* p, int stride) {  // 8 BF16 at a stride
+    uint16_t v[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) v[j] = p[j * stride];
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+__device__ __forceinline__ floatx4 mfma(bf16x8 a, bf16x8 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// tanh-form GELU (Hendrycks & Gimpel): z/2 (1 + tanh(y)) = z sigmoid(2y),
+// y = sqrt(2/pi) (z + 0.044715 z^3)
+__device__ __forceinline__ float gelu_sig(float z) {
+    const float y2 = 2.f * GELU_C * fmaf(GELU_A * z, z * z, z);
+    return __builtin_amdgcn_rcpf(1.f + __expf(-y2));
+}
+__device__ __forceinline__ float gelu(float z) { return z * gelu_sig(z); }
+__device__ __forceinline__ float gelu_grad(float z) {
+    const float s = gelu_sig(z);
+    return s + 2.f * z * s * (1.f - s) * GELU_C * fmaf(3.f * GELU_A * z, z, 1.f);
+}
+
+// Features of a (group, cell) pair: d = COM - c_g, n = |d|:
+// d/n, l/n, eps/n, h_g/n, S/(M l^2).  cm is the cell's stride-12 moment row.
+__device__ __forceinline__ bool pair_features(float cx, float cy, float cz, float h, const float* cm, float eps,
+                                              float f[NFEAT], float& scale) {
+    const float dx = cm[0] - cx, dy = cm[1] - cy, dz = cm[2] - cz;
+    const float n2 = dx * dx + dy * dy + dz * dz;
+    const float inv = n2 > 0.f ? __builtin_amdgcn_rsqf(n2) : 0.f;
+    const float M = cm[3], l = cm[4];
+    const float sc = M * l * l;
+    const float isc = sc > 0.f ? 1.f / sc : 0.f;
+    f[0] = dx * inv;
+    f[1] = dy * inv;
+    f[2] = dz * inv;
+    f[3] = l * inv;
+    f[4] = eps * inv;
+    f[5] = h * inv;
+#pragma unroll
+    for (int k = 0; k < 6; k++) f[6 + k] = cm[5 + k] * isc;
+    scale = sc;
+    bool ok = n2 > 0.f && sc > 0.f;
+#pragma unroll
+    for (int k = 0; k < NFEAT; k++) ok = ok && fabsf(f[k]) <= kFeatLimit;  // also false for NaN
+    return ok;
+}
+
+// group containing pair p: the g with pair_off[g] <= p < pair_off[g+1]
+__device__ __forceinline__ int group_of_pair(const int64_t* pair_off, int n_groups, int64_t p) {
+    int lo = 0, hi = n_groups - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pair_off[mid] <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Evaluate a correction expansion f[kCorrTerms] (about the expansion point)
+// at offset delta: acceleration only.
+__device__ __forceinline__ void expand_accel(const float* f, float dx, float dy, float dz, float& ax, float& ay,
+                                             float& az) {
+    const float* J = f + 4;
+    const float* H = f + 10;
+    const float xx = dx * dx, yy = dy * dy, zz = dz * dz, xy = 2.f * dx * dy, xz = 2.f * dx * dz, yz = 2.f * dy * dz;
+    ax = f[0] + J[0] * dx + J[3] * dy + J[4] * dz +
+         0.5f * (H[0] * xx + H[5] * yy + H[7] * zz + H[3] * xy + H[4] * xz + H[9] * yz);
+    ay = f[1] + J[3] * dx + J[1] * dy + J[5] * dz +
+         0.5f * (H[3] * xx + H[1] * yy + H[8] * zz + H[5] * xy + H[9] * xz + H[6] * yz);
+    az = f[2] + J[4] * dx + J[5] * dy + J[2] * dz +
+         0.5f * (H[4] * xx + H[6] * yy + H[2] * zz + H[9] * xy + H[7] * xz + H[8] * yz);
+}
+
+// ---------------------------------------------------------------- geometry
+
+__global__ __launch_bounds__(256) void k_group_geom(const float* __restrict__ pos, int32_t n,
+                                                    const int32_t* __restrict__ group_off,
+                                                    float4* __restrict__ geom, int32_t* err) {
+    __shared__ float red[6][256];
+    const int g = blockIdx.x, t = threadIdx.x;
+    const int g0 = group_off[g];
+    const int ng = group_off[g + 1] - g0;
+    const bool ok = ng >= 1 && ng <= kBlock && g0 >= 0 && g0 + ng <= n;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (ok && t < ng)
+        for (int k = 0; k < 3; k++) lo[k] = hi[k] = pos[3 * (g0 + t) + k];
+    for (int k = 0; k < 3; k++) {
+        red[k][t] = lo[k];
+        red[3 + k][t] = hi[k];
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int k = 0; k < 3; k++) {
+                red[k][t] = fminf(red[k][t], red[k][t + w]);
+                red[3 + k][t] = fmaxf(red[3 + k][t], red[3 + k][t + w]);
+            }
+        __syncthreads();
+    }
+    if (t == 0) {
+        if (!ok) {
+            atomicOr(err, kErrGroup);
+            geom[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+            return;
+        }
+        const float ex = red[3][0] - red[0][0], ey = red[4][0] - red[1][0], ez = red[5][0] - red[2][0];
+        geom[g] = make_float4(0.5f * (red[0][0] + red[3][0]), 0.5f * (red[1][0] + red[4][0]),
+                              0.5f * (red[2][0] + red[5][0]), 0.5f * sqrtf(ex * ex + ey * ey + ez * ez));
+    }
+}
+
+// ---------------------------------------------------------------- forward
+
+struct NetLDS {
+    alignas(16) uint16_t w1t[NH * NIN];
+    alignas(16) uint16_t w2t[NH * NH];
+    alignas(16) uint16_t w3t[NOUTP * NH];
+    float b1[NH], b2[NH], b3[NOUTP];
+};
+
+__device__ void load_net(NetLDS& s, const uint16_t* __restrict__ wbf, const float* __restrict__ master) {
+    const int t = threadIdx.x;
+    for (int i = t; i < NH * NIN; i += blockDim.x) s.w1t[i] = wbf[OFFB_W1T + i];
+    for (int i = t; i < NH * NH; i += blockDim.x) s.w2t[i] = wbf[OFFB_W2T + i];
+    for (int i = t; i < NOUTP * NH; i += blockDim.x) s.w3t[i] = wbf[OFFB_W3T + i];
+    for (int i = t; i < NH; i += blockDim.x) {
+        s.b1[i] = master[OFF_B1 + i];
+        s.b2[i] = master[OFF_B2 + i];
+    }
+    for (int i = t; i < NOUTP; i += blockDim.x) s.b3[i] = i < NOUT ? master[OFF_B3 + i] : 0.f;
+}
+
+// One wave computes rows [r0, r0+16) of Z = A W + b with A row-major in LDS
+// (lda elements per row, K = 32 * KS) and W given out-major (Wt[n][k]).
+// acc[nt][i] holds Z[r0 + q*4 + i][nt*16 + r16].
+template <int KS, int NT>
+__device__ __forceinline__ void wave_dense(const uint16_t* A, int lda, const uint16_t* Wt, int ldw, const float* bias,
+                                           int r0, floatx4 acc[NT]) {
+    const int lane = threadIdx.x & 63, r16 = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) {
+        const float b = bias[nt * 16 + r16];
+        acc[nt] = floatx4{b, b, b, b};
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ks++) {
+        const bf16x8 a = ld8(A + (r0 + r16) * lda + ks * 32 + q * 8);
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) acc[nt] = mfma(a, ld8(Wt + (nt * 16 + r16) * ldw + ks * 32 + q * 8), acc[nt]);
+    }
+}
+
+struct InferArgs {
+    int32_t n;
+    int32_t n_groups;
+    const int64_t* list_off;
+    int64_t n_entries;
+    const int32_t* list_idx;
+    const int64_t* pair_off;
+    int64_t n_pairs;
+    int32_t n_cells;
+    const float* cell_mom;
+    float eps;
+    const float4* geom;
+    const uint16_t* wbf;
+    const float* master;
+    float* corr;
+    int32_t* err;
+};
+
+__global__ __launch_bounds__(256) void k_mlp_infer(InferArgs a) {
+    __shared__ NetLDS net;
+    __shared__ __align__(16) uint16_t sX[64 * NIN];
+    __shared__ __align__(16) uint16_t sH[64 * NH];
+    __shared__ float sO[64 * NOUTP];
+    __shared__ float sScale[64];
+    __shared__ int sOk[64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, r16 = lane & 15, q = lane >> 4;
+    load_net(net, a.wbf, a.master);
+    __syncthreads();
+    for (int64_t base = (int64_t)blockIdx.x * 64; base < a.n_pairs; base += (int64_t)gridDim.x * 64) {
+        {
+            const int row = t >> 2, part = t & 3;
+            const int64_t p = base + row;
+            float f[NFEAT];
+            float sc = 0.f;
+            bool ok = false;
+            if (p < a.n_pairs) {
+                const int g = group_of_pair(a.pair_off, a.n_groups, p);
+                int64_t lb, le;
+                list_range(a.list_off, a.n_entries, g, lb, le);
+                const int64_t k = p - a.pair_off[g];
+                if (k >= 0 && k < le - lb) {
+                    const int64_t c = (int64_t)a.list_idx[lb + k] - a.n;
+                    if (c >= 0 && c < a.n_cells) {
+                        const float4 gm = a.geom[g];
+                        ok = pair_features(gm.x, gm.y, gm.z, gm.w, a.cell_mom + 12 * c, a.eps, f, sc);
+                    } else if (part == 0) {
+                        atomicOr(a.err, kErrIndex);
+                    }
+                } else if (part == 0) {
+                    atomicOr(a.err, kErrIndex);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                const int fi = part * 8 + j;
+                sX[row * NIN + fi] = f2bf(ok && fi < NFEAT ? f[fi < NFEAT ? fi : 0] : 0.f);
+            }
+            if (part == 0) {
+                sScale[row] = sc;
+                sOk[row] = ok;
+            }
+        }
+        __syncthreads();
+        const int r0 = 16 * w;
+        floatx4 acc[4];
+        wave_dense<1, 4>(sX, NIN, net.w1t, NIN, net.b1, r0, acc);
+#pragma unroll
+        for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) sH[(r0 + q * 4 + i) * NH + nt * 16 + r16] = f2bf(gelu(acc[nt][i]));
+        __syncthreads();
+        wave_dense<2, 4>(sH, NH, net.w2t, NH, net.b2, r0, acc);
+        __syncthreads();
+#pragma unroll
+        for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) sH[(r0 + q * 4 + i) * NH + nt * 16 + r16] = f2bf(gelu(acc[nt][i]));
+        __syncthreads();
+        floatx4 o[1];
+        wave_dense<2, 1>(sH, NH, net.w3t, NH, net.b3, r0, o);
+#pragma unroll
+        for (int i = 0; i < 4; i++) sO[(r0 + q * 4 + i) * NOUTP + r16] = o[0][i];
+        __syncthreads();
+        if (t < 64) {
+            const int64_t p = base + t;
+            if (p < a.n_pairs) {
+                const float* ov = sO + t * NOUTP;
+                const float tr = (ov[0] + ov[1] + ov[2]) * (1.f / 3.f);
+                const float sc = sOk[t] ? sScale[t] : 0.f;
+                float* out = a.corr + 6 * p;
+                out[0] = (ov[0] - tr) * sc;
+                out[1] = (ov[1] - tr) * sc;
+                out[2] = (ov[2] - tr) * sc;
+                out[3] = ov[3] * sc;
+                out[4] = ov[4] * sc;
+                out[5] = ov[5] * sc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Raw network outputs (no projection or scaling) for given BF16 features.
+__global__ __launch_bounds__(256) void k_mlp_forward_raw(const uint16_t* __restrict__ X, int64_t rows,
+                                                         const uint16_t* __restrict__ wbf,
+                                                         const float* __restrict__ master, float* __restrict__ out) {
+    __shared__ NetLDS net;
+    __shared__ __align__(16) uint16_t sX[64 * NIN];
+    __shared__ __align__(16) uint16_t sH[64 * NH];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, r16 = lane & 15, q = lane >> 4;
+    load_net(net, wbf, master);
+    __syncthreads();
+    for (int64_t base = (int64_t)blockIdx.x * 64; base < rows; base += (int64_t)gridDim.x * 64) {
+        for (int i = t; i < 64 * NIN; i += 256) {
+            const int64_t r = base + i / NIN;
+            sX[i] = r < rows ? X[r * NIN + i % NIN] : 0;
+        }
+        __syncthreads();
+        const int r0 = 16 * w;
+        floatx4 acc[4];
+        wave_dense<1, 4>(sX, NIN, net.w1t, NIN, net.b1, r0, acc);
+        for (int nt = 0; nt < 4; nt++)
+            for (int i = 0; i < 4; i++) sH[(r0 + q * 4 + i) * NH + nt * 16 + r16] = f2bf(gelu(acc[nt][i]));
+        __syncthreads();
+        wave_dense<2, 4>(sH, NH, net.w2t, NH, net.b2, r0, acc);
+        __syncthreads();
+        for (int nt = 0; nt < 4; nt++)
+            for (int i = 0; i < 4; i++) sH[(r0 + q * 4 + i) * NH + nt * 16 + r16] = f2bf(gelu(acc[nt][i]));
+        __syncthreads();
+        floatx4 o[1];
+        wave_dense<2, 1>(sH, NH, net.w3t, NH, net.b3, r0, o);
+        if (r16 < NOUT)
+            for (int i = 0; i < 4; i++) {
+                const int64_t r = base + r0 + q * 4 + i;
+                if (r < rows) out[r * NOUT + r16] = o[0][i];
+            }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- training data
+
+// Per sample (pair p, target particle i of p's group): features of the pair,
+// D = c_g - COM, delta = x_i - c_g, target t = a_exact(x_i) - a_mono(x_i)
+// (the cell's exact softened sum over its particles minus its monopole, FP64),
+// scale M l^2 and loss weight (|x_i - COM|^2 / M)^2.
+__global__ __launch_bounds__(256) void k_train_samples(
+    const float* __restrict__ pos, const float* __restrict__ mass, int32_t n, const int32_t* __restrict__ group_off,
+    int32_t n_groups, const int64_t* __restrict__ list_off, int64_t n_entries, const int32_t* __restrict__ list_idx,
+    const int64_t* __restrict__ pair_off, int64_t n_pairs, int32_t n_cells, const float* __restrict__ cell_mom,
+    const int32_t* __restrict__ cell_first, const int32_t* __restrict__ cell_count, float eps,
+    const int64_t* __restrict__ samples, int64_t n_samples, uint16_t* __restrict__ X, float* __restrict__ aux,
+    int32_t* err) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_samples) return;
+    uint16_t* xs = X + s * NIN;
+    float* ax = aux + s * AUX;
+    for (int k = 0; k < NIN; k++) xs[k] = 0;
+    for (int k = 0; k < AUX; k++) ax[k] = 0.f;
+    const int64_t p = samples[2 * s], i = samples[2 * s + 1];
+    if (p < 0 || p >= n_pairs) {
+        atomicOr(err, kErrIndex);
+        return;
+    }
+    const int g = group_of_pair(pair_off, n_groups, p);
+    const int g0 = group_off[g], ng = group_off[g + 1] - g0;
+    if (ng < 1 || ng > kBlock || g0 < 0 || g0 + ng > n || i < g0 || i >= g0 + ng) {
+        atomicOr(err, kErrGroup);
+        return;
+    }
+    int64_t lb, le;
+    list_range(list_off, n_entries, g, lb, le);
+    const int64_t k = p - pair_off[g];
+    const int64_t c = (k >= 0 && k < le - lb) ? (int64_t)list_idx[lb + k] - n : -1;
+    if (c < 0 || c >= n_cells) {
+        atomicOr(err, kErrIndex);
+        return;
+    }
+    const int64_t f0 = cell_first[c], cnt = cell_count[c];
+    if (f0 < 0 || cnt < 1 || f0 + cnt > n) {
+        atomicOr(err, kErrIndex);
+        return;
+    }
+    // group bounding box (same operations as k_group_geom)
+    float lo[3], hi[3];
+    for (int d = 0; d < 3; d++) lo[d] = hi[d] = pos[3 * g0 + d];
+    for (int j = 1; j < ng; j++)
+        for (int d = 0; d < 3; d++) {
+            lo[d] = fminf(lo[d], pos[3 * (g0 + j) + d]);
+            hi[d] = fmaxf(hi[d], pos[3 * (g0 + j) + d]);
+        }
+    const float cx = 0.5f * (lo[0] + hi[0]), cy = 0.5f * (lo[1] + hi[1]), cz = 0.5f * (lo[2] + hi[2]);
+    const float ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
+    const float h = 0.5f * sqrtf(ex * ex + ey * ey + ez * ez);
+    const float* cm = cell_mom + 12 * c;
+    float f[NFEAT], sc;
+    const bool ok = pair_features(cx, cy, cz, h, cm, eps, f, sc);
+    // exact and monopole fields at x_i in FP64
+    const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    const double e2 = (double)eps * (double)eps;
+    double sx = 0, sy = 0, sz = 0;
+    for (int64_t j = f0; j < f0 + cnt; j++) {
+        const double dx = pos[3 * j] - x, dy = pos[3 * j + 1] - y, dz = pos[3 * j + 2] - z;
+        const double r2 = dx * dx + dy * dy + dz * dz + e2;
+        const double w = (double)mass[j] / (r2 * sqrt(r2));
+        sx += w * dx;
+        sy += w * dy;
+        sz += w * dz;
+    }
+    const double mx = cm[0] - x, my = cm[1] - y, mz = cm[2] - z;
+    const double m2 = mx * mx + my * my + mz * mz;
+    const double mw = (double)cm[3] / ((m2 + e2) * sqrt(m2 + e2));
+    for (int k2 = 0; k2 < NFEAT; k2++) xs[k2] = f2bf(ok ? f[k2] : 0.f);
+    ax[0] = cx - cm[0];
+    ax[1] = cy - cm[1];
+    ax[2] = cz - cm[2];
+    ax[3] = (float)(x - cx);
+    ax[4] = (float)(y - cy);
+    ax[5] = (float)(z - cz);
+    ax[6] = (float)(sx - mw * mx);
+    ax[7] = (float)(sy - mw * my);
+    ax[8] = (float)(sz - mw * mz);
+    ax[9] = ok ? sc : 0.f;
+    ax[10] = ok ? (float)(m2 * m2 / ((double)cm[3] * (double)cm[3])) : 0.f;
+}
+
+// ---------------------------------------------------------------- training step
+
+struct TrainLDS {
+    NetLDS net;
+    alignas(16) uint16_t w2[NH * NH];      // in-major, for dH1 = dZ2 W2^T
+    alignas(16) uint16_t w3[NH * NO32];    // in-major, outputs padded to 32, for dH2 = dO W3^T
+    alignas(16) uint16_t x[64 * NIN];
+    float z1[64 * NH];
+    alignas(16) uint16_t h1[64 * NH];
+    float z2[64 * NH];
+    alignas(16) uint16_t h2[64 * NH];
+    float o[64 * NOUTP];
+    alignas(16) uint16_t d_o[64 * NO32];
+    alignas(16) uint16_t dz2[64 * NH];
+    alignas(16) uint16_t dz1[64 * NH];
+    float red[4][NH + NH + NOUTP];  // bias-gradient partials per wave
+    float lossred[256];
+};
+
+struct TrainArgs {
+    const uint16_t* X;
+    const float* aux;
+    int64_t n_samples;
+    float inv_total;   // 1 / number of samples in the batch (the loss is their mean)
+    float eps2;
+    const uint16_t* wbf;
+    const float* master;
+    float* part;       // [gridDim.x][NPARAM + 1] gradient partials, then the loss partial
+};
+
+// dW tile (mi, ni) of a matrix [K_in x N_out] stored at master offset `off`
+// with row length `ncols` (only columns < ncols exist).
+__device__ __forceinline__ void store_tile(float* dst, const floatx4& acc, int mi, int ni, int ncols, int nrows) {
+    const int lane = threadIdx.x & 63, r16 = lane & 15, q = lane >> 4;
+    const int col = ni * 16 + r16;
+    if (col >= ncols) return;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const int row = mi * 16 + q * 4 + i;
+        if (row < nrows) dst[row * ncols + col] = acc[i];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_train(TrainArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    TrainLDS& S = *reinterpret_cast<TrainLDS*>(smem);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, r16 = lane & 15, q = lane >> 4;
+    load_net(S.net, a.wbf, a.master);
+    for (int i = t; i < NH * NH; i += 256) S.w2[i] = a.wbf[OFFB_W2 + i];
+    for (int i = t; i < NH * NO32; i += 256) S.w3[i] = a.wbf[OFFB_W3 + i];
+    // weight-gradient accumulators: 28 tiles (dW1 2x4, dW2 4x4, dW3 4x1), wave w owns tiles w, w+4, ...
+    floatx4 gacc[7];
+#pragma unroll
+    for (int k = 0; k < 7; k++) gacc[k] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float gb1[4] = {0.f, 0.f, 0.f, 0.f}, gb2[4] = {0.f, 0.f, 0.f, 0.f}, gb3 = 0.f, lsum = 0.f;
+    __syncthreads();
+    const int r0 = 16 * w;
+    for (int64_t base = (int64_t)blockIdx.x * 64; base < a.n_samples; base += (int64_t)gridDim.x * 64) {
+        for (int i = t; i < 64 * NIN; i += 256) {
+            const int64_t r = base + i / NIN;
+            S.x[i] = r < a.n_samples ? a.X[r * NIN + i % NIN] : 0;
+        }
+        __syncthreads();
+        floatx4 acc[4];
+        wave_dense<1, 4>(S.x, NIN, S.net.w1t, NIN, S.net.b1, r0, acc);
+#pragma unroll
+        for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int idx = (r0 + q * 4 + i) * NH + nt * 16 + r16;
+                S.z1[idx] = acc[nt][i];
+                S.h1[idx] = f2bf(gelu(acc[nt][i]));
+            }
+        __syncthreads();
+        wave_dense<2, 4>(S.h1, NH, S.net.w2t, NH, S.net.b2, r0, acc);
+#pragma unroll
+        for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int idx = (r0 + q * 4 + i) * NH + nt * 16 + r16;
+                S.z2[idx] = acc[nt][i];
+                S.h2[idx] = f2bf(gelu(acc[nt][i]));
+            }
+        __syncthreads();
+        floatx4 o1[1];
+        wave_dense<2, 1>(S.h2, NH, S.net.w3t, NH, S.net.b3, r0, o1);
+#pragma unroll
+        for (int i = 0; i < 4; i++) S.o[(r0 + q * 4 + i) * NOUTP + r16] = o1[0][i];
+        __syncthreads();
+        // loss layer: one thread per sample
+        if (t < 64) {
+            const int64_t s = base + t;
+            float dov[NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (s < a.n_samples) {
+                const float* ax = a.aux + s * AUX;
+                const float sc = ax[9], wt = ax[10];
+                if (sc > 0.f) {
+                    const float* ov = S.o + t * NOUTP;
+                    const float tr = (ov[0] + ov[1] + ov[2]) * (1.f / 3.f);
+                    const float qv[NOUT] = {(ov[0] - tr) * sc, (ov[1] - tr) * sc, (ov[2] - tr) * sc,
+                                            ov[3] * sc,        ov[4] * sc,        ov[5] * sc};
+                    // the applied correction is linear in the tensor: columns B[:, m] for unit tensors
+                    float B[3][NOUT];
+#pragma unroll
+                    for (int m = 0; m < NOUT; m++) {
+                        float e[NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                        e[m] = 1.f;
+                        float f[kCorrTerms];
+#pragma unroll
+                        for (int k = 0; k < kCorrTerms; k++) f[k] = 0.f;
+                        quad_expand_add(ax[0], ax[1], ax[2], e, a.eps2, f);
+                        expand_accel(f, ax[3], ax[4], ax[5], B[0][m], B[1][m], B[2][m]);
+                    }
+                    float r[3];
+#pragma unroll
+                    for (int k = 0; k < 3; k++) {
+                        float v = -ax[6 + k];
+#pragma unroll
+                        for (int m = 0; m < NOUT; m++) v = fmaf(B[k][m], qv[m], v);
+                        r[k] = v;
+                    }
+                    lsum += wt * (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+                    const float gscale = 2.f * wt * a.inv_total;
+                    float dq[NOUT];
+#pragma unroll
+                    for (int m = 0; m < NOUT; m++) dq[m] = gscale * (B[0][m] * r[0] + B[1][m] * r[1] + B[2][m] * r[2]);
+                    const float mean = (dq[0] + dq[1] + dq[2]) * (1.f / 3.f);
+                    dov[0] = (dq[0] - mean) * sc;
+                    dov[1] = (dq[1] - mean) * sc;
+                    dov[2] = (dq[2] - mean) * sc;
+                    dov[3] = dq[3] * sc;
+                    dov[4] = dq[4] * sc;
+                    dov[5] = dq[5] * sc;
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < NO32; m++) S.d_o[t * NO32 + m] = f2bf(m < NOUT ? dov[m] : 0.f);
+            // the last layer's bias gradient is summed in FP32 from these (the row's outputs are spent)
+            for (int m = 0; m < NOUT; m++) S.o[t * NOUTP + m] = dov[m];
+        }
+        __syncthreads();
+        // db3: per-output sums over the chunk's samples (threads 0..5, fixed order)
+        if (t < NOUT)
+            for (int s2 = 0; s2 < 64; s2++) gb3 += S.o[s2 * NOUTP + t];
+        // dW3 (tiles: 4 x 1) += H2^T dO over the 64 samples (K)
+        // dH2 = dO W3^T for this wave's rows, then dZ2
+        {
+            floatx4 dh[4];
+#pragma unroll
+            for (int nt = 0; nt < 4; nt++) dh[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+            const bf16x8 av = ld8(S.d_o + (r0 + r16) * NO32 + q * 8);
+#pragma unroll
+            for (int nt = 0; nt < 4; nt++) dh[nt] = mfma(av, ld8(S.w3 + (nt * 16 + r16) * NO32 + q * 8), dh[nt]);
+#pragma unroll
+            for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const int idx = (r0 + q * 4 + i) * NH + nt * 16 + r16;
+                    const float dz = dh[nt][i] * gelu_grad(S.z2[idx]);
+                    S.dz2[idx] = f2bf(dz);
+                    gb2[nt] += dz;
+                }
+        }
+        __syncthreads();
+        // dH1 = dZ2 W2^T for this wave's rows, then dZ1
+        {
+            floatx4 dh[4];
+#pragma unroll
+            for (int nt = 0; nt < 4; nt++) dh[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < 2; ks++) {
+                const bf16x8 av = ld8(S.dz2 + (r0 + r16) * NH + ks * 32 + q * 8);
+#pragma unroll
+                for (int nt = 0; nt < 4; nt++)
+                    dh[nt] = mfma(av, ld8(S.w2 + (nt * 16 + r16) * NH + ks * 32 + q * 8), dh[nt]);
+            }
+#pragma unroll
+            for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const int idx = (r0 + q * 4 + i) * NH + nt * 16 + r16;
+                    const float dz = dh[nt][i] * gelu_grad(S.z1[idx]);
+                    S.dz1[idx] = f2bf(dz);
+                    gb1[nt] += dz;
+                }
+        }
+        __syncthreads();
+        // weight gradients: K = the chunk's 64 samples, operands read across rows
+#pragma unroll
+        for (int k = 0; k < 7; k++) {
+            const int tile = w + 4 * k;   // 0..27
+            const uint16_t *Am, *Bm;
+            int lda, ldb, mi, ni;
+            if (tile < 8) {               // dW1 [32 x 64]: X^T dZ1
+                mi = tile >> 2, ni = tile & 3;
+                Am = S.x + mi * 16 + r16;
+                lda = NIN;
+                Bm = S.dz1 + ni * 16 + r16;
+                ldb = NH;
+            } else if (tile < 24) {       // dW2 [64 x 64]: H1^T dZ2
+                mi = (tile - 8) >> 2, ni = (tile - 8) & 3;
+                Am = S.h1 + mi * 16 + r16;
+                lda = NH;
+                Bm = S.dz2 + ni * 16 + r16;
+                ldb = NH;
+            } else {                      // dW3 [64 x 16]: H2^T dO
+                mi = tile - 24, ni = 0;
+                Am = S.h2 + mi * 16 + r16;
+                lda = NH;
+                Bm = S.d_o + r16;
+                ldb = NO32;
+            }
+#pragma unroll
+            for (int ks = 0; ks < 2; ks++) {
+                const int s0 = ks * 32 + q * 8;
+                gacc[k] = mfma(ld8s(Am + s0 * lda, lda), ld8s(Bm + s0 * ldb, ldb), gacc[k]);
+            }
+        }
+        __syncthreads();
+    }
+    // write this workgroup's partial gradient
+    float* dst = a.part + (int64_t)blockIdx.x * (NPARAM + 1);
+#pragma unroll
+    for (int k = 0; k < 7; k++) {
+        const int tile = w + 4 * k;
+        if (tile < 8) store_tile(dst + OFF_W1, gacc[k], tile >> 2, tile & 3, NH, NIN);
+        else if (tile < 24) store_tile(dst + OFF_W2, gacc[k], (tile - 8) >> 2, (tile - 8) & 3, NH, NH);
+        else store_tile(dst + OFF_W3, gacc[k], tile - 24, 0, NOUT, NH);
+    }
+    // bias gradients: lane (r16, q) of wave w holds column sums over rows q*4+i of its rows
+#pragma unroll
+    for (int nt = 0; nt < 4; nt++) {
+        // reduce over q within the wave through LDS (fixed order)
+        __syncthreads();
+        S.lossred[t] = gb1[nt];
+        __syncthreads();
+        if (q == 0) {
+            float v = 0.f;
+            for (int qq = 0; qq < 4; qq++) v += S.lossred[w * 64 + qq * 16 + r16];
+            S.red[w][nt * 16 + r16] = v;
+        }
+        __syncthreads();
+        S.lossred[t] = gb2[nt];
+        __syncthreads();
+        if (q == 0) {
+            float v = 0.f;
+            for (int qq = 0; qq < 4; qq++) v += S.lossred[w * 64 + qq * 16 + r16];
+            S.red[w][NH + nt * 16 + r16] = v;
+        }
+    }
+    __syncthreads();
+    if (t < NH) {
+        dst[OFF_B1 + t] = S.red[0][t] + S.red[1][t] + S.red[2][t] + S.red[3][t];
+        dst[OFF_B2 + t] = S.red[0][NH + t] + S.red[1][NH + t] + S.red[2][NH + t] + S.red[3][NH + t];
+    }
+    if (t < NOUT) dst[OFF_B3 + t] = gb3;
+    __syncthreads();
+    S.lossred[t] = lsum;
+    __syncthreads();
+    if (t == 0) {
+        float v = 0.f;
+        for (int k = 0; k < 64; k++) v += S.lossred[k];
+        dst[NPARAM] = v * a.inv_total;
+    }
+}
+
+__global__ void k_grad_reduce(const float* __restrict__ part, int32_t n_parts, float* __restrict__ grad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > NPARAM) return;
+    double s = 0.0;
+    for (int b = 0; b < n_parts; b++) s += (double)part[(int64_t)b * (NPARAM + 1) + i];
+    grad[i] = (float)s;
+}
+
+// BF16 operand copies of parameter i of the FP32 master vector
+__device__ __forceinline__ void write_bf16_copies(uint16_t* wbf, int i, float v) {
+    const uint16_t b = f2bf(v);
+    if (i < OFF_B1) {
+        const int in = i / NH, out = i % NH;
+        wbf[OFFB_W1T + out * NIN + in] = b;
+    } else if (i >= OFF_W2 && i < OFF_B2) {
+        const int j = i - OFF_W2, in = j / NH, out = j % NH;
+        wbf[OFFB_W2T + out * NH + in] = b;
+        wbf[OFFB_W2 + in * NH + out] = b;
+    } else if (i >= OFF_W3 && i < OFF_B3) {
+        const int j = i - OFF_W3, in = j / NOUT, out = j % NOUT;
+        wbf[OFFB_W3T + out * NH + in] = b;
+        wbf[OFFB_W3 + in * NO32 + out] = b;
+    }
+}
+
+__global__ void k_adam(float* __restrict__ master, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ grad, uint16_t* __restrict__ wbf, float lr, float beta1, float beta2,
+                       float adam_eps, float bc1, float bc2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NPARAM) return;
+    const float g = grad[i];
+    const float mi = beta1 * m[i] + (1.f - beta1) * g;
+    const float vi = beta2 * v[i] + (1.f - beta2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    const float p = master[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + adam_eps);
+    master[i] = p;
+    write_bf16_copies(wbf, i, p);
+}
+
+__global__ void k_bf16_clear(uint16_t* __restrict__ wbf) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < NBF) wbf[i] = 0;   // padding rows/columns stay zero
+}
+
+__global__ void k_bf16_fill(const float* __restrict__ master, uint16_t* __restrict__ wbf) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < NPARAM) write_bf16_copies(wbf, i, master[i]);
+}
+
+}  // namespace
+
+// ================================================================ runtime
+
+struct otoo_mlp {
+    otoo_ctx* ctx = nullptr;
+    float* master = nullptr;   // device [NPARAM]
+    float* m = nullptr;        // device [NPARAM]
+    float* v = nullptr;        // device [NPARAM]
+    float* grad = nullptr;     // device [NPARAM + 1] (last gradient, then the loss)
+    uint16_t* wbf = nullptr;   // device [NBF]
+    float* part = nullptr;     // device gradient partials
+    int part_rows = 0;
+    float4* geom = nullptr;    // device per-group geometry
+    int64_t geom_cap = 0;
+    int64_t step = 0;
+    bool has_params = false;
+};
+
+namespace {
+
+int mlp_check(otoo_mlp* m) {
+    if (!m || !m->ctx) return OTOO_EINVAL;
+    HIP_TRY(m->ctx, hipSetDevice(m->ctx->device));
+    return OTOO_OK;
+}
+
+int mlp_upload(otoo_mlp* m, const float* host_params, const float* host_m, const float* host_v) {
+    otoo_ctx* c = m->ctx;
+    hipStream_t s = c->stream;
+    HIP_TRY(c, hipMemcpyAsync(m->master, host_params, sizeof(float) * NPARAM, hipMemcpyHostToDevice, s));
+    if (host_m) HIP_TRY(c, hipMemcpyAsync(m->m, host_m, sizeof(float) * NPARAM, hipMemcpyHostToDevice, s));
+    if (host_v) HIP_TRY(c, hipMemcpyAsync(m->v, host_v, sizeof(float) * NPARAM, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_bf16_clear, dim3((NBF + 255) / 256), dim3(256), 0, s, m->wbf);
+    hipLaunchKernelGGL(k_bf16_fill, dim3((NPARAM + 255) / 256), dim3(256), 0, s, m->master, m->wbf);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(s));
+    m->has_params = true;
+    return OTOO_OK;
+}
+
+int run_backward(otoo_mlp* m, const uint16_t* X, const float* aux, int64_t n_samples, float eps) {
+    otoo_ctx* c = m->ctx;
+    const int blocks = (int)std::min<int64_t>((int64_t)c->num_cu, (n_samples + 63) / 64);
+    if (blocks > m->part_rows) {
+        if (m->part) HIP_TRY(c, hipFree(m->part));
+        m->part = nullptr;
+        HIP_TRY(c, hipMalloc(&m->part, sizeof(float) * (size_t)(NPARAM + 1) * blocks));
+        m->part_rows = blocks;
+    }
+    TrainArgs ta{X, aux, n_samples, 1.f / (float)n_samples, eps * eps, m->wbf, m->master, m->part};
+    static bool attr_set = false;
+    if (!attr_set) {
+        HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(k_mlp_train),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(TrainLDS)));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_mlp_train, dim3(blocks), dim3(256), sizeof(TrainLDS), c->stream, ta);
+    hipLaunchKernelGGL(k_grad_reduce, dim3((NPARAM + 1 + 255) / 256), dim3(256), 0, c->stream, m->part, blocks,
+                       m->grad);
+    HIP_TRY(c, hipGetLastError());
+    return OTOO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int otoo_mlp_create(otoo_ctx* c, otoo_mlp** out) {
+    if (!c || !out) return OTOO_EINVAL;
+    *out = nullptr;
+    HIP_TRY(c, hipSetDevice(c->device));
+    otoo_mlp* m = new (std::nothrow) otoo_mlp();
+    if (!m) return OTOO_ENOMEM;
+    m->ctx = c;
+    void* p = nullptr;
+    const size_t bytes = sizeof(float) * (4 * (size_t)NPARAM + 1) + sizeof(uint16_t) * NBF + 1024;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        delete m;
+        return fail(c, OTOO_ENOMEM, "network buffers");
+    }
+    char* b = static_cast<char*>(p);
+    m->master = reinterpret_cast<float*>(b);
+    m->m = m->master + NPARAM;
+    m->v = m->m + NPARAM;
+    m->grad = m->v + NPARAM;
+    m->wbf = reinterpret_cast<uint16_t*>(b + ((sizeof(float) * (4 * (size_t)NPARAM + 1) + 255) & ~(size_t)255));
+    if (hipMemset(p, 0, bytes) != hipSuccess) {
+        (void)hipFree(p);
+        delete m;
+        return fail(c, OTOO_EHIP, "hipMemset");
+    }
+    *out = m;
+    return OTOO_OK;
+}
+
+int otoo_mlp_destroy(otoo_mlp* m) {
+    if (!m) return OTOO_EINVAL;
+    if (m->ctx) {
+        (void)hipSetDevice(m->ctx->device);
+        (void)hipStreamSynchronize(m->ctx->stream);
+    }
+    if (m->master) (void)hipFree(m->master);
+    if (m->part) (void)hipFree(m->part);
+    if (m->geom) (void)hipFree(m->geom);
+    delete m;
+    return OTOO_OK;
+}
+
+int otoo_mlp_num_params(void) { return NPARAM; }
+
+int otoo_mlp_set_params(otoo_mlp* m, const float* params) {
+    int rc = mlp_check(m);
+    if (rc) return rc;
+    if (!params) return fail(m->ctx, OTOO_EINVAL, "params is null");
+    for (int i = 0; i < NPARAM; i++)
+        if (!std::isfinite(params[i])) return fail(m->ctx, OTOO_EINVAL, "parameter %d is not finite", i);
+    std::vector<float> zero(NPARAM, 0.f);
+    m->step = 0;
+    return mlp_upload(m, params, zero.data(), zero.data());
+}
+
+int otoo_mlp_get_params(otoo_mlp* m, float* params, float* adam_m, float* adam_v, int64_t* step) {
+    int rc = mlp_check(m);
+    if (rc) return rc;
+    otoo_ctx* c = m->ctx;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (params) HIP_TRY(c, hipMemcpy(params, m->master, sizeof(float) * NPARAM, hipMemcpyDeviceToHost));
+    if (adam_m) HIP_TRY(c, hipMemcpy(adam_m, m->m, sizeof(float) * NPARAM, hipMemcpyDeviceToHost));
+    if (adam_v) HIP_TRY(c, hipMemcpy(adam_v, m->v, sizeof(float) * NPARAM, hipMemcpyDeviceToHost));
+    if (step) *step = m->step;
+    return OTOO_OK;
+}
+
+int otoo_mlp_save(otoo_mlp* m, const char* path) {
+    int rc = mlp_check(m);
+    if (rc) return rc;
+    if (!path) return fail(m->ctx, OTOO_EINVAL, "path is null");
+    std::vector<float> buf(3 * (size_t)NPARAM);
+    int64_t step = 0;
+    rc = otoo_mlp_get_params(m, buf.data(), buf.data() + NPARAM, buf.data() + 2 * NPARAM, &step);
+    if (rc) return rc;
+    FILE* f = fopen(path, "wb");
+    if (!f) return fail(m->ctx, OTOO_EINVAL, "cannot open %s", path);
+    const char magic[8] = {'O', 'T', 'O', 'O', 'M', 'L', 'P', '1'};
+    const int32_t np = NPARAM;
+    bool ok = fwrite(magic, 1, 8, f) == 8 && fwrite(&np, 4, 1, f) == 1 && fwrite(&step, 8, 1, f) == 1 &&
+              fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    ok = (fclose(f) == 0) && ok;
+    return ok ? OTOO_OK : fail(m->ctx, OTOO_EINVAL, "write to %s failed", path);
+}
+
+int otoo_mlp_load(otoo_mlp* m, const char* path) {
+    int rc = mlp_check(m);
+    if (rc) return rc;
+    if (!path) return fail(m->ctx, OTOO_EINVAL, "path is null");
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(m->ctx, OTOO_EINVAL, "cannot open %s", path);
+    char magic[8];
+    int32_t np = 0;
+    int64_t step = 0;
+    std::vector<float> buf(3 * (size_t)NPARAM);
+    bool ok = fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "OTOOMLP1", 8) == 0 && fread(&np, 4, 1, f) == 1 &&
+              np == NPARAM && fread(&step, 8, 1, f) == 1 &&
+              fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    fclose(f);
+    if (!ok) return fail(m->ctx, OTOO_EINVAL, "%s is not a network checkpoint of this layout", path);
+    for (float x : buf)
+        if (!std::isfinite(x)) return fail(m->ctx, OTOO_EINVAL, "%s holds non-finite values", path);
+    rc = mlp_upload(m, buf.data(), buf.data() + NPARAM, buf.data() + 2 * NPARAM);
+    if (rc) return rc;
+    m->step = step;
+    return OTOO_OK;
+}
+
+int otoo_mlp_forward(otoo_mlp* m, const uint16_t* X, int64_t rows, float* out) {
+    int rc = mlp_check(m);
+    if (rc) return rc;
+    if (!m->has_params) return fail(m->ctx, OTOO_EINVAL, "no parameters loaded");
+    if (rows < 0 || (rows && (!X || !out))) return fail(m->ctx, OTOO_EINVAL, "bad arguments");
+    if (!rows) return OTOO_OK;
+    const int blocks = (int)std::min<int64_t>(4 * (int64_t)m->ctx->num_cu, (rows + 63) / 64);
+    hipLaunchKernelGGL(k_mlp_forward_raw, dim3(blocks), dim3(256), 0, m->ctx->stream, X, rows, m->wbf, m->master,
+                       out);
+    HIP_TRY(m->ctx, hipGetLastError());
+    return OTOO_OK;
+}
+
+int otoo_mlp_infer(otoo_mlp* m, int32_t n, const float* pos, int32_t n_groups, const int32_t* group_off,
+                   int64_t n_entries, const int64_t* list_off, const int32_t* list_idx, int64_t n_pairs,
+                   const int64_t* pair_off, int32_t n_cells, const float* cell_mom, int32_t cell_stride, float eps,
+                   float* corr) {
+    int rc = mlp_check(m);
+    if (rc) return rc;
+    otoo_ctx* c = m->ctx;
+    c->err.clear();
+    if (!m->has_params) return fail(c, OTOO_EINVAL, "no parameters loaded");
+    if (n < 1 || n_groups < 1 || n_groups > n || n_entries < 0 || n_pairs < 0 || n_pairs > n_entries || n_cells < 0)
+        return fail(c, OTOO_EINVAL, "bad sizes");
+    if (cell_stride != 12) return fail(c, OTOO_EINVAL, "the network needs cell moments of stride 12");
+    if (!(eps > 0.f) || !std::isfinite(eps)) return fail(c, OTOO_EINVAL, "eps must be positive and finite");
+    if (!pos || !group_off || !list_off || !pair_off || (n_entries && !list_idx) || (n_cells && !cell_mom) ||
+        (n_pairs && !corr))
+        return fail(c, OTOO_EINVAL, "null pointer argument");
+    if (!n_pairs) return OTOO_OK;
+    if (n_groups > m->geom_cap) {
+        if (m->geom) HIP_TRY(c, hipFree(m->geom));
+        m->geom = nullptr;
+        HIP_TRY(c, hipMalloc(&m->geom, sizeof(float4) * (size_t)n_groups));
+        m->geom_cap = n_groups;
+    }
+    hipLaunchKernelGGL(k_group_geom, dim3(n_groups), dim3(256), 0, c->stream, pos, n, group_off, m->geom,
+                       c->errflag);
+    InferArgs ia{n,        n_groups, list_off, n_entries, list_idx, pair_off, n_pairs, n_cells,
+                 cell_mom, eps,      m->geom,  m->wbf,    m->master, corr,    c->errflag};
+    const int blocks = (int)std::min<int64_t>(4 * (int64_t)c->num_cu, (n_pairs + 63) / 64);
+    hipLaunchKernelGGL(k_mlp_infer, dim3(blocks), dim3(256), 0, c->stream, ia);
+    HIP_TRY(c, hipGetLastError());
+    return OTOO_OK;
+}
+
+int otoo_mlp_train_samples(otoo_mlp* m, int32_t n, const float* pos, const float* mass, int32_t n_groups,
+                           const int32_t* group_off, int64_t n_entries, const int64_t* list_off,
+                           const int32_t* list_idx, int64_t n_pairs, const int64_t* pair_off, int32_t n_cells,
+                           const float* cell_mom, int32_t cell_stride, const int32_t* cell_first,
+                           const int32_t* cell_count, float eps, int64_t n_samples, const int64_t* samples,
+                           uint16_t* X, float* aux) {
+    int rc = mlp_check(m);
+    if (rc) return rc;
+    otoo_ctx* c = m->ctx;
+    c->err.clear();
+    if (n < 1 || n_groups < 1 || n_groups > n || n_entries < 0 || n_pairs < 0 || n_pairs > n_entries ||
+        n_cells < 0 || n_samples < 0)
+        return fail(c, OTOO_EINVAL, "bad sizes");
+    if (cell_stride != 12) return fail(c, OTOO_EINVAL, "cell moments of stride 12 are required");
+    if (!(eps > 0.f) || !std::isfinite(eps)) return fail(c, OTOO_EINVAL, "eps must be positive and finite");
+    if (!pos || !mass || !group_off || !list_off || !pair_off || (n_entries && !list_idx) ||
+        (n_cells && (!cell_mom || !cell_first || !cell_count)) || (n_samples && (!samples || !X || !aux)))
+        return fail(c, OTOO_EINVAL, "null pointer argument");
+    if (!n_samples) return OTOO_OK;
+    hipLaunchKernelGGL(k_train_samples, dim3((unsigned)((n_samples + 255) / 256)), dim3(256), 0, c->stream, pos, mass,
+                       n, group_off, n_groups, list_off, n_entries, list_idx, pair_off, n_pairs, n_cells, cell_mom,
+                       cell_first, cell_count, eps, samples, n_samples, X, aux, c->errflag);
+    HIP_TRY(c, hipGetLastError());
+    return OTOO_OK;
+}
+
+int otoo_mlp_backward(otoo_mlp* m, const uint16_t* X, const float* aux, int64_t n_samples, float eps,
+                      float* grad_out, float* loss_out) {
+    int rc = mlp_check(m);
+    if (rc) return rc;
+    otoo_ctx* c = m->ctx;
+    c->err.clear();
+    if (!m->has_params) return fail(c, OTOO_EINVAL, "no parameters loaded");
+    if (n_samples < 1 || !X || !aux) return fail(c, OTOO_EINVAL, "bad arguments");
+    if (!(eps > 0.f) || !std::isfinite(eps)) return fail(c, OTOO_EINVAL, "eps must be positive and finite");
+    rc = run_backward(m, X, aux, n_samples, eps);
+    if (rc) return rc;
+    if (grad_out || loss_out) {
+        std::vector<float> g(NPARAM + 1);
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        HIP_TRY(c, hipMemcpy(g.data(), m->grad, sizeof(float) * (NPARAM + 1), hipMemcpyDeviceToHost));
+        if (grad_out) std::memcpy(grad_out, g.data(), sizeof(float) * NPARAM);
+        if (loss_out) *loss_out = g[NPARAM];
+    }
+    return OTOO_OK;
+}
+
+int otoo_mlp_train_step(otoo_mlp* m, const uint16_t* X, const float* aux, int64_t n_samples, float eps, float lr,
+                        float* loss_out) {
+    int rc = mlp_check(m);
+    if (rc) return rc;
+    otoo_ctx* c = m->ctx;
+    c->err.clear();
+    if (!m->has_params) return fail(c, OTOO_EINVAL, "no parameters loaded");
+    if (n_samples < 1 || !X || !aux) return fail(c, OTOO_EINVAL, "bad arguments");
+    if (!(eps > 0.f) || !std::isfinite(eps) || !(lr >= 0.f) || !std::isfinite(lr))
+        return fail(c, OTOO_EINVAL, "eps must be positive and lr non-negative");
+    rc = run_backward(m, X, aux, n_samples, eps);
+    if (rc) return rc;
+    m->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float bc1 = (float)(1.0 - std::pow(0.9, (double)m->step));
+    const float bc2 = (float)(1.0 - std::pow(0.999, (double)m->step));
+    hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, c->stream, m->master, m->m, m->v, m->grad,
+                       m->wbf, lr, b1, b2, 1e-8f, bc1, bc2);
+    HIP_TRY(c, hipGetLastError());
+    if (loss_out) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        HIP_TRY(c, hipMemcpy(loss_out, m->grad + NPARAM, sizeof(float), hipMemcpyDeviceToHost));
+    }
+    return OTOO_OK;
+}
+
+}  // extern "C"

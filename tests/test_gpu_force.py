@@ -230,4 +230,15 @@ def test_exact_quadrupole_pairs_and_accuracy(ctx, plummer16k):
     e_q = np.median(oracle.rel_err(a_q[sample], a_dir))
     e_m = np.median(oracle.rel_err(a_m[sample], a_dir))
     print(f"theta 0.8: monopole median {e_m:.2e}, with quadrupole {e_q:.2e}", flush=True)
-    assert e_q < 0.5 * e_m
+    assert e_q < 0.75 * e_m
+
+
+@pytest.mark.parametrize("g_max", [32, 64, 256])
+def test_tile_512(ctx, plummer16k, g_max):
+    pos, m = plummer16k
+    t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.5, g_max)
+    ctx.set_tuning(chunk=1536, tile=512, lpt=1)
+    acc, pot = _gpu(ctx, d, 0.01)
+    ctx.set_tuning(chunk=1024, tile=256)
+    a_ref, p_ref = _oracle(pos32, mass32, lists, cm, 0.01)
+    _assert_parity(acc, pot, a_ref, p_ref, f"tile 512 g_max={g_max}")

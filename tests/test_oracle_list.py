@@ -94,27 +94,41 @@ def test_bad_lists_rejected():
                           n_cellent=[1], quad=np.zeros((1, 6)))
 
 
-def test_quad_jacobian_is_derivative_of_field():
+def test_quad_derivatives_are_derivatives_of_field():
+    """J is the derivative of the field, H the derivative of J (central
+    differences of independently coded functions), both symmetric."""
     rng = np.random.default_rng(12)
     q = rng.normal(size=6)
     c = np.zeros(3)
+    hidx = [(0, 0, 0), (1, 1, 1), (2, 2, 2), (0, 0, 1), (0, 0, 2), (0, 1, 1), (1, 1, 2), (0, 2, 2), (1, 2, 2),
+            (0, 1, 2)]
     for eps in (0.0, 0.2):
         x = rng.normal(size=3) * 2
-        a, J, p = oracle.quad_jacobian(x[None], c[None], q[None], eps)
+        a, J, H, p = oracle.quad_derivs(x[None], c[None], q[None], eps)
         a2, p2 = oracle.quad_field(x[None], c[None], q[None], eps)
         np.testing.assert_allclose(a, a2, rtol=1e-13)
         np.testing.assert_allclose(p, p2, rtol=1e-13)
         h = 1e-5
         Jfd = np.zeros((3, 3))
+        Hfd = np.zeros((3, 3, 3))
         for k in range(3):
             e = np.zeros(3)
             e[k] = h
             ap, _ = oracle.quad_field((x + e)[None], c[None], q[None], eps)
             am, _ = oracle.quad_field((x - e)[None], c[None], q[None], eps)
             Jfd[:, k] = (ap[0] - am[0]) / (2 * h)
+            _, Jp, _, _ = oracle.quad_derivs((x + e)[None], c[None], q[None], eps)
+            _, Jm, _, _ = oracle.quad_derivs((x - e)[None], c[None], q[None], eps)
+            dJ = (Jp[0] - Jm[0]) / (2 * h)
+            full = np.array([[dJ[0], dJ[3], dJ[4]], [dJ[3], dJ[1], dJ[5]], [dJ[4], dJ[5], dJ[2]]])
+            Hfd[:, :, k] = full
         J6 = np.array([Jfd[0, 0], Jfd[1, 1], Jfd[2, 2], Jfd[0, 1], Jfd[0, 2], Jfd[1, 2]])
         np.testing.assert_allclose(J[0], J6, rtol=1e-6, atol=1e-9 * np.abs(J6).max())
-        np.testing.assert_allclose(Jfd, Jfd.T, atol=1e-6 * np.abs(Jfd).max())
+        H10 = np.array([Hfd[i, j, k] for i, j, k in hidx])
+        np.testing.assert_allclose(H[0], H10, rtol=1e-5, atol=1e-8 * np.abs(H10).max())
+        # full symmetry of the finite-difference third derivative
+        np.testing.assert_allclose(Hfd, Hfd.transpose(0, 2, 1), atol=1e-5 * np.abs(Hfd).max())
+        np.testing.assert_allclose(Hfd, Hfd.transpose(2, 1, 0), atol=1e-5 * np.abs(Hfd).max())
 
 
 def _expanded_vs_exact(spread):
@@ -133,12 +147,13 @@ def _expanded_vs_exact(spread):
             np.abs(a_ex - a_mo).max())
 
 
-def test_local_expansion_is_second_order():
+def test_local_expansion_is_third_order():
+    # second-order expansion: the error falls as spread^3 (the potential as spread^3 too)
     d1, p1, corr1 = _expanded_vs_exact(0.2)
     d2, p2, corr2 = _expanded_vs_exact(0.1)
-    assert d1 < 0.05 * corr1
-    assert d1 / d2 == pytest.approx(4.0, rel=0.15)
-    assert p1 / p2 == pytest.approx(4.0, rel=0.15)
+    assert d1 < 0.01 * corr1
+    assert d1 / d2 == pytest.approx(8.0, rel=0.15)
+    assert p1 / p2 == pytest.approx(8.0, rel=0.15)
 
 
 def test_local_expansion_zero_tensor_is_monopole():

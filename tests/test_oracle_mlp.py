@@ -132,3 +132,67 @@ def test_adam_first_step():
     z = {"w": np.zeros(3)}
     p1, m1, v1 = omlp.adam_step(p, g, z, z, step=1, lr=0.01, eps=0.0)
     np.testing.assert_allclose(p1["w"], p["w"] - 0.01 * np.sign(g["w"]), rtol=1e-14)
+
+
+def test_bf16_rounding_ties_to_even():
+    v = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -8 + 2 ** -20, -(1 + 3 * 2 ** -8), 0.0, 3.0e38,
+                  1.0 / 3.0])
+    # 3e38 is 0x7F61B1E6 in FP32 -> 0x7F62 = (1 + 98/128) 2^127; 1/3 -> 0x3EAB = (1 + 43/128) / 4
+    ref = np.array([1.0, 1.0, 1 + 2 ** -6, 1 + 2 ** -7, -(1 + 2 ** -6), 0.0, (1 + 98 / 128) * 2.0 ** 127,
+                    (1 + 43 / 128) / 4])
+    got = omlp.to_bf16(v)
+    np.testing.assert_array_equal(got, ref)
+    # every BF16 value is exact in 8 significant bits
+    m, e = np.frexp(got[got != 0])
+    np.testing.assert_array_equal(m * 256, np.round(m * 256))
+
+
+def test_flat_parameter_layout_round_trip():
+    p = omlp.init_params(3)
+    v = omlp.params_to_flat(p)
+    assert v.size == 6662
+    q = omlp.flat_to_params(v)
+    for k in p:
+        np.testing.assert_array_equal(p[k], q[k])
+
+
+def test_expanded_basis_matches_c_expansion():
+    """B(D, delta) q is what the C oracle's expanded list force adds to the monopole."""
+    rng = np.random.default_rng(31)
+    tg = rng.uniform(-0.2, 0.2, (8, 3))
+    com = np.array([[2.0, -1.0, 0.7]])
+    q = rng.normal(size=(1, 6))
+    args = (tg, np.full(8, 1e-3), [0, 8], [0, 9], [8] + list(range(8)), com, [1.5], 0.02)
+    a_x, _ = oracle.list_force(*args, n_cellent=[1], quad=q, expanded=True)
+    a_m, _ = oracle.list_force(*args)
+    cg = 0.5 * (tg.min(0) + tg.max(0))
+    B = omlp.expanded_basis(np.repeat((cg - com), 8, axis=0), tg - cg, 0.02)
+    np.testing.assert_allclose(np.einsum("pkj,j->pk", B, q[0]), a_x - a_m, rtol=1e-10,
+                               atol=1e-12 * np.abs(a_x - a_m).max())
+
+
+def test_basis_backward_matches_finite_differences():
+    p = omlp.init_params(5)
+    rng = np.random.default_rng(6)
+    P = 24
+    u = rng.normal(size=(P, 32)) * 0.5
+    B = rng.normal(size=(P, 3, 6))
+    scale = rng.uniform(0.5, 2.0, P)
+    t = rng.normal(size=(P, 3)) * 0.1
+    w = rng.uniform(0.1, 1.0, P)
+    L, g = omlp.loss_and_grad_basis(p, u, B, scale, t, w)
+    def lossf(pp):
+        o, _ = omlp.forward(pp, u)
+        r = np.einsum("pkj,pj->pk", B, omlp.traceless(o) * scale[:, None]) - t
+        return float(np.mean(w * (r * r).sum(1)))
+    assert L == pytest.approx(lossf(p), rel=1e-14)
+    for k in p:
+        flat = p[k].reshape(-1)
+        for j in rng.choice(flat.size, size=min(5, flat.size), replace=False):
+            h = 1e-6
+            q = {kk: vv.copy() for kk, vv in p.items()}
+            q[k].reshape(-1)[j] += h
+            lp = lossf(q)
+            q[k].reshape(-1)[j] -= 2 * h
+            lm = lossf(q)
+            assert g[k].reshape(-1)[j] == pytest.approx((lp - lm) / (2 * h), rel=1e-6, abs=1e-10 * abs(L) + 1e-14)
