@@ -208,6 +208,9 @@ def main():
     ap.add_argument("--learned", action="store_true", help="add the learned-correction comparison")
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after timing, one device-to-device copy of this many MiB (a known-size kernel for "
+                         "calibrating hardware byte counters)")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
 
@@ -341,6 +344,14 @@ def main():
         log(f"accuracy {res['accuracy']}")
     if args.learned:
         res["learned"] = learned_comparison(ctx, log, args.steps, args.train_steps, max(5, min(args.steps, 20)))
+    if args.calib_copy_mib:
+        nbytes = args.calib_copy_mib << 20
+        src_t = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst_t = torch.empty_like(src_t)
+        torch.cuda.synchronize()
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        res["calib_copy_bytes"] = nbytes
     print(json.dumps(res), flush=True)
 
 
