@@ -205,6 +205,7 @@ def main():
     ap.add_argument("--lpt", type=int, default=-1)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--autotune", action="store_true", help="sweep the schedule and store the best in the cache")
+    ap.add_argument("--cache", default="", help="autotune cache file (default: the package's)")
     ap.add_argument("--learned", action="store_true", help="add the learned-correction comparison")
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -235,15 +236,16 @@ def main():
     ctx = otoo.Context(0)
 
     key = f"{at.device_key(0)}:{args.workload}"
+    cache_path = args.cache or at.DEFAULT_CACHE
     sched = dict(DEFAULT_SCHEDULE)
     source = "defaults"
     if args.autotune:
         best, table = at.autotune(tree, eps, theta, ctx, log=log)
-        at.save_cache(key, best)
+        at.save_cache(key, best, cache_path)
         sched.update({k: best[k] for k in sched})
         source = "autotuned now"
     else:
-        cached = at.load_cache().get(key)
+        cached = at.load_cache(cache_path).get(key)
         if cached:
             sched.update({k: cached[k] for k in sched})
             source = "autotune cache"

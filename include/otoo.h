@@ -236,8 +236,10 @@ typedef struct otoo_mlp otoo_mlp;
 /* Number of FP32 parameters (6662): W1 [32][64], b1 [64], W2 [64][64],
  * b2 [64], W3 [64][6], b3 [6], concatenated row-major in that order. */
 int otoo_mlp_num_params(void);
-/* A network bound to a context (its device, its stream).  No parameters
- * until otoo_mlp_set_params or otoo_mlp_load. */
+/* A network bound to a context (its device, its stream); the context must
+ * stay alive for every network call except otoo_mlp_destroy, which may come
+ * after otoo_destroy.  No parameters until otoo_mlp_set_params or
+ * otoo_mlp_load. */
 int otoo_mlp_create(otoo_ctx* ctx, otoo_mlp** mlp);
 int otoo_mlp_destroy(otoo_mlp* mlp);
 /* Host parameter vector in, optimiser state reset (EINVAL on non-finite values). */

@@ -731,14 +731,16 @@ __device__ __forceinline__ void write_bf16_copies(uint16_t* wbf, int i, float v)
     }
 }
 
+// Adam (Kingma & Ba): omb1 = 1 - beta1 and omb2 = 1 - beta2 come from the
+// host in double precision (1 - 0.999f in FP32 would be off by 1.3e-5).
 __global__ void k_adam(float* __restrict__ master, float* __restrict__ m, float* __restrict__ v,
                        const float* __restrict__ grad, uint16_t* __restrict__ wbf, float lr, float beta1, float beta2,
-                       float adam_eps, float bc1, float bc2) {
+                       float omb1, float omb2, float adam_eps, float bc1, float bc2) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= NPARAM) return;
     const float g = grad[i];
-    const float mi = beta1 * m[i] + (1.f - beta1) * g;
-    const float vi = beta2 * v[i] + (1.f - beta2) * g * g;
+    const float mi = beta1 * m[i] + omb1 * g;
+    const float vi = beta2 * v[i] + omb2 * g * g;
     m[i] = mi;
     v[i] = vi;
     const float p = master[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + adam_eps);
@@ -761,7 +763,8 @@ __global__ void k_bf16_fill(const float* __restrict__ master, uint16_t* __restri
 // ================================================================ runtime
 
 struct otoo_mlp {
-    otoo_ctx* ctx = nullptr;
+    otoo_ctx* ctx = nullptr;   // must outlive every call except otoo_mlp_destroy
+    int device = 0;
     float* master = nullptr;   // device [NPARAM]
     float* m = nullptr;        // device [NPARAM]
     float* v = nullptr;        // device [NPARAM]
@@ -831,6 +834,7 @@ int otoo_mlp_create(otoo_ctx* c, otoo_mlp** out) {
     otoo_mlp* m = new (std::nothrow) otoo_mlp();
     if (!m) return OTOO_ENOMEM;
     m->ctx = c;
+    m->device = c->device;
     void* p = nullptr;
     const size_t bytes = sizeof(float) * (4 * (size_t)NPARAM + 1) + sizeof(uint16_t) * NBF + 1024;
     if (hipMalloc(&p, bytes) != hipSuccess) {
@@ -854,10 +858,8 @@ int otoo_mlp_create(otoo_ctx* c, otoo_mlp** out) {
 
 int otoo_mlp_destroy(otoo_mlp* m) {
     if (!m) return OTOO_EINVAL;
-    if (m->ctx) {
-        (void)hipSetDevice(m->ctx->device);
-        (void)hipStreamSynchronize(m->ctx->stream);
-    }
+    // does not touch the context (it may already be gone); hipFree waits for the device
+    (void)hipSetDevice(m->device);
     if (m->master) (void)hipFree(m->master);
     if (m->part) (void)hipFree(m->part);
     if (m->geom) (void)hipFree(m->geom);
@@ -1037,11 +1039,11 @@ int otoo_mlp_train_step(otoo_mlp* m, const uint16_t* X, const float* aux, int64_
     rc = run_backward(m, X, aux, n_samples, eps);
     if (rc) return rc;
     m->step += 1;
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float bc1 = (float)(1.0 - std::pow(0.9, (double)m->step));
-    const float bc2 = (float)(1.0 - std::pow(0.999, (double)m->step));
+    const double b1 = 0.9, b2 = 0.999;
+    const float bc1 = (float)(1.0 - std::pow(b1, (double)m->step));
+    const float bc2 = (float)(1.0 - std::pow(b2, (double)m->step));
     hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, c->stream, m->master, m->m, m->v, m->grad,
-                       m->wbf, lr, b1, b2, 1e-8f, bc1, bc2);
+                       m->wbf, lr, (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2), 1e-8f, bc1, bc2);
     HIP_TRY(c, hipGetLastError());
     if (loss_out) {
         HIP_TRY(c, hipStreamSynchronize(c->stream));

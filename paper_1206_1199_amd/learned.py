@@ -81,10 +81,7 @@ class Network:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None:
-            try:
-                _bind().otoo_mlp_destroy(h)
-            except Exception:
-                pass
+            _bind().otoo_mlp_destroy(h)   # safe after the context is gone
             self._h = None
 
     def _raise(self, rc, what):

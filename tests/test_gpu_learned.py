@@ -72,7 +72,7 @@ def test_train_samples_match_exact_cell_sums(env):
     X = bf16_bits_to_f64(env["X"])
     first, count = env["cells"]["first"], env["cells"]["count"]
     sel = np.arange(0, len(env["samples"]), 7)
-    t_ref, D_ref, del_ref, feat_ref = [], [], [], []
+    t_ref, D_ref, del_ref, feat_ref, mono_ref = [], [], [], [], []
     for s in sel:
         p, i = env["samples"][s]
         g, c = _pair_cell(lists, n, p)
@@ -85,15 +85,24 @@ def test_train_samples_match_exact_cell_sums(env):
         a_mo, _ = oracle.point_field(x[None], [0, 1], [0], com[None], cm[c, 3:4].astype(np.float64),
                                      float(np.float32(EPS)))
         t_ref.append(a_ex[0] - a_mo[0])
+        mono_ref.append(np.linalg.norm(a_mo[0]))
         D_ref.append(cg - com)
         del_ref.append(x - cg)
         feat_ref.append(omlp.features((com - cg)[None], cm[c, 4:5].astype(np.float64), float(np.float32(EPS)),
                                       np.array([h]), cm[c, 5:11][None].astype(np.float64),
                                       cm[c, 3:4].astype(np.float64))[0])
-    t_ref, D_ref, del_ref, feat_ref = map(np.array, (t_ref, D_ref, del_ref, feat_ref))
-    err_t = np.linalg.norm(aux[sel, 6:9] - t_ref, axis=1) / np.linalg.norm(t_ref, axis=1)
-    print(f"targets: median rel err {np.median(err_t):.2e}, max {err_t.max():.2e}", flush=True)
-    assert np.median(err_t) <= 1e-5 and np.quantile(err_t, 0.99) <= 1e-3
+    t_ref, D_ref, del_ref, feat_ref, mono_ref = map(np.array, (t_ref, D_ref, del_ref, feat_ref, mono_ref))
+    # t is a small difference of FP64 sums stored in FP32: within FP32 rounding
+    # of t plus FP64 rounding of the monopole-sized sums (a one-particle cell
+    # has t = 0 up to that rounding)
+    dt = np.linalg.norm(aux[sel, 6:9] - t_ref, axis=1)
+    tn = np.linalg.norm(t_ref, axis=1)
+    assert np.all(dt <= 1e-7 * tn + 1e-12 * mono_ref)
+    nz = tn > 1e-9 * mono_ref
+    err_t = dt[nz] / tn[nz]
+    print(f"targets: median rel err {np.median(err_t):.2e}, max {err_t.max():.2e}, one-particle {np.sum(~nz)}",
+          flush=True)
+    assert np.median(err_t) <= 1e-6
     scale = np.abs(D_ref).max()
     np.testing.assert_allclose(aux[sel, 0:3], D_ref, atol=1e-6 * scale)
     np.testing.assert_allclose(aux[sel, 3:6], del_ref, atol=1e-6 * scale)
