@@ -142,6 +142,7 @@ void otoo_lists_free(otoo_lists* lists);
  * ====================================================================== */
 
 typedef struct otoo_ctx otoo_ctx;
+typedef struct otoo_mlp otoo_mlp;   /* the learned correction's network, below */
 
 /* Create a context on HIP device `device` (its stream is the null stream
  * until otoo_set_stream).  EHIP if the device cannot be used. */
@@ -178,21 +179,12 @@ int otoo_get_tuning(const otoo_ctx* ctx, otoo_tuning* tuning);
  *   n_cells     >= 0; cell_mom [n_cells][cell_stride] FP32, COM xyz then M
  *               (cell_stride 4 or 12)
  *   eps         Plummer softening, > 0 and finite
- *   n_pairs, pair_off, corr  cell correction (n_pairs = 0 and both pointers
- *               NULL for the plain monopole): pair_off [n_groups+1] int64 =
- *               prefix sums of the groups' cell counts (the first
- *               pair_off[g+1]-pair_off[g] entries of L_g are cells),
- *               n_pairs = pair_off[n_groups], corr [n_pairs][6] FP32 symmetric
- *               tensors Q (xx, yy, zz, xy, xz, yz), one per (group, cell) pair,
- *               whose quadrupole-form field
- *                   a = Qd r^-5 - 5/2 (d.Qd) d r^-7,  phi = -1/2 d.Qd r^-5
- *               (d = x - COM, r^2 = |d|^2 + eps^2) is added through a
- *               first-order local expansion about the centre c_g of the
- *               group's bounding box: a_i += A_g + J_g (x_i - c_g),
- *               phi_i += Phi_g - A_g.(x_i - c_g), with A_g, J_g (the Jacobian)
- *               and Phi_g summed over the group's cells at c_g.  The tensors
- *               come from otoo_quad_exact (the textbook quadrupole of each
- *               cell) or otoo_mlp_infer (the learned effective tensor).
+ *   gcorr       per-group cell correction from otoo_correction
+ *               ([n_groups][24] FP32), or NULL for the plain monopole: the
+ *               second-order local expansion of the correction field about
+ *               the centre c_g of each group's bounding box, applied per
+ *               target as a_i += A + J d + 1/2 H[d, d] and
+ *               phi_i += Phi - A.d - 1/2 d.J d with d = x_i - c_g
  *   out_acc [n][3] FP32, out_pot [n] FP64 (the potential is reduced in FP64)
  * Arithmetic: FP32 pairs; per-tile FP32 partial sums combined with Kahan
  * compensation across tiles and work items; FP64 for the final potential.
@@ -202,8 +194,8 @@ int otoo_get_tuning(const otoo_ctx* ctx, otoo_tuning* tuning);
  * reports them; with debug_validate the call returns EINVAL instead. */
 int otoo_force(otoo_ctx* ctx, int32_t n, const float* pos, const float* mass, int32_t n_groups,
                const int32_t* group_off, int64_t n_entries, const int64_t* list_off, const int32_t* list_idx,
-               int32_t n_cells, const float* cell_mom, int32_t cell_stride, float eps, int64_t n_pairs,
-               const int64_t* pair_off, const float* corr, float* out_acc, double* out_pot);
+               int32_t n_cells, const float* cell_mom, int32_t cell_stride, float eps, const float* gcorr,
+               float* out_acc, double* out_pot);
 
 /* Textbook quadrupole tensor of every (group, cell) pair (the p = 2 term of
  * the multipole expansion the paper names in Sec. 2 but does not use):
@@ -230,8 +222,6 @@ int otoo_quad_exact(otoo_ctx* ctx, int32_t n, int32_t n_groups, int64_t n_entrie
  * tensor (plain monopole).  GELU is the tanh form.  BF16 operands on MFMA,
  * FP32 accumulation, FP32 master weights with Adam.
  * ====================================================================== */
-
-typedef struct otoo_mlp otoo_mlp;
 
 /* Number of FP32 parameters (6662): W1 [32][64], b1 [64], W2 [64][64],
  * b2 [64], W3 [64][6], b3 [6], concatenated row-major in that order. */
@@ -289,6 +279,30 @@ int otoo_mlp_backward(otoo_mlp* mlp, const uint16_t* X, const float* aux, int64_
 int otoo_mlp_train_step(otoo_mlp* mlp, const uint16_t* X, const float* aux, int64_t n_samples, float eps, float lr,
                         float* loss);
 
+enum otoo_corr_kind {
+    OTOO_CORR_PAIRS = 0,   /* given tensors corr [n_pairs][6], one per (group, cell) pair */
+    OTOO_CORR_QUAD = 1,    /* the textbook quadrupole 3 S_c - tr(S_c) I of each accepted cell */
+    OTOO_CORR_MLP = 2      /* the learned effective tensor of each (group, cell) pair (otoo_mlp_*) */
+};
+
+/* Per-group cell correction for otoo_force.  For every (group, cell) pair
+ * (the first pair_off[g+1]-pair_off[g] entries of group g's list are its
+ * cells; pair_off [n_groups+1] int64, n_pairs = pair_off[n_groups]) a
+ * symmetric tensor Q (xx, yy, zz, xy, xz, yz) -- given, textbook or learned --
+ * defines the quadrupole-form field
+ *     phi = -1/2 d.Qd r^-5,  a = -grad phi  (d = x - COM_c, r^2 = |d|^2 + eps^2);
+ * the field, its first and second derivatives and its potential at the
+ * centre c_g of the group's bounding box are summed over the group's cells
+ * (fixed order) into gcorr [n_groups][24] = {A xyz, Phi, J (xx yy zz xy xz yz),
+ * H (xxx yyy zzz xxy xxz xyy yyz xzz yzz xyz), c_g xyz, 0}.  The multipole
+ * expansion beyond the monopole is what the paper names but does not use
+ * (Sec. 2).  Device pointers; asynchronous; mlp only for OTOO_CORR_MLP;
+ * cell_stride 12 for QUAD and MLP (the second-moment tensor). */
+int otoo_correction(otoo_ctx* ctx, int32_t kind, otoo_mlp* mlp, int32_t n, const float* pos, int32_t n_groups,
+                    const int32_t* group_off, int64_t n_entries, const int64_t* list_off, const int32_t* list_idx,
+                    int64_t n_pairs, const int64_t* pair_off, int32_t n_cells, const float* cell_mom,
+                    int32_t cell_stride, float eps, const float* corr, float* gcorr);
+
 /* Synchronise the context's stream and report whether any kernel since the
  * last otoo_check met malformed input (EINVAL) or not (OK); clears the flag. */
 int otoo_check(otoo_ctx* ctx);
@@ -307,8 +321,7 @@ int otoo_last_timing(otoo_ctx* ctx, float* ms_force_kernel, float* ms_total);
 int otoo_graph_capture(otoo_ctx* ctx, int32_t n, const float* pos, const float* mass, int32_t n_groups,
                        const int32_t* group_off, int64_t n_entries, const int64_t* list_off,
                        const int32_t* list_idx, int32_t n_cells, const float* cell_mom, int32_t cell_stride,
-                       float eps, int64_t n_pairs, const int64_t* pair_off, const float* corr, float* out_acc,
-                       double* out_pot);
+                       float eps, const float* gcorr, float* out_acc, double* out_pot);
 int otoo_graph_launch(otoo_ctx* ctx);
 
 #ifdef __cplusplus

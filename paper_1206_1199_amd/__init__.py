@@ -28,6 +28,8 @@ MAX_GROUP = 256
 THETA_LIMIT = 1.15
 MAC_BH, MAC_ABSOLUTE = 0, 1
 GROUP_CHUNK, GROUP_CELL = 0, 1
+CORR_PAIRS, CORR_QUAD, CORR_MLP = 0, 1, 2
+CORR_STRIDE = 24
 
 _lib = None
 
@@ -63,7 +65,7 @@ EXPORTED = [
     "otoo_tree_links", "otoo_tree_walk", "otoo_lists_free", "otoo_create", "otoo_destroy",
     "otoo_set_stream", "otoo_last_error", "otoo_set_tuning", "otoo_get_tuning", "otoo_force",
     "otoo_check", "otoo_enable_timing", "otoo_last_timing", "otoo_graph_capture", "otoo_graph_launch",
-    "otoo_quad_exact", "otoo_mlp_num_params", "otoo_mlp_create", "otoo_mlp_destroy", "otoo_mlp_set_params",
+    "otoo_quad_exact", "otoo_correction", "otoo_mlp_num_params", "otoo_mlp_create", "otoo_mlp_destroy", "otoo_mlp_set_params",
     "otoo_mlp_get_params", "otoo_mlp_save", "otoo_mlp_load", "otoo_mlp_forward", "otoo_mlp_infer",
     "otoo_mlp_train_samples", "otoo_mlp_backward", "otoo_mlp_train_step",
 ]
@@ -94,12 +96,13 @@ def lib():
         "otoo_last_error": ([P], ctypes.c_char_p),
         "otoo_set_tuning": ([P, ctypes.POINTER(Tuning)], I32),
         "otoo_get_tuning": ([P, ctypes.POINTER(Tuning)], I32),
-        "otoo_force": ([P, I32, P, P, I32, P, I64, P, P, I32, P, I32, F, I64, P, P, P, P], I32),
+        "otoo_force": ([P, I32, P, P, I32, P, I64, P, P, I32, P, I32, F, P, P, P], I32),
+        "otoo_correction": ([P, I32, P, I32, P, I32, P, I64, P, P, I64, P, I32, P, I32, F, P, P], I32),
         "otoo_quad_exact": ([P, I32, I32, I64, P, P, I64, P, I32, P, I32, P], I32),
         "otoo_check": ([P], I32),
         "otoo_enable_timing": ([P, I32], I32),
         "otoo_last_timing": ([P, ctypes.POINTER(F), ctypes.POINTER(F)], I32),
-        "otoo_graph_capture": ([P, I32, P, P, I32, P, I64, P, P, I32, P, I32, F, I64, P, P, P, P], I32),
+        "otoo_graph_capture": ([P, I32, P, P, I32, P, I64, P, P, I32, P, I32, F, P, P, P], I32),
         "otoo_graph_launch": ([P], I32),
     }
     for name, (args, res) in sig.items():
@@ -308,28 +311,39 @@ class Context:
         self._raise(lib().otoo_get_tuning(self._h, ctypes.byref(t)), "otoo_get_tuning")
         return t
 
-    def _args(self, d: DeviceLists, eps, out_acc, out_pot, corr=None):
+    def _args(self, d: DeviceLists, eps, out_acc, out_pot, gcorr=None):
         stride = int(d.cell_mom.shape[1]) if d.cell_mom.dim() == 2 else 4
-        n_pairs = int(corr.shape[0]) if corr is not None else 0
         return (self._h, d.n, _tptr(d.pos), _tptr(d.mass), d.n_groups, _tptr(d.group_off), int(d.n_entries),
                 _tptr(d.list_off), _tptr(d.list_idx), d.n_cells, _tptr(d.cell_mom) if d.n_cells else None,
-                stride, float(eps), n_pairs, _tptr(d.pair_off) if corr is not None else None, _tptr(corr),
-                _tptr(out_acc), _tptr(out_pot))
+                stride, float(eps), _tptr(gcorr), _tptr(out_acc), _tptr(out_pot))
 
     def outputs(self, n):
         import torch
         return (torch.empty((n, 3), dtype=torch.float32, device=f"cuda:{self.device}"),
                 torch.empty(n, dtype=torch.float64, device=f"cuda:{self.device}"))
 
-    def force(self, d: DeviceLists, eps: float, out=None, corr=None):
+    def force(self, d: DeviceLists, eps: float, out=None, gcorr=None):
         """Accelerations [n,3] FP32 and potentials [n] FP64 in key order (asynchronous).
 
-        ``corr``: optional float32 tensor [n_pairs, 6] of per-(group, cell)
-        tensors applied through the group local expansion.
+        ``gcorr``: optional per-group cell correction [n_groups, 24] from
+        ``correction``.
         """
         acc, pot = out if out is not None else self.outputs(d.n)
-        self._raise(lib().otoo_force(*self._args(d, eps, acc, pot, corr)), "otoo_force")
+        self._raise(lib().otoo_force(*self._args(d, eps, acc, pot, gcorr)), "otoo_force")
         return acc, pot
+
+    def correction(self, d: DeviceLists, kind: int, eps: float, net=None, corr=None, out=None):
+        """Per-group correction expansion [n_groups, 24] (kind CORR_PAIRS with
+        ``corr`` [n_pairs, 6], CORR_QUAD, or CORR_MLP with ``net``)."""
+        import torch
+        g = out if out is not None else torch.empty((d.n_groups, CORR_STRIDE), dtype=torch.float32,
+                                                    device=f"cuda:{self.device}")
+        self._raise(lib().otoo_correction(self._h, int(kind), net._h if net is not None else None, d.n, _tptr(d.pos),
+                                          d.n_groups, _tptr(d.group_off), int(d.n_entries), _tptr(d.list_off),
+                                          _tptr(d.list_idx), d.n_pairs, _tptr(d.pair_off), d.n_cells,
+                                          _tptr(d.cell_mom) if d.n_cells else None, int(d.cell_mom.shape[1]),
+                                          float(eps), _tptr(corr), _tptr(g)), "otoo_correction")
+        return g
 
     def quad_exact(self, d: DeviceLists, out=None):
         """Textbook quadrupole 3S - tr(S) I of each (group, cell) pair: float32 [n_pairs, 6]."""
@@ -358,9 +372,9 @@ class Context:
         self._raise(lib().otoo_last_timing(self._h, ctypes.byref(k), ctypes.byref(t)), "otoo_last_timing")
         return k.value, t.value
 
-    def graph_capture(self, d: DeviceLists, eps: float, out, corr=None):
+    def graph_capture(self, d: DeviceLists, eps: float, out, gcorr=None):
         acc, pot = out
-        self._raise(lib().otoo_graph_capture(*self._args(d, eps, acc, pot, corr)), "otoo_graph_capture")
+        self._raise(lib().otoo_graph_capture(*self._args(d, eps, acc, pot, gcorr)), "otoo_graph_capture")
 
     def graph_launch(self):
         self._raise(lib().otoo_graph_launch(self._h), "otoo_graph_launch")

@@ -37,10 +37,10 @@ def device_key(device: int = 0) -> str:
     return f"{arch}:{p.multi_processor_count}cu"
 
 
-def time_replays(ctx: Context, d: DeviceLists, eps: float, out, reps: int = 10, corr=None) -> float:
+def time_replays(ctx: Context, d: DeviceLists, eps: float, out, reps: int = 10, gcorr=None) -> float:
     """Median-free mean of `reps` graph replays (ms), after two warm-ups."""
     import torch
-    ctx.graph_capture(d, eps, out, corr=corr)
+    ctx.graph_capture(d, eps, out, gcorr=gcorr)
     for _ in range(2):
         ctx.graph_launch()
     torch.cuda.synchronize()

@@ -14,8 +14,8 @@
 //                 directly; longer lists leave per-item partial rows.
 //   k_reduce      per particle: Kahan over the item partials in item order,
 //                 potential in FP64, self pair removed.
-// The pair term is the Plummer-softened monopole; cell entries may add the
-// quadrupole-form field of a per-(group, cell) tensor (learned correction).
+// The pair term is the Plummer-softened monopole; an optional per-group
+// second-order local expansion (from otoo_correction) adds a cell correction.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -267,83 +267,6 @@ __global__ __launch_bounds__(256) void k_lpt_scatter(const int2* __restrict__ it
 }
 
 // ---------------------------------------------------------------- cell correction
-
-// One workgroup per group: bounding-box centre c_g of the group's particles,
-// then the sums over the group's cell entries of the quadrupole-form field,
-// its derivatives and potential at c_g (fixed summation order: strided per
-// thread, then a fixed tree in LDS).
-__global__ __launch_bounds__(256) void k_corr_expand(const float4* __restrict__ src, int32_t n, int64_t n_src,
-                                                     const int32_t* __restrict__ group_off,
-                                                     const int64_t* __restrict__ list_off, int64_t n_entries,
-                                                     const int32_t* __restrict__ list_idx,
-                                                     const int64_t* __restrict__ pair_off, int64_t n_pairs,
-                                                     const float* __restrict__ corr, float eps2,
-                                                     float* __restrict__ gcorr, int32_t* err) {
-    __shared__ float red[kCorrTerms][256];
-    const int g = blockIdx.x;
-    const int t = threadIdx.x;
-    const int g0 = group_off[g];
-    const int ng = group_off[g + 1] - g0;
-    const bool ok = ng >= 1 && ng <= kBlock && g0 >= 0 && g0 + ng <= n;
-    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    if (ok && t < ng) {
-        const float4 p = src[g0 + t];
-        lo[0] = hi[0] = p.x;
-        lo[1] = hi[1] = p.y;
-        lo[2] = hi[2] = p.z;
-    }
-    for (int k = 0; k < 3; k++) {
-        red[k][t] = lo[k];
-        red[3 + k][t] = hi[k];
-    }
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (t < w)
-            for (int k = 0; k < 3; k++) {
-                red[k][t] = fminf(red[k][t], red[k][t + w]);
-                red[3 + k][t] = fmaxf(red[3 + k][t], red[3 + k][t + w]);
-            }
-        __syncthreads();
-    }
-    const float cx = 0.5f * (red[0][0] + red[3][0]);
-    const float cy = 0.5f * (red[1][0] + red[4][0]);
-    const float cz = 0.5f * (red[2][0] + red[5][0]);
-    __syncthreads();
-    float f[kCorrTerms];
-#pragma unroll
-    for (int k = 0; k < kCorrTerms; k++) f[k] = 0.f;
-    if (ok) {
-        int64_t lb, le;
-        list_range(list_off, n_entries, g, lb, le);
-        const int64_t p0 = clamp64(pair_off[g], 0, n_pairs);
-        const int64_t p1 = clamp64(pair_off[g + 1], p0, n_pairs);
-        const int64_t nce = (p1 - p0) < (le - lb) ? (p1 - p0) : (le - lb);
-        for (int64_t k = t; k < nce; k += 256) {
-            const int32_t j = list_idx[lb + k];
-            if (j < n || j >= n_src) {
-                atomicOr(err, kErrIndex);
-                continue;
-            }
-            const float4 cm = src[j];
-            quad_expand_add(cx - cm.x, cy - cm.y, cz - cm.z, corr + 6 * (p0 + k), eps2, f);
-        }
-    } else if (t == 0) {
-        atomicOr(err, kErrGroup);
-    }
-#pragma unroll
-    for (int k = 0; k < kCorrTerms; k++) red[k][t] = f[k];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (t < w)
-            for (int k = 0; k < kCorrTerms; k++) red[k][t] += red[k][t + w];
-        __syncthreads();
-    }
-    float* out = gcorr + (int64_t)kCorrStride * g;
-    if (t < kCorrTerms) out[t] = red[t][0];
-    if (t == kCorrTerms) out[kCorrTerms] = cx;
-    if (t == kCorrTerms + 1) out[kCorrTerms + 1] = cy;
-    if (t == kCorrTerms + 2) out[kCorrTerms + 2] = cz;
-}
 
 // Textbook quadrupole of each accepted cell, Q = 3 S - tr(S) I from the
 // cell's second-moment tensor S, written per (group, cell) pair.
@@ -648,7 +571,7 @@ __global__ __launch_bounds__(256) void k_reduce(const float4* __restrict__ src, 
 namespace {
 
 struct Layout {
-    size_t src, item_base, part_base, block_tot, items, order, partial, gcorr, total;
+    size_t src, item_base, part_base, block_tot, items, order, partial, total;
     int64_t item_cap, part_cap;
 };
 
@@ -677,8 +600,6 @@ Layout plan_layout(int32_t n, int32_t n_groups, int64_t n_entries, int32_t n_cel
     off = align_up(off + sizeof(int32_t) * (size_t)L.item_cap);
     L.partial = off;
     off = align_up(off + 2 * sizeof(float4) * (size_t)L.part_cap);
-    L.gcorr = off;
-    off = align_up(off + sizeof(float) * kCorrStride * ((size_t)n_groups + 1));
     L.total = off;
     return L;
 }
@@ -714,9 +635,7 @@ struct Call {
     const float* cell_mom;
     int32_t cell_stride;
     float eps;
-    int64_t n_pairs;
-    const int64_t* pair_off;
-    const float* corr;
+    const float* gcorr;
     float* out_acc;
     double* out_pot;
 };
@@ -734,10 +653,6 @@ int check_args(otoo_ctx* c, const Call& a) {
         return fail(c, OTOO_EINVAL, "null pointer argument");
     if (a.n_entries > 0 && !a.list_idx) return fail(c, OTOO_EINVAL, "list_idx is null");
     if (a.n_cells > 0 && !a.cell_mom) return fail(c, OTOO_EINVAL, "cell_mom is null");
-    if ((a.pair_off == nullptr) != (a.corr == nullptr))
-        return fail(c, OTOO_EINVAL, "pair_off and corr must both be given or both be null");
-    if (a.n_pairs < 0 || (a.n_pairs > 0 && !a.corr) || (a.corr && a.n_pairs > a.n_entries))
-        return fail(c, OTOO_EINVAL, "n_pairs = %lld inconsistent with corr / n_entries", (long long)a.n_pairs);
     return OTOO_OK;
 }
 
@@ -782,7 +697,7 @@ int enqueue(otoo_ctx* c, const Call& a, bool allow_timing) {
     int2* items = reinterpret_cast<int2*>(base + L.items);
     int32_t* order = reinterpret_cast<int32_t*>(base + L.order);
     float4* partial = reinterpret_cast<float4*>(base + L.partial);
-    float* gcorr = a.corr ? reinterpret_cast<float*>(base + L.gcorr) : nullptr;
+    const float* gcorr = a.gcorr;
     hipStream_t s = c->stream;
     const bool tm = allow_timing && c->timing;
 
@@ -802,10 +717,6 @@ int enqueue(otoo_ctx* c, const Call& a, bool allow_timing) {
         hipLaunchKernelGGL(k_lpt_scatter, dim3(1024), dim3(256), 0, s, items, a.group_off, a.list_off, a.n_entries,
                            tu.chunk, L.item_cap, c->meta, order);
     }
-    if (gcorr)
-        hipLaunchKernelGGL(k_corr_expand, dim3(a.n_groups), dim3(256), 0, s, src, a.n, n_src, a.group_off,
-                           a.list_off, a.n_entries, a.list_idx, a.pair_off, a.n_pairs, a.corr, a.eps * a.eps,
-                           gcorr, c->errflag);
     ForceArgs fa;
     fa.src = src;
     fa.n_src = n_src;
@@ -834,7 +745,8 @@ int enqueue(otoo_ctx* c, const Call& a, bool allow_timing) {
     else
         hipLaunchKernelGGL(k_force<256>, dim3(grid), dim3(kBlock), 0, s, fa);
     if (tm) HIP_TRY(c, hipEventRecord(c->ev[2], s));
-    hipLaunchKernelGGL(k_reduce, dim3((a.n + 255) / 256), dim3(256), 0, s, src, a.group_off, a.n_groups,
+    if ((int64_t)tu.chunk < a.n_entries)   // otherwise no list is split and k_force wrote every output
+        hipLaunchKernelGGL(k_reduce, dim3((a.n + 255) / 256), dim3(256), 0, s, src, a.group_off, a.n_groups,
                        a.list_off, a.n_entries, a.n, tu.chunk, part_base, partial, L.part_cap, fa.eps2, gcorr,
                        a.out_acc, a.out_pot);
     HIP_TRY(c, hipGetLastError());
@@ -937,12 +849,12 @@ int otoo_get_tuning(const otoo_ctx* c, otoo_tuning* t) {
 
 int otoo_force(otoo_ctx* c, int32_t n, const float* pos, const float* mass, int32_t n_groups,
                const int32_t* group_off, int64_t n_entries, const int64_t* list_off, const int32_t* list_idx,
-               int32_t n_cells, const float* cell_mom, int32_t cell_stride, float eps, int64_t n_pairs,
-               const int64_t* pair_off, const float* corr, float* out_acc, double* out_pot) {
+               int32_t n_cells, const float* cell_mom, int32_t cell_stride, float eps, const float* gcorr,
+               float* out_acc, double* out_pot) {
     if (!c) return OTOO_EINVAL;
     c->err.clear();
     Call a{n, pos, mass, n_groups, group_off, n_entries, list_off, list_idx, n_cells, cell_mom, cell_stride, eps,
-           n_pairs, pair_off, corr, out_acc, out_pot};
+           gcorr, out_acc, out_pot};
     HIP_TRY(c, hipSetDevice(c->device));
     int rc = prepare(c, a);
     if (rc) return rc;
@@ -1004,12 +916,11 @@ int otoo_last_timing(otoo_ctx* c, float* ms_kernel, float* ms_total) {
 int otoo_graph_capture(otoo_ctx* c, int32_t n, const float* pos, const float* mass, int32_t n_groups,
                        const int32_t* group_off, int64_t n_entries, const int64_t* list_off,
                        const int32_t* list_idx, int32_t n_cells, const float* cell_mom, int32_t cell_stride,
-                       float eps, int64_t n_pairs, const int64_t* pair_off, const float* corr, float* out_acc,
-                       double* out_pot) {
+                       float eps, const float* gcorr, float* out_acc, double* out_pot) {
     if (!c) return OTOO_EINVAL;
     c->err.clear();
     Call a{n, pos, mass, n_groups, group_off, n_entries, list_off, list_idx, n_cells, cell_mom, cell_stride, eps,
-           n_pairs, pair_off, corr, out_acc, out_pot};
+           gcorr, out_acc, out_pot};
     HIP_TRY(c, hipSetDevice(c->device));
     int rc = prepare(c, a);  // all allocation happens before capture
     if (rc) return rc;

@@ -113,6 +113,53 @@ __device__ __forceinline__ void quad_expand_add(float dx, float dy, float dz, co
     }
 }
 
+// The two halves of quad_expand_add, for two lanes sharing one pair:
+// part 0 adds {a, phi, J} (f[0..9]), part 1 adds H (f[10..19]).
+__device__ __forceinline__ void quad_expand_add_part(int part, float dx, float dy, float dz, const float* qp,
+                                                     float eps2, float* f) {
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float ri2 = ri * ri;
+    const float ri3 = ri2 * ri;
+    const float e[3] = {dx * ri, dy * ri, dz * ri};
+    const float Q[3][3] = {{qp[0], qp[3], qp[4]}, {qp[3], qp[1], qp[5]}, {qp[4], qp[5], qp[2]}};
+    float qe[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) qe[k] = Q[k][0] * e[0] + Q[k][1] * e[1] + Q[k][2] * e[2];
+    const float u = e[0] * qe[0] + e[1] * qe[1] + e[2] * qe[2];
+    const float hu = 0.5f * u;
+    float R2[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) R2[i][j] = (i == j ? -5.f : 0.f) + 35.f * e[i] * e[j];
+    if (part == 0) {
+        const float ri4 = ri2 * ri2;
+        const float ri5 = ri4 * ri;
+#pragma unroll
+        for (int k = 0; k < 3; k++) f[k] += ri4 * (qe[k] - 2.5f * u * e[k]);
+        f[3] += -hu * ri3;
+        constexpr int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+        for (int m = 0; m < 6; m++) {
+            const int i = ia[m], j = ib[m];
+            f[4 + m] += ri5 * (Q[i][j] - 5.f * (qe[i] * e[j] + qe[j] * e[i]) + hu * R2[i][j]);
+        }
+    } else {
+        const float ri6 = ri3 * ri3;
+        constexpr int ha[10] = {0, 1, 2, 0, 0, 0, 1, 0, 1, 0}, hb[10] = {0, 1, 2, 0, 0, 1, 1, 2, 2, 1},
+                      hc[10] = {0, 1, 2, 1, 2, 1, 2, 2, 2, 2};
+#pragma unroll
+        for (int m = 0; m < 10; m++) {
+            const int i = ha[m], j = hb[m], k = hc[m];
+            const float R3 = 35.f * ((i == j ? e[k] : 0.f) + (i == k ? e[j] : 0.f) + (j == k ? e[i] : 0.f)) -
+                             315.f * e[i] * e[j] * e[k];
+            f[10 + m] += ri6 * (-5.f * (Q[i][j] * e[k] + Q[i][k] * e[j] + Q[j][k] * e[i]) + qe[i] * R2[j][k] +
+                                qe[j] * R2[i][k] + qe[k] * R2[i][j] + hu * R3);
+        }
+    }
+}
+
 }  // namespace otoo_detail
 
 struct otoo_ctx {

@@ -51,10 +51,8 @@ static_assert(NPARAM == 6662, "parameter count");
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+__device__ __forceinline__ uint16_t f2bf(float f) {  // v_cvt_pk_bf16_f32: round to nearest even
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 
 __device__ __forceinline__ bf16x8 ld8(const uint16_t* p) {  // 8 contiguous BF16, 16-byte aligned
@@ -351,6 +349,208 @@ __global__ __launch_bounds__(256) void k_mlp_forward_raw(const uint16_t* __restr
                 if (r < rows) out[r * NOUT + r16] = o[0][i];
             }
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- fused per-group correction
+
+enum { kCorrPairs = 0, kCorrQuad = 1, kCorrMlp = 2 };
+
+struct CorrArgs {
+    int32_t n;
+    const float* pos;
+    int32_t n_groups;
+    const int32_t* group_off;
+    const int64_t* list_off;
+    int64_t n_entries;
+    const int32_t* list_idx;
+    const int64_t* pair_off;
+    int64_t n_pairs;
+    int32_t n_cells;
+    const float* cell_mom;
+    int32_t stride;
+    float eps;
+    const float* corr;        // kCorrPairs: given tensors [n_pairs][6]
+    const uint16_t* wbf;      // kCorrMlp: network
+    const float* master;
+    float* gcorr;             // [n_groups][kCorrStride]
+    int32_t* err;
+};
+
+// One workgroup per group (grid-stride over groups): the centre c_g of the
+// group's bounding box, then the tensor of every (group, cell) pair -- given
+// (kCorrPairs), the textbook quadrupole 3S - tr(S) I (kCorrQuad) or the
+// network's prediction (kCorrMlp, 64 pairs at a time on MFMA) -- and its
+// quadrupole-form field, Jacobian, Hessian and potential at c_g, summed in a
+// fixed order into the group's local expansion.  No per-pair tensor touches
+// HBM.
+constexpr int kCorrRows = 128;   // pairs per chunk in the network variant (2 row tiles per wave)
+
+template <int KIND>
+__global__ __launch_bounds__(256) void k_corr_group(CorrArgs a) {
+    constexpr bool NET = KIND == kCorrMlp;
+    __shared__ NetLDS net;
+    __shared__ __align__(16) uint16_t sX[NET ? kCorrRows * NIN : 8];
+    __shared__ __align__(16) uint16_t sH[NET ? kCorrRows * NH : 8];
+    __shared__ float sO[NET ? kCorrRows * NOUTP : 1];
+    __shared__ float sScale[kCorrRows];
+    __shared__ int sCell[kCorrRows];
+    __shared__ float red[kCorrTerms][256];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, r16 = lane & 15, q = lane >> 4;
+    const float eps2 = a.eps * a.eps;
+    if (NET) {
+        load_net(net, a.wbf, a.master);
+        for (int i = t; i < kCorrRows * NIN; i += 256) sX[i] = 0;   // padding columns stay zero
+    }
+    for (int g = blockIdx.x; g < a.n_groups; g += gridDim.x) {
+        const int g0 = a.group_off[g];
+        const int ng = a.group_off[g + 1] - g0;
+        const bool ok = ng >= 1 && ng <= kBlock && g0 >= 0 && g0 + ng <= a.n;
+        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        if (ok && t < ng)
+            for (int k = 0; k < 3; k++) lo[k] = hi[k] = a.pos[3 * (g0 + t) + k];
+        __syncthreads();   // the previous group's reduction has been read
+        for (int k = 0; k < 3; k++) {
+            red[k][t] = lo[k];
+            red[3 + k][t] = hi[k];
+        }
+        __syncthreads();
+        for (int s2 = 128; s2 > 0; s2 >>= 1) {
+            if (t < s2)
+                for (int k = 0; k < 3; k++) {
+                    red[k][t] = fminf(red[k][t], red[k][t + s2]);
+                    red[3 + k][t] = fmaxf(red[3 + k][t], red[3 + k][t + s2]);
+                }
+            __syncthreads();
+        }
+        const float cx = 0.5f * (red[0][0] + red[3][0]);
+        const float cy = 0.5f * (red[1][0] + red[4][0]);
+        const float cz = 0.5f * (red[2][0] + red[5][0]);
+        const float ex = red[3][0] - red[0][0], ey = red[4][0] - red[1][0], ez = red[5][0] - red[2][0];
+        const float h = 0.5f * sqrtf(ex * ex + ey * ey + ez * ez);
+        __syncthreads();
+        float f[kCorrTerms];
+#pragma unroll
+        for (int k = 0; k < kCorrTerms; k++) f[k] = 0.f;
+        int64_t lb = 0, le = 0, p0 = 0, nce = 0;
+        if (ok) {
+            list_range(a.list_off, a.n_entries, g, lb, le);
+            p0 = clamp64(a.pair_off[g], 0, a.n_pairs);
+            const int64_t p1 = clamp64(a.pair_off[g + 1], p0, a.n_pairs);
+            nce = (p1 - p0) < (le - lb) ? (p1 - p0) : (le - lb);
+        } else if (t == 0) {
+            atomicOr(a.err, kErrGroup);
+        }
+        if (!NET) {
+            for (int64_t k = t; k < nce; k += 256) {
+                const int64_t c = (int64_t)a.list_idx[lb + k] - a.n;
+                if (c < 0 || c >= a.n_cells) {
+                    atomicOr(a.err, kErrIndex);
+                    continue;
+                }
+                const float* cm = a.cell_mom + (int64_t)a.stride * c;
+                float Q[6];
+                if (KIND == kCorrPairs) {
+                    for (int m = 0; m < 6; m++) Q[m] = a.corr[6 * (p0 + k) + m];
+                } else {
+                    const float* S = cm + 5;
+                    const float tr = S[0] + S[1] + S[2];
+                    Q[0] = 3.f * S[0] - tr;
+                    Q[1] = 3.f * S[1] - tr;
+                    Q[2] = 3.f * S[2] - tr;
+                    Q[3] = 3.f * S[3];
+                    Q[4] = 3.f * S[4];
+                    Q[5] = 3.f * S[5];
+                }
+                quad_expand_add(cx - cm[0], cy - cm[1], cz - cm[2], Q, eps2, f);
+            }
+        } else {
+            for (int64_t base = 0; base < nce; base += kCorrRows) {
+                if (t < kCorrRows) {   // features: one thread per row
+                    const int64_t k = base + t;
+                    float fe[NFEAT];
+                    float sc = 0.f;
+                    bool fok = false;
+                    int64_t c = -1;
+                    if (k < nce) {
+                        c = (int64_t)a.list_idx[lb + k] - a.n;
+                        if (c >= 0 && c < a.n_cells) {
+                            fok = pair_features(cx, cy, cz, h, a.cell_mom + 12 * c, a.eps, fe, sc);
+                        } else {
+                            atomicOr(a.err, kErrIndex);
+                            c = -1;
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < NFEAT; j++) sX[t * NIN + j] = f2bf(fok ? fe[j] : 0.f);
+                    sScale[t] = fok ? sc : 0.f;
+                    sCell[t] = (int)c;
+                }
+                __syncthreads();
+                floatx4 acc[4];
+#pragma unroll
+                for (int mt = 0; mt < 2; mt++) {
+                    const int r0 = 32 * w + 16 * mt;
+                    wave_dense<1, 4>(sX, NIN, net.w1t, NIN, net.b1, r0, acc);
+#pragma unroll
+                    for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+                        for (int i = 0; i < 4; i++)
+                            sH[(r0 + q * 4 + i) * NH + nt * 16 + r16] = f2bf(gelu(acc[nt][i]));
+                }
+                __syncthreads();
+                floatx4 acc2[2][4];
+#pragma unroll
+                for (int mt = 0; mt < 2; mt++) wave_dense<2, 4>(sH, NH, net.w2t, NH, net.b2, 32 * w + 16 * mt, acc2[mt]);
+                __syncthreads();
+#pragma unroll
+                for (int mt = 0; mt < 2; mt++) {
+                    const int r0 = 32 * w + 16 * mt;
+#pragma unroll
+                    for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+                        for (int i = 0; i < 4; i++)
+                            sH[(r0 + q * 4 + i) * NH + nt * 16 + r16] = f2bf(gelu(acc2[mt][nt][i]));
+                }
+                __syncthreads();
+#pragma unroll
+                for (int mt = 0; mt < 2; mt++) {
+                    const int r0 = 32 * w + 16 * mt;
+                    floatx4 o[1];
+                    wave_dense<2, 1>(sH, NH, net.w3t, NH, net.b3, r0, o);
+#pragma unroll
+                    for (int i = 0; i < 4; i++) sO[(r0 + q * 4 + i) * NOUTP + r16] = o[0][i];
+                }
+                __syncthreads();
+                {   // two threads per row share the expansion: {a, phi, J} and H
+                    const int row = t >> 1, part = t & 1;
+                    if (base + row < nce && sCell[row] >= 0 && sScale[row] > 0.f) {
+                        const float* ov = sO + row * NOUTP;
+                        const float tr = (ov[0] + ov[1] + ov[2]) * (1.f / 3.f);
+                        const float sc = sScale[row];
+                        const float Q[6] = {(ov[0] - tr) * sc, (ov[1] - tr) * sc, (ov[2] - tr) * sc,
+                                            ov[3] * sc,        ov[4] * sc,        ov[5] * sc};
+                        const float* cm = a.cell_mom + 12 * (int64_t)sCell[row];
+                        quad_expand_add_part(part, cx - cm[0], cy - cm[1], cz - cm[2], Q, eps2, f);
+                    }
+                }
+                __syncthreads();
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kCorrTerms; k++) red[k][t] = f[k];
+        __syncthreads();
+        for (int s2 = 128; s2 > 0; s2 >>= 1) {
+            if (t < s2)
+                for (int k = 0; k < kCorrTerms; k++) red[k][t] += red[k][t + s2];
+            __syncthreads();
+        }
+        float* out = a.gcorr + (int64_t)kCorrStride * g;
+        if (t < kCorrTerms) out[t] = red[t][0];
+        if (t == kCorrTerms) out[kCorrTerms] = cx;
+        if (t == kCorrTerms + 1) out[kCorrTerms + 1] = cy;
+        if (t == kCorrTerms + 2) out[kCorrTerms + 2] = cz;
+        if (t == kCorrTerms + 3) out[kCorrTerms + 3] = 0.f;
     }
 }
 
@@ -975,6 +1175,43 @@ int otoo_mlp_infer(otoo_mlp* m, int32_t n, const float* pos, int32_t n_groups, c
                  cell_mom, eps,      m->geom,  m->wbf,    m->master, corr,    c->errflag};
     const int blocks = (int)std::min<int64_t>(4 * (int64_t)c->num_cu, (n_pairs + 63) / 64);
     hipLaunchKernelGGL(k_mlp_infer, dim3(blocks), dim3(256), 0, c->stream, ia);
+    HIP_TRY(c, hipGetLastError());
+    return OTOO_OK;
+}
+
+int otoo_correction(otoo_ctx* c, int32_t kind, otoo_mlp* m, int32_t n, const float* pos, int32_t n_groups,
+                    const int32_t* group_off, int64_t n_entries, const int64_t* list_off, const int32_t* list_idx,
+                    int64_t n_pairs, const int64_t* pair_off, int32_t n_cells, const float* cell_mom,
+                    int32_t cell_stride, float eps, const float* corr, float* gcorr) {
+    if (!c) return OTOO_EINVAL;
+    c->err.clear();
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (kind != OTOO_CORR_PAIRS && kind != OTOO_CORR_QUAD && kind != OTOO_CORR_MLP)
+        return fail(c, OTOO_EINVAL, "unknown correction kind %d", kind);
+    if (n < 1 || n_groups < 1 || n_groups > n || n_entries < 0 || n_pairs < 0 || n_pairs > n_entries || n_cells < 0)
+        return fail(c, OTOO_EINVAL, "bad sizes");
+    if (cell_stride != 4 && cell_stride != 12) return fail(c, OTOO_EINVAL, "cell_stride must be 4 or 12");
+    if (kind != OTOO_CORR_PAIRS && cell_stride != 12)
+        return fail(c, OTOO_EINVAL, "this correction needs cell moments of stride 12");
+    if (!(eps > 0.f) || !std::isfinite(eps)) return fail(c, OTOO_EINVAL, "eps must be positive and finite");
+    if (!pos || !group_off || !list_off || !pair_off || !gcorr || (n_entries && !list_idx) ||
+        (n_cells && !cell_mom) || (kind == OTOO_CORR_PAIRS && n_pairs && !corr))
+        return fail(c, OTOO_EINVAL, "null pointer argument");
+    if (kind == OTOO_CORR_MLP) {
+        if (!m || m->ctx != c) return fail(c, OTOO_EINVAL, "a network of this context is required");
+        if (!m->has_params) return fail(c, OTOO_EINVAL, "no parameters loaded");
+    }
+    CorrArgs ca{n,        pos,     n_groups, group_off, list_off, n_entries, list_idx,
+                pair_off, n_pairs, n_cells,  cell_mom,  cell_stride, eps,   corr,
+                m ? m->wbf : nullptr, m ? m->master : nullptr, gcorr, c->errflag};
+    const int per_cu = kind == OTOO_CORR_MLP ? 2 : 6;
+    const int blocks = (int)std::min<int64_t>((int64_t)per_cu * c->num_cu, n_groups);
+    if (kind == OTOO_CORR_PAIRS)
+        hipLaunchKernelGGL(k_corr_group<kCorrPairs>, dim3(blocks), dim3(256), 0, c->stream, ca);
+    else if (kind == OTOO_CORR_QUAD)
+        hipLaunchKernelGGL(k_corr_group<kCorrQuad>, dim3(blocks), dim3(256), 0, c->stream, ca);
+    else
+        hipLaunchKernelGGL(k_corr_group<kCorrMlp>, dim3(blocks), dim3(256), 0, c->stream, ca);
     HIP_TRY(c, hipGetLastError());
     return OTOO_OK;
 }

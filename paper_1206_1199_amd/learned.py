@@ -6,8 +6,8 @@ by the library's forward/backward/Adam kernels).
     net.set_params(init_params(seed=0))
     X, aux = make_training_set(ctx, net, configs, n_samples, seed)
     fit(net, X, aux, eps_list..., steps=..., lr=...)
-    corr = net.infer(dev_lists, eps)          # per (group, cell) tensors
-    acc, pot = ctx.force(dev_lists, eps, corr=corr)
+    gcorr = ctx.correction(dev_lists, CORR_MLP, eps, net=net)   # fused per-group expansion
+    acc, pot = ctx.force(dev_lists, eps, gcorr=gcorr)
 """
 from __future__ import annotations
 

@@ -29,8 +29,10 @@ def test_every_declared_symbol_is_exported():
 
 def test_null_context_and_bad_arguments_return_einval():
     lib = otoo.lib()
-    assert lib.otoo_force(None, 1, None, None, 1, None, 0, None, None, 0, None, 4, 0.1, 0, None, None, None,
+    assert lib.otoo_force(None, 1, None, None, 1, None, 0, None, None, 0, None, 4, 0.1, None, None,
                           None) == otoo.EINVAL
+    assert lib.otoo_correction(None, 1, None, 1, None, 1, None, 0, None, None, 0, None, 0, None, 12, 0.1, None,
+                               None) == otoo.EINVAL
     assert lib.otoo_quad_exact(None, 1, 1, 0, None, None, 0, None, 0, None, 12, None) == otoo.EINVAL
     assert lib.otoo_check(None) == otoo.EINVAL
     assert lib.otoo_graph_launch(None) == otoo.EINVAL

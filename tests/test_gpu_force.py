@@ -196,7 +196,8 @@ def test_cell_tensors_local_expansion(ctx, plummer16k):
         - t.n]
     quad = (rng.normal(size=(n_pairs, 6)) * 0.3 * scale[:, None]).astype(np.float32)
     corr = torch.from_numpy(quad).cuda()
-    acc, pot = ctx.force(d, 0.01, corr=corr)
+    gc = ctx.correction(d, otoo.CORR_PAIRS, 0.01, corr=corr)
+    acc, pot = ctx.force(d, 0.01, gcorr=gc)
     torch.cuda.synchronize()
     ctx.check()
     a_ref, p_ref = _oracle_quad(pos32, mass32, lists, cm, 0.01, quad.astype(np.float64))
@@ -205,8 +206,9 @@ def test_cell_tensors_local_expansion(ctx, plummer16k):
 
 def test_exact_quadrupole_pairs_and_accuracy(ctx, plummer16k):
     """Device quadrupole tensors equal 3S - tr(S) I of the exported cell
-    moments (FP32, 1e-6 relative); with them, theta = 0.8 beats the plain
-    monopole at theta = 0.8 against the direct sum."""
+    moments (FP32, 1e-6 relative); the fused quadrupole correction meets the
+    parity bar; at theta = 0.8 it beats the plain monopole against the direct
+    sum."""
     from oracle import mlp as omlp
     pos, m = plummer16k
     t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.8, 64, stride=12)
@@ -218,8 +220,10 @@ def test_exact_quadrupole_pairs_and_accuracy(ctx, plummer16k):
     q_ref = omlp.exact_quadrupole(cm[cells, 5:11].astype(np.float64))
     q_gpu = corr.cpu().numpy().astype(np.float64)
     np.testing.assert_allclose(q_gpu, q_ref, rtol=1e-6, atol=1e-6 * np.abs(q_ref).max())
-    acc, pot = ctx.force(d, 0.01, corr=corr)
+    gc = ctx.correction(d, otoo.CORR_QUAD, 0.01)
+    acc, pot = ctx.force(d, 0.01, gcorr=gc)
     torch.cuda.synchronize()
+    ctx.check()
     a_q = acc.cpu().numpy().astype(np.float64)
     a_ref, p_ref = _oracle_quad(pos32, mass32, lists, cm, 0.01, q_ref)
     _assert_parity(a_q, pot.cpu().numpy(), a_ref, p_ref, "exact quadrupole")

@@ -225,8 +225,8 @@ def test_training_reduces_loss_and_helps_forces(env):
     lists = tree.walk(theta=0.8, g_max=64)
     d, _, _ = learned.device_tree_arrays(tree, lists)
     _, pos32, mass32, _ = tree.export(12)
-    corr = net.infer(d, EPS)
-    a_l, _ = ctx.force(d, EPS, corr=corr)
+    gc = ctx.correction(d, otoo.CORR_MLP, EPS, net=net)
+    a_l, _ = ctx.force(d, EPS, gcorr=gc)
     a_m, _ = ctx.force(d, EPS)
     torch.cuda.synchronize()
     ctx.check()
@@ -237,3 +237,39 @@ def test_training_reduces_loss_and_helps_forces(env):
     e_m = np.median(oracle.rel_err(a_m.cpu().numpy()[sample], a_dir))
     print(f"theta 0.8 held out: monopole median {e_m:.2e}, learned {e_l:.2e}", flush=True)
     assert e_l < 0.8 * e_m
+
+
+def test_fused_learned_correction_matches_oracle(env):
+    """The fused per-group learned correction against the oracle's list force
+    with the oracle network's tensors (FP64 features rounded to BF16, BF16
+    weights): the tensors differ by the BF16 activations (~3e-3 relative), and
+    the correction is a small part of the force."""
+    ctx, net, d, lists, cm, pos32, mass32 = (env[k] for k in ("ctx", "net", "d", "lists", "cm", "pos32", "mass32"))
+    net.set_params(env["params"])
+    gc = ctx.correction(d, otoo.CORR_MLP, EPS, net=net)
+    acc, pot = ctx.force(d, EPS, gcorr=gc)
+    torch.cuda.synchronize()
+    ctx.check()
+    n = len(pos32)
+    feats, scale = [], []
+    for p in range(int(lists.pair_off[-1])):
+        g, c = _pair_cell(lists, n, p)
+        cg, h = _group_geometry(pos32, lists, g)
+        com = cm[c, :3].astype(np.float64)
+        feats.append(omlp.features((com - cg)[None], cm[c, 4:5].astype(np.float64), float(np.float32(EPS)),
+                                   np.array([h]), cm[c, 5:11][None].astype(np.float64),
+                                   cm[c, 3:4].astype(np.float64))[0])
+        scale.append(float(cm[c, 3]) * float(cm[c, 4]) ** 2)
+    o, _ = omlp.forward(omlp.bf16_params(omlp.flat_to_params(env["params"])), omlp.to_bf16(np.array(feats)))
+    quad = omlp.traceless(o) * np.array(scale)[:, None]
+    sample = synth.sample_idx(n, 2048, seed=7)
+    a_ref, p_ref = oracle.list_force(pos32.astype(np.float64), mass32.astype(np.float64), lists.group_off,
+                                     lists.list_off, lists.list_idx, cm[:, :3].astype(np.float64),
+                                     cm[:, 3].astype(np.float64), float(np.float32(EPS)), tgt=sample,
+                                     n_cellent=lists.n_cellent, quad=quad, expanded=True)
+    ea = oracle.rel_err(acc.cpu().numpy().astype(np.float64)[sample], a_ref)
+    ep = oracle.rel_err(pot.cpu().numpy()[sample], p_ref)
+    print(f"fused learned correction: acc median {np.median(ea):.2e} p99 {np.quantile(ea, 0.99):.2e}, "
+          f"pot median {np.median(ep):.2e}", flush=True)
+    assert np.median(ea) <= 2e-5 and np.quantile(ea, 0.99) <= 2e-4
+    assert np.median(ep) <= 2e-5
