@@ -160,6 +160,11 @@ def learned_comparison(ctx, log, steps, train_steps, timing_reps):
     cells = tree.cells()
 
     def run(theta, modes, g_max):
+        # schedules from the autotuner's sweep: whole lists for small groups, split lists for large ones
+        if g_max <= 32:
+            ctx.set_tuning(chunk=1 << 24, blocks_per_cu=8, lpt=0, tile=512)
+        else:
+            ctx.set_tuning(chunk=2048, blocks_per_cu=8, lpt=1, tile=256)
         lists = tree.walk(theta=theta, g_max=g_max)
         d, _, _ = learned.device_tree_arrays(tree, lists)
         out = ctx.outputs(d.n)
@@ -193,10 +198,11 @@ def learned_comparison(ctx, log, steps, train_steps, timing_reps):
                              p99_err=float(np.quantile(err, 0.99))))
         return rows
 
-    g_plain = DEFAULT_SCHEDULE["g_max"]
     rows = []
     for th in (0.5, 0.6, 0.65, 0.7, 0.75, 0.8, 0.85, 0.9):
-        rows += run(th, ("plain",), g_plain)
+        rows += run(th, ("plain",), 32)
+    for th in (0.5, 0.75):
+        rows += run(th, ("plain",), 64)
     for g_max in (32, 64, 128):
         for th in (0.8, 0.9, 1.0):
             rows += run(th, ("quad", "learned"), g_max)

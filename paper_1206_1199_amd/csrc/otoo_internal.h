@@ -166,7 +166,7 @@ struct otoo_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
-    otoo_tuning tune{1024, 8, 1, 0, 256};
+    otoo_tuning tune{1024, 8, 1, 0, 256, 0};
     int num_cu = 0;
     // scratch
     void* buf = nullptr;

@@ -386,22 +386,32 @@ struct CorrArgs {
 // HBM.
 constexpr int kCorrRows = 128;   // pairs per chunk in the network variant (2 row tiles per wave)
 
+// LDS of the network variant: the features (X) and hidden activations (H)
+// of one chunk; the outputs (O) reuse X once layer 1 has read it, and the
+// per-group reductions reuse the whole area between chunks.
+union CorrScratch {
+    struct {
+        alignas(16) uint16_t x[kCorrRows * NIN];
+        alignas(16) uint16_t h[kCorrRows * NH];
+    } net;
+    float o[kCorrRows * NOUTP];
+    float red[kCorrTerms][256];
+};
+
 template <int KIND>
-__global__ __launch_bounds__(256) void k_corr_group(CorrArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_corr_group(CorrArgs a) {
     constexpr bool NET = KIND == kCorrMlp;
     __shared__ NetLDS net;
-    __shared__ __align__(16) uint16_t sX[NET ? kCorrRows * NIN : 8];
-    __shared__ __align__(16) uint16_t sH[NET ? kCorrRows * NH : 8];
-    __shared__ float sO[NET ? kCorrRows * NOUTP : 1];
+    __shared__ CorrScratch scr;
     __shared__ float sScale[kCorrRows];
     __shared__ int sCell[kCorrRows];
-    __shared__ float red[kCorrTerms][256];
+    uint16_t* sX = scr.net.x;
+    uint16_t* sH = scr.net.h;
+    float* sO = scr.o;
+    auto& red = scr.red;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, r16 = lane & 15, q = lane >> 4;
     const float eps2 = a.eps * a.eps;
-    if (NET) {
-        load_net(net, a.wbf, a.master);
-        for (int i = t; i < kCorrRows * NIN; i += 256) sX[i] = 0;   // padding columns stay zero
-    }
+    if (NET) load_net(net, a.wbf, a.master);
     for (int g = blockIdx.x; g < a.n_groups; g += gridDim.x) {
         const int g0 = a.group_off[g];
         const int ng = a.group_off[g + 1] - g0;
@@ -466,7 +476,10 @@ __global__ __launch_bounds__(256) void k_corr_group(CorrArgs a) {
             }
         } else {
             for (int64_t base = 0; base < nce; base += kCorrRows) {
-                if (t < kCorrRows) {   // features: one thread per row
+                if (t >= kCorrRows) {  // zero the padding columns (X shares its space with O and the reductions)
+                    const int row = t - kCorrRows;
+                    for (int j = NFEAT; j < NIN; j++) sX[row * NIN + j] = 0;
+                } else {               // features: one thread per row
                     const int64_t k = base + t;
                     float fe[NFEAT];
                     float sc = 0.f;
@@ -537,6 +550,177 @@ __global__ __launch_bounds__(256) void k_corr_group(CorrArgs a) {
                 __syncthreads();
             }
         }
+#pragma unroll
+        for (int k = 0; k < kCorrTerms; k++) red[k][t] = f[k];
+        __syncthreads();
+        for (int s2 = 128; s2 > 0; s2 >>= 1) {
+            if (t < s2)
+                for (int k = 0; k < kCorrTerms; k++) red[k][t] += red[k][t + s2];
+            __syncthreads();
+        }
+        float* out = a.gcorr + (int64_t)kCorrStride * g;
+        if (t < kCorrTerms) out[t] = red[t][0];
+        if (t == kCorrTerms) out[kCorrTerms] = cx;
+        if (t == kCorrTerms + 1) out[kCorrTerms + 1] = cy;
+        if (t == kCorrTerms + 2) out[kCorrTerms + 2] = cz;
+        if (t == kCorrTerms + 3) out[kCorrTerms + 3] = 0.f;
+    }
+}
+
+// Register-resident network variant of the learned correction.  Each wave
+// evaluates the network for 64 pairs at a time with the activations kept in
+// registers: the products are written transposed (weights are the MFMA's A
+// operand, held in registers for the whole kernel; pairs are the N
+// dimension), so the output layout of one layer is the B layout of the next
+// once the next layer's K index is permuted to match:  K slot q*8 + j of
+// step ks holds hidden unit (2 ks + j/4)*16 + q*4 + j%4.  Features go in and
+// outputs come out through lane shuffles; no LDS and no workgroup barrier
+// inside the network.
+__device__ __forceinline__ bf16x8 pack8(const floatx4& a, const floatx4& b) {
+    bf16x8 r;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        r[i] = (__bf16)gelu(a[i]);
+        r[4 + i] = (__bf16)gelu(b[i]);
+    }
+    return r;
+}
+
+// 8 BF16 of row `row` of an out-major weight copy: units (2ks)*16 + q*4 .. +3
+// then (2ks+1)*16 + q*4 .. +3 (the permuted K order above)
+__device__ __forceinline__ bf16x8 ld_perm(const uint16_t* W, int ld, int row, int ks, int q) {
+    const uint2 lo = *reinterpret_cast<const uint2*>(W + row * ld + (2 * ks) * 16 + q * 4);
+    const uint2 hi = *reinterpret_cast<const uint2*>(W + row * ld + (2 * ks + 1) * 16 + q * 4);
+    const uint4 v = make_uint4(lo.x, lo.y, hi.x, hi.y);
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_corr_net(CorrArgs a) {
+    __shared__ float sb[NH + NH + NOUTP];
+    __shared__ float red[kCorrTerms][256];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, r16 = lane & 15, q = lane >> 4;
+    const float eps2 = a.eps * a.eps;
+    for (int i = t; i < NH; i += 256) {
+        sb[i] = a.master[OFF_B1 + i];
+        sb[NH + i] = a.master[OFF_B2 + i];
+    }
+    if (t < NOUTP) sb[2 * NH + t] = t < NOUT ? a.master[OFF_B3 + t] : 0.f;
+    bf16x8 w1a[4], w2a[4][2], w3a[2];
+#pragma unroll
+    for (int mt = 0; mt < 4; mt++) {
+        w1a[mt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(a.wbf + OFFB_W1T + (mt * 16 + r16) * NIN + q * 8));
+#pragma unroll
+        for (int ks = 0; ks < 2; ks++) w2a[mt][ks] = ld_perm(a.wbf + OFFB_W2T, NH, mt * 16 + r16, ks, q);
+    }
+#pragma unroll
+    for (int ks = 0; ks < 2; ks++) w3a[ks] = ld_perm(a.wbf + OFFB_W3T, NH, r16, ks, q);
+    __syncthreads();
+    for (int g = blockIdx.x; g < a.n_groups; g += gridDim.x) {
+        const int g0 = a.group_off[g];
+        const int ng = a.group_off[g + 1] - g0;
+        const bool gok = ng >= 1 && ng <= kBlock && g0 >= 0 && g0 + ng <= a.n;
+        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        if (gok && t < ng)
+            for (int k = 0; k < 3; k++) lo[k] = hi[k] = a.pos[3 * (g0 + t) + k];
+        __syncthreads();
+        for (int k = 0; k < 3; k++) {
+            red[k][t] = lo[k];
+            red[3 + k][t] = hi[k];
+        }
+        __syncthreads();
+        for (int s2 = 128; s2 > 0; s2 >>= 1) {
+            if (t < s2)
+                for (int k = 0; k < 3; k++) {
+                    red[k][t] = fminf(red[k][t], red[k][t + s2]);
+                    red[3 + k][t] = fmaxf(red[3 + k][t], red[3 + k][t + s2]);
+                }
+            __syncthreads();
+        }
+        const float cx = 0.5f * (red[0][0] + red[3][0]);
+        const float cy = 0.5f * (red[1][0] + red[4][0]);
+        const float cz = 0.5f * (red[2][0] + red[5][0]);
+        const float ex = red[3][0] - red[0][0], ey = red[4][0] - red[1][0], ez = red[5][0] - red[2][0];
+        const float h = 0.5f * sqrtf(ex * ex + ey * ey + ez * ez);
+        float f[kCorrTerms];
+#pragma unroll
+        for (int k = 0; k < kCorrTerms; k++) f[k] = 0.f;
+        int64_t lb = 0, le = 0, p0 = 0, nce = 0;
+        if (gok) {
+            list_range(a.list_off, a.n_entries, g, lb, le);
+            p0 = clamp64(a.pair_off[g], 0, a.n_pairs);
+            const int64_t p1 = clamp64(a.pair_off[g + 1], p0, a.n_pairs);
+            nce = (p1 - p0) < (le - lb) ? (p1 - p0) : (le - lb);
+        } else if (t == 0) {
+            atomicOr(a.err, kErrGroup);
+        }
+        for (int64_t base = 64 * (int64_t)w; base < nce; base += 256) {
+            // features of this lane's pair
+            const int64_t k = base + lane;
+            float fe[NFEAT];
+            float sc = 0.f, mx = 0.f, my = 0.f, mz = 0.f;
+            bool fok = false;
+            if (k < nce) {
+                const int64_t c = (int64_t)a.list_idx[lb + k] - a.n;
+                if (c >= 0 && c < a.n_cells) {
+                    const float* cm = a.cell_mom + 12 * c;
+                    fok = pair_features(cx, cy, cz, h, cm, a.eps, fe, sc);
+                    mx = cm[0];
+                    my = cm[1];
+                    mz = cm[2];
+                } else {
+                    atomicOr(a.err, kErrIndex);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < NFEAT; j++) fe[j] = fok ? fe[j] : 0.f;
+            float ov[NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int tau = 0; tau < 4; tau++) {
+                const int src = tau * 16 + r16;
+                float v[NFEAT];
+#pragma unroll
+                for (int j = 0; j < NFEAT; j++) v[j] = __shfl(fe[j], src);
+                bf16x8 xb;
+#pragma unroll
+                for (int j = 0; j < 8; j++) {
+                    const float x = q == 0 ? v[j] : (q == 1 && j < 4 ? v[8 + j] : 0.f);
+                    xb[j] = (__bf16)x;
+                }
+                floatx4 acc[4];
+#pragma unroll
+                for (int mt = 0; mt < 4; mt++) {
+                    const float4 b = *reinterpret_cast<const float4*>(sb + mt * 16 + q * 4);
+                    acc[mt] = mfma(w1a[mt], xb, floatx4{b.x, b.y, b.z, b.w});
+                }
+                const bf16x8 h0 = pack8(acc[0], acc[1]), h1 = pack8(acc[2], acc[3]);
+#pragma unroll
+                for (int mt = 0; mt < 4; mt++) {
+                    const float4 b = *reinterpret_cast<const float4*>(sb + NH + mt * 16 + q * 4);
+                    acc[mt] = mfma(w2a[mt][0], h0, floatx4{b.x, b.y, b.z, b.w});
+                    acc[mt] = mfma(w2a[mt][1], h1, acc[mt]);
+                }
+                const bf16x8 g0b = pack8(acc[0], acc[1]), g1b = pack8(acc[2], acc[3]);
+                const float4 b3 = *reinterpret_cast<const float4*>(sb + 2 * NH + q * 4);
+                floatx4 o = mfma(w3a[0], g0b, floatx4{b3.x, b3.y, b3.z, b3.w});
+                o = mfma(w3a[1], g1b, o);
+                // outputs 0..3 of pair (tau, r16) sit in lane r16, outputs 4, 5 in lane r16 + 16
+                float s[NOUT];
+#pragma unroll
+                for (int i = 0; i < 4; i++) s[i] = __shfl(o[i], r16);
+                s[4] = __shfl(o[0], r16 + 16);
+                s[5] = __shfl(o[1], r16 + 16);
+                if (q == tau)
+#pragma unroll
+                    for (int i = 0; i < NOUT; i++) ov[i] = s[i];
+            }
+            if (fok && sc > 0.f) {
+                const float tr = (ov[0] + ov[1] + ov[2]) * (1.f / 3.f);
+                const float Q[6] = {(ov[0] - tr) * sc, (ov[1] - tr) * sc, (ov[2] - tr) * sc,
+                                    ov[3] * sc,        ov[4] * sc,        ov[5] * sc};
+                quad_expand_add(cx - mx, cy - my, cz - mz, Q, eps2, f);
+            }
+        }
+        __syncthreads();
 #pragma unroll
         for (int k = 0; k < kCorrTerms; k++) red[k][t] = f[k];
         __syncthreads();
@@ -1204,14 +1388,17 @@ int otoo_correction(otoo_ctx* c, int32_t kind, otoo_mlp* m, int32_t n, const flo
     CorrArgs ca{n,        pos,     n_groups, group_off, list_off, n_entries, list_idx,
                 pair_off, n_pairs, n_cells,  cell_mom,  cell_stride, eps,   corr,
                 m ? m->wbf : nullptr, m ? m->master : nullptr, gcorr, c->errflag};
-    const int per_cu = kind == OTOO_CORR_MLP ? 2 : 6;
+    const int per_cu = kind == OTOO_CORR_MLP ? 3 : 6;
     const int blocks = (int)std::min<int64_t>((int64_t)per_cu * c->num_cu, n_groups);
     if (kind == OTOO_CORR_PAIRS)
         hipLaunchKernelGGL(k_corr_group<kCorrPairs>, dim3(blocks), dim3(256), 0, c->stream, ca);
     else if (kind == OTOO_CORR_QUAD)
         hipLaunchKernelGGL(k_corr_group<kCorrQuad>, dim3(blocks), dim3(256), 0, c->stream, ca);
-    else
+    else if (c->tune.net_kernel == 1)
         hipLaunchKernelGGL(k_corr_group<kCorrMlp>, dim3(blocks), dim3(256), 0, c->stream, ca);
+    else
+        hipLaunchKernelGGL(k_corr_net, dim3((int)std::min<int64_t>(2LL * c->num_cu, n_groups)), dim3(256), 0,
+                           c->stream, ca);
     HIP_TRY(c, hipGetLastError());
     return OTOO_OK;
 }

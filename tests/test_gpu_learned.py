@@ -239,14 +239,22 @@ def test_training_reduces_loss_and_helps_forces(env):
     assert e_l < 0.8 * e_m
 
 
-def test_fused_learned_correction_matches_oracle(env):
-    """The fused per-group learned correction against the oracle's list force
-    with the oracle network's tensors (FP64 features rounded to BF16, BF16
-    weights): the tensors differ by the BF16 activations (~3e-3 relative), and
-    the correction is a small part of the force."""
+@pytest.mark.parametrize("net_kernel", [0, 1])
+def test_fused_learned_correction_matches_oracle(env, net_kernel):
+    """The fused per-group learned correction (register-resident network, or
+    the LDS-staged one) against the oracle's list force with the oracle
+    network's tensors (FP64 features rounded to BF16, BF16 weights): the
+    tensors differ by the BF16 activations (~3e-3 relative), and the
+    correction is a small part of the force."""
     ctx, net, d, lists, cm, pos32, mass32 = (env[k] for k in ("ctx", "net", "d", "lists", "cm", "pos32", "mass32"))
     net.set_params(env["params"])
-    gc = ctx.correction(d, otoo.CORR_MLP, EPS, net=net)
+    old = ctx.tuning()
+    ctx.set_tuning(net_kernel=net_kernel)
+    try:
+        gc = ctx.correction(d, otoo.CORR_MLP, EPS, net=net)
+    finally:
+        ctx.set_tuning(chunk=old.chunk, blocks_per_cu=old.blocks_per_cu, lpt=old.lpt, tile=old.tile,
+                       net_kernel=old.net_kernel)
     acc, pot = ctx.force(d, EPS, gcorr=gc)
     torch.cuda.synchronize()
     ctx.check()
