@@ -44,7 +44,6 @@ WORKLOADS = {
     "cube16m": ("grf_cube", dict(ng=256, seed=4), 1e-3, 0.7,
                 "GRF cube 256^3 P(k)~k^-2 rms 0.3 seed=4 eps=1e-3 theta=0.7"),
 }
-DEFAULT_SCHEDULE = dict(group_mode="chunk", g_max=32, chunk=1 << 24, blocks_per_cu=8, lpt=0, tile=256)
 SAMPLE_SEED = {"plummer16k": 100, "plummer1m": 101, "polytrope2m": 102, "cube16m": 104}
 
 
@@ -81,12 +80,11 @@ def make_workload(name):
 # ------------------------------------------------------------------ CPU baseline leg (the oracle)
 
 
-def cpu_baseline(pos32, mass32, lists, cm, eps, pos64_sorted, m64_sorted, sample):
-    """The FP64 oracle timed on this host over the whole workload (list sums
-    for every target) plus the direct-sum references of a 4096-particle sample.
+def cpu_baseline(pos32, mass32, lists, cm, eps):
+    """The FP64 oracle timed on this host over the whole workload: list sums
+    for every target, on the same FP32 inputs and lists as the device.
 
-    Returns (baseline dict, list-sum references (acc, pot), direct references
-    (acc, pot) on the sample)."""
+    Returns (baseline dict, list-sum references (acc, pot))."""
     import oracle
     oracle.build()
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -95,18 +93,20 @@ def cpu_baseline(pos32, mass32, lists, cm, eps, pos64_sorted, m64_sorted, sample
                             lists.list_idx, cm[:, :3].astype(np.float64), cm[:, 3].astype(np.float64),
                             float(np.float32(eps)))
     dt = time.perf_counter() - t0
-    direct = oracle.direct(pos64_sorted, m64_sorted, eps, tgt=sample)
     base = {"value": lists.interactions / dt / 1e9, "unit": "Ginteractions/s", "cores": threads, "kind": "oracle",
             "sample": f"FP64 list sums over all {len(mass32)} targets of the workload "
                       f"({lists.interactions} interactions) in {dt:.2f} s"}
-    return base, ref, direct
+    return base, ref
 
 
-def direct_reference(pos64_sorted, m64_sorted, eps, sample):
-    """Direct-sum references for the learned comparison (part of the CPU leg)."""
-    import oracle
-    oracle.build()
-    return oracle.direct(pos64_sorted, m64_sorted, eps, tgt=sample)
+def direct_reference(ctx, d, sample, eps):
+    """FP64 direct sums on the device at the sample (indices in device order)."""
+    import torch
+    tgt = torch.from_numpy(np.asarray(sample, np.int32)).to(d.pos.device)
+    a, p = ctx.direct(d.pos, d.mass, tgt, eps)
+    torch.cuda.synchronize()
+    ctx.check()
+    return a.cpu().numpy(), p.cpu().numpy()
 
 
 def rel_err(a, ref):
@@ -156,8 +156,8 @@ def learned_comparison(ctx, log, steps, train_steps, timing_reps):
     tree = otoo.Tree(pos, m, n_crit=16)
     perm, pos32, mass32, cm = tree.export(12)
     sample = synth.sample_idx(len(m), 4096, seed=103)
-    a_dir, _ = direct_reference(pos[perm], m[perm], eps, sample)
-    cells = tree.cells()
+    a_dir, _ = direct_reference(ctx, otoo.DeviceLists.from_host(pos32, mass32, tree.walk(theta=0.5), cm, "cuda:0"),
+                                sample, eps)
 
     def run(theta, modes, g_max):
         # schedules from the autotuner's sweep: whole lists for small groups, split lists for large ones
@@ -272,18 +272,13 @@ def main():
 
     key = f"{at.device_key(0)}:{args.workload}"
     cache_path = args.cache or at.DEFAULT_CACHE
-    sched = dict(DEFAULT_SCHEDULE)
-    source = "defaults"
     if args.autotune:
         best, table = at.autotune(tree, eps, theta, ctx, log=log)
         at.save_cache(key, best, cache_path)
-        sched.update({k: best[k] for k in sched})
+        sched = {k: best[k] for k in at.DEFAULT_SCHEDULE}
         source = "autotuned now"
     else:
-        cached = at.load_cache(cache_path).get(key)
-        if cached:
-            sched.update({k: cached[k] for k in sched})
-            source = "autotune cache"
+        sched, source = at.cached_schedule(args.workload, 0, cache_path)
     for k, v in (("g_max", args.g_max), ("group_mode", args.group_mode), ("chunk", args.chunk),
                  ("blocks_per_cu", args.blocks_per_cu), ("tile", args.tile)):
         if v:
@@ -366,19 +361,20 @@ def main():
                      "kernel": "k_force", "kernel_ms": k_ms, "flops_per_interaction": FLOPS_PER_INTERACTION},
         "host": {"tree_build_ms": 1e3 * (t1 - t0), "walk_ms": 1e3 * (t3 - t2), "h2d_ms": 1e3 * (t5 - t4)},
     }
+    # accuracy of the tree force: FP64 direct sums on the device at a 4096-particle sample
+    sample = __import__("synth").sample_idx(len(m), 4096, seed=SAMPLE_SEED.get(args.workload, 100))
+    a_dir, p_dir = direct_reference(ctx, d, sample, eps)
+    et, ept = rel_err(acc[sample], a_dir), rel_err(pot[sample], p_dir)
+    res["accuracy"] = {"tree_acc_median_vs_direct": float(np.median(et)),
+                       "tree_acc_p99_vs_direct": float(np.quantile(et, 0.99)),
+                       "tree_pot_median_vs_direct": float(np.median(ept)), "direct_sample": len(sample)}
     if not args.no_cpu_baseline:
-        sample = __import__("synth").sample_idx(len(m), 4096, seed=SAMPLE_SEED.get(args.workload, 100))
-        base, (a_ref, p_ref), (a_dir, p_dir) = cpu_baseline(pos32, mass32, lists, cm, eps, pos[perm], m[perm],
-                                                            sample)
+        base, (a_ref, p_ref) = cpu_baseline(pos32, mass32, lists, cm, eps)
         ea, ep = rel_err(acc, a_ref), rel_err(pot, p_ref)
-        et, ept = rel_err(acc[sample], a_dir), rel_err(pot[sample], p_dir)
         res["cpu_baseline"] = base
-        res["accuracy"] = {"parity_acc_median": float(np.median(ea)), "parity_acc_max": float(ea.max()),
-                           "parity_pot_median": float(np.median(ep)), "parity_pot_max": float(ep.max()),
-                           "tree_acc_median_vs_direct": float(np.median(et)),
-                           "tree_acc_p99_vs_direct": float(np.quantile(et, 0.99)),
-                           "tree_pot_median_vs_direct": float(np.median(ept)), "direct_sample": len(sample)}
-        log(f"accuracy {res['accuracy']}")
+        res["accuracy"].update({"parity_acc_median": float(np.median(ea)), "parity_acc_max": float(ea.max()),
+                                "parity_pot_median": float(np.median(ep)), "parity_pot_max": float(ep.max())})
+    log(f"accuracy {res['accuracy']}")
     if not args.no_learned:
         try:
             res["learned"] = learned_comparison(ctx, log, args.steps, args.train_steps, max(5, min(args.steps, 20)))

@@ -198,6 +198,21 @@ int otoo_force(otoo_ctx* ctx, int32_t n, const float* pos, const float* mass, in
                int32_t n_cells, const float* cell_mom, int32_t cell_stride, float eps, const float* gcorr,
                float* out_acc, double* out_pot);
 
+/* Direct summation at selected targets: the O(N^2) sum of Sec. 2 that the
+ * tree approximates, used as the accuracy reference of the tree force.  For
+ * k < n_tgt and i = tgt[k], with d = x_j - x_i and r^2 = |d|^2 + eps^2:
+ *   out_acc[k] = sum_{j != i} m_j d r^-3,   out_pot[k] = -sum_{j != i} m_j r^-1
+ * in FP64 over the FP32 inputs.  Device pointers: pos [n][3], mass [n],
+ * tgt [n_tgt] int32 indices into pos; out_acc [n_tgt][3] FP64 and
+ * out_pot [n_tgt] FP64 are overwritten.  Asynchronous on the context stream;
+ * the sum over j runs in fixed slices combined in a fixed order, so results
+ * are reproducible.  A target outside [0, n) gives zeros and is flagged for
+ * otoo_check.  Returns EINVAL for n < 1, n_tgt < 0, eps not positive and
+ * finite, or a null pointer (tgt and the outputs may be NULL when
+ * n_tgt == 0). */
+int otoo_direct(otoo_ctx* ctx, int32_t n, const float* pos, const float* mass, int32_t n_tgt, const int32_t* tgt,
+                float eps, double* out_acc, double* out_pot);
+
 /* Textbook quadrupole tensor of every (group, cell) pair (the p = 2 term of
  * the multipole expansion the paper names in Sec. 2 but does not use):
  * corr[pair_off[g] + k] = 3 S_c - tr(S_c) I for the k-th cell entry c of

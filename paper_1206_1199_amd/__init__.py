@@ -65,7 +65,7 @@ EXPORTED = [
     "otoo_tree_links", "otoo_tree_walk", "otoo_lists_free", "otoo_create", "otoo_destroy",
     "otoo_set_stream", "otoo_last_error", "otoo_set_tuning", "otoo_get_tuning", "otoo_force",
     "otoo_check", "otoo_enable_timing", "otoo_last_timing", "otoo_graph_capture", "otoo_graph_launch",
-    "otoo_quad_exact", "otoo_correction", "otoo_mlp_num_params", "otoo_mlp_create", "otoo_mlp_destroy", "otoo_mlp_set_params",
+    "otoo_quad_exact", "otoo_correction", "otoo_direct", "otoo_mlp_num_params", "otoo_mlp_create", "otoo_mlp_destroy", "otoo_mlp_set_params",
     "otoo_mlp_get_params", "otoo_mlp_save", "otoo_mlp_load", "otoo_mlp_forward", "otoo_mlp_infer",
     "otoo_mlp_train_samples", "otoo_mlp_backward", "otoo_mlp_train_step",
 ]
@@ -99,6 +99,7 @@ def lib():
         "otoo_force": ([P, I32, P, P, I32, P, I64, P, P, I32, P, I32, F, P, P, P], I32),
         "otoo_correction": ([P, I32, P, I32, P, I32, P, I64, P, P, I64, P, I32, P, I32, F, P, P], I32),
         "otoo_quad_exact": ([P, I32, I32, I64, P, P, I64, P, I32, P, I32, P], I32),
+        "otoo_direct": ([P, I32, P, P, I32, P, F, P, P], I32),
         "otoo_check": ([P], I32),
         "otoo_enable_timing": ([P, I32], I32),
         "otoo_last_timing": ([P, ctypes.POINTER(F), ctypes.POINTER(F)], I32),
@@ -360,6 +361,18 @@ class Context:
                                           _tptr(corr)),
                     "otoo_quad_exact")
         return corr
+
+    def direct(self, pos, mass, tgt, eps: float):
+        """FP64 direct sums at targets ``tgt`` (int32 device tensor of indices into
+        ``pos``): (acc float64 [n_tgt, 3], pot float64 [n_tgt])."""
+        import torch
+        n_tgt = int(tgt.numel())
+        dev = f"cuda:{self.device}"
+        acc = torch.empty((max(n_tgt, 1), 3), dtype=torch.float64, device=dev)[:n_tgt]
+        pot = torch.empty(max(n_tgt, 1), dtype=torch.float64, device=dev)[:n_tgt]
+        self._raise(lib().otoo_direct(self._h, int(pos.shape[0]), _tptr(pos), _tptr(mass), n_tgt, _tptr(tgt),
+                                      float(eps), _tptr(acc), _tptr(pot)), "otoo_direct")
+        return acc, pot
 
     def check(self):
         self._raise(lib().otoo_check(self._h), "otoo_check")

@@ -99,3 +99,23 @@ def save_cache(entry_key: str, best: dict, path: str = DEFAULT_CACHE):
     with open(tmp, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)
     os.replace(tmp, path)
+
+
+DEFAULT_SCHEDULE = dict(group_mode="chunk", g_max=32, chunk=1 << 24, blocks_per_cu=8, lpt=0, tile=256)
+
+
+def cached_schedule(workload: str, device: int = 0, path: str = DEFAULT_CACHE):
+    """(schedule, source): the cached choice for this device and workload, or the defaults."""
+    sched = dict(DEFAULT_SCHEDULE)
+    cached = load_cache(path).get(f"{device_key(device)}:{workload}")
+    if not cached:
+        return sched, "defaults"
+    sched.update({k: cached[k] for k in sched})
+    return sched, "autotune cache"
+
+
+def apply_schedule(ctx: Context, sched: dict):
+    """Set the device half of a schedule on a context."""
+    ctx.set_tuning(chunk=int(sched["chunk"]), blocks_per_cu=int(sched["blocks_per_cu"]), lpt=int(sched["lpt"]),
+                   tile=int(sched["tile"]))
+

@@ -71,10 +71,15 @@ __device__ __forceinline__ floatx4 mfma(bf16x8 a, bf16x8 b, floatx4 c) {
 }
 
 // tanh-form GELU (Hendrycks & Gimpel): z/2 (1 + tanh(y)) = z sigmoid(2y),
-// y = sqrt(2/pi) (z + 0.044715 z^3)
+// y = sqrt(2/pi) (z + 0.044715 z^3).  sigmoid(2y) = 1 / (1 + 2^(-2 y log2 e))
+// and -2 y log2 e = z (G1 + G2 z^2): three VALU, one v_exp_f32, one add and
+// one v_rcp_f32.
+constexpr double kLog2e = 1.4426950408889634;
+constexpr float GELU_G1 = (float)(-2.0 * 0.7978845608028654 * kLog2e);
+constexpr float GELU_G2 = (float)(-2.0 * 0.7978845608028654 * kLog2e * 0.044715);
 __device__ __forceinline__ float gelu_sig(float z) {
-    const float y2 = 2.f * GELU_C * fmaf(GELU_A * z, z * z, z);
-    return __builtin_amdgcn_rcpf(1.f + __expf(-y2));
+    const float e = __builtin_amdgcn_exp2f(z * fmaf(GELU_G2, z * z, GELU_G1));
+    return __builtin_amdgcn_rcpf(1.f + e);
 }
 __device__ __forceinline__ float gelu(float z) { return z * gelu_sig(z); }
 __device__ __forceinline__ float gelu_grad(float z) {

@@ -34,6 +34,7 @@ def test_null_context_and_bad_arguments_return_einval():
     assert lib.otoo_correction(None, 1, None, 1, None, 1, None, 0, None, None, 0, None, 0, None, 12, 0.1, None,
                                None) == otoo.EINVAL
     assert lib.otoo_quad_exact(None, 1, 1, 0, None, None, 0, None, 0, None, 12, None) == otoo.EINVAL
+    assert lib.otoo_direct(None, 1, None, None, 0, None, 0.1, None, None) == otoo.EINVAL
     assert lib.otoo_check(None) == otoo.EINVAL
     assert lib.otoo_graph_launch(None) == otoo.EINVAL
     assert lib.otoo_set_tuning(None, None) == otoo.EINVAL

@@ -166,14 +166,70 @@ def test_malformed_lists_are_reported(ctx):
 
 def test_plummer_1m_sampled(ctx):
     """The benchmark workload (Plummer 2^20, eps 0.005, theta 0.5) on a
-    4096-particle sample, in the launch configuration the benchmark times."""
+    4096-particle sample, in the launch configuration the benchmark times
+    (group size and schedule from the autotuner's cache, else its defaults)."""
+    from paper_1206_1199_amd import autotune as at
+    sched, source = at.cached_schedule("plummer1m")
+    mode = otoo.GROUP_CHUNK if sched["group_mode"] == "chunk" else otoo.GROUP_CELL
     pos, m = synth.plummer(1 << 20, seed=1)
-    t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.5, 64)
-    ctx.set_tuning(chunk=1024, lpt=1, blocks_per_cu=8)
-    acc, pot = _gpu(ctx, d, 0.005)
+    t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.5, sched["g_max"], mode)
+    old = ctx.tuning()
+    at.apply_schedule(ctx, sched)
+    try:
+        acc, pot = _gpu(ctx, d, 0.005)
+    finally:
+        ctx.set_tuning(chunk=old.chunk, blocks_per_cu=old.blocks_per_cu, lpt=old.lpt, tile=old.tile)
     sample = synth.sample_idx(len(m), 4096, seed=101)
     a_ref, p_ref = _oracle(pos32, mass32, lists, cm, 0.005, tgt=sample)
-    _assert_parity(acc[sample], pot[sample], a_ref, p_ref, "plummer 2^20 sample")
+    _assert_parity(acc[sample], pot[sample], a_ref, p_ref, f"plummer 2^20 sample ({source}: {sched})")
+
+
+def _direct(ctx, pos32, mass32, tgt, eps):
+    dev = "cuda:0"
+    a, p = ctx.direct(torch.from_numpy(pos32).to(dev), torch.from_numpy(mass32).to(dev),
+                      torch.from_numpy(np.asarray(tgt, np.int32)).to(dev), eps)
+    torch.cuda.synchronize()
+    ctx.check()
+    return a.cpu().numpy(), p.cpu().numpy()
+
+
+def test_direct_sum_matches_oracle(ctx):
+    """FP64 direct sums on the device (the accuracy reference of the tree
+    force) against the oracle's direct sum: both FP64, different order."""
+    pos, m = synth.plummer(20000, seed=8)
+    pos32, mass32 = pos.astype(np.float32), m.astype(np.float32)
+    tgt = synth.sample_idx(len(m), 999, seed=9)
+    a, p = _direct(ctx, pos32, mass32, tgt, 0.01)
+    a_ref, p_ref = oracle.direct(pos32.astype(np.float64), mass32.astype(np.float64), float(np.float32(0.01)),
+                                 tgt=tgt)
+    ea, ep = oracle.rel_err(a, a_ref), oracle.rel_err(p, p_ref)
+    print(f"direct: acc max {ea.max():.2e} pot max {ep.max():.2e}", flush=True)
+    assert ea.max() <= 1e-12 and ep.max() <= 1e-12
+    # a repeated call is bitwise identical
+    a2, p2 = _direct(ctx, pos32, mass32, tgt, 0.01)
+    assert np.array_equal(a, a2) and np.array_equal(p, p2)
+
+
+def test_direct_sum_edge_cases(ctx):
+    pos32 = np.array([[0, 0, 0], [1, 0, 0], [0, 2, 0]], np.float32)
+    mass32 = np.array([1, 2, 3], np.float32)
+    a, p = _direct(ctx, pos32[:1], mass32[:1], [0], 0.5)          # one particle: no pair
+    assert np.all(a == 0) and np.all(p == 0)
+    a, p = _direct(ctx, pos32, mass32, [0, 2, 0], 0.5)            # repeated targets, ragged block
+    a_ref, p_ref = oracle.direct(pos32.astype(np.float64), mass32.astype(np.float64), 0.5, tgt=[0, 2, 0])
+    assert np.allclose(a, a_ref, rtol=1e-14, atol=0) and np.allclose(p, p_ref, rtol=1e-14, atol=0)
+    a, p = _direct(ctx, pos32, mass32, [], 0.5)                   # no targets
+    assert a.shape == (0, 3) and p.shape == (0,)
+    dev = "cuda:0"
+    a_t, p_t = ctx.direct(torch.from_numpy(pos32).to(dev), torch.from_numpy(mass32).to(dev),
+                          torch.tensor([1, 3], dtype=torch.int32, device=dev), 0.5)   # index 3 is out of range
+    torch.cuda.synchronize()
+    with pytest.raises(otoo.OtooError):
+        ctx.check()
+    assert np.all(a_t.cpu().numpy()[1] == 0)
+    with pytest.raises(otoo.OtooError):
+        ctx.direct(torch.from_numpy(pos32).to(dev), torch.from_numpy(mass32).to(dev),
+                   torch.tensor([0], dtype=torch.int32, device=dev), 0.0)
 
 
 def _oracle_quad(pos32, mass32, lists, cm, eps, quad, tgt=None):
