@@ -12,6 +12,7 @@ Contents
                                            tensors per (group, cell))  (oracle.c)
   point_field(x, src_off, src_idx, ...)   exact field of source sets at points
   quad_field(x, centre, quad, eps)        quadrupole-form field alone
+  sph_kernel(r, h), sph_sum(pos, h, q)    SPH gather sums, brute force (oracle.c)
   tree                                    recursive octree, moments, walk (tree.py)
   mlp                                     FP64 network, loss and hand backward (mlp.py)
 
@@ -62,6 +63,10 @@ def _load():
         lib.oracle_list_force_expanded.restype = ctypes.c_int
         lib.oracle_quad_derivs.argtypes = [I, P, P, P, D, P, P, P, P]
         lib.oracle_quad_derivs.restype = None
+        lib.oracle_sph_kernel.argtypes = [D, D]
+        lib.oracle_sph_kernel.restype = D
+        lib.oracle_sph_sum.argtypes = [I, P, P, P, I, P, P]
+        lib.oracle_sph_sum.restype = None
         _lib = lib
     return _lib
 
@@ -170,6 +175,24 @@ def quad_derivs(x, centre, quad, eps):
     lib.oracle_quad_derivs(len(x), _ptr(x), _ptr(c), _ptr(q), float(eps), _ptr(acc), _ptr(jac), _ptr(hess),
                            _ptr(pot))
     return acc, jac, hess, pot
+
+
+def sph_kernel(r, h):
+    """Cubic B-spline W(r, h) of compact support h (oracle.c, sph_w)."""
+    lib = _load()
+    return float(lib.oracle_sph_kernel(float(r), float(h)))
+
+
+def sph_sum(pos, h, q, tgt=None):
+    """s_i = sum_j q_j (W(r_ij, h_i) + W(r_ij, h_j)) / 2 over all j, self included."""
+    lib = _load()
+    pos, h, q = _f64(pos), _f64(h), _f64(q)
+    n = len(h)
+    tg = None if tgt is None else _i64(tgt)
+    nt = n if tg is None else len(tg)
+    out = np.empty(nt)
+    lib.oracle_sph_sum(n, _ptr(pos), _ptr(h), _ptr(q), nt, _ptr(tg), _ptr(out))
+    return out
 
 
 def rel_err(a, ref):

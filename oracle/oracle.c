@@ -377,3 +377,53 @@ void oracle_quad_field(int64_t n_pts, const double *x, const double *centre, con
         pot[t] = phi;
     }
 }
+
+/*
+ * SPH-style gather sums (Sec. 2.3, Eq. 4): for each target i,
+ *     s_i = sum over all j (i included) of q_j Wbar_ij,
+ *     Wbar_ij = (W(r_ij, h_i) + W(r_ij, h_j)) / 2,
+ * with the cubic B-spline kernel of compact support h (Monaghan & Lattanzio
+ * 1985):  W(r, h) = 8 / (pi h^3) w(r / h),
+ *     w(u) = 1 - 6 u^2 + 6 u^3    for 0 <= u <= 1/2,
+ *            2 (1 - u)^3          for 1/2 < u <= 1,
+ *            0                    beyond.
+ * The paper leaves the kernel open (bell-shaped, zero beyond the neighbour
+ * radius h); this kernel and the symmetrised pair weight are the reading
+ * taken.  Brute force over all j: no tree and no lists.
+ */
+static const double kPi = 3.14159265358979323846;
+
+static double sph_w(double r, double h)
+{
+    double u = r / h;
+    double w;
+    if (u <= 0.5) {
+        w = 1.0 - 6.0 * u * u + 6.0 * u * u * u;
+    } else if (u <= 1.0) {
+        double v = 1.0 - u;
+        w = 2.0 * v * v * v;
+    } else {
+        w = 0.0;
+    }
+    return 8.0 / (kPi * h * h * h) * w;
+}
+
+double oracle_sph_kernel(double r, double h) { return sph_w(r, h); }
+
+void oracle_sph_sum(int64_t n, const double *pos, const double *h, const double *q, int64_t n_tgt,
+                    const int64_t *tgt, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < n_tgt; k++) {
+        int64_t i = tgt ? tgt[k] : k;
+        double s = 0.0;
+        for (int64_t j = 0; j < n; j++) {
+            double dx = pos[3 * j + 0] - pos[3 * i + 0];
+            double dy = pos[3 * j + 1] - pos[3 * i + 1];
+            double dz = pos[3 * j + 2] - pos[3 * i + 2];
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            s += q[j] * 0.5 * (sph_w(r, h[i]) + sph_w(r, h[j]));
+        }
+        out[k] = s;
+    }
+}
