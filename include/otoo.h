@@ -135,6 +135,20 @@ typedef struct {
  * device force relies on to remove the self pair.  *out is freed by
  * otoo_lists_free.  EINVAL on bad parameters, ENOMEM on allocation failure. */
 int otoo_tree_walk(const otoo_tree* tree, const otoo_walk_params* params, otoo_lists** out);
+
+/* Neighbour lists for SPH gather sums (Sec. 2.3, Eq. 4-5): the same grouped
+ * walk with the SPH bounding radius in place of the MAC.  There is no
+ * particle-cell interaction: a cell is either opened or skipped whole, so
+ * lists hold particles only (n_cellent = 0).  With R_c = max |COM_c - x_j|
+ * and r_SPH = max (|COM_c - x_j| + h_j) over the cell's particles (Eq. 5),
+ * a cell is skipped iff d_min >= max(r_SPH, R_c + max_{i in g} h_i), so every
+ * pair closer than max(h_i, h_j) -- every pair with a nonzero symmetrised
+ * kernel weight -- is listed.  h [n] (host, FP64, > 0 and finite) is given
+ * in the caller's particle order, as passed to otoo_tree_build.  *out is
+ * freed by otoo_lists_free.  EINVAL on bad parameters, ENOMEM on allocation
+ * failure. */
+int otoo_tree_walk_sph(const otoo_tree* tree, const double* h, int32_t group_mode, int32_t g_max,
+                       otoo_lists** out);
 void otoo_lists_free(otoo_lists* lists);
 
 /* ======================================================================
@@ -212,6 +226,25 @@ int otoo_force(otoo_ctx* ctx, int32_t n, const float* pos, const float* mass, in
  * n_tgt == 0). */
 int otoo_direct(otoo_ctx* ctx, int32_t n, const float* pos, const float* mass, int32_t n_tgt, const int32_t* tgt,
                 float eps, double* out_acc, double* out_pot);
+
+/* SPH-style gather sums over neighbour lists (Sec. 2.3, Eq. 4).  For every
+ * particle i of group g:
+ *   out[i] = sum over j in L_g of q_j (W(r_ij, h_i) + W(r_ij, h_j)) / 2,
+ * with the cubic B-spline kernel of compact support h,
+ *   W(r, h) = 8 / (pi h^3) w(r / h),  w(u) = 1 - 6u^2 + 6u^3 (u <= 1/2),
+ *   2 (1 - u)^3 (1/2 < u <= 1), 0 beyond.
+ * With the lists of otoo_tree_walk_sph, which hold every pair of nonzero
+ * weight, this is the sum over all particles, the particle's own term
+ * q_i W(0, h_i) included (q = m gives the SPH density).  Device pointers, in
+ * the key order of the device arrays: pos [n][3], h [n] (> 0), q [n] FP32;
+ * group_off, list_off, list_idx as for otoo_force (particle entries only);
+ * out [n] FP32 is overwritten.  FP32 arithmetic; per target the slices of a
+ * workgroup are combined in a fixed order, so results are reproducible.
+ * Entries that are not particles, and malformed groups, are skipped and
+ * flagged for otoo_check.  Asynchronous on the context stream. */
+int otoo_sph_sum(otoo_ctx* ctx, int32_t n, const float* pos, const float* h, const float* q, int32_t n_groups,
+                 const int32_t* group_off, int64_t n_entries, const int64_t* list_off, const int32_t* list_idx,
+                 float* out);
 
 /* Textbook quadrupole tensor of every (group, cell) pair (the p = 2 term of
  * the multipole expansion the paper names in Sec. 2 but does not use):

@@ -62,10 +62,10 @@ class Tuning(ctypes.Structure):
 
 EXPORTED = [
     "otoo_tree_build", "otoo_tree_free", "otoo_tree_info", "otoo_tree_export", "otoo_tree_cells",
-    "otoo_tree_links", "otoo_tree_walk", "otoo_lists_free", "otoo_create", "otoo_destroy",
+    "otoo_tree_links", "otoo_tree_walk", "otoo_tree_walk_sph", "otoo_lists_free", "otoo_create", "otoo_destroy",
     "otoo_set_stream", "otoo_last_error", "otoo_set_tuning", "otoo_get_tuning", "otoo_force",
     "otoo_check", "otoo_enable_timing", "otoo_last_timing", "otoo_graph_capture", "otoo_graph_launch",
-    "otoo_quad_exact", "otoo_correction", "otoo_direct", "otoo_mlp_num_params", "otoo_mlp_create", "otoo_mlp_destroy", "otoo_mlp_set_params",
+    "otoo_quad_exact", "otoo_correction", "otoo_direct", "otoo_sph_sum", "otoo_mlp_num_params", "otoo_mlp_create", "otoo_mlp_destroy", "otoo_mlp_set_params",
     "otoo_mlp_get_params", "otoo_mlp_save", "otoo_mlp_load", "otoo_mlp_forward", "otoo_mlp_infer",
     "otoo_mlp_train_samples", "otoo_mlp_backward", "otoo_mlp_train_step",
 ]
@@ -89,6 +89,7 @@ def lib():
         "otoo_tree_cells": ([P, P, P, P, P, P, P, P, P, P, P], I32),
         "otoo_tree_links": ([P, P, P], I32),
         "otoo_tree_walk": ([P, ctypes.POINTER(_WalkParams), ctypes.POINTER(ctypes.POINTER(_Lists))], I32),
+        "otoo_tree_walk_sph": ([P, P, I32, I32, ctypes.POINTER(ctypes.POINTER(_Lists))], I32),
         "otoo_lists_free": ([ctypes.POINTER(_Lists)], None),
         "otoo_create": ([pp, I32], I32),
         "otoo_destroy": ([P], I32),
@@ -100,6 +101,7 @@ def lib():
         "otoo_correction": ([P, I32, P, I32, P, I32, P, I64, P, P, I64, P, I32, P, I32, F, P, P], I32),
         "otoo_quad_exact": ([P, I32, I32, I64, P, P, I64, P, I32, P, I32, P], I32),
         "otoo_direct": ([P, I32, P, P, I32, P, F, P, P], I32),
+        "otoo_sph_sum": ([P, I32, P, P, P, I32, P, I64, P, P, P], I32),
         "otoo_check": ([P], I32),
         "otoo_enable_timing": ([P, I32], I32),
         "otoo_last_timing": ([P, ctypes.POINTER(F), ctypes.POINTER(F)], I32),
@@ -210,6 +212,19 @@ class Tree:
         p = _WalkParams(mac=mac, theta=theta, delta=delta, m_limit=m_limit, group_mode=group_mode, g_max=g_max)
         out = ctypes.POINTER(_Lists)()
         _check(lib().otoo_tree_walk(self._h, ctypes.byref(p), ctypes.byref(out)), "otoo_tree_walk")
+        return self._take_lists(out)
+
+    def walk_sph(self, h, g_max: int = 64, group_mode: int = GROUP_CHUNK) -> Lists:
+        """Neighbour lists for SPH gather sums; h [n] in the caller's particle order."""
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        if h.shape != (self.n,):
+            raise ValueError("h must have one entry per particle")
+        out = ctypes.POINTER(_Lists)()
+        _check(lib().otoo_tree_walk_sph(self._h, h.ctypes.data_as(ctypes.c_void_p), int(group_mode), int(g_max),
+                                        ctypes.byref(out)), "otoo_tree_walk_sph")
+        return self._take_lists(out)
+
+    def _take_lists(self, out) -> Lists:
         try:
             s = out.contents
             G, E = s.n_groups, s.n_entries
@@ -373,6 +388,16 @@ class Context:
         self._raise(lib().otoo_direct(self._h, int(pos.shape[0]), _tptr(pos), _tptr(mass), n_tgt, _tptr(tgt),
                                       float(eps), _tptr(acc), _tptr(pot)), "otoo_direct")
         return acc, pot
+
+    def sph_sum(self, d: DeviceLists, h, q, out=None):
+        """SPH gather sums over the lists of ``d`` (from Tree.walk_sph): float32 [n].
+        ``h`` and ``q`` are float32 device tensors in the device (key) order."""
+        import torch
+        o = out if out is not None else torch.empty(d.n, dtype=torch.float32, device=f"cuda:{self.device}")
+        self._raise(lib().otoo_sph_sum(self._h, d.n, _tptr(d.pos), _tptr(h), _tptr(q), d.n_groups,
+                                       _tptr(d.group_off), int(d.n_entries), _tptr(d.list_off), _tptr(d.list_idx),
+                                       _tptr(o)), "otoo_sph_sum")
+        return o
 
     def check(self):
         self._raise(lib().otoo_check(self._h), "otoo_check")

@@ -133,6 +133,124 @@ int64_t build_cells(otoo_tree& t, int64_t lo, int64_t hi, int level, int n_crit,
     return c;
 }
 
+enum WalkAction { kOpen = 0, kAccept = 1, kSkip = 2 };
+
+// groups: contiguous ranges of key order, returned as offsets (size G + 1)
+std::vector<int64_t> make_groups(const otoo_tree* t, int mode, int G) {
+    const int64_t n = t->n;
+    std::vector<int64_t> goff;
+    if (mode == OTOO_GROUP_CHUNK) {
+        for (int64_t a = 0; a < n; a += G) goff.push_back(a);
+    } else {
+        // maximal cells with at most G particles, found in preorder; a leaf
+        // above G (only possible at the depth cap) is cut into chunks
+        std::vector<int64_t> stack{0};
+        while (!stack.empty()) {
+            const int64_t c = stack.back();
+            stack.pop_back();
+            if (t->count[c] <= G) {
+                goff.push_back(t->first[c]);
+            } else if (t->nchild[c] == 0) {
+                for (int64_t a = t->first[c]; a < t->first[c] + t->count[c]; a += G) goff.push_back(a);
+            } else {
+                for (int k = t->nchild[c] - 1; k >= 0; k--) stack.push_back(t->children[t->child0[c] + k]);
+            }
+        }
+    }
+    goff.push_back(n);
+    if ((int64_t)goff.size() - 1 > INT32_MAX) throw std::bad_alloc();
+    return goff;
+}
+
+// The stackless next/more walk of every group.  decide(c, d_min, g) says
+// what to do with cell c, where d_min is the distance from the cell's COM to
+// the group's bounding box: open it, accept it as one entry, or skip it.
+// Particles reached are always listed.  Lists hold the accepted cells, then
+// the particles, each part in walk (ascending) order.
+template <class Decide>
+void walk_groups(const otoo_tree* t, const std::vector<int64_t>& goff, Decide decide, otoo_lists_impl* L) {
+    const int64_t n = t->n;
+    const int64_t ng = (int64_t)goff.size() - 1;
+    const int nth = omp_get_max_threads();
+    std::vector<std::vector<int32_t>> buf(nth);
+    std::vector<int64_t> g_thread(ng), g_start(ng), g_ncell(ng), g_len(ng);
+    L->group_box.resize(6 * (size_t)ng);
+#pragma omp parallel
+    {
+        const int tid = omp_get_thread_num();
+        std::vector<int32_t>& B = buf[tid];
+        std::vector<int32_t> parts;
+#pragma omp for schedule(dynamic, 8)
+        for (int64_t g = 0; g < ng; g++) {
+            double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+            for (int64_t p = goff[g]; p < goff[g + 1]; p++)
+                for (int k = 0; k < 3; k++) {
+                    lo[k] = std::min(lo[k], t->pos[3 * p + k]);
+                    hi[k] = std::max(hi[k], t->pos[3 * p + k]);
+                }
+            for (int k = 0; k < 3; k++) {
+                L->group_box[6 * g + k] = (float)lo[k];
+                L->group_box[6 * g + 3 + k] = (float)hi[k];
+            }
+            const size_t start = B.size();
+            parts.clear();
+            int64_t u = n;  // root cell
+            while (u >= 0) {
+                if (u < n) {
+                    parts.push_back((int32_t)u);
+                    u = t->next[u];
+                    continue;
+                }
+                const int64_t c = u - n;
+                const double* cm = &t->com[3 * c];
+                double d2 = 0;
+                for (int k = 0; k < 3; k++) {
+                    const double dk = std::max(0.0, std::max(lo[k] - cm[k], cm[k] - hi[k]));
+                    d2 += dk * dk;
+                }
+                const int act = decide(c, std::sqrt(d2), g);
+                if (act == kOpen) {
+                    u = t->more[u];
+                } else {
+                    if (act == kAccept) B.push_back((int32_t)u);
+                    u = t->next[u];
+                }
+            }
+            g_thread[g] = tid;
+            g_start[g] = (int64_t)start;
+            g_ncell[g] = (int64_t)(B.size() - start);
+            B.insert(B.end(), parts.begin(), parts.end());
+            g_len[g] = (int64_t)(B.size() - start);
+        }
+    }
+    L->group_off.resize(ng + 1);
+    L->list_off.resize(ng + 1);
+    L->n_cellent.resize(ng);
+    int64_t tot = 0, inter = 0;
+    for (int64_t g = 0; g < ng; g++) {
+        L->group_off[g] = (int32_t)goff[g];
+        L->list_off[g] = tot;
+        L->n_cellent[g] = (int32_t)g_ncell[g];
+        tot += g_len[g];
+        inter += (goff[g + 1] - goff[g]) * g_len[g];
+    }
+    L->group_off[ng] = (int32_t)n;
+    L->list_off[ng] = tot;
+    L->list_idx.resize(tot);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t g = 0; g < ng; g++)
+        std::memcpy(&L->list_idx[L->list_off[g]], &buf[g_thread[g]][g_start[g]], sizeof(int32_t) * g_len[g]);
+    L->pub.n_groups = (int32_t)ng;
+    L->pub.n_entries = tot;
+    L->pub.interactions = inter;
+    L->pub.group_off = L->group_off.data();
+    L->pub.list_off = L->list_off.data();
+    L->pub.list_idx = L->list_idx.data();
+    L->pub.n_cellent = L->n_cellent.data();
+    L->pub.group_box = L->group_box.data();
+    L->pub.impl = L;
+}
+
 }  // namespace
 
 extern "C" {
@@ -428,31 +546,8 @@ int otoo_tree_walk(const otoo_tree* t, const otoo_walk_params* wp, otoo_lists** 
     otoo_lists_impl* L = new (std::nothrow) otoo_lists_impl();
     if (!L) return OTOO_ENOMEM;
     try {
-        const int64_t n = t->n, nc = t->n_cells();
-        const int G = wp->g_max;
-        // groups: contiguous ranges of key order
-        std::vector<int64_t> goff;
-        if (wp->group_mode == OTOO_GROUP_CHUNK) {
-            for (int64_t a = 0; a < n; a += G) goff.push_back(a);
-        } else {
-            // maximal cells with at most G particles, found in preorder; a leaf
-            // above G (only possible at the depth cap) is cut into chunks
-            std::vector<int64_t> stack{0};
-            while (!stack.empty()) {
-                const int64_t c = stack.back();
-                stack.pop_back();
-                if (t->count[c] <= G) {
-                    goff.push_back(t->first[c]);
-                } else if (t->nchild[c] == 0) {
-                    for (int64_t a = t->first[c]; a < t->first[c] + t->count[c]; a += G) goff.push_back(a);
-                } else {
-                    for (int k = t->nchild[c] - 1; k >= 0; k--) stack.push_back(t->children[t->child0[c] + k]);
-                }
-            }
-        }
-        goff.push_back(n);
-        const int64_t ng = (int64_t)goff.size() - 1;
-        if (ng > INT32_MAX) throw std::bad_alloc();
+        const int64_t nc = t->n_cells();
+        const std::vector<int64_t> goff = make_groups(t, wp->group_mode, wp->g_max);
         // acceptance radius per cell: accept iff d_min > rc
         std::vector<double> rc(nc);
         for (int64_t c = 0; c < nc; c++) {
@@ -467,83 +562,61 @@ int otoo_tree_walk(const otoo_tree* t, const otoo_walk_params* wp, otoo_lists** 
                 }
             }
         }
-        const int nth = omp_get_max_threads();
-        std::vector<std::vector<int32_t>> buf(nth);
-        std::vector<int64_t> g_thread(ng), g_start(ng), g_ncell(ng), g_len(ng);
-        L->group_box.resize(6 * (size_t)ng);
-#pragma omp parallel
-        {
-            const int tid = omp_get_thread_num();
-            std::vector<int32_t>& B = buf[tid];
-            std::vector<int32_t> parts;
-#pragma omp for schedule(dynamic, 8)
-            for (int64_t g = 0; g < ng; g++) {
-                double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-                for (int64_t p = goff[g]; p < goff[g + 1]; p++)
-                    for (int k = 0; k < 3; k++) {
-                        lo[k] = std::min(lo[k], t->pos[3 * p + k]);
-                        hi[k] = std::max(hi[k], t->pos[3 * p + k]);
-                    }
-                for (int k = 0; k < 3; k++) {
-                    L->group_box[6 * g + k] = (float)lo[k];
-                    L->group_box[6 * g + 3 + k] = (float)hi[k];
-                }
-                const size_t start = B.size();
-                parts.clear();
-                int64_t u = n;  // root cell
-                while (u >= 0) {
-                    if (u < n) {
-                        parts.push_back((int32_t)u);
-                        u = t->next[u];
-                        continue;
-                    }
-                    const int64_t c = u - n;
-                    const double* cm = &t->com[3 * c];
-                    double d2 = 0;
-                    for (int k = 0; k < 3; k++) {
-                        const double dk = std::max(0.0, std::max(lo[k] - cm[k], cm[k] - hi[k]));
-                        d2 += dk * dk;
-                    }
-                    if (std::sqrt(d2) > rc[c]) {
-                        B.push_back((int32_t)u);
-                        u = t->next[u];
-                    } else {
-                        u = t->more[u];
-                    }
-                }
-                g_thread[g] = tid;
-                g_start[g] = (int64_t)start;
-                g_ncell[g] = (int64_t)(B.size() - start);
-                B.insert(B.end(), parts.begin(), parts.end());
-                g_len[g] = (int64_t)(B.size() - start);
-            }
-        }
-        L->group_off.resize(ng + 1);
-        L->list_off.resize(ng + 1);
-        L->n_cellent.resize(ng);
-        int64_t tot = 0, inter = 0;
-        for (int64_t g = 0; g < ng; g++) {
-            L->group_off[g] = (int32_t)goff[g];
-            L->list_off[g] = tot;
-            L->n_cellent[g] = (int32_t)g_ncell[g];
-            tot += g_len[g];
-            inter += (goff[g + 1] - goff[g]) * g_len[g];
-        }
-        L->group_off[ng] = (int32_t)n;
-        L->list_off[ng] = tot;
-        L->list_idx.resize(tot);
+        walk_groups(t, goff, [&](int64_t c, double dmin, int64_t) { return dmin > rc[c] ? kAccept : kOpen; }, L);
+    } catch (const std::bad_alloc&) {
+        delete L;
+        return OTOO_ENOMEM;
+    }
+    *out = &L->pub;
+    return OTOO_OK;
+}
+
+int otoo_tree_walk_sph(const otoo_tree* t, const double* h, int32_t group_mode, int32_t g_max, otoo_lists** out) {
+    if (!t || !h || !out) return OTOO_EINVAL;
+    if (g_max < 1 || g_max > OTOO_MAX_GROUP) return OTOO_EINVAL;
+    if (group_mode != OTOO_GROUP_CHUNK && group_mode != OTOO_GROUP_CELL) return OTOO_EINVAL;
+    const int64_t n = t->n, nc = t->n_cells();
+    for (int64_t i = 0; i < n; i++)
+        if (!(h[i] > 0.0) || !std::isfinite(h[i])) return OTOO_EINVAL;
+    otoo_lists_impl* L = new (std::nothrow) otoo_lists_impl();
+    if (!L) return OTOO_ENOMEM;
+    try {
+        std::vector<double> hk(n);
+        for (int64_t p = 0; p < n; p++) hk[p] = h[t->perm[p]];
+        // per cell: extent R_c = max |COM_c - x_j| and the SPH bounding radius
+        // r_SPH = max (|COM_c - x_j| + h_j) of Eq. 5, over the cell's particles
+        std::vector<double> R(nc), rs(nc);
 #pragma omp parallel for schedule(dynamic, 64)
-        for (int64_t g = 0; g < ng; g++)
-            std::memcpy(&L->list_idx[L->list_off[g]], &buf[g_thread[g]][g_start[g]], sizeof(int32_t) * g_len[g]);
-        L->pub.n_groups = (int32_t)ng;
-        L->pub.n_entries = tot;
-        L->pub.interactions = inter;
-        L->pub.group_off = L->group_off.data();
-        L->pub.list_off = L->list_off.data();
-        L->pub.list_idx = L->list_idx.data();
-        L->pub.n_cellent = L->n_cellent.data();
-        L->pub.group_box = L->group_box.data();
-        L->pub.impl = L;
+        for (int64_t c = 0; c < nc; c++) {
+            const double* cm = &t->com[3 * c];
+            double r_max = 0.0, rs_max = 0.0;
+            for (int64_t p = t->first[c]; p < t->first[c] + t->count[c]; p++) {
+                double d2 = 0.0;
+                for (int k = 0; k < 3; k++) {
+                    const double dk = t->pos[3 * p + k] - cm[k];
+                    d2 += dk * dk;
+                }
+                const double d = std::sqrt(d2);
+                r_max = std::max(r_max, d);
+                rs_max = std::max(rs_max, d + hk[p]);
+            }
+            R[c] = r_max;
+            rs[c] = rs_max;
+        }
+        const std::vector<int64_t> goff = make_groups(t, group_mode, g_max);
+        const int64_t ng = (int64_t)goff.size() - 1;
+        std::vector<double> hg(ng);
+        for (int64_t g = 0; g < ng; g++) {
+            double m = 0.0;
+            for (int64_t p = goff[g]; p < goff[g + 1]; p++) m = std::max(m, hk[p]);
+            hg[g] = m;
+        }
+        // a cell can hold a neighbour of a group particle only if the group's
+        // box comes within r_SPH of its COM (the source's support) or within
+        // R_c + max_g h (the target's support); otherwise it is skipped whole
+        walk_groups(t, goff, [&](int64_t c, double dmin, int64_t g) {
+            return dmin >= std::max(rs[c], R[c] + hg[g]) ? kSkip : kOpen;
+        }, L);
     } catch (const std::bad_alloc&) {
         delete L;
         return OTOO_ENOMEM;

@@ -80,9 +80,13 @@ class Network:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None:
+        if h is None:
+            return
+        self._h = None
+        try:
             _bind().otoo_mlp_destroy(h)   # safe after the context is gone
-            self._h = None
+        except Exception:                 # interpreter shutdown: module globals already cleared
+            pass
 
     def _raise(self, rc, what):
         self.ctx._raise(rc, what)

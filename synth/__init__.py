@@ -193,6 +193,14 @@ def grf_cube(ng: int, seed: int, rms: float = 0.3, slope: float = -2.0,
     return pos, np.full(n, mass / n)
 
 
+def knn_radius(pos: np.ndarray, k: int = 32) -> np.ndarray:
+    """Distance from each point to its k-th nearest other point: the
+    neighbour radius h of an SPH particle with about k neighbours."""
+    from scipy.spatial import cKDTree
+    d, _ = cKDTree(pos).query(pos, k=k + 1, workers=-1)
+    return d[:, -1].astype(np.float64)
+
+
 def sample_idx(n: int, k: int, seed: int) -> np.ndarray:
     """``k`` distinct indices of [0, n) drawn without replacement, ascending."""
     rng = rng_for(seed)
