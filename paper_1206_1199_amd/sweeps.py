@@ -12,6 +12,10 @@ paper's models are Delta^-3/4 for the cost and Delta^1/4 for the error.
 
     python -m paper_1206_1199_amd.sweeps delta [--dist uniform|plummer] [--n N] [--eps E]
     python -m paper_1206_1199_amd.sweeps theta [--dist ...]
+    python -m paper_1206_1199_amd.sweeps sph [--dist polytrope|uniform|plummer] [--n N] [--k K]
+
+The sph sweep times the SPH neighbour walk and the gather sums (density,
+q = m) with neighbour radii from the K-th nearest neighbour, for each g_max.
 
 One JSON object per setting on stdout; a summary object last.
 """
@@ -117,10 +121,55 @@ def run(kind: str, dist: str, n: int, eps: float, g_list, values, m_limit: float
     return rows, summary
 
 
+def run_sph(dist: str, n: int, g_list, k: int, reps: int, seed: int, emit=print):
+    import torch
+    import synth
+    if dist == "polytrope":
+        pos, m, _, _ = synth.polytrope_pair(n // 2, seed=seed)
+    elif dist == "uniform":
+        pos, m = synth.uniform_sphere(n, seed=seed)
+    else:
+        pos, m = synth.plummer(n, seed=seed)
+    h = synth.knn_radius(pos, k)
+    tree = Tree(pos, m, n_crit=16)
+    perm, pos32, mass32, cm = tree.export(4)
+    ctx = Context(0)
+    dev = "cuda:0"
+    h_t = torch.from_numpy(h[perm].astype(np.float32)).to(dev)
+    q_t = torch.from_numpy(mass32).to(dev)
+    rows = []
+    for g_max in g_list:
+        t0 = time.perf_counter()
+        lists = tree.walk_sph(h, g_max=g_max)
+        t_walk = time.perf_counter() - t0
+        d = DeviceLists.from_host(pos32, mass32, lists, cm, dev)
+        out = ctx.sph_sum(d, h_t, q_t)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            ctx.sph_sum(d, h_t, q_t, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ctx.check()
+        ms = e0.elapsed_time(e1) / reps
+        row = {"sph": dist, "n": len(m), "k": k, "g_max": g_max, "walk_s": t_walk, "sum_ms": ms,
+               "pairs": lists.interactions, "list_entries": lists.n_entries,
+               "gpairs_per_s": lists.interactions / (ms * 1e-3) / 1e9}
+        rows.append(row)
+        emit(json.dumps(row))
+        sys.stdout.flush()
+        del d
+        torch.cuda.empty_cache()
+    return rows
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("kind", choices=["delta", "theta"])
-    ap.add_argument("--dist", choices=["uniform", "plummer"], default="uniform")
+    ap.add_argument("kind", choices=["delta", "theta", "sph"])
+    ap.add_argument("--dist", choices=["uniform", "plummer", "polytrope"], default="uniform")
+    ap.add_argument("--k", type=int, default=50, help="sph: neighbours inside h")
     ap.add_argument("--n", type=int, default=8000 * 1024)
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--g-max", default="32,64")
@@ -129,6 +178,9 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--seed", type=int, default=5)
     a = ap.parse_args(argv)
+    if a.kind == "sph":
+        run_sph(a.dist, a.n, [int(g) for g in a.g_max.split(",")], a.k, a.reps, a.seed)
+        return
     values = [float(x) for x in a.values.split(",")] if a.values else (DELTAS if a.kind == "delta" else THETAS)
     run(a.kind, a.dist, a.n, a.eps, [int(g) for g in a.g_max.split(",")], values, a.m_limit, a.reps, a.seed)
 
