@@ -10,8 +10,13 @@ added to the cell's monopole.
 Network:   u (12 features, zero-padded to 32)
            h1 = gelu(u W1 + b1)        W1 [32, 64]
            h2 = gelu(h1 W2 + b2)       W2 [64, 64]
-           o  = h2 W3 + b3             W3 [64, 6]
+           o  = h2 W3 + b3 + 3 s       W3 [64, 6]; s = u[6:12], the normalised S
            Qt = M_c l_c^2 * P(o)       P removes the trace: o_aa -= tr(o)/3
+The fixed skip term 3 s makes M_c l_c^2 P(3 s) = 3 S - tr(S) I, the textbook
+quadrupole: the layers learn the correction to it, and zero weights give
+the quadrupole exactly.  With a gate tau > 0 the layers run only for pairs
+whose feature l_c/n is at least tau; other pairs keep o = 3 s.  Both the
+skip and the gate read the BF16-rounded features the network sees.
 gelu is the tanh form of Hendrycks & Gimpel (2016):
            gelu(z) = z/2 (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3))).
 
@@ -91,14 +96,27 @@ def features(d, l_c, eps, h_g, S_c, M_c):
     return u
 
 
+def skip(u):
+    """The fixed skip term 3 s of the outputs (s = the normalised second moments)."""
+    return 3.0 * np.asarray(u, dtype=np.float64)[:, N_FEAT - N_OUT:N_FEAT]
+
+
 def forward(p, u):
     """Returns (o [P,6], cache)."""
     z1 = u @ p["W1"] + p["b1"]
     h1 = gelu(z1)
     z2 = h1 @ p["W2"] + p["b2"]
     h2 = gelu(z2)
-    o = h2 @ p["W3"] + p["b3"]
+    o = h2 @ p["W3"] + p["b3"] + skip(u)
     return o, (u, z1, h1, z2, h2)
+
+
+def gated_outputs(p, u, gate):
+    """Outputs with the gate applied: the layers' part only where u[:, 3] >= gate."""
+    o, _ = forward(p, u)
+    off = np.asarray(u)[:, 3] < gate
+    o[off] = skip(u[off])
+    return o
 
 
 def traceless(o):

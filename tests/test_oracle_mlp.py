@@ -196,3 +196,27 @@ def test_basis_backward_matches_finite_differences():
             q[k].reshape(-1)[j] -= 2 * h
             lm = lossf(q)
             assert g[k].reshape(-1)[j] == pytest.approx((lp - lm) / (2 * h), rel=1e-6, abs=1e-10 * abs(L) + 1e-14)
+
+
+def test_zero_layers_give_the_textbook_quadrupole():
+    """With every weight and bias zero the outputs are the skip term alone, and
+    M l^2 P(o) is the textbook quadrupole 3 S - tr(S) I of the cell (closed
+    form), independent of the other features; a gate above every l/n does the
+    same for any weights."""
+    rng = np.random.default_rng(5)
+    P = 30
+    S = rng.normal(size=(P, 6))
+    S[:, :3] = np.abs(S[:, :3]) + 1.0
+    M = rng.uniform(0.5, 2.0, P)
+    l = rng.uniform(0.1, 1.0, P)
+    u = omlp.features(rng.normal(size=(P, 3)) * 5, l, 0.01, rng.uniform(0, 1, P), S, M)
+    zero = {k: np.zeros_like(v) for k, v in omlp.init_params(0).items()}
+    o, _ = omlp.forward(zero, u)
+    q = omlp.traceless(o) * (M * l * l)[:, None]
+    np.testing.assert_allclose(q, omlp.exact_quadrupole(S), rtol=1e-12, atol=1e-12)
+    p = omlp.init_params(3)
+    og = omlp.gated_outputs(p, u, gate=np.inf)
+    np.testing.assert_allclose(omlp.traceless(og) * (M * l * l)[:, None], omlp.exact_quadrupole(S), rtol=1e-12,
+                               atol=1e-12)
+    # gate 0 leaves every pair to the layers
+    np.testing.assert_array_equal(omlp.gated_outputs(p, u, gate=0.0), omlp.forward(p, u)[0])
