@@ -45,6 +45,12 @@ WORKLOADS = {
                 "GRF cube 256^3 P(k)~k^-2 rms 0.3 seed=4 eps=1e-3 theta=0.7"),
 }
 SAMPLE_SEED = {"plummer16k": 100, "plummer1m": 101, "polytrope2m": 102, "cube16m": 104}
+# group sizes the workload allows the autotuner (the 2^20 Plummer sphere is
+# quoted with groups of 64-256 particles, the 16k sphere with groups <= 64)
+GROUPS = {
+    "plummer16k": [(0, 64), (1, 64)],
+    "plummer1m": [(0, 64), (0, 128), (0, 256), (1, 64), (1, 128), (1, 256)],
+}
 
 
 def measured_traffic(desc, sched):
@@ -120,11 +126,12 @@ def rel_err(a, ref):
 # ------------------------------------------------------------------ learned comparison
 
 
-def learned_comparison(ctx, log, steps, train_steps, timing_reps):
+def learned_comparison(ctx, log, steps, train_steps, timing_reps, gate=0.4):
     """Train the correction network on the GPU and compare, on a held-out
     Plummer sphere (N = 2^20, seed 3, eps 0.005), plain theta = 0.5, plain at
     the largest theta with median error <= 1e-3, the textbook quadrupole and
-    the learned correction, all timed per force evaluation."""
+    the learned correction (layers gated to pairs with l/n >= gate), all
+    timed per force evaluation with the best of a few schedules per setting."""
     import torch
     import synth
     import paper_1206_1199_amd as otoo
@@ -132,25 +139,30 @@ def learned_comparison(ctx, log, steps, train_steps, timing_reps):
     eps = 0.005
     net = learned.Network(ctx)
     net.set_params(learned.init_params(0))
+    net.set_gate(gate)
+    keep = 3 if gate > 0 else 1          # draws per kept sample: the gate passes about a third of the pairs
     rng = np.random.Generator(np.random.PCG64(12345))
-    cfgs = [learned.SampleConfig("plummer", 16384, 1000 + k, 0.01, float(rng.uniform(0.5, 0.9)), 64, 40000)
+    cfgs = [learned.SampleConfig("plummer", 16384, 1000 + k, 0.01, float(rng.uniform(0.5, 1.0)), 64, 40000 * keep)
             for k in range(20)]
-    cfgs += [learned.SampleConfig("plummer", 1 << 20, 1020 + k, eps, float(rng.uniform(0.5, 0.9)), 64, 240000)
-             for k in range(5)]
+    cfgs += [learned.SampleConfig("plummer", 1 << 20, 1020 + k, eps, float(rng.uniform(0.5, 1.0)),
+                                  int(rng.choice([32, 64, 128])), 240000 * keep) for k in range(5)]
     t0 = time.perf_counter()
-    X, aux, eps_all = learned.make_training_set(ctx, net, cfgs, seed=1)
+    X, aux, eps_all = learned.make_training_set(ctx, net, cfgs, seed=1, gate=gate)
     Xv, auxv, epsv = learned.make_training_set(
-        ctx, net, [learned.SampleConfig("plummer", 1 << 20, 1100, eps, 0.8, 64, 100000)], seed=2)
+        ctx, net, [learned.SampleConfig("plummer", 1 << 20, 1100, eps, 0.9, 64, 100000 * keep)], seed=2, gate=gate)
     t_data = time.perf_counter() - t0
     base_val = learned.zero_correction_loss(auxv)
+    net.set_params(np.zeros(learned.N_PARAMS, np.float32))
+    quad_val = learned.evaluate_loss(net, Xv, auxv, epsv)
+    net.set_params(learned.init_params(0))
     t0 = time.perf_counter()
     hist = learned.fit(net, X, aux, eps_all, steps=train_steps, batch=32768, lr=2e-3, seed=0, X_val=Xv,
                        aux_val=auxv, eps_val=epsv, log=log, log_every=max(1, train_steps // 5))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     val = learned.evaluate_loss(net, Xv, auxv, epsv)
-    log(f"learned: {X.shape[0]} samples in {t_data:.1f} s, {train_steps} steps in {t_train:.1f} s, "
-        f"validation loss {val:.3e} (plain monopole {base_val:.3e})")
+    log(f"learned: {X.shape[0]} samples (gate {gate}) in {t_data:.1f} s, {train_steps} steps in {t_train:.1f} s, "
+        f"validation loss {val:.3e} (plain monopole {base_val:.3e}, textbook quadrupole {quad_val:.3e})")
 
     pos, m = synth.plummer(1 << 20, seed=3)
     tree = otoo.Tree(pos, m, n_crit=16)
@@ -158,17 +170,36 @@ def learned_comparison(ctx, log, steps, train_steps, timing_reps):
     sample = synth.sample_idx(len(m), 4096, seed=103)
     a_dir, _ = direct_reference(ctx, otoo.DeviceLists.from_host(pos32, mass32, tree.walk(theta=0.5), cm, "cuda:0"),
                                 sample, eps)
+    schedules = [dict(chunk=1 << 24, blocks_per_cu=8, lpt=0, tile=512), dict(chunk=2048, blocks_per_cu=8, lpt=1, tile=256),
+                 dict(chunk=4096, blocks_per_cu=8, lpt=1, tile=512)]
+
+    def timed(step):
+        for _ in range(3):
+            step()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(timing_reps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        ctx.check()
+        return e0.elapsed_time(e1) / timing_reps
 
     def run(theta, modes, g_max):
-        # schedules from the autotuner's sweep: whole lists for small groups, split lists for large ones
-        if g_max <= 32:
-            ctx.set_tuning(chunk=1 << 24, blocks_per_cu=8, lpt=0, tile=512)
-        else:
-            ctx.set_tuning(chunk=2048, blocks_per_cu=8, lpt=1, tile=256)
         lists = tree.walk(theta=theta, g_max=g_max)
         d, _, _ = learned.device_tree_arrays(tree, lists)
         out = ctx.outputs(d.n)
         gc = torch.empty((d.n_groups, otoo.CORR_STRIDE), dtype=torch.float32, device="cuda:0")
+        # the force schedule: the fastest candidate for this list set, shared by every mode
+        best_s, best_ms = None, None
+        for sc in schedules:
+            ctx.set_tuning(**sc)
+            ms = timed(lambda: ctx.force(d, eps, out=out))
+            if best_ms is None or ms < best_ms:
+                best_s, best_ms = sc, ms
+        ctx.set_tuning(**best_s)
         rows = []
         for mode in modes:
             def step():
@@ -180,22 +211,11 @@ def learned_comparison(ctx, log, steps, train_steps, timing_reps):
                     ctx.force(d, eps, out=out, gcorr=gc)
                 else:
                     ctx.force(d, eps, out=out)
-            for _ in range(3):
-                step()
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(timing_reps):
-                step()
-            e1.record()
-            torch.cuda.synchronize()
-            ctx.check()
-            ms = e0.elapsed_time(e1) / timing_reps
+            ms = timed(step)
             err = rel_err(out[0].cpu().numpy()[sample], a_dir)
             rows.append(dict(mode=mode, theta=theta, g_max=g_max, ms=ms, interactions=lists.interactions,
                              pairs=d.n_pairs, median_err=float(np.median(err)),
-                             p99_err=float(np.quantile(err, 0.99))))
+                             p99_err=float(np.quantile(err, 0.99)), schedule=best_s))
         return rows
 
     rows = []
@@ -211,10 +231,11 @@ def learned_comparison(ctx, log, steps, train_steps, timing_reps):
             f"median err {r['median_err']:.2e}, pairs {r['pairs']}")
     ok = lambda mode: [r for r in rows if r["mode"] == mode and r["median_err"] <= 1e-3]
     best = {mode: (min(ok(mode), key=lambda r: r["ms"]) if ok(mode) else None) for mode in ("plain", "quad", "learned")}
-    plain05 = rows[0]   # plain, theta = 0.5
+    plain05 = min((r for r in rows if r["mode"] == "plain" and r["theta"] == 0.5), key=lambda r: r["ms"])
     res = {"workload": "Plummer N=1048576 seed=3 eps=0.005 (held out), error vs direct sum on 4096 particles",
+           "gate": gate,
            "training": {"samples": int(X.shape[0]), "steps": train_steps, "data_s": t_data, "train_s": t_train,
-                        "val_loss": val, "val_loss_plain_monopole": base_val},
+                        "val_loss": val, "val_loss_plain_monopole": base_val, "val_loss_textbook_quadrupole": quad_val},
            "plain_theta_0.5": plain05, "best_at_1e-3": best, "rows": rows}
     if best["learned"]:
         res["learned_speedup_vs_plain_theta_0.5"] = plain05["ms"] / best["learned"]["ms"]
@@ -242,7 +263,8 @@ def main():
     ap.add_argument("--cache", default="", help="autotune cache file (default: the package's)")
     ap.add_argument("--learned", action="store_true", help="add the learned-correction comparison (default on)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction comparison")
-    ap.add_argument("--train-steps", type=int, default=1500)
+    ap.add_argument("--gate", type=float, default=0.4, help="learned correction: layers only where l/n >= gate")
+    ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, one device-to-device copy of this many MiB (a known-size kernel for "
@@ -273,7 +295,10 @@ def main():
     key = f"{at.device_key(0)}:{args.workload}"
     cache_path = args.cache or at.DEFAULT_CACHE
     if args.autotune:
-        best, table = at.autotune(tree, eps, theta, ctx, log=log)
+        grid = dict(at.GRID)
+        if args.workload in GROUPS:
+            grid["group"] = GROUPS[args.workload]
+        best, table = at.autotune(tree, eps, theta, ctx, grid=grid, log=log)
         at.save_cache(key, best, cache_path)
         sched = {k: best[k] for k in at.DEFAULT_SCHEDULE}
         source = "autotuned now"
@@ -377,7 +402,8 @@ def main():
     log(f"accuracy {res['accuracy']}")
     if not args.no_learned:
         try:
-            res["learned"] = learned_comparison(ctx, log, args.steps, args.train_steps, max(5, min(args.steps, 20)))
+            res["learned"] = learned_comparison(ctx, log, args.steps, args.train_steps, max(5, min(args.steps, 20)),
+                                                gate=args.gate)
         except Exception as e:  # the headline measurement stands on its own
             res["learned"] = {"error": f"{type(e).__name__}: {e}"}
             log(f"learned comparison failed: {e}")

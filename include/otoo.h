@@ -261,15 +261,20 @@ int otoo_quad_exact(otoo_ctx* ctx, int32_t n, int32_t n_groups, int64_t n_entrie
 /* ======================================================================
  * Learned cell correction (not in the paper, which evaluates accepted cells
  * as monopoles, Sec. 2): for every (group g, accepted cell c) pair a network
- * 12 features (zero-padded to 32) -> 64 -> GELU -> 64 -> GELU -> 6 predicts a
- * symmetric traceless tensor Qt = M_c l_c^2 P(o) (P removes the trace) that
- * otoo_force applies through its local expansion.  Features, with
+ * 12 features (zero-padded to 32) -> 64 -> GELU -> 64 -> GELU -> 6, plus the
+ * fixed skip term 3 s (s the normalised second moments, features 6..11),
+ * gives o and the symmetric traceless tensor Qt = M_c l_c^2 P(o) (P removes
+ * the trace) that otoo_force applies through its local expansion.  With zero
+ * layers Qt is the textbook quadrupole 3 S_c - tr(S_c) I; the layers learn
+ * the correction to it.  Features, with
  * d = COM_c - c_g (c_g the centre of the group's bounding box) and n = |d|:
  *     d/n (3), l_c/n, eps/n, h_g/n (h_g the box half-diagonal),
  *     S_c / (M_c l_c^2) as (xx, yy, zz, xy, xz, yz).
  * A pair whose features are non-finite or exceed 8 in magnitude gets a zero
- * tensor (plain monopole).  GELU is the tanh form.  BF16 operands on MFMA,
- * FP32 accumulation, FP32 master weights with Adam.
+ * tensor (plain monopole).  A gate (otoo_mlp_set_gate) limits the layers to
+ * pairs whose BF16 feature l_c/n is at least the gate; the others keep the
+ * skip term alone (the textbook quadrupole).  GELU is the tanh form.  BF16
+ * operands on MFMA, FP32 accumulation, FP32 master weights with Adam.
  * ====================================================================== */
 
 /* Number of FP32 parameters (6662): W1 [32][64], b1 [64], W2 [64][64],
@@ -283,6 +288,11 @@ int otoo_mlp_create(otoo_ctx* ctx, otoo_mlp** mlp);
 int otoo_mlp_destroy(otoo_mlp* mlp);
 /* Host parameter vector in, optimiser state reset (EINVAL on non-finite values). */
 int otoo_mlp_set_params(otoo_mlp* mlp, const float* params);
+/* Gate of the layers for otoo_mlp_infer and otoo_correction: the layers run
+ * only for pairs whose BF16 feature l_c/n is >= gate (0, the default, runs
+ * them for every pair; +INFINITY for none).  A setting of the network object,
+ * not part of its checkpoint.  EINVAL for a negative or NaN gate. */
+int otoo_mlp_set_gate(otoo_mlp* mlp, float gate);
 /* Host copies of parameters, Adam moments and the step count (NULL skips). */
 int otoo_mlp_get_params(otoo_mlp* mlp, float* params, float* adam_m, float* adam_v, int64_t* step);
 /* Checkpoint: "OTOOMLP1", int32 parameter count, int64 step, then FP32
@@ -290,8 +300,9 @@ int otoo_mlp_get_params(otoo_mlp* mlp, float* params, float* adam_m, float* adam
 int otoo_mlp_save(otoo_mlp* mlp, const char* path);
 int otoo_mlp_load(otoo_mlp* mlp, const char* path);
 
-/* Raw network outputs o [rows][6] (before projection and scaling) for BF16
- * features X [rows][32] (device pointers; for parity checks). */
+/* Network outputs o [rows][6], skip term included and no gate (before
+ * projection and scaling), for BF16 features X [rows][32] (device pointers;
+ * for parity checks). */
 int otoo_mlp_forward(otoo_mlp* mlp, const uint16_t* X, int64_t rows, float* out);
 
 /* Tensors of every (group, cell) pair for otoo_force: corr [n_pairs][6].

@@ -101,7 +101,7 @@ def save_cache(entry_key: str, best: dict, path: str = DEFAULT_CACHE):
     os.replace(tmp, path)
 
 
-DEFAULT_SCHEDULE = dict(group_mode="chunk", g_max=32, chunk=1 << 24, blocks_per_cu=8, lpt=0, tile=256)
+DEFAULT_SCHEDULE = dict(group_mode="chunk", g_max=64, chunk=2048, blocks_per_cu=8, lpt=1, tile=256)
 
 
 def cached_schedule(workload: str, device: int = 0, path: str = DEFAULT_CACHE):

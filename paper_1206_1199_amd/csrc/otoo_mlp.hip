@@ -55,6 +55,18 @@ __device__ __forceinline__ uint16_t f2bf(float f) {  // v_cvt_pk_bf16_f32: round
     return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 
+__device__ __forceinline__ float bf2f(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
+__device__ __forceinline__ float bf_round(float f) { return bf2f(f2bf(f)); }
+
+// The network's fixed skip term: output m (< NOUT) gets 3 s_m, where s is
+// the BF16 normalised second-moment tensor (features kSkip0 ..), so that
+// M l^2 P(3 s) = 3 S - tr(S) I, the textbook quadrupole; the layers add the
+// learned correction to it.
+constexpr int kSkip0 = NFEAT - NOUT;
+__device__ __forceinline__ float skip_term(const uint16_t* xrow, int m) {
+    return m < NOUT ? 3.f * bf2f(xrow[kSkip0 + m]) : 0.f;
+}
+
 __device__ __forceinline__ bf16x8 ld8(const uint16_t* p) {  // 8 contiguous BF16, 16-byte aligned
     return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
 }
@@ -231,6 +243,7 @@ struct InferArgs {
     const float4* geom;
     const uint16_t* wbf;
     const float* master;
+    float gate;               // the layers run only where the BF16 feature l/n >= gate
     float* corr;
     int32_t* err;
 };
@@ -298,7 +311,11 @@ __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs a) {
         floatx4 o[1];
         wave_dense<2, 1>(sH, NH, net.w3t, NH, net.b3, r0, o);
 #pragma unroll
-        for (int i = 0; i < 4; i++) sO[(r0 + q * 4 + i) * NOUTP + r16] = o[0][i];
+        for (int i = 0; i < 4; i++) {
+            const uint16_t* xr = sX + (r0 + q * 4 + i) * NIN;
+            const bool on = bf2f(xr[3]) >= a.gate;
+            sO[(r0 + q * 4 + i) * NOUTP + r16] = (on ? o[0][i] : 0.f) + skip_term(xr, r16);
+        }
         __syncthreads();
         if (t < 64) {
             const int64_t p = base + t;
@@ -351,7 +368,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward_raw(const uint16_t* __restr
         if (r16 < NOUT)
             for (int i = 0; i < 4; i++) {
                 const int64_t r = base + r0 + q * 4 + i;
-                if (r < rows) out[r * NOUT + r16] = o[0][i];
+                if (r < rows) out[r * NOUT + r16] = o[0][i] + skip_term(sX + (r0 + q * 4 + i) * NIN, r16);
             }
         __syncthreads();
     }
@@ -378,6 +395,7 @@ struct CorrArgs {
     const float* corr;        // kCorrPairs: given tensors [n_pairs][6]
     const uint16_t* wbf;      // kCorrMlp: network
     const float* master;
+    float gate;               // kCorrMlp: the layers run only where the BF16 feature l/n >= gate
     float* gcorr;             // [n_groups][kCorrStride]
     int32_t* err;
 };
@@ -410,6 +428,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     __shared__ CorrScratch scr;
     __shared__ float sScale[kCorrRows];
     __shared__ int sCell[kCorrRows];
+    __shared__ float sSkip[NET ? kCorrRows * NOUT : 1];   // skip term of each row; the layers' part is
+    __shared__ int sOn[NET ? kCorrRows : 1];              // kept only for rows the gate lets through
     uint16_t* sX = scr.net.x;
     uint16_t* sH = scr.net.h;
     float* sO = scr.o;
@@ -501,6 +521,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                     }
 #pragma unroll
                     for (int j = 0; j < NFEAT; j++) sX[t * NIN + j] = f2bf(fok ? fe[j] : 0.f);
+#pragma unroll
+                    for (int m = 0; m < NOUT; m++) sSkip[t * NOUT + m] = fok ? 3.f * bf_round(fe[kSkip0 + m]) : 0.f;
+                    sOn[t] = fok && bf_round(fe[3]) >= a.gate;
                     sScale[t] = fok ? sc : 0.f;
                     sCell[t] = (int)c;
                 }
@@ -543,7 +566,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 {   // two threads per row share the expansion: {a, phi, J} and H
                     const int row = t >> 1, part = t & 1;
                     if (base + row < nce && sCell[row] >= 0 && sScale[row] > 0.f) {
-                        const float* ov = sO + row * NOUTP;
+                        const float* on = sO + row * NOUTP;
+                        const bool lay = sOn[row] != 0;
+                        float ov[NOUT];
+#pragma unroll
+                        for (int m = 0; m < NOUT; m++) ov[m] = (lay ? on[m] : 0.f) + sSkip[row * NOUT + m];
                         const float tr = (ov[0] + ov[1] + ov[2]) * (1.f / 3.f);
                         const float sc = sScale[row];
                         const float Q[6] = {(ov[0] - tr) * sc, (ov[1] - tr) * sc, (ov[2] - tr) * sc,
@@ -600,9 +627,27 @@ __device__ __forceinline__ bf16x8 ld_perm(const uint16_t* W, int ld, int row, in
     return __builtin_bit_cast(bf16x8, v);
 }
 
+// Traceless tensor of a pair from its outputs o (skip term included), times
+// the pair's scale M l^2, added to the group's expansion at offset d.
+__device__ __forceinline__ void expand_outputs(const float o[NOUT], float sc, float dx, float dy, float dz,
+                                               float eps2, float* f) {
+    const float tr = (o[0] + o[1] + o[2]) * (1.f / 3.f);
+    const float Q[6] = {(o[0] - tr) * sc, (o[1] - tr) * sc, (o[2] - tr) * sc, o[3] * sc, o[4] * sc, o[5] * sc};
+    quad_expand_add(dx, dy, dz, Q, eps2, f);
+}
+
+constexpr int kNetBuf = 512;   // gated pairs waiting for the network (two rounds of 4 waves x 64)
+
+// Per group: every cell entry's features in a window of 256 (one per
+// thread); a pair the gate keeps out gets the skip term alone (the textbook
+// quadrupole) at once, a gated pair is appended to an LDS queue in a fixed
+// order (wave ballots, waves in order).  Whenever 256 are queued (or the
+// list is done) each wave runs the network on 64 of them.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_corr_net(CorrArgs a) {
     __shared__ float sb[NH + NH + NOUTP];
     __shared__ float red[kCorrTerms][256];
+    __shared__ int32_t sPend[kNetBuf];
+    __shared__ int sWave[4];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, r16 = lane & 15, q = lane >> 4;
     const float eps2 = a.eps * a.eps;
     for (int i = t; i < NH; i += 256) {
@@ -655,75 +700,119 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             p0 = clamp64(a.pair_off[g], 0, a.n_pairs);
             const int64_t p1 = clamp64(a.pair_off[g + 1], p0, a.n_pairs);
             nce = (p1 - p0) < (le - lb) ? (p1 - p0) : (le - lb);
+            if (nce > INT32_MAX) {   // queue slots hold 32-bit list positions
+                nce = INT32_MAX;
+                if (t == 0) atomicOr(a.err, kErrCapacity);
+            }
         } else if (t == 0) {
             atomicOr(a.err, kErrGroup);
         }
-        for (int64_t base = 64 * (int64_t)w; base < nce; base += 256) {
-            // features of this lane's pair
-            const int64_t k = base + lane;
-            float fe[NFEAT];
-            float sc = 0.f, mx = 0.f, my = 0.f, mz = 0.f;
-            bool fok = false;
-            if (k < nce) {
-                const int64_t c = (int64_t)a.list_idx[lb + k] - a.n;
-                if (c >= 0 && c < a.n_cells) {
+        int64_t base = 0;
+        int pend = 0;
+        while (true) {
+            // fill the queue, a window of 256 entries at a time
+            while (base < nce && pend < 256) {
+                const int64_t k = base + t;
+                bool gated = false;
+                if (k < nce) {
+                    const int64_t c = (int64_t)a.list_idx[lb + k] - a.n;
+                    if (c >= 0 && c < a.n_cells) {
+                        const float* cm = a.cell_mom + 12 * c;
+                        float fe[NFEAT], sc;
+                        if (pair_features(cx, cy, cz, h, cm, a.eps, fe, sc)) {
+                            if (bf_round(fe[3]) >= a.gate) {
+                                gated = true;
+                            } else {
+                                float o[NOUT];
+#pragma unroll
+                                for (int m = 0; m < NOUT; m++) o[m] = 3.f * bf_round(fe[kSkip0 + m]);
+                                expand_outputs(o, sc, cx - cm[0], cy - cm[1], cz - cm[2], eps2, f);
+                            }
+                        }
+                    } else {
+                        atomicOr(a.err, kErrIndex);
+                    }
+                }
+                const uint64_t mask = __ballot(gated);
+                if (lane == 0) sWave[w] = __popcll(mask);
+                __syncthreads();
+                int off = pend;
+                for (int v = 0; v < w; v++) off += sWave[v];
+                if (gated) sPend[off + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)k;
+                pend += sWave[0] + sWave[1] + sWave[2] + sWave[3];
+                base += 256;
+                __syncthreads();
+            }
+            if (pend == 0) break;
+            const int take = pend < 256 ? pend : 256;
+            if (64 * w < take) {   // uniform within the wave
+                const int slot = 64 * w + lane;
+                const bool has = slot < take;
+                float fe[NFEAT], sc = 0.f, mx = 0.f, my = 0.f, mz = 0.f;
+#pragma unroll
+                for (int j = 0; j < NFEAT; j++) fe[j] = 0.f;
+                if (has) {
+                    const int64_t c = (int64_t)a.list_idx[lb + sPend[slot]] - a.n;   // checked when queued
                     const float* cm = a.cell_mom + 12 * c;
-                    fok = pair_features(cx, cy, cz, h, cm, a.eps, fe, sc);
+                    pair_features(cx, cy, cz, h, cm, a.eps, fe, sc);
                     mx = cm[0];
                     my = cm[1];
                     mz = cm[2];
-                } else {
-                    atomicOr(a.err, kErrIndex);
+                }
+                float ov[NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int tau = 0; tau < 4; tau++) {
+                    const int src = tau * 16 + r16;
+                    float v[NFEAT];
+#pragma unroll
+                    for (int j = 0; j < NFEAT; j++) v[j] = __shfl(fe[j], src);
+                    bf16x8 xb;
+#pragma unroll
+                    for (int j = 0; j < 8; j++) {
+                        const float x = q == 0 ? v[j] : (q == 1 && j < 4 ? v[8 + j] : 0.f);
+                        xb[j] = (__bf16)x;
+                    }
+                    floatx4 acc[4];
+#pragma unroll
+                    for (int mt = 0; mt < 4; mt++) {
+                        const float4 bb = *reinterpret_cast<const float4*>(sb + mt * 16 + q * 4);
+                        acc[mt] = mfma(w1a[mt], xb, floatx4{bb.x, bb.y, bb.z, bb.w});
+                    }
+                    const bf16x8 h0 = pack8(acc[0], acc[1]), h1 = pack8(acc[2], acc[3]);
+#pragma unroll
+                    for (int mt = 0; mt < 4; mt++) {
+                        const float4 bb = *reinterpret_cast<const float4*>(sb + NH + mt * 16 + q * 4);
+                        acc[mt] = mfma(w2a[mt][0], h0, floatx4{bb.x, bb.y, bb.z, bb.w});
+                        acc[mt] = mfma(w2a[mt][1], h1, acc[mt]);
+                    }
+                    const bf16x8 g0b = pack8(acc[0], acc[1]), g1b = pack8(acc[2], acc[3]);
+                    const float4 b3 = *reinterpret_cast<const float4*>(sb + 2 * NH + q * 4);
+                    floatx4 o = mfma(w3a[0], g0b, floatx4{b3.x, b3.y, b3.z, b3.w});
+                    o = mfma(w3a[1], g1b, o);
+                    // outputs 0..3 of pair (tau, r16) sit in lane r16, outputs 4, 5 in lane r16 + 16
+                    float sv[NOUT];
+#pragma unroll
+                    for (int i = 0; i < 4; i++) sv[i] = __shfl(o[i], r16);
+                    sv[4] = __shfl(o[0], r16 + 16);
+                    sv[5] = __shfl(o[1], r16 + 16);
+                    if (q == tau)
+#pragma unroll
+                        for (int i = 0; i < NOUT; i++) ov[i] = sv[i];
+                }
+                if (has && sc > 0.f) {
+#pragma unroll
+                    for (int m = 0; m < NOUT; m++) ov[m] += 3.f * bf_round(fe[kSkip0 + m]);
+                    expand_outputs(ov, sc, cx - mx, cy - my, cz - mz, eps2, f);
                 }
             }
-#pragma unroll
-            for (int j = 0; j < NFEAT; j++) fe[j] = fok ? fe[j] : 0.f;
-            float ov[NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int tau = 0; tau < 4; tau++) {
-                const int src = tau * 16 + r16;
-                float v[NFEAT];
-#pragma unroll
-                for (int j = 0; j < NFEAT; j++) v[j] = __shfl(fe[j], src);
-                bf16x8 xb;
-#pragma unroll
-                for (int j = 0; j < 8; j++) {
-                    const float x = q == 0 ? v[j] : (q == 1 && j < 4 ? v[8 + j] : 0.f);
-                    xb[j] = (__bf16)x;
-                }
-                floatx4 acc[4];
-#pragma unroll
-                for (int mt = 0; mt < 4; mt++) {
-                    const float4 b = *reinterpret_cast<const float4*>(sb + mt * 16 + q * 4);
-                    acc[mt] = mfma(w1a[mt], xb, floatx4{b.x, b.y, b.z, b.w});
-                }
-                const bf16x8 h0 = pack8(acc[0], acc[1]), h1 = pack8(acc[2], acc[3]);
-#pragma unroll
-                for (int mt = 0; mt < 4; mt++) {
-                    const float4 b = *reinterpret_cast<const float4*>(sb + NH + mt * 16 + q * 4);
-                    acc[mt] = mfma(w2a[mt][0], h0, floatx4{b.x, b.y, b.z, b.w});
-                    acc[mt] = mfma(w2a[mt][1], h1, acc[mt]);
-                }
-                const bf16x8 g0b = pack8(acc[0], acc[1]), g1b = pack8(acc[2], acc[3]);
-                const float4 b3 = *reinterpret_cast<const float4*>(sb + 2 * NH + q * 4);
-                floatx4 o = mfma(w3a[0], g0b, floatx4{b3.x, b3.y, b3.z, b3.w});
-                o = mfma(w3a[1], g1b, o);
-                // outputs 0..3 of pair (tau, r16) sit in lane r16, outputs 4, 5 in lane r16 + 16
-                float s[NOUT];
-#pragma unroll
-                for (int i = 0; i < 4; i++) s[i] = __shfl(o[i], r16);
-                s[4] = __shfl(o[0], r16 + 16);
-                s[5] = __shfl(o[1], r16 + 16);
-                if (q == tau)
-#pragma unroll
-                    for (int i = 0; i < NOUT; i++) ov[i] = s[i];
-            }
-            if (fok && sc > 0.f) {
-                const float tr = (ov[0] + ov[1] + ov[2]) * (1.f / 3.f);
-                const float Q[6] = {(ov[0] - tr) * sc, (ov[1] - tr) * sc, (ov[2] - tr) * sc,
-                                    ov[3] * sc,        ov[4] * sc,        ov[5] * sc};
-                quad_expand_add(cx - mx, cy - my, cz - mz, Q, eps2, f);
-            }
+            __syncthreads();   // every wave has read its queue slots
+            const int rest = pend - take;   // <= 256, moved from [256, pend) to the front
+            int32_t moved = 0;
+            if (t < rest) moved = sPend[take + t];
+            __syncthreads();
+            if (t < rest) sPend[t] = moved;
+            __syncthreads();
+            pend = rest;
         }
         __syncthreads();
 #pragma unroll
@@ -916,7 +1005,8 @@ __global__ __launch_bounds__(256) void k_mlp_train(TrainArgs a) {
         floatx4 o1[1];
         wave_dense<2, 1>(S.h2, NH, S.net.w3t, NH, S.net.b3, r0, o1);
 #pragma unroll
-        for (int i = 0; i < 4; i++) S.o[(r0 + q * 4 + i) * NOUTP + r16] = o1[0][i];
+        for (int i = 0; i < 4; i++)
+            S.o[(r0 + q * 4 + i) * NOUTP + r16] = o1[0][i] + skip_term(S.x + (r0 + q * 4 + i) * NIN, r16);
         __syncthreads();
         // loss layer: one thread per sample
         if (t < 64) {
@@ -1165,6 +1255,7 @@ struct otoo_mlp {
     int64_t geom_cap = 0;
     int64_t step = 0;
     bool has_params = false;
+    float gate = 0.f;          // the layers run only for pairs whose BF16 l/n is at least this
 };
 
 namespace {
@@ -1269,6 +1360,14 @@ int otoo_mlp_set_params(otoo_mlp* m, const float* params) {
     return mlp_upload(m, params, zero.data(), zero.data());
 }
 
+int otoo_mlp_set_gate(otoo_mlp* m, float gate) {
+    int rc = mlp_check(m);
+    if (rc) return rc;
+    if (!(gate >= 0.f)) return fail(m->ctx, OTOO_EINVAL, "gate must be >= 0 (or +inf)");
+    m->gate = gate;
+    return OTOO_OK;
+}
+
 int otoo_mlp_get_params(otoo_mlp* m, float* params, float* adam_m, float* adam_v, int64_t* step) {
     int rc = mlp_check(m);
     if (rc) return rc;
@@ -1360,8 +1459,8 @@ int otoo_mlp_infer(otoo_mlp* m, int32_t n, const float* pos, int32_t n_groups, c
     }
     hipLaunchKernelGGL(k_group_geom, dim3(n_groups), dim3(256), 0, c->stream, pos, n, group_off, m->geom,
                        c->errflag);
-    InferArgs ia{n,        n_groups, list_off, n_entries, list_idx, pair_off, n_pairs, n_cells,
-                 cell_mom, eps,      m->geom,  m->wbf,    m->master, corr,    c->errflag};
+    InferArgs ia{n,        n_groups, list_off, n_entries, list_idx,  pair_off, n_pairs, n_cells,
+                 cell_mom, eps,      m->geom,  m->wbf,    m->master, m->gate, corr,    c->errflag};
     const int blocks = (int)std::min<int64_t>(4 * (int64_t)c->num_cu, (n_pairs + 63) / 64);
     hipLaunchKernelGGL(k_mlp_infer, dim3(blocks), dim3(256), 0, c->stream, ia);
     HIP_TRY(c, hipGetLastError());
@@ -1392,7 +1491,7 @@ int otoo_correction(otoo_ctx* c, int32_t kind, otoo_mlp* m, int32_t n, const flo
     }
     CorrArgs ca{n,        pos,     n_groups, group_off, list_off, n_entries, list_idx,
                 pair_off, n_pairs, n_cells,  cell_mom,  cell_stride, eps,   corr,
-                m ? m->wbf : nullptr, m ? m->master : nullptr, gcorr, c->errflag};
+                m ? m->wbf : nullptr, m ? m->master : nullptr, m ? m->gate : 0.f, gcorr, c->errflag};
     const int per_cu = kind == OTOO_CORR_MLP ? 3 : 6;
     const int blocks = (int)std::min<int64_t>((int64_t)per_cu * c->num_cu, n_groups);
     if (kind == OTOO_CORR_PAIRS)

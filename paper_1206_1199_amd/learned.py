@@ -36,6 +36,7 @@ def _bind():
         "otoo_mlp_create": ([P, pp], I32),
         "otoo_mlp_destroy": ([P], I32),
         "otoo_mlp_set_params": ([P, P], I32),
+        "otoo_mlp_set_gate": ([P, F], I32),
         "otoo_mlp_get_params": ([P, P, P, P, P], I32),
         "otoo_mlp_save": ([P, ctypes.c_char_p], I32),
         "otoo_mlp_load": ([P, ctypes.c_char_p], I32),
@@ -77,6 +78,7 @@ class Network:
         h = ctypes.c_void_p()
         ctx._raise(L.otoo_mlp_create(ctx._h, ctypes.byref(h)), "otoo_mlp_create")
         self._h = h
+        self.gate = 0.0
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -96,6 +98,11 @@ class Network:
         if p.size != N_PARAMS:
             raise ValueError(f"expected {N_PARAMS} parameters")
         self._raise(_bind().otoo_mlp_set_params(self._h, p.ctypes.data_as(ctypes.c_void_p)), "otoo_mlp_set_params")
+
+    def set_gate(self, gate: float):
+        """Run the layers only for pairs with BF16 feature l/n >= gate (textbook quadrupole elsewhere)."""
+        self._raise(_bind().otoo_mlp_set_gate(self._h, float(gate)), "otoo_mlp_set_gate")
+        self.gate = float(gate)
 
     def get_params(self):
         p = np.empty(N_PARAMS, np.float32)
@@ -203,11 +210,18 @@ def draw_samples(lists: Lists, n_samples: int, rng: np.random.Generator) -> np.n
     return np.stack([p, i], axis=1).astype(np.int64)
 
 
-def make_training_set(ctx, net: Network, configs, seed: int, device="cuda:0", log=None):
+def bf16_column(X, j):
+    """Column j of BF16 feature rows (int16 bit patterns) as float32."""
+    import torch
+    return (X[:, j].to(torch.int32) << 16).view(torch.float32)
+
+
+def make_training_set(ctx, net: Network, configs, seed: int, device="cuda:0", log=None, gate: float = 0.0):
     """Training samples from seeded walks (exact cell sums computed on the GPU).
 
-    Returns (X int16 [S,32], aux float32 [S,12], eps float32 [S]) on the device;
-    samples of different softening lengths carry their own eps.
+    Only pairs the gate lets through to the layers (BF16 feature l/n >= gate)
+    are kept.  Returns (X int16 [S,32], aux float32 [S,12], eps float32 [S])
+    on the device; samples of different softening lengths carry their own eps.
     """
     import torch
     import synth
@@ -223,6 +237,9 @@ def make_training_set(ctx, net: Network, configs, seed: int, device="cuda:0", lo
         d, first, count = device_tree_arrays(tree, lists, device)
         smp = torch.from_numpy(draw_samples(lists, cfg.n_samples, rng)).to(device)
         X, aux = net.train_samples(d, first, count, cfg.eps, smp)
+        if gate > 0.0:
+            keep = bf16_column(X, 3) >= gate
+            X, aux = X[keep].contiguous(), aux[keep].contiguous()
         Xs.append(X)
         auxs.append(aux)
         epss.append(torch.full((X.shape[0],), cfg.eps, dtype=torch.float32, device=device))

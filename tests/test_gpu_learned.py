@@ -182,10 +182,17 @@ def test_checkpoint_resume_is_exact(env, tmp_path):
     net.set_params(env["params"])
 
 
-def test_infer_matches_oracle(env):
+@pytest.mark.parametrize("gate", [0.0, 0.4])
+def test_infer_matches_oracle(env, gate):
+    """Per-pair tensors (skip term plus the layers where the gate lets them
+    run) against the oracle network at the same BF16 features."""
     net, d, lists, cm, pos32 = env["net"], env["d"], env["lists"], env["cm"], env["pos32"]
     net.set_params(env["params"])
-    corr = net.infer(d, EPS).cpu().numpy().astype(np.float64)
+    net.set_gate(gate)
+    try:
+        corr = net.infer(d, EPS).cpu().numpy().astype(np.float64)
+    finally:
+        net.set_gate(0.0)
     env["ctx"].check()
     n = len(pos32)
     sel = np.arange(0, int(lists.pair_off[-1]), 11)
@@ -199,11 +206,16 @@ def test_infer_matches_oracle(env):
                                    cm[c, 3:4].astype(np.float64))[0])
         scale.append(float(cm[c, 3]) * float(cm[c, 4]) ** 2)
     u = omlp.to_bf16(np.array(feats))
-    o, _ = omlp.forward(omlp.bf16_params(omlp.flat_to_params(env["params"])), u)
+    o = omlp.gated_outputs(omlp.bf16_params(omlp.flat_to_params(env["params"])), u, gate)
     q_ref = omlp.traceless(o) * np.array(scale)[:, None]
     e = rel_l2(corr[sel], q_ref)
-    print(f"inference rel L2 {e:.2e}", flush=True)
+    frac = np.mean(u[:, 3] >= gate)
+    print(f"inference gate {gate} ({frac:.2f} of pairs through the layers): rel L2 {e:.2e}", flush=True)
     assert e <= 3e-2
+    if gate > 0:
+        assert 0.05 < frac < 0.95
+        off = u[:, 3] < gate          # the skip term alone: the textbook quadrupole of the BF16 moments
+        np.testing.assert_allclose(corr[sel][off], q_ref[off], rtol=1e-5, atol=1e-6 * np.abs(q_ref).max())
 
 
 def test_training_reduces_loss_and_helps_forces(env):
@@ -213,12 +225,15 @@ def test_training_reduces_loss_and_helps_forces(env):
     X, aux, eps_all = learned.make_training_set(ctx, net, cfgs, seed=1)
     Xv, auxv, epsv = learned.make_training_set(
         ctx, net, [learned.SampleConfig("plummer", 16384, 1100, EPS, 0.8, 64, 30000)], seed=2)
-    net.set_params(learned.init_params(0))
     base = learned.zero_correction_loss(auxv)
+    net.set_params(np.zeros(learned.N_PARAMS, np.float32))     # zero layers: the textbook quadrupole
+    quad = learned.evaluate_loss(net, Xv, auxv, epsv)
+    net.set_params(learned.init_params(0))
     learned.fit(net, X, aux, eps_all, steps=600, batch=16384, lr=2e-3, seed=0)
     val = learned.evaluate_loss(net, Xv, auxv, epsv)
-    print(f"validation loss {val:.4e} vs plain monopole {base:.4e}", flush=True)
+    print(f"validation loss {val:.4e} vs plain monopole {base:.4e}, textbook quadrupole {quad:.4e}", flush=True)
     assert val < 0.5 * base
+    assert val < quad
     # forces on a held-out Plummer sphere at theta = 0.8
     pos, m = synth.plummer(16384, seed=1101)
     tree = otoo.Tree(pos, m, n_crit=16)
@@ -227,6 +242,7 @@ def test_training_reduces_loss_and_helps_forces(env):
     _, pos32, mass32, _ = tree.export(12)
     gc = ctx.correction(d, otoo.CORR_MLP, EPS, net=net)
     a_l, _ = ctx.force(d, EPS, gcorr=gc)
+    a_q, _ = ctx.force(d, EPS, gcorr=ctx.correction(d, otoo.CORR_QUAD, EPS))
     a_m, _ = ctx.force(d, EPS)
     torch.cuda.synchronize()
     ctx.check()
@@ -235,12 +251,13 @@ def test_training_reduces_loss_and_helps_forces(env):
                              tgt=sample)
     e_l = np.median(oracle.rel_err(a_l.cpu().numpy()[sample], a_dir))
     e_m = np.median(oracle.rel_err(a_m.cpu().numpy()[sample], a_dir))
-    print(f"theta 0.8 held out: monopole median {e_m:.2e}, learned {e_l:.2e}", flush=True)
+    e_q = np.median(oracle.rel_err(a_q.cpu().numpy()[sample], a_dir))
+    print(f"theta 0.8 held out: monopole median {e_m:.2e}, quadrupole {e_q:.2e}, learned {e_l:.2e}", flush=True)
     assert e_l < 0.8 * e_m
 
 
-@pytest.mark.parametrize("net_kernel", [0, 1])
-def test_fused_learned_correction_matches_oracle(env, net_kernel):
+@pytest.mark.parametrize("net_kernel,gate", [(0, 0.0), (1, 0.0), (0, 0.4), (1, 0.4)])
+def test_fused_learned_correction_matches_oracle(env, net_kernel, gate):
     """The fused per-group learned correction (register-resident network, or
     the LDS-staged one) against the oracle's list force with the oracle
     network's tensors (FP64 features rounded to BF16, BF16 weights): the
@@ -250,11 +267,13 @@ def test_fused_learned_correction_matches_oracle(env, net_kernel):
     net.set_params(env["params"])
     old = ctx.tuning()
     ctx.set_tuning(net_kernel=net_kernel)
+    net.set_gate(gate)
     try:
         gc = ctx.correction(d, otoo.CORR_MLP, EPS, net=net)
     finally:
         ctx.set_tuning(chunk=old.chunk, blocks_per_cu=old.blocks_per_cu, lpt=old.lpt, tile=old.tile,
                        net_kernel=old.net_kernel)
+        net.set_gate(0.0)
     acc, pot = ctx.force(d, EPS, gcorr=gc)
     torch.cuda.synchronize()
     ctx.check()
@@ -268,7 +287,8 @@ def test_fused_learned_correction_matches_oracle(env, net_kernel):
                                    np.array([h]), cm[c, 5:11][None].astype(np.float64),
                                    cm[c, 3:4].astype(np.float64))[0])
         scale.append(float(cm[c, 3]) * float(cm[c, 4]) ** 2)
-    o, _ = omlp.forward(omlp.bf16_params(omlp.flat_to_params(env["params"])), omlp.to_bf16(np.array(feats)))
+    o = omlp.gated_outputs(omlp.bf16_params(omlp.flat_to_params(env["params"])), omlp.to_bf16(np.array(feats)),
+                           gate)
     quad = omlp.traceless(o) * np.array(scale)[:, None]
     sample = synth.sample_idx(n, 2048, seed=7)
     a_ref, p_ref = oracle.list_force(pos32.astype(np.float64), mass32.astype(np.float64), lists.group_off,
@@ -277,7 +297,8 @@ def test_fused_learned_correction_matches_oracle(env, net_kernel):
                                      n_cellent=lists.n_cellent, quad=quad, expanded=True)
     ea = oracle.rel_err(acc.cpu().numpy().astype(np.float64)[sample], a_ref)
     ep = oracle.rel_err(pot.cpu().numpy()[sample], p_ref)
-    print(f"fused learned correction: acc median {np.median(ea):.2e} p99 {np.quantile(ea, 0.99):.2e}, "
+    print(f"fused learned correction (kernel {net_kernel}, gate {gate}): acc median {np.median(ea):.2e} "
+          f"p99 {np.quantile(ea, 0.99):.2e}, "
           f"pot median {np.median(ep):.2e}", flush=True)
     assert np.median(ea) <= 2e-5 and np.quantile(ea, 0.99) <= 2e-4
     assert np.median(ep) <= 2e-5
