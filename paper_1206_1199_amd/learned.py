@@ -219,8 +219,11 @@ def bf16_column(X, j):
 def make_training_set(ctx, net: Network, configs, seed: int, device="cuda:0", log=None, gate: float = 0.0):
     """Training samples from seeded walks (exact cell sums computed on the GPU).
 
-    Only pairs the gate lets through to the layers (BF16 feature l/n >= gate)
-    are kept.  Returns (X int16 [S,32], aux float32 [S,12], eps float32 [S])
+    Each sample is weighted by 1 / |a_i|^2, a_i the total force on its
+    target from the same walk (the per-particle relative error is what the
+    correction is judged by), normalised so that the zero-correction loss of
+    each configuration's samples is 1.  Only pairs the gate lets through to
+    the layers (BF16 feature l/n >= gate) are kept.  Returns (X int16 [S,32], aux float32 [S,12], eps float32 [S])
     on the device; samples of different softening lengths carry their own eps.
     """
     import torch
@@ -237,6 +240,13 @@ def make_training_set(ctx, net: Network, configs, seed: int, device="cuda:0", lo
         d, first, count = device_tree_arrays(tree, lists, device)
         smp = torch.from_numpy(draw_samples(lists, cfg.n_samples, rng)).to(device)
         X, aux = net.train_samples(d, first, count, cfg.eps, smp)
+        # weight: 1 / |a_i|^2 with a_i the target's total (monopole-tree) force,
+        # so a sample counts by its share of the per-particle relative error
+        acc, _ = ctx.force(d, cfg.eps)
+        a2 = (acc[smp[:, 1]].double() ** 2).sum(dim=1)
+        wt = 1.0 / a2
+        t2 = (aux[:, 6:9].double() ** 2).sum(dim=1)
+        aux[:, 10] = (wt / (wt * t2).mean()).float()     # normalised: the zero-correction loss is 1
         if gate > 0.0:
             keep = bf16_column(X, 3) >= gate
             X, aux = X[keep].contiguous(), aux[keep].contiguous()

@@ -222,9 +222,10 @@ def test_training_reduces_loss_and_helps_forces(env):
     ctx, net = env["ctx"], env["net"]
     cfgs = [learned.SampleConfig("plummer", 16384, 1000 + k, EPS, th, 64, 60000)
             for k, th in enumerate((0.5, 0.6, 0.7, 0.8, 0.9, 0.75))]
-    X, aux, eps_all = learned.make_training_set(ctx, net, cfgs, seed=1)
+    gate = 0.4
+    X, aux, eps_all = learned.make_training_set(ctx, net, cfgs, seed=1, gate=gate)
     Xv, auxv, epsv = learned.make_training_set(
-        ctx, net, [learned.SampleConfig("plummer", 16384, 1100, EPS, 0.8, 64, 30000)], seed=2)
+        ctx, net, [learned.SampleConfig("plummer", 16384, 1100, EPS, 0.8, 64, 30000)], seed=2, gate=gate)
     base = learned.zero_correction_loss(auxv)
     net.set_params(np.zeros(learned.N_PARAMS, np.float32))     # zero layers: the textbook quadrupole
     quad = learned.evaluate_loss(net, Xv, auxv, epsv)
@@ -240,7 +241,9 @@ def test_training_reduces_loss_and_helps_forces(env):
     lists = tree.walk(theta=0.8, g_max=64)
     d, _, _ = learned.device_tree_arrays(tree, lists)
     _, pos32, mass32, _ = tree.export(12)
+    net.set_gate(gate)
     gc = ctx.correction(d, otoo.CORR_MLP, EPS, net=net)
+    net.set_gate(0.0)
     a_l, _ = ctx.force(d, EPS, gcorr=gc)
     a_q, _ = ctx.force(d, EPS, gcorr=ctx.correction(d, otoo.CORR_QUAD, EPS))
     a_m, _ = ctx.force(d, EPS)
@@ -254,6 +257,7 @@ def test_training_reduces_loss_and_helps_forces(env):
     e_q = np.median(oracle.rel_err(a_q.cpu().numpy()[sample], a_dir))
     print(f"theta 0.8 held out: monopole median {e_m:.2e}, quadrupole {e_q:.2e}, learned {e_l:.2e}", flush=True)
     assert e_l < 0.8 * e_m
+    assert e_l < 1.05 * e_q
 
 
 @pytest.mark.parametrize("net_kernel,gate", [(0, 0.0), (1, 0.0), (0, 0.4), (1, 0.4)])
