@@ -19,19 +19,48 @@ __device__ __forceinline__ float spline_w(float u) {
     return fmaf(2.f * a * a, a, -8.f * b * b * b);
 }
 
+// Source record of one list entry, as staged in LDS: position and 1/h,
+// then q and q sigma (sigma = 8 / (pi h^3)).  Entries that are not particles
+// get q = 0.
+struct SphSrc {
+    float4 x;
+    float2 q;
+};
+
+__device__ __forceinline__ SphSrc load_src(const float* __restrict__ pos, const float* __restrict__ hh,
+                                           const float* __restrict__ q, const int32_t* __restrict__ list_idx,
+                                           int64_t e, int32_t n, int32_t* err) {
+    SphSrc r;
+    const int32_t j = list_idx[e];
+    if (j >= 0 && j < n) {
+        const float ih = 1.f / hh[j];
+        const float qj = q[j];
+        r.x = make_float4(pos[3 * j], pos[3 * j + 1], pos[3 * j + 2], ih);
+        r.q = make_float2(qj, qj * (8.f * kInvPi) * ih * ih * ih);
+    } else {
+        atomicOr(err, kErrIndex);
+        r.x = make_float4(0.f, 0.f, 0.f, 0.f);
+        r.q = make_float2(0.f, 0.f);
+    }
+    return r;
+}
+
 // One workgroup per group (grid-stride).  Lanes are (target, slice): with
-// n_g targets, S = 256 / n_g slices split each staged tile.  Per target the
-// slices' partial sums are combined in slice order, so results are
-// reproducible.  Sums A = sum q_j w(r/h_i) and B = sum q_j sigma_j w(r/h_j)
-// give out_i = (sigma_i A + B) / 2 with sigma = 8 / (pi h^3).
+// n_g targets, S = 256 / n_g slices split each staged tile.  Tiles are
+// double-buffered: each thread gathers its entry of the next tile into
+// registers while the workgroup works on the current one, so there is one
+// barrier per tile.  Per target the slices' partial sums are combined in
+// slice order, so results are reproducible.  Sums A = sum q_j w(r/h_i) and
+// B = sum q_j sigma_j w(r/h_j) give out_i = (sigma_i A + B) / 2 with
+// sigma = 8 / (pi h^3).
 __global__ __launch_bounds__(kBlock) void k_sph(int32_t n, const float* __restrict__ pos,
                                                 const float* __restrict__ hh, const float* __restrict__ q,
                                                 int32_t n_groups, const int32_t* __restrict__ group_off,
                                                 int64_t n_entries, const int64_t* __restrict__ list_off,
                                                 const int32_t* __restrict__ list_idx, float* __restrict__ out,
                                                 int32_t* err) {
-    __shared__ float4 sX[kSphTile];   // x, y, z, 1/h
-    __shared__ float2 sQ[kSphTile];   // q, q sigma
+    __shared__ float4 sX[2][kSphTile];   // x, y, z, 1/h
+    __shared__ float2 sQ[2][kSphTile];   // q, q sigma
     __shared__ float2 red[kBlock];
     const int t = threadIdx.x;
     for (int g = blockIdx.x; g < n_groups; g += gridDim.x) {
@@ -51,36 +80,40 @@ __global__ __launch_bounds__(kBlock) void k_sph(int32_t n, const float* __restri
         float A = 0.f, B = 0.f;
         int64_t lb, le;
         list_range(list_off, n_entries, g, lb, le);
-        for (int64_t base = lb; base < le; base += kSphTile) {
-            const int cnt = (int)((le - base) < kSphTile ? (le - base) : kSphTile);
-            __syncthreads();   // the previous tile has been read
-            if (t < cnt) {
-                const int32_t j = list_idx[base + t];
-                if (j >= 0 && j < n) {
-                    const float hj = hh[j];
-                    const float ih = 1.f / hj;
-                    const float qj = q[j];
-                    sX[t] = make_float4(pos[3 * j], pos[3 * j + 1], pos[3 * j + 2], ih);
-                    sQ[t] = make_float2(qj, qj * (8.f * kInvPi) * ih * ih * ih);
-                } else {
-                    atomicOr(err, kErrIndex);
-                    sX[t] = make_float4(0.f, 0.f, 0.f, 0.f);   // 1/h = 0: u = 0 but q = 0
-                    sQ[t] = make_float2(0.f, 0.f);
-                }
-            }
-            __syncthreads();
-            if (lane_on) {
-                for (int k = sl; k < cnt; k += S) {
-                    const float4 s = sX[k];
-                    const float2 w = sQ[k];
-                    const float dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
-                    const float r = __builtin_amdgcn_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
-                    A = fmaf(w.x, spline_w(r * ihi), A);
-                    B = fmaf(w.y, spline_w(r * s.w), B);
-                }
-            }
+        const int64_t len = le - lb;
+        const int n_tiles = (int)((len + kSphTile - 1) / kSphTile);
+        __syncthreads();   // the previous group's buffers and reduction have been read
+        if (n_tiles > 0 && t < len) {
+            const SphSrc r = load_src(pos, hh, q, list_idx, lb + t, n, err);
+            sX[0][t] = r.x;
+            sQ[0][t] = r.q;
         }
         __syncthreads();
+        for (int it = 0; it < n_tiles; it++) {
+            const int cur = it & 1;
+            const int64_t base = (int64_t)it * kSphTile;
+            const int cnt = (int)((len - base) < kSphTile ? (len - base) : kSphTile);
+            // gather this thread's entry of the next tile (lands while the current one is computed)
+            const int64_t nxt = base + kSphTile + t;
+            const bool pre = nxt < len;
+            SphSrc r;
+            if (pre) r = load_src(pos, hh, q, list_idx, lb + nxt, n, err);
+            if (lane_on) {
+                for (int k = sl; k < cnt; k += S) {
+                    const float4 s = sX[cur][k];
+                    const float2 w = sQ[cur][k];
+                    const float dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
+                    const float rr = __builtin_amdgcn_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+                    A = fmaf(w.x, spline_w(rr * ihi), A);
+                    B = fmaf(w.y, spline_w(rr * s.w), B);
+                }
+            }
+            if (pre) {
+                sX[cur ^ 1][t] = r.x;
+                sQ[cur ^ 1][t] = r.q;
+            }
+            __syncthreads();
+        }
         red[t] = make_float2(A, B);
         __syncthreads();
         if (t < ng) {
