@@ -99,6 +99,7 @@ __global__ __launch_bounds__(kBlock) void k_sph(int32_t n, const float* __restri
             SphSrc r;
             if (pre) r = load_src(pos, hh, q, list_idx, lb + nxt, n, err);
             if (lane_on) {
+#pragma unroll 4
                 for (int k = sl; k < cnt; k += S) {
                     const float4 s = sX[cur][k];
                     const float2 w = sQ[cur][k];
