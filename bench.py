@@ -76,11 +76,23 @@ def measured_traffic(desc, sched):
     return None
 
 
+def particle_classes(name, out):
+    """Boolean masks over the input order for the workload's particle classes
+    (the polytrope pair: star A, star B, and cores r < R/4 vs envelopes)."""
+    if name != "polytrope2m":
+        return {}
+    pos, _, star, centres = out
+    radius = np.where(star == 0, 0.02, 0.012)
+    r = np.linalg.norm(pos - centres[star], axis=1)
+    core = r < radius / 4
+    return {"A": star == 0, "B": star == 1, "core": core, "envelope": ~core}
+
+
 def make_workload(name):
     import synth
     gen, kw, eps, theta, desc = WORKLOADS[name]
     out = getattr(synth, gen)(**kw)
-    return out[0], out[1], eps, theta, desc
+    return out[0], out[1], eps, theta, desc, particle_classes(name, out)
 
 
 # ------------------------------------------------------------------ CPU baseline leg (the oracle)
@@ -285,7 +297,7 @@ def main():
     import paper_1206_1199_amd as otoo
     from paper_1206_1199_amd import autotune as at
 
-    pos, m, eps, theta, desc = make_workload(args.workload)
+    pos, m, eps, theta, desc, classes = make_workload(args.workload)
     log(f"workload {desc}: n={len(m)}")
     t0 = time.perf_counter()
     tree = otoo.Tree(pos, m, n_crit=16)
@@ -387,18 +399,31 @@ def main():
         "host": {"tree_build_ms": 1e3 * (t1 - t0), "walk_ms": 1e3 * (t3 - t2), "h2d_ms": 1e3 * (t5 - t4)},
     }
     # accuracy of the tree force: FP64 direct sums on the device at a 4096-particle sample
-    sample = __import__("synth").sample_idx(len(m), 4096, seed=SAMPLE_SEED.get(args.workload, 100))
+    import synth
+    seed = SAMPLE_SEED.get(args.workload, 100)
+    cls = {k: v[perm] for k, v in classes.items()}          # masks in device order
+    if "A" in cls:    # 2048 sampled particles per star
+        ia, ib = np.flatnonzero(cls["A"]), np.flatnonzero(cls["B"])
+        sample = np.concatenate([ia[synth.sample_idx(len(ia), 2048, seed)], ib[synth.sample_idx(len(ib), 2048, seed)]])
+    else:
+        sample = synth.sample_idx(len(m), 4096, seed=seed)
     a_dir, p_dir = direct_reference(ctx, d, sample, eps)
     et, ept = rel_err(acc[sample], a_dir), rel_err(pot[sample], p_dir)
     res["accuracy"] = {"tree_acc_median_vs_direct": float(np.median(et)),
                        "tree_acc_p99_vs_direct": float(np.quantile(et, 0.99)),
                        "tree_pot_median_vs_direct": float(np.median(ept)), "direct_sample": len(sample)}
+    for k, mask in cls.items():
+        sel = mask[sample]
+        res["accuracy"][f"tree_acc_median_vs_direct_{k}"] = float(np.median(et[sel])) if sel.any() else None
     if not args.no_cpu_baseline:
         base, (a_ref, p_ref) = cpu_baseline(pos32, mass32, lists, cm, eps)
         ea, ep = rel_err(acc, a_ref), rel_err(pot, p_ref)
         res["cpu_baseline"] = base
         res["accuracy"].update({"parity_acc_median": float(np.median(ea)), "parity_acc_max": float(ea.max()),
                                 "parity_pot_median": float(np.median(ep)), "parity_pot_max": float(ep.max())})
+        for k, mask in cls.items():
+            res["accuracy"][f"parity_acc_median_{k}"] = float(np.median(ea[mask]))
+            res["accuracy"][f"parity_acc_max_{k}"] = float(ea[mask].max())
     log(f"accuracy {res['accuracy']}")
     if not args.no_learned:
         try:

@@ -119,11 +119,18 @@ def test_theta_zero_equals_direct_sum(ctx):
 
 
 def test_polytrope_pair_and_cube(ctx):
-    pos, m, star, _ = synth.polytrope_pair(8192, seed=2)
+    pos, m, star, centres = synth.polytrope_pair(8192, seed=2)
     t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.6, 64)
     acc, pot = _gpu(ctx, d, 1e-4)
     a_ref, p_ref = _oracle(pos32, mass32, lists, cm, 1e-4)
     _assert_parity(acc, pot, a_ref, p_ref, "polytrope pair eps=1e-4")
+    # per particle class: each star, and cores (r < R/4) against envelopes
+    perm = t.export(4)[0]
+    r = np.linalg.norm(pos - centres[star], axis=1)
+    core = r < np.where(star == 0, 0.02, 0.012) / 4
+    for name, mask in (("A", star == 0), ("B", star == 1), ("core", core), ("envelope", ~core)):
+        sel = mask[perm]
+        _assert_parity(acc[sel], pot[sel], a_ref[sel], p_ref[sel], f"polytrope class {name}")
     pos, m = synth.grf_cube(24, seed=4)
     t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.7, 256, otoo.GROUP_CELL)
     acc, pot = _gpu(ctx, d, 1e-3)
