@@ -136,6 +136,18 @@ typedef struct {
  * otoo_lists_free.  EINVAL on bad parameters, ENOMEM on allocation failure. */
 int otoo_tree_walk(const otoo_tree* tree, const otoo_walk_params* params, otoo_lists** out);
 
+/* Number of groups the walk forms for (group_mode, g_max). */
+int otoo_tree_groups(const otoo_tree* tree, int32_t group_mode, int32_t g_max, int32_t* n_groups);
+/* The walk of otoo_tree_walk restricted to groups [g_begin, g_end) of its
+ * grouping (g_end is clamped to the group count), so that a caller can walk
+ * in batches and evaluate earlier batches meanwhile.  group_off holds the
+ * groups' absolute particle offsets (group_off[0] is the first particle of
+ * group g_begin, group_off[n_groups] one past the last of group g_end - 1);
+ * list_off starts at 0.  The concatenated batches equal the whole walk.
+ * EINVAL if g_begin < 0, g_end <= g_begin or g_begin >= the group count. */
+int otoo_tree_walk_range(const otoo_tree* tree, const otoo_walk_params* params, int32_t g_begin, int32_t g_end,
+                         otoo_lists** out);
+
 /* Neighbour lists for SPH gather sums (Sec. 2.3, Eq. 4-5): the same grouped
  * walk with the SPH bounding radius in place of the MAC.  There is no
  * particle-cell interaction: a cell is either opened or skipped whole, so
@@ -203,6 +215,10 @@ int otoo_get_tuning(const otoo_ctx* ctx, otoo_tuning* tuning);
  *   out_acc [n][3] FP32, out_pot [n] FP64 (the potential is reduced in FP64)
  * Arithmetic: FP32 pairs; per-tile FP32 partial sums combined with Kahan
  * compensation across tiles and work items; FP64 for the final potential.
+ * The groups may cover a contiguous sub-range [group_off[0],
+ * group_off[n_groups]) of the particles (a batch of otoo_tree_walk_range);
+ * only those particles' outputs are written, and every group's result is
+ * the same as in a call over all groups.
  * Results are bitwise reproducible for fixed tuning.  Malformed device CSR
  * (indices out of range, group sizes outside 1..OTOO_MAX_GROUP) never causes
  * an out-of-bounds access: such entries are skipped and otoo_check(ctx)

@@ -62,7 +62,7 @@ class Tuning(ctypes.Structure):
 
 EXPORTED = [
     "otoo_tree_build", "otoo_tree_free", "otoo_tree_info", "otoo_tree_export", "otoo_tree_cells",
-    "otoo_tree_links", "otoo_tree_walk", "otoo_tree_walk_sph", "otoo_lists_free", "otoo_create", "otoo_destroy",
+    "otoo_tree_links", "otoo_tree_walk", "otoo_tree_groups", "otoo_tree_walk_range", "otoo_tree_walk_sph", "otoo_lists_free", "otoo_create", "otoo_destroy",
     "otoo_set_stream", "otoo_last_error", "otoo_set_tuning", "otoo_get_tuning", "otoo_force",
     "otoo_check", "otoo_enable_timing", "otoo_last_timing", "otoo_graph_capture", "otoo_graph_launch",
     "otoo_quad_exact", "otoo_correction", "otoo_direct", "otoo_sph_sum", "otoo_mlp_num_params", "otoo_mlp_create", "otoo_mlp_destroy", "otoo_mlp_set_params", "otoo_mlp_set_gate",
@@ -90,6 +90,9 @@ def lib():
         "otoo_tree_links": ([P, P, P], I32),
         "otoo_tree_walk": ([P, ctypes.POINTER(_WalkParams), ctypes.POINTER(ctypes.POINTER(_Lists))], I32),
         "otoo_tree_walk_sph": ([P, P, I32, I32, ctypes.POINTER(ctypes.POINTER(_Lists))], I32),
+        "otoo_tree_groups": ([P, I32, I32, ctypes.POINTER(I32)], I32),
+        "otoo_tree_walk_range": ([P, ctypes.POINTER(_WalkParams), I32, I32,
+                                  ctypes.POINTER(ctypes.POINTER(_Lists))], I32),
         "otoo_lists_free": ([ctypes.POINTER(_Lists)], None),
         "otoo_create": ([pp, I32], I32),
         "otoo_destroy": ([P], I32),
@@ -214,6 +217,22 @@ class Tree:
         _check(lib().otoo_tree_walk(self._h, ctypes.byref(p), ctypes.byref(out)), "otoo_tree_walk")
         return self._take_lists(out)
 
+    def n_groups(self, g_max: int = 64, group_mode: int = GROUP_CHUNK) -> int:
+        """Number of groups the walk forms for (group_mode, g_max)."""
+        ng = ctypes.c_int32()
+        _check(lib().otoo_tree_groups(self._h, int(group_mode), int(g_max), ctypes.byref(ng)), "otoo_tree_groups")
+        return ng.value
+
+    def walk_range(self, g_begin: int, g_end: int, theta: float = 0.5, g_max: int = 64,
+                   group_mode: int = GROUP_CHUNK, mac: int = MAC_BH, delta: float = 0.01,
+                   m_limit: float = math.inf) -> Lists:
+        """The walk restricted to groups [g_begin, g_end): absolute group_off, list_off from 0."""
+        p = _WalkParams(mac=mac, theta=theta, delta=delta, m_limit=m_limit, group_mode=group_mode, g_max=g_max)
+        out = ctypes.POINTER(_Lists)()
+        _check(lib().otoo_tree_walk_range(self._h, ctypes.byref(p), int(g_begin), int(g_end), ctypes.byref(out)),
+               "otoo_tree_walk_range")
+        return self._take_lists(out)
+
     def walk_sph(self, h, g_max: int = 64, group_mode: int = GROUP_CHUNK) -> Lists:
         """Neighbour lists for SPH gather sums; h [n] in the caller's particle order."""
         h = np.ascontiguousarray(h, dtype=np.float64)
@@ -282,6 +301,21 @@ class DeviceLists:
                    list_idx=t(lists.list_idx if lists.n_entries else np.zeros(1, np.int32), np.int32),
                    cell_mom=t(cm, np.float32)[:len(cell_mom)], pair_off=t(lists.pair_off, np.int64),
                    n_entries=lists.n_entries, interactions=lists.interactions)
+
+
+def _lists_on_device(cls, pos, mass, cell_mom, lists: Lists):
+    """DeviceLists of one batch: particle and cell arrays already on the device,
+    the batch's CSR copied over (its group_off may start past particle 0)."""
+    import torch
+    dev = pos.device
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(dev)
+    return cls(pos=pos, mass=mass, group_off=t(lists.group_off, np.int32), list_off=t(lists.list_off, np.int64),
+               list_idx=t(lists.list_idx if lists.n_entries else np.zeros(1, np.int32), np.int32),
+               cell_mom=cell_mom, pair_off=t(lists.pair_off, np.int64), n_entries=lists.n_entries,
+               interactions=lists.interactions)
+
+
+DeviceLists.on_device = classmethod(_lists_on_device)
 
 
 def _tptr(x):

@@ -234,7 +234,7 @@ void walk_groups(const otoo_tree* t, const std::vector<int64_t>& goff, Decide de
         tot += g_len[g];
         inter += (goff[g + 1] - goff[g]) * g_len[g];
     }
-    L->group_off[ng] = (int32_t)n;
+    L->group_off[ng] = (int32_t)goff[ng];
     L->list_off[ng] = tot;
     L->list_idx.resize(tot);
 #pragma omp parallel for schedule(dynamic, 64)
@@ -532,8 +532,26 @@ int otoo_tree_links(const otoo_tree* t, int64_t* next, int64_t* more) {
     return OTOO_OK;
 }
 
+int otoo_tree_groups(const otoo_tree* t, int32_t group_mode, int32_t g_max, int32_t* n_groups) {
+    if (!t || !n_groups) return OTOO_EINVAL;
+    if (g_max < 1 || g_max > OTOO_MAX_GROUP) return OTOO_EINVAL;
+    if (group_mode != OTOO_GROUP_CHUNK && group_mode != OTOO_GROUP_CELL) return OTOO_EINVAL;
+    try {
+        *n_groups = (int32_t)(make_groups(t, group_mode, g_max).size() - 1);
+    } catch (const std::bad_alloc&) {
+        return OTOO_ENOMEM;
+    }
+    return OTOO_OK;
+}
+
 int otoo_tree_walk(const otoo_tree* t, const otoo_walk_params* wp, otoo_lists** out) {
+    return otoo_tree_walk_range(t, wp, 0, INT32_MAX, out);
+}
+
+int otoo_tree_walk_range(const otoo_tree* t, const otoo_walk_params* wp, int32_t g_begin, int32_t g_end,
+                         otoo_lists** out) {
     if (!t || !wp || !out) return OTOO_EINVAL;
+    if (g_begin < 0 || g_end <= g_begin) return OTOO_EINVAL;
     if (wp->g_max < 1 || wp->g_max > OTOO_MAX_GROUP) return OTOO_EINVAL;
     if (wp->mac == OTOO_MAC_BH) {
         if (!(wp->theta >= 0.0) || !(wp->theta < OTOO_THETA_LIMIT)) return OTOO_EINVAL;
@@ -547,7 +565,14 @@ int otoo_tree_walk(const otoo_tree* t, const otoo_walk_params* wp, otoo_lists** 
     if (!L) return OTOO_ENOMEM;
     try {
         const int64_t nc = t->n_cells();
-        const std::vector<int64_t> goff = make_groups(t, wp->group_mode, wp->g_max);
+        std::vector<int64_t> goff = make_groups(t, wp->group_mode, wp->g_max);
+        const int64_t ng_all = (int64_t)goff.size() - 1;
+        if (g_begin >= ng_all) {
+            delete L;
+            return OTOO_EINVAL;
+        }
+        const int64_t g1 = std::min<int64_t>(g_end, ng_all);
+        goff = std::vector<int64_t>(goff.begin() + g_begin, goff.begin() + g1 + 1);
         // acceptance radius per cell: accept iff d_min > rc
         std::vector<double> rc(nc);
         for (int64_t c = 0; c < nc; c++) {

@@ -666,7 +666,8 @@ int validate_csr(otoo_ctx* c, const Call& a) {
     HIP_TRY(c, hipMemcpy(lo.data(), a.list_off, sizeof(int64_t) * lo.size(), hipMemcpyDeviceToHost));
     if (a.n_entries)
         HIP_TRY(c, hipMemcpy(li.data(), a.list_idx, sizeof(int32_t) * li.size(), hipMemcpyDeviceToHost));
-    if (go[0] != 0 || go[a.n_groups] != a.n) return fail(c, OTOO_EINVAL, "group_off must run from 0 to n");
+    if (go[0] < 0 || go[a.n_groups] > a.n || go[0] > go[a.n_groups])
+        return fail(c, OTOO_EINVAL, "group_off must lie within 0..n");
     if (lo[0] != 0 || lo[a.n_groups] != a.n_entries)
         return fail(c, OTOO_EINVAL, "list_off must run from 0 to n_entries");
     const int64_t n_src = (int64_t)a.n + a.n_cells;

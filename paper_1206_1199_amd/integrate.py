@@ -6,9 +6,19 @@ positions, (2) build the tree, (7) update the cell properties for gravity,
 paper, everything except the force runs on the host: the state stays in FP64
 on the host in the caller's particle order, the tree is rebuilt every step
 and the force comes back from the device (kick-drift-kick leap-frog).
+
+Two ways to run step (8):
+- ``batches > 1``: the host walks the groups in batches on a worker thread
+  while the device evaluates the batches already walked (the host rebuild
+  overlapped with the GPU force);
+- ``batches == 1``: one walk, then the step's force launch captured in a
+  HIP graph and replayed (``use_graph``) or enqueued directly.
+The forces are bitwise the same either way.
 """
 from __future__ import annotations
 
+import queue
+import threading
 import time
 from dataclasses import dataclass, field
 
@@ -19,37 +29,95 @@ from . import GROUP_CHUNK, Context, DeviceLists, Tree
 
 @dataclass
 class StepTimes:
+    """Per-step host wall times: tree build, host walk (summed over batches),
+    and step 8 as a whole (walk, copies and device force, overlapped when
+    batched) until the forces are back on the host."""
     tree_ms: list = field(default_factory=list)
     walk_ms: list = field(default_factory=list)
-    h2d_ms: list = field(default_factory=list)
-    force_ms: list = field(default_factory=list)
+    eval_ms: list = field(default_factory=list)
 
 
 class LeapFrog:
     """Kick-drift-kick integrator with softening eps and opening angle theta."""
 
     def __init__(self, pos, vel, mass, eps: float, theta: float, g_max: int = 64, ctx: Context | None = None,
-                 group_mode: int = GROUP_CHUNK):
+                 group_mode: int = GROUP_CHUNK, batches: int = 1, use_graph: bool = False):
         self.x = np.array(pos, dtype=np.float64)
         self.v = np.array(vel, dtype=np.float64)
         self.m = np.array(mass, dtype=np.float64)
         self.eps, self.theta, self.g_max, self.group_mode = eps, theta, g_max, group_mode
+        self.batches, self.use_graph = max(1, int(batches)), use_graph
         self.ctx = ctx or Context(0)
         self.times = StepTimes()
         self.a, self.phi = self._force()
 
-    def _force(self):
+    def _walk_kw(self):
+        return dict(theta=self.theta, g_max=self.g_max, group_mode=self.group_mode)
+
+    def _evaluate_whole(self, tree, pos32, mass32, cm):
         import torch
+        t0 = time.perf_counter()
+        lists = tree.walk(**self._walk_kw())
+        t1 = time.perf_counter()
+        d = DeviceLists.from_host(pos32, mass32, lists, cm)
+        out = self.ctx.outputs(d.n)
+        if self.use_graph:
+            self.ctx.graph_capture(d, self.eps, out)
+            self.ctx.graph_launch()
+        else:
+            self.ctx.force(d, self.eps, out=out)
+        torch.cuda.synchronize()
+        return out, t1 - t0
+
+    def _evaluate_pipelined(self, tree, pos32, mass32, cm):
+        """Walk batches of groups on a worker thread; evaluate each on the
+        device as soon as it is walked (the library call releases the GIL)."""
+        import torch
+        dev = f"cuda:{self.ctx.device}"
+        pos_d = torch.from_numpy(pos32).to(dev)
+        mass_d = torch.from_numpy(mass32).to(dev)
+        cm_d = torch.from_numpy(np.ascontiguousarray(cm)).to(dev)
+        G = tree.n_groups(self.g_max, self.group_mode)
+        edges = np.linspace(0, G, min(self.batches, G) + 1).round().astype(int)
+        ready: queue.Queue = queue.Queue()
+        walk_s = [0.0]
+
+        def walker():
+            try:
+                for b in range(len(edges) - 1):
+                    t0 = time.perf_counter()
+                    lists = tree.walk_range(int(edges[b]), int(edges[b + 1]), **self._walk_kw())
+                    walk_s[0] += time.perf_counter() - t0
+                    ready.put(lists)
+            except BaseException as e:   # handed to the main thread
+                ready.put(e)
+
+        th = threading.Thread(target=walker, daemon=True)
+        th.start()
+        out = self.ctx.outputs(len(mass32))
+        alive = []
+        try:
+            for _ in range(len(edges) - 1):
+                lists = ready.get()
+                if isinstance(lists, BaseException):
+                    raise lists
+                d = DeviceLists.on_device(pos_d, mass_d, cm_d, lists)
+                self.ctx.force(d, self.eps, out=out)
+                alive.append(d)        # keep each batch's device lists until the stream is done
+            torch.cuda.synchronize()
+        finally:
+            th.join()
+        return out, walk_s[0]
+
+    def _force(self):
         t0 = time.perf_counter()
         tree = Tree(self.x, self.m, n_crit=16)                      # steps 2 and 7
         t1 = time.perf_counter()
-        lists = tree.walk(theta=self.theta, g_max=self.g_max, group_mode=self.group_mode)
-        t2 = time.perf_counter()
         perm, pos32, mass32, cm = tree.export(4)
-        d = DeviceLists.from_host(pos32, mass32, lists, cm)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        acc, pot = self.ctx.force(d, self.eps)                       # step 8
+        if self.batches > 1:                                         # step 8
+            (acc, pot), walk_s = self._evaluate_pipelined(tree, pos32, mass32, cm)
+        else:
+            (acc, pot), walk_s = self._evaluate_whole(tree, pos32, mass32, cm)
         a_k = acc.cpu().numpy().astype(np.float64)
         p_k = pot.cpu().numpy()
         t4 = time.perf_counter()
@@ -58,8 +126,7 @@ class LeapFrog:
         phi = np.empty_like(p_k)
         a[perm] = a_k
         phi[perm] = p_k
-        for lst, dt in ((self.times.tree_ms, t1 - t0), (self.times.walk_ms, t2 - t1), (self.times.h2d_ms, t3 - t2),
-                        (self.times.force_ms, t4 - t3)):
+        for lst, dt in ((self.times.tree_ms, t1 - t0), (self.times.walk_ms, walk_s), (self.times.eval_ms, t4 - t1)):
             lst.append(1e3 * dt)
         return a, phi
 

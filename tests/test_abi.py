@@ -37,6 +37,8 @@ def test_null_context_and_bad_arguments_return_einval():
     assert lib.otoo_direct(None, 1, None, None, 0, None, 0.1, None, None) == otoo.EINVAL
     assert lib.otoo_sph_sum(None, 1, None, None, None, 1, None, 0, None, None, None) == otoo.EINVAL
     assert lib.otoo_tree_walk_sph(None, None, 0, 64, None) == otoo.EINVAL
+    assert lib.otoo_tree_groups(None, 0, 64, None) == otoo.EINVAL
+    assert lib.otoo_tree_walk_range(None, None, 0, 1, None) == otoo.EINVAL
     assert lib.otoo_check(None) == otoo.EINVAL
     assert lib.otoo_graph_launch(None) == otoo.EINVAL
     assert lib.otoo_set_tuning(None, None) == otoo.EINVAL

@@ -132,3 +132,35 @@ def test_host_entry_points_reject_bad_arguments():
                dict(mac=otoo.MAC_ABSOLUTE, delta=0.0)):
         with pytest.raises(otoo.OtooError):
             t.walk(**kw)
+
+
+@pytest.mark.parametrize("mode,g_max", [(otoo.GROUP_CHUNK, 64), (otoo.GROUP_CELL, 100)])
+def test_walk_in_batches_equals_whole_walk(mode, g_max):
+    """Walking groups [g0, g1) batch by batch gives exactly the whole walk's
+    lists (absolute group offsets, each batch's list offsets from 0)."""
+    pos, m = synth.plummer(20000, seed=31)
+    tree = otoo.Tree(pos, m, n_crit=16)
+    whole = tree.walk(theta=0.6, g_max=g_max, group_mode=mode)
+    G = tree.n_groups(g_max, mode)
+    assert G == whole.n_groups
+    edges = [0, 1, G // 3, G // 3 + 1, G - 5, G]
+    go, lo, li, nc, inter = [0], [0], [], [], 0
+    for a, b in zip(edges[:-1], edges[1:]):
+        part = tree.walk_range(a, b, theta=0.6, g_max=g_max, group_mode=mode)
+        assert part.n_groups == b - a and part.list_off[0] == 0
+        assert part.group_off[0] == whole.group_off[a] and part.group_off[-1] == whole.group_off[b]
+        go += list(part.group_off[1:])
+        lo += list(part.list_off[1:] + lo[-1])
+        li.append(part.list_idx)
+        nc.append(part.n_cellent)
+        inter += part.interactions
+    np.testing.assert_array_equal(go, whole.group_off)
+    np.testing.assert_array_equal(lo, whole.list_off)
+    np.testing.assert_array_equal(np.concatenate(li), whole.list_idx)
+    np.testing.assert_array_equal(np.concatenate(nc), whole.n_cellent)
+    assert inter == whole.interactions
+    # g_end past the group count is clamped; empty or out-of-range batches are rejected
+    assert tree.walk_range(G - 2, G + 100, theta=0.6, g_max=g_max, group_mode=mode).n_groups == 2
+    for a, b in ((5, 5), (-1, 3), (G, G + 1)):
+        with pytest.raises(otoo.OtooError):
+            tree.walk_range(a, b, theta=0.6, g_max=g_max, group_mode=mode)

@@ -24,11 +24,12 @@ def test_plummer_velocities_virial():
 
 
 @pytest.mark.gpu
-def test_leapfrog_energy_conservation():
+@pytest.mark.parametrize("batches,use_graph", [(1, False), (6, False), (1, True)])
+def test_leapfrog_energy_conservation(batches, use_graph):
     from paper_1206_1199_amd.integrate import LeapFrog, plummer_velocities
     pos, m = synth.plummer(8192, seed=13)
     v = plummer_velocities(pos, seed=14)
-    lf = LeapFrog(pos, v, m, eps=0.01, theta=0.4, g_max=64)
+    lf = LeapFrog(pos, v, m, eps=0.01, theta=0.4, g_max=64, batches=batches, use_graph=use_graph)
     e0 = lf.energy()[2]
     for _ in range(25):
         lf.step(2e-3)
@@ -57,3 +58,21 @@ def test_leapfrog_theta0_follows_direct_sum():
         v += 0.5 * dt * a
     np.testing.assert_allclose(lf.x, x, rtol=0, atol=1e-6)
     np.testing.assert_allclose(lf.v, v, rtol=0, atol=1e-6)
+
+
+@pytest.mark.gpu
+def test_pipelined_and_graph_forces_match_plain_bitwise():
+    """Walking in batches overlapped with the device force, or replaying a
+    captured graph, gives bitwise the forces of one plain force call."""
+    import paper_1206_1199_amd as otoo
+    from paper_1206_1199_amd.integrate import LeapFrog
+    pos, m = synth.plummer(30000, seed=16)
+    v = np.zeros_like(pos)
+    ctx = otoo.Context(0)
+    ref = LeapFrog(pos, v, m, eps=0.01, theta=0.6, g_max=64, ctx=ctx)
+    for batches, use_graph in ((7, False), (1, True), (200, False)):
+        lf = LeapFrog(pos, v, m, eps=0.01, theta=0.6, g_max=64, ctx=ctx, batches=batches, use_graph=use_graph)
+        np.testing.assert_array_equal(lf.a, ref.a)
+        np.testing.assert_array_equal(lf.phi, ref.phi)
+    print(f"step times: tree {ref.times.tree_ms[-1]:.1f} ms, walk {ref.times.walk_ms[-1]:.1f} ms, "
+          f"eval {ref.times.eval_ms[-1]:.1f} ms; batched eval {lf.times.eval_ms[-1]:.1f} ms", flush=True)
