@@ -41,7 +41,7 @@ enum otoo_status {
     OTOO_EINVAL = -1,      /* bad argument (null pointer, size, eps, stride, ...) */
     OTOO_ENOMEM = -2,      /* host or device allocation failed, or the scratch cap was hit */
     OTOO_EHIP = -3,        /* a HIP runtime call failed; otoo_last_error has its message */
-    OTOO_EUNSUPPORTED = -4 /* option not available in this build */
+    OTOO_EUNSUPPORTED = -4 /* option not available in this library */
 };
 
 /* Largest group (number of target particles sharing one list) the device

@@ -36,12 +36,6 @@ namespace {
 
 constexpr int kScanBlock = 1024;      // groups per scan block (256 threads x 4)
 
-
-
-
-
-// ---------------------------------------------------------------- helpers
-
 // ---------------------------------------------------------------- K1 pack
 
 __global__ void k_pack(const float* __restrict__ pos, const float* __restrict__ mass, int32_t n,

@@ -4,11 +4,17 @@
 // symmetric traceless tensor Qt_gc whose quadrupole-form field, applied
 // through the group's local expansion, corrects the cell's monopole toward
 // the cell's exact direct sum (the paper uses monopoles only and names higher
-// multipoles without using them, Sec. 2).
+// multipoles without using them, Sec. 2).  A fixed skip term makes the
+// network's tensor the textbook quadrupole plus a learned correction, and a
+// gate on l/|d| limits the layers to near cells.
 //
+//   k_corr_net      per group: features, gated network (register-resident,
+//                   v_mfma_f32_16x16x32_bf16) and the local expansion
+//   k_corr_group    per group, LDS-staged: given tensors, the textbook
+//                   quadrupole, or the network
 //   k_group_geom    bounding-box centre and half-diagonal of each group
-//   k_mlp_infer     features -> 32-64-64-6 GELU network on BF16 MFMA
-//                   (v_mfma_f32_16x16x32_bf16, FP32 accumulate) -> Qt per pair
+//   k_mlp_infer     Qt of every pair (for checks and external use)
+//   k_mlp_forward_raw network outputs for given BF16 features
 //   k_train_samples exact cell sums at target particles (FP64) and features
 //   k_mlp_train     forward, loss through the expansion, backward (MFMA for
 //                   every product), per-workgroup gradient partials
