@@ -133,7 +133,8 @@ def _check(rc, what="call"):
 
 @dataclass
 class Lists:
-    """Interaction-list CSR (host numpy arrays, copied out of the library)."""
+    """Interaction-list CSR: host numpy arrays viewing the library's buffers,
+    which are freed when the last of these arrays is gone."""
     group_off: np.ndarray    # int32 [G+1]
     list_off: np.ndarray     # int64 [G+1]
     list_idx: np.ndarray     # int32 [E]
@@ -244,19 +245,37 @@ class Tree:
         return self._take_lists(out)
 
     def _take_lists(self, out) -> Lists:
-        try:
-            s = out.contents
-            G, E = s.n_groups, s.n_entries
-            res = Lists(
-                group_off=np.ctypeslib.as_array(s.group_off, (G + 1,)).copy(),
-                list_off=np.ctypeslib.as_array(s.list_off, (G + 1,)).copy(),
-                list_idx=(np.ctypeslib.as_array(s.list_idx, (E,)).copy() if E else np.zeros(0, np.int32)),
-                n_cellent=np.ctypeslib.as_array(s.n_cellent, (G,)).copy(),
-                group_box=np.ctypeslib.as_array(s.group_box, (G * 6,)).copy().reshape(G, 6),
-                interactions=int(s.interactions))
-        finally:
-            lib().otoo_lists_free(out)
-        return res
+        # the arrays are views of the library's buffers (no copy of the often
+        # hundreds of MB of list indices); the buffers are freed with the last view
+        owner = _ListsOwner(out)
+        s = out.contents
+        G, E = s.n_groups, s.n_entries
+        return Lists(group_off=_view(s.group_off, ctypes.c_int32, G + 1, owner, np.int32),
+                     list_off=_view(s.list_off, ctypes.c_int64, G + 1, owner, np.int64),
+                     list_idx=_view(s.list_idx, ctypes.c_int32, E, owner, np.int32),
+                     n_cellent=_view(s.n_cellent, ctypes.c_int32, G, owner, np.int32),
+                     group_box=_view(s.group_box, ctypes.c_float, G * 6, owner, np.float32).reshape(G, 6),
+                     interactions=int(s.interactions))
+
+
+class _ListsOwner:
+    """Holds a library list allocation until every array viewing it is gone."""
+
+    def __init__(self, ptr):
+        self.ptr = ptr
+
+    def __del__(self):
+        if _lib is not None and self.ptr is not None:
+            _lib.otoo_lists_free(self.ptr)
+            self.ptr = None
+
+
+def _view(ptr, ctype, count, owner, dtype):
+    if count == 0:
+        return np.zeros(0, dtype)
+    buf = (ctype * count).from_address(ctypes.cast(ptr, ctypes.c_void_p).value)
+    buf._owner = owner
+    return np.frombuffer(buf, dtype=dtype)
 
 
 # ------------------------------------------------------------------ device

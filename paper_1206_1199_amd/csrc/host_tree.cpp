@@ -27,6 +27,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <memory>
 #include <vector>
 
 namespace {
@@ -97,7 +98,8 @@ struct otoo_tree {
 
 struct otoo_lists_impl {
     otoo_lists pub;
-    std::vector<int32_t> group_off, list_idx, n_cellent;
+    std::vector<int32_t> group_off, n_cellent;
+    std::unique_ptr<int32_t[]> list_idx;
     std::vector<int64_t> list_off;
     std::vector<float> group_box;  // [G][6] lo xyz, hi xyz (FP32, rounded outward is not needed: informative)
 };
@@ -162,13 +164,45 @@ std::vector<int64_t> make_groups(const otoo_tree* t, int mode, int G) {
     return goff;
 }
 
-// The stackless next/more walk of every group.  decide(c, d_min, g) says
-// what to do with cell c, where d_min is the distance from the cell's COM to
-// the group's bounding box: open it, accept it as one entry, or skip it.
-// Particles reached are always listed.  Lists hold the accepted cells, then
-// the particles, each part in walk (ascending) order.
+// Per-cell record of the walk, packed into one cache line: COM, two radii
+// for the opening criterion, the next/more links and the particle range.
+struct alignas(64) WalkCell {
+    double com[3];
+    double ra, rb;     // criterion radii (meaning set by the caller)
+    int64_t next, more;
+    int64_t first;     // first particle (key order)
+    int32_t count;     // particles in the cell
+    int32_t leaf;      // no children
+};
+
+std::vector<WalkCell> walk_cells(const otoo_tree* t) {
+    const int64_t n = t->n, nc = t->n_cells();
+    std::vector<WalkCell> w(nc);
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; c++) {
+        WalkCell& x = w[c];
+        for (int k = 0; k < 3; k++) x.com[k] = t->com[3 * c + k];
+        x.ra = x.rb = 0.0;
+        x.next = t->next[n + c];
+        x.more = t->more[n + c];
+        x.first = t->first[c];
+        x.count = (int32_t)t->count[c];
+        x.leaf = t->nchild[c] == 0;
+    }
+    return w;
+}
+
+// The stackless next/more walk of every group.  decide(cell, d_min, g) says
+// what to do with a cell, where d_min is the distance from the cell's COM to
+// the group's bounding box: open it, accept it as one entry, or skip it.  An
+// opened leaf contributes its particles (a contiguous key range, the same
+// entries its more/next chain visits) without visiting them one by one.
+// Lists hold the accepted cells, then the particles, each part in walk
+// (ascending) order.  Threads take groups in chunks of 8; each keeps its
+// lists in its own buffer until they are gathered into one CSR.
 template <class Decide>
-void walk_groups(const otoo_tree* t, const std::vector<int64_t>& goff, Decide decide, otoo_lists_impl* L) {
+void walk_groups(const otoo_tree* t, const std::vector<int64_t>& goff, const std::vector<WalkCell>& cells,
+                 Decide decide, otoo_lists_impl* L) {
     const int64_t n = t->n;
     const int64_t ng = (int64_t)goff.size() - 1;
     const int nth = omp_get_max_threads();
@@ -179,7 +213,7 @@ void walk_groups(const otoo_tree* t, const std::vector<int64_t>& goff, Decide de
     {
         const int tid = omp_get_thread_num();
         std::vector<int32_t>& B = buf[tid];
-        std::vector<int32_t> parts;
+        std::vector<int32_t> cellv, partv;
 #pragma omp for schedule(dynamic, 8)
         for (int64_t g = 0; g < ng; g++) {
             double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -192,35 +226,34 @@ void walk_groups(const otoo_tree* t, const std::vector<int64_t>& goff, Decide de
                 L->group_box[6 * g + k] = (float)lo[k];
                 L->group_box[6 * g + 3 + k] = (float)hi[k];
             }
-            const size_t start = B.size();
-            parts.clear();
+            cellv.clear();
+            partv.clear();
             int64_t u = n;  // root cell
             while (u >= 0) {
-                if (u < n) {
-                    parts.push_back((int32_t)u);
+                if (u < n) {   // a particle reached through a link (not taken when leaves are expanded whole)
+                    partv.push_back((int32_t)u);
                     u = t->next[u];
                     continue;
                 }
-                const int64_t c = u - n;
-                const double* cm = &t->com[3 * c];
+                const WalkCell& c = cells[u - n];
                 double d2 = 0;
                 for (int k = 0; k < 3; k++) {
-                    const double dk = std::max(0.0, std::max(lo[k] - cm[k], cm[k] - hi[k]));
+                    const double dk = std::max(0.0, std::max(lo[k] - c.com[k], c.com[k] - hi[k]));
                     d2 += dk * dk;
                 }
                 const int act = decide(c, std::sqrt(d2), g);
-                if (act == kOpen) {
-                    u = t->more[u];
-                } else {
-                    if (act == kAccept) B.push_back((int32_t)u);
-                    u = t->next[u];
-                }
+                const bool open = act == kOpen;
+                if (open && c.leaf)
+                    for (int32_t k = 0; k < c.count; k++) partv.push_back((int32_t)(c.first + k));
+                if (act == kAccept) cellv.push_back((int32_t)u);
+                u = (open && !c.leaf) ? c.more : c.next;
             }
             g_thread[g] = tid;
-            g_start[g] = (int64_t)start;
-            g_ncell[g] = (int64_t)(B.size() - start);
-            B.insert(B.end(), parts.begin(), parts.end());
-            g_len[g] = (int64_t)(B.size() - start);
+            g_start[g] = (int64_t)B.size();
+            g_ncell[g] = (int64_t)cellv.size();
+            B.insert(B.end(), cellv.begin(), cellv.end());
+            B.insert(B.end(), partv.begin(), partv.end());
+            g_len[g] = (int64_t)B.size() - g_start[g];
         }
     }
     L->group_off.resize(ng + 1);
@@ -236,7 +269,7 @@ void walk_groups(const otoo_tree* t, const std::vector<int64_t>& goff, Decide de
     }
     L->group_off[ng] = (int32_t)goff[ng];
     L->list_off[ng] = tot;
-    L->list_idx.resize(tot);
+    L->list_idx.reset(new int32_t[tot > 0 ? tot : 1]);   // every entry is written below
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t g = 0; g < ng; g++)
         std::memcpy(&L->list_idx[L->list_off[g]], &buf[g_thread[g]][g_start[g]], sizeof(int32_t) * g_len[g]);
@@ -245,7 +278,7 @@ void walk_groups(const otoo_tree* t, const std::vector<int64_t>& goff, Decide de
     L->pub.interactions = inter;
     L->pub.group_off = L->group_off.data();
     L->pub.list_off = L->list_off.data();
-    L->pub.list_idx = L->list_idx.data();
+    L->pub.list_idx = L->list_idx.get();
     L->pub.n_cellent = L->n_cellent.data();
     L->pub.group_box = L->group_box.data();
     L->pub.impl = L;
@@ -573,21 +606,23 @@ int otoo_tree_walk_range(const otoo_tree* t, const otoo_walk_params* wp, int32_t
         }
         const int64_t g1 = std::min<int64_t>(g_end, ng_all);
         goff = std::vector<int64_t>(goff.begin() + g_begin, goff.begin() + g1 + 1);
-        // acceptance radius per cell: accept iff d_min > rc
-        std::vector<double> rc(nc);
+        // acceptance radius per cell (ra): accept iff d_min > ra
+        std::vector<WalkCell> cells = walk_cells(t);
         for (int64_t c = 0; c < nc; c++) {
+            double& rc = cells[c].ra;
             if (wp->mac == OTOO_MAC_BH) {
-                rc[c] = wp->theta > 0.0 ? t->csize[c] / wp->theta + t->s[c] : INFINITY;
+                rc = wp->theta > 0.0 ? t->csize[c] / wp->theta + t->s[c] : INFINITY;
             } else {
                 if (t->M[c] > wp->m_limit) {
-                    rc[c] = 2.0 * t->side;
+                    rc = 2.0 * t->side;
                 } else {
                     const double b = t->bmax[c], B2 = t->S6[6 * c] + t->S6[6 * c + 1] + t->S6[6 * c + 2];
-                    rc[c] = b / 2.0 + std::sqrt(b * b / 4.0 + std::sqrt(3.0 * B2 / wp->delta));
+                    rc = b / 2.0 + std::sqrt(b * b / 4.0 + std::sqrt(3.0 * B2 / wp->delta));
                 }
             }
         }
-        walk_groups(t, goff, [&](int64_t c, double dmin, int64_t) { return dmin > rc[c] ? kAccept : kOpen; }, L);
+        walk_groups(t, goff, cells, [](const WalkCell& w, double dmin, int64_t) { return dmin > w.ra ? kAccept : kOpen; },
+                    L);
     } catch (const std::bad_alloc&) {
         delete L;
         return OTOO_ENOMEM;
@@ -608,9 +643,10 @@ int otoo_tree_walk_sph(const otoo_tree* t, const double* h, int32_t group_mode, 
     try {
         std::vector<double> hk(n);
         for (int64_t p = 0; p < n; p++) hk[p] = h[t->perm[p]];
-        // per cell: extent R_c = max |COM_c - x_j| and the SPH bounding radius
-        // r_SPH = max (|COM_c - x_j| + h_j) of Eq. 5, over the cell's particles
-        std::vector<double> R(nc), rs(nc);
+        // per cell: extent R_c = max |COM_c - x_j| (rb) and the SPH bounding
+        // radius r_SPH = max (|COM_c - x_j| + h_j) of Eq. 5 (ra), over the
+        // cell's particles
+        std::vector<WalkCell> cells = walk_cells(t);
 #pragma omp parallel for schedule(dynamic, 64)
         for (int64_t c = 0; c < nc; c++) {
             const double* cm = &t->com[3 * c];
@@ -625,8 +661,8 @@ int otoo_tree_walk_sph(const otoo_tree* t, const double* h, int32_t group_mode, 
                 r_max = std::max(r_max, d);
                 rs_max = std::max(rs_max, d + hk[p]);
             }
-            R[c] = r_max;
-            rs[c] = rs_max;
+            cells[c].rb = r_max;
+            cells[c].ra = rs_max;
         }
         const std::vector<int64_t> goff = make_groups(t, group_mode, g_max);
         const int64_t ng = (int64_t)goff.size() - 1;
@@ -639,8 +675,8 @@ int otoo_tree_walk_sph(const otoo_tree* t, const double* h, int32_t group_mode, 
         // a cell can hold a neighbour of a group particle only if the group's
         // box comes within r_SPH of its COM (the source's support) or within
         // R_c + max_g h (the target's support); otherwise it is skipped whole
-        walk_groups(t, goff, [&](int64_t c, double dmin, int64_t g) {
-            return dmin >= std::max(rs[c], R[c] + hg[g]) ? kSkip : kOpen;
+        walk_groups(t, goff, cells, [&](const WalkCell& w, double dmin, int64_t g) {
+            return dmin >= std::max(w.ra, w.rb + hg[g]) ? kSkip : kOpen;
         }, L);
     } catch (const std::bad_alloc&) {
         delete L;
