@@ -306,3 +306,39 @@ def test_fused_learned_correction_matches_oracle(env, net_kernel, gate):
           f"pot median {np.median(ep):.2e}", flush=True)
     assert np.median(ea) <= 2e-5 and np.quantile(ea, 0.99) <= 2e-4
     assert np.median(ep) <= 2e-5
+
+
+@pytest.mark.parametrize("gate", [0.0, 0.3])
+def test_queue_rounds_on_long_lists(env, gate):
+    """Groups of 256 at theta 0.5 hold thousands of cells, so the register-
+    resident kernel's queue of gated pairs runs many rounds and carries a
+    remainder between them.  Its per-group expansion must match the
+    LDS-staged kernel's, which runs every pair through the layers in order
+    (the gate applied afterwards) with no queue."""
+    ctx, net = env["ctx"], env["net"]
+    net.set_params(env["params"])
+    pos, m = synth.plummer(1 << 17, seed=41)
+    tree = otoo.Tree(pos, m, n_crit=16)
+    lists = tree.walk(theta=0.5, g_max=256)
+    d, _, _ = learned.device_tree_arrays(tree, lists)
+    cells_per_group = np.diff(lists.pair_off)
+    print(f"cells per group: median {np.median(cells_per_group):.0f}, max {cells_per_group.max()}", flush=True)
+    assert np.median(cells_per_group) > 2048
+    old = ctx.tuning()
+    out = {}
+    net.set_gate(gate)
+    try:
+        for k in (0, 1):
+            ctx.set_tuning(net_kernel=k)
+            out[k] = ctx.correction(d, otoo.CORR_MLP, EPS, net=net).cpu().numpy().astype(np.float64)
+    finally:
+        net.set_gate(0.0)
+        ctx.set_tuning(chunk=old.chunk, blocks_per_cu=old.blocks_per_cu, lpt=old.lpt, tile=old.tile,
+                       net_kernel=old.net_kernel)
+    ctx.check()
+    a0, a1 = out[0][:, :20], out[1][:, :20]
+    scale = np.abs(a1).max(axis=0) + 1e-30
+    err = (np.abs(a0 - a1) / scale).max()
+    print(f"gate {gate}: max difference {err:.2e} of each term's largest magnitude", flush=True)
+    assert err <= 1e-4
+    np.testing.assert_array_equal(out[0][:, 20:23], out[1][:, 20:23])     # group centres
