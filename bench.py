@@ -138,15 +138,10 @@ def rel_err(a, ref):
 # ------------------------------------------------------------------ learned comparison
 
 
-def learned_comparison(ctx, log, steps, train_steps, timing_reps, gate=0.4):
-    """Train the correction network on the GPU and compare, on a held-out
-    Plummer sphere (N = 2^20, seed 3, eps 0.005), plain theta = 0.5, plain at
-    the largest theta with median error <= 1e-3, the textbook quadrupole and
-    the learned correction (layers gated to pairs with l/n >= gate), all
-    timed per force evaluation with the best of a few schedules per setting."""
+def train_network(ctx, log, train_steps, gate=0.4):
+    """Train the correction network on the GPU on samples of seeded Plummer
+    walks (layers gated to pairs with l/n >= gate); returns (net, summary)."""
     import torch
-    import synth
-    import paper_1206_1199_amd as otoo
     from paper_1206_1199_amd import learned
     eps = 0.005
     net = learned.Network(ctx)
@@ -168,14 +163,68 @@ def learned_comparison(ctx, log, steps, train_steps, timing_reps, gate=0.4):
     quad_val = learned.evaluate_loss(net, Xv, auxv, epsv)
     net.set_params(learned.init_params(0))
     t0 = time.perf_counter()
-    hist = learned.fit(net, X, aux, eps_all, steps=train_steps, batch=32768, lr=2e-3, seed=0, X_val=Xv,
-                       aux_val=auxv, eps_val=epsv, log=log, log_every=max(1, train_steps // 5))
+    learned.fit(net, X, aux, eps_all, steps=train_steps, batch=32768, lr=2e-3, seed=0, X_val=Xv, aux_val=auxv,
+                eps_val=epsv, log=log, log_every=max(1, train_steps // 5))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     val = learned.evaluate_loss(net, Xv, auxv, epsv)
     log(f"learned: {X.shape[0]} samples (gate {gate}) in {t_data:.1f} s, {train_steps} steps in {t_train:.1f} s, "
         f"validation loss {val:.3e} (plain monopole {base_val:.3e}, textbook quadrupole {quad_val:.3e})")
+    return net, {"gate": gate, "samples": int(X.shape[0]), "steps": train_steps, "data_s": t_data,
+                 "train_s": t_train, "val_loss": val, "val_loss_plain_monopole": base_val,
+                 "val_loss_textbook_quadrupole": quad_val}
 
+
+def workload_learned(ctx, net, training, log, lists, tree, eps, sample, a_dir, reps):
+    """Plain, textbook-quadrupole and learned force on the benchmark workload
+    itself (its theta and schedule), each step (correction + force) captured
+    in one graph and replayed; error against the direct sums of the sample."""
+    import torch
+    import paper_1206_1199_amd as otoo
+    from paper_1206_1199_amd import learned
+    d, _, _ = learned.device_tree_arrays(tree, lists)
+    out = ctx.outputs(d.n)
+    gc = torch.empty((d.n_groups, otoo.CORR_STRIDE), dtype=torch.float32, device="cuda:0")
+    rows = []
+    for mode in ("plain", "quad", "learned"):
+        def step():
+            if mode == "learned":
+                ctx.correction(d, otoo.CORR_MLP, eps, net=net, out=gc)
+                ctx.force(d, eps, out=out, gcorr=gc)
+            elif mode == "quad":
+                ctx.correction(d, otoo.CORR_QUAD, eps, out=gc)
+                ctx.force(d, eps, out=out, gcorr=gc)
+            else:
+                ctx.force(d, eps, out=out)
+        g = ctx.capture(step)
+        g.replay()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ctx.check()
+        err = rel_err(out[0].cpu().numpy()[sample], a_dir)
+        rows.append(dict(mode=mode, ms=e0.elapsed_time(e1) / reps, pairs=d.n_pairs, median_err=float(np.median(err)),
+                         p99_err=float(np.quantile(err, 0.99))))
+        log(f"  {mode:8s} (graph replay): {rows[-1]['ms']:.3f} ms, median err {rows[-1]['median_err']:.2e}")
+    return {"training": training, "rows": rows}
+
+
+def learned_comparison(ctx, net, training, log, timing_reps):
+    """Compare, on a held-out Plummer sphere (N = 2^20, seed 3, eps 0.005),
+    plain theta = 0.5, plain at the largest theta with median error <= 1e-3,
+    the textbook quadrupole and the learned correction, all timed per force
+    evaluation with the best of a few schedules per setting."""
+    import torch
+    import synth
+    import paper_1206_1199_amd as otoo
+    from paper_1206_1199_amd import learned
+    eps = 0.005
+    gate = training["gate"]
     pos, m = synth.plummer(1 << 20, seed=3)
     tree = otoo.Tree(pos, m, n_crit=16)
     perm, pos32, mass32, cm = tree.export(12)
@@ -245,10 +294,7 @@ def learned_comparison(ctx, log, steps, train_steps, timing_reps, gate=0.4):
     best = {mode: (min(ok(mode), key=lambda r: r["ms"]) if ok(mode) else None) for mode in ("plain", "quad", "learned")}
     plain05 = min((r for r in rows if r["mode"] == "plain" and r["theta"] == 0.5), key=lambda r: r["ms"])
     res = {"workload": "Plummer N=1048576 seed=3 eps=0.005 (held out), error vs direct sum on 4096 particles",
-           "gate": gate,
-           "training": {"samples": int(X.shape[0]), "steps": train_steps, "data_s": t_data, "train_s": t_train,
-                        "val_loss": val, "val_loss_plain_monopole": base_val, "val_loss_textbook_quadrupole": quad_val},
-           "plain_theta_0.5": plain05, "best_at_1e-3": best, "rows": rows}
+           "gate": gate, "training": training, "plain_theta_0.5": plain05, "best_at_1e-3": best, "rows": rows}
     if best["learned"]:
         res["learned_speedup_vs_plain_theta_0.5"] = plain05["ms"] / best["learned"]["ms"]
         if best["plain"]:
@@ -427,8 +473,12 @@ def main():
     log(f"accuracy {res['accuracy']}")
     if not args.no_learned:
         try:
-            res["learned"] = learned_comparison(ctx, log, args.steps, args.train_steps, max(5, min(args.steps, 20)),
-                                                gate=args.gate)
+            net, training = train_network(ctx, log, args.train_steps, gate=args.gate)
+            reps = max(5, min(args.steps, 20))
+            if args.workload == "plummer1m":
+                res["learned"] = learned_comparison(ctx, net, training, log, reps)
+            else:
+                res["learned"] = workload_learned(ctx, net, training, log, lists, tree, eps, sample, a_dir, reps)
         except Exception as e:  # the headline measurement stands on its own
             res["learned"] = {"error": f"{type(e).__name__}: {e}"}
             log(f"learned comparison failed: {e}")

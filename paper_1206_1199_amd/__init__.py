@@ -387,6 +387,23 @@ class Context:
                 _tptr(d.list_off), _tptr(d.list_idx), d.n_cells, _tptr(d.cell_mom) if d.n_cells else None,
                 stride, float(eps), _tptr(gcorr), _tptr(out_acc), _tptr(out_pot))
 
+    def capture(self, fn):
+        """A torch CUDA graph of fn() (calls on this context, with preallocated
+        outputs).  fn runs once eagerly first, so that every scratch buffer is
+        allocated outside the capture; the context follows the capture stream
+        and returns to the current stream afterwards."""
+        import torch
+        fn()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        try:
+            with torch.cuda.graph(g):
+                self.sync_stream()
+                fn()
+        finally:
+            self.sync_stream()
+        return g
+
     def outputs(self, n):
         import torch
         return (torch.empty((n, 3), dtype=torch.float32, device=f"cuda:{self.device}"),

@@ -342,3 +342,35 @@ def test_queue_rounds_on_long_lists(env, gate):
     print(f"gate {gate}: max difference {err:.2e} of each term's largest magnitude", flush=True)
     assert err <= 1e-4
     np.testing.assert_array_equal(out[0][:, 20:23], out[1][:, 20:23])     # group centres
+
+
+def test_captured_correction_and_force_replay_matches_eager(env):
+    """The learned correction and the force captured together in one graph (a
+    per-step force launch) give bitwise the eager results on every replay,
+    with eager work on the same stream between replays."""
+    ctx, net, d = env["ctx"], env["net"], env["d"]
+    net.set_params(env["params"])
+    net.set_gate(0.4)
+    try:
+        gc = torch.empty((d.n_groups, otoo.CORR_STRIDE), dtype=torch.float32, device="cuda:0")
+        out = ctx.outputs(d.n)
+
+        def step():
+            ctx.correction(d, otoo.CORR_MLP, EPS, net=net, out=gc)
+            ctx.force(d, EPS, out=out, gcorr=gc)
+
+        step()
+        torch.cuda.synchronize()
+        ref = (out[0].clone(), out[1].clone())
+        g = ctx.capture(step)
+        for rep in range(3):
+            out[0].zero_()
+            out[1].zero_()
+            gc.zero_()
+            ctx.force(d, EPS)                    # eager work between replays
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1]), f"replay {rep}"
+        ctx.check()
+    finally:
+        net.set_gate(0.0)
