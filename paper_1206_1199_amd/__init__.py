@@ -293,6 +293,7 @@ class DeviceLists:
     pair_off: "object"   # int64 [G+1]: prefix sums of the groups' cell counts
     n_entries: int
     interactions: int
+    pair_count: int = -1   # pair_off[-1] known on the host (-1: read it from the device)
 
     @property
     def n(self):
@@ -308,7 +309,8 @@ class DeviceLists:
 
     @property
     def n_pairs(self):
-        return int(self.pair_off[-1].item())
+        # a host copy avoids a device read, which is not allowed inside a graph capture
+        return self.pair_count if self.pair_count >= 0 else int(self.pair_off[-1].item())
 
     @classmethod
     def from_host(cls, pos32, mass32, lists: Lists, cell_mom, device="cuda:0"):
@@ -319,7 +321,7 @@ class DeviceLists:
                    list_off=t(lists.list_off, np.int64),
                    list_idx=t(lists.list_idx if lists.n_entries else np.zeros(1, np.int32), np.int32),
                    cell_mom=t(cm, np.float32)[:len(cell_mom)], pair_off=t(lists.pair_off, np.int64),
-                   n_entries=lists.n_entries, interactions=lists.interactions)
+                   n_entries=lists.n_entries, interactions=lists.interactions, pair_count=int(lists.pair_off[-1]))
 
 
 def _lists_on_device(cls, pos, mass, cell_mom, lists: Lists):
@@ -331,7 +333,7 @@ def _lists_on_device(cls, pos, mass, cell_mom, lists: Lists):
     return cls(pos=pos, mass=mass, group_off=t(lists.group_off, np.int32), list_off=t(lists.list_off, np.int64),
                list_idx=t(lists.list_idx if lists.n_entries else np.zeros(1, np.int32), np.int32),
                cell_mom=cell_mom, pair_off=t(lists.pair_off, np.int64), n_entries=lists.n_entries,
-               interactions=lists.interactions)
+               interactions=lists.interactions, pair_count=int(lists.pair_off[-1]))
 
 
 DeviceLists.on_device = classmethod(_lists_on_device)
