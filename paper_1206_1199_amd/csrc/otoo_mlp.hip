@@ -406,13 +406,13 @@ struct CorrArgs {
     int32_t* err;
 };
 
-// One workgroup per group (grid-stride over groups): the centre c_g of the
-// group's bounding box, then the tensor of every (group, cell) pair -- given
-// (kCorrPairs), the textbook quadrupole 3S - tr(S) I (kCorrQuad) or the
-// network's prediction (kCorrMlp, 64 pairs at a time on MFMA) -- and its
-// quadrupole-form field, Jacobian, Hessian and potential at c_g, summed in a
-// fixed order into the group's local expansion.  No per-pair tensor touches
-// HBM.
+// The network through LDS, one workgroup per group (grid-stride over
+// groups): the centre c_g of the group's bounding box, then the network's
+// tensor for 128 (group, cell) pairs at a time on MFMA with the activations
+// staged in LDS, and each pair's quadrupole-form field, Jacobian, Hessian
+// and potential at c_g, summed in a fixed order into the group's local
+// expansion.  No per-pair tensor touches HBM.  (The register-resident
+// k_corr_net below is the default; this one is the reference variant.)
 constexpr int kCorrRows = 128;   // pairs per chunk in the network variant (2 row tiles per wave)
 
 // LDS of the network variant: the features (X) and hidden activations (H)
@@ -427,22 +427,20 @@ union CorrScratch {
     float red[kCorrTerms][256];
 };
 
-template <int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_corr_group(CorrArgs a) {
-    constexpr bool NET = KIND == kCorrMlp;
     __shared__ NetLDS net;
     __shared__ CorrScratch scr;
     __shared__ float sScale[kCorrRows];
     __shared__ int sCell[kCorrRows];
-    __shared__ float sSkip[NET ? kCorrRows * NOUT : 1];   // skip term of each row; the layers' part is
-    __shared__ int sOn[NET ? kCorrRows : 1];              // kept only for rows the gate lets through
+    __shared__ float sSkip[kCorrRows * NOUT];   // skip term of each row; the layers' part is
+    __shared__ int sOn[kCorrRows];              // kept only for rows the gate lets through
     uint16_t* sX = scr.net.x;
     uint16_t* sH = scr.net.h;
     float* sO = scr.o;
     auto& red = scr.red;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, r16 = lane & 15, q = lane >> 4;
     const float eps2 = a.eps * a.eps;
-    if (NET) load_net(net, a.wbf, a.master);
+    load_net(net, a.wbf, a.master);
     for (int g = blockIdx.x; g < a.n_groups; g += gridDim.x) {
         const int g0 = a.group_off[g];
         const int ng = a.group_off[g + 1] - g0;
@@ -482,111 +480,86 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         } else if (t == 0) {
             atomicOr(a.err, kErrGroup);
         }
-        if (!NET) {
-            for (int64_t k = t; k < nce; k += 256) {
-                const int64_t c = (int64_t)a.list_idx[lb + k] - a.n;
-                if (c < 0 || c >= a.n_cells) {
-                    atomicOr(a.err, kErrIndex);
-                    continue;
-                }
-                const float* cm = a.cell_mom + (int64_t)a.stride * c;
-                float Q[6];
-                if (KIND == kCorrPairs) {
-                    for (int m = 0; m < 6; m++) Q[m] = a.corr[6 * (p0 + k) + m];
-                } else {
-                    const float* S = cm + 5;
-                    const float tr = S[0] + S[1] + S[2];
-                    Q[0] = 3.f * S[0] - tr;
-                    Q[1] = 3.f * S[1] - tr;
-                    Q[2] = 3.f * S[2] - tr;
-                    Q[3] = 3.f * S[3];
-                    Q[4] = 3.f * S[4];
-                    Q[5] = 3.f * S[5];
-                }
-                quad_expand_add(cx - cm[0], cy - cm[1], cz - cm[2], Q, eps2, f);
-            }
-        } else {
-            for (int64_t base = 0; base < nce; base += kCorrRows) {
-                if (t >= kCorrRows) {  // zero the padding columns (X shares its space with O and the reductions)
-                    const int row = t - kCorrRows;
-                    for (int j = NFEAT; j < NIN; j++) sX[row * NIN + j] = 0;
-                } else {               // features: one thread per row
-                    const int64_t k = base + t;
-                    float fe[NFEAT];
-                    float sc = 0.f;
-                    bool fok = false;
-                    int64_t c = -1;
-                    if (k < nce) {
-                        c = (int64_t)a.list_idx[lb + k] - a.n;
-                        if (c >= 0 && c < a.n_cells) {
-                            fok = pair_features(cx, cy, cz, h, a.cell_mom + 12 * c, a.eps, fe, sc);
-                        } else {
-                            atomicOr(a.err, kErrIndex);
-                            c = -1;
-                        }
-                    }
-#pragma unroll
-                    for (int j = 0; j < NFEAT; j++) sX[t * NIN + j] = f2bf(fok ? fe[j] : 0.f);
-#pragma unroll
-                    for (int m = 0; m < NOUT; m++) sSkip[t * NOUT + m] = fok ? 3.f * bf_round(fe[kSkip0 + m]) : 0.f;
-                    sOn[t] = fok && bf_round(fe[3]) >= a.gate;
-                    sScale[t] = fok ? sc : 0.f;
-                    sCell[t] = (int)c;
-                }
-                __syncthreads();
-                floatx4 acc[4];
-#pragma unroll
-                for (int mt = 0; mt < 2; mt++) {
-                    const int r0 = 32 * w + 16 * mt;
-                    wave_dense<1, 4>(sX, NIN, net.w1t, NIN, net.b1, r0, acc);
-#pragma unroll
-                    for (int nt = 0; nt < 4; nt++)
-#pragma unroll
-                        for (int i = 0; i < 4; i++)
-                            sH[(r0 + q * 4 + i) * NH + nt * 16 + r16] = f2bf(gelu(acc[nt][i]));
-                }
-                __syncthreads();
-                floatx4 acc2[2][4];
-#pragma unroll
-                for (int mt = 0; mt < 2; mt++) wave_dense<2, 4>(sH, NH, net.w2t, NH, net.b2, 32 * w + 16 * mt, acc2[mt]);
-                __syncthreads();
-#pragma unroll
-                for (int mt = 0; mt < 2; mt++) {
-                    const int r0 = 32 * w + 16 * mt;
-#pragma unroll
-                    for (int nt = 0; nt < 4; nt++)
-#pragma unroll
-                        for (int i = 0; i < 4; i++)
-                            sH[(r0 + q * 4 + i) * NH + nt * 16 + r16] = f2bf(gelu(acc2[mt][nt][i]));
-                }
-                __syncthreads();
-#pragma unroll
-                for (int mt = 0; mt < 2; mt++) {
-                    const int r0 = 32 * w + 16 * mt;
-                    floatx4 o[1];
-                    wave_dense<2, 1>(sH, NH, net.w3t, NH, net.b3, r0, o);
-#pragma unroll
-                    for (int i = 0; i < 4; i++) sO[(r0 + q * 4 + i) * NOUTP + r16] = o[0][i];
-                }
-                __syncthreads();
-                {   // two threads per row share the expansion: {a, phi, J} and H
-                    const int row = t >> 1, part = t & 1;
-                    if (base + row < nce && sCell[row] >= 0 && sScale[row] > 0.f) {
-                        const float* on = sO + row * NOUTP;
-                        const bool lay = sOn[row] != 0;
-                        float ov[NOUT];
-#pragma unroll
-                        for (int m = 0; m < NOUT; m++) ov[m] = (lay ? on[m] : 0.f) + sSkip[row * NOUT + m];
-                        const float tr = (ov[0] + ov[1] + ov[2]) * (1.f / 3.f);
-                        const float sc = sScale[row];
-                        const float Q[6] = {(ov[0] - tr) * sc, (ov[1] - tr) * sc, (ov[2] - tr) * sc,
-                                            ov[3] * sc,        ov[4] * sc,        ov[5] * sc};
-                        const float* cm = a.cell_mom + 12 * (int64_t)sCell[row];
-                        quad_expand_add_part(part, cx - cm[0], cy - cm[1], cz - cm[2], Q, eps2, f);
+        for (int64_t base = 0; base < nce; base += kCorrRows) {
+            if (t >= kCorrRows) {  // zero the padding columns (X shares its space with O and the reductions)
+                const int row = t - kCorrRows;
+                for (int j = NFEAT; j < NIN; j++) sX[row * NIN + j] = 0;
+            } else {               // features: one thread per row
+                const int64_t k = base + t;
+                float fe[NFEAT];
+                float sc = 0.f;
+                bool fok = false;
+                int64_t c = -1;
+                if (k < nce) {
+                    c = (int64_t)a.list_idx[lb + k] - a.n;
+                    if (c >= 0 && c < a.n_cells) {
+                        fok = pair_features(cx, cy, cz, h, a.cell_mom + 12 * c, a.eps, fe, sc);
+                    } else {
+                        atomicOr(a.err, kErrIndex);
+                        c = -1;
                     }
                 }
-                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < NFEAT; j++) sX[t * NIN + j] = f2bf(fok ? fe[j] : 0.f);
+#pragma unroll
+                for (int m = 0; m < NOUT; m++) sSkip[t * NOUT + m] = fok ? 3.f * bf_round(fe[kSkip0 + m]) : 0.f;
+                sOn[t] = fok && bf_round(fe[3]) >= a.gate;
+                sScale[t] = fok ? sc : 0.f;
+                sCell[t] = (int)c;
             }
+            __syncthreads();
+            floatx4 acc[4];
+#pragma unroll
+            for (int mt = 0; mt < 2; mt++) {
+                const int r0 = 32 * w + 16 * mt;
+                wave_dense<1, 4>(sX, NIN, net.w1t, NIN, net.b1, r0, acc);
+#pragma unroll
+                for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+                    for (int i = 0; i < 4; i++)
+                        sH[(r0 + q * 4 + i) * NH + nt * 16 + r16] = f2bf(gelu(acc[nt][i]));
+            }
+            __syncthreads();
+            floatx4 acc2[2][4];
+#pragma unroll
+            for (int mt = 0; mt < 2; mt++) wave_dense<2, 4>(sH, NH, net.w2t, NH, net.b2, 32 * w + 16 * mt, acc2[mt]);
+            __syncthreads();
+#pragma unroll
+            for (int mt = 0; mt < 2; mt++) {
+                const int r0 = 32 * w + 16 * mt;
+#pragma unroll
+                for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+                    for (int i = 0; i < 4; i++)
+                        sH[(r0 + q * 4 + i) * NH + nt * 16 + r16] = f2bf(gelu(acc2[mt][nt][i]));
+            }
+            __syncthreads();
+#pragma unroll
+            for (int mt = 0; mt < 2; mt++) {
+                const int r0 = 32 * w + 16 * mt;
+                floatx4 o[1];
+                wave_dense<2, 1>(sH, NH, net.w3t, NH, net.b3, r0, o);
+#pragma unroll
+                for (int i = 0; i < 4; i++) sO[(r0 + q * 4 + i) * NOUTP + r16] = o[0][i];
+            }
+            __syncthreads();
+            {   // two threads per row share the expansion: {a, phi, J} and H
+                const int row = t >> 1, part = t & 1;
+                if (base + row < nce && sCell[row] >= 0 && sScale[row] > 0.f) {
+                    const float* on = sO + row * NOUTP;
+                    const bool lay = sOn[row] != 0;
+                    float ov[NOUT];
+#pragma unroll
+                    for (int m = 0; m < NOUT; m++) ov[m] = (lay ? on[m] : 0.f) + sSkip[row * NOUT + m];
+                    const float tr = (ov[0] + ov[1] + ov[2]) * (1.f / 3.f);
+                    const float sc = sScale[row];
+                    const float Q[6] = {(ov[0] - tr) * sc, (ov[1] - tr) * sc, (ov[2] - tr) * sc,
+                                        ov[3] * sc,        ov[4] * sc,        ov[5] * sc};
+                    const float* cm = a.cell_mom + 12 * (int64_t)sCell[row];
+                    quad_expand_add_part(part, cx - cm[0], cy - cm[1], cz - cm[2], Q, eps2, f);
+                }
+            }
+            __syncthreads();
         }
 #pragma unroll
         for (int k = 0; k < kCorrTerms; k++) red[k][t] = f[k];
@@ -642,19 +615,136 @@ __device__ __forceinline__ void expand_outputs(const float o[NOUT], float sc, fl
     quad_expand_add(dx, dy, dz, Q, eps2, f);
 }
 
-constexpr int kNetBuf = 512;   // gated pairs waiting for the network (two rounds of 4 waves x 64)
+// Wave-level reductions by butterfly (fixed order; lane 0's value is used).
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
 
-// Per group: every cell entry's features in a window of 256 (one per
-// thread); a pair the gate keeps out gets the skip term alone (the textbook
-// quadrupole) at once, a gated pair is appended to an LDS queue in a fixed
-// order (wave ballots, waves in order).  Whenever 256 are queued (or the
-// list is done) each wave runs the network on 64 of them.
+// Geometry of group g for one wave: centre and half-diagonal of the
+// bounding box of its particles; false for a malformed group.
+__device__ __forceinline__ bool wave_group_box(const CorrArgs& a, int g, int lane, float& cx, float& cy, float& cz,
+                                               float& h) {
+    const int g0 = a.group_off[g];
+    const int ng = a.group_off[g + 1] - g0;
+    const bool ok = ng >= 1 && ng <= kBlock && g0 >= 0 && g0 + ng <= a.n;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (ok)
+        for (int p = lane; p < ng; p += 64)
+            for (int k = 0; k < 3; k++) {
+                const float x = a.pos[3 * (g0 + p) + k];
+                lo[k] = fminf(lo[k], x);
+                hi[k] = fmaxf(hi[k], x);
+            }
+    for (int k = 0; k < 3; k++) {
+        lo[k] = __shfl(wave_min(lo[k]), 0);
+        hi[k] = __shfl(wave_max(hi[k]), 0);
+    }
+    cx = 0.5f * (lo[0] + hi[0]);
+    cy = 0.5f * (lo[1] + hi[1]);
+    cz = 0.5f * (lo[2] + hi[2]);
+    const float ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
+    h = 0.5f * sqrtf(ex * ex + ey * ey + ez * ez);
+    return ok;
+}
+
+// The group's cell-entry range [lb, lb + nce) of its list, nce = its pair count.
+__device__ __forceinline__ void group_pairs(const CorrArgs& a, int g, int64_t& lb, int64_t& p0, int64_t& nce) {
+    int64_t le;
+    list_range(a.list_off, a.n_entries, g, lb, le);
+    p0 = clamp64(a.pair_off[g], 0, a.n_pairs);
+    const int64_t p1 = clamp64(a.pair_off[g + 1], p0, a.n_pairs);
+    nce = (p1 - p0) < (le - lb) ? (p1 - p0) : (le - lb);
+}
+
+// Sum the lanes' expansion terms and write group g's row (lane 0).
+__device__ __forceinline__ void wave_store_expansion(const CorrArgs& a, int g, int lane, float f[kCorrTerms], float cx,
+                                                     float cy, float cz) {
+#pragma unroll
+    for (int k = 0; k < kCorrTerms; k++) f[k] = wave_sum(f[k]);
+    if (lane == 0) {
+        float* out = a.gcorr + (int64_t)kCorrStride * g;
+#pragma unroll
+        for (int k = 0; k < kCorrTerms; k++) out[k] = f[k];
+        out[kCorrTerms] = cx;
+        out[kCorrTerms + 1] = cy;
+        out[kCorrTerms + 2] = cz;
+        out[kCorrTerms + 3] = 0.f;
+    }
+}
+
+// Given or textbook tensors, one wave per group: no workgroup barrier; the
+// group's box and the expansion terms are reduced with lane shuffles.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_corr_wave(CorrArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int waves = blockDim.x >> 6;
+    const float eps2 = a.eps * a.eps;
+    for (int g = blockIdx.x * waves + (threadIdx.x >> 6); g < a.n_groups; g += gridDim.x * waves) {
+        float cx, cy, cz, h;
+        const bool ok = wave_group_box(a, g, lane, cx, cy, cz, h);
+        float f[kCorrTerms];
+#pragma unroll
+        for (int k = 0; k < kCorrTerms; k++) f[k] = 0.f;
+        if (ok) {
+            int64_t lb, p0, nce;
+            group_pairs(a, g, lb, p0, nce);
+            for (int64_t k = lane; k < nce; k += 64) {
+                const int64_t c = (int64_t)a.list_idx[lb + k] - a.n;
+                if (c < 0 || c >= a.n_cells) {
+                    atomicOr(a.err, kErrIndex);
+                    continue;
+                }
+                const float* cm = a.cell_mom + (int64_t)a.stride * c;
+                float Q[6];
+                if (KIND == kCorrPairs) {
+                    for (int m = 0; m < 6; m++) Q[m] = a.corr[6 * (p0 + k) + m];
+                } else {
+                    const float* S = cm + 5;
+                    const float tr = S[0] + S[1] + S[2];
+                    Q[0] = 3.f * S[0] - tr;
+                    Q[1] = 3.f * S[1] - tr;
+                    Q[2] = 3.f * S[2] - tr;
+                    Q[3] = 3.f * S[3];
+                    Q[4] = 3.f * S[4];
+                    Q[5] = 3.f * S[5];
+                }
+                quad_expand_add(cx - cm[0], cy - cm[1], cz - cm[2], Q, eps2, f);
+            }
+        } else if (lane == 0) {
+            atomicOr(a.err, kErrGroup);
+        }
+        wave_store_expansion(a, g, lane, f, cx, cy, cz);
+    }
+}
+
+// Register-resident network, one wave per group.  The wave walks its
+// group's cell entries 64 at a time: a pair the gate keeps out gets the skip
+// term alone (the textbook quadrupole) at once; a gated pair is appended to
+// the wave's LDS queue (ballot order).  Whenever 64 are queued, and once at
+// the end of the group, the wave runs the network on them: weights are the
+// MFMA's A operand, held in registers for the whole kernel; the 64 pairs are
+// the N dimension in four steps of 16, and each layer's output layout is
+// the next layer's B layout once the K index is permuted (K slot q*8 + j of
+// step ks holds hidden unit (2 ks + j/4)*16 + q*4 + j%4).  No workgroup
+// barrier after the weights are loaded.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_corr_net(CorrArgs a) {
+    constexpr int kQueue = 128;
     __shared__ float sb[NH + NH + NOUTP];
-    __shared__ float red[kCorrTerms][256];
-    __shared__ int32_t sPend[kNetBuf];
-    __shared__ int sWave[4];
+    __shared__ int32_t sPend[4][kQueue];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, r16 = lane & 15, q = lane >> 4;
+    int32_t* pendq = sPend[w];
     const float eps2 = a.eps * a.eps;
     for (int i = t; i < NH; i += 256) {
         sb[i] = a.master[OFF_B1 + i];
@@ -671,170 +761,121 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
     for (int ks = 0; ks < 2; ks++) w3a[ks] = ld_perm(a.wbf + OFFB_W3T, NH, r16, ks, q);
     __syncthreads();
-    for (int g = blockIdx.x; g < a.n_groups; g += gridDim.x) {
-        const int g0 = a.group_off[g];
-        const int ng = a.group_off[g + 1] - g0;
-        const bool gok = ng >= 1 && ng <= kBlock && g0 >= 0 && g0 + ng <= a.n;
-        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-        if (gok && t < ng)
-            for (int k = 0; k < 3; k++) lo[k] = hi[k] = a.pos[3 * (g0 + t) + k];
-        __syncthreads();
-        for (int k = 0; k < 3; k++) {
-            red[k][t] = lo[k];
-            red[3 + k][t] = hi[k];
-        }
-        __syncthreads();
-        for (int s2 = 128; s2 > 0; s2 >>= 1) {
-            if (t < s2)
-                for (int k = 0; k < 3; k++) {
-                    red[k][t] = fminf(red[k][t], red[k][t + s2]);
-                    red[3 + k][t] = fmaxf(red[3 + k][t], red[3 + k][t + s2]);
-                }
-            __syncthreads();
-        }
-        const float cx = 0.5f * (red[0][0] + red[3][0]);
-        const float cy = 0.5f * (red[1][0] + red[4][0]);
-        const float cz = 0.5f * (red[2][0] + red[5][0]);
-        const float ex = red[3][0] - red[0][0], ey = red[4][0] - red[1][0], ez = red[5][0] - red[2][0];
-        const float h = 0.5f * sqrtf(ex * ex + ey * ey + ez * ez);
+    for (int g = blockIdx.x * 4 + w; g < a.n_groups; g += gridDim.x * 4) {
+        float cx, cy, cz, h;
+        const bool ok = wave_group_box(a, g, lane, cx, cy, cz, h);
         float f[kCorrTerms];
 #pragma unroll
         for (int k = 0; k < kCorrTerms; k++) f[k] = 0.f;
-        int64_t lb = 0, le = 0, p0 = 0, nce = 0;
-        if (gok) {
-            list_range(a.list_off, a.n_entries, g, lb, le);
-            p0 = clamp64(a.pair_off[g], 0, a.n_pairs);
-            const int64_t p1 = clamp64(a.pair_off[g + 1], p0, a.n_pairs);
-            nce = (p1 - p0) < (le - lb) ? (p1 - p0) : (le - lb);
+        int64_t lb = 0, p0 = 0, nce = 0;
+        if (ok) {
+            group_pairs(a, g, lb, p0, nce);
             if (nce > INT32_MAX) {   // queue slots hold 32-bit list positions
                 nce = INT32_MAX;
-                if (t == 0) atomicOr(a.err, kErrCapacity);
+                if (lane == 0) atomicOr(a.err, kErrCapacity);
             }
-        } else if (t == 0) {
+        } else if (lane == 0) {
             atomicOr(a.err, kErrGroup);
         }
-        int64_t base = 0;
-        int pend = 0;
-        while (true) {
-            // fill the queue, a window of 256 entries at a time
-            while (base < nce && pend < 256) {
-                const int64_t k = base + t;
-                bool gated = false;
-                if (k < nce) {
-                    const int64_t c = (int64_t)a.list_idx[lb + k] - a.n;
-                    if (c >= 0 && c < a.n_cells) {
-                        const float* cm = a.cell_mom + 12 * c;
-                        float fe[NFEAT], sc;
-                        if (pair_features(cx, cy, cz, h, cm, a.eps, fe, sc)) {
-                            if (bf_round(fe[3]) >= a.gate) {
-                                gated = true;
-                            } else {
-                                float o[NOUT];
+        // the network on queue slots [0, cnt): features, layers, skip term, expansion
+        auto run_net = [&](int cnt) {
+            const bool has = lane < cnt;
+            float fe[NFEAT], sc = 0.f, mx = 0.f, my = 0.f, mz = 0.f;
 #pragma unroll
-                                for (int m = 0; m < NOUT; m++) o[m] = 3.f * bf_round(fe[kSkip0 + m]);
-                                expand_outputs(o, sc, cx - cm[0], cy - cm[1], cz - cm[2], eps2, f);
-                            }
-                        }
-                    } else {
-                        atomicOr(a.err, kErrIndex);
-                    }
-                }
-                const uint64_t mask = __ballot(gated);
-                if (lane == 0) sWave[w] = __popcll(mask);
-                __syncthreads();
-                int off = pend;
-                for (int v = 0; v < w; v++) off += sWave[v];
-                if (gated) sPend[off + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)k;
-                pend += sWave[0] + sWave[1] + sWave[2] + sWave[3];
-                base += 256;
-                __syncthreads();
+            for (int j = 0; j < NFEAT; j++) fe[j] = 0.f;
+            if (has) {
+                const int64_t c = (int64_t)a.list_idx[lb + pendq[lane]] - a.n;   // checked when queued
+                const float* cm = a.cell_mom + 12 * c;
+                pair_features(cx, cy, cz, h, cm, a.eps, fe, sc);
+                mx = cm[0];
+                my = cm[1];
+                mz = cm[2];
             }
-            if (pend == 0) break;
-            const int take = pend < 256 ? pend : 256;
-            if (64 * w < take) {   // uniform within the wave
-                const int slot = 64 * w + lane;
-                const bool has = slot < take;
-                float fe[NFEAT], sc = 0.f, mx = 0.f, my = 0.f, mz = 0.f;
+            float ov[NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int j = 0; j < NFEAT; j++) fe[j] = 0.f;
-                if (has) {
-                    const int64_t c = (int64_t)a.list_idx[lb + sPend[slot]] - a.n;   // checked when queued
+            for (int tau = 0; tau < 4; tau++) {
+                const int src = tau * 16 + r16;
+                float v[NFEAT];
+#pragma unroll
+                for (int j = 0; j < NFEAT; j++) v[j] = __shfl(fe[j], src);
+                bf16x8 xb;
+#pragma unroll
+                for (int j = 0; j < 8; j++) {
+                    const float x = q == 0 ? v[j] : (q == 1 && j < 4 ? v[8 + j] : 0.f);
+                    xb[j] = (__bf16)x;
+                }
+                floatx4 acc[4];
+#pragma unroll
+                for (int mt = 0; mt < 4; mt++) {
+                    const float4 bb = *reinterpret_cast<const float4*>(sb + mt * 16 + q * 4);
+                    acc[mt] = mfma(w1a[mt], xb, floatx4{bb.x, bb.y, bb.z, bb.w});
+                }
+                const bf16x8 h0 = pack8(acc[0], acc[1]), h1 = pack8(acc[2], acc[3]);
+#pragma unroll
+                for (int mt = 0; mt < 4; mt++) {
+                    const float4 bb = *reinterpret_cast<const float4*>(sb + NH + mt * 16 + q * 4);
+                    acc[mt] = mfma(w2a[mt][0], h0, floatx4{bb.x, bb.y, bb.z, bb.w});
+                    acc[mt] = mfma(w2a[mt][1], h1, acc[mt]);
+                }
+                const bf16x8 g0b = pack8(acc[0], acc[1]), g1b = pack8(acc[2], acc[3]);
+                const float4 b3 = *reinterpret_cast<const float4*>(sb + 2 * NH + q * 4);
+                floatx4 o = mfma(w3a[0], g0b, floatx4{b3.x, b3.y, b3.z, b3.w});
+                o = mfma(w3a[1], g1b, o);
+                // outputs 0..3 of pair (tau, r16) sit in lane r16, outputs 4, 5 in lane r16 + 16
+                float sv[NOUT];
+#pragma unroll
+                for (int i = 0; i < 4; i++) sv[i] = __shfl(o[i], r16);
+                sv[4] = __shfl(o[0], r16 + 16);
+                sv[5] = __shfl(o[1], r16 + 16);
+                if (q == tau)
+#pragma unroll
+                    for (int i = 0; i < NOUT; i++) ov[i] = sv[i];
+            }
+            if (has && sc > 0.f) {
+#pragma unroll
+                for (int m = 0; m < NOUT; m++) ov[m] += 3.f * bf_round(fe[kSkip0 + m]);
+                expand_outputs(ov, sc, cx - mx, cy - my, cz - mz, eps2, f);
+            }
+        };
+        int pend = 0;   // uniform within the wave
+        for (int64_t base = 0; base < nce; base += 64) {
+            const int64_t k = base + lane;
+            bool gated = false;
+            if (k < nce) {
+                const int64_t c = (int64_t)a.list_idx[lb + k] - a.n;
+                if (c >= 0 && c < a.n_cells) {
                     const float* cm = a.cell_mom + 12 * c;
-                    pair_features(cx, cy, cz, h, cm, a.eps, fe, sc);
-                    mx = cm[0];
-                    my = cm[1];
-                    mz = cm[2];
-                }
-                float ov[NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                    float fe[NFEAT], sc;
+                    if (pair_features(cx, cy, cz, h, cm, a.eps, fe, sc)) {
+                        if (bf_round(fe[3]) >= a.gate) {
+                            gated = true;
+                        } else {
+                            float o[NOUT];
 #pragma unroll
-                for (int tau = 0; tau < 4; tau++) {
-                    const int src = tau * 16 + r16;
-                    float v[NFEAT];
-#pragma unroll
-                    for (int j = 0; j < NFEAT; j++) v[j] = __shfl(fe[j], src);
-                    bf16x8 xb;
-#pragma unroll
-                    for (int j = 0; j < 8; j++) {
-                        const float x = q == 0 ? v[j] : (q == 1 && j < 4 ? v[8 + j] : 0.f);
-                        xb[j] = (__bf16)x;
+                            for (int m = 0; m < NOUT; m++) o[m] = 3.f * bf_round(fe[kSkip0 + m]);
+                            expand_outputs(o, sc, cx - cm[0], cy - cm[1], cz - cm[2], eps2, f);
+                        }
                     }
-                    floatx4 acc[4];
-#pragma unroll
-                    for (int mt = 0; mt < 4; mt++) {
-                        const float4 bb = *reinterpret_cast<const float4*>(sb + mt * 16 + q * 4);
-                        acc[mt] = mfma(w1a[mt], xb, floatx4{bb.x, bb.y, bb.z, bb.w});
-                    }
-                    const bf16x8 h0 = pack8(acc[0], acc[1]), h1 = pack8(acc[2], acc[3]);
-#pragma unroll
-                    for (int mt = 0; mt < 4; mt++) {
-                        const float4 bb = *reinterpret_cast<const float4*>(sb + NH + mt * 16 + q * 4);
-                        acc[mt] = mfma(w2a[mt][0], h0, floatx4{bb.x, bb.y, bb.z, bb.w});
-                        acc[mt] = mfma(w2a[mt][1], h1, acc[mt]);
-                    }
-                    const bf16x8 g0b = pack8(acc[0], acc[1]), g1b = pack8(acc[2], acc[3]);
-                    const float4 b3 = *reinterpret_cast<const float4*>(sb + 2 * NH + q * 4);
-                    floatx4 o = mfma(w3a[0], g0b, floatx4{b3.x, b3.y, b3.z, b3.w});
-                    o = mfma(w3a[1], g1b, o);
-                    // outputs 0..3 of pair (tau, r16) sit in lane r16, outputs 4, 5 in lane r16 + 16
-                    float sv[NOUT];
-#pragma unroll
-                    for (int i = 0; i < 4; i++) sv[i] = __shfl(o[i], r16);
-                    sv[4] = __shfl(o[0], r16 + 16);
-                    sv[5] = __shfl(o[1], r16 + 16);
-                    if (q == tau)
-#pragma unroll
-                        for (int i = 0; i < NOUT; i++) ov[i] = sv[i];
-                }
-                if (has && sc > 0.f) {
-#pragma unroll
-                    for (int m = 0; m < NOUT; m++) ov[m] += 3.f * bf_round(fe[kSkip0 + m]);
-                    expand_outputs(ov, sc, cx - mx, cy - my, cz - mz, eps2, f);
+                } else {
+                    atomicOr(a.err, kErrIndex);
                 }
             }
-            __syncthreads();   // every wave has read its queue slots
-            const int rest = pend - take;   // <= 256, moved from [256, pend) to the front
-            int32_t moved = 0;
-            if (t < rest) moved = sPend[take + t];
-            __syncthreads();
-            if (t < rest) sPend[t] = moved;
-            __syncthreads();
-            pend = rest;
+            const uint64_t mask = __ballot(gated);
+            if (gated) pendq[pend + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)k;   // pend < 64
+            pend += __popcll(mask);
+            __builtin_amdgcn_wave_barrier();
+            if (pend >= 64) {
+                run_net(64);
+                const int rest = pend - 64;   // < 64, moved from [64, pend) to the front
+                const int32_t moved = lane < rest ? pendq[64 + lane] : 0;
+                __builtin_amdgcn_wave_barrier();
+                if (lane < rest) pendq[lane] = moved;
+                __builtin_amdgcn_wave_barrier();
+                pend = rest;
+            }
         }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kCorrTerms; k++) red[k][t] = f[k];
-        __syncthreads();
-        for (int s2 = 128; s2 > 0; s2 >>= 1) {
-            if (t < s2)
-                for (int k = 0; k < kCorrTerms; k++) red[k][t] += red[k][t + s2];
-            __syncthreads();
-        }
-        float* out = a.gcorr + (int64_t)kCorrStride * g;
-        if (t < kCorrTerms) out[t] = red[t][0];
-        if (t == kCorrTerms) out[kCorrTerms] = cx;
-        if (t == kCorrTerms + 1) out[kCorrTerms + 1] = cy;
-        if (t == kCorrTerms + 2) out[kCorrTerms + 2] = cz;
-        if (t == kCorrTerms + 3) out[kCorrTerms + 3] = 0.f;
+        if (pend > 0) run_net(pend);
+        wave_store_expansion(a, g, lane, f, cx, cy, cz);
     }
 }
 
@@ -1498,16 +1539,20 @@ int otoo_correction(otoo_ctx* c, int32_t kind, otoo_mlp* m, int32_t n, const flo
     CorrArgs ca{n,        pos,     n_groups, group_off, list_off, n_entries, list_idx,
                 pair_off, n_pairs, n_cells,  cell_mom,  cell_stride, eps,   corr,
                 m ? m->wbf : nullptr, m ? m->master : nullptr, m ? m->gate : 0.f, gcorr, c->errflag};
-    const int per_cu = kind == OTOO_CORR_MLP ? 3 : 6;
-    const int blocks = (int)std::min<int64_t>((int64_t)per_cu * c->num_cu, n_groups);
+    // one wave per group (four per workgroup) for the given and textbook tensors and the
+    // register-resident network; one workgroup per group for the LDS-staged network
+    const int64_t wave_blocks = ((int64_t)n_groups + 3) / 4;
     if (kind == OTOO_CORR_PAIRS)
-        hipLaunchKernelGGL(k_corr_group<kCorrPairs>, dim3(blocks), dim3(256), 0, c->stream, ca);
+        hipLaunchKernelGGL(k_corr_wave<kCorrPairs>, dim3((int)std::min<int64_t>(16LL * c->num_cu, wave_blocks)),
+                           dim3(256), 0, c->stream, ca);
     else if (kind == OTOO_CORR_QUAD)
-        hipLaunchKernelGGL(k_corr_group<kCorrQuad>, dim3(blocks), dim3(256), 0, c->stream, ca);
+        hipLaunchKernelGGL(k_corr_wave<kCorrQuad>, dim3((int)std::min<int64_t>(16LL * c->num_cu, wave_blocks)),
+                           dim3(256), 0, c->stream, ca);
     else if (c->tune.net_kernel == 1)
-        hipLaunchKernelGGL(k_corr_group<kCorrMlp>, dim3(blocks), dim3(256), 0, c->stream, ca);
+        hipLaunchKernelGGL(k_corr_group, dim3((int)std::min<int64_t>(3LL * c->num_cu, n_groups)),
+                           dim3(256), 0, c->stream, ca);
     else
-        hipLaunchKernelGGL(k_corr_net, dim3((int)std::min<int64_t>(2LL * c->num_cu, n_groups)), dim3(256), 0,
+        hipLaunchKernelGGL(k_corr_net, dim3((int)std::min<int64_t>(2LL * c->num_cu, wave_blocks)), dim3(256), 0,
                            c->stream, ca);
     HIP_TRY(c, hipGetLastError());
     return OTOO_OK;
