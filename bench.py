@@ -301,10 +301,12 @@ def learned_comparison(ctx, net, training, log, timing_reps):
     rows = []
     for th in (0.5, 0.6, 0.65, 0.7, 0.75, 0.8, 0.85, 0.9):
         rows += run(th, ("plain",), 32)
-    for th in (0.5, 0.75):
+    for th in (0.5, 0.7, 0.75, 0.8):
         rows += run(th, ("plain",), 64)
-    for g_max in (32, 64, 128):
-        for th in (0.8, 0.9, 1.0):
+    for th in (0.8, 0.9):
+        rows += run(th, ("quad", "learned"), 32)
+    for g_max in (64, 128):
+        for th in (0.8, 0.85, 0.9, 0.95, 1.0):
             rows += run(th, ("quad", "learned"), g_max)
     for r in rows:
         log(f"  {r['mode']:8s} g_max {r['g_max']:3d} theta {r['theta']:.2f}: {r['ms']:.3f} ms, "
