@@ -309,3 +309,29 @@ def test_tile_512(ctx, plummer16k, g_max):
     ctx.set_tuning(chunk=1024, tile=256)
     a_ref, p_ref = _oracle(pos32, mass32, lists, cm, 0.01)
     _assert_parity(acc, pot, a_ref, p_ref, f"tile 512 g_max={g_max}")
+
+
+@pytest.mark.parametrize("workload", ["polytrope2m", "cube16m"])
+def test_full_size_workloads_sampled(ctx, workload):
+    """The two-polytrope (2 x 2^20) and GRF-cube (2^24) workloads at full size,
+    in the launch configuration the benchmark times for them (autotuner cache
+    or defaults), against the oracle's list sums on 2048 sampled particles."""
+    from paper_1206_1199_amd import autotune as at
+    if workload == "polytrope2m":
+        pos, m, _, _ = synth.polytrope_pair(1 << 20, seed=2)
+        eps, theta, seed = 1e-4, 0.6, 102
+    else:
+        pos, m = synth.grf_cube(256, seed=4)
+        eps, theta, seed = 1e-3, 0.7, 104
+    sched, source = at.cached_schedule(workload)
+    mode = otoo.GROUP_CHUNK if sched["group_mode"] == "chunk" else otoo.GROUP_CELL
+    t, lists, pos32, mass32, cm, d = _setup(pos, m, theta, sched["g_max"], mode)
+    old = ctx.tuning()
+    at.apply_schedule(ctx, sched)
+    try:
+        acc, pot = _gpu(ctx, d, eps)
+    finally:
+        ctx.set_tuning(chunk=old.chunk, blocks_per_cu=old.blocks_per_cu, lpt=old.lpt, tile=old.tile)
+    sample = synth.sample_idx(len(m), 2048, seed=seed)
+    a_ref, p_ref = _oracle(pos32, mass32, lists, cm, eps, tgt=sample)
+    _assert_parity(acc[sample], pot[sample], a_ref, p_ref, f"{workload} sample ({source}: {sched})")
