@@ -46,11 +46,13 @@ __device__ __forceinline__ SphSrc load_src(const float* __restrict__ pos, const 
 }
 
 // One workgroup per group (grid-stride).  Lanes are (target, slice): with
-// n_g targets, S = 256 / n_g slices split each staged tile.  Tiles are
-// double-buffered: each thread gathers its entry of the next tile into
-// registers while the workgroup works on the current one, so there is one
-// barrier per tile.  Per target the slices' partial sums are combined in
-// slice order, so results are reproducible.  Sums A = sum q_j w(r/h_i) and
+// n_g targets, S = 256 / n_g slices split each staged tile into S
+// contiguous runs of `rows` entries, padded with zero-weight entries, so
+// every lane runs the same trip count over consecutive LDS records.  Tiles
+// are double-buffered: each thread gathers its entry of the next tile into
+// registers while the workgroup works on the current one (one barrier per
+// tile).  Per target the slices' partial sums are combined in slice order,
+// so results are reproducible.  Sums A = sum q_j w(r/h_i) and
 // B = sum q_j sigma_j w(r/h_j) give out_i = (sigma_i A + B) / 2 with
 // sigma = 8 / (pi h^3).
 __global__ __launch_bounds__(kBlock) void k_sph(int32_t n, const float* __restrict__ pos,
@@ -63,6 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_sph(int32_t n, const float* __restri
     __shared__ float2 sQ[2][kSphTile];   // q, q sigma
     __shared__ float2 red[kBlock];
     const int t = threadIdx.x;
+    const SphSrc zero{make_float4(0.f, 0.f, 0.f, 0.f), make_float2(0.f, 0.f)};
     for (int g = blockIdx.x; g < n_groups; g += gridDim.x) {
         const int g0 = group_off[g];
         const int ng = group_off[g + 1] - g0;
@@ -74,6 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_sph(int32_t n, const float* __restri
         const int S = kBlock / ng;
         const int ti = t % ng, sl = t / ng;
         const bool lane_on = sl < S;
+        const int tstride = S * (kSphTile / S);   // entries per tile, a multiple of S
         const int i = g0 + ti;
         const float xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
         const float ihi = 1.f / hh[i];
@@ -81,39 +85,32 @@ __global__ __launch_bounds__(kBlock) void k_sph(int32_t n, const float* __restri
         int64_t lb, le;
         list_range(list_off, n_entries, g, lb, le);
         const int64_t len = le - lb;
-        const int n_tiles = (int)((len + kSphTile - 1) / kSphTile);
         __syncthreads();   // the previous group's buffers and reduction have been read
-        if (n_tiles > 0 && t < len) {
-            const SphSrc r = load_src(pos, hh, q, list_idx, lb + t, n, err);
-            sX[0][t] = r.x;
-            sQ[0][t] = r.q;
-        }
-        __syncthreads();
-        for (int it = 0; it < n_tiles; it++) {
-            const int cur = it & 1;
-            const int64_t base = (int64_t)it * kSphTile;
-            const int cnt = (int)((len - base) < kSphTile ? (len - base) : kSphTile);
-            // gather this thread's entry of the next tile (lands while the current one is computed)
-            const int64_t nxt = base + kSphTile + t;
-            const bool pre = nxt < len;
-            SphSrc r;
-            if (pre) r = load_src(pos, hh, q, list_idx, lb + nxt, n, err);
+        SphSrc r = (t < tstride && t < len) ? load_src(pos, hh, q, list_idx, lb + t, n, err) : zero;
+        int cur = 0;
+        for (int64_t base = 0; base < len; base += tstride) {
+            const int tl = (int)((len - base) < tstride ? (len - base) : tstride);
+            const int rows = (tl + S - 1) / S;
+            sX[cur][t] = r.x;     // entries at or beyond tl are zero weight
+            sQ[cur][t] = r.q;
+            __syncthreads();
+            // gather this thread's entry of the next tile (lands while this one is computed)
+            const int64_t nxt = base + tstride + t;
+            r = (t < tstride && nxt < len) ? load_src(pos, hh, q, list_idx, lb + nxt, n, err) : zero;
             if (lane_on) {
-#pragma unroll 4
-                for (int k = sl; k < cnt; k += S) {
-                    const float4 s = sX[cur][k];
-                    const float2 w = sQ[cur][k];
-                    const float dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
+                const float4* xp = sX[cur] + sl * rows;
+                const float2* qp = sQ[cur] + sl * rows;
+#pragma unroll 8
+                for (int m = 0; m < rows; m++) {
+                    const float4 s4 = xp[m];
+                    const float2 w = qp[m];
+                    const float dx = s4.x - xi, dy = s4.y - yi, dz = s4.z - zi;
                     const float rr = __builtin_amdgcn_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
                     A = fmaf(w.x, spline_w(rr * ihi), A);
-                    B = fmaf(w.y, spline_w(rr * s.w), B);
+                    B = fmaf(w.y, spline_w(rr * s4.w), B);
                 }
             }
-            if (pre) {
-                sX[cur ^ 1][t] = r.x;
-                sQ[cur ^ 1][t] = r.q;
-            }
-            __syncthreads();
+            cur ^= 1;
         }
         red[t] = make_float2(A, B);
         __syncthreads();
