@@ -185,9 +185,9 @@ def workload_learned(ctx, net, training, log, tree, eps, theta, sched, sample, a
     import paper_1206_1199_amd as otoo
     from paper_1206_1199_amd import learned
     mode_id = otoo.GROUP_CHUNK if sched["group_mode"] == "chunk" else otoo.GROUP_CELL
-    thetas = {"plain": [round(theta - 0.2, 2), round(theta - 0.1, 2), theta],
-              "quad": [theta, round(theta + 0.1, 2)],
-              "learned": [theta, round(theta + 0.1, 2), round(theta + 0.2, 2), round(theta + 0.3, 2)]}
+    thetas = {"plain": [round(theta - 0.2, 2), round(theta - 0.1, 2), round(theta - 0.05, 2), theta],
+              "quad": [theta, round(theta + 0.05, 2), round(theta + 0.1, 2), round(theta + 0.2, 2)],
+              "learned": [theta, round(theta + 0.05, 2), round(theta + 0.1, 2), round(theta + 0.2, 2)]}
     rows = []
     for th in sorted({t for v in thetas.values() for t in v}):
         lists = tree.walk(theta=th, g_max=sched["g_max"], group_mode=mode_id)
