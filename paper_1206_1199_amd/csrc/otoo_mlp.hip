@@ -1232,12 +1232,25 @@ __global__ __launch_bounds__(256) void k_mlp_train(TrainArgs a) {
     }
 }
 
-__global__ void k_grad_reduce(const float* __restrict__ part, int32_t n_parts, float* __restrict__ grad) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > NPARAM) return;
+// Fixed-order FP64 sum of the per-workgroup partial rows: a workgroup takes
+// kGradCols consecutive entries (parameters, then the loss) and kGradSlices
+// interleaved subsets of the rows; the slices are then added in slice order.
+constexpr int kGradCols = 32, kGradSlices = 8;
+__global__ __launch_bounds__(kGradCols * kGradSlices) void k_grad_reduce(const float* __restrict__ part,
+                                                                         int32_t n_parts, float* __restrict__ grad) {
+    __shared__ double red[kGradSlices][kGradCols];
+    const int c = threadIdx.x % kGradCols, sl = threadIdx.x / kGradCols;
+    const int i = blockIdx.x * kGradCols + c;
     double s = 0.0;
-    for (int b = 0; b < n_parts; b++) s += (double)part[(int64_t)b * (NPARAM + 1) + i];
-    grad[i] = (float)s;
+    if (i <= NPARAM)
+        for (int b = sl; b < n_parts; b += kGradSlices) s += (double)part[(int64_t)b * (NPARAM + 1) + i];
+    red[sl][c] = s;
+    __syncthreads();
+    if (sl == 0 && i <= NPARAM) {
+        double tot = 0.0;
+        for (int k = 0; k < kGradSlices; k++) tot += red[k][c];
+        grad[i] = (float)tot;
+    }
 }
 
 // BF16 operand copies of parameter i of the FP32 master vector
@@ -1344,8 +1357,8 @@ int run_backward(otoo_mlp* m, const uint16_t* X, const float* aux, int64_t n_sam
         attr_set = true;
     }
     hipLaunchKernelGGL(k_mlp_train, dim3(blocks), dim3(256), sizeof(TrainLDS), c->stream, ta);
-    hipLaunchKernelGGL(k_grad_reduce, dim3((NPARAM + 1 + 255) / 256), dim3(256), 0, c->stream, m->part, blocks,
-                       m->grad);
+    hipLaunchKernelGGL(k_grad_reduce, dim3((NPARAM + 1 + kGradCols - 1) / kGradCols), dim3(kGradCols * kGradSlices), 0,
+                       c->stream, m->part, blocks, m->grad);
     HIP_TRY(c, hipGetLastError());
     return OTOO_OK;
 }
