@@ -23,8 +23,8 @@ DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotu
 GRID = {
     "group": [(GROUP_CHUNK, 32), (GROUP_CHUNK, 64), (GROUP_CHUNK, 128), (GROUP_CELL, 64), (GROUP_CELL, 128),
               (GROUP_CELL, 256)],
-    "chunk": [2048, 8192, 1 << 24],
-    "blocks_per_cu": [4, 8],
+    "chunk": [2048, 4096, 8192, 16384, 1 << 24],
+    "blocks_per_cu": [4, 6, 8],
     "lpt": [0, 1],
     "tile": [256, 512],
 }
