@@ -180,8 +180,9 @@ int otoo_set_stream(otoo_ctx* ctx, void* hip_stream);
 /* Message of the last failing call on this context ("" if none). */
 const char* otoo_last_error(const otoo_ctx* ctx);
 
-/* Kernel schedule knobs (the autotuner's search space).  Zero fields keep
- * the current value. */
+/* Kernel schedule knobs (the autotuner's search space).  A zero chunk,
+ * blocks_per_cu or tile keeps the current value; lpt, debug_validate and
+ * net_kernel are taken as given. */
 typedef struct {
     int32_t chunk;        /* list entries per work item (a long list is split into items); >= 64 */
     int32_t blocks_per_cu;/* persistent workgroups per compute unit, 1..16 */
@@ -378,6 +379,28 @@ int otoo_correction(otoo_ctx* ctx, int32_t kind, otoo_mlp* mlp, int32_t n, const
                     const int32_t* group_off, int64_t n_entries, const int64_t* list_off, const int32_t* list_idx,
                     int64_t n_pairs, const int64_t* pair_off, int32_t n_cells, const float* cell_mom,
                     int32_t cell_stride, float eps, const float* corr, float* gcorr);
+
+/* Autotuner of the force evaluation (the group size of Sec. 3.4's
+ * vectorised walk and the device schedule).  For each group choice, the
+ * tree is walked with *walk's criterion and that (group_mode, g_max), the
+ * lists and the particle/cell arrays (cell stride 4) are copied to the
+ * device, and every schedule in `schedules` is timed as the mean of `reps`
+ * replays of a captured force graph (after two warm-up replays) on the
+ * context stream.  ms [n_choices][n_schedules] (host, may be NULL) receives
+ * every time and interactions [n_choices] (may be NULL) the interaction
+ * counts; *best_choice and *best_tuning receive the fastest pair and
+ * *best_ms its time.  The context's tuning is restored afterwards and any
+ * graph it held (otoo_graph_capture) is discarded.  The library allocates
+ * and frees the device copies itself.  Synchronous.
+ * EINVAL on bad arguments (a schedule set_tuning rejects included). */
+typedef struct {
+    int32_t group_mode;   /* otoo_group_mode */
+    int32_t g_max;        /* 1 .. OTOO_MAX_GROUP */
+} otoo_group_choice;
+int otoo_autotune(otoo_ctx* ctx, const otoo_tree* tree, const otoo_walk_params* walk,
+                  const otoo_group_choice* choices, int32_t n_choices, const otoo_tuning* schedules,
+                  int32_t n_schedules, float eps, int32_t reps, float* ms, int64_t* interactions,
+                  otoo_group_choice* best_choice, otoo_tuning* best_tuning, float* best_ms);
 
 /* Synchronise the context's stream and report whether any kernel since the
  * last otoo_check met malformed input (EINVAL) or not (OK); clears the flag. */

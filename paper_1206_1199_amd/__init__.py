@@ -60,11 +60,16 @@ class Tuning(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class GroupChoice(ctypes.Structure):
+    _fields_ = [("group_mode", ctypes.c_int32), ("g_max", ctypes.c_int32)]
+
+
 EXPORTED = [
     "otoo_tree_build", "otoo_tree_free", "otoo_tree_info", "otoo_tree_export", "otoo_tree_cells",
     "otoo_tree_links", "otoo_tree_walk", "otoo_tree_groups", "otoo_tree_walk_range", "otoo_tree_walk_sph", "otoo_lists_free", "otoo_create", "otoo_destroy",
     "otoo_set_stream", "otoo_last_error", "otoo_set_tuning", "otoo_get_tuning", "otoo_force",
     "otoo_check", "otoo_enable_timing", "otoo_last_timing", "otoo_graph_capture", "otoo_graph_launch",
+    "otoo_autotune",
     "otoo_quad_exact", "otoo_correction", "otoo_direct", "otoo_sph_sum", "otoo_mlp_num_params", "otoo_mlp_create", "otoo_mlp_destroy", "otoo_mlp_set_params", "otoo_mlp_set_gate",
     "otoo_mlp_get_params", "otoo_mlp_save", "otoo_mlp_load", "otoo_mlp_forward", "otoo_mlp_infer",
     "otoo_mlp_train_samples", "otoo_mlp_backward", "otoo_mlp_train_step",
@@ -110,6 +115,9 @@ def lib():
         "otoo_last_timing": ([P, ctypes.POINTER(F), ctypes.POINTER(F)], I32),
         "otoo_graph_capture": ([P, I32, P, P, I32, P, I64, P, P, I32, P, I32, F, P, P, P], I32),
         "otoo_graph_launch": ([P], I32),
+        "otoo_autotune": ([P, P, ctypes.POINTER(_WalkParams), ctypes.POINTER(GroupChoice), I32,
+                           ctypes.POINTER(Tuning), I32, F, I32, P, P, ctypes.POINTER(GroupChoice),
+                           ctypes.POINTER(Tuning), ctypes.POINTER(F)], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -489,3 +497,23 @@ class Context:
 
     def graph_launch(self):
         self._raise(lib().otoo_graph_launch(self._h), "otoo_graph_launch")
+
+    def autotune(self, tree: Tree, eps: float, choices, schedules, reps: int = 10, theta: float = 0.5,
+                 mac: int = MAC_BH, delta: float = 0.01, m_limit: float = math.inf):
+        """Time every (group_mode, g_max) choice x device schedule as graph replays
+        (otoo_autotune).  schedules: dicts with chunk, blocks_per_cu, lpt, tile.
+        Returns (ms [n_choices, n_schedules], interactions [n_choices],
+        best (group_mode, g_max), best Tuning, best ms).  Discards any graph the
+        context held."""
+        ch = (GroupChoice * len(choices))(*[GroupChoice(int(m), int(g)) for m, g in choices])
+        sc = (Tuning * len(schedules))(*[Tuning(chunk=int(s["chunk"]), blocks_per_cu=int(s["blocks_per_cu"]),
+                                                lpt=int(s["lpt"]), tile=int(s["tile"])) for s in schedules])
+        ms = np.zeros((len(choices), len(schedules)), np.float32)
+        inter = np.zeros(len(choices), np.int64)
+        bc, bt, bms = GroupChoice(), Tuning(), ctypes.c_float()
+        p = _WalkParams(mac=mac, theta=theta, delta=delta, m_limit=m_limit, group_mode=GROUP_CHUNK, g_max=1)
+        rc = lib().otoo_autotune(self._h, tree._h, ctypes.byref(p), ch, len(choices), sc, len(schedules),
+                                 float(eps), int(reps), _np_ptr(ms), _np_ptr(inter), ctypes.byref(bc),
+                                 ctypes.byref(bt), ctypes.byref(bms))
+        self._raise(rc, "otoo_autotune")
+        return ms, inter, (bc.group_mode, bc.g_max), bt, bms.value

@@ -12,11 +12,8 @@ from __future__ import annotations
 import itertools
 import json
 import os
-import time
 
-import numpy as np
-
-from . import GROUP_CELL, GROUP_CHUNK, Context, DeviceLists, Tree
+from . import GROUP_CELL, GROUP_CHUNK, Context, Tree
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
@@ -37,51 +34,25 @@ def device_key(device: int = 0) -> str:
     return f"{arch}:{p.multi_processor_count}cu"
 
 
-def time_replays(ctx: Context, d: DeviceLists, eps: float, out, reps: int = 10, gcorr=None) -> float:
-    """Median-free mean of `reps` graph replays (ms), after two warm-ups."""
-    import torch
-    ctx.graph_capture(d, eps, out, gcorr=gcorr)
-    for _ in range(2):
-        ctx.graph_launch()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    stream = torch.cuda.current_stream()
-    e0.record(stream)
-    for _ in range(reps):
-        ctx.graph_launch()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / reps
-
-
 def autotune(tree: Tree, eps: float, theta: float, ctx: Context, grid=None, reps: int = 10, log=None):
-    """Sweep the grid; returns (best dict, table of all measurements)."""
+    """Sweep the grid through the library's otoo_autotune; returns (best dict,
+    table of all measurements)."""
     grid = grid or GRID
+    choices = list(grid["group"])
+    schedules = [dict(chunk=c, blocks_per_cu=b, lpt=l, tile=t)
+                 for c, b, l, t in itertools.product(grid["chunk"], grid["blocks_per_cu"], grid["lpt"], grid["tile"])]
+    ctx.sync_stream()
+    ms, inter, _, _, _ = ctx.autotune(tree, eps, choices, schedules, reps=reps, theta=theta)
     table = []
-    best = None
-    for mode, g_max in grid["group"]:
-        t0 = time.perf_counter()
-        lists = tree.walk(theta=theta, g_max=g_max, group_mode=mode)
-        walk_ms = 1e3 * (time.perf_counter() - t0)
-        _, pos32, mass32, cm = tree.export(4)
-        d = DeviceLists.from_host(pos32, mass32, lists, cm)
-        out = ctx.outputs(d.n)
-        for chunk, bpc, lpt, tile in itertools.product(grid["chunk"], grid["blocks_per_cu"], grid["lpt"],
-                                                      grid["tile"]):
-            ctx.set_tuning(chunk=chunk, blocks_per_cu=bpc, lpt=lpt, tile=tile)
-            ms = time_replays(ctx, d, eps, out, reps)
-            row = dict(group_mode="chunk" if mode == GROUP_CHUNK else "cell", g_max=g_max, chunk=chunk,
-                       blocks_per_cu=bpc, lpt=lpt, tile=tile, ms=ms, interactions=lists.interactions,
-                       gint_s=lists.interactions / ms / 1e6, walk_ms=walk_ms)
-            table.append(row)
-            if best is None or ms < best["ms"]:
-                best = row
-        ctx.check()
+    for gi, (mode, g_max) in enumerate(choices):
+        rows = [dict(group_mode="chunk" if mode == GROUP_CHUNK else "cell", g_max=g_max, **s, ms=float(ms[gi, si]),
+                     interactions=int(inter[gi]), gint_s=float(inter[gi] / ms[gi, si] / 1e6))
+                for si, s in enumerate(schedules)]
+        table += rows
         if log:
-            sub = [r for r in table if r["g_max"] == g_max and r["group_mode"] == table[-1]["group_mode"]]
-            b = min(sub, key=lambda r: r["ms"])
+            b = min(rows, key=lambda r: r["ms"])
             log(f"  {b['group_mode']} g_max={g_max}: best {b['ms']:.3f} ms ({b['gint_s']:.0f} Gint/s)")
+    best = min(table, key=lambda r: r["ms"])
     return best, table
 
 

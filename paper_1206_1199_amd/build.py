@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libotoo.so")
 
-HIP_SOURCES = ["otoo_force.hip", "otoo_mlp.hip", "otoo_direct.hip", "otoo_sph.hip"]
+HIP_SOURCES = ["otoo_force.hip", "otoo_mlp.hip", "otoo_direct.hip", "otoo_sph.hip", "otoo_autotune.hip"]
 HOST_SOURCES = ["host_tree.cpp"]
 ARCH = os.environ.get("OTOO_OFFLOAD_ARCH", "gfx950")
 
