@@ -33,7 +33,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Ginteractions/s and ms per full force eval at 1e-3 median force error, 1 GPU"
 FLOPS_PER_INTERACTION = 20          # the paper's counting convention (Sec. 5)
-PEAK_FP32_TFLOPS = 157.3            # MI355X FP32 vector peak (packed); 78.6 without packed FP32
+PEAK_FP32_TFLOPS = 157.3            # MI355X FP32 vector peak (packed)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 flops (FMA) x 2.4 GHz, one FP32 op per lane per clock
 
 WORKLOADS = {
     # name: (generator, kwargs, eps, theta, description)
@@ -98,23 +99,65 @@ def make_workload(name):
 # ------------------------------------------------------------------ CPU baseline leg (the oracle)
 
 
-def cpu_baseline(pos32, mass32, lists, cm, eps):
-    """The FP64 oracle timed on this host over the whole workload: list sums
-    for every target, on the same FP32 inputs and lists as the device.
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    Returns (baseline dict, list-sum references (acc, pot))."""
+
+def _omp_threads(k):
+    """Set the OpenMP thread count of the oracle's runtime (libgomp)."""
+    import ctypes
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(k))
+
+
+def cpu_baseline(pos32, mass32, lists, cm, eps, sample=None):
+    """The FP64 oracle timed on this host: list sums for every target on all
+    cores (same FP32 inputs and lists as the device), the same sums for every
+    16th group on one core, and the O(N^2) direct sum at the accuracy sample.
+
+    Returns (baseline dict, list-sum references (acc, pot), direct sums at the
+    sample or None)."""
     import oracle
     oracle.build()
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    p64, m64 = pos32.astype(np.float64), mass32.astype(np.float64)
+    com, cmass, e = cm[:, :3].astype(np.float64), cm[:, 3].astype(np.float64), float(np.float32(eps))
     t0 = time.perf_counter()
-    ref = oracle.list_force(pos32.astype(np.float64), mass32.astype(np.float64), lists.group_off, lists.list_off,
-                            lists.list_idx, cm[:, :3].astype(np.float64), cm[:, 3].astype(np.float64),
-                            float(np.float32(eps)))
+    ref = oracle.list_force(p64, m64, lists.group_off, lists.list_off, lists.list_idx, com, cmass, e)
     dt = time.perf_counter() - t0
     base = {"value": lists.interactions / dt / 1e9, "unit": "Ginteractions/s", "cores": threads, "kind": "oracle",
             "sample": f"FP64 list sums over all {len(mass32)} targets of the workload "
-                      f"({lists.interactions} interactions) in {dt:.2f} s"}
-    return base, ref
+                      f"({lists.interactions} interactions) in {dt:.2f} s",
+            "cpu": _cpu_model(), "nproc": os.cpu_count()}
+    # one core, every 16th group
+    go, lo = np.asarray(lists.group_off, np.int64), np.asarray(lists.list_off, np.int64)
+    groups = np.arange(0, len(go) - 1, 16)
+    tgt = np.concatenate([np.arange(go[g], go[g + 1]) for g in groups])
+    inter1 = int(((go[groups + 1] - go[groups]) * (lo[groups + 1] - lo[groups])).sum())
+    _omp_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.list_force(p64, m64, lists.group_off, lists.list_off, lists.list_idx, com, cmass, e, tgt=tgt)
+        dt1 = time.perf_counter() - t0
+    finally:
+        _omp_threads(threads)
+    base["one_core"] = {"value": inter1 / dt1 / 1e9, "unit": "Ginteractions/s", "cores": 1,
+                        "sample": f"every 16th group ({len(groups)} groups, {len(tgt)} targets, {inter1} "
+                                  f"interactions) in {dt1:.2f} s"}
+    direct = None
+    if sample is not None:
+        t0 = time.perf_counter()
+        direct = oracle.direct(p64, m64, e, tgt=np.asarray(sample, np.int64))
+        dtd = time.perf_counter() - t0
+        pairs = len(sample) * len(mass32)
+        base["direct"] = {"value": pairs / dtd / 1e9, "unit": "Gpairs/s", "cores": threads,
+                          "sample": f"O(N^2) FP64 sums at {len(sample)} targets ({pairs} pairs) in {dtd:.2f} s"}
+    return base, ref, direct
 
 
 def direct_reference(ctx, d, sample, eps):
@@ -462,6 +505,9 @@ def main():
                    "interactions": inter, "n_cells": tree.n_cells, "schedule": sched, "schedule_source": source},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(desc, sched),
+                     # the library is built with packed FP32 instructions disabled, which halves the issue ceiling
+                     "peak_without_packed_fp32": PEAK_FP32_NONPACKED_TFLOPS,
+                     "frac_without_packed_fp32": achieved / PEAK_FP32_NONPACKED_TFLOPS,
                      "kernel": "k_force", "kernel_ms": k_ms, "flops_per_interaction": FLOPS_PER_INTERACTION},
         "host": {"tree_build_ms": 1e3 * (t1 - t0), "walk_ms": 1e3 * (t3 - t2), "h2d_ms": 1e3 * (t5 - t4)},
     }
@@ -483,11 +529,14 @@ def main():
         sel = mask[sample]
         res["accuracy"][f"tree_acc_median_vs_direct_{k}"] = float(np.median(et[sel])) if sel.any() else None
     if not args.no_cpu_baseline:
-        base, (a_ref, p_ref) = cpu_baseline(pos32, mass32, lists, cm, eps)
+        base, (a_ref, p_ref), cpu_direct = cpu_baseline(pos32, mass32, lists, cm, eps, sample)
         ea, ep = rel_err(acc, a_ref), rel_err(pot, p_ref)
         res["cpu_baseline"] = base
         res["accuracy"].update({"parity_acc_median": float(np.median(ea)), "parity_acc_max": float(ea.max()),
                                 "parity_pot_median": float(np.median(ep)), "parity_pot_max": float(ep.max())})
+        # the device's FP64 direct sums (the accuracy reference) against the oracle's
+        eda, edp = rel_err(a_dir, cpu_direct[0]), rel_err(p_dir, cpu_direct[1])
+        res["accuracy"].update({"direct_parity_acc_max": float(eda.max()), "direct_parity_pot_max": float(edp.max())})
         for k, mask in cls.items():
             res["accuracy"][f"parity_acc_median_{k}"] = float(np.median(ea[mask]))
             res["accuracy"][f"parity_acc_max_{k}"] = float(ea[mask].max())
