@@ -782,6 +782,7 @@ int otoo_create(otoo_ctx** out, int32_t device) {
     c->num_cu = cu;
     c->meta = static_cast<Meta*>(small);
     c->errflag = reinterpret_cast<int32_t*>(static_cast<char*>(small) + 2048);
+    c->sph_meta = static_cast<char*>(small) + 1024;
     if (hipMemset(small, 0, 4096) != hipSuccess) {
         (void)hipFree(small);
         delete c;
@@ -808,6 +809,7 @@ int otoo_destroy(otoo_ctx* c) {
     for (auto& ev : c->ev)
         if (ev) (void)hipEventDestroy(ev);
     if (c->buf) (void)hipFree(c->buf);
+    if (c->sph_buf) (void)hipFree(c->sph_buf);
     if (c->meta) (void)hipFree(c->meta);
     delete c;
     return OTOO_OK;

@@ -29,6 +29,9 @@ struct Meta {
     int32_t hist[kClasses];
     int32_t cursor[kClasses];
 };
+// The context's 4 KiB counter block: Meta at 0, the SPH counters at 1024,
+// the error flag at 2048.
+static_assert(sizeof(Meta) <= 1024, "Meta must fit below the SPH counters");
 
 __device__ __forceinline__ void kahan_add(float& sum, float& comp, float x) {
     // sum + comp carries the running value; comp holds what rounding dropped
@@ -180,6 +183,11 @@ struct otoo_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_stream = nullptr;
+    // SPH gather sums: work-queue counters (inside the 4 KiB block of meta)
+    // and scratch for the item lists and chunk partials, grown on demand
+    void* sph_meta = nullptr;
+    void* sph_buf = nullptr;
+    size_t sph_bytes = 0;
 };
 
 

@@ -7,125 +7,317 @@ using namespace otoo_detail;
 
 namespace {
 
-constexpr int kSphTile = 256;   // list entries staged in LDS per step
+constexpr int kSphPer = 2;                   // list entries each thread gathers per tile
+constexpr int kSphCap = kSphPer * kBlock;    // records per LDS tile buffer
 constexpr float kInvPi = 0.318309886183790672f;
+constexpr float kCbrt4 = 1.58740105196819947f;       // k with k^3 = 4
+constexpr float kHalfCbrt4 = 0.793700525984099737f;  // k / 2
 
-// cubic B-spline shape: w(u) = 1 - 6u^2 + 6u^3 on [0, 1/2], 2 (1 - u)^3 on
-// [1/2, 1], 0 beyond, written as 2 a^3 - 8 b^3 with a = max(1 - u, 0) and
-// b = max(1/2 - u, 0) (the two truncated cubics agree with the pieces)
-__device__ __forceinline__ float spline_w(float u) {
-    const float a = fmaxf(1.f - u, 0.f);
-    const float b = fmaxf(0.5f - u, 0.f);
-    return fmaf(2.f * a * a, a, -8.f * b * b * b);
+// Half the cubic B-spline shape at u = r/h: w(u) = 1 - 6u^2 + 6u^3 on
+// [0, 1/2], 2 (1 - u)^3 on [1/2, 1], 0 beyond, equals 2 a^3 - 8 b^3 with
+// a = max(1 - u, 0), b = max(1/2 - u, 0) (the truncated cubics agree with
+// the pieces).  With b' = k b, k^3 = 4, that is 2 (a^3 - b'^3); this returns
+// a^3 - b'^3, the factor 2 being carried by the source weights.
+__device__ __forceinline__ float spline_half(float r, float ih, float kih) {
+    const float a = fmaxf(fmaf(-ih, r, 1.f), 0.f);
+    const float b = fmaxf(fmaf(-kih, r, kHalfCbrt4), 0.f);
+    return fmaf(a * a, a, -(b * b) * b);
 }
 
-// Source record of one list entry, as staged in LDS: position and 1/h,
-// then q and q sigma (sigma = 8 / (pi h^3)).  Entries that are not particles
-// get q = 0.
-struct SphSrc {
+// Source record of one list entry as staged in LDS: position and 1/h, then
+// 2q and 2q sigma (sigma = 8 / (pi h^3)).  Entries that are not particles,
+// and the padding of a tile, get zero weights.
+struct SphRec {
     float4 x;
-    float2 q;
+    float2 w;
 };
 
-__device__ __forceinline__ SphSrc load_src(const float* __restrict__ pos, const float* __restrict__ hh,
+__device__ __forceinline__ SphRec load_rec(const float* __restrict__ pos, const float* __restrict__ hh,
                                            const float* __restrict__ q, const int32_t* __restrict__ list_idx,
                                            int64_t e, int32_t n, int32_t* err) {
-    SphSrc r;
+    SphRec r;
     const int32_t j = list_idx[e];
     if (j >= 0 && j < n) {
         const float ih = 1.f / hh[j];
-        const float qj = q[j];
+        const float q2 = 2.f * q[j];
         r.x = make_float4(pos[3 * j], pos[3 * j + 1], pos[3 * j + 2], ih);
-        r.q = make_float2(qj, qj * (8.f * kInvPi) * ih * ih * ih);
+        r.w = make_float2(q2, q2 * (8.f * kInvPi) * ih * ih * ih);
     } else {
         atomicOr(err, kErrIndex);
         r.x = make_float4(0.f, 0.f, 0.f, 0.f);
-        r.q = make_float2(0.f, 0.f);
+        r.w = make_float2(0.f, 0.f);
     }
     return r;
 }
 
-// One workgroup per group (grid-stride).  Lanes are (target, slice): with
-// n_g targets, S = 256 / n_g slices split each staged tile into S
-// contiguous runs of `rows` entries, padded with zero-weight entries, so
-// every lane runs the same trip count over consecutive LDS records.  Tiles
-// are double-buffered: each thread gathers its entry of the next tile into
-// registers while the workgroup works on the current one (one barrier per
-// tile).  Per target the slices' partial sums are combined in slice order,
-// so results are reproducible.  Sums A = sum q_j w(r/h_i) and
-// B = sum q_j sigma_j w(r/h_j) give out_i = (sigma_i A + B) / 2 with
-// sigma = 8 / (pi h^3).
-__global__ __launch_bounds__(kBlock) void k_sph(int32_t n, const float* __restrict__ pos,
+// A group's particle range and list range (uniform across the workgroup).
+struct Geo {
+    int g0, ng;
+    int64_t lb, len;
+    bool ok;
+};
+
+__device__ __forceinline__ Geo load_geo(int g, int32_t n, const int32_t* __restrict__ group_off, int64_t n_entries,
+                                        const int64_t* __restrict__ list_off) {
+    Geo c;
+    c.g0 = group_off[g];
+    c.ng = group_off[g + 1] - c.g0;
+    c.ok = c.ng >= 1 && c.ng <= kBlock && c.g0 >= 0 && c.g0 + c.ng <= n;
+    int64_t le;
+    list_range(list_off, n_entries, g, c.lb, le);
+    c.len = le - c.lb;
+    return c;
+}
+
+// Slices of a group of ng targets and the entries per tile (a multiple of
+// the slice count).
+__device__ __forceinline__ int slices(int ng) { return kBlock / ng; }
+__device__ __forceinline__ int tile_len(int ng) {
+    const int S = slices(ng);
+    return S * (kSphCap / S);
+}
+
+// Work items.  A list longer than a quarter chunk is a "long" group: its
+// list is cut into chunks of C entries, each an item (g, k, m, nc) with nc
+// the chunk count and m the group's slot among the split groups (nc > 1) or
+// -1; these items are taken first.  Every other group is one "short" item.
+// Chunk partials of a split group go to slots base_m + k ng + i and are
+// summed in chunk order by k_sph_merge.
+struct SphMeta {
+    int32_t head;                 // next item of the queue
+    int32_t n_long;               // long items
+    int32_t n_short;              // short items
+    int32_t n_split;              // split groups
+    unsigned long long n_parts;   // partial slots handed out
+};
+
+struct SphPlan {
+    SphMeta* meta;
+    int32_t chunk;
+    int64_t cap_long, cap_split, cap_parts;
+    int4* items_long;
+    int32_t* items_short;
+    int32_t* split_g;
+    int64_t* split_base;
+    float2* parts;
+};
+
+__global__ void k_sph_reset(SphMeta* m) {
+    if (threadIdx.x == 0) {
+        m->head = 0;
+        m->n_long = 0;
+        m->n_short = 0;
+        m->n_split = 0;
+        m->n_parts = 0;
+    }
+}
+
+// One thread per group: classify it and append its items (wave-aggregated
+// appends for the short ones).
+__global__ __launch_bounds__(256) void k_sph_plan(SphPlan pl, int32_t n, int32_t n_groups,
+                                                  const int32_t* __restrict__ group_off, int64_t n_entries,
+                                                  const int64_t* __restrict__ list_off, int32_t* err) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    bool valid = g < n_groups;
+    Geo c{};
+    if (valid) {
+        c = load_geo(g, n, group_off, n_entries, list_off);
+        if (!c.ok) {
+            atomicOr(err, kErrGroup);
+            valid = false;
+        }
+    }
+    const int C = pl.chunk;
+    const bool is_long = valid && c.len > C / 4;
+    const bool is_short = valid && !is_long;
+    const unsigned long long mask = __ballot(is_short);
+    if (mask) {
+        const int leader = __ffsll((long long)mask) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&pl.meta->n_short, __popcll(mask));
+        base = __shfl(base, leader);
+        if (is_short) pl.items_short[base + __popcll(mask & ((1ull << lane) - 1))] = g;
+    }
+    if (is_long) {
+        const int nc = (int)((c.len + C - 1) / C);
+        int m = -1;
+        if (nc > 1) {
+            m = atomicAdd(&pl.meta->n_split, 1);
+            const unsigned long long pb = atomicAdd(&pl.meta->n_parts, (unsigned long long)nc * c.ng);
+            if (m >= pl.cap_split) {
+                atomicOr(err, kErrCapacity);
+                return;
+            }
+            if ((int64_t)(pb + (unsigned long long)nc * c.ng) > pl.cap_parts) {
+                pl.split_g[m] = -1;   // k_sph_merge skips the slot
+                atomicOr(err, kErrCapacity);
+                return;
+            }
+            pl.split_g[m] = g;
+            pl.split_base[m] = (int64_t)pb;
+        }
+        const int base = atomicAdd(&pl.meta->n_long, nc);
+        const bool fits = (int64_t)base + nc <= pl.cap_long;
+        if (!fits) atomicOr(err, kErrCapacity);
+        for (int k = 0; k < nc && (int64_t)base + k < pl.cap_long; k++)   // slots in range are always written
+            pl.items_long[base + k] = fits ? make_int4(g, k, m, nc) : make_int4(-2, 0, -1, 0);
+    }
+}
+
+// Persistent workgroups pull items from the queue (long items first).  Per
+// item, lanes are (target, slice): with ng targets, S = 256 / ng slices;
+// slice s of a staged tile takes entries s, s + S, s + 2S, ..., so the
+// slices that share a wave read consecutive records (no bank conflicts) and
+// every lane runs the same trip count (the tail is zero-weight padding).
+// Tiles are double-buffered: each thread gathers its entries of the next
+// tile while the workgroup sums the current one.  Per target the slices'
+// partial sums are combined in slice order, so results are reproducible.
+// Sums A = sum q_j w(r/h_i) and B = sum q_j sigma_j w(r/h_j) give
+// out_i = (sigma_i A + B) / 2 with sigma = 8 / (pi h^3).
+__global__ __launch_bounds__(kBlock) void k_sph(SphPlan pl, int32_t n, const float* __restrict__ pos,
                                                 const float* __restrict__ hh, const float* __restrict__ q,
                                                 int32_t n_groups, const int32_t* __restrict__ group_off,
-                                                int64_t n_entries, const int64_t* __restrict__ list_off,
+                                                int64_t n_entries,
+                                                const int64_t* __restrict__ list_off,
                                                 const int32_t* __restrict__ list_idx, float* __restrict__ out,
                                                 int32_t* err) {
-    __shared__ float4 sX[2][kSphTile];   // x, y, z, 1/h
-    __shared__ float2 sQ[2][kSphTile];   // q, q sigma
+    __shared__ float4 sX[2][kSphCap];   // x, y, z, 1/h
+    __shared__ float2 sW[2][kSphCap];   // 2q, 2q sigma
     __shared__ float2 red[kBlock];
+    __shared__ int4 s_item;
     const int t = threadIdx.x;
-    const SphSrc zero{make_float4(0.f, 0.f, 0.f, 0.f), make_float2(0.f, 0.f)};
-    for (int g = blockIdx.x; g < n_groups; g += gridDim.x) {
-        const int g0 = group_off[g];
-        const int ng = group_off[g + 1] - g0;
-        const bool gok = ng >= 1 && ng <= kBlock && g0 >= 0 && g0 + ng <= n;
-        if (!gok) {
-            if (t == 0) atomicOr(err, kErrGroup);
-            continue;   // uniform across the workgroup
+    const int n_long = (int)std::min<int64_t>(pl.meta->n_long, pl.cap_long);
+    const int n_items = n_long + pl.meta->n_short;
+    const SphRec zero{make_float4(0.f, 0.f, 0.f, 0.f), make_float2(0.f, 0.f)};
+    for (;;) {
+        if (t == 0) {
+            const int it = atomicAdd(&pl.meta->head, 1);
+            s_item = it < n_long    ? pl.items_long[it]
+                     : it < n_items ? make_int4(pl.items_short[it - n_long], 0, -1, 1)
+                                    : make_int4(-1, 0, -1, 0);
         }
-        const int S = kBlock / ng;
-        const int ti = t % ng, sl = t / ng;
-        const bool lane_on = sl < S;
-        const int tstride = S * (kSphTile / S);   // entries per tile, a multiple of S
-        const int i = g0 + ti;
+        __syncthreads();
+        const int4 item = s_item;   // uniform
+        if (item.x == -1) break;
+        const bool bad = item.x < 0 || item.x >= n_groups || (item.w > 1 && (item.z < 0 || item.z >= pl.cap_split));
+        const Geo c = bad ? Geo{} : load_geo(item.x, n, group_off, n_entries, list_off);
+        if (bad || !c.ok) {   // a slot of a failed plan: nothing to sum
+            __syncthreads();  // every thread has read s_item before it is rewritten
+            continue;
+        }
+        const int S = slices(c.ng);
+        const int ts = tile_len(c.ng);
+        const int64_t e0 = (int64_t)item.y * pl.chunk;
+        const int64_t e1 = std::min<int64_t>(c.len, e0 + pl.chunk);
+        const int64_t len = std::max<int64_t>(e1 - e0, 0);
+        const int64_t lb = c.lb + e0;
+        const int ti = t % c.ng, sl = t / c.ng;
+        const int i = c.g0 + ti;
         const float xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
         const float ihi = 1.f / hh[i];
+        const float kihi = kCbrt4 * ihi;
         float A = 0.f, B = 0.f;
-        int64_t lb, le;
-        list_range(list_off, n_entries, g, lb, le);
-        const int64_t len = le - lb;
-        __syncthreads();   // the previous group's buffers and reduction have been read
-        SphSrc r = (t < tstride && t < len) ? load_src(pos, hh, q, list_idx, lb + t, n, err) : zero;
+        SphRec rec[kSphPer];
+#pragma unroll
+        for (int p = 0; p < kSphPer; p++) {
+            const int e = p * kBlock + t;
+            rec[p] = (e < ts && e < len) ? load_rec(pos, hh, q, list_idx, lb + e, n, err) : zero;
+        }
         int cur = 0;
-        for (int64_t base = 0; base < len; base += tstride) {
-            const int tl = (int)((len - base) < tstride ? (len - base) : tstride);
-            const int rows = (tl + S - 1) / S;
-            sX[cur][t] = r.x;     // entries at or beyond tl are zero weight
-            sQ[cur][t] = r.q;
+        for (int64_t base = 0; base < len; base += ts) {
+            const int tl = (int)((len - base) < ts ? (len - base) : ts);
+            const int rows = (tl + S - 1) / S;   // rows * S <= ts: the lanes stay inside the tile
+#pragma unroll
+            for (int p = 0; p < kSphPer; p++) {
+                sX[cur][p * kBlock + t] = rec[p].x;   // entries at or beyond tl are zero weight
+                sW[cur][p * kBlock + t] = rec[p].w;
+            }
             __syncthreads();
-            // gather this thread's entry of the next tile (lands while this one is computed)
-            const int64_t nxt = base + tstride + t;
-            r = (t < tstride && nxt < len) ? load_src(pos, hh, q, list_idx, lb + nxt, n, err) : zero;
-            if (lane_on) {
-                const float4* xp = sX[cur] + sl * rows;
-                const float2* qp = sQ[cur] + sl * rows;
-#pragma unroll 8
+#pragma unroll
+            for (int p = 0; p < kSphPer; p++) {
+                const int e = p * kBlock + t;
+                const int64_t nx = base + ts + e;
+                rec[p] = (e < ts && nx < len) ? load_rec(pos, hh, q, list_idx, lb + nx, n, err) : zero;
+            }
+            if (sl < S) {
+                const float4* xp = sX[cur] + sl;
+                const float2* wp = sW[cur] + sl;
+#pragma unroll 4
                 for (int m = 0; m < rows; m++) {
-                    const float4 s4 = xp[m];
-                    const float2 w = qp[m];
+                    const float4 s4 = xp[m * S];
+                    const float2 w2 = wp[m * S];
                     const float dx = s4.x - xi, dy = s4.y - yi, dz = s4.z - zi;
                     const float rr = __builtin_amdgcn_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
-                    A = fmaf(w.x, spline_w(rr * ihi), A);
-                    B = fmaf(w.y, spline_w(rr * s4.w), B);
+                    A = fmaf(w2.x, spline_half(rr, ihi, kihi), A);
+                    B = fmaf(w2.y, spline_half(rr, s4.w, kCbrt4 * s4.w), B);
                 }
             }
             cur ^= 1;
         }
         red[t] = make_float2(A, B);
         __syncthreads();
-        if (t < ng) {
+        if (t < c.ng) {
             float a = 0.f, b = 0.f;
             for (int s = 0; s < S; s++) {
-                const float2 v = red[s * ng + t];
+                const float2 v = red[s * c.ng + t];
                 a += v.x;
                 b += v.y;
             }
-            const float sig = (8.f * kInvPi) * ihi * ihi * ihi;
-            out[i] = 0.5f * fmaf(sig, a, b);
+            if (item.w == 1) {
+                const float sig = (8.f * kInvPi) * ihi * ihi * ihi;
+                out[c.g0 + t] = 0.5f * fmaf(sig, a, b);
+            } else {
+                pl.parts[pl.split_base[item.z] + (int64_t)item.y * c.ng + t] = make_float2(a, b);
+            }
         }
     }
 }
+
+// Split groups: chunk partials summed in chunk order, then the output.
+__global__ __launch_bounds__(kBlock) void k_sph_merge(SphPlan pl, int32_t n, const float* __restrict__ hh,
+                                                      int32_t n_groups, const int32_t* __restrict__ group_off,
+                                                      int64_t n_entries, const int64_t* __restrict__ list_off,
+                                                      float* __restrict__ out) {
+    const int n_split = pl.meta->n_split;
+    const int t = threadIdx.x;
+    for (int m = blockIdx.x; m < n_split && m < pl.cap_split; m += gridDim.x) {
+        const int g = pl.split_g[m];
+        if (g < 0 || g >= n_groups) continue;
+        const Geo c = load_geo(g, n, group_off, n_entries, list_off);
+        if (!c.ok || t >= c.ng) continue;
+        const int nc = (int)((c.len + pl.chunk - 1) / pl.chunk);
+        const float2* pp = pl.parts + pl.split_base[m] + t;
+        float a = 0.f, b = 0.f;
+        for (int k = 0; k < nc; k++) {
+            const float2 v = pp[(int64_t)k * c.ng];
+            a += v.x;
+            b += v.y;
+        }
+        const float ih = 1.f / hh[c.g0 + t];
+        out[c.g0 + t] = 0.5f * fmaf((8.f * kInvPi) * ih * ih * ih, a, b);
+    }
+}
+
+int ensure_sph_scratch(otoo_ctx* c, size_t bytes) {
+    if (bytes <= c->sph_bytes) return OTOO_OK;
+    if (c->sph_buf) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        HIP_TRY(c, hipFree(c->sph_buf));
+        c->sph_buf = nullptr;
+        c->sph_bytes = 0;
+    }
+    const size_t want = bytes + bytes / 4;
+    if (hipMalloc(&c->sph_buf, want) != hipSuccess) {
+        (void)hipGetLastError();
+        c->sph_buf = nullptr;
+        return fail(c, OTOO_ENOMEM, "SPH scratch of %zu bytes could not be allocated", want);
+    }
+    c->sph_bytes = want;
+    return OTOO_OK;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 }  // namespace
 
@@ -138,9 +330,43 @@ extern "C" int otoo_sph_sum(otoo_ctx* c, int32_t n, const float* pos, const floa
     if (!pos || !h || !q || !group_off || !list_off || !out || (n_entries && !list_idx))
         return fail(c, OTOO_EINVAL, "null pointer argument");
     HIP_TRY(c, hipSetDevice(c->device));
-    const int blocks = (int)std::min<int64_t>((int64_t)8 * c->num_cu, n_groups);
-    hipLaunchKernelGGL(k_sph, dim3(blocks), dim3(kBlock), 0, c->stream, n, pos, h, q, n_groups, group_off, n_entries,
-                       list_off, list_idx, out, c->errflag);
+    // Chunk length: 2048 entries, doubled until the partial slots of the
+    // split groups (at most 2 kBlock n_entries / C) fit in max(8 n, 2^20).
+    const int64_t budget = std::max<int64_t>(8LL * n, 1LL << 20);
+    int64_t C = 2048;
+    while (2LL * kBlock * (n_entries / C + 1) > budget) C *= 2;
+    SphPlan pl{};
+    pl.chunk = (int32_t)C;
+    pl.cap_long = 5 * (n_entries / C) + n_groups / 64 + 1;
+    pl.cap_split = n_entries / C + 1;
+    pl.cap_parts = 2LL * kBlock * (n_entries / C + 1);
+    const size_t o_short = align256(sizeof(int4) * (size_t)pl.cap_long);
+    const size_t o_sg = o_short + align256(sizeof(int32_t) * (size_t)n_groups);
+    const size_t o_sb = o_sg + align256(sizeof(int32_t) * (size_t)pl.cap_split);
+    const size_t o_parts = o_sb + align256(sizeof(int64_t) * (size_t)pl.cap_split);
+    const size_t total = o_parts + sizeof(float2) * (size_t)pl.cap_parts;
+    int rc = ensure_sph_scratch(c, total);
+    if (rc) return rc;
+    char* b = static_cast<char*>(c->sph_buf);
+    pl.meta = static_cast<SphMeta*>(c->sph_meta);
+    pl.items_long = reinterpret_cast<int4*>(b);
+    pl.items_short = reinterpret_cast<int32_t*>(b + o_short);
+    pl.split_g = reinterpret_cast<int32_t*>(b + o_sg);
+    pl.split_base = reinterpret_cast<int64_t*>(b + o_sb);
+    pl.parts = reinterpret_cast<float2*>(b + o_parts);
+    static int per_cu = 0;   // resident workgroups of k_sph per CU (the same for every device of this build)
+    if (!per_cu) {
+        HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sph, kBlock, 0));
+        per_cu = std::max(per_cu, 1);
+    }
+    hipLaunchKernelGGL(k_sph_reset, dim3(1), dim3(64), 0, c->stream, pl.meta);
+    hipLaunchKernelGGL(k_sph_plan, dim3((n_groups + 255) / 256), dim3(256), 0, c->stream, pl, n, n_groups, group_off,
+                       n_entries, list_off, c->errflag);
+    hipLaunchKernelGGL(k_sph, dim3(per_cu * c->num_cu), dim3(kBlock), 0, c->stream, pl, n, pos, h, q, n_groups,
+                       group_off, n_entries, list_off, list_idx, out, c->errflag);
+    const int merge_blocks = (int)std::min<int64_t>(4LL * c->num_cu, pl.cap_split);
+    hipLaunchKernelGGL(k_sph_merge, dim3(merge_blocks), dim3(kBlock), 0, c->stream, pl, n, h, n_groups, group_off,
+                       n_entries, list_off, out);
     HIP_TRY(c, hipGetLastError());
     return OTOO_OK;
 }

@@ -99,3 +99,25 @@ def test_non_particle_entries_are_reported(ctx):
     with pytest.raises(otoo.OtooError):
         ctx.check()
     ctx.check()
+
+
+def test_long_lists_split_into_chunks_reproducible(ctx):
+    """Particles whose support covers the whole cloud give groups whose lists
+    hold every particle: those lists are cut into chunks taken by different
+    workgroups and merged in chunk order.  Against the oracle, and two calls
+    agree bitwise whatever order the queue hands out the chunks."""
+    rng = np.random.default_rng(26)
+    pos = rng.random((20000, 3))
+    m = np.full(len(pos), 1.0 / len(pos))
+    h = synth.knn_radius(pos, 32)
+    wide = rng.choice(len(pos), 100, replace=False)
+    h[wide] = 2.0                                     # reaches every particle of the unit cube
+    got, pos32, h32, q32, lists, d = _run(ctx, pos, m, h, m, 64)
+    lengths = np.diff(np.asarray(lists.list_off))
+    assert lengths.max() > 4 * 2048                   # several chunks of the smallest chunk length
+    ref = oracle.sph_sum(pos32.astype(np.float64), h32.astype(np.float64), q32.astype(np.float64))
+    _check(got, ref, "uniform cube with wide kernels")
+    again = ctx.sph_sum(d, torch.from_numpy(h32).to(DEV), torch.from_numpy(q32).to(DEV))
+    torch.cuda.synchronize()
+    ctx.check()
+    assert np.array_equal(again.cpu().numpy().astype(np.float64), got)
