@@ -373,8 +373,12 @@ enum otoo_corr_kind {
  * (fixed order) into gcorr [n_groups][24] = {A xyz, Phi, J (xx yy zz xy xz yz),
  * H (xxx yyy zzz xxy xxz xyy yyz xzz yzz xyz), c_g xyz, 0}.  The multipole
  * expansion beyond the monopole is what the paper names but does not use
- * (Sec. 2).  Device pointers; asynchronous; mlp only for OTOO_CORR_MLP;
- * cell_stride 12 for QUAD and MLP (the second-moment tensor). */
+ * (Sec. 2).  A group's cells are summed in segments of 1024 pairs, and the
+ * segment sums are added in segment order, so results do not depend on how
+ * the work is scheduled.  Device pointers; asynchronous; mlp only for
+ * OTOO_CORR_MLP; cell_stride 12 for QUAD and MLP (the second-moment tensor).
+ * The context keeps scratch for the work items and segment sums (grown on
+ * demand). */
 int otoo_correction(otoo_ctx* ctx, int32_t kind, otoo_mlp* mlp, int32_t n, const float* pos, int32_t n_groups,
                     const int32_t* group_off, int64_t n_entries, const int64_t* list_off, const int32_t* list_idx,
                     int64_t n_pairs, const int64_t* pair_off, int32_t n_cells, const float* cell_mom,
@@ -416,7 +420,12 @@ int otoo_last_timing(otoo_ctx* ctx, float* ms_force_kernel, float* ms_total);
  * into a HIP graph held by the context (replacing any previous one), and
  * replay it with otoo_graph_launch on the context stream.  The pointers are
  * baked into the graph; list contents may change between replays as long as
- * n_groups, n_entries and the pointers stay the same. */
+ * n_groups, n_entries and the pointers stay the same.  The graph also names
+ * the context's scratch: a later otoo_force that needs more scratch than the
+ * context holds reallocates it and discards the graph (otoo_graph_launch then
+ * returns EINVAL).  Graphs that a caller captures around calls of this library
+ * must likewise be captured again after a call that grows the context's
+ * scratch. */
 int otoo_graph_capture(otoo_ctx* ctx, int32_t n, const float* pos, const float* mass, int32_t n_groups,
                        const int32_t* group_off, int64_t n_entries, const int64_t* list_off,
                        const int32_t* list_idx, int32_t n_cells, const float* cell_mom, int32_t cell_stride,

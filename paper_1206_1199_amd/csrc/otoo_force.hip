@@ -602,6 +602,11 @@ int ensure_scratch(otoo_ctx* c, size_t bytes) {
     if (bytes <= c->buf_bytes) return OTOO_OK;
     if (c->buf) {
         HIP_TRY(c, hipStreamSynchronize(c->stream));
+        // a captured graph names the old buffer: it cannot be replayed any more
+        if (c->gexec) HIP_TRY(c, hipGraphExecDestroy(c->gexec));
+        if (c->graph) HIP_TRY(c, hipGraphDestroy(c->graph));
+        c->gexec = nullptr;
+        c->graph = nullptr;
         HIP_TRY(c, hipFree(c->buf));
         c->buf = nullptr;
         c->buf_bytes = 0;
@@ -810,6 +815,7 @@ int otoo_destroy(otoo_ctx* c) {
         if (ev) (void)hipEventDestroy(ev);
     if (c->buf) (void)hipFree(c->buf);
     if (c->sph_buf) (void)hipFree(c->sph_buf);
+    if (c->corr_buf) (void)hipFree(c->corr_buf);
     if (c->meta) (void)hipFree(c->meta);
     delete c;
     return OTOO_OK;
@@ -952,7 +958,7 @@ int otoo_graph_capture(otoo_ctx* c, int32_t n, const float* pos, const float* ma
 
 int otoo_graph_launch(otoo_ctx* c) {
     if (!c) return OTOO_EINVAL;
-    if (!c->gexec) return fail(c, OTOO_EINVAL, "no graph captured");
+    if (!c->gexec) return fail(c, OTOO_EINVAL, "no graph captured (or the context's scratch grew since the capture)");
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
     return OTOO_OK;

@@ -384,6 +384,20 @@ __global__ __launch_bounds__(256) void k_mlp_forward_raw(const uint16_t* __restr
 
 enum { kCorrPairs = 0, kCorrQuad = 1, kCorrMlp = 2 };
 
+// Work items of the per-wave correction kernels: the cell pairs of all
+// groups, in pair order (pair_off is their prefix sum), cut into items of
+// kCorrSeg pairs, taken statically by the waves.  A group whose pairs lie in
+// one item writes its row of gcorr there; a group that straddles items leaves
+// a partial expansion in each: in slot R of its first item, and in slot L of
+// every later one.  k_corr_merge adds them in item order, so the result does
+// not depend on the schedule.
+constexpr int kCorrSeg = 1024;
+struct CorrPlan {
+    int64_t n_items;
+    float* part_l;   // [n_items][kCorrStride]: 20 terms, centre xyz, pad
+    float* part_r;   // [n_items][kCorrStride]
+};
+
 struct CorrArgs {
     int32_t n;
     const float* pos;
@@ -404,6 +418,7 @@ struct CorrArgs {
     float gate;               // kCorrMlp: the layers run only where the BF16 feature l/n >= gate
     float* gcorr;             // [n_groups][kCorrStride]
     int32_t* err;
+    CorrPlan plan;            // work items of the wave kernels
 };
 
 // The network through LDS, one workgroup per group (grid-stride over
@@ -659,22 +674,12 @@ __device__ __forceinline__ bool wave_group_box(const CorrArgs& a, int g, int lan
     return ok;
 }
 
-// The group's cell-entry range [lb, lb + nce) of its list, nce = its pair count.
-__device__ __forceinline__ void group_pairs(const CorrArgs& a, int g, int64_t& lb, int64_t& p0, int64_t& nce) {
-    int64_t le;
-    list_range(a.list_off, a.n_entries, g, lb, le);
-    p0 = clamp64(a.pair_off[g], 0, a.n_pairs);
-    const int64_t p1 = clamp64(a.pair_off[g + 1], p0, a.n_pairs);
-    nce = (p1 - p0) < (le - lb) ? (p1 - p0) : (le - lb);
-}
-
-// Sum the lanes' expansion terms and write group g's row (lane 0).
-__device__ __forceinline__ void wave_store_expansion(const CorrArgs& a, int g, int lane, float f[kCorrTerms], float cx,
-                                                     float cy, float cz) {
+// Sum the lanes' expansion terms into a partial slot (lane 0).
+__device__ __forceinline__ void wave_store_part(float* out, int lane, float f[kCorrTerms], float cx, float cy,
+                                                float cz) {
 #pragma unroll
     for (int k = 0; k < kCorrTerms; k++) f[k] = wave_sum(f[k]);
     if (lane == 0) {
-        float* out = a.gcorr + (int64_t)kCorrStride * g;
 #pragma unroll
         for (int k = 0; k < kCorrTerms; k++) out[k] = f[k];
         out[kCorrTerms] = cx;
@@ -684,48 +689,153 @@ __device__ __forceinline__ void wave_store_expansion(const CorrArgs& a, int g, i
     }
 }
 
-// Given or textbook tensors, one wave per group: no workgroup barrier; the
-// group's box and the expansion terms are reduced with lane shuffles.
+// Pair range of group g in pair order, clamped to [0, n_pairs] and made
+// non-decreasing from its start, the same way in every kernel.
+__device__ __forceinline__ void pair_range(const CorrArgs& a, int g, int64_t& p0, int64_t& p1) {
+    p0 = clamp64(a.pair_off[g], 0, a.n_pairs);
+    p1 = clamp64(a.pair_off[g + 1], p0, a.n_pairs);
+}
+
+// The group holding pair q: the last g with pair_off[g] <= q (binary search,
+// wave-uniform).
+__device__ __forceinline__ int group_of_pair(const CorrArgs& a, int64_t q) {
+    int lo = 0, hi = a.n_groups;   // pair_off[lo] <= q is assumed, the answer is in [lo, hi)
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (clamp64(a.pair_off[mid], 0, a.n_pairs) <= q)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Where the expansion of group g over pairs [q0, q1) of item `it` goes.
+__device__ __forceinline__ float* corr_target(const CorrArgs& a, int g, int64_t it, int64_t p0, int64_t p1,
+                                              int64_t q0, int64_t q1) {
+    if (p0 >= q0 && p1 <= q1) return a.gcorr + (int64_t)kCorrStride * g;   // whole group
+    if (p0 < q0) return a.plan.part_l + (int64_t)kCorrStride * it;         // continues from an earlier item
+    return a.plan.part_r + (int64_t)kCorrStride * it;                        // starts here, continues later
+}
+
+// Rows of the groups that straddle items (partials added in item order) and
+// of the groups without cell pairs (zero terms, their box centre): one
+// thread per group.
+__global__ __launch_bounds__(256) void k_corr_merge(CorrArgs a) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < a.n_groups; g += gridDim.x * blockDim.x) {
+        int64_t p0, p1;
+        pair_range(a, g, p0, p1);
+        float* row = a.gcorr + (int64_t)kCorrStride * g;
+        if (p1 == p0) {
+            const int g0 = a.group_off[g], ng = a.group_off[g + 1] - g0;
+            float lo[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f};
+            if (ng >= 1 && ng <= kBlock && g0 >= 0 && g0 + ng <= a.n)
+                for (int k = 0; k < 3; k++) {
+                    lo[k] = hi[k] = a.pos[3 * g0 + k];
+                    for (int p = 1; p < ng; p++) {
+                        lo[k] = fminf(lo[k], a.pos[3 * (g0 + p) + k]);
+                        hi[k] = fmaxf(hi[k], a.pos[3 * (g0 + p) + k]);
+                    }
+                }
+            for (int k = 0; k < kCorrTerms; k++) row[k] = 0.f;
+            for (int k = 0; k < 3; k++) row[kCorrTerms + k] = 0.5f * (lo[k] + hi[k]);
+            row[kCorrTerms + 3] = 0.f;
+            continue;
+        }
+        const int64_t i0 = p0 / kCorrSeg, i1 = (p1 - 1) / kCorrSeg;
+        if (i0 == i1) continue;   // written whole by its item
+        const float* r = a.plan.part_r + (int64_t)kCorrStride * i0;
+        float v[kCorrTerms];
+        for (int k = 0; k < kCorrTerms; k++) v[k] = r[k];
+        for (int64_t i = i0 + 1; i <= i1; i++) {
+            const float* l = a.plan.part_l + (int64_t)kCorrStride * i;
+            for (int k = 0; k < kCorrTerms; k++) v[k] += l[k];
+        }
+        for (int k = 0; k < kCorrTerms; k++) row[k] = v[k];
+        for (int k = 0; k < 4; k++) row[kCorrTerms + k] = r[kCorrTerms + k];
+    }
+}
+
+// One (group, cell) pair of the given or textbook kind: the cell's COM and
+// its tensor, gathered from pair position p of the group's cells.  A position
+// past the item, or an entry that is not a cell (flagged), is not valid.
+struct CorrCell {
+    float com[3];
+    float q[6];
+    bool valid;
+};
+
+template <int KIND>
+__device__ __forceinline__ CorrCell load_corr_cell(const CorrArgs& a, int64_t p, int64_t a1, int64_t p0, int64_t lb,
+                                                   int64_t le) {
+    CorrCell r{};
+    r.valid = false;
+    if (p >= a1) return r;
+    const int64_t k = p - p0;   // the group's cells lead its list
+    const int64_t c = k < le - lb ? (int64_t)a.list_idx[lb + k] - a.n : -1;
+    if (c < 0 || c >= a.n_cells) {
+        atomicOr(a.err, kErrIndex);
+        return r;
+    }
+    const float* cm = a.cell_mom + (int64_t)a.stride * c;
+    r.com[0] = cm[0];
+    r.com[1] = cm[1];
+    r.com[2] = cm[2];
+    if (KIND == kCorrPairs) {
+        for (int m = 0; m < 6; m++) r.q[m] = a.corr[6 * p + m];
+    } else {
+        const float* S = cm + 5;
+        const float tr = S[0] + S[1] + S[2];
+        r.q[0] = 3.f * S[0] - tr;
+        r.q[1] = 3.f * S[1] - tr;
+        r.q[2] = 3.f * S[2] - tr;
+        r.q[3] = 3.f * S[3];
+        r.q[4] = 3.f * S[4];
+        r.q[5] = 3.f * S[5];
+    }
+    r.valid = true;
+    return r;
+}
+
+// Given or textbook tensors, one wave per item (items wave w, w + W, ...):
+// for each group with pairs in the item, its box, then its pairs of the item;
+// no workgroup barrier; the box and the expansion terms are reduced with
+// lane shuffles in a fixed order.
 template <int KIND>
 __global__ __launch_bounds__(256) void k_corr_wave(CorrArgs a) {
     const int lane = threadIdx.x & 63;
-    const int waves = blockDim.x >> 6;
     const float eps2 = a.eps * a.eps;
-    for (int g = blockIdx.x * waves + (threadIdx.x >> 6); g < a.n_groups; g += gridDim.x * waves) {
-        float cx, cy, cz, h;
-        const bool ok = wave_group_box(a, g, lane, cx, cy, cz, h);
-        float f[kCorrTerms];
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t it = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+         it < a.plan.n_items; it += waves) {
+        const int64_t q0 = it * kCorrSeg;
+        const int64_t q1 = q0 + kCorrSeg < a.n_pairs ? q0 + kCorrSeg : a.n_pairs;
+        for (int g = group_of_pair(a, q0); g < a.n_groups; g++) {
+            int64_t p0, p1;
+            pair_range(a, g, p0, p1);
+            if (p0 >= q1) break;
+            const int64_t a0 = p0 > q0 ? p0 : q0, a1 = p1 < q1 ? p1 : q1;
+            if (a1 <= a0) continue;   // no pairs of this group in the item
+            float cx, cy, cz, h;
+            const bool ok = wave_group_box(a, g, lane, cx, cy, cz, h);
+            float f[kCorrTerms];
 #pragma unroll
-        for (int k = 0; k < kCorrTerms; k++) f[k] = 0.f;
-        if (ok) {
-            int64_t lb, p0, nce;
-            group_pairs(a, g, lb, p0, nce);
-            for (int64_t k = lane; k < nce; k += 64) {
-                const int64_t c = (int64_t)a.list_idx[lb + k] - a.n;
-                if (c < 0 || c >= a.n_cells) {
-                    atomicOr(a.err, kErrIndex);
-                    continue;
+            for (int k = 0; k < kCorrTerms; k++) f[k] = 0.f;
+            if (ok) {
+                int64_t lb, le;
+                list_range(a.list_off, a.n_entries, g, lb, le);
+                // software pipeline: the next pair's cell record is gathered while this one is summed
+                CorrCell cur = load_corr_cell<KIND>(a, a0 + lane, a1, p0, lb, le);
+                for (int64_t p = a0 + lane; p < a1; p += 64) {
+                    const CorrCell nxt = load_corr_cell<KIND>(a, p + 64, a1, p0, lb, le);
+                    if (cur.valid) quad_expand_add(cx - cur.com[0], cy - cur.com[1], cz - cur.com[2], cur.q, eps2, f);
+                    cur = nxt;
                 }
-                const float* cm = a.cell_mom + (int64_t)a.stride * c;
-                float Q[6];
-                if (KIND == kCorrPairs) {
-                    for (int m = 0; m < 6; m++) Q[m] = a.corr[6 * (p0 + k) + m];
-                } else {
-                    const float* S = cm + 5;
-                    const float tr = S[0] + S[1] + S[2];
-                    Q[0] = 3.f * S[0] - tr;
-                    Q[1] = 3.f * S[1] - tr;
-                    Q[2] = 3.f * S[2] - tr;
-                    Q[3] = 3.f * S[3];
-                    Q[4] = 3.f * S[4];
-                    Q[5] = 3.f * S[5];
-                }
-                quad_expand_add(cx - cm[0], cy - cm[1], cz - cm[2], Q, eps2, f);
+            } else if (lane == 0) {
+                atomicOr(a.err, kErrGroup);
             }
-        } else if (lane == 0) {
-            atomicOr(a.err, kErrGroup);
+            wave_store_part(corr_target(a, g, it, p0, p1, q0, q1), lane, f, cx, cy, cz);
         }
-        wave_store_expansion(a, g, lane, f, cx, cy, cz);
     }
 }
 
@@ -761,17 +871,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
     for (int ks = 0; ks < 2; ks++) w3a[ks] = ld_perm(a.wbf + OFFB_W3T, NH, r16, ks, q);
     __syncthreads();
-    for (int g = blockIdx.x * 4 + w; g < a.n_groups; g += gridDim.x * 4) {
+    const int64_t waves = (int64_t)gridDim.x * 4;
+    for (int64_t it = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w); it < a.plan.n_items; it += waves)
+    for (int g = group_of_pair(a, it * kCorrSeg); g < a.n_groups; g++) {
+        const int64_t q0 = it * kCorrSeg;
+        const int64_t q1 = q0 + kCorrSeg < a.n_pairs ? q0 + kCorrSeg : a.n_pairs;
+        int64_t p0, p1;
+        pair_range(a, g, p0, p1);
+        if (p0 >= q1) break;
+        const int64_t a0 = p0 > q0 ? p0 : q0, a1 = p1 < q1 ? p1 : q1;
+        if (a1 <= a0) continue;   // no pairs of this group in the item
         float cx, cy, cz, h;
         const bool ok = wave_group_box(a, g, lane, cx, cy, cz, h);
         float f[kCorrTerms];
 #pragma unroll
         for (int k = 0; k < kCorrTerms; k++) f[k] = 0.f;
-        int64_t lb = 0, p0 = 0, nce = 0;
+        int64_t lb = 0, k0 = 0, k1 = 0;   // this item's part of the group's list: positions [k0, k1)
         if (ok) {
-            group_pairs(a, g, lb, p0, nce);
-            if (nce > INT32_MAX) {   // queue slots hold 32-bit list positions
-                nce = INT32_MAX;
+            int64_t le;
+            list_range(a.list_off, a.n_entries, g, lb, le);
+            k0 = a0 - p0;
+            k1 = (a1 - p0) < (le - lb) ? (a1 - p0) : (le - lb);
+            if (k1 > INT32_MAX) {   // queue slots hold 32-bit list positions
+                k1 = INT32_MAX;
                 if (lane == 0) atomicOr(a.err, kErrCapacity);
             }
         } else if (lane == 0) {
@@ -838,10 +960,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             }
         };
         int pend = 0;   // uniform within the wave
-        for (int64_t base = 0; base < nce; base += 64) {
+        for (int64_t base = k0; base < k1; base += 64) {
             const int64_t k = base + lane;
             bool gated = false;
-            if (k < nce) {
+            if (k < k1) {
                 const int64_t c = (int64_t)a.list_idx[lb + k] - a.n;
                 if (c >= 0 && c < a.n_cells) {
                     const float* cm = a.cell_mom + 12 * c;
@@ -875,7 +997,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             }
         }
         if (pend > 0) run_net(pend);
-        wave_store_expansion(a, g, lane, f, cx, cy, cz);
+        wave_store_part(corr_target(a, g, it, p0, p1, q0, q1), lane, f, cx, cy, cz);
     }
 }
 
@@ -1363,6 +1485,27 @@ int run_backward(otoo_mlp* m, const uint16_t* X, const float* aux, int64_t n_sam
     return OTOO_OK;
 }
 
+int ensure_corr_scratch(otoo_ctx* c, size_t bytes) {
+    if (bytes <= c->corr_bytes) return OTOO_OK;
+    if (c->corr_buf) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        HIP_TRY(c, hipFree(c->corr_buf));
+        c->corr_buf = nullptr;
+        c->corr_bytes = 0;
+    }
+    const size_t want = bytes + bytes / 4;
+    if (hipMalloc(&c->corr_buf, want) != hipSuccess) {
+        (void)hipGetLastError();
+        c->corr_buf = nullptr;
+        return fail(c, OTOO_ENOMEM, "correction scratch of %zu bytes could not be allocated", want);
+    }
+    c->corr_bytes = want;
+    return OTOO_OK;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+
 }  // namespace
 
 extern "C" {
@@ -1551,22 +1694,42 @@ int otoo_correction(otoo_ctx* c, int32_t kind, otoo_mlp* m, int32_t n, const flo
     }
     CorrArgs ca{n,        pos,     n_groups, group_off, list_off, n_entries, list_idx,
                 pair_off, n_pairs, n_cells,  cell_mom,  cell_stride, eps,   corr,
-                m ? m->wbf : nullptr, m ? m->master : nullptr, m ? m->gate : 0.f, gcorr, c->errflag};
-    // one wave per group (four per workgroup) for the given and textbook tensors and the
-    // register-resident network; one workgroup per group for the LDS-staged network
-    const int64_t wave_blocks = ((int64_t)n_groups + 3) / 4;
-    if (kind == OTOO_CORR_PAIRS)
-        hipLaunchKernelGGL(k_corr_wave<kCorrPairs>, dim3((int)std::min<int64_t>(16LL * c->num_cu, wave_blocks)),
-                           dim3(256), 0, c->stream, ca);
-    else if (kind == OTOO_CORR_QUAD)
-        hipLaunchKernelGGL(k_corr_wave<kCorrQuad>, dim3((int)std::min<int64_t>(16LL * c->num_cu, wave_blocks)),
-                           dim3(256), 0, c->stream, ca);
-    else if (c->tune.net_kernel == 1)
-        hipLaunchKernelGGL(k_corr_group, dim3((int)std::min<int64_t>(3LL * c->num_cu, n_groups)),
-                           dim3(256), 0, c->stream, ca);
-    else
-        hipLaunchKernelGGL(k_corr_net, dim3((int)std::min<int64_t>(2LL * c->num_cu, wave_blocks)), dim3(256), 0,
+                m ? m->wbf : nullptr, m ? m->master : nullptr, m ? m->gate : 0.f, gcorr, c->errflag, CorrPlan{}};
+    if (kind == OTOO_CORR_MLP && c->tune.net_kernel == 1) {   // one workgroup per group, LDS-staged network
+        hipLaunchKernelGGL(k_corr_group, dim3((int)std::min<int64_t>(3LL * c->num_cu, n_groups)), dim3(256), 0,
                            c->stream, ca);
+        HIP_TRY(c, hipGetLastError());
+        return OTOO_OK;
+    }
+    // one wave per item of kCorrSeg pairs (items taken statically), then the rows of the groups
+    // that straddle items or have no pairs
+    CorrPlan& pl = ca.plan;
+    pl.n_items = (n_pairs + kCorrSeg - 1) / kCorrSeg;
+    const size_t part_bytes = align256(sizeof(float) * kCorrStride * (size_t)std::max<int64_t>(pl.n_items, 1));
+    int rc = ensure_corr_scratch(c, 2 * part_bytes);
+    if (rc) return rc;
+    pl.part_l = static_cast<float*>(c->corr_buf);
+    pl.part_r = reinterpret_cast<float*>(static_cast<char*>(c->corr_buf) + part_bytes);
+    // resident workgroups per CU of each kernel (the same for every device of this build)
+    static int occ[3] = {0, 0, 0};
+    const int which = kind == OTOO_CORR_PAIRS ? 0 : kind == OTOO_CORR_QUAD ? 1 : 2;
+    if (!occ[which]) {
+        const void* fn = which == 0   ? reinterpret_cast<const void*>(&k_corr_wave<kCorrPairs>)
+                         : which == 1 ? reinterpret_cast<const void*>(&k_corr_wave<kCorrQuad>)
+                                      : reinterpret_cast<const void*>(&k_corr_net);
+        HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[which], fn, 256, 0));
+        occ[which] = std::max(occ[which], 1);
+    }
+    const int64_t item_blocks = std::max<int64_t>((pl.n_items + 3) / 4, 1);
+    const dim3 grid((unsigned)std::min<int64_t>((int64_t)occ[which] * c->num_cu, item_blocks));
+    if (which == 0)
+        hipLaunchKernelGGL(k_corr_wave<kCorrPairs>, grid, dim3(256), 0, c->stream, ca);
+    else if (which == 1)
+        hipLaunchKernelGGL(k_corr_wave<kCorrQuad>, grid, dim3(256), 0, c->stream, ca);
+    else
+        hipLaunchKernelGGL(k_corr_net, grid, dim3(256), 0, c->stream, ca);
+    const int merge_blocks = (int)std::min<int64_t>(4LL * c->num_cu, ((int64_t)n_groups + 255) / 256);
+    hipLaunchKernelGGL(k_corr_merge, dim3(merge_blocks), dim3(256), 0, c->stream, ca);
     HIP_TRY(c, hipGetLastError());
     return OTOO_OK;
 }

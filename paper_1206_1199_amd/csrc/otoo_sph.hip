@@ -198,7 +198,11 @@ __global__ __launch_bounds__(kBlock) void k_sph(SphPlan pl, int32_t n, const flo
                                     : make_int4(-1, 0, -1, 0);
         }
         __syncthreads();
-        const int4 item = s_item;   // uniform
+        // the same item for every thread; readfirstlane makes that visible to the
+        // compiler, so the item loop and its exits are wave-uniform scalar branches
+        const int4 si = s_item;
+        const int4 item = make_int4(__builtin_amdgcn_readfirstlane(si.x), __builtin_amdgcn_readfirstlane(si.y),
+                                    __builtin_amdgcn_readfirstlane(si.z), __builtin_amdgcn_readfirstlane(si.w));
         if (item.x == -1) break;
         const bool bad = item.x < 0 || item.x >= n_groups || (item.w > 1 && (item.z < 0 || item.z >= pl.cap_split));
         const Geo c = bad ? Geo{} : load_geo(item.x, n, group_off, n_entries, list_off);

@@ -335,3 +335,53 @@ def test_full_size_workloads_sampled(ctx, workload):
     sample = synth.sample_idx(len(m), 2048, seed=seed)
     a_ref, p_ref = _oracle(pos32, mass32, lists, cm, eps, tgt=sample)
     _assert_parity(acc[sample], pot[sample], a_ref, p_ref, f"{workload} sample ({source}: {sched})")
+
+
+def test_corrections_split_into_segments(ctx):
+    """Groups with more cell pairs than one segment (1024) are summed by
+    several waves and their segment sums merged in segment order; groups
+    with fewer take one wave.  The textbook quadrupole through both kinds of
+    item meets the parity bar, and a second call gives the same bits."""
+    from oracle import mlp as omlp
+    pos, m = synth.plummer(32768, seed=6)
+    t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.25, 256, stride=12)
+    nce = np.asarray(lists.n_cellent)
+    assert (nce > 2 * 1024).any() and (nce <= 1024).any()
+    gc = ctx.correction(d, otoo.CORR_QUAD, 0.01)
+    acc, pot = ctx.force(d, 0.01, gcorr=gc)
+    torch.cuda.synchronize()
+    ctx.check()
+    cells = np.concatenate([lists.list_idx[lists.list_off[g]:lists.list_off[g] + lists.n_cellent[g]]
+                            for g in range(lists.n_groups)]) - t.n
+    q_ref = omlp.exact_quadrupole(cm[cells, 5:11].astype(np.float64))
+    sample = synth.sample_idx(len(m), 4096, seed=7)
+    a_ref, p_ref = _oracle_quad(pos32, mass32, lists, cm, 0.01, q_ref, tgt=sample)
+    _assert_parity(acc.cpu().numpy().astype(np.float64)[sample], pot.cpu().numpy()[sample], a_ref, p_ref,
+                   "quadrupole, split groups")
+    gc2 = ctx.correction(d, otoo.CORR_QUAD, 0.01)
+    torch.cuda.synchronize()
+    assert torch.equal(gc, gc2)
+
+
+def test_captured_graph_dropped_when_scratch_grows():
+    """A graph captured on a context names its scratch; a later call that
+    grows the scratch discards the graph, so replaying it fails cleanly
+    instead of touching freed memory.  A new capture works again."""
+    c = otoo.Context(0)
+    pos, m = synth.plummer(2000, seed=8)
+    _, _, _, _, _, d_small = _setup(pos, m, 0.5, 64)
+    out = c.outputs(d_small.n)
+    c.graph_capture(d_small, 0.01, out)
+    c.graph_launch()
+    torch.cuda.synchronize()
+    pos, m = synth.plummer(16384, seed=9)
+    _, lists, pos32, mass32, cm, d_big = _setup(pos, m, 0.5, 64)
+    acc, pot = _gpu(c, d_big, 0.01)
+    with pytest.raises(otoo.OtooError) as e:
+        c.graph_launch()
+    assert e.value.code == otoo.EINVAL
+    out_big = c.outputs(d_big.n)
+    c.graph_capture(d_big, 0.01, out_big)
+    c.graph_launch()
+    torch.cuda.synchronize()
+    assert np.array_equal(out_big[0].cpu().numpy().astype(np.float64), acc)
