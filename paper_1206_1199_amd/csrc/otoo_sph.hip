@@ -165,7 +165,8 @@ __global__ __launch_bounds__(256) void k_sph_plan(SphPlan pl, int32_t n, int32_t
     }
 }
 
-// Persistent workgroups pull items from the queue (long items first).  Per
+// Persistent workgroups pull items from the queue (long items first), a
+// batch of consecutive items per atomic.  Per
 // item, lanes are (target, slice): with ng targets, S = 256 / ng slices;
 // slice s of a staged tile takes entries s, s + S, s + 2S, ..., so the
 // slices that share a wave read consecutive records (no bank conflicts) and
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(256) void k_sph_plan(SphPlan pl, int32_t n, int32_t
 // partial sums are combined in slice order, so results are reproducible.
 // Sums A = sum q_j w(r/h_i) and B = sum q_j sigma_j w(r/h_j) give
 // out_i = (sigma_i A + B) / 2 with sigma = 8 / (pi h^3).
-__global__ __launch_bounds__(kBlock) void k_sph(SphPlan pl, int32_t n, const float* __restrict__ pos,
+__global__ __launch_bounds__(kBlock) void k_sph(SphPlan pl, int32_t batch, int32_t n, const float* __restrict__ pos,
                                                 const float* __restrict__ hh, const float* __restrict__ q,
                                                 int32_t n_groups, const int32_t* __restrict__ group_off,
                                                 int64_t n_entries,
@@ -190,9 +191,15 @@ __global__ __launch_bounds__(kBlock) void k_sph(SphPlan pl, int32_t n, const flo
     const int n_long = (int)std::min<int64_t>(pl.meta->n_long, pl.cap_long);
     const int n_items = n_long + pl.meta->n_short;
     const SphRec zero{make_float4(0.f, 0.f, 0.f, 0.f), make_float2(0.f, 0.f)};
+    int next_it = 0, batch_left = 0;   // thread 0's batch of consecutive items
     for (;;) {
         if (t == 0) {
-            const int it = atomicAdd(&pl.meta->head, 1);
+            if (batch_left == 0) {   // one atomic per batch: a single counter serves every workgroup
+                next_it = atomicAdd(&pl.meta->head, batch);
+                batch_left = batch;
+            }
+            const int it = next_it++;
+            batch_left--;
             s_item = it < n_long    ? pl.items_long[it]
                      : it < n_items ? make_int4(pl.items_short[it - n_long], 0, -1, 1)
                                     : make_int4(-1, 0, -1, 0);
@@ -366,8 +373,11 @@ extern "C" int otoo_sph_sum(otoo_ctx* c, int32_t n, const float* pos, const floa
     hipLaunchKernelGGL(k_sph_reset, dim3(1), dim3(64), 0, c->stream, pl.meta);
     hipLaunchKernelGGL(k_sph_plan, dim3((n_groups + 255) / 256), dim3(256), 0, c->stream, pl, n, n_groups, group_off,
                        n_entries, list_off, c->errflag);
-    hipLaunchKernelGGL(k_sph, dim3(per_cu * c->num_cu), dim3(kBlock), 0, c->stream, pl, n, pos, h, q, n_groups,
-                       group_off, n_entries, list_off, list_idx, out, c->errflag);
+    // items per queue access: at least 16 batches per workgroup (there are at least n_groups items)
+    const int blocks = per_cu * c->num_cu;
+    const int batch = (int)std::max<int64_t>(1, std::min<int64_t>(8, (int64_t)n_groups / (16LL * blocks)));
+    hipLaunchKernelGGL(k_sph, dim3(blocks), dim3(kBlock), 0, c->stream, pl, batch, n, pos, h, q, n_groups, group_off,
+                       n_entries, list_off, list_idx, out, c->errflag);
     const int merge_blocks = (int)std::min<int64_t>(4LL * c->num_cu, pl.cap_split);
     hipLaunchKernelGGL(k_sph_merge, dim3(merge_blocks), dim3(kBlock), 0, c->stream, pl, n, h, n_groups, group_off,
                        n_entries, list_off, out);
