@@ -373,12 +373,12 @@ enum otoo_corr_kind {
  * (fixed order) into gcorr [n_groups][24] = {A xyz, Phi, J (xx yy zz xy xz yz),
  * H (xxx yyy zzz xxy xxz xyy yyz xzz yzz xyz), c_g xyz, 0}.  The multipole
  * expansion beyond the monopole is what the paper names but does not use
- * (Sec. 2).  A group's cells are summed in segments of 1024 pairs, and the
- * segment sums are added in segment order, so results do not depend on how
- * the work is scheduled.  Device pointers; asynchronous; mlp only for
- * OTOO_CORR_MLP; cell_stride 12 for QUAD and MLP (the second-moment tensor).
- * The context keeps scratch for the work items and segment sums (grown on
- * demand). */
+ * (Sec. 2).  The work is cut into items of 1024 consecutive (group, cell)
+ * pairs in pair order; a group whose pairs span several items has its item
+ * sums added in item order, so results do not depend on how the work is
+ * scheduled.  Device pointers; asynchronous; mlp only for OTOO_CORR_MLP;
+ * cell_stride 12 for QUAD and MLP (the second-moment tensor).  The context
+ * keeps scratch for the item sums (grown on demand). */
 int otoo_correction(otoo_ctx* ctx, int32_t kind, otoo_mlp* mlp, int32_t n, const float* pos, int32_t n_groups,
                     const int32_t* group_off, int64_t n_entries, const int64_t* list_off, const int32_t* list_idx,
                     int64_t n_pairs, const int64_t* pair_off, int32_t n_cells, const float* cell_mom,

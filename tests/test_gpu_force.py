@@ -385,3 +385,24 @@ def test_captured_graph_dropped_when_scratch_grows():
     c.graph_launch()
     torch.cuda.synchronize()
     assert np.array_equal(out_big[0].cpu().numpy().astype(np.float64), acc)
+
+
+def test_correction_without_cells(ctx):
+    """theta = 0 opens every cell: no group has cell pairs, so every row of the
+    correction is zero terms with the group's box centre (written by the
+    merge pass), and the corrected force equals the plain one bit for bit."""
+    pos, m = synth.plummer(3000, seed=13)
+    t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.0, 64, stride=12)
+    assert int(lists.pair_off[-1]) == 0
+    gc = ctx.correction(d, otoo.CORR_QUAD, 0.01)
+    acc, pot = ctx.force(d, 0.01, gcorr=gc)
+    torch.cuda.synchronize()
+    ctx.check()
+    g = gc.cpu().numpy()
+    assert np.all(g[:, :20] == 0) and np.all(g[:, 23] == 0)
+    go = np.asarray(lists.group_off)
+    centre = np.stack([0.5 * (pos32[go[i]:go[i + 1]].min(0) + pos32[go[i]:go[i + 1]].max(0))
+                       for i in range(lists.n_groups)])
+    np.testing.assert_allclose(g[:, 20:23], centre, rtol=0, atol=1e-6)
+    a0, p0 = _gpu(ctx, d, 0.01)
+    assert np.array_equal(acc.cpu().numpy().astype(np.float64), a0) and np.array_equal(pot.cpu().numpy(), p0)
