@@ -26,6 +26,8 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <new>
 #include <memory>
 #include <vector>
@@ -71,6 +73,23 @@ inline uint64_t hilbert_key(uint32_t x0, uint32_t x1, uint32_t x2) {
 
 }  // namespace
 
+namespace {
+struct WalkCell;
+}
+
+// Walk inputs that depend only on the tree and the opening criterion (the
+// per-cell records) or the grouping (group offsets).  They are kept on the
+// tree, so that a step walked in batches of groups builds them once; the
+// shared pointers keep a set alive for a walk that is still using it.
+struct WalkCache {
+    std::mutex mu;
+    int mac = -1;
+    double theta = 0.0, delta = 0.0, m_limit = 0.0;
+    std::shared_ptr<const std::vector<WalkCell>> cells;
+    int gmode = -1, gmax = -1;
+    std::shared_ptr<const std::vector<int64_t>> goff;
+};
+
 struct otoo_tree {
     int64_t n = 0;
     double lo[3] = {0, 0, 0};
@@ -93,6 +112,7 @@ struct otoo_tree {
     // moments
     std::vector<double> M, com, S6, s, bmax, centre, csize;
     int32_t depth = 0;
+    mutable WalkCache cache;
     int64_t n_cells() const { return (int64_t)first.size(); }
 };
 
@@ -282,6 +302,46 @@ void walk_groups(const otoo_tree* t, const std::vector<int64_t>& goff, const std
     L->pub.n_cellent = L->n_cellent.data();
     L->pub.group_box = L->group_box.data();
     L->pub.impl = L;
+}
+
+// The per-cell records with the acceptance radius of the criterion (ra:
+// accept iff d_min > ra), from the tree's cache or built and cached.
+std::shared_ptr<const std::vector<WalkCell>> cached_cells(const otoo_tree* t, const otoo_walk_params& wp) {
+    WalkCache& k = t->cache;
+    std::lock_guard<std::mutex> lock(k.mu);
+    if (k.cells && k.mac == wp.mac && k.theta == wp.theta && k.delta == wp.delta && k.m_limit == wp.m_limit)
+        return k.cells;
+    auto cells = std::make_shared<std::vector<WalkCell>>(walk_cells(t));
+    const int64_t nc = t->n_cells();
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; c++) {
+        double& rc = (*cells)[c].ra;
+        if (wp.mac == OTOO_MAC_BH) {
+            rc = wp.theta > 0.0 ? t->csize[c] / wp.theta + t->s[c] : INFINITY;
+        } else if (t->M[c] > wp.m_limit) {
+            rc = 2.0 * t->side;
+        } else {
+            const double b = t->bmax[c], B2 = t->S6[6 * c] + t->S6[6 * c + 1] + t->S6[6 * c + 2];
+            rc = b / 2.0 + std::sqrt(b * b / 4.0 + std::sqrt(3.0 * B2 / wp.delta));
+        }
+    }
+    k.mac = wp.mac;
+    k.theta = wp.theta;
+    k.delta = wp.delta;
+    k.m_limit = wp.m_limit;
+    k.cells = cells;
+    return k.cells;
+}
+
+// The group offsets of a grouping, from the tree's cache or built and cached.
+std::shared_ptr<const std::vector<int64_t>> cached_groups(const otoo_tree* t, int mode, int g_max) {
+    WalkCache& k = t->cache;
+    std::lock_guard<std::mutex> lock(k.mu);
+    if (k.goff && k.gmode == mode && k.gmax == g_max) return k.goff;
+    k.goff = std::make_shared<const std::vector<int64_t>>(make_groups(t, mode, g_max));
+    k.gmode = mode;
+    k.gmax = g_max;
+    return k.goff;
 }
 
 }  // namespace
@@ -597,31 +657,16 @@ int otoo_tree_walk_range(const otoo_tree* t, const otoo_walk_params* wp, int32_t
     otoo_lists_impl* L = new (std::nothrow) otoo_lists_impl();
     if (!L) return OTOO_ENOMEM;
     try {
-        const int64_t nc = t->n_cells();
-        std::vector<int64_t> goff = make_groups(t, wp->group_mode, wp->g_max);
-        const int64_t ng_all = (int64_t)goff.size() - 1;
+        const std::shared_ptr<const std::vector<int64_t>> all = cached_groups(t, wp->group_mode, wp->g_max);
+        const int64_t ng_all = (int64_t)all->size() - 1;
         if (g_begin >= ng_all) {
             delete L;
             return OTOO_EINVAL;
         }
         const int64_t g1 = std::min<int64_t>(g_end, ng_all);
-        goff = std::vector<int64_t>(goff.begin() + g_begin, goff.begin() + g1 + 1);
-        // acceptance radius per cell (ra): accept iff d_min > ra
-        std::vector<WalkCell> cells = walk_cells(t);
-        for (int64_t c = 0; c < nc; c++) {
-            double& rc = cells[c].ra;
-            if (wp->mac == OTOO_MAC_BH) {
-                rc = wp->theta > 0.0 ? t->csize[c] / wp->theta + t->s[c] : INFINITY;
-            } else {
-                if (t->M[c] > wp->m_limit) {
-                    rc = 2.0 * t->side;
-                } else {
-                    const double b = t->bmax[c], B2 = t->S6[6 * c] + t->S6[6 * c + 1] + t->S6[6 * c + 2];
-                    rc = b / 2.0 + std::sqrt(b * b / 4.0 + std::sqrt(3.0 * B2 / wp->delta));
-                }
-            }
-        }
-        walk_groups(t, goff, cells, [](const WalkCell& w, double dmin, int64_t) { return dmin > w.ra ? kAccept : kOpen; },
+        const std::vector<int64_t> goff(all->begin() + g_begin, all->begin() + g1 + 1);
+        const std::shared_ptr<const std::vector<WalkCell>> cells = cached_cells(t, *wp);
+        walk_groups(t, goff, *cells, [](const WalkCell& w, double dmin, int64_t) { return dmin > w.ra ? kAccept : kOpen; },
                     L);
     } catch (const std::bad_alloc&) {
         delete L;
