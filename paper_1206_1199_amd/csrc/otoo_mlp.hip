@@ -839,11 +839,12 @@ __global__ __launch_bounds__(256) void k_corr_wave(CorrArgs a) {
     }
 }
 
-// Register-resident network, one wave per group.  The wave walks its
-// group's cell entries 64 at a time: a pair the gate keeps out gets the skip
-// term alone (the textbook quadrupole) at once; a gated pair is appended to
-// the wave's LDS queue (ballot order).  Whenever 64 are queued, and once at
-// the end of the group, the wave runs the network on them: weights are the
+// Register-resident network, one wave per item (the items of k_corr_wave).
+// For each group with pairs in the item the wave walks those cell entries 64
+// at a time: a pair the gate keeps out gets the skip term alone (the textbook
+// quadrupole) at once; a gated pair is appended to the wave's LDS queue
+// (ballot order).  Whenever 64 are queued, and once at the end of the
+// group's part of the item, the wave runs the network on them: weights are the
 // MFMA's A operand, held in registers for the whole kernel; the 64 pairs are
 // the N dimension in four steps of 16, and each layer's output layout is
 // the next layer's B layout once the K index is permuted (K slot q*8 + j of
