@@ -396,6 +396,7 @@ struct CorrPlan {
     int64_t n_items;
     float* part_l;   // [n_items][kCorrStride]: 20 terms, centre xyz, pad
     float* part_r;   // [n_items][kCorrStride]
+    float4* box;     // [n_groups]: box centre xyz and half-diagonal, -1 for a malformed group
 };
 
 struct CorrArgs {
@@ -674,6 +675,30 @@ __device__ __forceinline__ bool wave_group_box(const CorrArgs& a, int g, int lan
     return ok;
 }
 
+// Each group's bounding box once, for every item that holds pairs of it:
+// one wave per group.
+__global__ __launch_bounds__(256) void k_corr_box(CorrArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (g >= a.n_groups) return;   // whole waves: g is the same for the wave's lanes
+    float cx, cy, cz, h;
+    const bool ok = wave_group_box(a, g, lane, cx, cy, cz, h);
+    if (lane == 0) {
+        a.plan.box[g] = make_float4(cx, cy, cz, ok ? h : -1.f);
+        if (!ok) atomicOr(a.err, kErrGroup);
+    }
+}
+
+// Group g's box from k_corr_box (wave-uniform); false for a malformed group.
+__device__ __forceinline__ bool group_box(const CorrArgs& a, int g, float& cx, float& cy, float& cz, float& h) {
+    const float4 b = a.plan.box[g];
+    cx = b.x;
+    cy = b.y;
+    cz = b.z;
+    h = b.w;
+    return b.w >= 0.f;
+}
+
 // Sum the lanes' expansion terms into a partial slot (lane 0).
 __device__ __forceinline__ void wave_store_part(float* out, int lane, float f[kCorrTerms], float cx, float cy,
                                                 float cz) {
@@ -727,18 +752,11 @@ __global__ __launch_bounds__(256) void k_corr_merge(CorrArgs a) {
         pair_range(a, g, p0, p1);
         float* row = a.gcorr + (int64_t)kCorrStride * g;
         if (p1 == p0) {
-            const int g0 = a.group_off[g], ng = a.group_off[g + 1] - g0;
-            float lo[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f};
-            if (ng >= 1 && ng <= kBlock && g0 >= 0 && g0 + ng <= a.n)
-                for (int k = 0; k < 3; k++) {
-                    lo[k] = hi[k] = a.pos[3 * g0 + k];
-                    for (int p = 1; p < ng; p++) {
-                        lo[k] = fminf(lo[k], a.pos[3 * (g0 + p) + k]);
-                        hi[k] = fmaxf(hi[k], a.pos[3 * (g0 + p) + k]);
-                    }
-                }
+            const float4 b = a.plan.box[g];
             for (int k = 0; k < kCorrTerms; k++) row[k] = 0.f;
-            for (int k = 0; k < 3; k++) row[kCorrTerms + k] = 0.5f * (lo[k] + hi[k]);
+            row[kCorrTerms] = b.x;
+            row[kCorrTerms + 1] = b.y;
+            row[kCorrTerms + 2] = b.z;
             row[kCorrTerms + 3] = 0.f;
             continue;
         }
@@ -817,7 +835,7 @@ __global__ __launch_bounds__(256) void k_corr_wave(CorrArgs a) {
             const int64_t a0 = p0 > q0 ? p0 : q0, a1 = p1 < q1 ? p1 : q1;
             if (a1 <= a0) continue;   // no pairs of this group in the item
             float cx, cy, cz, h;
-            const bool ok = wave_group_box(a, g, lane, cx, cy, cz, h);
+            const bool ok = group_box(a, g, cx, cy, cz, h);
             float f[kCorrTerms];
 #pragma unroll
             for (int k = 0; k < kCorrTerms; k++) f[k] = 0.f;
@@ -831,9 +849,7 @@ __global__ __launch_bounds__(256) void k_corr_wave(CorrArgs a) {
                     if (cur.valid) quad_expand_add(cx - cur.com[0], cy - cur.com[1], cz - cur.com[2], cur.q, eps2, f);
                     cur = nxt;
                 }
-            } else if (lane == 0) {
-                atomicOr(a.err, kErrGroup);
-            }
+            }   // a malformed group was flagged by k_corr_box
             wave_store_part(corr_target(a, g, it, p0, p1, q0, q1), lane, f, cx, cy, cz);
         }
     }
@@ -883,7 +899,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int64_t a0 = p0 > q0 ? p0 : q0, a1 = p1 < q1 ? p1 : q1;
         if (a1 <= a0) continue;   // no pairs of this group in the item
         float cx, cy, cz, h;
-        const bool ok = wave_group_box(a, g, lane, cx, cy, cz, h);
+        const bool ok = group_box(a, g, cx, cy, cz, h);
         float f[kCorrTerms];
 #pragma unroll
         for (int k = 0; k < kCorrTerms; k++) f[k] = 0.f;
@@ -897,9 +913,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 k1 = INT32_MAX;
                 if (lane == 0) atomicOr(a.err, kErrCapacity);
             }
-        } else if (lane == 0) {
-            atomicOr(a.err, kErrGroup);
-        }
+        }   // a malformed group was flagged by k_corr_box
         // the network on queue slots [0, cnt): features, layers, skip term, expansion
         auto run_net = [&](int cnt) {
             const bool has = lane < cnt;
@@ -1707,10 +1721,12 @@ int otoo_correction(otoo_ctx* c, int32_t kind, otoo_mlp* m, int32_t n, const flo
     CorrPlan& pl = ca.plan;
     pl.n_items = (n_pairs + kCorrSeg - 1) / kCorrSeg;
     const size_t part_bytes = align256(sizeof(float) * kCorrStride * (size_t)std::max<int64_t>(pl.n_items, 1));
-    int rc = ensure_corr_scratch(c, 2 * part_bytes);
+    const size_t box_bytes = align256(sizeof(float4) * (size_t)n_groups);
+    int rc = ensure_corr_scratch(c, 2 * part_bytes + box_bytes);
     if (rc) return rc;
     pl.part_l = static_cast<float*>(c->corr_buf);
     pl.part_r = reinterpret_cast<float*>(static_cast<char*>(c->corr_buf) + part_bytes);
+    pl.box = reinterpret_cast<float4*>(static_cast<char*>(c->corr_buf) + 2 * part_bytes);
     // resident workgroups per CU of each kernel (the same for every device of this build)
     static int occ[3] = {0, 0, 0};
     const int which = kind == OTOO_CORR_PAIRS ? 0 : kind == OTOO_CORR_QUAD ? 1 : 2;
@@ -1721,6 +1737,7 @@ int otoo_correction(otoo_ctx* c, int32_t kind, otoo_mlp* m, int32_t n, const flo
         HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[which], fn, 256, 0));
         occ[which] = std::max(occ[which], 1);
     }
+    hipLaunchKernelGGL(k_corr_box, dim3((unsigned)(((int64_t)n_groups + 3) / 4)), dim3(256), 0, c->stream, ca);
     const int64_t item_blocks = std::max<int64_t>((pl.n_items + 3) / 4, 1);
     const dim3 grid((unsigned)std::min<int64_t>((int64_t)occ[which] * c->num_cu, item_blocks));
     if (which == 0)
