@@ -774,45 +774,65 @@ __global__ __launch_bounds__(256) void k_corr_merge(CorrArgs a) {
     }
 }
 
-// One (group, cell) pair of the given or textbook kind: the cell's COM and
-// its tensor, gathered from pair position p of the group's cells.  A position
-// past the item, or an entry that is not a cell (flagged), is not valid.
+// One (group, cell) pair of the given or textbook kind as gathered: the
+// cell's COM and either the given tensor or the cell's second moments S
+// (raw, so that a prefetched pair costs no arithmetic until it is used).  A
+// position past the item, or an entry that is not a cell (flagged), is not
+// valid.
 struct CorrCell {
     float com[3];
-    float q[6];
+    float t[6];
     bool valid;
 };
 
-template <int KIND>
-__device__ __forceinline__ CorrCell load_corr_cell(const CorrArgs& a, int64_t p, int64_t a1, int64_t p0, int64_t lb,
-                                                   int64_t le) {
-    CorrCell r{};
-    r.valid = false;
-    if (p >= a1) return r;
+// Branch-free gathers for the software pipeline below: every load reads a
+// clamped, in-range address, and whether the pair counts is decided from
+// positions alone (pv) or once the loaded value is used, so that a load
+// issued ahead is not waited for until its pair is summed.
+struct CorrEntry {
+    int64_t e;   // list entry (loaded)
+    bool pv;     // the position is a pair of this item
+};
+
+// The list entry at pair position p (k = p - p0 of the group's list, whose
+// last position is kmax >= 0).
+__device__ __forceinline__ CorrEntry corr_list_entry(const CorrArgs& a, int64_t p, int64_t a1, int64_t p0, int64_t lb,
+                                                     int64_t kmax) {
     const int64_t k = p - p0;   // the group's cells lead its list
-    const int64_t c = k < le - lb ? (int64_t)a.list_idx[lb + k] - a.n : -1;
-    if (c < 0 || c >= a.n_cells) {
-        atomicOr(a.err, kErrIndex);
-        return r;
-    }
-    const float* cm = a.cell_mom + (int64_t)a.stride * c;
-    r.com[0] = cm[0];
-    r.com[1] = cm[1];
-    r.com[2] = cm[2];
-    if (KIND == kCorrPairs) {
-        for (int m = 0; m < 6; m++) r.q[m] = a.corr[6 * p + m];
-    } else {
-        const float* S = cm + 5;
-        const float tr = S[0] + S[1] + S[2];
-        r.q[0] = 3.f * S[0] - tr;
-        r.q[1] = 3.f * S[1] - tr;
-        r.q[2] = 3.f * S[2] - tr;
-        r.q[3] = 3.f * S[3];
-        r.q[4] = 3.f * S[4];
-        r.q[5] = 3.f * S[5];
-    }
-    r.valid = true;
+    return CorrEntry{(int64_t)a.list_idx[lb + (k < kmax ? k : kmax)], p < a1 && k <= kmax};
+}
+
+// The pair's cell record; an entry that is not a cell makes the pair invalid
+// and sets bad (cell 0 stands in for its loads).  pmax is the item's last
+// pair position (for the given tensors).
+template <int KIND>
+__device__ __forceinline__ CorrCell load_corr_cell(const CorrArgs& a, CorrEntry en, int64_t p, int64_t pmax, bool& bad) {
+    const int64_t c = en.e - a.n;
+    const bool ok = en.pv && c >= 0 && c < a.n_cells;
+    bad |= en.pv && !ok;
+    const float* cm = a.cell_mom + (int64_t)a.stride * (ok ? c : 0);
+    const float* src = KIND == kCorrPairs ? a.corr + 6 * (p < pmax ? p : pmax) : cm + 5;
+    CorrCell r;
+    for (int m = 0; m < 3; m++) r.com[m] = cm[m];
+    for (int m = 0; m < 6; m++) r.t[m] = src[m];
+    r.valid = ok;
     return r;
+}
+
+// The tensor of a gathered pair: given, or 3 S - tr(S) I.
+template <int KIND>
+__device__ __forceinline__ void corr_tensor(const CorrCell& cc, float Q[6]) {
+    if (KIND == kCorrPairs) {
+        for (int m = 0; m < 6; m++) Q[m] = cc.t[m];
+    } else {
+        const float tr = cc.t[0] + cc.t[1] + cc.t[2];
+        Q[0] = 3.f * cc.t[0] - tr;
+        Q[1] = 3.f * cc.t[1] - tr;
+        Q[2] = 3.f * cc.t[2] - tr;
+        Q[3] = 3.f * cc.t[3];
+        Q[4] = 3.f * cc.t[4];
+        Q[5] = 3.f * cc.t[5];
+    }
 }
 
 // Given or textbook tensors, one wave per item (items wave w, w + W, ...):
@@ -839,16 +859,33 @@ __global__ __launch_bounds__(256) void k_corr_wave(CorrArgs a) {
             float f[kCorrTerms];
 #pragma unroll
             for (int k = 0; k < kCorrTerms; k++) f[k] = 0.f;
-            if (ok) {
-                int64_t lb, le;
-                list_range(a.list_off, a.n_entries, g, lb, le);
-                // software pipeline: the next pair's cell record is gathered while this one is summed
-                CorrCell cur = load_corr_cell<KIND>(a, a0 + lane, a1, p0, lb, le);
-                for (int64_t p = a0 + lane; p < a1; p += 64) {
-                    const CorrCell nxt = load_corr_cell<KIND>(a, p + 64, a1, p0, lb, le);
-                    if (cur.valid) quad_expand_add(cx - cur.com[0], cy - cur.com[1], cz - cur.com[2], cur.q, eps2, f);
+            int64_t lb, le;
+            list_range(a.list_off, a.n_entries, g, lb, le);
+            if (ok && le > lb && a.n_cells > 0) {
+                // software pipeline: while a pair is summed, the next pair's cell record and the
+                // list entry of the pair after it are in flight (a lane's loads retire in order,
+                // and nothing waits for them before its pair is summed)
+                const int64_t kmax = le - lb - 1, pmax = a1 - 1;
+                const int64_t p_first = a0 + lane;
+                bool bad = false;
+                CorrCell cur = load_corr_cell<KIND>(a, corr_list_entry(a, p_first, a1, p0, lb, kmax), p_first, pmax, bad);
+                CorrEntry e_next = corr_list_entry(a, p_first + 64, a1, p0, lb, kmax);
+                for (int64_t p = p_first; p < a1; p += 64) {
+                    const CorrEntry e_after = corr_list_entry(a, p + 128, a1, p0, lb, kmax);
+                    const CorrCell nxt = load_corr_cell<KIND>(a, e_next, p + 64, pmax, bad);
+                    // keeps these loads ahead of the sum below: the compiler would otherwise move
+                    // them into the next iteration, next to their use, and wait for them there
+                    __asm__ volatile("" ::: "memory");
+                    float Q[6];
+                    corr_tensor<KIND>(cur, Q);
+                    const float w = cur.valid ? 1.f : 0.f;   // an invalid pair adds zero
+#pragma unroll
+                    for (int m = 0; m < 6; m++) Q[m] *= w;
+                    quad_expand_add(cx - cur.com[0], cy - cur.com[1], cz - cur.com[2], Q, eps2, f);
                     cur = nxt;
+                    e_next = e_after;
                 }
+                if (bad) atomicOr(a.err, kErrIndex);
             }   // a malformed group was flagged by k_corr_box
             wave_store_part(corr_target(a, g, it, p0, p1, q0, q1), lane, f, cx, cy, cz);
         }
