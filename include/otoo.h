@@ -194,6 +194,13 @@ typedef struct {
 int otoo_set_tuning(otoo_ctx* ctx, const otoo_tuning* tuning);
 int otoo_get_tuning(const otoo_ctx* ctx, otoo_tuning* tuning);
 
+/* Cap, in bytes, on each device scratch buffer of the context (force
+ * schedule and partials, SPH items and partials, correction item sums);
+ * 0 (the default) means no cap.  A call that would need a larger buffer
+ * returns ENOMEM before it enqueues anything.  Buffers already allocated are
+ * kept.  EINVAL for a negative cap. */
+int otoo_set_scratch_limit(otoo_ctx* ctx, int64_t max_bytes);
+
 /* Force evaluation over interaction lists (device pointers).
  *   n           number of particles, 1 .. 2^30
  *   pos [n][3], mass [n]   FP32 targets and particle sources, in group order
@@ -256,7 +263,10 @@ int otoo_direct(otoo_ctx* ctx, int32_t n, const float* pos, const float* mass, i
  * the key order of the device arrays: pos [n][3], h [n] (> 0), q [n] FP32;
  * group_off, list_off, list_idx as for otoo_force (particle entries only);
  * out [n] FP32 is overwritten.  FP32 arithmetic; per target the slices of a
- * workgroup are combined in a fixed order, so results are reproducible.
+ * workgroup are combined in a fixed order, and a long list is cut into
+ * chunks whose sums are added in chunk order, so results are reproducible.
+ * The context keeps scratch for the work items and chunk sums (grown on
+ * demand).
  * Entries that are not particles, and malformed groups, are skipped and
  * flagged for otoo_check.  Asynchronous on the context stream. */
 int otoo_sph_sum(otoo_ctx* ctx, int32_t n, const float* pos, const float* h, const float* q, int32_t n_groups,

@@ -69,7 +69,7 @@ EXPORTED = [
     "otoo_tree_links", "otoo_tree_walk", "otoo_tree_groups", "otoo_tree_walk_range", "otoo_tree_walk_sph", "otoo_lists_free", "otoo_create", "otoo_destroy",
     "otoo_set_stream", "otoo_last_error", "otoo_set_tuning", "otoo_get_tuning", "otoo_force",
     "otoo_check", "otoo_enable_timing", "otoo_last_timing", "otoo_graph_capture", "otoo_graph_launch",
-    "otoo_autotune",
+    "otoo_autotune", "otoo_set_scratch_limit",
     "otoo_quad_exact", "otoo_correction", "otoo_direct", "otoo_sph_sum", "otoo_mlp_num_params", "otoo_mlp_create", "otoo_mlp_destroy", "otoo_mlp_set_params", "otoo_mlp_set_gate",
     "otoo_mlp_get_params", "otoo_mlp_save", "otoo_mlp_load", "otoo_mlp_forward", "otoo_mlp_infer",
     "otoo_mlp_train_samples", "otoo_mlp_backward", "otoo_mlp_train_step",
@@ -105,6 +105,7 @@ def lib():
         "otoo_last_error": ([P], ctypes.c_char_p),
         "otoo_set_tuning": ([P, ctypes.POINTER(Tuning)], I32),
         "otoo_get_tuning": ([P, ctypes.POINTER(Tuning)], I32),
+        "otoo_set_scratch_limit": ([P, I64], I32),
         "otoo_force": ([P, I32, P, P, I32, P, I64, P, P, I32, P, I32, F, P, P, P], I32),
         "otoo_correction": ([P, I32, P, I32, P, I32, P, I64, P, P, I64, P, I32, P, I32, F, P, P], I32),
         "otoo_quad_exact": ([P, I32, I32, I64, P, P, I64, P, I32, P, I32, P], I32),
@@ -385,6 +386,11 @@ class Context:
                    debug_validate=cur.debug_validate if debug_validate is None else int(debug_validate), tile=tile,
                    net_kernel=cur.net_kernel if net_kernel is None else int(net_kernel))
         self._raise(lib().otoo_set_tuning(self._h, ctypes.byref(t)), "otoo_set_tuning")
+
+    def set_scratch_limit(self, max_bytes: int = 0):
+        """Cap on each device scratch buffer of the context (0: no cap); a
+        call that would need more raises OtooError(ENOMEM)."""
+        self._raise(lib().otoo_set_scratch_limit(self._h, int(max_bytes)), "otoo_set_scratch_limit")
 
     def tuning(self) -> Tuning:
         t = Tuning()

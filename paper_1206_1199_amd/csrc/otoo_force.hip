@@ -600,6 +600,8 @@ Layout plan_layout(int32_t n, int32_t n_groups, int64_t n_entries, int32_t n_cel
 
 int ensure_scratch(otoo_ctx* c, size_t bytes) {
     if (bytes <= c->buf_bytes) return OTOO_OK;
+    if (c->scratch_cap && bytes > c->scratch_cap)
+        return fail(c, OTOO_ENOMEM, "force scratch of %zu bytes exceeds the cap of %zu", bytes, c->scratch_cap);
     if (c->buf) {
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         // a captured graph names the old buffer: it cannot be replayed any more
@@ -612,6 +614,7 @@ int ensure_scratch(otoo_ctx* c, size_t bytes) {
         c->buf_bytes = 0;
     }
     size_t want = bytes + bytes / 4;
+    if (c->scratch_cap) want = std::min(want, c->scratch_cap);
     if (hipMalloc(&c->buf, want) != hipSuccess) {
         (void)hipGetLastError();
         c->buf = nullptr;
@@ -849,6 +852,13 @@ int otoo_set_tuning(otoo_ctx* c, const otoo_tuning* t) {
 int otoo_get_tuning(const otoo_ctx* c, otoo_tuning* t) {
     if (!c || !t) return OTOO_EINVAL;
     *t = c->tune;
+    return OTOO_OK;
+}
+
+int otoo_set_scratch_limit(otoo_ctx* c, int64_t max_bytes) {
+    if (!c) return OTOO_EINVAL;
+    if (max_bytes < 0) return fail(c, OTOO_EINVAL, "the scratch cap must not be negative");
+    c->scratch_cap = (size_t)max_bytes;
     return OTOO_OK;
 }
 

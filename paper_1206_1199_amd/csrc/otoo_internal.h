@@ -174,6 +174,7 @@ struct otoo_ctx {
     std::string err;
     otoo_tuning tune{1024, 8, 1, 0, 256, 0};
     int num_cu = 0;
+    size_t scratch_cap = 0;   // largest scratch buffer allowed (0: no cap)
     // scratch
     void* buf = nullptr;
     size_t buf_bytes = 0;

@@ -1539,13 +1539,15 @@ int run_backward(otoo_mlp* m, const uint16_t* X, const float* aux, int64_t n_sam
 
 int ensure_corr_scratch(otoo_ctx* c, size_t bytes) {
     if (bytes <= c->corr_bytes) return OTOO_OK;
+    if (c->scratch_cap && bytes > c->scratch_cap)
+        return fail(c, OTOO_ENOMEM, "correction scratch of %zu bytes exceeds the cap of %zu", bytes, c->scratch_cap);
     if (c->corr_buf) {
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         HIP_TRY(c, hipFree(c->corr_buf));
         c->corr_buf = nullptr;
         c->corr_bytes = 0;
     }
-    const size_t want = bytes + bytes / 4;
+    const size_t want = c->scratch_cap ? std::min(bytes + bytes / 4, c->scratch_cap) : bytes + bytes / 4;
     if (hipMalloc(&c->corr_buf, want) != hipSuccess) {
         (void)hipGetLastError();
         c->corr_buf = nullptr;

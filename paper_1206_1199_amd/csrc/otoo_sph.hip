@@ -1,6 +1,8 @@
 // SPH-style gather sums over neighbour lists (Sec. 2.3, Eq. 4): the second
 // workload on the group/list machinery of the gravity path.  Particles only,
 // no cells (a cell is opened or skipped whole by the SPH walk).
+#include <algorithm>
+
 #include "otoo_internal.h"
 
 using namespace otoo_detail;
@@ -312,13 +314,15 @@ __global__ __launch_bounds__(kBlock) void k_sph_merge(SphPlan pl, int32_t n, con
 
 int ensure_sph_scratch(otoo_ctx* c, size_t bytes) {
     if (bytes <= c->sph_bytes) return OTOO_OK;
+    if (c->scratch_cap && bytes > c->scratch_cap)
+        return fail(c, OTOO_ENOMEM, "SPH scratch of %zu bytes exceeds the cap of %zu", bytes, c->scratch_cap);
     if (c->sph_buf) {
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         HIP_TRY(c, hipFree(c->sph_buf));
         c->sph_buf = nullptr;
         c->sph_bytes = 0;
     }
-    const size_t want = bytes + bytes / 4;
+    const size_t want = c->scratch_cap ? std::min(bytes + bytes / 4, c->scratch_cap) : bytes + bytes / 4;
     if (hipMalloc(&c->sph_buf, want) != hipSuccess) {
         (void)hipGetLastError();
         c->sph_buf = nullptr;

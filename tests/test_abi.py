@@ -44,6 +44,7 @@ def test_null_context_and_bad_arguments_return_einval():
     assert lib.otoo_autotune(None, None, None, None, 1, None, 1, 0.1, 1, None, None, None, None,
                              None) == otoo.EINVAL
     assert lib.otoo_set_tuning(None, None) == otoo.EINVAL
+    assert lib.otoo_set_scratch_limit(None, 0) == otoo.EINVAL
     assert lib.otoo_last_error(None) == b"null context"
     assert lib.otoo_tree_build(None, None, 0, 16, None) == otoo.EINVAL
     assert lib.otoo_tree_walk(None, None, None) == otoo.EINVAL

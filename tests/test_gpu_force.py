@@ -406,3 +406,33 @@ def test_correction_without_cells(ctx):
     np.testing.assert_allclose(g[:, 20:23], centre, rtol=0, atol=1e-6)
     a0, p0 = _gpu(ctx, d, 0.01)
     assert np.array_equal(acc.cpu().numpy().astype(np.float64), a0) and np.array_equal(pot.cpu().numpy(), p0)
+
+
+def test_scratch_cap():
+    """A scratch cap below what a call needs makes the call fail with ENOMEM
+    before it enqueues anything (force, correction and SPH passes); without
+    the cap the same calls work on the same context."""
+    c = otoo.Context(0)
+    pos, m = synth.plummer(4096, seed=14)
+    t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.6, 64, stride=12)
+    with pytest.raises(otoo.OtooError):
+        c.set_scratch_limit(-1)
+    c.set_scratch_limit(1024)
+    for call in (lambda: c.force(d, 0.01), lambda: c.correction(d, otoo.CORR_QUAD, 0.01)):
+        with pytest.raises(otoo.OtooError) as e:
+            call()
+        assert e.value.code == otoo.ENOMEM and "cap" in str(e.value)
+    h = torch.full((d.n,), 0.05, dtype=torch.float32, device="cuda:0")
+    sl = t.walk_sph(np.full(len(m), 0.05), g_max=64)
+    ds = otoo.DeviceLists.from_host(pos32, mass32, sl, cm, "cuda:0")
+    with pytest.raises(otoo.OtooError) as e:
+        c.sph_sum(ds, h, ds.mass)
+    assert e.value.code == otoo.ENOMEM
+    c.set_scratch_limit(0)
+    a_cap, p_cap = _gpu(c, d, 0.01)
+    a_ref, p_ref = _gpu(otoo.Context(0), d, 0.01)
+    assert np.array_equal(a_cap, a_ref) and np.array_equal(p_cap, p_ref)
+    c.correction(d, otoo.CORR_QUAD, 0.01)
+    c.sph_sum(ds, h, ds.mass)
+    torch.cuda.synchronize()
+    c.check()
