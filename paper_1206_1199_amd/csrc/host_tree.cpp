@@ -29,7 +29,6 @@
 #include <memory>
 #include <mutex>
 #include <new>
-#include <memory>
 #include <vector>
 
 namespace {
@@ -229,6 +228,9 @@ void walk_groups(const otoo_tree* t, const std::vector<int64_t>& goff, const std
     std::vector<std::vector<int32_t>> buf(nth);
     std::vector<int64_t> g_thread(ng), g_start(ng), g_ncell(ng), g_len(ng);
     L->group_box.resize(6 * (size_t)ng);
+    // an exception cannot leave an OpenMP region: a failed allocation inside
+    // it is recorded here and rethrown after the region
+    std::atomic<bool> out_of_memory{false};
 #pragma omp parallel
     {
         const int tid = omp_get_thread_num();
@@ -236,46 +238,52 @@ void walk_groups(const otoo_tree* t, const std::vector<int64_t>& goff, const std
         std::vector<int32_t> cellv, partv;
 #pragma omp for schedule(dynamic, 8)
         for (int64_t g = 0; g < ng; g++) {
-            double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-            for (int64_t p = goff[g]; p < goff[g + 1]; p++)
+            if (out_of_memory.load(std::memory_order_relaxed)) continue;
+            try {
+                double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+                for (int64_t p = goff[g]; p < goff[g + 1]; p++)
+                    for (int k = 0; k < 3; k++) {
+                        lo[k] = std::min(lo[k], t->pos[3 * p + k]);
+                        hi[k] = std::max(hi[k], t->pos[3 * p + k]);
+                    }
                 for (int k = 0; k < 3; k++) {
-                    lo[k] = std::min(lo[k], t->pos[3 * p + k]);
-                    hi[k] = std::max(hi[k], t->pos[3 * p + k]);
+                    L->group_box[6 * g + k] = (float)lo[k];
+                    L->group_box[6 * g + 3 + k] = (float)hi[k];
                 }
-            for (int k = 0; k < 3; k++) {
-                L->group_box[6 * g + k] = (float)lo[k];
-                L->group_box[6 * g + 3 + k] = (float)hi[k];
+                cellv.clear();
+                partv.clear();
+                int64_t u = n;  // root cell
+                while (u >= 0) {
+                    if (u < n) {   // a particle reached through a link (not taken when leaves are expanded whole)
+                        partv.push_back((int32_t)u);
+                        u = t->next[u];
+                        continue;
+                    }
+                    const WalkCell& c = cells[u - n];
+                    double d2 = 0;
+                    for (int k = 0; k < 3; k++) {
+                        const double dk = std::max(0.0, std::max(lo[k] - c.com[k], c.com[k] - hi[k]));
+                        d2 += dk * dk;
+                    }
+                    const int act = decide(c, std::sqrt(d2), g);
+                    const bool open = act == kOpen;
+                    if (open && c.leaf)
+                        for (int32_t k = 0; k < c.count; k++) partv.push_back((int32_t)(c.first + k));
+                    if (act == kAccept) cellv.push_back((int32_t)u);
+                    u = (open && !c.leaf) ? c.more : c.next;
+                }
+                g_thread[g] = tid;
+                g_start[g] = (int64_t)B.size();
+                g_ncell[g] = (int64_t)cellv.size();
+                B.insert(B.end(), cellv.begin(), cellv.end());
+                B.insert(B.end(), partv.begin(), partv.end());
+                g_len[g] = (int64_t)B.size() - g_start[g];
+            } catch (const std::bad_alloc&) {
+                out_of_memory.store(true, std::memory_order_relaxed);
             }
-            cellv.clear();
-            partv.clear();
-            int64_t u = n;  // root cell
-            while (u >= 0) {
-                if (u < n) {   // a particle reached through a link (not taken when leaves are expanded whole)
-                    partv.push_back((int32_t)u);
-                    u = t->next[u];
-                    continue;
-                }
-                const WalkCell& c = cells[u - n];
-                double d2 = 0;
-                for (int k = 0; k < 3; k++) {
-                    const double dk = std::max(0.0, std::max(lo[k] - c.com[k], c.com[k] - hi[k]));
-                    d2 += dk * dk;
-                }
-                const int act = decide(c, std::sqrt(d2), g);
-                const bool open = act == kOpen;
-                if (open && c.leaf)
-                    for (int32_t k = 0; k < c.count; k++) partv.push_back((int32_t)(c.first + k));
-                if (act == kAccept) cellv.push_back((int32_t)u);
-                u = (open && !c.leaf) ? c.more : c.next;
-            }
-            g_thread[g] = tid;
-            g_start[g] = (int64_t)B.size();
-            g_ncell[g] = (int64_t)cellv.size();
-            B.insert(B.end(), cellv.begin(), cellv.end());
-            B.insert(B.end(), partv.begin(), partv.end());
-            g_len[g] = (int64_t)B.size() - g_start[g];
         }
     }
+    if (out_of_memory.load()) throw std::bad_alloc();
     L->group_off.resize(ng + 1);
     L->list_off.resize(ng + 1);
     L->n_cellent.resize(ng);

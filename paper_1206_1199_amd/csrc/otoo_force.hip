@@ -764,6 +764,12 @@ int prepare(otoo_ctx* c, const Call& a) {
         if (rc) return rc;
     }
     const Layout L = plan_layout(a.n, a.n_groups, a.n_entries, a.n_cells, c->tune.chunk);
+    // the queue head, the item table's chunk index and the longest-first
+    // order are 32-bit: every fetch, including each workgroup's last one,
+    // must stay below 2^31
+    if (L.item_cap + (int64_t)c->num_cu * c->tune.blocks_per_cu >= INT32_MAX)
+        return fail(c, OTOO_EINVAL, "%lld work items exceed the 32-bit queue; use a longer chunk",
+                    (long long)L.item_cap);
     return ensure_scratch(c, L.total);
 }
 

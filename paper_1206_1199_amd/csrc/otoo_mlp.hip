@@ -8,10 +8,15 @@
 // network's tensor the textbook quadrupole plus a learned correction, and a
 // gate on l/|d| limits the layers to near cells.
 //
-//   k_corr_net      per group: features, gated network (register-resident,
-//                   v_mfma_f32_16x16x32_bf16) and the local expansion
-//   k_corr_group    per group, LDS-staged: given tensors, the textbook
-//                   quadrupole, or the network
+//   k_corr_box      bounding box of each group (the expansion centre)
+//   k_corr_net      per item of consecutive cell pairs: features, gated
+//                   network (register-resident, v_mfma_f32_16x16x32_bf16)
+//                   and the local expansion
+//   k_corr_wave     the same items with given tensors or the textbook
+//                   quadrupole
+//   k_corr_merge    item sums of the groups that straddle items, in item
+//                   order, and the rows of groups without cell pairs
+//   k_corr_group    per group, LDS-staged: the network (alternative kernel)
 //   k_group_geom    bounding-box centre and half-diagonal of each group
 //   k_mlp_infer     Qt of every pair (for checks and external use)
 //   k_mlp_forward_raw network outputs for given BF16 features
@@ -21,6 +26,7 @@
 //   k_grad_reduce   fixed-order sum of the partials
 //   k_adam          Adam on FP32 master weights, BF16 operand copies
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -1520,16 +1526,14 @@ int run_backward(otoo_mlp* m, const uint16_t* X, const float* aux, int64_t n_sam
     if (blocks > m->part_rows) {
         if (m->part) HIP_TRY(c, hipFree(m->part));
         m->part = nullptr;
+        m->part_rows = 0;   // stays 0 if the allocation fails
         HIP_TRY(c, hipMalloc(&m->part, sizeof(float) * (size_t)(NPARAM + 1) * blocks));
         m->part_rows = blocks;
     }
     TrainArgs ta{X, aux, n_samples, 1.f / (float)n_samples, eps * eps, m->wbf, m->master, m->part};
-    static bool attr_set = false;
-    if (!attr_set) {
-        HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(k_mlp_train),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(TrainLDS)));
-        attr_set = true;
-    }
+    // set on every call: the attribute belongs to the current device
+    HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(k_mlp_train),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(TrainLDS)));
     hipLaunchKernelGGL(k_mlp_train, dim3(blocks), dim3(256), sizeof(TrainLDS), c->stream, ta);
     hipLaunchKernelGGL(k_grad_reduce, dim3((NPARAM + 1 + kGradCols - 1) / kGradCols), dim3(kGradCols * kGradSlices), 0,
                        c->stream, m->part, blocks, m->grad);
@@ -1711,6 +1715,7 @@ int otoo_mlp_infer(otoo_mlp* m, int32_t n, const float* pos, int32_t n_groups, c
     if (n_groups > m->geom_cap) {
         if (m->geom) HIP_TRY(c, hipFree(m->geom));
         m->geom = nullptr;
+        m->geom_cap = 0;   // stays 0 if the allocation fails
         HIP_TRY(c, hipMalloc(&m->geom, sizeof(float4) * (size_t)n_groups));
         m->geom_cap = n_groups;
     }
@@ -1767,18 +1772,20 @@ int otoo_correction(otoo_ctx* c, int32_t kind, otoo_mlp* m, int32_t n, const flo
     pl.part_r = reinterpret_cast<float*>(static_cast<char*>(c->corr_buf) + part_bytes);
     pl.box = reinterpret_cast<float4*>(static_cast<char*>(c->corr_buf) + 2 * part_bytes);
     // resident workgroups per CU of each kernel (the same for every device of this build)
-    static int occ[3] = {0, 0, 0};
+    static std::atomic<int> occ[3] = {0, 0, 0};
     const int which = kind == OTOO_CORR_PAIRS ? 0 : kind == OTOO_CORR_QUAD ? 1 : 2;
-    if (!occ[which]) {
+    int per_cu = occ[which].load(std::memory_order_relaxed);
+    if (!per_cu) {
         const void* fn = which == 0   ? reinterpret_cast<const void*>(&k_corr_wave<kCorrPairs>)
                          : which == 1 ? reinterpret_cast<const void*>(&k_corr_wave<kCorrQuad>)
                                       : reinterpret_cast<const void*>(&k_corr_net);
-        HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[which], fn, 256, 0));
-        occ[which] = std::max(occ[which], 1);
+        HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0));
+        per_cu = std::max(per_cu, 1);
+        occ[which].store(per_cu, std::memory_order_relaxed);
     }
     hipLaunchKernelGGL(k_corr_box, dim3((unsigned)(((int64_t)n_groups + 3) / 4)), dim3(256), 0, c->stream, ca);
     const int64_t item_blocks = std::max<int64_t>((pl.n_items + 3) / 4, 1);
-    const dim3 grid((unsigned)std::min<int64_t>((int64_t)occ[which] * c->num_cu, item_blocks));
+    const dim3 grid((unsigned)std::min<int64_t>((int64_t)per_cu * c->num_cu, item_blocks));
     if (which == 0)
         hipLaunchKernelGGL(k_corr_wave<kCorrPairs>, grid, dim3(256), 0, c->stream, ca);
     else if (which == 1)

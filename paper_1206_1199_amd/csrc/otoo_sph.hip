@@ -2,6 +2,7 @@
 // workload on the group/list machinery of the gravity path.  Particles only,
 // no cells (a cell is opened or skipped whole by the SPH walk).
 #include <algorithm>
+#include <atomic>
 
 #include "otoo_internal.h"
 
@@ -369,10 +370,13 @@ extern "C" int otoo_sph_sum(otoo_ctx* c, int32_t n, const float* pos, const floa
     pl.split_g = reinterpret_cast<int32_t*>(b + o_sg);
     pl.split_base = reinterpret_cast<int64_t*>(b + o_sb);
     pl.parts = reinterpret_cast<float2*>(b + o_parts);
-    static int per_cu = 0;   // resident workgroups of k_sph per CU (the same for every device of this build)
+    // resident workgroups of k_sph per CU (the same for every device of this build)
+    static std::atomic<int> occ{0};
+    int per_cu = occ.load(std::memory_order_relaxed);
     if (!per_cu) {
         HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sph, kBlock, 0));
         per_cu = std::max(per_cu, 1);
+        occ.store(per_cu, std::memory_order_relaxed);
     }
     hipLaunchKernelGGL(k_sph_reset, dim3(1), dim3(64), 0, c->stream, pl.meta);
     hipLaunchKernelGGL(k_sph_plan, dim3((n_groups + 255) / 256), dim3(256), 0, c->stream, pl, n, n_groups, group_off,
