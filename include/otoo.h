@@ -188,7 +188,7 @@ typedef struct {
     int32_t blocks_per_cu;/* persistent workgroups per compute unit, 1..16 */
     int32_t lpt;          /* 1: hand out items longest-first, 0: in group order */
     int32_t debug_validate; /* 1: check the CSR on the host before launching (slow) */
-    int32_t tile;         /* list entries staged in LDS per tile: 256 or 512 */
+    int32_t tile;         /* list entries staged in LDS per tile: 256, 512 or 1024 */
     int32_t net_kernel;   /* learned correction kernel: 0 registers-resident (default), 1 LDS-staged */
 } otoo_tuning;
 int otoo_set_tuning(otoo_ctx* ctx, const otoo_tuning* tuning);

@@ -341,6 +341,13 @@ struct ForceArgs {
     int32_t* err;
 };
 
+// A 64-bit value that is the same in every lane, moved to scalar registers.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Interaction of one target with one source: Plummer-softened monopole.
 // 13 VALU operations and one v_rsq_f32.
 __device__ __forceinline__ void pair_mono(float xi, float yi, float zi, float4 s, float eps2, float& ax, float& ay,
@@ -360,95 +367,140 @@ __device__ __forceinline__ void pair_mono(float xi, float yi, float zi, float4 s
     ph += mr;
 }
 
+// One work item as every thread of the workgroup sees it.  The values are
+// the same in every lane (loads of one address); readfirstlane keeps them,
+// and the control of the tile loop, in scalar registers (integer division
+// and 64-bit compares run on the vector unit).
+struct ItemGeo {
+    int g, k, g0, ng;
+    int S;             // slices: lanes are (target, slice)
+    int rows_full;     // rows of a full tile per slice
+    int tstride;       // entries per tile, a multiple of S
+    int clen;          // entries of this item (at most one chunk)
+    int64_t nch;       // items of the group's list
+    const int32_t* idx;   // the item's entries, idx[0 .. clen)
+};
+
+// Decodes queue slot q; false for a malformed group.
+template <int TILE>
+__device__ __forceinline__ bool decode_item(const ForceArgs& a, int q, ItemGeo& m) {
+    const int qi = a.order ? __builtin_amdgcn_readfirstlane(a.order[q]) : q;
+    const int2 it = a.items[qi];
+    m.g = __builtin_amdgcn_readfirstlane(it.x);
+    m.k = __builtin_amdgcn_readfirstlane(it.y);
+    m.g0 = __builtin_amdgcn_readfirstlane(a.group_off[m.g]);
+    m.ng = __builtin_amdgcn_readfirstlane(a.group_off[m.g + 1]) - m.g0;
+    if (m.ng < 1 || m.ng > kBlock || m.g0 < 0 || m.g0 + m.ng > a.n) return false;
+    int64_t lb, le;
+    list_range(a.list_off, a.n_entries, m.g, lb, le);
+    lb = uniform64(lb);
+    le = uniform64(le);
+    m.nch = n_chunks(le - lb, a.chunk);
+    const int64_t cb = lb + (int64_t)m.k * a.chunk;
+    const int64_t rest = le - cb;
+    m.clen = __builtin_amdgcn_readfirstlane(rest <= 0 ? 0 : (rest < a.chunk ? (int)rest : a.chunk));
+    m.idx = a.list_idx + cb;
+    m.S = __builtin_amdgcn_readfirstlane(kBlock / m.ng);
+    m.rows_full = __builtin_amdgcn_readfirstlane(TILE / m.S);
+    m.tstride = m.S * m.rows_full;
+    return true;
+}
+
+// The gather of a tile runs in two stages one tile apart, so that no wave
+// waits on memory between tiles: load_idx issues the list-index loads of a
+// tile (thread t takes entries base + t + l kBlock; entries past the tile or
+// the item are marked absent), and one tile later load_src issues the
+// source-record loads for those indices (absent entries are zero mass).
+// Waiting for an index load right after issuing it would also wait for every
+// load issued before it (the vector memory counter drains in order).
+template <int L>
+__device__ __forceinline__ void load_idx(const ItemGeo& m, int t, int base, int32_t (&j)[L], bool (&has)[L]) {
+#pragma unroll
+    for (int l = 0; l < L; l++) {
+        const int te = t + l * kBlock;
+        const int e = base + te;
+        has[l] = te < m.tstride && e < m.clen;
+        j[l] = has[l] ? m.idx[e] : 0;
+    }
+}
+template <int L>
+__device__ __forceinline__ void load_src(const ForceArgs& a, const int32_t (&j)[L], const bool (&has)[L],
+                                         float4 (&pre)[L]) {
+#pragma unroll
+    for (int l = 0; l < L; l++) {
+        pre[l] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (has[l]) {
+            if (j[l] >= 0 && j[l] < a.n_src) {
+                pre[l] = a.src[j[l]];
+            } else {
+                atomicOr(a.err, kErrIndex);
+            }
+        }
+    }
+}
+
 // TILE list entries are staged in LDS per tile (TILE / kBlock per thread).
 template <int TILE>
-__global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
+__device__ __forceinline__ void force_items(const ForceArgs& a) {
     constexpr int L = TILE / kBlock;
     static_assert(L * kBlock == TILE && L >= 1, "tile must be a multiple of the workgroup");
     __shared__ float4 tile[2][TILE];
     __shared__ int s_q;
     const int t = threadIdx.x;
-    const int64_t n_items = a.meta->n_items < a.item_cap ? a.meta->n_items : a.item_cap;
+    const int64_t n_items = uniform64(a.meta->n_items < a.item_cap ? a.meta->n_items : a.item_cap);
 
     for (;;) {
         if (t == 0) s_q = atomicAdd(&a.meta->head, 1);
         __syncthreads();
-        const int64_t q = s_q;
+        const int q = __builtin_amdgcn_readfirstlane(s_q);
         __syncthreads();
         if (q >= n_items) break;
-        const int64_t qi = a.order ? a.order[q] : q;
-        const int2 it = a.items[qi];
-        const int g = it.x, k = it.y;
-        const int g0 = a.group_off[g];
-        const int ng = a.group_off[g + 1] - g0;
-        if (ng < 1 || ng > kBlock || g0 < 0 || g0 + ng > a.n) {
+        ItemGeo m;
+        if (!decode_item<TILE>(a, q, m)) {
             if (t == 0) atomicOr(a.err, kErrGroup);
             continue;
         }
-        int64_t lb, le;
-        list_range(a.list_off, a.n_entries, g, lb, le);
-        const int64_t len = le - lb;
-        const int64_t nch = n_chunks(len, a.chunk);
-        const int64_t cb = lb + (int64_t)k * a.chunk;
-        const int64_t ce = (cb + a.chunk < le) ? cb + a.chunk : le;
+        const int g = m.g, k = m.k, g0 = m.g0, ng = m.ng, S = m.S;
+        const int64_t nch = m.nch;
 
         // Lanes are (target i, slice sl): S slices split each tile into S
         // contiguous runs of `rows` entries, padded with zero-mass entries, so
         // every lane runs the same uniform trip count.
-        const int S = kBlock / ng;
         const int i = t % ng;
         const int sl = t / ng;
         const bool active = sl < S;
-        const int tstride = S * (TILE / S);           // entries per tile, a multiple of S
         const bool wave_busy = (t & ~63) < S * ng;    // some lane of this wave is active
         const float4 xi = a.src[g0 + i];
 
         float s_ax = 0.f, s_ay = 0.f, s_az = 0.f, s_ph = 0.f;
         float c_ax = 0.f, c_ay = 0.f, c_az = 0.f, c_ph = 0.f;
 
-        // prefetch the first tile into registers
+        // tile 0's records and tile 1's indices in flight
         float4 pre[L];
-#pragma unroll
-        for (int l = 0; l < L; l++) {
-            pre[l] = make_float4(0.f, 0.f, 0.f, 0.f);
-            const int te = t + l * kBlock;
-            const int64_t e = cb + te;
-            if (te < tstride && e < ce) {
-                const int32_t j = a.list_idx[e];
-                if (j >= 0 && j < a.n_src) {
-                    pre[l] = a.src[j];
-                } else {
-                    atomicOr(a.err, kErrIndex);
-                }
-            }
-        }
+        int32_t jn[L];
+        bool has[L];
+        load_idx(m, t, 0, jn, has);
+        load_src(a, jn, has, pre);
+        load_idx(m, t, m.tstride, jn, has);
         int buf = 0;
-        for (int64_t tb = cb; tb < ce; tb += tstride) {
-            const int tl = (int)((ce - tb) < tstride ? (ce - tb) : tstride);
-            const int rows = (tl + S - 1) / S;
+        for (int tb = 0; tb < m.clen; tb += m.tstride) {
+            const int tl = (m.clen - tb) < m.tstride ? (m.clen - tb) : m.tstride;
+            const int rows = tl == m.tstride ? m.rows_full : __builtin_amdgcn_readfirstlane((tl + S - 1) / S);
 #pragma unroll
             for (int l = 0; l < L; l++) tile[buf][t + l * kBlock] = pre[l];
             __syncthreads();
-            // next tile's gather overlaps this tile's arithmetic
-#pragma unroll
-            for (int l = 0; l < L; l++) {
-                const int te = t + l * kBlock;
-                const int64_t e = tb + tstride + te;
-                pre[l] = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (te < tstride && e < ce) {
-                    const int32_t j = a.list_idx[e];
-                    if (j >= 0 && j < a.n_src) {
-                        pre[l] = a.src[j];
-                    } else {
-                        atomicOr(a.err, kErrIndex);
-                    }
-                }
+            // the next tile's records (its indices arrived during the previous
+            // tile) and the indices of the tile after it load while this tile
+            // is summed
+            if (tb + m.tstride < m.clen) {
+                load_src(a, jn, has, pre);
+                load_idx(m, t, tb + 2 * m.tstride, jn, has);
             }
             float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
             if (wave_busy) {
                 const float4* tp = tile[buf] + (active ? sl : 0) * rows;
 #pragma unroll 8
-                for (int m = 0; m < rows; m++) pair_mono(xi.x, xi.y, xi.z, tp[m], a.eps2, ax, ay, az, ph);
+                for (int mm = 0; mm < rows; mm++) pair_mono(xi.x, xi.y, xi.z, tp[mm], a.eps2, ax, ay, az, ph);
             }
             kahan_add(s_ax, c_ax, ax);
             kahan_add(s_ay, c_ay, ay);
@@ -503,6 +555,11 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
         }
         __syncthreads();  // the reduction space is the next item's tile buffer
     }
+}
+
+template <int TILE>
+__global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
+    force_items<TILE>(a);
 }
 
 // ---------------------------------------------------------------- K3 reduce
@@ -743,7 +800,9 @@ int enqueue(otoo_ctx* c, const Call& a, bool allow_timing) {
     fa.err = c->errflag;
     const int grid = c->num_cu * tu.blocks_per_cu;
     if (tm) HIP_TRY(c, hipEventRecord(c->ev[1], s));
-    if (tu.tile == 512)
+    if (tu.tile == 1024)
+        hipLaunchKernelGGL(k_force<1024>, dim3(grid), dim3(kBlock), 0, s, fa);
+    else if (tu.tile == 512)
         hipLaunchKernelGGL(k_force<512>, dim3(grid), dim3(kBlock), 0, s, fa);
     else
         hipLaunchKernelGGL(k_force<256>, dim3(grid), dim3(kBlock), 0, s, fa);
@@ -849,7 +908,7 @@ int otoo_set_tuning(otoo_ctx* c, const otoo_tuning* t) {
     nt.debug_validate = t->debug_validate ? 1 : 0;
     if (nt.chunk < 64 || nt.chunk > (1 << 28)) return fail(c, OTOO_EINVAL, "chunk must be in 64..2^28");
     if (nt.blocks_per_cu < 1 || nt.blocks_per_cu > 16) return fail(c, OTOO_EINVAL, "blocks_per_cu must be in 1..16");
-    if (nt.tile != 256 && nt.tile != 512) return fail(c, OTOO_EINVAL, "tile must be 256 or 512");
+    if (nt.tile != 256 && nt.tile != 512 && nt.tile != 1024) return fail(c, OTOO_EINVAL, "tile must be 256, 512 or 1024");
     if (nt.net_kernel != 0 && nt.net_kernel != 1) return fail(c, OTOO_EINVAL, "net_kernel must be 0 or 1");
     c->tune = nt;
     return OTOO_OK;

@@ -300,15 +300,17 @@ def test_exact_quadrupole_pairs_and_accuracy(ctx, plummer16k):
     assert e_q < 0.75 * e_m
 
 
+@pytest.mark.parametrize("tile", [512, 1024])
 @pytest.mark.parametrize("g_max", [32, 64, 256])
-def test_tile_512(ctx, plummer16k, g_max):
+def test_deeper_tiles(ctx, plummer16k, g_max, tile):
+    # chunk 1536: lists split into items with ragged last tiles
     pos, m = plummer16k
     t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.5, g_max)
-    ctx.set_tuning(chunk=1536, tile=512, lpt=1)
+    ctx.set_tuning(chunk=1536, tile=tile, lpt=1)
     acc, pot = _gpu(ctx, d, 0.01)
     ctx.set_tuning(chunk=1024, tile=256)
     a_ref, p_ref = _oracle(pos32, mass32, lists, cm, 0.01)
-    _assert_parity(acc, pot, a_ref, p_ref, f"tile 512 g_max={g_max}")
+    _assert_parity(acc, pot, a_ref, p_ref, f"tile {tile} g_max={g_max}")
 
 
 @pytest.mark.parametrize("workload", ["polytrope2m", "cube16m"])
