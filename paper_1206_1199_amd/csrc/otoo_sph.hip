@@ -35,22 +35,58 @@ struct SphRec {
     float2 w;
 };
 
-__device__ __forceinline__ SphRec load_rec(const float* __restrict__ pos, const float* __restrict__ hh,
-                                           const float* __restrict__ q, const int32_t* __restrict__ list_idx,
-                                           int64_t e, int32_t n, int32_t* err) {
-    SphRec r;
-    const int32_t j = list_idx[e];
-    if (j >= 0 && j < n) {
-        const float ih = 1.f / hh[j];
-        const float q2 = 2.f * q[j];
-        r.x = make_float4(pos[3 * j], pos[3 * j + 1], pos[3 * j + 2], ih);
-        r.w = make_float2(q2, q2 * (8.f * kInvPi) * ih * ih * ih);
-    } else {
-        atomicOr(err, kErrIndex);
-        r.x = make_float4(0.f, 0.f, 0.f, 0.f);
-        r.w = make_float2(0.f, 0.f);
+// A 64-bit value that is the same in every lane, moved to scalar registers.
+__device__ __forceinline__ int64_t sph_uniform64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// A tile's records are gathered in three steps, each one tile after the
+// previous: the list indices (sph_load_idx), the raw particle data for those
+// indices (sph_load_raw), and the record itself (sph_make_rec, the
+// arithmetic on the raw data, as the tile is written to LDS).  Waiting for a
+// load right after issuing it would also wait for every earlier load (the
+// vector memory counter drains in order); the lag leaves no wait between
+// tiles.  Entries that are absent or out of range get zero weights and h = 1.
+struct SphRaw {
+    float x, y, z, h, q;
+};
+
+__device__ __forceinline__ void sph_load_idx(const int32_t* __restrict__ list_idx, int64_t lb, int64_t len, int ts,
+                                             int t, int64_t base, int32_t (&j)[kSphPer], bool (&has)[kSphPer]) {
+#pragma unroll
+    for (int p = 0; p < kSphPer; p++) {
+        const int e = p * kBlock + t;
+        has[p] = e < ts && base + e < len;
+        j[p] = has[p] ? list_idx[lb + base + e] : 0;
     }
-    return r;
+}
+
+__device__ __forceinline__ void sph_load_raw(const float* __restrict__ pos, const float* __restrict__ hh,
+                                             const float* __restrict__ q, int32_t n, int32_t* err,
+                                             const int32_t (&j)[kSphPer], const bool (&has)[kSphPer],
+                                             SphRaw (&raw)[kSphPer]) {
+#pragma unroll
+    for (int p = 0; p < kSphPer; p++) {
+        raw[p] = SphRaw{0.f, 0.f, 0.f, 1.f, 0.f};
+        if (has[p]) {
+            if (j[p] >= 0 && j[p] < n) {
+                raw[p] = SphRaw{pos[3 * j[p]], pos[3 * j[p] + 1], pos[3 * j[p] + 2], hh[j[p]], q[j[p]]};
+            } else {
+                atomicOr(err, kErrIndex);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ SphRec sph_make_rec(const SphRaw& r) {
+    const float ih = 1.f / r.h;
+    const float q2 = 2.f * r.q;
+    SphRec c;
+    c.x = make_float4(r.x, r.y, r.z, ih);
+    c.w = make_float2(q2, q2 * (8.f * kInvPi) * ih * ih * ih);
+    return c;
 }
 
 // A group's particle range and list range (uniform across the workgroup).
@@ -193,7 +229,6 @@ __global__ __launch_bounds__(kBlock) void k_sph(SphPlan pl, int32_t batch, int32
     const int t = threadIdx.x;
     const int n_long = (int)std::min<int64_t>(pl.meta->n_long, pl.cap_long);
     const int n_items = n_long + pl.meta->n_short;
-    const SphRec zero{make_float4(0.f, 0.f, 0.f, 0.f), make_float2(0.f, 0.f)};
     int next_it = 0, batch_left = 0;   // thread 0's batch of consecutive items
     for (;;) {
         if (t == 0) {
@@ -220,39 +255,46 @@ __global__ __launch_bounds__(kBlock) void k_sph(SphPlan pl, int32_t batch, int32
             __syncthreads();  // every thread has read s_item before it is rewritten
             continue;
         }
-        const int S = slices(c.ng);
-        const int ts = tile_len(c.ng);
+        // the group's ranges are uniform too (loads of one address); readfirstlane
+        // keeps them, the slice count and the tile length in scalar registers
+        const int g0 = __builtin_amdgcn_readfirstlane(c.g0);
+        const int ng = __builtin_amdgcn_readfirstlane(c.ng);
+        const int S = __builtin_amdgcn_readfirstlane(slices(ng));
+        const int ts = __builtin_amdgcn_readfirstlane(tile_len(ng));
         const int64_t e0 = (int64_t)item.y * pl.chunk;
         const int64_t e1 = std::min<int64_t>(c.len, e0 + pl.chunk);
-        const int64_t len = std::max<int64_t>(e1 - e0, 0);
-        const int64_t lb = c.lb + e0;
-        const int ti = t % c.ng, sl = t / c.ng;
-        const int i = c.g0 + ti;
+        const int len = __builtin_amdgcn_readfirstlane((int)std::max<int64_t>(e1 - e0, 0));   // <= chunk
+        const int64_t lb = sph_uniform64(c.lb + e0);
+        const int ti = t % ng, sl = t / ng;
+        const int i = g0 + ti;
         const float xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
         const float ihi = 1.f / hh[i];
         const float kihi = kCbrt4 * ihi;
         float A = 0.f, B = 0.f;
-        SphRec rec[kSphPer];
-#pragma unroll
-        for (int p = 0; p < kSphPer; p++) {
-            const int e = p * kBlock + t;
-            rec[p] = (e < ts && e < len) ? load_rec(pos, hh, q, list_idx, lb + e, n, err) : zero;
-        }
+        // tile 0's raw data and tile 1's indices in flight
+        int32_t jn[kSphPer];
+        bool has[kSphPer];
+        SphRaw raw[kSphPer];
+        sph_load_idx(list_idx, lb, len, ts, t, 0, jn, has);
+        sph_load_raw(pos, hh, q, n, err, jn, has, raw);
+        sph_load_idx(list_idx, lb, len, ts, t, ts, jn, has);
         int cur = 0;
-        for (int64_t base = 0; base < len; base += ts) {
-            const int tl = (int)((len - base) < ts ? (len - base) : ts);
-            const int rows = (tl + S - 1) / S;   // rows * S <= ts: the lanes stay inside the tile
+        for (int base = 0; base < len; base += ts) {
+            const int tl = (len - base) < ts ? (len - base) : ts;
+            const int rows = __builtin_amdgcn_readfirstlane((tl + S - 1) / S);   // rows * S <= ts: inside the tile
 #pragma unroll
             for (int p = 0; p < kSphPer; p++) {
-                sX[cur][p * kBlock + t] = rec[p].x;   // entries at or beyond tl are zero weight
-                sW[cur][p * kBlock + t] = rec[p].w;
+                const SphRec rec = sph_make_rec(raw[p]);   // entries at or beyond tl are zero weight
+                sX[cur][p * kBlock + t] = rec.x;
+                sW[cur][p * kBlock + t] = rec.w;
             }
             __syncthreads();
-#pragma unroll
-            for (int p = 0; p < kSphPer; p++) {
-                const int e = p * kBlock + t;
-                const int64_t nx = base + ts + e;
-                rec[p] = (e < ts && nx < len) ? load_rec(pos, hh, q, list_idx, lb + nx, n, err) : zero;
+            // the next tile's raw data (its indices arrived during the previous
+            // tile) and the indices of the tile after it load while this tile
+            // is summed
+            if (base + ts < len) {
+                sph_load_raw(pos, hh, q, n, err, jn, has, raw);
+                sph_load_idx(list_idx, lb, len, ts, t, base + 2 * ts, jn, has);
             }
             if (sl < S) {
                 const float4* xp = sX[cur] + sl;
@@ -271,18 +313,18 @@ __global__ __launch_bounds__(kBlock) void k_sph(SphPlan pl, int32_t batch, int32
         }
         red[t] = make_float2(A, B);
         __syncthreads();
-        if (t < c.ng) {
+        if (t < ng) {
             float a = 0.f, b = 0.f;
             for (int s = 0; s < S; s++) {
-                const float2 v = red[s * c.ng + t];
+                const float2 v = red[s * ng + t];
                 a += v.x;
                 b += v.y;
             }
             if (item.w == 1) {
                 const float sig = (8.f * kInvPi) * ihi * ihi * ihi;
-                out[c.g0 + t] = 0.5f * fmaf(sig, a, b);
+                out[g0 + t] = 0.5f * fmaf(sig, a, b);
             } else {
-                pl.parts[pl.split_base[item.z] + (int64_t)item.y * c.ng + t] = make_float2(a, b);
+                pl.parts[pl.split_base[item.z] + (int64_t)item.y * ng + t] = make_float2(a, b);
             }
         }
     }
