@@ -438,3 +438,25 @@ def test_scratch_cap():
     c.sph_sum(ds, h, ds.mass)
     torch.cuda.synchronize()
     c.check()
+
+
+def test_queue_range_checked_on_the_host():
+    """Sizes that would need 2^31 or more work items (the device queue, the
+    item table and the longest-first order are 32-bit) are rejected with
+    EINVAL by the host before anything is enqueued or allocated; the device
+    buffers passed are never read."""
+    import ctypes
+    c = otoo.Context(0)
+    c.set_tuning(chunk=64)
+    buf = torch.zeros(64, dtype=torch.float64, device="cuda:0")
+    p = ctypes.c_void_p(buf.data_ptr())
+    n = 1 << 30
+    rc = otoo.lib().otoo_force(c._h, n, p, p, n, p, 1 << 37, p, p, 0, None, 4, 0.01, None, p, p)
+    assert rc == otoo.EINVAL
+    assert "32-bit queue" in otoo.lib().otoo_last_error(c._h).decode()
+    # the context still works
+    pos, m = synth.plummer(2048, seed=15)
+    t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.5, 64)
+    a, pt = _gpu(c, d, 0.01)
+    a_ref, p_ref = _oracle(pos32, mass32, lists, cm, 0.01)
+    _assert_parity(a, pt, a_ref, p_ref, "after a rejected call")
