@@ -7,9 +7,15 @@ if ``libotoo.so`` is missing, importing the binding's entry points raises.
 
     tree  = Tree(pos64, mass64, n_crit=16)          # host octree (key order)
     lists = tree.walk(theta=0.5, g_max=64)          # interaction-list CSR
-    dev   = DeviceLists.upload(tree, lists, device)  # torch tensors on the GPU
+    perm, pos32, mass32, cell_mom = tree.export(4)
+    dev   = DeviceLists.from_host(pos32, mass32, lists, cell_mom, "cuda:0")
     ctx   = Context(device=0)
     acc, pot = ctx.force(dev, eps=0.01)
+
+Environment overrides: OTOO_CHUNK, OTOO_TILE, OTOO_BLOCKS_PER_CU, OTOO_LPT and
+OTOO_DEBUG_VALIDATE set the schedule of every new Context; OTOO_GMAX sets the
+walks' default group size (64 otherwise); OTOO_AUTOTUNE_CACHE names the
+autotuner's cache file.
 """
 from __future__ import annotations
 
@@ -32,6 +38,28 @@ CORR_PAIRS, CORR_QUAD, CORR_MLP = 0, 1, 2
 CORR_STRIDE = 24
 
 _lib = None
+
+_ENV_KEYS = (("OTOO_CHUNK", "chunk"), ("OTOO_TILE", "tile"), ("OTOO_BLOCKS_PER_CU", "blocks_per_cu"),
+             ("OTOO_LPT", "lpt"), ("OTOO_DEBUG_VALIDATE", "debug_validate"), ("OTOO_GMAX", "g_max"))
+
+
+def env_overrides(environ=None) -> dict:
+    """Integer settings from the environment (the OTOO_* variables above), by
+    field name; unset or empty variables are left out."""
+    env = os.environ if environ is None else environ
+    out = {}
+    for key, name in _ENV_KEYS:
+        v = env.get(key, "")
+        if v.strip():
+            try:
+                out[name] = int(v)
+            except ValueError:
+                raise ValueError(f"{key}={v!r} is not an integer") from None
+    return out
+
+
+def _g_max(g_max):
+    return int(g_max) if g_max is not None else env_overrides().get("g_max", 64)
 
 
 class OtooError(RuntimeError):
@@ -220,36 +248,38 @@ class Tree:
         _check(lib().otoo_tree_links(self._h, _np_ptr(nxt), _np_ptr(more)), "otoo_tree_links")
         return nxt, more
 
-    def walk(self, theta: float = 0.5, g_max: int = 64, group_mode: int = GROUP_CHUNK, mac: int = MAC_BH,
+    def walk(self, theta: float = 0.5, g_max: int | None = None, group_mode: int = GROUP_CHUNK, mac: int = MAC_BH,
              delta: float = 0.01, m_limit: float = math.inf) -> Lists:
-        p = _WalkParams(mac=mac, theta=theta, delta=delta, m_limit=m_limit, group_mode=group_mode, g_max=g_max)
+        p = _WalkParams(mac=mac, theta=theta, delta=delta, m_limit=m_limit, group_mode=group_mode,
+                        g_max=_g_max(g_max))
         out = ctypes.POINTER(_Lists)()
         _check(lib().otoo_tree_walk(self._h, ctypes.byref(p), ctypes.byref(out)), "otoo_tree_walk")
         return self._take_lists(out)
 
-    def n_groups(self, g_max: int = 64, group_mode: int = GROUP_CHUNK) -> int:
+    def n_groups(self, g_max: int | None = None, group_mode: int = GROUP_CHUNK) -> int:
         """Number of groups the walk forms for (group_mode, g_max)."""
         ng = ctypes.c_int32()
-        _check(lib().otoo_tree_groups(self._h, int(group_mode), int(g_max), ctypes.byref(ng)), "otoo_tree_groups")
+        _check(lib().otoo_tree_groups(self._h, int(group_mode), _g_max(g_max), ctypes.byref(ng)), "otoo_tree_groups")
         return ng.value
 
-    def walk_range(self, g_begin: int, g_end: int, theta: float = 0.5, g_max: int = 64,
+    def walk_range(self, g_begin: int, g_end: int, theta: float = 0.5, g_max: int | None = None,
                    group_mode: int = GROUP_CHUNK, mac: int = MAC_BH, delta: float = 0.01,
                    m_limit: float = math.inf) -> Lists:
         """The walk restricted to groups [g_begin, g_end): absolute group_off, list_off from 0."""
-        p = _WalkParams(mac=mac, theta=theta, delta=delta, m_limit=m_limit, group_mode=group_mode, g_max=g_max)
+        p = _WalkParams(mac=mac, theta=theta, delta=delta, m_limit=m_limit, group_mode=group_mode,
+                        g_max=_g_max(g_max))
         out = ctypes.POINTER(_Lists)()
         _check(lib().otoo_tree_walk_range(self._h, ctypes.byref(p), int(g_begin), int(g_end), ctypes.byref(out)),
                "otoo_tree_walk_range")
         return self._take_lists(out)
 
-    def walk_sph(self, h, g_max: int = 64, group_mode: int = GROUP_CHUNK) -> Lists:
+    def walk_sph(self, h, g_max: int | None = None, group_mode: int = GROUP_CHUNK) -> Lists:
         """Neighbour lists for SPH gather sums; h [n] in the caller's particle order."""
         h = np.ascontiguousarray(h, dtype=np.float64)
         if h.shape != (self.n,):
             raise ValueError("h must have one entry per particle")
         out = ctypes.POINTER(_Lists)()
-        _check(lib().otoo_tree_walk_sph(self._h, h.ctypes.data_as(ctypes.c_void_p), int(group_mode), int(g_max),
+        _check(lib().otoo_tree_walk_sph(self._h, h.ctypes.data_as(ctypes.c_void_p), int(group_mode), _g_max(g_max),
                                         ctypes.byref(out)), "otoo_tree_walk_sph")
         return self._take_lists(out)
 
@@ -364,6 +394,9 @@ class Context:
         _check(lib().otoo_create(ctypes.byref(h), int(device)), "otoo_create")
         self._h = h
         self.sync_stream()
+        sched = {k: v for k, v in env_overrides().items() if k != "g_max"}
+        if sched:
+            self.set_tuning(**sched)
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -15,7 +15,16 @@ import os
 
 from . import GROUP_CELL, GROUP_CHUNK, Context, Tree
 
-DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
+PACKAGE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
+
+
+def default_cache(environ=None) -> str:
+    """The cache file: OTOO_AUTOTUNE_CACHE if set, else the package's."""
+    env = os.environ if environ is None else environ
+    return env.get("OTOO_AUTOTUNE_CACHE", "").strip() or PACKAGE_CACHE
+
+
+DEFAULT_CACHE = default_cache()
 TIE = 0.01   # relative time difference below which two schedules count as equally fast
 
 GRID = {
