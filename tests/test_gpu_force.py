@@ -138,13 +138,18 @@ def test_polytrope_pair_and_cube(ctx):
     _assert_parity(acc, pot, a_ref, p_ref, "grf cube")
 
 
+@pytest.mark.parametrize("tile", [256, 1024])
 @pytest.mark.parametrize("n", [1, 2, 3, 65])
-def test_tiny_inputs(ctx, n):
+def test_tiny_inputs(ctx, n, tile):
     rng = np.random.default_rng(n)
     pos = rng.normal(size=(n, 3))
     m = rng.uniform(0.5, 1.5, n)
     t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.5, 64)
-    acc, pot = _gpu(ctx, d, 0.05)
+    ctx.set_tuning(tile=tile)
+    try:
+        acc, pot = _gpu(ctx, d, 0.05)
+    finally:
+        ctx.set_tuning(tile=256)
     a_ref, p_ref = _oracle(pos32, mass32, lists, cm, 0.05)
     if n == 1:
         assert np.all(acc == 0) and np.all(pot == 0)
