@@ -13,9 +13,14 @@ paper's models are Delta^-3/4 for the cost and Delta^1/4 for the error.
     python -m paper_1206_1199_amd.sweeps delta [--dist uniform|plummer] [--n N] [--eps E]
     python -m paper_1206_1199_amd.sweeps theta [--dist ...]
     python -m paper_1206_1199_amd.sweeps sph [--dist polytrope|uniform|plummer] [--n N] [--k K]
+    python -m paper_1206_1199_amd.sweeps corr [--dist plummer] [--n N] [--values THETA] [--gates G,...]
 
 The sph sweep times the SPH neighbour walk and the gather sums (density,
 q = m) with neighbour radii from the K-th nearest neighbour, for each g_max.
+The corr sweep times the cell-correction passes on the lists of one opening
+angle: the textbook quadrupole and the network at each gate (the network's
+initial parameters: the gate depends on the features only, so the cost is
+that of a trained network).
 
 One JSON object per setting on stdout; a summary object last.
 """
@@ -165,9 +170,48 @@ def run_sph(dist: str, n: int, g_list, k: int, reps: int, seed: int, emit=print)
     return rows
 
 
+def run_corr(dist: str, n: int, g_list, theta: float, gates, eps: float, reps: int, seed: int, emit=print):
+    import torch
+    import synth
+    from . import CORR_MLP, CORR_QUAD, learned
+    pos, m = synth.plummer(n, seed=seed) if dist == "plummer" else synth.uniform_sphere(n, seed=seed)
+    tree = Tree(pos, m, n_crit=16)
+    _, pos32, mass32, cm = tree.export(12)
+    ctx = Context(0)
+    net = learned.Network(ctx)
+    net.set_params(learned.init_params(0))
+    rows = []
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ctx.check()
+        return e0.elapsed_time(e1) / reps
+
+    for g_max in g_list:
+        d = DeviceLists.from_host(pos32, mass32, tree.walk(theta=theta, g_max=g_max), cm, "cuda:0")
+        out = ctx.correction(d, CORR_QUAD, eps)
+        row = {"corr": dist, "n": len(m), "theta": theta, "g_max": g_max, "pairs": d.n_pairs,
+               "quad_ms": timed(lambda: ctx.correction(d, CORR_QUAD, eps, out=out))}
+        for gate in gates:
+            net.set_gate(gate)
+            row[f"net_ms_gate_{gate:g}"] = timed(lambda: ctx.correction(d, CORR_MLP, eps, net=net, out=out))
+        rows.append(row)
+        emit(json.dumps(row))
+        sys.stdout.flush()
+    return rows
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("kind", choices=["delta", "theta", "sph"])
+    ap.add_argument("kind", choices=["delta", "theta", "sph", "corr"])
     ap.add_argument("--dist", choices=["uniform", "plummer", "polytrope"], default="uniform")
     ap.add_argument("--k", type=int, default=50, help="sph: neighbours inside h")
     ap.add_argument("--n", type=int, default=8000 * 1024)
@@ -177,7 +221,13 @@ def main(argv=None):
     ap.add_argument("--m-limit", type=float, default=0.05)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--seed", type=int, default=5)
+    ap.add_argument("--gates", default="0.4,0", help="corr: network gates (l/|d| thresholds)")
     a = ap.parse_args(argv)
+    if a.kind == "corr":
+        theta = float(a.values) if a.values else 0.9
+        run_corr(a.dist, a.n, [int(g) for g in a.g_max.split(",")], theta, [float(x) for x in a.gates.split(",")],
+                 a.eps, a.reps, a.seed)
+        return
     if a.kind == "sph":
         run_sph(a.dist, a.n, [int(g) for g in a.g_max.split(",")], a.k, a.reps, a.seed)
         return
