@@ -4,8 +4,9 @@ by the library's forward/backward/Adam kernels).
 
     net = Network(ctx)
     net.set_params(init_params(seed=0))
-    X, aux = make_training_set(ctx, net, configs, n_samples, seed)
-    fit(net, X, aux, eps_list..., steps=..., lr=...)
+    X, aux, eps_all = make_training_set(ctx, net, configs, seed, gate=0.4)
+    fit(net, X, aux, eps_all, steps=3000, batch=32768, lr=2e-3, seed=1)
+    net.set_gate(0.4)
     gcorr = ctx.correction(dev_lists, CORR_MLP, eps, net=net)   # fused per-group expansion
     acc, pot = ctx.force(dev_lists, eps, gcorr=gcorr)
 """
@@ -243,7 +244,7 @@ def make_training_set(ctx, net: Network, configs, seed: int, device="cuda:0", lo
         # weight: 1 / |a_i|^2 with a_i the target's total (monopole-tree) force,
         # so a sample counts by its share of the per-particle relative error
         acc, _ = ctx.force(d, cfg.eps)
-        a2 = (acc[smp[:, 1]].double() ** 2).sum(dim=1)
+        a2 = (acc[smp[:, 1]].double() ** 2).sum(dim=1).clamp_min(1e-300)   # a target at rest: finite weight
         wt = 1.0 / a2
         t2 = (aux[:, 6:9].double() ** 2).sum(dim=1)
         aux[:, 10] = (wt / (wt * t2).mean()).float()     # normalised: the zero-correction loss is 1
@@ -293,10 +294,10 @@ def fit(net: Network, X, aux, eps_all, steps: int, batch: int, lr: float, seed: 
 
 def evaluate_loss(net: Network, X, aux, eps_all):
     """Sample-weighted mean loss over eps classes (no update)."""
+    import torch
     eps_host = eps_all.cpu().numpy()
     tot, cnt = 0.0, 0
     for e in np.unique(eps_host):
-        import torch
         idx = torch.from_numpy(np.where(eps_host == e)[0]).to(X.device)
         _, loss = net.backward(X[idx].contiguous(), aux[idx].contiguous(), float(e))
         tot += loss * len(idx)
