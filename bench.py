@@ -21,6 +21,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import contextlib
 import json
 import os
 import sys
@@ -55,6 +56,24 @@ GROUPS = {
     "plummer16k": [(0, 64), (1, 64)],
     "plummer1m": [(0, 64), (0, 128), (0, 256)],
 }
+
+
+@contextlib.contextmanager
+def marker(name):
+    """A roctx range around a host phase (torch's NVTX calls are roctx on
+    ROCm), shown by a rocprofv3 marker trace; a no-op where markers are
+    unavailable."""
+    try:
+        import torch
+        torch.cuda.nvtx.range_push(name)
+        pushed = True
+    except Exception:
+        pushed = False
+    try:
+        yield
+    finally:
+        if pushed:
+            torch.cuda.nvtx.range_pop()
 
 
 def measured_traffic(desc, sched):
@@ -413,7 +432,8 @@ def main():
     pos, m, eps, theta, desc, classes = make_workload(args.workload)
     log(f"workload {desc}: n={len(m)}")
     t0 = time.perf_counter()
-    tree = otoo.Tree(pos, m, n_crit=16)
+    with marker("tree build"):
+        tree = otoo.Tree(pos, m, n_crit=16)
     t1 = time.perf_counter()
     ctx = otoo.Context(0)
 
@@ -440,7 +460,8 @@ def main():
     log(f"schedule ({source}): {sched}")
 
     t2 = time.perf_counter()
-    lists = tree.walk(theta=theta, g_max=sched["g_max"], group_mode=mode)
+    with marker("host walk"):
+        lists = tree.walk(theta=theta, g_max=sched["g_max"], group_mode=mode)
     t3 = time.perf_counter()
     perm, pos32, mass32, cm = tree.export(4)
     log(f"tree {1e3 * (t1 - t0):.0f} ms, walk {1e3 * (t3 - t2):.0f} ms: groups {lists.n_groups}, "
@@ -448,8 +469,9 @@ def main():
 
     torch.cuda.synchronize()
     t4 = time.perf_counter()
-    d = otoo.DeviceLists.from_host(pos32, mass32, lists, cm, "cuda:0")
-    torch.cuda.synchronize()
+    with marker("copy to device"):
+        d = otoo.DeviceLists.from_host(pos32, mass32, lists, cm, "cuda:0")
+        torch.cuda.synchronize()
     t5 = time.perf_counter()
 
     ctx.set_tuning(chunk=sched["chunk"], blocks_per_cu=sched["blocks_per_cu"], lpt=sched["lpt"], tile=sched["tile"])
@@ -476,13 +498,14 @@ def main():
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    w0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        ctx.graph_launch()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    w1 = time.perf_counter()
+    with marker("timed force evaluations"):
+        w0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            ctx.graph_launch()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        w1 = time.perf_counter()
     ms = e0.elapsed_time(e1) / args.steps
     ctx.check()
     log(f"force eval {ms:.3f} ms/step (wall {1e3 * (w1 - w0) / args.steps:.3f}), force kernel {k_ms:.3f} ms")
