@@ -12,8 +12,9 @@
 //                 FP32 pair arithmetic, per-tile FP32 partials, Kahan across
 //                 tiles.  A group whose list is one item writes its results
 //                 directly; longer lists leave per-item partial rows.
-//   k_reduce      per particle: Kahan over the item partials in item order,
-//                 potential in FP64, self pair removed.
+//   k_reduce      per particle of the groups whose list was split: Kahan
+//                 over the item partials in item order, potential in FP64,
+//                 self pair removed.
 // The pair term is the Plummer-softened monopole; an optional per-group
 // second-order local expansion (from otoo_correction) adds a cell correction.
 #include <hip/hip_runtime.h>
@@ -44,6 +45,7 @@ __global__ void k_pack(const float* __restrict__ pos, const float* __restrict__ 
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e == 0) {
         meta->head = 0;
+        meta->n_split = 0;
         for (int c = 0; c < kClasses; c++) {
             meta->hist[c] = 0;
             meta->cursor[c] = 0;
@@ -166,17 +168,21 @@ __device__ __forceinline__ int cost_class(int64_t cost) {
     return c >= kClasses ? kClasses - 1 : c;
 }
 
-// Item table (g, k) and, for longest-first, a histogram of cost classes
-// (counted in LDS, one global atomic per class per workgroup).
+// Item table (g, k), the list of groups split into several items (for the
+// reduction) and, for longest-first, a histogram of cost classes (counted in
+// LDS, one global atomic per class and one for the split list per workgroup).
 __global__ __launch_bounds__(256) void k_sched_fill(const int32_t* __restrict__ group_off,
                                                     const int64_t* __restrict__ list_off, int64_t n_entries,
                                                     int32_t n_groups, int32_t chunk, int64_t* item_base,
                                                     int64_t* part_base, const int64_t* __restrict__ block_tot,
                                                     int2* items, int64_t item_cap, int32_t lpt, Meta* meta,
-                                                    int32_t* err) {
+                                                    int32_t* __restrict__ split, int32_t* err) {
     __shared__ int hist[kClasses];
+    __shared__ int s_split[256];
+    __shared__ int s_nsplit, s_base;
     const int t = threadIdx.x;
     if (t < kClasses) hist[t] = 0;
+    if (t == 0) s_nsplit = 0;
     __syncthreads();
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + t;
     if (g < n_groups) {
@@ -202,8 +208,13 @@ __global__ __launch_bounds__(256) void k_sched_fill(const int32_t* __restrict__ 
                 atomicAdd(&hist[cost_class((int64_t)ng * (l > 0 ? l : 1))], 1);
             }
         }
+        if (c > 1) s_split[atomicAdd(&s_nsplit, 1)] = (int)g;
     }
     __syncthreads();
+    if (t == 0) s_base = s_nsplit ? atomicAdd(&meta->n_split, s_nsplit) : 0;
+    __syncthreads();
+    // n_split never exceeds n_groups, the capacity of the split list
+    if (t < s_nsplit) split[s_base + t] = s_split[t];
     if (lpt && t < kClasses && hist[t]) atomicAdd(&meta->hist[t], hist[t]);
 }
 
@@ -564,34 +575,18 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
 
 // ---------------------------------------------------------------- K3 reduce
 
-// One thread per particle of a group whose list was split into several
-// items: Kahan over the item partials in item order (acceleration, FP32) and
-// an FP64 sum for the potential, then the self pair is removed.
-__global__ __launch_bounds__(256) void k_reduce(const float4* __restrict__ src, const int32_t* __restrict__ group_off,
-                                                int32_t n_groups, const int64_t* __restrict__ list_off,
-                                                int64_t n_entries, int32_t n, int32_t chunk,
+// The reduction of particle i of split group g (see k_reduce).
+__device__ __forceinline__ void reduce_particle(const float4* __restrict__ src, const int64_t* __restrict__ list_off,
+                                                int64_t n_entries, int32_t chunk,
                                                 const int64_t* __restrict__ part_base,
                                                 const float4* __restrict__ partial, int64_t part_cap, float eps2,
-                                                const float* __restrict__ gcorr, float* __restrict__ out_acc,
-                                                double* __restrict__ out_pot) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    // group of particle p: last g with group_off[g] <= p
-    int lo = 0, hi = n_groups - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (group_off[mid] <= p) lo = mid;
-        else hi = mid - 1;
-    }
-    const int g = lo;
-    const int g0 = group_off[g];
-    const int ng = group_off[g + 1] - g0;
-    if (ng < 1 || ng > kBlock || g0 < 0 || g0 + ng > n || p < g0 || p >= g0 + ng) return;
+                                                const float* __restrict__ gcorr, int g, int g0, int ng, int i,
+                                                float* __restrict__ out_acc, double* __restrict__ out_pot) {
     int64_t lb, le;
     list_range(list_off, n_entries, g, lb, le);
     const int64_t nch = n_chunks(le - lb, chunk);
     if (nch == 1) return;
-    const int i = p - g0;
+    const int p = g0 + i;
     float s_ax = 0.f, s_ay = 0.f, s_az = 0.f, c_ax = 0.f, c_ay = 0.f, c_az = 0.f;
     double ph = 0.0;
     for (int64_t k = 0; k < nch; k++) {
@@ -615,6 +610,30 @@ __global__ __launch_bounds__(256) void k_reduce(const float4* __restrict__ src, 
     out_pot[p] = phi;
 }
 
+// The groups whose list was split into several items, one workgroup per
+// group in turn, one thread per particle: Kahan over the item partials in
+// item order (acceleration, FP32) and an FP64 sum for the potential, then the
+// self pair is removed.  (The other groups' outputs were written by k_force.)
+__global__ __launch_bounds__(256) void k_reduce(const float4* __restrict__ src, const int32_t* __restrict__ group_off,
+                                                int32_t n_groups, const int64_t* __restrict__ list_off,
+                                                int64_t n_entries, int32_t n, int32_t chunk,
+                                                const int64_t* __restrict__ part_base,
+                                                const float4* __restrict__ partial, int64_t part_cap, float eps2,
+                                                const float* __restrict__ gcorr, const Meta* __restrict__ meta,
+                                                const int32_t* __restrict__ split, float* __restrict__ out_acc,
+                                                double* __restrict__ out_pot) {
+    const int n_split = meta->n_split < n_groups ? meta->n_split : n_groups;
+    for (int s = blockIdx.x; s < n_split; s += gridDim.x) {
+        const int g = split[s];
+        if (g < 0 || g >= n_groups) continue;
+        const int g0 = group_off[g];
+        const int ng = group_off[g + 1] - g0;
+        if (ng < 1 || ng > kBlock || g0 < 0 || g0 + ng > n || (int)threadIdx.x >= ng) continue;
+        reduce_particle(src, list_off, n_entries, chunk, part_base, partial, part_cap, eps2, gcorr, g, g0, ng,
+                        (int)threadIdx.x, out_acc, out_pot);
+    }
+}
+
 }  // namespace
 
 // ================================================================ runtime
@@ -622,7 +641,7 @@ __global__ __launch_bounds__(256) void k_reduce(const float4* __restrict__ src, 
 namespace {
 
 struct Layout {
-    size_t src, item_base, part_base, block_tot, items, order, partial, total;
+    size_t src, item_base, part_base, block_tot, items, order, split, partial, total;
     int64_t item_cap, part_cap;
 };
 
@@ -649,6 +668,8 @@ Layout plan_layout(int32_t n, int32_t n_groups, int64_t n_entries, int32_t n_cel
     off = align_up(off + sizeof(int2) * (size_t)L.item_cap);
     L.order = off;
     off = align_up(off + sizeof(int32_t) * (size_t)L.item_cap);
+    L.split = off;
+    off = align_up(off + sizeof(int32_t) * ((size_t)n_groups + 1));
     L.partial = off;
     off = align_up(off + 2 * sizeof(float4) * (size_t)L.part_cap);
     L.total = off;
@@ -756,6 +777,7 @@ int enqueue(otoo_ctx* c, const Call& a, bool allow_timing) {
     int64_t* block_tot = reinterpret_cast<int64_t*>(base + L.block_tot);
     int2* items = reinterpret_cast<int2*>(base + L.items);
     int32_t* order = reinterpret_cast<int32_t*>(base + L.order);
+    int32_t* split = reinterpret_cast<int32_t*>(base + L.split);
     float4* partial = reinterpret_cast<float4*>(base + L.partial);
     const float* gcorr = a.gcorr;
     hipStream_t s = c->stream;
@@ -771,7 +793,7 @@ int enqueue(otoo_ctx* c, const Call& a, bool allow_timing) {
     hipLaunchKernelGGL(k_sched_scan2, dim3(1), dim3(256), 0, s, block_tot, n_blocks, c->meta);
     hipLaunchKernelGGL(k_sched_fill, dim3((a.n_groups + 255) / 256), dim3(256), 0, s, a.group_off, a.list_off,
                        a.n_entries, a.n_groups, tu.chunk, item_base, part_base, block_tot, items, L.item_cap,
-                       tu.lpt, c->meta, c->errflag);
+                       tu.lpt, c->meta, split, c->errflag);
     if (tu.lpt) {
         hipLaunchKernelGGL(k_lpt_offsets, dim3(1), dim3(64), 0, s, c->meta);
         hipLaunchKernelGGL(k_lpt_scatter, dim3(1024), dim3(256), 0, s, items, a.group_off, a.list_off, a.n_entries,
@@ -807,10 +829,12 @@ int enqueue(otoo_ctx* c, const Call& a, bool allow_timing) {
     else
         hipLaunchKernelGGL(k_force<256>, dim3(grid), dim3(kBlock), 0, s, fa);
     if (tm) HIP_TRY(c, hipEventRecord(c->ev[2], s));
-    if ((int64_t)tu.chunk < a.n_entries)   // otherwise no list is split and k_force wrote every output
-        hipLaunchKernelGGL(k_reduce, dim3((a.n + 255) / 256), dim3(256), 0, s, src, a.group_off, a.n_groups,
-                       a.list_off, a.n_entries, a.n, tu.chunk, part_base, partial, L.part_cap, fa.eps2, gcorr,
-                       a.out_acc, a.out_pot);
+    if ((int64_t)tu.chunk < a.n_entries) {   // otherwise no list is split and k_force wrote every output
+        const int red_grid = (int)std::min<int64_t>(a.n_groups, 8LL * c->num_cu);
+        hipLaunchKernelGGL(k_reduce, dim3(red_grid), dim3(256), 0, s, src, a.group_off, a.n_groups, a.list_off,
+                           a.n_entries, a.n, tu.chunk, part_base, partial, L.part_cap, fa.eps2, gcorr, c->meta,
+                           split, a.out_acc, a.out_pot);
+    }
     HIP_TRY(c, hipGetLastError());
     return OTOO_OK;
 }

@@ -25,7 +25,7 @@ struct Meta {
     int64_t n_items;
     int64_t n_parts;
     int32_t head;
-    int32_t pad;
+    int32_t n_split;   // groups whose list is split into several items (listed for the reduction)
     int32_t hist[kClasses];
     int32_t cursor[kClasses];
 };
