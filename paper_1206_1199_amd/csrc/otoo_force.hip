@@ -218,17 +218,6 @@ __global__ __launch_bounds__(256) void k_sched_fill(const int32_t* __restrict__ 
     if (lpt && t < kClasses && hist[t]) atomicAdd(&meta->hist[t], hist[t]);
 }
 
-// Longest-first order: classes from the most to the least expensive.
-__global__ void k_lpt_offsets(Meta* meta) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        int run = 0;
-        for (int c = kClasses - 1; c >= 0; c--) {
-            meta->cursor[c] = run;
-            run += meta->hist[c];
-        }
-    }
-}
-
 __device__ __forceinline__ int item_class(const int2 it, const int32_t* group_off, const int64_t* list_off,
                                           int64_t n_entries, int32_t chunk) {
     int64_t b, e;
@@ -241,15 +230,24 @@ __device__ __forceinline__ int item_class(const int2 it, const int32_t* group_of
     return cost_class((int64_t)ng * (l > 0 ? l : 1));
 }
 
-// Scatter items into class order.  Each workgroup takes a contiguous range of
-// items, ranks them per class in LDS and reserves its slots with one global
-// atomic per class.
+// Scatter items into longest-first order: classes from the most to the least
+// expensive.  Each workgroup takes a contiguous range of items, ranks them
+// per class in LDS and reserves its slots with one global atomic per class
+// (a class's slots start after every more expensive class, summed from the
+// histogram).
 __global__ __launch_bounds__(256) void k_lpt_scatter(const int2* __restrict__ items, const int32_t* __restrict__ group_off,
                                                      const int64_t* __restrict__ list_off, int64_t n_entries,
                                                      int32_t chunk, int64_t item_cap, Meta* meta,
                                                      int32_t* __restrict__ order) {
-    __shared__ int cnt[kClasses], base[kClasses], rank[kClasses];
+    __shared__ int cnt[kClasses], base[kClasses], rank[kClasses], first[kClasses];
     const int t = threadIdx.x;
+    if (t == 0) {
+        int run = 0;
+        for (int c = kClasses - 1; c >= 0; c--) {
+            first[c] = run;
+            run += meta->hist[c];
+        }
+    }
     const int64_t n_items = meta->n_items < item_cap ? meta->n_items : item_cap;
     const int64_t per = (n_items + gridDim.x - 1) / gridDim.x;
     const int64_t q0 = (int64_t)blockIdx.x * per;
@@ -262,7 +260,7 @@ __global__ __launch_bounds__(256) void k_lpt_scatter(const int2* __restrict__ it
     for (int64_t q = q0 + t; q < q1; q += blockDim.x)
         atomicAdd(&cnt[item_class(items[q], group_off, list_off, n_entries, chunk)], 1);
     __syncthreads();
-    if (t < kClasses) base[t] = cnt[t] ? atomicAdd(&meta->cursor[t], cnt[t]) : 0;
+    if (t < kClasses) base[t] = cnt[t] ? first[t] + atomicAdd(&meta->cursor[t], cnt[t]) : 0;
     __syncthreads();
     for (int64_t q = q0 + t; q < q1; q += blockDim.x) {
         const int cls = item_class(items[q], group_off, list_off, n_entries, chunk);
@@ -795,9 +793,9 @@ int enqueue(otoo_ctx* c, const Call& a, bool allow_timing) {
                        a.n_entries, a.n_groups, tu.chunk, item_base, part_base, block_tot, items, L.item_cap,
                        tu.lpt, c->meta, split, c->errflag);
     if (tu.lpt) {
-        hipLaunchKernelGGL(k_lpt_offsets, dim3(1), dim3(64), 0, s, c->meta);
-        hipLaunchKernelGGL(k_lpt_scatter, dim3(1024), dim3(256), 0, s, items, a.group_off, a.list_off, a.n_entries,
-                           tu.chunk, L.item_cap, c->meta, order);
+        const int lpt_grid = (int)std::min<int64_t>(1024, (L.item_cap + 255) / 256);
+        hipLaunchKernelGGL(k_lpt_scatter, dim3(lpt_grid), dim3(256), 0, s, items, a.group_off, a.list_off,
+                           a.n_entries, tu.chunk, L.item_cap, c->meta, order);
     }
     ForceArgs fa;
     fa.src = src;
