@@ -236,6 +236,29 @@ int otoo_force(otoo_ctx* ctx, int32_t n, const float* pos, const float* mass, in
                int32_t n_cells, const float* cell_mom, int32_t cell_stride, float eps, const float* gcorr,
                float* out_acc, double* out_pot);
 
+/* Host-only plan of an otoo_force call (no device call, no context): the
+ * same size checks otoo_force makes before it touches the device, and the
+ * bytes of context scratch such a call needs (unified source table, work
+ * items, longest-first order, partial rows of split lists).
+ *   n, n_groups, n_entries, n_cells   as for otoo_force
+ *   chunk        list entries per work item (otoo_tuning.chunk, 64 .. 2^28)
+ *   workgroups   persistent workgroups of the force kernel (CUs x
+ *                blocks_per_cu), 1 .. 2^20
+ *   *scratch_bytes (may be NULL) receives the scratch size.
+ * EINVAL for sizes out of range, and when the work items plus one last
+ * queue fetch per workgroup would reach 2^31: the device queue head, the
+ * item table and the longest-first order are 32-bit, so such a call is
+ * refused before anything is allocated or enqueued. */
+int otoo_force_plan(int32_t n, int32_t n_groups, int64_t n_entries, int32_t n_cells, int32_t chunk,
+                    int32_t workgroups, int64_t* scratch_bytes);
+
+/* Generation of the context's device scratch: a counter raised every time
+ * the context allocates a scratch buffer anew (force, SPH and correction
+ * scratch, and the per-group geometry of a network bound to it).  A graph
+ * captured around calls of this library names the scratch of its
+ * generation; after the counter changes it must be captured again. */
+int otoo_scratch_generation(const otoo_ctx* ctx, int64_t* gen);
+
 /* Direct summation at selected targets: the O(N^2) sum of Sec. 2 that the
  * tree approximates, used as the accuracy reference of the tree force.  For
  * k < n_tgt and i = tgt[k], with d = x_j - x_i and r^2 = |d|^2 + eps^2:

@@ -97,7 +97,7 @@ EXPORTED = [
     "otoo_tree_links", "otoo_tree_walk", "otoo_tree_groups", "otoo_tree_walk_range", "otoo_tree_walk_sph", "otoo_lists_free", "otoo_create", "otoo_destroy",
     "otoo_set_stream", "otoo_last_error", "otoo_set_tuning", "otoo_get_tuning", "otoo_force",
     "otoo_check", "otoo_enable_timing", "otoo_last_timing", "otoo_graph_capture", "otoo_graph_launch",
-    "otoo_autotune", "otoo_set_scratch_limit",
+    "otoo_autotune", "otoo_set_scratch_limit", "otoo_force_plan", "otoo_scratch_generation",
     "otoo_quad_exact", "otoo_correction", "otoo_direct", "otoo_sph_sum", "otoo_mlp_num_params", "otoo_mlp_create", "otoo_mlp_destroy", "otoo_mlp_set_params", "otoo_mlp_set_gate",
     "otoo_mlp_get_params", "otoo_mlp_save", "otoo_mlp_load", "otoo_mlp_forward", "otoo_mlp_infer",
     "otoo_mlp_train_samples", "otoo_mlp_backward", "otoo_mlp_train_step",
@@ -134,6 +134,8 @@ def lib():
         "otoo_set_tuning": ([P, ctypes.POINTER(Tuning)], I32),
         "otoo_get_tuning": ([P, ctypes.POINTER(Tuning)], I32),
         "otoo_set_scratch_limit": ([P, I64], I32),
+        "otoo_force_plan": ([I32, I32, I64, I32, I32, I32, ctypes.POINTER(I64)], I32),
+        "otoo_scratch_generation": ([P, ctypes.POINTER(I64)], I32),
         "otoo_force": ([P, I32, P, P, I32, P, I64, P, P, I32, P, I32, F, P, P, P], I32),
         "otoo_correction": ([P, I32, P, I32, P, I32, P, I64, P, P, I64, P, I32, P, I32, F, P, P], I32),
         "otoo_quad_exact": ([P, I32, I32, I64, P, P, I64, P, I32, P, I32, P], I32),
@@ -378,6 +380,36 @@ def _lists_on_device(cls, pos, mass, cell_mom, lists: Lists):
 DeviceLists.on_device = classmethod(_lists_on_device)
 
 
+def force_plan(n: int, n_groups: int, n_entries: int, n_cells: int, chunk: int, workgroups: int) -> int:
+    """Scratch bytes of an otoo_force call with these sizes (host only, no
+    device); raises OtooError(EINVAL) for sizes the call would refuse,
+    among them work queues of 2^31 or more items."""
+    b = ctypes.c_int64()
+    rc = lib().otoo_force_plan(int(n), int(n_groups), int(n_entries), int(n_cells), int(chunk), int(workgroups),
+                               ctypes.byref(b))
+    _check(rc, "otoo_force_plan")
+    return b.value
+
+
+class CapturedGraph:
+    """A torch CUDA graph of library calls on one context, guarded against
+    replays after the context's scratch was allocated anew."""
+
+    def __init__(self, ctx, graph, generation):
+        self.ctx = ctx
+        self.graph = graph
+        self.generation = generation
+
+    def stale(self) -> bool:
+        return self.ctx.scratch_generation() != self.generation
+
+    def replay(self):
+        if self.stale():
+            raise OtooError(EINVAL, "the context's scratch was reallocated after this graph was captured; "
+                                    "capture it again")
+        self.graph.replay()
+
+
 def _tptr(x):
     return ctypes.c_void_p(x.data_ptr()) if x is not None else None
 
@@ -436,11 +468,20 @@ class Context:
                 _tptr(d.list_off), _tptr(d.list_idx), d.n_cells, _tptr(d.cell_mom) if d.n_cells else None,
                 stride, float(eps), _tptr(gcorr), _tptr(out_acc), _tptr(out_pot))
 
+    def scratch_generation(self) -> int:
+        """Counter raised whenever the context allocates a scratch buffer anew."""
+        g = ctypes.c_int64()
+        self._raise(lib().otoo_scratch_generation(self._h, ctypes.byref(g)), "otoo_scratch_generation")
+        return g.value
+
     def capture(self, fn):
-        """A torch CUDA graph of fn() (calls on this context, with preallocated
+        """A replayable graph of fn() (calls on this context, with preallocated
         outputs).  fn runs once eagerly first, so that every scratch buffer is
         allocated outside the capture; the context follows the capture stream
-        and returns to the current stream afterwards."""
+        and returns to the current stream afterwards.  The graph names the
+        context's scratch as it was at capture: ``replay`` raises once the
+        context has allocated scratch anew (a later call needed more), instead
+        of writing freed memory."""
         import torch
         fn()
         torch.cuda.synchronize()
@@ -451,7 +492,7 @@ class Context:
                 fn()
         finally:
             self.sync_stream()
-        return g
+        return CapturedGraph(self, g, self.scratch_generation())
 
     def outputs(self, n):
         import torch

@@ -708,6 +708,7 @@ int ensure_scratch(otoo_ctx* c, size_t bytes) {
         return fail(c, OTOO_ENOMEM, "device scratch of %zu bytes could not be allocated", want);
     }
     c->buf_bytes = want;
+    c->scratch_gen++;
     return OTOO_OK;
 }
 
@@ -848,20 +849,36 @@ int enqueue(otoo_ctx* c, const Call& a, bool allow_timing) {
     return OTOO_OK;
 }
 
+// The host-side plan of a call: sizes in range and the scratch layout.  The
+// queue head, the item table's chunk index and the longest-first order are
+// 32-bit: every fetch, including each of the `workgroups` persistent
+// workgroups' last one, must stay below 2^31.  Touches no device state.
+int plan_call(otoo_ctx* c, int32_t n, int32_t n_groups, int64_t n_entries, int32_t n_cells, int32_t chunk,
+              int64_t workgroups, Layout& L) {
+    if (n < 1 || n > (1 << 30)) return fail(c, OTOO_EINVAL, "n = %d outside 1..2^30", n);
+    if (n_groups < 1 || n_groups > n) return fail(c, OTOO_EINVAL, "n_groups = %d outside 1..n", n_groups);
+    if (n_entries < 0) return fail(c, OTOO_EINVAL, "n_entries < 0");
+    if (n_cells < 0 || (int64_t)n + n_cells > INT32_MAX) return fail(c, OTOO_EINVAL, "n_cells = %d out of range", n_cells);
+    if (chunk < 64 || chunk > (1 << 28)) return fail(c, OTOO_EINVAL, "chunk must be in 64..2^28");
+    if (workgroups < 1 || workgroups > (1 << 20)) return fail(c, OTOO_EINVAL, "workgroups out of range");
+    L = plan_layout(n, n_groups, n_entries, n_cells, chunk);
+    if (L.item_cap + workgroups >= INT32_MAX)
+        return fail(c, OTOO_EINVAL, "%lld work items exceed the 32-bit queue; use a longer chunk",
+                    (long long)L.item_cap);
+    return OTOO_OK;
+}
+
 int prepare(otoo_ctx* c, const Call& a) {
     int rc = check_args(c, a);
+    if (rc) return rc;
+    Layout L;
+    rc = plan_call(c, a.n, a.n_groups, a.n_entries, a.n_cells, c->tune.chunk,
+                   (int64_t)c->num_cu * c->tune.blocks_per_cu, L);
     if (rc) return rc;
     if (c->tune.debug_validate) {
         rc = validate_csr(c, a);
         if (rc) return rc;
     }
-    const Layout L = plan_layout(a.n, a.n_groups, a.n_entries, a.n_cells, c->tune.chunk);
-    // the queue head, the item table's chunk index and the longest-first
-    // order are 32-bit: every fetch, including each workgroup's last one,
-    // must stay below 2^31
-    if (L.item_cap + (int64_t)c->num_cu * c->tune.blocks_per_cu >= INT32_MAX)
-        return fail(c, OTOO_EINVAL, "%lld work items exceed the 32-bit queue; use a longer chunk",
-                    (long long)L.item_cap);
     return ensure_scratch(c, L.total);
 }
 
@@ -957,6 +974,21 @@ int otoo_set_scratch_limit(otoo_ctx* c, int64_t max_bytes) {
     if (!c) return OTOO_EINVAL;
     if (max_bytes < 0) return fail(c, OTOO_EINVAL, "the scratch cap must not be negative");
     c->scratch_cap = (size_t)max_bytes;
+    return OTOO_OK;
+}
+
+int otoo_force_plan(int32_t n, int32_t n_groups, int64_t n_entries, int32_t n_cells, int32_t chunk,
+                    int32_t workgroups, int64_t* scratch_bytes) {
+    Layout L;
+    const int rc = plan_call(nullptr, n, n_groups, n_entries, n_cells, chunk, workgroups, L);
+    if (rc) return rc;
+    if (scratch_bytes) *scratch_bytes = (int64_t)L.total;
+    return OTOO_OK;
+}
+
+int otoo_scratch_generation(const otoo_ctx* c, int64_t* gen) {
+    if (!c || !gen) return OTOO_EINVAL;
+    *gen = c->scratch_gen;
     return OTOO_OK;
 }
 

@@ -175,6 +175,9 @@ struct otoo_ctx {
     otoo_tuning tune{1024, 8, 1, 0, 256, 0};
     int num_cu = 0;
     size_t scratch_cap = 0;   // largest scratch buffer allowed (0: no cap)
+    // bumped whenever a scratch buffer of the context (or of a network bound
+    // to it) is allocated anew: a graph captured before names freed memory
+    int64_t scratch_gen = 0;
     // scratch
     void* buf = nullptr;
     size_t buf_bytes = 0;

@@ -1558,6 +1558,7 @@ int ensure_corr_scratch(otoo_ctx* c, size_t bytes) {
         return fail(c, OTOO_ENOMEM, "correction scratch of %zu bytes could not be allocated", want);
     }
     c->corr_bytes = want;
+    c->scratch_gen++;
     return OTOO_OK;
 }
 
@@ -1718,6 +1719,7 @@ int otoo_mlp_infer(otoo_mlp* m, int32_t n, const float* pos, int32_t n_groups, c
         m->geom_cap = 0;   // stays 0 if the allocation fails
         HIP_TRY(c, hipMalloc(&m->geom, sizeof(float4) * (size_t)n_groups));
         m->geom_cap = n_groups;
+        c->scratch_gen++;
     }
     hipLaunchKernelGGL(k_group_geom, dim3(n_groups), dim3(256), 0, c->stream, pos, n, group_off, m->geom,
                        c->errflag);

@@ -372,6 +372,7 @@ int ensure_sph_scratch(otoo_ctx* c, size_t bytes) {
         return fail(c, OTOO_ENOMEM, "SPH scratch of %zu bytes could not be allocated", want);
     }
     c->sph_bytes = want;
+    c->scratch_gen++;
     return OTOO_OK;
 }
 

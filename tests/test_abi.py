@@ -48,3 +48,32 @@ def test_null_context_and_bad_arguments_return_einval():
     assert lib.otoo_last_error(None) == b"null context"
     assert lib.otoo_tree_build(None, None, 0, 16, None) == otoo.EINVAL
     assert lib.otoo_tree_walk(None, None, None) == otoo.EINVAL
+    assert lib.otoo_scratch_generation(None, None) == otoo.EINVAL
+
+
+def test_force_plan_checks_the_queue_range_on_the_host():
+    """The size checks and scratch plan of otoo_force run on the host alone
+    (the same function otoo_force calls before it touches the device): a call
+    whose work items, plus one last queue fetch per persistent workgroup,
+    would reach 2^31 is refused, since the device queue head, the item table
+    and the longest-first order are 32-bit."""
+    lib = otoo.lib()
+    # 2^30 particles in 2^30 one-particle groups with 2^37 list entries in
+    # chunks of 64: 2^30 + 2^31 items
+    with pytest.raises(otoo.OtooError) as e:
+        otoo.force_plan(1 << 30, 1 << 30, 1 << 37, 0, 64, 2048)
+    assert e.value.code == otoo.EINVAL
+    # just below the limit: items = n_groups + n_entries // chunk + 1
+    wg = 2048
+    n_groups = 1 << 20
+    entries = (2 ** 31 - 1 - wg - n_groups - 2) * 64
+    assert otoo.force_plan(1 << 30, n_groups, entries, 0, 64, wg) > 0
+    with pytest.raises(otoo.OtooError):
+        otoo.force_plan(1 << 30, n_groups, entries + 64, 0, 64, wg)
+    # the other checks of otoo_force's sizes
+    for args in ((0, 1, 0, 0, 1024, 1), (10, 11, 0, 0, 1024, 1), (10, 1, -1, 0, 1024, 1), (10, 1, 0, -1, 1024, 1),
+                 (10, 1, 0, 0, 32, 1), (10, 1, 0, 0, 1024, 0)):
+        assert lib.otoo_force_plan(*args, None) == otoo.EINVAL, args
+    # the scratch holds at least the unified source table
+    n, nc = 16384, 2500
+    assert otoo.force_plan(n, 256, 400000, nc, 1024, 2048) >= 16 * (n + nc)

@@ -394,6 +394,46 @@ def test_captured_graph_dropped_when_scratch_grows():
     assert np.array_equal(out_big[0].cpu().numpy().astype(np.float64), acc)
 
 
+def test_captured_step_refuses_replay_after_scratch_grows():
+    """A torch graph of library calls (Context.capture) names the context's
+    scratch of the moment.  A later eager call that needs more scratch makes
+    the context allocate anew; the captured step then refuses to replay (it
+    would write freed memory) without being replayed, and a new capture
+    gives the eager result again."""
+    c = otoo.Context(0)
+    pos, m = synth.plummer(2000, seed=8)
+    d_small = _setup(pos, m, 0.5, 64, stride=12)[-1]
+    out = c.outputs(d_small.n)
+    gc = torch.empty((d_small.n_groups, otoo.CORR_STRIDE), dtype=torch.float32, device="cuda:0")
+
+    def step():
+        c.correction(d_small, otoo.CORR_QUAD, 0.01, out=gc)
+        c.force(d_small, 0.01, out=out, gcorr=gc)
+
+    g = c.capture(step)
+    g.replay()
+    torch.cuda.synchronize()
+    ref = out[0].clone()
+    gen = c.scratch_generation()
+    assert not g.stale()
+    pos, m = synth.plummer(16384, seed=9)
+    d_big = _setup(pos, m, 0.5, 64, stride=12)[-1]
+    gc_big = c.correction(d_big, otoo.CORR_QUAD, 0.01)
+    c.force(d_big, 0.01, gcorr=gc_big)
+    torch.cuda.synchronize()
+    assert c.scratch_generation() > gen
+    assert g.stale()
+    with pytest.raises(otoo.OtooError) as e:
+        g.replay()
+    assert e.value.code == otoo.EINVAL
+    g2 = c.capture(step)
+    out[0].zero_()
+    g2.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(out[0], ref)
+    c.check()
+
+
 def test_correction_without_cells(ctx):
     """theta = 0 opens every cell: no group has cell pairs, so every row of the
     correction is zero terms with the group's box centre (written by the
@@ -443,25 +483,3 @@ def test_scratch_cap():
     c.sph_sum(ds, h, ds.mass)
     torch.cuda.synchronize()
     c.check()
-
-
-def test_queue_range_checked_on_the_host():
-    """Sizes that would need 2^31 or more work items (the device queue, the
-    item table and the longest-first order are 32-bit) are rejected with
-    EINVAL by the host before anything is enqueued or allocated; the device
-    buffers passed are never read."""
-    import ctypes
-    c = otoo.Context(0)
-    c.set_tuning(chunk=64)
-    buf = torch.zeros(64, dtype=torch.float64, device="cuda:0")
-    p = ctypes.c_void_p(buf.data_ptr())
-    n = 1 << 30
-    rc = otoo.lib().otoo_force(c._h, n, p, p, n, p, 1 << 37, p, p, 0, None, 4, 0.01, None, p, p)
-    assert rc == otoo.EINVAL
-    assert "32-bit queue" in otoo.lib().otoo_last_error(c._h).decode()
-    # the context still works
-    pos, m = synth.plummer(2048, seed=15)
-    t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.5, 64)
-    a, pt = _gpu(c, d, 0.01)
-    a_ref, p_ref = _oracle(pos32, mass32, lists, cm, 0.01)
-    _assert_parity(a, pt, a_ref, p_ref, "after a rejected call")
