@@ -1,20 +1,24 @@
 """Benchmark: Ginteractions/s and ms per full force evaluation on one MI355X.
 
-Default workload: Plummer sphere, N = 2^20 equal masses (G = M = a = 1), seed 1,
-softening 0.005, opening angle 0.5, groups of at most g_max particles (group
-size and schedule from the autotuner's cache, or its defaults).  The host
-builds the tree and walks it once (timed separately, like the paper's TREE /
-KERNEL / PCIe breakdown); the lists are uploaded once; a step is one full
-force evaluation on the device (pack, schedule, force kernel, reduction)
-replayed from a captured HIP graph with all inputs resident in HBM.
+Default workload: the isolated GRF cube of 256^3 = 2^24 particles (P(k) ~ k^-2,
+rms 0.3, seed 4), softening 1e-3, opening angle 0.7, with the learned cell
+correction and FP32 + Kahan sums: the largest single-GPU configuration.  The
+host builds the tree and walks it once (timed separately, like the paper's
+TREE / KERNEL / PCIe breakdown); the lists are uploaded once; the network is
+trained here on the GPU from the method's own walks; a step is one full force
+evaluation on the device -- the learned correction pass (features, gated
+network, per-group local expansion) and the force (pack, schedule, force
+kernel, reduction) -- captured in one graph and replayed with every input
+resident in HBM.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload plummer1m]
-                    [--autotune] [--no-learned] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload cube16m]
+                    [--mode plain|quad|learned] [--autotune] [--no-learned]
+                    [--no-cpu-baseline] [--no-plummer]
 
-The run also adds the learned-correction comparison (skip with --no-learned)
-on a held-out Plummer sphere (N = 2^20, seed 3): the network is trained here
-on the GPU from the method's own walks, then plain, textbook-quadrupole and
-learned evaluations are timed and checked against the direct sum.
+Other workloads (plummer1m, polytrope2m, plummer16k) default to the plain
+monopole force.  The line also carries the Plummer 2^20 plain headline
+(skip with --no-plummer) and the learned-correction comparison on a held-out
+Plummer sphere at equal 1e-3 median error (skip with --no-learned).
 
 Prints one JSON line.
 """
@@ -388,6 +392,157 @@ def learned_comparison(ctx, net, training, log, timing_reps):
     return res
 
 
+# ------------------------------------------------------------------ the corrected step
+
+
+HEADLINE_MODE = {"cube16m": "learned"}      # the cube is quoted with the learned correction
+
+
+def make_step(ctx, d, eps, mode, net, out, gc):
+    """One full force evaluation of the given mode (correction pass, if any,
+    then the force), writing `out` (and the per-group expansion `gc`)."""
+    import paper_1206_1199_amd as otoo
+    if mode == "plain":
+        return lambda: ctx.force(d, eps, out=out)
+    kind = otoo.CORR_MLP if mode == "learned" else otoo.CORR_QUAD
+
+    def step():
+        ctx.correction(d, kind, eps, net=net, out=gc)
+        ctx.force(d, eps, out=out, gcorr=gc)
+    return step
+
+
+def kernel_times(ctx, d, eps, mode, net, out, gc, reps):
+    """Average durations of the force kernel (HIP events the library records
+    around it on its stream) and of the correction pass (events on torch's
+    current stream, which is the context's stream), from eager launches of
+    the step's own calls."""
+    import torch
+    import paper_1206_1199_amd as otoo
+    kind = otoo.CORR_MLP if mode == "learned" else otoo.CORR_QUAD
+    kf, kc = [], []
+    ctx.enable_timing(True)
+    try:
+        for r in range(reps + 2):
+            if mode != "plain":
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                ctx.correction(d, kind, eps, net=net, out=gc)
+                e1.record()
+                ctx.force(d, eps, out=out, gcorr=gc)
+            else:
+                ctx.force(d, eps, out=out)
+            k, _ = ctx.last_timing()
+            if r >= 2:
+                kf.append(k)
+                if mode != "plain":
+                    kc.append(e0.elapsed_time(e1))
+    finally:
+        ctx.enable_timing(False)
+    ctx.check()
+    return float(np.mean(kf)), (float(np.mean(kc)) if kc else 0.0)
+
+
+def time_graph(ctx, step, warmup, steps):
+    """ms per step of `steps` replays of the step's graph (after `warmup`),
+    bracketed by a device synchronisation on both sides, with HIP events on
+    the replay stream."""
+    import torch
+    g = ctx.capture(step)
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    with marker("timed force evaluations"):
+        w0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(steps):
+            g.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        w1 = time.perf_counter()
+    ctx.check()
+    return e0.elapsed_time(e1) / steps, 1e3 * (w1 - w0) / steps
+
+
+def cpu_baseline_corrected(pos32, mass32, lists, cm, eps, mode, params, gate, groups, tgt):
+    """The FP64 oracle timed on this host for the corrected force of a sample
+    of the workload's groups: the oracle's tensors of the sampled groups'
+    (group, cell) pairs (textbook, or the FP64 network at the trained BF16
+    weights) and its list sums with the cell tensors applied through the
+    same local expansion, for every particle of those groups.  Returns
+    (baseline dict, (acc, pot) at `tgt`)."""
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from corr_parity import pair_tensors
+    from learned_helpers import sub_lists
+    oracle.build()
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    go = np.asarray(lists.group_off, np.int64)
+    lo = np.asarray(lists.list_off, np.int64)
+    all_t = np.concatenate([np.arange(go[g], go[g + 1]) for g in groups]).astype(np.int64)
+    inter = int(((go[groups + 1] - go[groups]) * (lo[groups + 1] - lo[groups])).sum())
+    p64, m64 = pos32.astype(np.float64), mass32.astype(np.float64)
+    com, cmass, e = cm[:, :3].astype(np.float64), cm[:, 3].astype(np.float64), float(np.float32(eps))
+    t0 = time.perf_counter()
+    sub = sub_lists(lists, groups)
+    Q, _ = pair_tensors("mlp" if mode == "learned" else "quad", lists, pos32, cm, eps, sub["pairs"], params, gate)
+    acc, pot = oracle.list_force(p64, m64, sub["group_off"], sub["list_off"], sub["list_idx"], com, cmass, e,
+                                 tgt=all_t, n_cellent=sub["n_cellent"], quad=Q, expanded=True)
+    dt = time.perf_counter() - t0
+    base = {"value": inter / dt / 1e9, "unit": "Ginteractions/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle, {mode} correction: network/textbook tensors of {len(Q)} (group, cell) pairs "
+                      f"and list sums with the expansion for all {len(all_t)} particles of {len(groups)} sampled "
+                      f"groups ({inter} interactions) in {dt:.2f} s",
+            "cpu": _cpu_model(), "nproc": os.cpu_count()}
+    pos_of = {int(i): k for k, i in enumerate(all_t)}
+    rows = np.array([pos_of[int(i)] for i in tgt], np.int64)
+    return base, (acc[rows], pot[rows])
+
+
+def plain_headline(ctx, log, steps, warmup, reps):
+    """The plain monopole headline on the 2^20 Plummer sphere (theta 0.5, its
+    cached schedule): ms per evaluation, interactions/s and the median error
+    against direct sums at its 4096-particle sample."""
+    import torch
+    import paper_1206_1199_amd as otoo
+    from paper_1206_1199_amd import autotune as at
+    pos, m, eps, theta, desc, _ = make_workload("plummer1m")
+    tree = otoo.Tree(pos, m, n_crit=16)
+    sched, source = at.cached_schedule("plummer1m", 0)
+    lists = tree.walk(theta=theta, g_max=sched["g_max"],
+                      group_mode=otoo.GROUP_CHUNK if sched["group_mode"] == "chunk" else otoo.GROUP_CELL)
+    _, pos32, mass32, cm = tree.export(4)
+    d = otoo.DeviceLists.from_host(pos32, mass32, lists, cm, "cuda:0")
+    old = ctx.tuning()
+    ctx.set_tuning(chunk=sched["chunk"], blocks_per_cu=sched["blocks_per_cu"], lpt=sched["lpt"], tile=sched["tile"])
+    try:
+        out = ctx.outputs(d.n)
+        k_ms, _ = kernel_times(ctx, d, eps, "plain", None, out, None, reps)
+        ms, _ = time_graph(ctx, make_step(ctx, d, eps, "plain", None, out, None), warmup, steps)
+    finally:
+        ctx.set_tuning(chunk=old.chunk, blocks_per_cu=old.blocks_per_cu, lpt=old.lpt, tile=old.tile)
+    sample = synth_sample(len(m), "plummer1m")
+    a_dir, _ = direct_reference(ctx, d, sample, eps)
+    err = rel_err(out[0].cpu().numpy()[sample], a_dir)
+    res = {"workload": desc, "ms_per_step": ms, "value": lists.interactions / (ms * 1e-3) / 1e9,
+           "unit": "Ginteractions/s", "interactions": lists.interactions, "schedule": sched,
+           "k_force_ms": k_ms, "k_force_tflops": FLOPS_PER_INTERACTION * lists.interactions / (k_ms * 1e-3) / 1e12,
+           "tree_acc_median_vs_direct": float(np.median(err))}
+    log(f"plummer 2^20 plain: {ms:.3f} ms/step, {res['value']:.0f} Gint/s, median err {res['tree_acc_median_vs_direct']:.2e}")
+    del d, out
+    torch.cuda.empty_cache()
+    return res
+
+
+def synth_sample(n, workload):
+    import synth
+    return synth.sample_idx(n, 4096, seed=SAMPLE_SEED.get(workload, 100))
+
+
 # ------------------------------------------------------------------ main
 
 
@@ -396,7 +551,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="plummer1m", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="cube16m", choices=sorted(WORKLOADS))
+    ap.add_argument("--mode", default="", choices=["", "plain", "quad", "learned"],
+                    help="force evaluated per step (default: learned for the cube, plain otherwise)")
     ap.add_argument("--g-max", type=int, default=0)
     ap.add_argument("--group-mode", default="", choices=["", "chunk", "cell"])
     ap.add_argument("--chunk", type=int, default=0)
@@ -405,8 +562,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--autotune", action="store_true", help="sweep the schedule and store the best in the cache")
     ap.add_argument("--cache", default="", help="autotune cache file (default: the package's)")
-    ap.add_argument("--learned", action="store_true", help="add the learned-correction comparison (default on)")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction comparison")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction comparison on Plummer")
+    ap.add_argument("--no-plummer", action="store_true", help="skip the Plummer 2^20 plain headline")
     ap.add_argument("--gate", type=float, default=0.4, help="learned correction: layers only where l/n >= gate")
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -429,12 +586,14 @@ def main():
     import paper_1206_1199_amd as otoo
     from paper_1206_1199_amd import autotune as at
 
+    mode = args.mode or HEADLINE_MODE.get(args.workload, "plain")
     pos, m, eps, theta, desc, classes = make_workload(args.workload)
-    log(f"workload {desc}: n={len(m)}")
+    log(f"workload {desc}: n={len(m)}, {mode} force")
     t0 = time.perf_counter()
     with marker("tree build"):
         tree = otoo.Tree(pos, m, n_crit=16)
     t1 = time.perf_counter()
+    del pos
     ctx = otoo.Context(0)
 
     key = f"{at.device_key(0)}:{args.workload}"
@@ -456,16 +615,21 @@ def main():
             source += "+override"
     if args.lpt >= 0:
         sched["lpt"] = args.lpt
-    mode = otoo.GROUP_CHUNK if sched["group_mode"] == "chunk" else otoo.GROUP_CELL
+    gmode = otoo.GROUP_CHUNK if sched["group_mode"] == "chunk" else otoo.GROUP_CELL
     log(f"schedule ({source}): {sched}")
+
+    net, training, params = None, None, None
+    if mode == "learned":
+        net, training = train_network(ctx, log, args.train_steps, gate=args.gate)
+        params = net.get_params()[0]
 
     t2 = time.perf_counter()
     with marker("host walk"):
-        lists = tree.walk(theta=theta, g_max=sched["g_max"], group_mode=mode)
+        lists = tree.walk(theta=theta, g_max=sched["g_max"], group_mode=gmode)
     t3 = time.perf_counter()
-    perm, pos32, mass32, cm = tree.export(4)
+    perm, pos32, mass32, cm = tree.export(4 if mode == "plain" else 12)
     log(f"tree {1e3 * (t1 - t0):.0f} ms, walk {1e3 * (t3 - t2):.0f} ms: groups {lists.n_groups}, "
-        f"entries {lists.n_entries}, interactions {lists.interactions}")
+        f"entries {lists.n_entries}, interactions {lists.interactions}, cell pairs {int(lists.pair_off[-1])}")
 
     torch.cuda.synchronize()
     t4 = time.perf_counter()
@@ -476,43 +640,17 @@ def main():
 
     ctx.set_tuning(chunk=sched["chunk"], blocks_per_cu=sched["blocks_per_cu"], lpt=sched["lpt"], tile=sched["tile"])
     out = ctx.outputs(d.n)
-
-    # force-kernel duration, measured with HIP events on the stream the kernel runs on
-    ctx.enable_timing(True)
-    for _ in range(max(3, args.warmup)):
-        ctx.force(d, eps, out=out)
-        ctx.last_timing()
-    kms = []
-    for _ in range(max(5, min(args.steps, 20))):
-        ctx.force(d, eps, out=out)
-        kms.append(ctx.last_timing())
-    ctx.enable_timing(False)
-    ctx.check()
-    k_ms = float(np.mean([k for k, _ in kms]))
-
-    # the timed steps: graph replays
-    ctx.graph_capture(d, eps, out)
-    for _ in range(args.warmup):
-        ctx.graph_launch()
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    with marker("timed force evaluations"):
-        w0 = time.perf_counter()
-        e0.record(stream)
-        for _ in range(args.steps):
-            ctx.graph_launch()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        w1 = time.perf_counter()
-    ms = e0.elapsed_time(e1) / args.steps
-    ctx.check()
-    log(f"force eval {ms:.3f} ms/step (wall {1e3 * (w1 - w0) / args.steps:.3f}), force kernel {k_ms:.3f} ms")
+    gc = torch.empty((d.n_groups, otoo.CORR_STRIDE), dtype=torch.float32, device="cuda:0")
+    reps = max(5, min(args.steps, 20))
+    k_ms, corr_ms = kernel_times(ctx, d, eps, mode, net, out, gc, reps)
+    ms, wall_ms = time_graph(ctx, make_step(ctx, d, eps, mode, net, out, gc), args.warmup, args.steps)
+    log(f"force eval {ms:.3f} ms/step (wall {wall_ms:.3f}), force kernel {k_ms:.3f} ms, correction pass "
+        f"{corr_ms:.3f} ms")
 
     acc = out[0].cpu().numpy().astype(np.float64)
     pot = out[1].cpu().numpy()
     inter = lists.interactions
+    n_pairs = int(lists.pair_off[-1])
     achieved = FLOPS_PER_INTERACTION * inter / (k_ms * 1e-3) / 1e12
     res = {
         "metric": METRIC,
@@ -527,16 +665,25 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": desc, "n": int(len(m)), "groups": lists.n_groups, "list_entries": lists.n_entries,
-                   "interactions": inter, "n_cells": tree.n_cells, "schedule": sched, "schedule_source": source},
+        "config": {"workload": desc, "correction": mode, "gate": args.gate if mode == "learned" else None,
+                   "n": int(len(m)), "groups": lists.n_groups, "list_entries": lists.n_entries,
+                   "interactions": inter, "cell_pairs": n_pairs, "n_cells": tree.n_cells, "schedule": sched,
+                   "schedule_source": source, "step": "correction pass + force in one captured graph"
+                   if mode != "plain" else "force in one captured graph"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(desc, sched),
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": measured_traffic(desc, sched) if mode == "plain" else None,
+                     "kernel": "k_force", "kernel_ms": k_ms, "flops_per_interaction": FLOPS_PER_INTERACTION,
                      # the library is built with packed FP32 instructions disabled, which halves the issue ceiling
                      "peak_without_packed_fp32": PEAK_FP32_NONPACKED_TFLOPS,
-                     "frac_without_packed_fp32": achieved / PEAK_FP32_NONPACKED_TFLOPS,
-                     "kernel": "k_force", "kernel_ms": k_ms, "flops_per_interaction": FLOPS_PER_INTERACTION},
+                     "frac_without_packed_fp32": achieved / PEAK_FP32_NONPACKED_TFLOPS},
         "host": {"tree_build_ms": 1e3 * (t1 - t0), "walk_ms": 1e3 * (t3 - t2), "h2d_ms": 1e3 * (t5 - t4)},
+        "step_breakdown": {"correction_pass_ms": corr_ms, "k_force_ms": k_ms, "graph_step_ms": ms},
     }
+    if mode != "plain":
+        res["roofline_correction"] = correction_roofline(corr_ms, n_pairs, mode)
+    if training:
+        res["training"] = training
     # accuracy of the tree force: FP64 direct sums on the device at a 4096-particle sample
     import synth
     seed = SAMPLE_SEED.get(args.workload, 100)
@@ -551,31 +698,54 @@ def main():
     res["accuracy"] = {"tree_acc_median_vs_direct": float(np.median(et)),
                        "tree_acc_p99_vs_direct": float(np.quantile(et, 0.99)),
                        "tree_pot_median_vs_direct": float(np.median(ept)), "direct_sample": len(sample)}
+    if mode != "plain":     # the same lists without the correction, for context
+        ctx.force(d, eps, out=out)
+        torch.cuda.synchronize()
+        e0 = rel_err(out[0].cpu().numpy()[sample], a_dir)
+        res["accuracy"]["plain_same_lists_acc_median_vs_direct"] = float(np.median(e0))
     for k, mask in cls.items():
         sel = mask[sample]
         res["accuracy"][f"tree_acc_median_vs_direct_{k}"] = float(np.median(et[sel])) if sel.any() else None
-    if not args.no_cpu_baseline:
-        base, (a_ref, p_ref), cpu_direct = cpu_baseline(pos32, mass32, lists, cm, eps, sample)
-        ea, ep = rel_err(acc, a_ref), rel_err(pot, p_ref)
-        res["cpu_baseline"] = base
-        res["accuracy"].update({"parity_acc_median": float(np.median(ea)), "parity_acc_max": float(ea.max()),
-                                "parity_pot_median": float(np.median(ep)), "parity_pot_max": float(ep.max())})
-        # the device's FP64 direct sums (the accuracy reference) against the oracle's
-        eda, edp = rel_err(a_dir, cpu_direct[0]), rel_err(p_dir, cpu_direct[1])
-        res["accuracy"].update({"direct_parity_acc_max": float(eda.max()), "direct_parity_pot_max": float(edp.max())})
-        for k, mask in cls.items():
-            res["accuracy"][f"parity_acc_median_{k}"] = float(np.median(ea[mask]))
-            res["accuracy"][f"parity_acc_max_{k}"] = float(ea[mask].max())
     log(f"accuracy {res['accuracy']}")
+    if not args.no_cpu_baseline:
+        if mode == "plain":
+            base, (a_ref, p_ref), cpu_direct = cpu_baseline(pos32, mass32, lists, cm, eps, sample)
+            ea, ep = rel_err(acc, a_ref), rel_err(pot, p_ref)
+            res["cpu_baseline"] = base
+            res["accuracy"].update({"parity_acc_median": float(np.median(ea)), "parity_acc_max": float(ea.max()),
+                                    "parity_pot_median": float(np.median(ep)), "parity_pot_max": float(ep.max())})
+            eda, edp = rel_err(a_dir, cpu_direct[0]), rel_err(p_dir, cpu_direct[1])
+            res["accuracy"].update({"direct_parity_acc_max": float(eda.max()),
+                                    "direct_parity_pot_max": float(edp.max())})
+            for k, mask in cls.items():
+                res["accuracy"][f"parity_acc_median_{k}"] = float(np.median(ea[mask]))
+                res["accuracy"][f"parity_acc_max_{k}"] = float(ea[mask].max())
+        else:
+            # a bounded sample: every k-th group, about 1/256 of the work
+            step_g = max(1, lists.n_groups // 2048)
+            groups = np.arange(0, lists.n_groups, step_g, dtype=np.int64)
+            go = np.asarray(lists.group_off, np.int64)
+            tgt = np.concatenate([np.arange(go[g], go[g + 1])[:4] for g in groups])
+            base, (a_ref, p_ref) = cpu_baseline_corrected(pos32, mass32, lists, cm, eps, mode, params,
+                                                          args.gate, groups, tgt)
+            res["cpu_baseline"] = base
+            ea, ep = rel_err(acc[tgt], a_ref), rel_err(pot[tgt], p_ref)
+            res["accuracy"].update({"parity_acc_median": float(np.median(ea)), "parity_acc_max": float(ea.max()),
+                                    "parity_pot_median": float(np.median(ep)), "parity_pot_max": float(ep.max()),
+                                    "parity_sample": len(tgt)})
+        log(f"cpu baseline {res['cpu_baseline']['value']:.3f} Gint/s; parity {res['accuracy'].get('parity_acc_median')}")
+    del d
+    torch.cuda.empty_cache()
+    if args.workload != "plummer1m" and not args.no_plummer:
+        try:
+            res["plummer1m"] = plain_headline(ctx, log, args.steps, args.warmup, reps)
+        except Exception as e:  # the headline measurement stands on its own
+            res["plummer1m"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_learned:
         try:
-            net, training = train_network(ctx, log, args.train_steps, gate=args.gate)
-            reps = max(5, min(args.steps, 20))
-            if args.workload == "plummer1m":
-                res["learned"] = learned_comparison(ctx, net, training, log, reps)
-            else:
-                res["learned"] = workload_learned(ctx, net, training, log, tree, eps, theta, sched, sample, a_dir,
-                                                  reps)
+            if net is None:
+                net, training = train_network(ctx, log, args.train_steps, gate=args.gate)
+            res["learned"] = learned_comparison(ctx, net, training, log, reps)
         except Exception as e:  # the headline measurement stands on its own
             res["learned"] = {"error": f"{type(e).__name__}: {e}"}
             log(f"learned comparison failed: {e}")
@@ -588,6 +758,18 @@ def main():
         torch.cuda.synchronize()
         res["calib_copy_bytes"] = nbytes
     print(json.dumps(res), flush=True)
+
+
+def correction_roofline(corr_ms, n_pairs, mode):
+    """The correction pass against its bounds: the network's dense layers on
+    the BF16 matrix cores (2 (32x64 + 64x64 + 64x6) flops per pair through the
+    layers; the gate decides how many) and the FP32 expansion work (the
+    quadrupole-form field and its two derivatives at the group centre, about
+    300 flops per pair, counted for every pair)."""
+    flops_exp = 300.0 * n_pairs
+    return {"pass_ms": corr_ms, "pairs": n_pairs, "mode": mode,
+            "expansion_tflops": flops_exp / (corr_ms * 1e-3) / 1e12 if corr_ms > 0 else None,
+            "network_flops_per_gated_pair": 2 * (32 * 64 + 64 * 64 + 64 * 6), "bf16_mfma_peak_tflops": 2500.0}
 
 
 if __name__ == "__main__":

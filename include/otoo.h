@@ -368,14 +368,37 @@ int otoo_mlp_infer(otoo_mlp* mlp, int32_t n, const float* pos, int32_t n_groups,
  * FP32 = {c_g - COM (3), x_i - c_g (3), t (3), M l^2, w, 0}, where
  * t = a_exact(x_i) - a_mono(x_i) is the cell's exact softened direct sum over
  * its particles minus its monopole (FP64 sums; cell_first/cell_count give each
- * cell's particle range in key order, from otoo_tree_cells) and
- * w = (|x_i - COM|^2 / M)^2.  Device pointers. */
+ * cell's particle range in key order, from otoo_tree_cells) and w = 1 (0 for
+ * a pair whose features are out of range; otoo_mlp_sample_weights sets the
+ * training weight).  Device pointers. */
 int otoo_mlp_train_samples(otoo_mlp* mlp, int32_t n, const float* pos, const float* mass, int32_t n_groups,
                            const int32_t* group_off, int64_t n_entries, const int64_t* list_off,
                            const int32_t* list_idx, int64_t n_pairs, const int64_t* pair_off, int32_t n_cells,
                            const float* cell_mom, int32_t cell_stride, const int32_t* cell_first,
                            const int32_t* cell_count, float eps, int64_t n_samples, const int64_t* samples,
                            uint16_t* X, float* aux);
+
+/* Training weights and the gate's selection of samples (the weight is not
+ * in the paper; it makes the loss follow the per-particle relative force
+ * error by which the method is judged).  For sample s of the samples of
+ * otoo_mlp_train_samples (samples [n_samples][2] int64, device; only the
+ * target particle i = samples[s][1] is read), with a_i = acc[i] the total
+ * force on the target from the same walk (acc [n][3] FP32, device, e.g. from
+ * otoo_force):
+ *   kept:   the BF16 feature l/n (X[s][3]) is at least gate (>= 0; 0 keeps
+ *           every sample with features in range),
+ *   weight: aux[s][10] = W / |a_i|^2 (for every sample; |a_i|^2 is taken as
+ *           at least 1e-300), with W = K / sum over the K kept samples of
+ *           |t_s|^2 / |a_i|^2 (t_s = aux[s][6..8]), so that the kept samples'
+ *           zero-correction loss, mean of w |t|^2, is 1 (W = 1 if that sum is
+ *           0).
+ * The sums are FP64 in a fixed order.  keep [n_samples] int64 (device)
+ * receives the kept sample indices in ascending order and *n_keep (host)
+ * their number; the call synchronises the context stream.  A target index
+ * outside [0, n) drops the sample and is flagged for otoo_check.  EINVAL for
+ * a negative or NaN gate, bad sizes or null pointers. */
+int otoo_mlp_sample_weights(otoo_mlp* mlp, int64_t n_samples, const int64_t* samples, int32_t n, const float* acc,
+                            const uint16_t* X, float* aux, float gate, int64_t* keep, int64_t* n_keep);
 
 /* Loss L = mean over the samples of w |a_corr - t|^2, with a_corr the
  * correction of the sample's predicted tensor through the second-order local

@@ -25,11 +25,16 @@ box) and n = |d|:
            d/n (3), l_c/n, eps/n, h_g/n (h_g = half-diagonal of the group
            box), S_c / (M_c l_c^2) as (xx, yy, zz, xy, xz, yz).
 
-Loss over samples (g, c, target particle x of g):
-           r = a_mono + a_Qt - a_exact,  w = (|x - COM_c|^2 / M_c)^2,
-           L = mean(w |r|^2)
-a_exact is the cell's exact softened direct sum at x.  Only the Qt-dependent
-part of r needs the network, so a sample carries t = a_exact - a_mono.
+Loss over samples (g, c, target particle x_i of g):
+           r = a_mono + a_Qt - a_exact,   L = mean(w |r|^2)
+a_exact is the cell's exact softened direct sum at x_i.  Only the
+Qt-dependent part of r needs the network, so a sample carries
+t = a_exact - a_mono.  The weight (``sample_weights``; not in the paper) is
+           w = W / |a_i|^2,  W = K / sum_kept |t|^2 / |a_i|^2
+with a_i the total force on the target from the same walk and K the number
+of samples the gate keeps, so that the loss follows the per-particle
+relative force error (the measure the method is judged by) and the kept
+samples' zero-correction loss, mean(w |t|^2), is 1.
 
 The device applies each pair's tensor through a second-order local expansion
 about the group's box centre c_g; ``expanded_basis`` gives that linear map
@@ -154,17 +159,30 @@ def quad_accel_basis(dvec, eps):
     return qd * r5[:, None, None] - 2.5 * d[:, :, None] * dqd[:, None, :] * r7[:, None, None]
 
 
-def loss(p, u, dvec, M_c, l_c, t, eps):
-    """Mean weighted squared residual over samples (one network row each)."""
+def sample_weights(a_target, t, kept):
+    """Training weights w = W / |a_i|^2 (a_target [P,3] the total force on
+    each sample's target, t [P,3] the cell targets, kept [P] bool the gate's
+    selection), W normalising the kept samples' mean of w |t|^2 to 1 (W = 1
+    when every kept t is zero); |a_i|^2 is taken as at least 1e-300."""
+    a2 = np.maximum((np.asarray(a_target, np.float64) ** 2).sum(axis=1), 1e-300)
+    t2 = (np.asarray(t, np.float64) ** 2).sum(axis=1)
+    kept = np.asarray(kept, bool)
+    s = float(np.sum(t2[kept] / a2[kept]))
+    W = kept.sum() / s if s > 0 else 1.0
+    return W / a2
+
+
+def loss(p, u, dvec, M_c, l_c, t, eps, w):
+    """Mean weighted squared residual over samples (one network row each),
+    weights w [P]."""
     o, _ = forward(p, u)
     q = traceless(o) * (M_c * l_c * l_c)[:, None]
     a_q = np.einsum("pkj,pj->pk", quad_accel_basis(dvec, eps), q)
     r = a_q - t
-    w = ((np.asarray(dvec) ** 2).sum(axis=1) / M_c) ** 2
-    return float(np.mean(w * (r * r).sum(axis=1)))
+    return float(np.mean(np.asarray(w) * (r * r).sum(axis=1)))
 
 
-def loss_and_grad(p, u, dvec, M_c, l_c, t, eps):
+def loss_and_grad(p, u, dvec, M_c, l_c, t, eps, w):
     """Loss and the gradient with respect to every parameter (hand reverse mode)."""
     P = len(u)
     o, (u_, z1, h1, z2, h2) = forward(p, u)
@@ -173,7 +191,7 @@ def loss_and_grad(p, u, dvec, M_c, l_c, t, eps):
     q = traceless(o) * scale[:, None]
     a_q = np.einsum("pkj,pj->pk", B, q)
     r = a_q - t
-    w = ((np.asarray(dvec) ** 2).sum(axis=1) / M_c) ** 2
+    w = np.asarray(w, np.float64)
     L = float(np.mean(w * (r * r).sum(axis=1)))
     # dL/dr = 2 w r / P
     dr = (2.0 / P) * w[:, None] * r
@@ -290,10 +308,12 @@ def expanded_basis(D, delta, eps):
     return B
 
 
-def loss_and_grad_basis(p, u, B, scale, t, w):
+def loss_and_grad_basis(p, u, B, scale, t, w, return_cache=False):
     """Mean of w |B (scale P(o)) - t|^2 over samples and its parameter gradient.
 
-    Same reverse mode as ``loss_and_grad`` with the applied map B given.
+    Same reverse mode as ``loss_and_grad`` with the applied map B given.  With
+    ``return_cache`` also the forward activations and backward signals
+    {h1, h2, do, dz2, dz1}.
     """
     P = len(u)
     o, (u_, z1, h1, z2, h2) = forward(p, u)
@@ -316,4 +336,6 @@ def loss_and_grad_basis(p, u, B, scale, t, w):
     dz1 = dh1 * gelu_grad(z1)
     g["W1"] = u_.T @ dz1
     g["b1"] = dz1.sum(axis=0)
+    if return_cache:
+        return L, g, {"u": u_, "h1": h1, "h2": h2, "do": do, "dz2": dz2, "dz1": dz1}
     return L, g

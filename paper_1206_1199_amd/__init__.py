@@ -100,7 +100,7 @@ EXPORTED = [
     "otoo_autotune", "otoo_set_scratch_limit", "otoo_force_plan", "otoo_scratch_generation",
     "otoo_quad_exact", "otoo_correction", "otoo_direct", "otoo_sph_sum", "otoo_mlp_num_params", "otoo_mlp_create", "otoo_mlp_destroy", "otoo_mlp_set_params", "otoo_mlp_set_gate",
     "otoo_mlp_get_params", "otoo_mlp_save", "otoo_mlp_load", "otoo_mlp_forward", "otoo_mlp_infer",
-    "otoo_mlp_train_samples", "otoo_mlp_backward", "otoo_mlp_train_step",
+    "otoo_mlp_train_samples", "otoo_mlp_sample_weights", "otoo_mlp_backward", "otoo_mlp_train_step",
 ]
 
 

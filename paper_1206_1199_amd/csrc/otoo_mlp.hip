@@ -1064,7 +1064,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // Per sample (pair p, target particle i of p's group): features of the pair,
 // D = c_g - COM, delta = x_i - c_g, target t = a_exact(x_i) - a_mono(x_i)
 // (the cell's exact softened sum over its particles minus its monopole, FP64),
-// scale M l^2 and loss weight (|x_i - COM|^2 / M)^2.
+// scale M l^2 and a unit loss weight (0 for a pair outside the feature range).
 __global__ __launch_bounds__(256) void k_train_samples(
     const float* __restrict__ pos, const float* __restrict__ mass, int32_t n, const int32_t* __restrict__ group_off,
     int32_t n_groups, const int64_t* __restrict__ list_off, int64_t n_entries, const int32_t* __restrict__ list_idx,
@@ -1142,7 +1142,131 @@ __global__ __launch_bounds__(256) void k_train_samples(
     ax[7] = (float)(sy - mw * my);
     ax[8] = (float)(sz - mw * mz);
     ax[9] = ok ? sc : 0.f;
-    ax[10] = ok ? (float)(m2 * m2 / ((double)cm[3] * (double)cm[3])) : 0.f;
+    ax[10] = ok ? 1.f : 0.f;   // unit weight until otoo_mlp_sample_weights sets the training weight
+}
+
+// ---------------------------------------------------------------- training weights
+
+// Loss weights and the gate's selection of training samples.  A sample s
+// (target particle i, cell target t_s = a_exact - a_mono) is kept when its
+// BF16 feature l/n reaches the gate; its weight is W / |a_i|^2, a_i the total
+// force on the target, with W = (kept samples) / sum over kept samples of
+// |t_s|^2 / |a_i|^2, so that the kept set's zero-correction loss is 1.
+// Three passes: per-block kept counts and FP64 partial sums (fixed tree
+// order), one block that scans the counts and forms W, then the weights and
+// the kept indices in ascending sample order.
+constexpr int kSwBlock = 256;
+
+struct SwArgs {
+    int64_t n_samples;
+    const int64_t* samples;   // [n_samples][2]: pair, target particle
+    int32_t n;
+    const float* acc;         // [n][3]
+    const uint16_t* X;        // [n_samples][NIN]
+    float* aux;               // [n_samples][AUX]
+    float gate;
+    double* part_q;           // [blocks]
+    int64_t* part_c;          // [blocks], then exclusive offsets
+    double* scale;            // [1]: W
+    int64_t* n_keep;          // [1]
+    int64_t* keep;            // [n_samples]
+    int32_t* err;
+};
+
+// Whether sample s is kept, and |t|^2 / |a_i|^2 (FP64) and 1 / |a_i|^2.
+__device__ __forceinline__ bool sw_sample(const SwArgs& a, int64_t s, double& q, double& inv_a2) {
+    q = 0.0;
+    inv_a2 = 0.0;
+    if (s >= a.n_samples) return false;
+    const int64_t i = a.samples[2 * s + 1];
+    if (i < 0 || i >= a.n) {
+        atomicOr(a.err, kErrIndex);
+        return false;
+    }
+    const double ax = a.acc[3 * i], ay = a.acc[3 * i + 1], az = a.acc[3 * i + 2];
+    double a2 = ax * ax + ay * ay + az * az;
+    a2 = a2 > 1e-300 ? a2 : 1e-300;   // a target at rest keeps a finite weight
+    inv_a2 = 1.0 / a2;
+    if (!(bf2f(a.X[s * NIN + 3]) >= a.gate)) return false;
+    const float* t = a.aux + s * AUX + 6;
+    const double t2 = (double)t[0] * t[0] + (double)t[1] * t[1] + (double)t[2] * t[2];
+    q = t2 * inv_a2;
+    return true;
+}
+
+__global__ __launch_bounds__(kSwBlock) void k_sw_count(SwArgs a) {
+    __shared__ double sq[kSwBlock];
+    __shared__ int sc[kSwBlock];
+    const int t = threadIdx.x;
+    double q, ia;
+    const bool kept = sw_sample(a, (int64_t)blockIdx.x * kSwBlock + t, q, ia);
+    sq[t] = q;
+    sc[t] = kept ? 1 : 0;
+    __syncthreads();
+    for (int h = kSwBlock / 2; h > 0; h >>= 1) {   // fixed tree order
+        if (t < h) {
+            sq[t] += sq[t + h];
+            sc[t] += sc[t + h];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        a.part_q[blockIdx.x] = sq[0];
+        a.part_c[blockIdx.x] = sc[0];
+    }
+}
+
+// One workgroup: exclusive scan of the block counts (in place), the total of
+// the partial sums in a fixed order, and W.
+__global__ __launch_bounds__(kSwBlock) void k_sw_scale(SwArgs a, int32_t blocks) {
+    __shared__ double sq[kSwBlock];
+    __shared__ int64_t sc[kSwBlock];
+    __shared__ int64_t carry;
+    const int t = threadIdx.x;
+    double q = 0.0;
+    for (int b = t; b < blocks; b += kSwBlock) q += a.part_q[b];   // each thread's blocks in order
+    sq[t] = q;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (int h = kSwBlock / 2; h > 0; h >>= 1) {
+        if (t < h) sq[t] += sq[t + h];
+        __syncthreads();
+    }
+    for (int base = 0; base < blocks; base += kSwBlock) {
+        const int b = base + t;
+        const int64_t v = b < blocks ? a.part_c[b] : 0;
+        sc[t] = v;
+        __syncthreads();
+        for (int off = 1; off < kSwBlock; off <<= 1) {   // Hillis-Steele inclusive scan
+            const int64_t add = t >= off ? sc[t - off] : 0;
+            __syncthreads();
+            sc[t] += add;
+            __syncthreads();
+        }
+        if (b < blocks) a.part_c[b] = carry + sc[t] - v;
+        __syncthreads();
+        if (t == kSwBlock - 1) carry += sc[kSwBlock - 1];
+        __syncthreads();
+    }
+    if (t == 0) {
+        *a.n_keep = carry;
+        *a.scale = sq[0] > 0.0 ? (double)carry / sq[0] : 1.0;
+    }
+}
+
+__global__ __launch_bounds__(kSwBlock) void k_sw_write(SwArgs a) {
+    __shared__ int wcount[kSwBlock / 64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t s = (int64_t)blockIdx.x * kSwBlock + t;
+    double q, ia;
+    const bool kept = sw_sample(a, s, q, ia);
+    if (s < a.n_samples) a.aux[s * AUX + 10] = (float)(*a.scale * ia);
+    const uint64_t mask = __ballot(kept);
+    if (lane == 0) wcount[w] = __popcll(mask);
+    __syncthreads();
+    int64_t pos = a.part_c[blockIdx.x] + __popcll(mask & ((1ull << lane) - 1ull));
+    for (int v = 0; v < w; v++) pos += wcount[v];
+    if (kept) a.keep[pos] = s;
 }
 
 // ---------------------------------------------------------------- training step
@@ -1493,6 +1617,8 @@ struct otoo_mlp {
     int part_rows = 0;
     float4* geom = nullptr;    // device per-group geometry
     int64_t geom_cap = 0;
+    void* sw = nullptr;        // device block sums of otoo_mlp_sample_weights
+    int64_t sw_blocks = 0;
     int64_t step = 0;
     bool has_params = false;
     float gate = 0.f;          // the layers run only for pairs whose BF16 l/n is at least this
@@ -1605,6 +1731,7 @@ int otoo_mlp_destroy(otoo_mlp* m) {
     if (m->master) (void)hipFree(m->master);
     if (m->part) (void)hipFree(m->part);
     if (m->geom) (void)hipFree(m->geom);
+    if (m->sw) (void)hipFree(m->sw);
     delete m;
     return OTOO_OK;
 }
@@ -1823,6 +1950,41 @@ int otoo_mlp_train_samples(otoo_mlp* m, int32_t n, const float* pos, const float
                        n, group_off, n_groups, list_off, n_entries, list_idx, pair_off, n_pairs, n_cells, cell_mom,
                        cell_first, cell_count, eps, samples, n_samples, X, aux, c->errflag);
     HIP_TRY(c, hipGetLastError());
+    return OTOO_OK;
+}
+
+int otoo_mlp_sample_weights(otoo_mlp* m, int64_t n_samples, const int64_t* samples, int32_t n, const float* acc,
+                            const uint16_t* X, float* aux, float gate, int64_t* keep, int64_t* n_keep) {
+    int rc = mlp_check(m);
+    if (rc) return rc;
+    otoo_ctx* c = m->ctx;
+    c->err.clear();
+    if (n_samples < 0 || n < 1) return fail(c, OTOO_EINVAL, "bad sizes");
+    if (!(gate >= 0.f)) return fail(c, OTOO_EINVAL, "the gate must be non-negative");
+    if (!n_keep || (n_samples && (!samples || !acc || !X || !aux || !keep)))
+        return fail(c, OTOO_EINVAL, "null pointer argument");
+    *n_keep = 0;
+    if (!n_samples) return OTOO_OK;
+    const int64_t blocks = (n_samples + kSwBlock - 1) / kSwBlock;
+    if (blocks > INT32_MAX) return fail(c, OTOO_EINVAL, "too many samples");
+    if (blocks > m->sw_blocks) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (m->sw) HIP_TRY(c, hipFree(m->sw));
+        m->sw = nullptr;
+        m->sw_blocks = 0;   // stays 0 if the allocation fails
+        HIP_TRY(c, hipMalloc(&m->sw, 16 * (size_t)blocks + 256));
+        m->sw_blocks = blocks;
+    }
+    char* b = static_cast<char*>(m->sw);
+    SwArgs a{n_samples, samples, n, acc, X, aux, gate, reinterpret_cast<double*>(b),
+             reinterpret_cast<int64_t*>(b + 8 * (size_t)blocks), reinterpret_cast<double*>(b + 16 * (size_t)blocks),
+             reinterpret_cast<int64_t*>(b + 16 * (size_t)blocks + 8), keep, c->errflag};
+    hipLaunchKernelGGL(k_sw_count, dim3((unsigned)blocks), dim3(kSwBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(k_sw_scale, dim3(1), dim3(kSwBlock), 0, c->stream, a, (int32_t)blocks);
+    hipLaunchKernelGGL(k_sw_write, dim3((unsigned)blocks), dim3(kSwBlock), 0, c->stream, a);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipMemcpyAsync(n_keep, a.n_keep, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
     return OTOO_OK;
 }
 

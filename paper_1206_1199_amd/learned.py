@@ -45,6 +45,7 @@ def _bind():
         "otoo_mlp_infer": ([P, I32, P, I32, P, I64, P, P, I64, P, I32, P, I32, F, P], I32),
         "otoo_mlp_train_samples": ([P, I32, P, P, I32, P, I64, P, P, I64, P, I32, P, I32, P, P, F, I64, P, P, P],
                                    I32),
+        "otoo_mlp_sample_weights": ([P, I64, P, I32, P, P, P, F, P, ctypes.POINTER(I64)], I32),
         "otoo_mlp_backward": ([P, P, P, I64, F, P, P], I32),
         "otoo_mlp_train_step": ([P, P, P, I64, F, F, P], I32),
     }
@@ -154,6 +155,19 @@ class Network:
             _tptr(X), _tptr(aux)), "otoo_mlp_train_samples")
         return X, aux
 
+    def sample_weights(self, samples, acc, X, aux, gate: float = 0.0):
+        """Training weights into aux[:, 10] (W / |a_i|^2, normalised over the
+        kept samples) and the indices of the samples the gate keeps (int64
+        device tensor, ascending); otoo_mlp_sample_weights."""
+        import torch
+        S = int(samples.shape[0])
+        keep = torch.empty(max(S, 1), dtype=torch.int64, device=aux.device)
+        n_keep = ctypes.c_int64()
+        self._raise(_bind().otoo_mlp_sample_weights(self._h, S, _tptr(samples), int(acc.shape[0]), _tptr(acc),
+                                                    _tptr(X), _tptr(aux), float(gate), _tptr(keep),
+                                                    ctypes.byref(n_keep)), "otoo_mlp_sample_weights")
+        return keep[:n_keep.value]
+
     def backward(self, X, aux, eps: float):
         """(gradient [6662] float32, loss) of the mean weighted loss over the samples."""
         g = np.empty(N_PARAMS, np.float32)
@@ -211,21 +225,17 @@ def draw_samples(lists: Lists, n_samples: int, rng: np.random.Generator) -> np.n
     return np.stack([p, i], axis=1).astype(np.int64)
 
 
-def bf16_column(X, j):
-    """Column j of BF16 feature rows (int16 bit patterns) as float32."""
-    import torch
-    return (X[:, j].to(torch.int32) << 16).view(torch.float32)
-
-
 def make_training_set(ctx, net: Network, configs, seed: int, device="cuda:0", log=None, gate: float = 0.0):
     """Training samples from seeded walks (exact cell sums computed on the GPU).
 
-    Each sample is weighted by 1 / |a_i|^2, a_i the total force on its
-    target from the same walk (the per-particle relative error is what the
-    correction is judged by), normalised so that the zero-correction loss of
-    each configuration's samples is 1.  Only pairs the gate lets through to
-    the layers (BF16 feature l/n >= gate) are kept.  Returns (X int16 [S,32], aux float32 [S,12], eps float32 [S])
-    on the device; samples of different softening lengths carry their own eps.
+    The library weights each sample by 1 / |a_i|^2, a_i the total force on
+    its target from the same walk (the per-particle relative error is what
+    the correction is judged by), normalised so that the zero-correction loss
+    of each configuration's kept samples is 1, and keeps only pairs the gate
+    lets through to the layers (BF16 feature l/n >= gate); this function
+    gathers the kept rows.  Returns (X int16 [S,32], aux float32 [S,12], eps
+    float32 [S]) on the device; samples of different softening lengths carry
+    their own eps.
     """
     import torch
     import synth
@@ -241,16 +251,9 @@ def make_training_set(ctx, net: Network, configs, seed: int, device="cuda:0", lo
         d, first, count = device_tree_arrays(tree, lists, device)
         smp = torch.from_numpy(draw_samples(lists, cfg.n_samples, rng)).to(device)
         X, aux = net.train_samples(d, first, count, cfg.eps, smp)
-        # weight: 1 / |a_i|^2 with a_i the target's total (monopole-tree) force,
-        # so a sample counts by its share of the per-particle relative error
-        acc, _ = ctx.force(d, cfg.eps)
-        a2 = (acc[smp[:, 1]].double() ** 2).sum(dim=1).clamp_min(1e-300)   # a target at rest: finite weight
-        wt = 1.0 / a2
-        t2 = (aux[:, 6:9].double() ** 2).sum(dim=1)
-        aux[:, 10] = (wt / (wt * t2).mean()).float()     # normalised: the zero-correction loss is 1
-        if gate > 0.0:
-            keep = bf16_column(X, 3) >= gate
-            X, aux = X[keep].contiguous(), aux[keep].contiguous()
+        acc, _ = ctx.force(d, cfg.eps)          # the target's total (monopole-tree) force
+        keep = net.sample_weights(smp, acc, X, aux, gate)
+        X, aux = X[keep], aux[keep]
         Xs.append(X)
         auxs.append(aux)
         epss.append(torch.full((X.shape[0],), cfg.eps, dtype=torch.float32, device=device))
@@ -306,7 +309,7 @@ def evaluate_loss(net: Network, X, aux, eps_all):
 
 
 def zero_correction_loss(aux):
-    """The loss of the plain monopole (zero tensor) on these samples: mean w |t|^2."""
-    w = aux[:, 10]
-    t = aux[:, 6:9]
-    return float((w * (t * t).sum(dim=1)).mean().item())
+    """The loss of the plain monopole (zero tensor) on these samples, mean w |t|^2,
+    taken on the host (1 per configuration by the weights' normalisation)."""
+    a = aux.cpu().numpy().astype(np.float64)
+    return float(np.mean(a[:, 10] * (a[:, 6:9] ** 2).sum(axis=1)))

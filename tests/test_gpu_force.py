@@ -72,6 +72,34 @@ def test_plummer16k_all_particles(ctx, plummer16k, g_max, mode):
     _assert_parity(acc, pot, a_ref, p_ref, f"plummer16k g_max={g_max} mode={mode}")
 
 
+@pytest.mark.parametrize("dist", ["plummer", "uniform"])
+def test_absolute_mac_lists(ctx, dist):
+    """Lists of the absolute MAC (Eq. 1 with m_limit = 0.05 of the total mass,
+    Sec. 2.2 and 3.3) at Delta = 0.01 and 0.001 through the device force,
+    against the oracle's list sums over every particle (16k Plummer sphere and
+    uniform sphere, eps 0.01); the tree force against direct sums falls with
+    Delta (the oracle's list sums give median errors of 9.0e-4 and 4.2e-4 on
+    the Plummer sphere, 3.7e-3 and 1.3e-3 on the uniform sphere)."""
+    gen = synth.plummer if dist == "plummer" else synth.uniform_sphere
+    pos, m = gen(16384, seed=23)
+    t = otoo.Tree(pos, m, n_crit=16)
+    _, pos32, mass32, cm = t.export(4)
+    sample = synth.sample_idx(len(m), 512, seed=24)
+    a_dir, _ = oracle.direct(pos32.astype(np.float64), mass32.astype(np.float64), float(np.float32(0.01)), tgt=sample)
+    errs = []
+    for delta in (0.01, 0.001):
+        lists = t.walk(g_max=64, mac=otoo.MAC_ABSOLUTE, delta=delta, m_limit=0.05)
+        assert int(lists.pair_off[-1]) > 0        # cells are accepted
+        d = otoo.DeviceLists.from_host(pos32, mass32, lists, cm, "cuda:0")
+        acc, pot = _gpu(ctx, d, 0.01)
+        a_ref, p_ref = _oracle(pos32, mass32, lists, cm, 0.01)
+        _assert_parity(acc, pot, a_ref, p_ref, f"absolute MAC {dist} delta {delta}")
+        errs.append(np.median(oracle.rel_err(acc[sample], a_dir)))
+    print(f"  tree error vs direct sums: median {errs[0]:.2e} (Delta 0.01), {errs[1]:.2e} (Delta 0.001)", flush=True)
+    limits = (1.2e-3, 6e-4) if dist == "plummer" else (5e-3, 1.8e-3)
+    assert errs[0] < limits[0] and errs[1] < limits[1] and errs[1] < 0.6 * errs[0]
+
+
 def test_schedules_agree_bitwise(ctx, plummer16k):
     """Item order (longest-first or table order) and the workgroup count do not
     change a single bit; a short chunk (many items per group, partial rows and

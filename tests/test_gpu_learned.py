@@ -1,10 +1,14 @@
-"""GPU parity of the learned cell correction against the FP64 network oracle.
+"""GPU parity of the learned cell correction against the FP64 oracle.
 
 The device runs the network with BF16 operands (weights, features and hidden
 activations rounded to BF16) and FP32 accumulation; the oracle runs in FP64 at
-the same BF16-rounded weights and inputs, so the remaining difference is the
-rounding of hidden activations and of the FP32 sums: relative L2 <= 2e-2 per
-tensor.  Training targets are FP64 sums on both sides (1e-5 of |t|).
+the same BF16-rounded weights and at its own BF16-rounded features.  Every
+network quantity is compared entry by entry against BF16_TOL (five BF16 unit
+roundoffs) times that entry's absolute-value scale, the sum of the absolute
+terms it is formed from, so that one wrong row, column or output cannot hide
+in a norm.  Training samples (cell targets, geometry, scale and weight) are
+computed by the oracle from the positions and lists alone; nothing the device
+computes enters the oracle's side.
 """
 import numpy as np
 import pytest
@@ -13,23 +17,54 @@ import oracle
 import synth
 import paper_1206_1199_amd as otoo
 from oracle import mlp as omlp
+from corr_parity import BF16_TOL, abs_scale_outputs, compare, pair_tensors
+from learned_helpers import group_geometry, pair_cells, sample_groups
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 learned = pytest.importorskip("paper_1206_1199_amd.learned")
 
 EPS = 0.01
-
-
-def rel_l2(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+FEAT_LIMIT = 8.0     # a pair with a feature beyond this (or non-finite) gets no correction
 
 
 def bf16_bits_to_f64(X):
     b = X.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
     return b.view(np.float32).astype(np.float64)
+
+
+def oracle_samples(pos32, mass32, lists, cm, eps, samples):
+    """The oracle's view of training samples (pair p, target i): features
+    (FP64 and BF16-rounded, zero for a pair out of the feature range), D =
+    c_g - COM, delta = x_i - c_g, the cell target t = a_exact - a_mono at x_i
+    (FP64 sums over the cell's particles), the scale M l^2 and the target's
+    total force from the walk (for the weights)."""
+    n = len(mass32)
+    p64, m64 = pos32.astype(np.float64), mass32.astype(np.float64)
+    cmd = cm.astype(np.float64)
+    e = float(np.float32(eps))
+    p, i = samples[:, 0], samples[:, 1]
+    g, c = pair_cells(lists, n, p)
+    centre, hdiag = group_geometry(p64, lists.group_off)
+    com, M, l = cmd[c, :3], cmd[c, 3], cmd[c, 4]
+    u = omlp.features(com - centre[g], l, e, hdiag[g], cmd[c, 5:11], M)
+    valid = np.all(np.isfinite(u[:, :12]) & (np.abs(u[:, :12]) <= FEAT_LIMIT), axis=1) & (M * l * l > 0)
+    u[~valid] = 0.0
+    return dict(g=g, c=c, u=u, ub=omlp.to_bf16(u), valid=valid, D=centre[g] - com, delta=p64[i] - centre[g],
+                scale=np.where(valid, M * l * l, 0.0), x=p64[i], com=com, M=M, i=i)
+
+
+def cell_targets(o, pos32, mass32, cell_first, cell_count, eps):
+    """t = a_exact - a_mono at each sample's target (FP64)."""
+    p64, m64 = pos32.astype(np.float64), mass32.astype(np.float64)
+    e = float(np.float32(eps))
+    first, count = cell_first[o["c"]], cell_count[o["c"]]
+    off = np.concatenate([[0], np.cumsum(count)]).astype(np.int64)
+    idx = np.concatenate([np.arange(f, f + k) for f, k in zip(first, count)]).astype(np.int64)
+    a_ex, _ = oracle.point_field(o["x"], off, idx, p64, m64, e)
+    S = len(o["x"])
+    a_mo, _ = oracle.point_field(o["x"], np.arange(S + 1), np.arange(S), o["com"], o["M"], e)
+    return a_ex - a_mo, np.linalg.norm(a_mo, axis=1)
 
 
 @pytest.fixture(scope="module")
@@ -46,109 +81,140 @@ def env():
     samples = learned.draw_samples(lists, 3000, rng)
     params = learned.init_params(7)
     net.set_params(params)
-    X, aux = net.train_samples(d, first, count, EPS, torch.from_numpy(samples).cuda())
+    smp = torch.from_numpy(samples).cuda()
+    X, aux = net.train_samples(d, first, count, EPS, smp)
+    aux_unit = aux.clone()
+    acc, _ = ctx.force(d, EPS)
     torch.cuda.synchronize()
     ctx.check()
+    o = oracle_samples(pos32, mass32, lists, cm, EPS, samples)
+    o["t"], o["mono"] = cell_targets(o, pos32, mass32, cells["first"], cells["count"], EPS)
+    a_tot, _ = oracle.list_force(pos32.astype(np.float64), mass32.astype(np.float64), lists.group_off,
+                                 lists.list_off, lists.list_idx, cm[:, :3].astype(np.float64),
+                                 cm[:, 3].astype(np.float64), float(np.float32(EPS)), tgt=o["i"])
+    o["a_tot"] = a_tot
     return dict(ctx=ctx, net=net, tree=tree, lists=lists, d=d, pos32=pos32, mass32=mass32, cm=cm, cells=cells,
-                samples=samples, params=params, X=X, aux=aux)
+                samples=samples, smp=smp, params=params, X=X, aux=aux, aux_unit=aux_unit, acc=acc, o=o)
 
 
-def _pair_cell(lists, n, p):
-    g = np.searchsorted(lists.pair_off, p, side="right") - 1
-    k = p - lists.pair_off[g]
-    return g, lists.list_idx[lists.list_off[g] + k] - n
-
-
-def _group_geometry(pos32, lists, g):
-    pts = pos32[lists.group_off[g]:lists.group_off[g + 1]].astype(np.float64)
-    lo, hi = pts.min(0), pts.max(0)
-    return 0.5 * (lo + hi), 0.5 * np.linalg.norm(hi - lo)
+def weighted(env, gate):
+    """Device aux with the library's weights for `gate`, and its kept indices."""
+    aux = env["aux_unit"].clone()
+    keep = env["net"].sample_weights(env["smp"], env["acc"], env["X"], aux, gate)
+    torch.cuda.synchronize()
+    env["ctx"].check()
+    return aux, keep
 
 
 def test_train_samples_match_exact_cell_sums(env):
-    lists, cm, pos32, mass32 = env["lists"], env["cm"], env["pos32"], env["mass32"]
-    n = len(mass32)
-    aux = env["aux"].cpu().numpy().astype(np.float64)
+    o = env["o"]
+    aux = env["aux_unit"].cpu().numpy().astype(np.float64)
     X = bf16_bits_to_f64(env["X"])
-    first, count = env["cells"]["first"], env["cells"]["count"]
-    sel = np.arange(0, len(env["samples"]), 7)
-    t_ref, D_ref, del_ref, feat_ref, mono_ref = [], [], [], [], []
-    for s in sel:
-        p, i = env["samples"][s]
-        g, c = _pair_cell(lists, n, p)
-        cg, h = _group_geometry(pos32, lists, g)
-        ids = np.arange(first[c], first[c] + count[c])
-        x = pos32[i].astype(np.float64)
-        a_ex, _ = oracle.point_field(x[None], [0, len(ids)], ids, pos32.astype(np.float64),
-                                     mass32.astype(np.float64), float(np.float32(EPS)))
-        com = cm[c, :3].astype(np.float64)
-        a_mo, _ = oracle.point_field(x[None], [0, 1], [0], com[None], cm[c, 3:4].astype(np.float64),
-                                     float(np.float32(EPS)))
-        t_ref.append(a_ex[0] - a_mo[0])
-        mono_ref.append(np.linalg.norm(a_mo[0]))
-        D_ref.append(cg - com)
-        del_ref.append(x - cg)
-        feat_ref.append(omlp.features((com - cg)[None], cm[c, 4:5].astype(np.float64), float(np.float32(EPS)),
-                                      np.array([h]), cm[c, 5:11][None].astype(np.float64),
-                                      cm[c, 3:4].astype(np.float64))[0])
-    t_ref, D_ref, del_ref, feat_ref, mono_ref = map(np.array, (t_ref, D_ref, del_ref, feat_ref, mono_ref))
+    v = o["valid"]
     # t is a small difference of FP64 sums stored in FP32: within FP32 rounding
     # of t plus FP64 rounding of the monopole-sized sums (a one-particle cell
     # has t = 0 up to that rounding)
-    dt = np.linalg.norm(aux[sel, 6:9] - t_ref, axis=1)
-    tn = np.linalg.norm(t_ref, axis=1)
-    assert np.all(dt <= 1e-7 * tn + 1e-12 * mono_ref)
-    nz = tn > 1e-9 * mono_ref
+    dt = np.linalg.norm(aux[:, 6:9] - o["t"], axis=1)
+    tn = np.linalg.norm(o["t"], axis=1)
+    assert np.all(dt <= 1e-7 * tn + 1e-12 * o["mono"])
+    nz = tn > 1e-9 * o["mono"]
     err_t = dt[nz] / tn[nz]
-    print(f"targets: median rel err {np.median(err_t):.2e}, max {err_t.max():.2e}, one-particle {np.sum(~nz)}",
-          flush=True)
+    print(f"targets: median rel err {np.median(err_t):.2e}, max {err_t.max():.2e}, one-particle {np.sum(~nz)}, "
+          f"out of feature range {np.sum(~v)}", flush=True)
     assert np.median(err_t) <= 1e-6
-    scale = np.abs(D_ref).max()
-    np.testing.assert_allclose(aux[sel, 0:3], D_ref, atol=1e-6 * scale)
-    np.testing.assert_allclose(aux[sel, 3:6], del_ref, atol=1e-6 * scale)
+    scale = np.abs(o["D"]).max()
+    np.testing.assert_allclose(aux[:, 0:3], o["D"], atol=1e-6 * scale)
+    np.testing.assert_allclose(aux[:, 3:6], o["delta"], atol=1e-6 * scale)
+    np.testing.assert_allclose(aux[:, 9], o["scale"], rtol=1e-6)
+    np.testing.assert_array_equal(aux[:, 10], v.astype(np.float64))     # unit weight until weighted
     # features: the device rounds its FP32 features to BF16
-    np.testing.assert_allclose(X[sel, :12], feat_ref[:, :12], rtol=2 ** -7, atol=1e-6)
+    np.testing.assert_allclose(X[:, :12], o["u"][:, :12], rtol=2 ** -7, atol=1e-6)
     assert np.all(X[:, 12:] == 0)
 
 
-def test_forward_matches_oracle(env):
-    out = env["net"].forward(env["X"]).cpu().numpy()
-    p = omlp.bf16_params(omlp.flat_to_params(env["params"]))
-    o_ref, _ = omlp.forward(p, bf16_bits_to_f64(env["X"]))
-    e = rel_l2(out, o_ref)
-    print(f"forward rel L2 {e:.2e}", flush=True)
-    assert e <= 2e-2
+@pytest.mark.parametrize("gate", [0.0, 0.4])
+def test_sample_weights_match_oracle(env, gate):
+    """The library's training weights W / |a_i|^2 and its gate selection
+    against the oracle's (total force from the oracle's list sums, targets
+    from its exact cell sums, the gate on its own BF16 features).  Where the
+    FP64 feature l/n lies within a BF16 rounding step of the gate, the two
+    sides may round to different sides of it; elsewhere the kept sets are
+    equal."""
+    o = env["o"]
+    aux, keep = weighted(env, gate)
+    aux = aux.cpu().numpy().astype(np.float64)
+    keep = keep.cpu().numpy()
+    kept_ref = o["ub"][:, 3] >= gate
+    ambiguous = np.abs(o["u"][:, 3] - gate) <= 2 ** -7 * max(gate, 1e-30)
+    kept_dev = np.zeros(len(kept_ref), bool)
+    kept_dev[keep] = True
+    assert np.all(np.diff(keep) > 0)
+    assert np.array_equal(kept_dev[~ambiguous], kept_ref[~ambiguous])
+    w_ref = omlp.sample_weights(o["a_tot"], o["t"], kept_dev)
+    rel = np.abs(aux[:, 10] - w_ref) / w_ref
+    print(f"gate {gate}: kept {kept_dev.sum()} of {len(kept_dev)} (ambiguous {ambiguous.sum()}); weight rel err "
+          f"median {np.median(rel):.2e} max {rel.max():.2e}", flush=True)
+    assert np.median(rel) <= 1e-6 and rel.max() <= 5e-4
+    zc = np.mean((aux[:, 10] * (aux[:, 6:9] ** 2).sum(axis=1))[kept_dev])
+    assert zc == pytest.approx(1.0, rel=1e-5)
 
 
-def _oracle_loss_grad(env, params):
-    aux = env["aux"].cpu().numpy().astype(np.float64)
-    B = omlp.expanded_basis(aux[:, 0:3], aux[:, 3:6], float(np.float32(EPS)))
+def _net_ref(params, u):
     p = omlp.bf16_params(omlp.flat_to_params(params))
-    return omlp.loss_and_grad_basis(p, bf16_bits_to_f64(env["X"]), B, aux[:, 9], aux[:, 6:9], aux[:, 10])
+    o, cache = omlp.forward(p, u)
+    return p, o, cache
+
+
+def test_forward_matches_oracle(env):
+    out = env["net"].forward(env["X"]).cpu().numpy().astype(np.float64)
+    u = bf16_bits_to_f64(env["X"])      # the same BF16 features on both sides
+    p, o_ref, cache = _net_ref(env["params"], u)
+    tol = BF16_TOL * abs_scale_outputs(p, u, cache)
+    r = np.abs(out - o_ref) / tol
+    print(f"forward: largest deviation {r.max():.3f} of the per-entry tolerance", flush=True)
+    assert np.all(r <= 1.0)
+
+
+def _grad_scales(p, cache):
+    """Absolute-value scale of every gradient entry: the sums over samples of
+    the absolute products that form it."""
+    u, h1, h2, do, dz2, dz1 = (cache[k] for k in ("u", "h1", "h2", "do", "dz2", "dz1"))
+    return {"W3": np.abs(h2).T @ np.abs(do), "b3": np.abs(do).sum(axis=0), "W2": np.abs(h1).T @ np.abs(dz2),
+            "b2": np.abs(dz2).sum(axis=0), "W1": np.abs(u).T @ np.abs(dz1), "b1": np.abs(dz1).sum(axis=0)}
 
 
 def test_backward_matches_oracle(env):
-    net = env["net"]
+    """Loss and gradient on the device (its own samples and weights) against
+    the oracle's loss and reverse mode on samples the oracle computed itself
+    (geometry, cell targets, scale and weight), entry by entry."""
+    net, o = env["net"], env["o"]
     rng = np.random.default_rng(3)
     params = env["params"] + rng.normal(size=env["params"].shape).astype(np.float32) * 0.05
     net.set_params(params)
-    g, L = net.backward(env["X"], env["aux"], EPS)
-    L_ref, g_ref = _oracle_loss_grad(env, params)
+    aux, _ = weighted(env, 0.0)
+    g, L = net.backward(env["X"], aux, EPS)
+    kept = o["ub"][:, 3] >= 0.0
+    w = omlp.sample_weights(o["a_tot"], o["t"], kept)
+    B = omlp.expanded_basis(o["D"], o["delta"], float(np.float32(EPS)))
+    p = omlp.bf16_params(omlp.flat_to_params(params))
+    L_ref, g_ref, cache = omlp.loss_and_grad_basis(p, o["ub"], B, o["scale"], o["t"], w, return_cache=True)
+    scales = _grad_scales(p, cache)
     gd = omlp.flat_to_params(g)
     print(f"loss {L:.6e} oracle {L_ref:.6e}", flush=True)
     assert L == pytest.approx(L_ref, rel=1e-2)
     for k in g_ref:
-        e = rel_l2(gd[k], g_ref[k])
-        print(f"grad {k}: rel L2 {e:.2e}", flush=True)
-        assert e <= 2e-2, k
+        r = np.abs(gd[k] - g_ref[k]) / (BF16_TOL * scales[k] + 1e-30)
+        print(f"grad {k}: largest deviation {r.max():.3f} of the per-entry tolerance", flush=True)
+        assert np.all(r <= 1.0), k
     net.set_params(env["params"])
 
 
 def test_adam_step_matches_oracle(env):
     net = env["net"]
     net.set_params(env["params"])
-    g, _ = net.backward(env["X"], env["aux"], EPS)
-    net.train_step(env["X"], env["aux"], EPS, 1e-3)
+    aux, _ = weighted(env, 0.0)
+    g, _ = net.backward(env["X"], aux, EPS)
+    net.train_step(env["X"], aux, EPS, 1e-3)
     p1, m1, v1, step = net.get_params()
     assert step == 1
     p0 = omlp.flat_to_params(env["params"].astype(np.float64))
@@ -162,7 +228,8 @@ def test_adam_step_matches_oracle(env):
 
 
 def test_checkpoint_resume_is_exact(env, tmp_path):
-    net, X, aux = env["net"], env["X"], env["aux"]
+    net, X = env["net"], env["X"]
+    aux, _ = weighted(env, 0.0)
     net.set_params(env["params"])
     for _ in range(3):
         net.train_step(X, aux, EPS, 1e-3)
@@ -185,7 +252,9 @@ def test_checkpoint_resume_is_exact(env, tmp_path):
 @pytest.mark.parametrize("gate", [0.0, 0.4])
 def test_infer_matches_oracle(env, gate):
     """Per-pair tensors (skip term plus the layers where the gate lets them
-    run) against the oracle network at the same BF16 features."""
+    run) against the oracle network at its own BF16 features, entry by
+    entry; pairs the gate keeps out carry the textbook quadrupole of the BF16
+    moments alone."""
     net, d, lists, cm, pos32 = env["net"], env["d"], env["lists"], env["cm"], env["pos32"]
     net.set_params(env["params"])
     net.set_gate(gate)
@@ -194,79 +263,92 @@ def test_infer_matches_oracle(env, gate):
     finally:
         net.set_gate(0.0)
     env["ctx"].check()
-    n = len(pos32)
-    sel = np.arange(0, int(lists.pair_off[-1]), 11)
-    feats, scale = [], []
-    for p in sel:
-        g, c = _pair_cell(lists, n, p)
-        cg, h = _group_geometry(pos32, lists, g)
-        com = cm[c, :3].astype(np.float64)
-        feats.append(omlp.features((com - cg)[None], cm[c, 4:5].astype(np.float64), float(np.float32(EPS)),
-                                   np.array([h]), cm[c, 5:11][None].astype(np.float64),
-                                   cm[c, 3:4].astype(np.float64))[0])
-        scale.append(float(cm[c, 3]) * float(cm[c, 4]) ** 2)
-    u = omlp.to_bf16(np.array(feats))
-    o = omlp.gated_outputs(omlp.bf16_params(omlp.flat_to_params(env["params"])), u, gate)
-    q_ref = omlp.traceless(o) * np.array(scale)[:, None]
-    e = rel_l2(corr[sel], q_ref)
-    frac = np.mean(u[:, 3] >= gate)
-    print(f"inference gate {gate} ({frac:.2f} of pairs through the layers): rel L2 {e:.2e}", flush=True)
-    assert e <= 3e-2
+    pairs = np.arange(0, int(lists.pair_off[-1]), 3)
+    q_ref, q_tol = pair_tensors("mlp", lists, pos32, cm, EPS, pairs, env["params"], gate)
+    g, c = pair_cells(lists, len(pos32), pairs)
+    on = q_tol[:, 0] > 0
+    frac = np.mean(on)
+    r = np.abs(corr[pairs][on] - q_ref[on]) / q_tol[on]
+    print(f"inference gate {gate} ({frac:.2f} of pairs through the layers): largest deviation {r.max():.3f} of "
+          f"the per-entry tolerance", flush=True)
+    assert np.all(r <= 1.0)
     if gate > 0:
         assert 0.05 < frac < 0.95
-        off = u[:, 3] < gate          # the skip term alone: the textbook quadrupole of the BF16 moments
-        np.testing.assert_allclose(corr[sel][off], q_ref[off], rtol=1e-5, atol=1e-6 * np.abs(q_ref).max())
+    np.testing.assert_allclose(corr[pairs][~on], q_ref[~on], rtol=1e-5, atol=1e-6 * np.abs(q_ref).max())
 
 
-def test_training_reduces_loss_and_helps_forces(env):
+@pytest.fixture(scope="module")
+def trained(env):
+    """A network trained on the GPU on the method's own samples (walks of
+    Plummer spheres of 2^14 and 2^18 particles at opening angles drawn from
+    0.5-1.0 and groups of 32-128, layers gated at l/n >= 0.4), 3000 Adam
+    steps of 32768 samples."""
     ctx, net = env["ctx"], env["net"]
-    cfgs = [learned.SampleConfig("plummer", 16384, 1000 + k, EPS, th, 64, 60000)
-            for k, th in enumerate((0.5, 0.6, 0.7, 0.8, 0.9, 0.75))]
+    rng = np.random.Generator(np.random.PCG64(77))
+    cfgs = [learned.SampleConfig("plummer", 16384, 1000 + k, EPS, float(rng.uniform(0.5, 1.0)), 64, 120000)
+            for k in range(12)]
+    cfgs += [learned.SampleConfig("plummer", 1 << 18, 1020 + k, 0.005, float(rng.uniform(0.5, 1.0)),
+                                  int(rng.choice([32, 64, 128])), 240000) for k in range(3)]
     gate = 0.4
     X, aux, eps_all = learned.make_training_set(ctx, net, cfgs, seed=1, gate=gate)
     Xv, auxv, epsv = learned.make_training_set(
-        ctx, net, [learned.SampleConfig("plummer", 16384, 1100, EPS, 0.8, 64, 30000)], seed=2, gate=gate)
+        ctx, net, [learned.SampleConfig("plummer", 16384, 1100, EPS, 0.8, 64, 60000)], seed=2, gate=gate)
     base = learned.zero_correction_loss(auxv)
     net.set_params(np.zeros(learned.N_PARAMS, np.float32))     # zero layers: the textbook quadrupole
     quad = learned.evaluate_loss(net, Xv, auxv, epsv)
     net.set_params(learned.init_params(0))
-    learned.fit(net, X, aux, eps_all, steps=600, batch=16384, lr=2e-3, seed=0)
+    learned.fit(net, X, aux, eps_all, steps=3000, batch=32768, lr=2e-3, seed=0)
     val = learned.evaluate_loss(net, Xv, auxv, epsv)
-    print(f"validation loss {val:.4e} vs plain monopole {base:.4e}, textbook quadrupole {quad:.4e}", flush=True)
-    assert val < 0.5 * base
-    assert val < quad
-    # forces on a held-out Plummer sphere at theta = 0.8
-    pos, m = synth.plummer(16384, seed=1101)
+    params = net.get_params()[0].copy()
+    net.set_params(env["params"])
+    return dict(params=params, gate=gate, val=val, base=base, quad=quad)
+
+
+@pytest.mark.parametrize("n,eps,theta,g_max", [(16384, EPS, 0.8, 64), (1 << 18, 0.005, 0.9, 128)])
+def test_training_reduces_loss_and_helps_forces(env, trained, n, eps, theta, g_max):
+    """What the trained network gains, on held-out Plummer spheres: a lower
+    validation loss than the plain monopole and the textbook quadrupole, and
+    a median force error against direct sums at least 5 % below the textbook
+    quadrupole's on the same lists (and 20 % below the plain monopole's)."""
+    ctx = env["ctx"]
+    print(f"validation loss {trained['val']:.4e} vs plain monopole {trained['base']:.4e}, textbook quadrupole "
+          f"{trained['quad']:.4e}", flush=True)
+    assert trained["base"] == pytest.approx(1.0, rel=1e-5)      # the weights' normalisation
+    assert trained["val"] < 0.5 * trained["base"]
+    assert trained["val"] < trained["quad"]
+    net = learned.Network(ctx)
+    net.set_params(trained["params"])
+    pos, m = synth.plummer(n, seed=1101)
     tree = otoo.Tree(pos, m, n_crit=16)
-    lists = tree.walk(theta=0.8, g_max=64)
+    lists = tree.walk(theta=theta, g_max=g_max)
     d, _, _ = learned.device_tree_arrays(tree, lists)
     _, pos32, mass32, _ = tree.export(12)
-    net.set_gate(gate)
-    gc = ctx.correction(d, otoo.CORR_MLP, EPS, net=net)
-    net.set_gate(0.0)
-    a_l, _ = ctx.force(d, EPS, gcorr=gc)
-    a_q, _ = ctx.force(d, EPS, gcorr=ctx.correction(d, otoo.CORR_QUAD, EPS))
-    a_m, _ = ctx.force(d, EPS)
+    net.set_gate(trained["gate"])
+    gc = ctx.correction(d, otoo.CORR_MLP, eps, net=net)
+    a_l, _ = ctx.force(d, eps, gcorr=gc)
+    a_q, _ = ctx.force(d, eps, gcorr=ctx.correction(d, otoo.CORR_QUAD, eps))
+    a_m, _ = ctx.force(d, eps)
     torch.cuda.synchronize()
     ctx.check()
-    sample = synth.sample_idx(16384, 1024, seed=103)
-    a_dir, _ = oracle.direct(pos32.astype(np.float64), mass32.astype(np.float64), float(np.float32(EPS)),
+    sample = synth.sample_idx(n, 1024, seed=103)
+    a_dir, _ = oracle.direct(pos32.astype(np.float64), mass32.astype(np.float64), float(np.float32(eps)),
                              tgt=sample)
     e_l = np.median(oracle.rel_err(a_l.cpu().numpy()[sample], a_dir))
     e_m = np.median(oracle.rel_err(a_m.cpu().numpy()[sample], a_dir))
     e_q = np.median(oracle.rel_err(a_q.cpu().numpy()[sample], a_dir))
-    print(f"theta 0.8 held out: monopole median {e_m:.2e}, quadrupole {e_q:.2e}, learned {e_l:.2e}", flush=True)
+    print(f"N={n} theta {theta} g_max {g_max} held out: monopole median {e_m:.2e}, quadrupole {e_q:.2e}, learned "
+          f"{e_l:.2e}", flush=True)
     assert e_l < 0.8 * e_m
-    assert e_l < 1.05 * e_q
+    assert e_l <= 0.95 * e_q
 
 
 @pytest.mark.parametrize("net_kernel,gate", [(0, 0.0), (1, 0.0), (0, 0.4), (1, 0.4)])
 def test_fused_learned_correction_matches_oracle(env, net_kernel, gate):
     """The fused per-group learned correction (register-resident network, or
-    the LDS-staged one) against the oracle's list force with the oracle
-    network's tensors (FP64 features rounded to BF16, BF16 weights): the
-    tensors differ by the BF16 activations (~3e-3 relative), and the
-    correction is a small part of the force."""
+    the LDS-staged one) and the force, against the oracle's list force with
+    the oracle network's tensors: element by element against the expanded
+    form, and per target against the per-particle definition within the
+    truncation bound (corr_parity.compare)."""
     ctx, net, d, lists, cm, pos32, mass32 = (env[k] for k in ("ctx", "net", "d", "lists", "cm", "pos32", "mass32"))
     net.set_params(env["params"])
     old = ctx.tuning()
@@ -281,67 +363,145 @@ def test_fused_learned_correction_matches_oracle(env, net_kernel, gate):
     acc, pot = ctx.force(d, EPS, gcorr=gc)
     torch.cuda.synchronize()
     ctx.check()
-    n = len(pos32)
-    feats, scale = [], []
-    for p in range(int(lists.pair_off[-1])):
-        g, c = _pair_cell(lists, n, p)
-        cg, h = _group_geometry(pos32, lists, g)
-        com = cm[c, :3].astype(np.float64)
-        feats.append(omlp.features((com - cg)[None], cm[c, 4:5].astype(np.float64), float(np.float32(EPS)),
-                                   np.array([h]), cm[c, 5:11][None].astype(np.float64),
-                                   cm[c, 3:4].astype(np.float64))[0])
-        scale.append(float(cm[c, 3]) * float(cm[c, 4]) ** 2)
-    o = omlp.gated_outputs(omlp.bf16_params(omlp.flat_to_params(env["params"])), omlp.to_bf16(np.array(feats)),
-                           gate)
-    quad = omlp.traceless(o) * np.array(scale)[:, None]
-    sample = synth.sample_idx(n, 2048, seed=7)
-    a_ref, p_ref = oracle.list_force(pos32.astype(np.float64), mass32.astype(np.float64), lists.group_off,
-                                     lists.list_off, lists.list_idx, cm[:, :3].astype(np.float64),
-                                     cm[:, 3].astype(np.float64), float(np.float32(EPS)), tgt=sample,
-                                     n_cellent=lists.n_cellent, quad=quad, expanded=True)
-    ea = oracle.rel_err(acc.cpu().numpy().astype(np.float64)[sample], a_ref)
-    ep = oracle.rel_err(pot.cpu().numpy()[sample], p_ref)
-    print(f"fused learned correction (kernel {net_kernel}, gate {gate}): acc median {np.median(ea):.2e} "
-          f"p99 {np.quantile(ea, 0.99):.2e}, "
-          f"pot median {np.median(ep):.2e}", flush=True)
-    assert np.median(ea) <= 2e-5 and np.quantile(ea, 0.99) <= 2e-4
-    assert np.median(ep) <= 2e-5
+    groups, tgt = sample_groups(lists, lists.n_groups, 16, seed=7)
+    compare(acc.cpu().numpy(), pot.cpu().numpy(), pos32, mass32, lists, cm, EPS, tgt, groups, "mlp", env["params"],
+            gate, med_bar=2e-5, p99_bar=2e-4, label=f"learned 16k kernel {net_kernel} gate {gate}")
+
+
+def _corrected_on(ctx, tree, theta, g_max, eps, kind, net=None, group_mode=otoo.GROUP_CHUNK, capture=False):
+    lists = tree.walk(theta=theta, g_max=g_max, group_mode=group_mode)
+    d, _, _ = learned.device_tree_arrays(tree, lists)
+    _, pos32, mass32, cm = tree.export(12)
+    gc = torch.empty((d.n_groups, otoo.CORR_STRIDE), dtype=torch.float32, device="cuda:0")
+    out = ctx.outputs(d.n)
+    corr_kind = otoo.CORR_MLP if kind == "mlp" else otoo.CORR_QUAD
+
+    def step():
+        ctx.correction(d, corr_kind, eps, net=net, out=gc)
+        ctx.force(d, eps, out=out, gcorr=gc)
+
+    if capture:
+        g = ctx.capture(step)
+        out[0].zero_()
+        out[1].zero_()
+        g.replay()
+    else:
+        step()
+    torch.cuda.synchronize()
+    ctx.check()
+    return lists, pos32, mass32, cm, out[0].cpu().numpy(), out[1].cpu().numpy()
+
+
+@pytest.mark.parametrize("n,theta,g_max", [(16384, 0.8, 64), (1 << 20, 0.9, 128)])
+def test_quadrupole_matches_definition(env, n, theta, g_max):
+    """The textbook quadrupole 3 S - tr(S) I through the device's correction
+    and force, against the oracle's per-particle quadrupole form and its
+    expanded form (Plummer 16k at theta 0.8 over every group; 2^20 at theta
+    0.9 with groups of 128, sampled)."""
+    ctx = env["ctx"]
+    eps = 0.01 if n == 16384 else 0.005
+    pos, m = synth.plummer(n, seed=0 if n == 16384 else 3)
+    tree = otoo.Tree(pos, m, n_crit=16)
+    lists, pos32, mass32, cm, acc, pot = _corrected_on(ctx, tree, theta, g_max, eps, "quad")
+    ng = lists.n_groups if n == 16384 else 256
+    groups, tgt = sample_groups(lists, ng, 16 if n == 16384 else 8, seed=11)
+    compare(acc, pot, pos32, mass32, lists, cm, eps, tgt, groups, "quad", label=f"quadrupole N={n} theta {theta}")
+
+
+@pytest.mark.parametrize("theta,g_max", [(0.8, 64), (0.8, 128), (0.9, 64), (0.9, 128)])
+def test_learned_plummer_1m(env, trained, theta, g_max):
+    """The learned correction at the sizes it is specified for: held-out
+    Plummer 2^20 (seed 3, eps 0.005), opening angle 0.8-0.9, groups of 64 and
+    128, gate 0.4, the trained network; 2048 targets of 256 sampled groups."""
+    ctx = env["ctx"]
+    net = learned.Network(ctx)
+    net.set_params(trained["params"])
+    net.set_gate(trained["gate"])
+    pos, m = synth.plummer(1 << 20, seed=3)
+    tree = otoo.Tree(pos, m, n_crit=16)
+    lists, pos32, mass32, cm, acc, pot = _corrected_on(ctx, tree, theta, g_max, 0.005, "mlp", net=net)
+    groups, tgt = sample_groups(lists, 256, 8, seed=12)
+    compare(acc, pot, pos32, mass32, lists, cm, 0.005, tgt, groups, "mlp", trained["params"], trained["gate"],
+            med_bar=2e-5, p99_bar=2e-4, label=f"learned Plummer 2^20 theta {theta} g_max {g_max}")
+
+
+def test_learned_cube_16m_captured(env, trained):
+    """The largest single-GPU case: the GRF cube of 256^3 particles (seed 4,
+    eps 1e-3, opening angle 0.7, groups of 32), learned correction and force
+    captured in one graph and replayed; 2048 targets of 256 sampled groups."""
+    ctx = env["ctx"]
+    net = learned.Network(ctx)
+    net.set_params(trained["params"])
+    net.set_gate(trained["gate"])
+    pos, m = synth.grf_cube(256, seed=4)
+    tree = otoo.Tree(pos, m, n_crit=16)
+    del pos, m
+    lists, pos32, mass32, cm, acc, pot = _corrected_on(ctx, tree, 0.7, 32, 1e-3, "mlp", net=net, capture=True)
+    groups, tgt = sample_groups(lists, 256, 8, seed=13)
+    compare(acc, pot, pos32, mass32, lists, cm, 1e-3, tgt, groups, "mlp", trained["params"], trained["gate"],
+            med_bar=2e-5, p99_bar=2e-4, label="learned cube 2^24 theta 0.7 (graph replay)")
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("gate", [0.0, 0.3])
-def test_queue_rounds_on_long_lists(env, gate):
+@pytest.mark.parametrize("net_kernel", [0, 1])
+def test_queue_rounds_on_long_lists(env, gate, net_kernel):
     """Groups of 256 at theta 0.5 hold thousands of cells, so the register-
     resident kernel's queue of gated pairs runs many rounds and carries a
-    remainder between them.  Its per-group expansion must match the
-    LDS-staged kernel's, which runs every pair through the layers in order
-    (the gate applied afterwards) with no queue."""
+    remainder between them (and the LDS-staged kernel many chunks).  Each
+    group's expansion terms {A, Phi, J, H} and centre, against the oracle's
+    sums over the group's cells of the quadrupole-form field derivatives of
+    the oracle network's tensors (oracle.quad_derivs at the box centre), term
+    by term: within the tensors' BF16 allowance carried through each term,
+    plus 1e-5 of the term's absolute sum for the FP32 arithmetic."""
     ctx, net = env["ctx"], env["net"]
     net.set_params(env["params"])
     pos, m = synth.plummer(1 << 17, seed=41)
     tree = otoo.Tree(pos, m, n_crit=16)
     lists = tree.walk(theta=0.5, g_max=256)
     d, _, _ = learned.device_tree_arrays(tree, lists)
+    _, pos32, mass32, cm = tree.export(12)
     cells_per_group = np.diff(lists.pair_off)
-    print(f"cells per group: median {np.median(cells_per_group):.0f}, max {cells_per_group.max()}", flush=True)
     assert np.median(cells_per_group) > 2048
     old = ctx.tuning()
-    out = {}
     net.set_gate(gate)
     try:
-        for k in (0, 1):
-            ctx.set_tuning(net_kernel=k)
-            out[k] = ctx.correction(d, otoo.CORR_MLP, EPS, net=net).cpu().numpy().astype(np.float64)
+        ctx.set_tuning(net_kernel=net_kernel)
+        gc = ctx.correction(d, otoo.CORR_MLP, EPS, net=net).cpu().numpy().astype(np.float64)
     finally:
         net.set_gate(0.0)
         ctx.set_tuning(chunk=old.chunk, blocks_per_cu=old.blocks_per_cu, lpt=old.lpt, tile=old.tile,
                        net_kernel=old.net_kernel)
     ctx.check()
-    a0, a1 = out[0][:, :20], out[1][:, :20]
-    scale = np.abs(a1).max(axis=0) + 1e-30
-    err = (np.abs(a0 - a1) / scale).max()
-    print(f"gate {gate}: max difference {err:.2e} of each term's largest magnitude", flush=True)
-    assert err <= 1e-4
-    np.testing.assert_array_equal(out[0][:, 20:23], out[1][:, 20:23])     # group centres
+    rng = np.random.default_rng(17)
+    groups = np.sort(rng.choice(lists.n_groups, 24, replace=False))
+    centre, _ = group_geometry(pos32.astype(np.float64), lists.group_off)
+    e = float(np.float32(EPS))
+    worst = 0.0
+    for g in groups:
+        pairs = np.arange(lists.pair_off[g], lists.pair_off[g + 1])
+        Q, Qtol = pair_tensors("mlp", lists, pos32, cm, EPS, pairs, env["params"], gate)
+        _, c = pair_cells(lists, len(pos32), pairs)
+        com = cm[c, :3].astype(np.float64)
+        x = np.repeat(centre[g][None], len(pairs), axis=0)
+
+        def terms(q):
+            a, j, h, p = oracle.quad_derivs(x, com, q, e)
+            return np.concatenate([a, p[:, None], j, h], axis=1)    # the 20 terms in the device's order
+
+        ref = terms(Q)
+        tol = 1e-5 * np.abs(ref).sum(axis=0)
+        for k in range(6):
+            unit = np.zeros_like(Q)
+            unit[:, k] = 1.0
+            tol += np.abs(terms(unit) * Qtol[:, k:k + 1]).sum(axis=0)
+        dev = gc[g, :20]
+        r = np.abs(dev - ref.sum(axis=0)) / (tol + 1e-300)
+        worst = max(worst, r.max())
+        np.testing.assert_allclose(gc[g, 20:23], centre[g], rtol=1e-6, atol=1e-7)
+    print(f"kernel {net_kernel} gate {gate}: cells per group median {np.median(cells_per_group):.0f}; largest "
+          f"deviation {worst:.3f} of the per-term tolerance", flush=True)
+    assert worst <= 1.0
 
 
 def test_captured_correction_and_force_replay_matches_eager(env):

@@ -49,8 +49,9 @@ def test_backward_matches_finite_differences():
     for k in p:
         p[k] = p[k] + np.random.default_rng(1).normal(size=p[k].shape) * 0.05
     u, dvec, M_c, l_c, t = _batch(2)
-    L, g, _ = omlp.loss_and_grad(p, u, dvec, M_c, l_c, t, 0.01)
-    assert L == pytest.approx(omlp.loss(p, u, dvec, M_c, l_c, t, 0.01), rel=1e-14)
+    w = np.random.default_rng(2).uniform(0.2, 3.0, len(u))
+    L, g, _ = omlp.loss_and_grad(p, u, dvec, M_c, l_c, t, 0.01, w)
+    assert L == pytest.approx(omlp.loss(p, u, dvec, M_c, l_c, t, 0.01, w), rel=1e-14)
     rng = np.random.default_rng(3)
     for k in p:
         flat = p[k].reshape(-1)
@@ -58,9 +59,9 @@ def test_backward_matches_finite_differences():
             h = 1e-6 * max(1.0, abs(flat[j]))
             q = {kk: vv.copy() for kk, vv in p.items()}
             q[k].reshape(-1)[j] += h
-            lp = omlp.loss(q, u, dvec, M_c, l_c, t, 0.01)
+            lp = omlp.loss(q, u, dvec, M_c, l_c, t, 0.01, w)
             q[k].reshape(-1)[j] -= 2 * h
-            lm = omlp.loss(q, u, dvec, M_c, l_c, t, 0.01)
+            lm = omlp.loss(q, u, dvec, M_c, l_c, t, 0.01, w)
             fd = (lp - lm) / (2 * h)
             assert g[k].reshape(-1)[j] == pytest.approx(fd, rel=1e-6, abs=1e-9 * abs(L) + 1e-14)
 
@@ -220,3 +221,18 @@ def test_zero_layers_give_the_textbook_quadrupole():
                                atol=1e-12)
     # gate 0 leaves every pair to the layers
     np.testing.assert_array_equal(omlp.gated_outputs(p, u, gate=0.0), omlp.forward(p, u)[0])
+
+
+def test_sample_weights_by_hand():
+    """Two kept samples with |t|^2/|a|^2 = 1 and 3 give W = 2 / 4 = 1/2, so
+    w = 1/2 / |a|^2; a sample the gate drops gets the same form of weight but
+    leaves W unchanged; the kept samples' mean of w |t|^2 is then 1, and a
+    target at rest keeps a finite weight."""
+    a = np.array([[1.0, 0.0, 0.0], [0.0, 2.0, 0.0], [0.0, 0.0, 3.0], [0.0, 0.0, 0.0]])
+    t = np.array([[1.0, 0.0, 0.0], [0.0, 0.0, 2.0 * np.sqrt(3.0)], [5.0, 0.0, 0.0], [1.0, 0.0, 0.0]])
+    kept = np.array([True, True, False, False])
+    w = omlp.sample_weights(a, t, kept)
+    np.testing.assert_allclose(w[:3], [0.5, 0.125, 0.5 / 9.0], rtol=1e-15)
+    assert w[3] == pytest.approx(0.5e300)
+    assert np.mean((w * (t * t).sum(axis=1))[kept]) == pytest.approx(1.0, rel=1e-15)
+    assert np.all(omlp.sample_weights(a[:2], np.zeros((2, 3)), kept[:2]) == 1.0 / np.array([1.0, 4.0]))
