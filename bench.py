@@ -560,7 +560,9 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--lpt", type=int, default=-1)
     ap.add_argument("--tile", type=int, default=0)
-    ap.add_argument("--autotune", action="store_true", help="sweep the schedule and store the best in the cache")
+    ap.add_argument("--autotune", action="store_true",
+                    help="sweep the schedule (of the corrected step in a corrected mode) and store the best in the cache")
+    ap.add_argument("--autotune-reps", type=int, default=10, help="timed replays per autotuned schedule")
     ap.add_argument("--cache", default="", help="autotune cache file (default: the package's)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction comparison on Plummer")
     ap.add_argument("--no-plummer", action="store_true", help="skip the Plummer 2^20 plain headline")
@@ -596,18 +598,25 @@ def main():
     del pos
     ctx = otoo.Context(0)
 
-    key = f"{at.device_key(0)}:{args.workload}"
+    net, training, params = None, None, None
+    if mode == "learned":
+        net, training = train_network(ctx, log, args.train_steps, gate=args.gate)
+        params = net.get_params()[0]
+
+    key = at.cache_key(args.workload, mode)
     cache_path = args.cache or at.DEFAULT_CACHE
     if args.autotune:
         grid = dict(at.GRID)
         if args.workload in GROUPS:
             grid["group"] = GROUPS[args.workload]
-        best, table = at.autotune(tree, eps, theta, ctx, grid=grid, log=log)
+        kind = {"plain": -1, "quad": otoo.CORR_QUAD, "learned": otoo.CORR_MLP}[mode]
+        best, table = at.autotune(tree, eps, theta, ctx, grid=grid, log=log, corr_kind=kind, net=net,
+                                  reps=args.autotune_reps)
         at.save_cache(key, best, cache_path)
         sched = {k: best[k] for k in at.DEFAULT_SCHEDULE}
-        source = "autotuned now"
+        source = "autotuned now" + ("" if mode == "plain" else f" ({mode} step)")
     else:
-        sched, source = at.cached_schedule(args.workload, 0, cache_path)
+        sched, source = at.cached_schedule(args.workload, 0, cache_path, mode=mode)
     for k, v in (("g_max", args.g_max), ("group_mode", args.group_mode), ("chunk", args.chunk),
                  ("blocks_per_cu", args.blocks_per_cu), ("tile", args.tile)):
         if v:
@@ -617,11 +626,6 @@ def main():
         sched["lpt"] = args.lpt
     gmode = otoo.GROUP_CHUNK if sched["group_mode"] == "chunk" else otoo.GROUP_CELL
     log(f"schedule ({source}): {sched}")
-
-    net, training, params = None, None, None
-    if mode == "learned":
-        net, training = train_network(ctx, log, args.train_steps, gate=args.gate)
-        params = net.get_params()[0]
 
     t2 = time.perf_counter()
     with marker("host walk"):

@@ -189,7 +189,9 @@ typedef struct {
     int32_t lpt;          /* 1: hand out items longest-first, 0: in group order */
     int32_t debug_validate; /* 1: check the CSR on the host before launching (slow) */
     int32_t tile;         /* list entries staged in LDS per tile: 256, 512 or 1024 */
-    int32_t net_kernel;   /* learned correction kernel: 0 registers-resident (default), 1 LDS-staged */
+    int32_t net_kernel;   /* learned correction kernel: 0 fused, registers-resident; 1 fused, LDS-staged;
+                             2 (default) a network pass writing the gated pairs' tensors, then the
+                             expansion pass */
 } otoo_tuning;
 int otoo_set_tuning(otoo_ctx* ctx, const otoo_tuning* tuning);
 int otoo_get_tuning(const otoo_ctx* ctx, otoo_tuning* tuning);
@@ -461,6 +463,21 @@ int otoo_autotune(otoo_ctx* ctx, const otoo_tree* tree, const otoo_walk_params* 
                   const otoo_group_choice* choices, int32_t n_choices, const otoo_tuning* schedules,
                   int32_t n_schedules, float eps, int32_t reps, float* ms, int64_t* interactions,
                   otoo_group_choice* best_choice, otoo_tuning* best_tuning, float* best_ms);
+/* The same sweep for a corrected evaluation: each timed replay is one graph
+ * holding the correction pass (otoo_correction of corr_kind, OTOO_CORR_QUAD
+ * or OTOO_CORR_MLP with the network mlp of this context) followed by the
+ * force with that correction, captured on the context's stream; the cell
+ * moments go with stride 12 and each group's cell-entry counts give the
+ * pair offsets.  Larger groups cut the (group, cell) pairs the correction
+ * pays for and raise the interactions the force pays for, so the corrected
+ * step has its own best group size.  corr_kind -1 is otoo_autotune.  The
+ * context's tuning (net_kernel included) is restored afterwards.  EINVAL as
+ * otoo_autotune, and for another corr_kind or a missing network. */
+int otoo_autotune_step(otoo_ctx* ctx, const otoo_tree* tree, const otoo_walk_params* walk,
+                       const otoo_group_choice* choices, int32_t n_choices, const otoo_tuning* schedules,
+                       int32_t n_schedules, float eps, int32_t corr_kind, otoo_mlp* mlp, int32_t reps, float* ms,
+                       int64_t* interactions, otoo_group_choice* best_choice, otoo_tuning* best_tuning,
+                       float* best_ms);
 
 /* Synchronise the context's stream and report whether any kernel since the
  * last otoo_check met malformed input (EINVAL) or not (OK); clears the flag. */

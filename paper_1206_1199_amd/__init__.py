@@ -97,7 +97,7 @@ EXPORTED = [
     "otoo_tree_links", "otoo_tree_walk", "otoo_tree_groups", "otoo_tree_walk_range", "otoo_tree_walk_sph", "otoo_lists_free", "otoo_create", "otoo_destroy",
     "otoo_set_stream", "otoo_last_error", "otoo_set_tuning", "otoo_get_tuning", "otoo_force",
     "otoo_check", "otoo_enable_timing", "otoo_last_timing", "otoo_graph_capture", "otoo_graph_launch",
-    "otoo_autotune", "otoo_set_scratch_limit", "otoo_force_plan", "otoo_scratch_generation",
+    "otoo_autotune", "otoo_autotune_step", "otoo_set_scratch_limit", "otoo_force_plan", "otoo_scratch_generation",
     "otoo_quad_exact", "otoo_correction", "otoo_direct", "otoo_sph_sum", "otoo_mlp_num_params", "otoo_mlp_create", "otoo_mlp_destroy", "otoo_mlp_set_params", "otoo_mlp_set_gate",
     "otoo_mlp_get_params", "otoo_mlp_save", "otoo_mlp_load", "otoo_mlp_forward", "otoo_mlp_infer",
     "otoo_mlp_train_samples", "otoo_mlp_sample_weights", "otoo_mlp_backward", "otoo_mlp_train_step",
@@ -149,6 +149,9 @@ def lib():
         "otoo_autotune": ([P, P, ctypes.POINTER(_WalkParams), ctypes.POINTER(GroupChoice), I32,
                            ctypes.POINTER(Tuning), I32, F, I32, P, P, ctypes.POINTER(GroupChoice),
                            ctypes.POINTER(Tuning), ctypes.POINTER(F)], I32),
+        "otoo_autotune_step": ([P, P, ctypes.POINTER(_WalkParams), ctypes.POINTER(GroupChoice), I32,
+                                ctypes.POINTER(Tuning), I32, F, I32, P, I32, P, P, ctypes.POINTER(GroupChoice),
+                                ctypes.POINTER(Tuning), ctypes.POINTER(F)], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -579,9 +582,11 @@ class Context:
         self._raise(lib().otoo_graph_launch(self._h), "otoo_graph_launch")
 
     def autotune(self, tree: Tree, eps: float, choices, schedules, reps: int = 10, theta: float = 0.5,
-                 mac: int = MAC_BH, delta: float = 0.01, m_limit: float = math.inf):
+                 mac: int = MAC_BH, delta: float = 0.01, m_limit: float = math.inf, corr_kind: int = -1, net=None):
         """Time every (group_mode, g_max) choice x device schedule as graph replays
-        (otoo_autotune).  schedules: dicts with chunk, blocks_per_cu, lpt, tile.
+        (otoo_autotune; with corr_kind CORR_QUAD or CORR_MLP (and ``net``)
+        otoo_autotune_step, each replay being the correction pass and the
+        force).  schedules: dicts with chunk, blocks_per_cu, lpt, tile.
         Returns (ms [n_choices, n_schedules], interactions [n_choices],
         best (group_mode, g_max), best Tuning, best ms).  Discards any graph the
         context held."""
@@ -592,8 +597,14 @@ class Context:
         inter = np.zeros(len(choices), np.int64)
         bc, bt, bms = GroupChoice(), Tuning(), ctypes.c_float()
         p = _WalkParams(mac=mac, theta=theta, delta=delta, m_limit=m_limit, group_mode=GROUP_CHUNK, g_max=1)
-        rc = lib().otoo_autotune(self._h, tree._h, ctypes.byref(p), ch, len(choices), sc, len(schedules),
-                                 float(eps), int(reps), _np_ptr(ms), _np_ptr(inter), ctypes.byref(bc),
-                                 ctypes.byref(bt), ctypes.byref(bms))
+        if corr_kind < 0:
+            rc = lib().otoo_autotune(self._h, tree._h, ctypes.byref(p), ch, len(choices), sc, len(schedules),
+                                     float(eps), int(reps), _np_ptr(ms), _np_ptr(inter), ctypes.byref(bc),
+                                     ctypes.byref(bt), ctypes.byref(bms))
+        else:
+            rc = lib().otoo_autotune_step(self._h, tree._h, ctypes.byref(p), ch, len(choices), sc, len(schedules),
+                                          float(eps), int(corr_kind), net._h if net is not None else None,
+                                          int(reps), _np_ptr(ms), _np_ptr(inter), ctypes.byref(bc),
+                                          ctypes.byref(bt), ctypes.byref(bms))
         self._raise(rc, "otoo_autotune")
         return ms, inter, (bc.group_mode, bc.g_max), bt, bms.value

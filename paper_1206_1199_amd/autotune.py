@@ -44,16 +44,20 @@ def device_key(device: int = 0) -> str:
     return f"{arch}:{p.multi_processor_count}cu"
 
 
-def autotune(tree: Tree, eps: float, theta: float, ctx: Context, grid=None, reps: int = 10, log=None):
-    """Sweep the grid through the library's otoo_autotune; returns (best dict,
-    table of all measurements).  The best is the fastest schedule, or, among
-    those within 1 % of it, the one with the most interactions per second."""
+def autotune(tree: Tree, eps: float, theta: float, ctx: Context, grid=None, reps: int = 10, log=None,
+             corr_kind: int = -1, net=None):
+    """Sweep the grid through the library's otoo_autotune (otoo_autotune_step
+    when corr_kind is CORR_QUAD or CORR_MLP: the timed step is the correction
+    pass and the force); returns (best dict, table of all measurements).  The
+    best is the fastest schedule, or, among those within 1 % of it, the one
+    with the most interactions per second."""
     grid = grid or GRID
     choices = list(grid["group"])
     schedules = [dict(chunk=c, blocks_per_cu=b, lpt=l, tile=t)
                  for c, b, l, t in itertools.product(grid["chunk"], grid["blocks_per_cu"], grid["lpt"], grid["tile"])]
     ctx.sync_stream()
-    ms, inter, _, _, _ = ctx.autotune(tree, eps, choices, schedules, reps=reps, theta=theta)
+    ms, inter, _, _, _ = ctx.autotune(tree, eps, choices, schedules, reps=reps, theta=theta, corr_kind=corr_kind,
+                                      net=net)
     table = []
     for gi, (mode, g_max) in enumerate(choices):
         rows = [dict(group_mode="chunk" if mode == GROUP_CHUNK else "cell", g_max=g_max, **s, ms=float(ms[gi, si]),
@@ -89,14 +93,27 @@ def save_cache(entry_key: str, best: dict, path: str = DEFAULT_CACHE):
 DEFAULT_SCHEDULE = dict(group_mode="chunk", g_max=64, chunk=2048, blocks_per_cu=8, lpt=1, tile=256)
 
 
-def cached_schedule(workload: str, device: int = 0, path: str = DEFAULT_CACHE):
-    """(schedule, source): the cached choice for this device and workload, or the defaults."""
+def cache_key(workload: str, mode: str = "plain", device: int = 0) -> str:
+    """Cache key of a workload's schedule: the plain force, or the corrected
+    step of mode "quad" or "learned" (which has its own best group size)."""
+    return f"{device_key(device)}:{workload}" + ("" if mode == "plain" else f"+{mode}")
+
+
+def cached_schedule(workload: str, device: int = 0, path: str = DEFAULT_CACHE, mode: str = "plain"):
+    """(schedule, source): the cached choice for this device, workload and
+    mode; for a corrected mode without its own entry, the plain force's; else
+    the defaults."""
     sched = dict(DEFAULT_SCHEDULE)
-    cached = load_cache(path).get(f"{device_key(device)}:{workload}")
+    cache = load_cache(path)
+    cached = cache.get(cache_key(workload, mode, device))
+    source = "autotune cache" + ("" if mode == "plain" else f" ({mode} step)")
+    if not cached and mode != "plain":
+        cached = cache.get(cache_key(workload, "plain", device))
+        source = "autotune cache (plain force)"
     if not cached:
         return sched, "defaults"
     sched.update({k: cached[k] for k in sched})
-    return sched, "autotune cache"
+    return sched, source
 
 
 def apply_schedule(ctx: Context, sched: dict):

@@ -403,6 +403,7 @@ struct CorrPlan {
     float* part_l;   // [n_items][kCorrStride]: 20 terms, centre xyz, pad
     float* part_r;   // [n_items][kCorrStride]
     float4* box;     // [n_groups]: box centre xyz and half-diagonal, -1 for a malformed group
+    uint4* crec;     // [n_cells][2]: the cells' records of the two-pass learned correction
 };
 
 struct CorrArgs {
@@ -780,6 +781,27 @@ __global__ __launch_bounds__(256) void k_corr_merge(CorrArgs a) {
     }
 }
 
+// Static, XCD-aware assignment of work items to the waves of a grid of
+// 256-thread workgroups.  The dispatcher deals workgroups to the chip's
+// eight XCDs in turn (workgroup b to XCD b mod 8), and each XCD has its own
+// L2; so each XCD takes a contiguous eighth of the items, and the waves that
+// share an L2 work on neighbouring items, whose groups gather the same
+// cells.  Within an XCD the waves take its items in turn.  Every item goes
+// to exactly one wave for any grid size.
+struct ItemRange {
+    int64_t first, end, step;
+};
+__device__ __forceinline__ ItemRange xcd_items(int64_t n_items) {
+    const int nx = gridDim.x < 8 ? (int)gridDim.x : 8;
+    const int b = blockIdx.x, x = b % nx, j = b / nx;
+    const int nblk = ((int)gridDim.x - x + nx - 1) / nx;   // workgroups of this XCD
+    const int64_t per = (n_items + nx - 1) / nx;
+    const int64_t lo = (int64_t)x * per < n_items ? (int64_t)x * per : n_items;
+    const int64_t hi = lo + per < n_items ? lo + per : n_items;
+    const int64_t first = lo + (int64_t)j * 4 + (threadIdx.x >> 6);
+    return ItemRange{__builtin_amdgcn_readfirstlane(first), hi, (int64_t)nblk * 4};
+}
+
 // One (group, cell) pair of the given or textbook kind as gathered: the
 // cell's COM and either the given tensor or the cell's second moments S
 // (raw, so that a prefetched pair costs no arithmetic until it is used).  A
@@ -849,9 +871,8 @@ template <int KIND>
 __global__ __launch_bounds__(256) void k_corr_wave(CorrArgs a) {
     const int lane = threadIdx.x & 63;
     const float eps2 = a.eps * a.eps;
-    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t it = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-         it < a.plan.n_items; it += waves) {
+    const ItemRange ir = xcd_items(a.plan.n_items);
+    for (int64_t it = ir.first; it < ir.end; it += ir.step) {
         const int64_t q0 = it * kCorrSeg;
         const int64_t q1 = q0 + kCorrSeg < a.n_pairs ? q0 + kCorrSeg : a.n_pairs;
         for (int g = group_of_pair(a, q0); g < a.n_groups; g++) {
@@ -931,8 +952,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
     for (int ks = 0; ks < 2; ks++) w3a[ks] = ld_perm(a.wbf + OFFB_W3T, NH, r16, ks, q);
     __syncthreads();
-    const int64_t waves = (int64_t)gridDim.x * 4;
-    for (int64_t it = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w); it < a.plan.n_items; it += waves)
+    const ItemRange ir = xcd_items(a.plan.n_items);
+    for (int64_t it = ir.first; it < ir.end; it += ir.step)
     for (int g = group_of_pair(a, it * kCorrSeg); g < a.n_groups; g++) {
         const int64_t q0 = it * kCorrSeg;
         const int64_t q1 = q0 + kCorrSeg < a.n_pairs ? q0 + kCorrSeg : a.n_pairs;
@@ -1056,6 +1077,334 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
         if (pend > 0) run_net(pend);
         wave_store_part(corr_target(a, g, it, p0, p1, q0, q1), lane, f, cx, cy, cz);
+    }
+}
+
+// ---------------------------------------------------------------- learned correction in two passes
+
+// The learned correction split into a network pass and an expansion pass,
+// so that neither carries the other's registers.
+//
+// k_corr_gnet: every wave takes the items of kCorrSeg pairs in turn (as the
+// wave kernels do) and decides per pair whether the gate sends it through
+// the layers (features in range and finite, BF16 l/n at least the gate).
+// The pairs that go are appended to the wave's queue in LDS with their BF16
+// features, scale M l^2 and pair number; each full batch of 64 runs the
+// network with the weights as the MFMA's A operand held in registers (the
+// layout of k_corr_net) and the features read from the queue as the B
+// operand, and each pair's traceless tensor M l^2 P(o + 3 s) goes to its row
+// of the pair buffer.  The queue carries over from group to group and item
+// to item, so only a wave's last batch runs partly empty.
+//
+// k_corr_apply: per item and group, the pairs in order, four-deep software
+// pipelined like k_corr_wave; a pair the gate keeps out gets the skip term
+// alone (the textbook quadrupole of the BF16 features) at once, a gated pair
+// is listed in LDS with its cell's COM, and whenever the list fills, and at
+// the end of the group's part of the item, the listed pairs' tensors are
+// read from the pair buffer and expanded.  The order of the sums is fixed by
+// the item alone.
+// Per-cell record of the two-pass learned correction, 32 bytes: COM xyz, l,
+// the scale M l^2 (0 when the cell's part of the features -- the normalised
+// second moments s = S / (M l^2) -- is out of range or not finite, or
+// M l^2 <= 0, so that none of its pairs counts), then s in BF16 (xx, yy, zz,
+// xy, xz, yz).  The pair features are those of pair_features: the same FP32
+// operations, split between the cell and the pair.
+__global__ __launch_bounds__(256) void k_corr_cells(CorrArgs a) {
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < a.n_cells; c += (int64_t)gridDim.x * 256) {
+        const float* cm = a.cell_mom + 12 * c;
+        const float4 u0 = *reinterpret_cast<const float4*>(cm);
+        const float4 u1 = *reinterpret_cast<const float4*>(cm + 4);
+        const float4 u2 = *reinterpret_cast<const float4*>(cm + 8);
+        const float M = u0.w, l = u1.x;
+        const float sc = M * l * l;
+        const float isc = sc > 0.f ? 1.f / sc : 0.f;
+        const float S[6] = {u1.y, u1.z, u1.w, u2.x, u2.y, u2.z};
+        float f[6];
+        bool ok = sc > 0.f;
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            f[k] = S[k] * isc;
+            ok = ok && fabsf(f[k]) <= kFeatLimit;   // also false for NaN
+        }
+        uint4* r = a.plan.crec + 2 * c;
+        r[0] = make_uint4(__float_as_uint(u0.x), __float_as_uint(u0.y), __float_as_uint(u0.z), __float_as_uint(l));
+        r[1] = make_uint4(__float_as_uint(ok ? sc : 0.f), (uint32_t)f2bf(f[0]) | ((uint32_t)f2bf(f[1]) << 16),
+                          (uint32_t)f2bf(f[2]) | ((uint32_t)f2bf(f[3]) << 16),
+                          (uint32_t)f2bf(f[4]) | ((uint32_t)f2bf(f[5]) << 16));
+    }
+}
+
+// A cell record as gathered: COM, l, scale (0: the cell's pairs do not count)
+// and the BF16 normalised second moments (three words).
+struct CellRec {
+    float com[3], l, sc;
+    uint32_t s[3];
+};
+__device__ __forceinline__ CellRec load_cell_rec(const uint4* crec, int64_t c) {
+    const uint4 r0 = crec[2 * c], r1 = crec[2 * c + 1];
+    return CellRec{{__uint_as_float(r0.x), __uint_as_float(r0.y), __uint_as_float(r0.z)}, __uint_as_float(r0.w),
+                   __uint_as_float(r1.x), {r1.y, r1.z, r1.w}};
+}
+// BF16 normalised second moment m (0..5) of a record
+__device__ __forceinline__ float rec_s(const CellRec& r, int m) {
+    return bf2f((uint16_t)(r.s[m >> 1] >> (16 * (m & 1))));
+}
+// The pair's own features d/n, l/n, eps/n, h/n (FP32) and whether the pair
+// counts (the conditions of pair_features).
+__device__ __forceinline__ bool rec_features(float cx, float cy, float cz, float h, const CellRec& r, float eps,
+                                             float f[6]) {
+    const float dx = r.com[0] - cx, dy = r.com[1] - cy, dz = r.com[2] - cz;
+    const float n2 = dx * dx + dy * dy + dz * dz;
+    const float inv = n2 > 0.f ? __builtin_amdgcn_rsqf(n2) : 0.f;
+    f[0] = dx * inv;
+    f[1] = dy * inv;
+    f[2] = dz * inv;
+    f[3] = r.l * inv;
+    f[4] = eps * inv;
+    f[5] = h * inv;
+    bool ok = n2 > 0.f && r.sc > 0.f;
+#pragma unroll
+    for (int k = 0; k < 6; k++) ok = ok && fabsf(f[k]) <= kFeatLimit;
+    return ok;
+}
+
+constexpr int kQRow = 8;     // floats per row of the pair buffer (6 used, 32-byte rows)
+constexpr int kGQ = 128;     // queue slots per wave of k_corr_gnet
+constexpr int kApList = 256; // listed gated pairs per wave of k_corr_apply
+
+struct GnetQueue {
+    alignas(16) uint16_t x[kGQ][16];   // BF16 features 0..11, then zeros (the first 16 of the K = 32 inputs)
+    float sc[kGQ];
+    int64_t p[kGQ];
+};
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_corr_gnet(CorrArgs a, float* __restrict__ qbuf) {
+    __shared__ float sb[NH + NH + NOUTP];
+    __shared__ __align__(16) uint16_t sw3[NOUTP * NH];   // the last layer's weights (out-major), read per batch
+    __shared__ GnetQueue sq[4];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, r16 = lane & 15, q = lane >> 4;
+    GnetQueue& Q = sq[w];
+    for (int i = t; i < NH; i += 256) {
+        sb[i] = a.master[OFF_B1 + i];
+        sb[NH + i] = a.master[OFF_B2 + i];
+    }
+    if (t < NOUTP) sb[2 * NH + t] = t < NOUT ? a.master[OFF_B3 + t] : 0.f;
+    for (int i = t; i < NOUTP * NH; i += 256) sw3[i] = a.wbf[OFFB_W3T + i];
+    bf16x8 w1a[4], w2a[4][2];
+#pragma unroll
+    for (int mt = 0; mt < 4; mt++) {
+        w1a[mt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(a.wbf + OFFB_W1T + (mt * 16 + r16) * NIN + q * 8));
+#pragma unroll
+        for (int ks = 0; ks < 2; ks++) w2a[mt][ks] = ld_perm(a.wbf + OFFB_W2T, NH, mt * 16 + r16, ks, q);
+    }
+    __syncthreads();
+
+    // the network on queue slots [0, cnt)
+    auto run_net = [&](int cnt) {
+#pragma unroll
+        for (int tau = 0; tau < 4; tau++) {
+            const int slot = tau * 16 + r16;
+            bf16x8 xb = {};
+            if (q < 2) xb = ld8(&Q.x[slot][q * 8]);   // K rows q*8 .. q*8+7 of pair column r16; rows >= 16 are zero
+            floatx4 acc[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; mt++) {
+                const float4 bb = *reinterpret_cast<const float4*>(sb + mt * 16 + q * 4);
+                acc[mt] = mfma(w1a[mt], xb, floatx4{bb.x, bb.y, bb.z, bb.w});
+            }
+            const bf16x8 h0 = pack8(acc[0], acc[1]), h1 = pack8(acc[2], acc[3]);
+#pragma unroll
+            for (int mt = 0; mt < 4; mt++) {
+                const float4 bb = *reinterpret_cast<const float4*>(sb + NH + mt * 16 + q * 4);
+                acc[mt] = mfma(w2a[mt][0], h0, floatx4{bb.x, bb.y, bb.z, bb.w});
+                acc[mt] = mfma(w2a[mt][1], h1, acc[mt]);
+            }
+            const bf16x8 g0b = pack8(acc[0], acc[1]), g1b = pack8(acc[2], acc[3]);
+            const float4 b3 = *reinterpret_cast<const float4*>(sb + 2 * NH + q * 4);
+            floatx4 o = mfma(ld_perm(sw3, NH, r16, 0, q), g0b, floatx4{b3.x, b3.y, b3.z, b3.w});
+            o = mfma(ld_perm(sw3, NH, r16, 1, q), g1b, o);
+            // lane (r16, q) holds outputs q*4 .. q*4+3 of the slot's pair: q = 0 has 0..3, q = 1 has 4, 5
+            if (slot < cnt && q < 2) {
+                const uint16_t* xr = Q.x[slot];
+                const float sc = Q.sc[slot];
+                float* row = qbuf + (int64_t)kQRow * Q.p[slot];
+                if (q == 0) {
+                    const float o0 = o[0] + 3.f * bf2f(xr[kSkip0]), o1 = o[1] + 3.f * bf2f(xr[kSkip0 + 1]);
+                    const float o2 = o[2] + 3.f * bf2f(xr[kSkip0 + 2]), o3 = o[3] + 3.f * bf2f(xr[kSkip0 + 3]);
+                    const float tr = (o0 + o1 + o2) * (1.f / 3.f);
+                    *reinterpret_cast<float4*>(row) = make_float4((o0 - tr) * sc, (o1 - tr) * sc, (o2 - tr) * sc, o3 * sc);
+                } else {
+                    const float o4 = o[0] + 3.f * bf2f(xr[kSkip0 + 4]), o5 = o[1] + 3.f * bf2f(xr[kSkip0 + 5]);
+                    *reinterpret_cast<float2*>(row + 4) = make_float2(o4 * sc, o5 * sc);
+                }
+            }
+        }
+    };
+
+    int pend = 0;   // queued pairs, uniform within the wave
+    const ItemRange ir = xcd_items(a.plan.n_items);
+    for (int64_t it = ir.first; it < ir.end; it += ir.step)
+    for (int g = group_of_pair(a, it * kCorrSeg); g < a.n_groups; g++) {
+        const int64_t q0 = it * kCorrSeg;
+        const int64_t q1 = q0 + kCorrSeg < a.n_pairs ? q0 + kCorrSeg : a.n_pairs;
+        int64_t p0, p1;
+        pair_range(a, g, p0, p1);
+        if (p0 >= q1) break;
+        const int64_t a0 = p0 > q0 ? p0 : q0, a1 = p1 < q1 ? p1 : q1;
+        if (a1 <= a0) continue;   // no pairs of this group in the item
+        float cx, cy, cz, h;
+        if (!group_box(a, g, cx, cy, cz, h)) continue;   // flagged by k_corr_box
+        int64_t lb, le;
+        list_range(a.list_off, a.n_entries, g, lb, le);
+        const int64_t k0 = a0 - p0, k1 = (a1 - p0) < (le - lb) ? (a1 - p0) : (le - lb);
+        for (int64_t base = k0; base < k1; base += 64) {
+            const int64_t k = base + lane;
+            bool gated = false;
+            float fe[6];
+            CellRec r{};
+            if (k < k1) {
+                const int64_t c = (int64_t)a.list_idx[lb + k] - a.n;   // a bad entry is flagged by k_corr_apply
+                if (c >= 0 && c < a.n_cells) {
+                    r = load_cell_rec(a.plan.crec, c);
+                    if (rec_features(cx, cy, cz, h, r, a.eps, fe)) gated = bf_round(fe[3]) >= a.gate;
+                }
+            }
+            const uint64_t mask = __ballot(gated);
+            if (gated) {
+                const int slot = pend + __popcll(mask & ((1ull << lane) - 1ull));   // pend < 64
+                uint4* dst = reinterpret_cast<uint4*>(Q.x[slot]);
+                dst[0] = make_uint4((uint32_t)f2bf(fe[0]) | ((uint32_t)f2bf(fe[1]) << 16),
+                                    (uint32_t)f2bf(fe[2]) | ((uint32_t)f2bf(fe[3]) << 16),
+                                    (uint32_t)f2bf(fe[4]) | ((uint32_t)f2bf(fe[5]) << 16), r.s[0]);
+                dst[1] = make_uint4(r.s[1], r.s[2], 0u, 0u);
+                Q.sc[slot] = r.sc;
+                Q.p[slot] = p0 + k;
+            }
+            pend += __popcll(mask);
+            __builtin_amdgcn_wave_barrier();
+            if (pend >= 64) {
+                run_net(64);
+                const int rest = pend - 64;   // < 64, moved from [64, pend) to the front
+                uint4 x0 = {}, x1 = {};
+                float s = 0.f;
+                int64_t pp = 0;
+                if (lane < rest) {
+                    x0 = reinterpret_cast<const uint4*>(Q.x[64 + lane])[0];
+                    x1 = reinterpret_cast<const uint4*>(Q.x[64 + lane])[1];
+                    s = Q.sc[64 + lane];
+                    pp = Q.p[64 + lane];
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (lane < rest) {
+                    reinterpret_cast<uint4*>(Q.x[lane])[0] = x0;
+                    reinterpret_cast<uint4*>(Q.x[lane])[1] = x1;
+                    Q.sc[lane] = s;
+                    Q.p[lane] = pp;
+                }
+                __builtin_amdgcn_wave_barrier();
+                pend = rest;
+            }
+        }
+    }
+    if (pend > 0) run_net(pend);
+}
+
+// The cell record of a pair for k_corr_apply (branch-free, as in
+// load_corr_cell: a position past the item, or an entry that is not a cell,
+// reads cell 0 and is not valid).
+struct ApCell {
+    CellRec r;
+    bool valid;
+};
+__device__ __forceinline__ ApCell load_ap_cell(const CorrArgs& a, CorrEntry en, bool& bad) {
+    const int64_t c = en.e - a.n;
+    const bool ok = en.pv && c >= 0 && c < a.n_cells;
+    bad |= en.pv && !ok;
+    return ApCell{load_cell_rec(a.plan.crec, ok ? c : 0), ok};
+}
+
+struct ApList {
+    float4 com[kApList];   // COM xyz, the pair's offset from the item segment's first pair (as float bits)
+};
+
+__global__ __launch_bounds__(256) void k_corr_apply(CorrArgs a, const float* __restrict__ qbuf) {
+    __shared__ ApList sl[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    ApList& L = sl[w];
+    const float eps2 = a.eps * a.eps;
+    const ItemRange ir = xcd_items(a.plan.n_items);
+    for (int64_t it = ir.first; it < ir.end; it += ir.step) {
+        const int64_t q0 = it * kCorrSeg;
+        const int64_t q1 = q0 + kCorrSeg < a.n_pairs ? q0 + kCorrSeg : a.n_pairs;
+        for (int g = group_of_pair(a, q0); g < a.n_groups; g++) {
+            int64_t p0, p1;
+            pair_range(a, g, p0, p1);
+            if (p0 >= q1) break;
+            const int64_t a0 = p0 > q0 ? p0 : q0, a1 = p1 < q1 ? p1 : q1;
+            if (a1 <= a0) continue;   // no pairs of this group in the item
+            float cx, cy, cz, h;
+            const bool ok = group_box(a, g, cx, cy, cz, h);
+            float f[kCorrTerms];
+#pragma unroll
+            for (int k = 0; k < kCorrTerms; k++) f[k] = 0.f;
+            int64_t lb, le;
+            list_range(a.list_off, a.n_entries, g, lb, le);
+            // the listed gated pairs [0, cnt): tensors from the pair buffer, expanded in list order
+            auto drain = [&](int cnt) {
+                for (int j0 = 0; j0 < cnt; j0 += 64) {
+                    const int j = j0 + lane;
+                    float Qv[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                    float4 cm = make_float4(cx, cy, cz, 0.f);
+                    if (j < cnt) {
+                        cm = L.com[j];
+                        const float* row = qbuf + (int64_t)kQRow * (a0 + (int64_t)__float_as_int(cm.w));
+                        const float4 r0 = *reinterpret_cast<const float4*>(row);
+                        const float2 r1 = *reinterpret_cast<const float2*>(row + 4);
+                        Qv[0] = r0.x; Qv[1] = r0.y; Qv[2] = r0.z; Qv[3] = r0.w; Qv[4] = r1.x; Qv[5] = r1.y;
+                    }
+                    quad_expand_add(cx - cm.x, cy - cm.y, cz - cm.z, Qv, eps2, f);
+                }
+                __builtin_amdgcn_wave_barrier();
+            };
+            int listed = 0;   // uniform within the wave
+            if (ok && le > lb && a.n_cells > 0) {
+                const int64_t kmax = le - lb - 1;
+                const int64_t p_first = a0 + lane;
+                bool bad = false;
+                ApCell cur = load_ap_cell(a, corr_list_entry(a, p_first, a1, p0, lb, kmax), bad);
+                CorrEntry e_next = corr_list_entry(a, p_first + 64, a1, p0, lb, kmax);
+                for (int64_t p = p_first; p - lane < a1; p += 64) {
+                    const CorrEntry e_after = corr_list_entry(a, p + 128, a1, p0, lb, kmax);
+                    const ApCell nxt = load_ap_cell(a, e_next, bad);
+                    // keeps these loads ahead of the sum below (see k_corr_wave)
+                    __asm__ volatile("" ::: "memory");
+                    float fe[6];
+                    const CellRec& r = cur.r;
+                    const bool valid = cur.valid && rec_features(cx, cy, cz, h, r, a.eps, fe);
+                    const bool gated = valid && bf_round(fe[3]) >= a.gate;
+                    const uint64_t mask = __ballot(gated);
+                    if (gated)
+                        L.com[listed + __popcll(mask & ((1ull << lane) - 1ull))] =
+                            make_float4(r.com[0], r.com[1], r.com[2], __int_as_float((int)(p - a0)));
+                    listed += __popcll(mask);
+                    const bool skip = valid && !gated;
+                    float o[NOUT];
+#pragma unroll
+                    for (int m = 0; m < NOUT; m++) o[m] = skip ? 3.f * rec_s(r, m) : 0.f;
+                    expand_outputs(o, skip ? r.sc : 0.f, cx - r.com[0], cy - r.com[1], cz - r.com[2], eps2, f);
+                    __builtin_amdgcn_wave_barrier();
+                    if (listed > kApList - 64) {
+                        drain(listed);
+                        listed = 0;
+                    }
+                    cur = nxt;
+                    e_next = e_after;
+                }
+                if (bad) atomicOr(a.err, kErrIndex);
+                if (listed > 0) drain(listed);
+            }   // a malformed group was flagged by k_corr_box
+            wave_store_part(corr_target(a, g, it, p0, p1, q0, q1), lane, f, cx, cy, cz);
+        }
     }
 }
 
@@ -1895,32 +2244,58 @@ int otoo_correction(otoo_ctx* c, int32_t kind, otoo_mlp* m, int32_t n, const flo
     pl.n_items = (n_pairs + kCorrSeg - 1) / kCorrSeg;
     const size_t part_bytes = align256(sizeof(float) * kCorrStride * (size_t)std::max<int64_t>(pl.n_items, 1));
     const size_t box_bytes = align256(sizeof(float4) * (size_t)n_groups);
-    int rc = ensure_corr_scratch(c, 2 * part_bytes + box_bytes);
+    const bool split = kind == OTOO_CORR_MLP && c->tune.net_kernel == 2;   // network pass + expansion pass
+    const size_t qbuf_bytes = split ? align256(sizeof(float) * kQRow * (size_t)std::max<int64_t>(n_pairs, 1)) : 0;
+    const size_t crec_bytes = split ? align256(2 * sizeof(uint4) * (size_t)std::max<int32_t>(n_cells, 1)) : 0;
+    int rc = ensure_corr_scratch(c, 2 * part_bytes + box_bytes + qbuf_bytes + crec_bytes);
     if (rc) return rc;
     pl.part_l = static_cast<float*>(c->corr_buf);
     pl.part_r = reinterpret_cast<float*>(static_cast<char*>(c->corr_buf) + part_bytes);
     pl.box = reinterpret_cast<float4*>(static_cast<char*>(c->corr_buf) + 2 * part_bytes);
+    float* qbuf = split ? reinterpret_cast<float*>(static_cast<char*>(c->corr_buf) + 2 * part_bytes + box_bytes)
+                        : nullptr;
+    pl.crec = split ? reinterpret_cast<uint4*>(static_cast<char*>(c->corr_buf) + 2 * part_bytes + box_bytes + qbuf_bytes)
+                    : nullptr;
     // resident workgroups per CU of each kernel (the same for every device of this build)
-    static std::atomic<int> occ[3] = {0, 0, 0};
-    const int which = kind == OTOO_CORR_PAIRS ? 0 : kind == OTOO_CORR_QUAD ? 1 : 2;
-    int per_cu = occ[which].load(std::memory_order_relaxed);
-    if (!per_cu) {
-        const void* fn = which == 0   ? reinterpret_cast<const void*>(&k_corr_wave<kCorrPairs>)
-                         : which == 1 ? reinterpret_cast<const void*>(&k_corr_wave<kCorrQuad>)
-                                      : reinterpret_cast<const void*>(&k_corr_net);
-        HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0));
-        per_cu = std::max(per_cu, 1);
-        occ[which].store(per_cu, std::memory_order_relaxed);
+    static std::atomic<int> occ[5] = {0, 0, 0, 0, 0};
+    auto resident = [&](int which, const void* fn, int& per_cu) -> int {
+        per_cu = occ[which].load(std::memory_order_relaxed);
+        if (!per_cu) {
+            HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0));
+            per_cu = std::max(per_cu, 1);
+            occ[which].store(per_cu, std::memory_order_relaxed);
+        }
+        return OTOO_OK;
+    };
+    const int which = kind == OTOO_CORR_PAIRS ? 0 : kind == OTOO_CORR_QUAD ? 1 : split ? 3 : 2;
+    const void* fn = which == 0   ? reinterpret_cast<const void*>(&k_corr_wave<kCorrPairs>)
+                     : which == 1 ? reinterpret_cast<const void*>(&k_corr_wave<kCorrQuad>)
+                     : which == 2 ? reinterpret_cast<const void*>(&k_corr_net)
+                                  : reinterpret_cast<const void*>(&k_corr_apply);
+    int per_cu = 0, per_cu_net = 0;
+    rc = resident(which, fn, per_cu);
+    if (rc) return rc;
+    if (split) {
+        rc = resident(4, reinterpret_cast<const void*>(&k_corr_gnet), per_cu_net);
+        if (rc) return rc;
     }
     hipLaunchKernelGGL(k_corr_box, dim3((unsigned)(((int64_t)n_groups + 3) / 4)), dim3(256), 0, c->stream, ca);
     const int64_t item_blocks = std::max<int64_t>((pl.n_items + 3) / 4, 1);
     const dim3 grid((unsigned)std::min<int64_t>((int64_t)per_cu * c->num_cu, item_blocks));
-    if (which == 0)
+    if (which == 0) {
         hipLaunchKernelGGL(k_corr_wave<kCorrPairs>, grid, dim3(256), 0, c->stream, ca);
-    else if (which == 1)
+    } else if (which == 1) {
         hipLaunchKernelGGL(k_corr_wave<kCorrQuad>, grid, dim3(256), 0, c->stream, ca);
-    else
+    } else if (which == 2) {
         hipLaunchKernelGGL(k_corr_net, grid, dim3(256), 0, c->stream, ca);
+    } else {
+        const dim3 grid_net((unsigned)std::min<int64_t>((int64_t)per_cu_net * c->num_cu, item_blocks));
+        if (n_cells > 0)
+            hipLaunchKernelGGL(k_corr_cells, dim3((unsigned)std::min<int64_t>(4LL * c->num_cu, ((int64_t)n_cells + 255) / 256)),
+                               dim3(256), 0, c->stream, ca);
+        hipLaunchKernelGGL(k_corr_gnet, grid_net, dim3(256), 0, c->stream, ca, qbuf);
+        hipLaunchKernelGGL(k_corr_apply, grid, dim3(256), 0, c->stream, ca, static_cast<const float*>(qbuf));
+    }
     const int merge_blocks = (int)std::min<int64_t>(4LL * c->num_cu, ((int64_t)n_groups + 255) / 256);
     hipLaunchKernelGGL(k_corr_merge, dim3(merge_blocks), dim3(256), 0, c->stream, ca);
     HIP_TRY(c, hipGetLastError());

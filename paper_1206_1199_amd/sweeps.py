@@ -13,14 +13,16 @@ paper's models are Delta^-3/4 for the cost and Delta^1/4 for the error.
     python -m paper_1206_1199_amd.sweeps delta [--dist uniform|plummer] [--n N] [--eps E]
     python -m paper_1206_1199_amd.sweeps theta [--dist ...]
     python -m paper_1206_1199_amd.sweeps sph [--dist polytrope|uniform|plummer] [--n N] [--k K]
-    python -m paper_1206_1199_amd.sweeps corr [--dist plummer] [--n N] [--values THETA] [--gates G,...]
+    python -m paper_1206_1199_amd.sweeps corr [--dist plummer|cube] [--n N] [--values THETA] [--gates G,...]
+                                              [--group-mode chunk|cell] [--net-kernels K,...]
 
 The sph sweep times the SPH neighbour walk and the gather sums (density,
 q = m) with neighbour radii from the K-th nearest neighbour, for each g_max.
 The corr sweep times the cell-correction passes on the lists of one opening
-angle: the textbook quadrupole and the network at each gate (the network's
-initial parameters: the gate depends on the features only, so the cost is
-that of a trained network).
+angle: the textbook quadrupole and the network at each gate and with each
+network kernel (the network's initial parameters: the gate depends on the
+features only, so the cost is that of a trained network).  The cube
+distribution is the GRF cube of (N^(1/3))^3 particles.
 
 One JSON object per setting on stdout; a summary object last.
 """
@@ -33,7 +35,7 @@ import time
 
 import numpy as np
 
-from . import GROUP_CHUNK, MAC_ABSOLUTE, MAC_BH, Context, DeviceLists, Tree
+from . import GROUP_CELL, GROUP_CHUNK, MAC_ABSOLUTE, MAC_BH, Context, DeviceLists, Tree
 
 DELTAS = (1.0, 0.3, 0.1, 0.03, 0.01, 0.003, 0.001, 3e-4)
 THETAS = (0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9)
@@ -170,11 +172,17 @@ def run_sph(dist: str, n: int, g_list, k: int, reps: int, seed: int, emit=print)
     return rows
 
 
-def run_corr(dist: str, n: int, g_list, theta: float, gates, eps: float, reps: int, seed: int, emit=print):
+def run_corr(dist: str, n: int, g_list, theta: float, gates, eps: float, reps: int, seed: int, emit=print,
+             group_mode: int = GROUP_CHUNK, net_kernels=(0,)):
     import torch
     import synth
     from . import CORR_MLP, CORR_QUAD, learned
-    pos, m = synth.plummer(n, seed=seed) if dist == "plummer" else synth.uniform_sphere(n, seed=seed)
+    if dist == "plummer":
+        pos, m = synth.plummer(n, seed=seed)
+    elif dist == "cube":
+        pos, m = synth.grf_cube(int(round(n ** (1.0 / 3.0))), seed=seed)
+    else:
+        pos, m = synth.uniform_sphere(n, seed=seed)
     tree = Tree(pos, m, n_crit=16)
     _, pos32, mass32, cm = tree.export(12)
     ctx = Context(0)
@@ -195,14 +203,21 @@ def run_corr(dist: str, n: int, g_list, theta: float, gates, eps: float, reps: i
         ctx.check()
         return e0.elapsed_time(e1) / reps
 
+    old = ctx.tuning()
     for g_max in g_list:
-        d = DeviceLists.from_host(pos32, mass32, tree.walk(theta=theta, g_max=g_max), cm, "cuda:0")
+        d = DeviceLists.from_host(pos32, mass32, tree.walk(theta=theta, g_max=g_max, group_mode=group_mode), cm,
+                                  "cuda:0")
         out = ctx.correction(d, CORR_QUAD, eps)
-        row = {"corr": dist, "n": len(m), "theta": theta, "g_max": g_max, "pairs": d.n_pairs,
+        row = {"corr": dist, "n": len(m), "theta": theta, "g_max": g_max,
+               "group_mode": "chunk" if group_mode == GROUP_CHUNK else "cell", "pairs": d.n_pairs,
                "quad_ms": timed(lambda: ctx.correction(d, CORR_QUAD, eps, out=out))}
-        for gate in gates:
-            net.set_gate(gate)
-            row[f"net_ms_gate_{gate:g}"] = timed(lambda: ctx.correction(d, CORR_MLP, eps, net=net, out=out))
+        for kernel in net_kernels:
+            ctx.set_tuning(net_kernel=kernel)
+            for gate in gates:
+                net.set_gate(gate)
+                key = f"net_ms_gate_{gate:g}" if len(net_kernels) == 1 else f"net{kernel}_ms_gate_{gate:g}"
+                row[key] = timed(lambda: ctx.correction(d, CORR_MLP, eps, net=net, out=out))
+        ctx.set_tuning(net_kernel=old.net_kernel)
         rows.append(row)
         emit(json.dumps(row))
         sys.stdout.flush()
@@ -212,7 +227,7 @@ def run_corr(dist: str, n: int, g_list, theta: float, gates, eps: float, reps: i
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("kind", choices=["delta", "theta", "sph", "corr"])
-    ap.add_argument("--dist", choices=["uniform", "plummer", "polytrope"], default="uniform")
+    ap.add_argument("--dist", choices=["uniform", "plummer", "polytrope", "cube"], default="uniform")
     ap.add_argument("--k", type=int, default=50, help="sph: neighbours inside h")
     ap.add_argument("--n", type=int, default=8000 * 1024)
     ap.add_argument("--eps", type=float, default=1e-3)
@@ -222,11 +237,15 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--gates", default="0.4,0", help="corr: network gates (l/|d| thresholds)")
+    ap.add_argument("--group-mode", choices=["chunk", "cell"], default="chunk", help="corr: how groups are formed")
+    ap.add_argument("--net-kernels", default="", help="corr: network kernels to time (default: the context's)")
     a = ap.parse_args(argv)
     if a.kind == "corr":
         theta = float(a.values) if a.values else 0.9
+        kernels = [int(k) for k in a.net_kernels.split(",")] if a.net_kernels else [Context(0).tuning().net_kernel]
         run_corr(a.dist, a.n, [int(g) for g in a.g_max.split(",")], theta, [float(x) for x in a.gates.split(",")],
-                 a.eps, a.reps, a.seed)
+                 a.eps, a.reps, a.seed, group_mode=GROUP_CHUNK if a.group_mode == "chunk" else GROUP_CELL,
+                 net_kernels=kernels)
         return
     if a.kind == "sph":
         run_sph(a.dist, a.n, [int(g) for g in a.g_max.split(",")], a.k, a.reps, a.seed)

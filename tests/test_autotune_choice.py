@@ -20,7 +20,7 @@ class _FakeContext:
     def sync_stream(self):
         pass
 
-    def autotune(self, tree, eps, choices, schedules, reps=10, theta=0.5):
+    def autotune(self, tree, eps, choices, schedules, reps=10, theta=0.5, corr_kind=-1, net=None):
         assert self.ms.shape == (len(choices), len(schedules))
         return self.ms, self.inter, None, None, None
 
@@ -41,3 +41,20 @@ def test_tie_goes_to_the_higher_interaction_rate():
     assert _pick([[1.70, 1.638], [1.70, 1.637]], [5.2e9, 4.5e9]) == ("chunk", 64, 16384)
     # and inside one group choice the faster schedule of the two
     assert _pick([[1.640, 1.638], [1.90, 1.90]], [5.2e9, 4.5e9]) == ("chunk", 64, 16384)
+
+
+def test_corrected_step_has_its_own_cache_entry(tmp_path, monkeypatch):
+    """A corrected mode reads its own entry, falls back to the plain force's,
+    and then to the defaults."""
+    monkeypatch.setattr(at, "device_key", lambda device=0: "gfx950:256cu")
+    path = str(tmp_path / "cache.json")
+    plain = dict(group_mode="chunk", g_max=32, chunk=2048, blocks_per_cu=8, lpt=0, tile=512)
+    learned = dict(group_mode="cell", g_max=256, chunk=4096, blocks_per_cu=6, lpt=1, tile=256)
+    assert at.cached_schedule("cube16m", path=path, mode="learned") == (at.DEFAULT_SCHEDULE, "defaults")
+    at.save_cache(at.cache_key("cube16m"), plain, path)
+    sched, source = at.cached_schedule("cube16m", path=path, mode="learned")
+    assert sched == plain and source == "autotune cache (plain force)"
+    at.save_cache(at.cache_key("cube16m", "learned"), learned, path)
+    sched, source = at.cached_schedule("cube16m", path=path, mode="learned")
+    assert sched == learned and source == "autotune cache (learned step)"
+    assert at.cached_schedule("cube16m", path=path) == (plain, "autotune cache")

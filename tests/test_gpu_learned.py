@@ -363,7 +363,7 @@ def test_training_reduces_loss_and_helps_forces(env, trained, case):
         assert e_l < e_q
 
 
-@pytest.mark.parametrize("net_kernel,gate", [(0, 0.0), (1, 0.0), (0, 0.4), (1, 0.4)])
+@pytest.mark.parametrize("net_kernel,gate", [(0, 0.0), (1, 0.0), (2, 0.0), (0, 0.4), (1, 0.4), (2, 0.4)])
 def test_fused_learned_correction_matches_oracle(env, net_kernel, gate):
     """The fused per-group learned correction (register-resident network, or
     the LDS-staged one) and the force, against the oracle's list force with
@@ -465,7 +465,7 @@ def test_learned_cube_16m_captured(env, trained):
 
 
 @pytest.mark.parametrize("gate", [0.0, 0.3])
-@pytest.mark.parametrize("net_kernel", [0, 1])
+@pytest.mark.parametrize("net_kernel", [0, 1, 2])
 def test_queue_rounds_on_long_lists(env, gate, net_kernel):
     """Groups of 256 at theta 0.5 hold thousands of cells, so the register-
     resident kernel's queue of gated pairs runs many rounds and carries a
