@@ -238,6 +238,25 @@ int otoo_force(otoo_ctx* ctx, int32_t n, const float* pos, const float* mass, in
                int32_t n_cells, const float* cell_mom, int32_t cell_stride, float eps, const float* gcorr,
                float* out_acc, double* out_pot);
 
+/* otoo_force without any device allocation, for callers that cannot
+ * allocate device memory: code under stream or graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments, launches and
+ * results (bitwise) as otoo_force with the context's tuning; the scratch is
+ * a fixed array of OTOO_NOALLOC_SCRATCH_BYTES in the library's device code,
+ * one per GPU (located once per device by otoo_create), instead of the
+ * context's buffer.  The context's 4 KiB counter block, made by otoo_create,
+ * is used as by otoo_force.  Every call on one GPU shares that array, which
+ * keeps the last call's contents (nothing in it needs to start at zero):
+ * calls that overlap on one GPU -- from two streams or two contexts -- race.
+ * EINVAL, before anything is enqueued, when the call's scratch (the size
+ * otoo_force_plan reports) exceeds the array, and when the context's debug
+ * validation is on (it copies the lists to the host). */
+#define OTOO_NOALLOC_SCRATCH_BYTES (128 * 1024 * 1024)
+int otoo_force_noalloc(otoo_ctx* ctx, int32_t n, const float* pos, const float* mass, int32_t n_groups,
+                       const int32_t* group_off, int64_t n_entries, const int64_t* list_off,
+                       const int32_t* list_idx, int32_t n_cells, const float* cell_mom, int32_t cell_stride,
+                       float eps, const float* gcorr, float* out_acc, double* out_pot);
+
 /* Host-only plan of an otoo_force call (no device call, no context): the
  * same size checks otoo_force makes before it touches the device, and the
  * bytes of context scratch such a call needs (unified source table, work

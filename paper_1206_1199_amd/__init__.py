@@ -34,6 +34,7 @@ MAX_GROUP = 256
 THETA_LIMIT = 1.15
 MAC_BH, MAC_ABSOLUTE = 0, 1
 GROUP_CHUNK, GROUP_CELL = 0, 1
+NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024   # OTOO_NOALLOC_SCRATCH_BYTES: otoo_force_noalloc's array per GPU
 CORR_PAIRS, CORR_QUAD, CORR_MLP = 0, 1, 2
 CORR_STRIDE = 24
 
@@ -95,7 +96,7 @@ class GroupChoice(ctypes.Structure):
 EXPORTED = [
     "otoo_tree_build", "otoo_tree_free", "otoo_tree_info", "otoo_tree_export", "otoo_tree_cells",
     "otoo_tree_links", "otoo_tree_walk", "otoo_tree_groups", "otoo_tree_walk_range", "otoo_tree_walk_sph", "otoo_lists_free", "otoo_create", "otoo_destroy",
-    "otoo_set_stream", "otoo_last_error", "otoo_set_tuning", "otoo_get_tuning", "otoo_force",
+    "otoo_set_stream", "otoo_last_error", "otoo_set_tuning", "otoo_get_tuning", "otoo_force", "otoo_force_noalloc",
     "otoo_check", "otoo_enable_timing", "otoo_last_timing", "otoo_graph_capture", "otoo_graph_launch",
     "otoo_autotune", "otoo_autotune_step", "otoo_set_scratch_limit", "otoo_force_plan", "otoo_scratch_generation",
     "otoo_quad_exact", "otoo_correction", "otoo_direct", "otoo_sph_sum", "otoo_mlp_num_params", "otoo_mlp_create", "otoo_mlp_destroy", "otoo_mlp_set_params", "otoo_mlp_set_gate",
@@ -137,6 +138,7 @@ def lib():
         "otoo_force_plan": ([I32, I32, I64, I32, I32, I32, ctypes.POINTER(I64)], I32),
         "otoo_scratch_generation": ([P, ctypes.POINTER(I64)], I32),
         "otoo_force": ([P, I32, P, P, I32, P, I64, P, P, I32, P, I32, F, P, P, P], I32),
+        "otoo_force_noalloc": ([P, I32, P, P, I32, P, I64, P, P, I32, P, I32, F, P, P, P], I32),
         "otoo_correction": ([P, I32, P, I32, P, I32, P, I64, P, P, I64, P, I32, P, I32, F, P, P], I32),
         "otoo_quad_exact": ([P, I32, I32, I64, P, P, I64, P, I32, P, I32, P], I32),
         "otoo_direct": ([P, I32, P, P, I32, P, F, P, P], I32),
@@ -510,6 +512,14 @@ class Context:
         """
         acc, pot = out if out is not None else self.outputs(d.n)
         self._raise(lib().otoo_force(*self._args(d, eps, acc, pot, gcorr)), "otoo_force")
+        return acc, pot
+
+    def force_noalloc(self, d: DeviceLists, eps: float, out, gcorr=None):
+        """otoo_force_noalloc: the force with the library's fixed per-GPU
+        scratch array instead of the context's (no device allocation; the
+        outputs ``out`` = (acc, pot) must be given)."""
+        acc, pot = out
+        self._raise(lib().otoo_force_noalloc(*self._args(d, eps, acc, pot, gcorr)), "otoo_force_noalloc")
         return acc, pot
 
     def correction(self, d: DeviceLists, kind: int, eps: float, net=None, corr=None, out=None):

@@ -25,6 +25,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -649,6 +650,36 @@ __global__ __launch_bounds__(256) void k_reduce(const float4* __restrict__ src, 
 
 namespace {
 
+}  // namespace
+
+// Scratch of otoo_force_noalloc: a file-scope device array, one copy per
+// GPU, held from the library's load until the process ends.  Host code
+// never passes this name to a kernel (on the host it is only a stand-in):
+// it uses the device address that hipGetSymbolAddress returns for the
+// current device, looked up once per device by otoo_create.
+static __device__ __align__(256) unsigned char scratch[OTOO_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device` (which must be current).
+hipError_t noalloc_scratch(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_noalloc_ptr[device] = p;
+    }
+    *out = g_noalloc_ptr[device];
+    return hipSuccess;
+}
+
 struct Layout {
     size_t src, item_base, part_base, block_tot, items, order, split, partial, total;
     int64_t item_cap, part_cap;
@@ -777,10 +808,12 @@ int validate_csr(otoo_ctx* c, const Call& a) {
     return OTOO_OK;
 }
 
-int enqueue(otoo_ctx* c, const Call& a, bool allow_timing) {
+// Launch the force path with its scratch at `buf` (the context's buffer,
+// or the no-allocation array), which holds at least the call's layout.
+int enqueue(otoo_ctx* c, const Call& a, bool allow_timing, void* buf) {
     const otoo_tuning& tu = c->tune;
     const Layout L = plan_layout(a.n, a.n_groups, a.n_entries, a.n_cells, tu.chunk);
-    char* base = static_cast<char*>(c->buf);
+    char* base = static_cast<char*>(buf);
     float4* src = reinterpret_cast<float4*>(base + L.src);
     int64_t* item_base = reinterpret_cast<int64_t*>(base + L.item_base);
     int64_t* part_base = reinterpret_cast<int64_t*>(base + L.part_base);
@@ -902,6 +935,12 @@ int otoo_create(otoo_ctx** out, int32_t device) {
         (void)hipGetLastError();
         return OTOO_EHIP;
     }
+    void* na = nullptr;
+    if (noalloc_scratch(device, &na) != hipSuccess) {   // device < 64: the table's size
+        (void)hipGetLastError();
+        na = nullptr;   // otoo_force_noalloc then reports the missing array
+    }
+    c->noalloc = na;
     c->num_cu = cu;
     c->meta = static_cast<Meta*>(small);
     c->errflag = reinterpret_cast<int32_t*>(static_cast<char*>(small) + 2048);
@@ -1003,7 +1042,33 @@ int otoo_force(otoo_ctx* c, int32_t n, const float* pos, const float* mass, int3
     HIP_TRY(c, hipSetDevice(c->device));
     int rc = prepare(c, a);
     if (rc) return rc;
-    return enqueue(c, a, true);
+    return enqueue(c, a, true, c->buf);
+}
+
+int otoo_force_noalloc(otoo_ctx* c, int32_t n, const float* pos, const float* mass, int32_t n_groups,
+                       const int32_t* group_off, int64_t n_entries, const int64_t* list_off,
+                       const int32_t* list_idx, int32_t n_cells, const float* cell_mom, int32_t cell_stride,
+                       float eps, const float* gcorr, float* out_acc, double* out_pot) {
+    if (!c) return OTOO_EINVAL;
+    c->err.clear();
+    Call a{n, pos, mass, n_groups, group_off, n_entries, list_off, list_idx, n_cells, cell_mom, cell_stride, eps,
+           gcorr, out_acc, out_pot};
+    int rc = check_args(c, a);
+    if (rc) return rc;
+    Layout L;
+    rc = plan_call(c, a.n, a.n_groups, a.n_entries, a.n_cells, c->tune.chunk,
+                   (int64_t)c->num_cu * c->tune.blocks_per_cu, L);
+    if (rc) return rc;
+    if (L.total > (size_t)OTOO_NOALLOC_SCRATCH_BYTES)
+        return fail(c, OTOO_EINVAL,
+                    "this call needs %zu bytes of scratch; otoo_force_noalloc holds %zu per GPU (use otoo_force, "
+                    "or a longer chunk)",
+                    L.total, (size_t)OTOO_NOALLOC_SCRATCH_BYTES);
+    if (c->tune.debug_validate)
+        return fail(c, OTOO_EINVAL, "debug validation copies the lists to the host; it is off for otoo_force_noalloc");
+    if (!c->noalloc) return fail(c, OTOO_EHIP, "the scratch array of device %d could not be located", c->device);
+    HIP_TRY(c, hipSetDevice(c->device));
+    return enqueue(c, a, true, c->noalloc);
 }
 
 int otoo_quad_exact(otoo_ctx* c, int32_t n, int32_t n_groups, int64_t n_entries, const int64_t* list_off,
@@ -1082,7 +1147,7 @@ int otoo_graph_capture(otoo_ctx* c, int32_t n, const float* pos, const float* ma
     hipStream_t user = c->stream;
     c->stream = c->cap_stream;
     HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    rc = enqueue(c, a, false);
+    rc = enqueue(c, a, false, c->buf);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     c->stream = user;

@@ -199,6 +199,9 @@ struct otoo_ctx {
     size_t sph_bytes = 0;
     void* corr_buf = nullptr;
     size_t corr_bytes = 0;
+    // device address of the no-allocation entry point's scratch array on
+    // this context's device (shared by every context on that device)
+    void* noalloc = nullptr;
 };
 
 

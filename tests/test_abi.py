@@ -77,3 +77,19 @@ def test_force_plan_checks_the_queue_range_on_the_host():
     # the scratch holds at least the unified source table
     n, nc = 16384, 2500
     assert otoo.force_plan(n, 256, 400000, nc, 1024, 2048) >= 16 * (n + nc)
+
+
+def test_noalloc_entry_point_checks_and_limit():
+    """otoo_force_noalloc rejects a null context like otoo_force; its array
+    size in the header is the binding's; and the scratch plan of the shapes
+    it serves fits (a 2^20 Plummer-sized call) while a 4M-particle call does
+    not (otoo_force_noalloc refuses such a call before it enqueues)."""
+    lib = otoo.lib()
+    assert lib.otoo_force_noalloc(None, 1, None, None, 1, None, 0, None, None, 0, None, 4, 0.1, None, None,
+                                  None) == otoo.EINVAL
+    txt = open(os.path.join(ROOT, "include", "otoo.h")).read()
+    m = re.search(r"#define OTOO_NOALLOC_SCRATCH_BYTES \((\d+) \* (\d+) \* (\d+)\)", txt)
+    assert m and int(m.group(1)) * int(m.group(2)) * int(m.group(3)) == otoo.NOALLOC_SCRATCH_BYTES
+    # Plummer 2^20, groups of 64, ~8e7 list entries, ~2.4e5 cells, chunk 16384, 8 workgroups per CU
+    assert otoo.force_plan(1 << 20, 1 << 14, 81_386_028, 241_881, 16384, 2048) <= otoo.NOALLOC_SCRATCH_BYTES
+    assert otoo.force_plan(1 << 22, 1 << 16, 330_000_000, 970_000, 16384, 2048) > otoo.NOALLOC_SCRATCH_BYTES
