@@ -638,21 +638,36 @@ __device__ __forceinline__ void expand_outputs(const float o[NOUT], float sc, fl
     quad_expand_add(dx, dy, dz, Q, eps2, f);
 }
 
-// Wave-level reductions by butterfly (fixed order; lane 0's value is used).
+// Wave-level reductions on the VALU through DPP lane moves, in a fixed
+// order, the result the same in every lane: within each row of 16 lanes the
+// partner lanes xor 1 and xor 2 (quad permutes), then the half-row and row
+// mirrors; the four row totals are then combined through the broadcasts of
+// lanes 15 and 31 into rows 1 and 3, and 2 and 3, and lane 63's value is
+// read into a scalar register.  `id` is the operation's identity, taken by
+// the rows a broadcast does not write.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_move(float old, float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old), __builtin_bit_cast(int, x),
+                                                                  CTRL, ROW_MASK, 0xF, false));
+}
+template <typename Op>
+__device__ __forceinline__ float wave_reduce(float v, float id, Op op) {
+    v = op(v, dpp_move<0xB1, 0xF>(id, v));    // quad_perm [1, 0, 3, 2]: lane xor 1
+    v = op(v, dpp_move<0x4E, 0xF>(id, v));    // quad_perm [2, 3, 0, 1]: lane xor 2
+    v = op(v, dpp_move<0x141, 0xF>(id, v));   // row_half_mirror: the other quad of each half-row
+    v = op(v, dpp_move<0x140, 0xF>(id, v));   // row_mirror: the other half of each row
+    v = op(v, dpp_move<0x142, 0xA>(id, v));   // row_bcast:15 into rows 1 and 3
+    v = op(v, dpp_move<0x143, 0xC>(id, v));   // row_bcast:31 into rows 2 and 3
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    return wave_reduce(v, 0.f, [](float x, float y) { return x + y; });
 }
 __device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o));
-    return v;
+    return wave_reduce(v, INFINITY, [](float x, float y) { return fminf(x, y); });
 }
 __device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-    return v;
+    return wave_reduce(v, -INFINITY, [](float x, float y) { return fmaxf(x, y); });
 }
 
 // Geometry of group g for one wave: centre and half-diagonal of the
@@ -671,8 +686,8 @@ __device__ __forceinline__ bool wave_group_box(const CorrArgs& a, int g, int lan
                 hi[k] = fmaxf(hi[k], x);
             }
     for (int k = 0; k < 3; k++) {
-        lo[k] = __shfl(wave_min(lo[k]), 0);
-        hi[k] = __shfl(wave_max(hi[k]), 0);
+        lo[k] = wave_min(lo[k]);
+        hi[k] = wave_max(hi[k]);
     }
     cx = 0.5f * (lo[0] + hi[0]);
     cy = 0.5f * (lo[1] + hi[1]);
@@ -711,13 +726,12 @@ __device__ __forceinline__ void wave_store_part(float* out, int lane, float f[kC
                                                 float cz) {
 #pragma unroll
     for (int k = 0; k < kCorrTerms; k++) f[k] = wave_sum(f[k]);
-    if (lane == 0) {
+    static_assert(kCorrTerms == 20 && kCorrStride == 24, "row layout");
+    if (lane == 0) {   // rows are 96 bytes: six 16-byte stores
+        float4* o4 = reinterpret_cast<float4*>(out);
 #pragma unroll
-        for (int k = 0; k < kCorrTerms; k++) out[k] = f[k];
-        out[kCorrTerms] = cx;
-        out[kCorrTerms + 1] = cy;
-        out[kCorrTerms + 2] = cz;
-        out[kCorrTerms + 3] = 0.f;
+        for (int k = 0; k < 5; k++) o4[k] = make_float4(f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]);
+        o4[5] = make_float4(cx, cy, cz, 0.f);
     }
 }
 
