@@ -245,59 +245,55 @@ def train_network(ctx, log, train_steps, gate=0.4):
                  "val_loss_textbook_quadrupole": quad_val}
 
 
-def workload_learned(ctx, net, training, log, tree, eps, theta, sched, sample, a_dir, reps):
+def workload_learned(ctx, net, training, log, tree, eps, theta, scheds, sample, a_dir, reps):
     """Plain, textbook-quadrupole and learned force on the benchmark workload
     itself, over opening angles around its own (plain at and below it, the
-    corrections at and above it), with its group mode and schedule.  Each
-    step (correction + force) is captured in one graph and replayed; errors
-    are against the direct sums of the sample."""
+    corrections at and above it), each mode with its own cached schedule
+    (``scheds[mode]``: the plain force's, or the corrected step's, whose best
+    group size differs).  Each step (correction + force) is captured in one
+    graph and replayed; errors are against the direct sums of the sample."""
     import torch
     import paper_1206_1199_amd as otoo
     from paper_1206_1199_amd import learned
-    mode_id = otoo.GROUP_CHUNK if sched["group_mode"] == "chunk" else otoo.GROUP_CELL
-    thetas = {"plain": [round(theta - 0.2, 2), round(theta - 0.1, 2), round(theta - 0.05, 2), theta],
-              "quad": [theta, round(theta + 0.05, 2), round(theta + 0.1, 2), round(theta + 0.2, 2)],
-              "learned": [theta, round(theta + 0.05, 2), round(theta + 0.1, 2), round(theta + 0.2, 2)]}
+    thetas = {"plain": [round(theta - 0.1, 2), round(theta - 0.05, 2), theta],
+              "quad": [theta, round(theta + 0.1, 2)],
+              "learned": [theta, round(theta + 0.05, 2), round(theta + 0.1, 2), round(theta + 0.15, 2)]}
+    old = ctx.tuning()
     rows = []
-    for th in sorted({t for v in thetas.values() for t in v}):
-        lists = tree.walk(theta=th, g_max=sched["g_max"], group_mode=mode_id)
-        d, _, _ = learned.device_tree_arrays(tree, lists)
-        out = ctx.outputs(d.n)
-        gc = torch.empty((d.n_groups, otoo.CORR_STRIDE), dtype=torch.float32, device="cuda:0")
+    try:
         for mode in ("plain", "quad", "learned"):
-            if th not in thetas[mode]:
-                continue
-
-            def step():
-                if mode == "learned":
-                    ctx.correction(d, otoo.CORR_MLP, eps, net=net, out=gc)
-                    ctx.force(d, eps, out=out, gcorr=gc)
-                elif mode == "quad":
-                    ctx.correction(d, otoo.CORR_QUAD, eps, out=gc)
-                    ctx.force(d, eps, out=out, gcorr=gc)
-                else:
-                    ctx.force(d, eps, out=out)
-            g = ctx.capture(step)
-            g.replay()
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(reps):
+            sc = scheds[mode]
+            ctx.set_tuning(chunk=sc["chunk"], blocks_per_cu=sc["blocks_per_cu"], lpt=sc["lpt"], tile=sc["tile"])
+            mode_id = otoo.GROUP_CHUNK if sc["group_mode"] == "chunk" else otoo.GROUP_CELL
+            for th in thetas[mode]:
+                lists = tree.walk(theta=th, g_max=sc["g_max"], group_mode=mode_id)
+                d, _, _ = learned.device_tree_arrays(tree, lists)
+                out = ctx.outputs(d.n)
+                gc = torch.empty((d.n_groups, otoo.CORR_STRIDE), dtype=torch.float32, device="cuda:0")
+                g = ctx.capture(make_step(ctx, d, eps, mode, net, out, gc))
                 g.replay()
-            e1.record()
-            torch.cuda.synchronize()
-            ctx.check()
-            err = rel_err(out[0].cpu().numpy()[sample], a_dir)
-            rows.append(dict(mode=mode, theta=th, ms=e0.elapsed_time(e1) / reps, interactions=lists.interactions,
-                             pairs=d.n_pairs, median_err=float(np.median(err)), p99_err=float(np.quantile(err, 0.99))))
-            log(f"  {mode:8s} theta {th:.2f} (graph replay): {rows[-1]['ms']:.3f} ms, "
-                f"median err {rows[-1]['median_err']:.2e}")
-        del d, out, gc
-        torch.cuda.empty_cache()
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    g.replay()
+                e1.record()
+                torch.cuda.synchronize()
+                ctx.check()
+                err = rel_err(out[0].cpu().numpy()[sample], a_dir)
+                rows.append(dict(mode=mode, theta=th, group_mode=sc["group_mode"], g_max=sc["g_max"],
+                                 ms=e0.elapsed_time(e1) / reps, interactions=lists.interactions, pairs=d.n_pairs,
+                                 median_err=float(np.median(err)), p99_err=float(np.quantile(err, 0.99))))
+                log(f"  {mode:8s} theta {th:.2f} {sc['group_mode']} {sc['g_max']} (graph replay): "
+                    f"{rows[-1]['ms']:.3f} ms, median err {rows[-1]['median_err']:.2e}")
+                del g, d, out, gc
+                torch.cuda.empty_cache()
+    finally:
+        ctx.set_tuning(chunk=old.chunk, blocks_per_cu=old.blocks_per_cu, lpt=old.lpt, tile=old.tile)
     ok = lambda mode: [r for r in rows if r["mode"] == mode and r["median_err"] <= 1e-3]
     best = {mode: (min(ok(mode), key=lambda r: r["ms"]) if ok(mode) else None) for mode in ("plain", "quad", "learned")}
-    res = {"training": training, "rows": rows, "best_at_1e-3": best}
+    res = {"rows": rows, "best_at_1e-3": best}
     if best["learned"] and best["plain"]:
         res["learned_speedup_vs_best_plain"] = best["plain"]["ms"] / best["learned"]["ms"]
     return res
@@ -781,6 +777,15 @@ def main():
         log(f"cpu baseline {res['cpu_baseline']['value']:.3f} Gint/s; parity {res['accuracy'].get('parity_acc_median')}")
     del d
     torch.cuda.empty_cache()
+    if mode == "learned" and not args.no_learned:   # the same comparison on the benchmark workload itself
+        try:
+            scheds = {"plain": at.cached_schedule(args.workload, 0, cache_path)[0],
+                      "quad": sched, "learned": sched}
+            res["learned_workload"] = workload_learned(ctx, net, training, log, tree, eps, theta, scheds, sample,
+                                                       a_dir, reps)
+        except Exception as e:  # the headline measurement stands on its own
+            res["learned_workload"] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"workload comparison failed: {e}")
     if args.workload != "plummer1m" and not args.no_plummer:
         try:
             res["plummer1m"] = plain_headline(ctx, log, args.steps, args.warmup, reps)
