@@ -208,25 +208,35 @@ def rel_err(a, ref):
 # ------------------------------------------------------------------ learned comparison
 
 
-def train_network(ctx, log, train_steps, gate=0.4):
-    """Train the correction network on the GPU on samples of seeded Plummer
-    walks (layers gated to pairs with l/n >= gate); returns (net, summary)."""
+def train_network(ctx, log, train_steps, gate=0.4, near=True):
+    """Train the correction network on the GPU on samples of seeded walks of
+    Plummer spheres and GRF cubes; returns (net, summary).  near: the samples are the near pairs
+    (l/|COM - c_g| >= gate), which the walks list first and which alone get
+    the correction, and the network runs on every pair it is given (device
+    gate 0); else the layers are gated to pairs with BF16 l/n >= gate and the
+    other pairs keep the textbook quadrupole."""
     import torch
     from paper_1206_1199_amd import learned
     eps = 0.005
     net = learned.Network(ctx)
     net.set_params(learned.init_params(0))
-    net.set_gate(gate)
-    keep = 3 if gate > 0 else 1          # draws per kept sample: the gate passes about a third of the pairs
+    net.set_gate(0.0 if near else gate)
+    keep = 3 if (gate > 0 and not near) else 1   # draws per kept sample: the gate passes about a third of the pairs
     rng = np.random.Generator(np.random.PCG64(12345))
     cfgs = [learned.SampleConfig("plummer", 16384, 1000 + k, 0.01, float(rng.uniform(0.5, 1.0)), 64, 40000 * keep)
             for k in range(20)]
     cfgs += [learned.SampleConfig("plummer", 1 << 20, 1020 + k, eps, float(rng.uniform(0.5, 1.0)),
                                   int(rng.choice([32, 64, 128])), 240000 * keep) for k in range(5)]
+    # GRF cubes of 64^3 and 128^3 particles (seeds 2000+, never the benchmark cube's), softening a
+    # quarter of the lattice spacing
+    cfgs += [learned.SampleConfig("grf_cube", ng ** 3, 2000 + k, 0.25 / ng, float(rng.uniform(0.6, 1.0)),
+                                  int(rng.choice([32, 64, 128])), 133000 * keep)
+             for k, ng in enumerate((64, 128, 64, 128, 64, 128, 64, 128))]
     t0 = time.perf_counter()
-    X, aux, eps_all = learned.make_training_set(ctx, net, cfgs, seed=1, gate=gate)
+    X, aux, eps_all = learned.make_training_set(ctx, net, cfgs, seed=1, gate=gate, near=near)
     Xv, auxv, epsv = learned.make_training_set(
-        ctx, net, [learned.SampleConfig("plummer", 1 << 20, 1100, eps, 0.9, 64, 100000 * keep)], seed=2, gate=gate)
+        ctx, net, [learned.SampleConfig("plummer", 1 << 20, 1100, eps, 0.9, 64, 100000 * keep)], seed=2, gate=gate,
+        near=near)
     t_data = time.perf_counter() - t0
     base_val = learned.zero_correction_loss(auxv)
     net.set_params(np.zeros(learned.N_PARAMS, np.float32))
@@ -238,26 +248,29 @@ def train_network(ctx, log, train_steps, gate=0.4):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     val = learned.evaluate_loss(net, Xv, auxv, epsv)
-    log(f"learned: {X.shape[0]} samples (gate {gate}) in {t_data:.1f} s, {train_steps} steps in {t_train:.1f} s, "
-        f"validation loss {val:.3e} (plain monopole {base_val:.3e}, textbook quadrupole {quad_val:.3e})")
-    return net, {"gate": gate, "samples": int(X.shape[0]), "steps": train_steps, "data_s": t_data,
+    log(f"learned: {X.shape[0]} samples (gate {gate}, {'near pairs' if near else 'all pairs'}) in {t_data:.1f} s, "
+        f"{train_steps} steps in {t_train:.1f} s, validation loss {val:.3e} (plain monopole {base_val:.3e}, textbook "
+        f"quadrupole {quad_val:.3e})")
+    return net, {"gate": gate, "pairs": "near" if near else "all", "samples": int(X.shape[0]), "steps": train_steps,
+                 "data_s": t_data,
                  "train_s": t_train, "val_loss": val, "val_loss_plain_monopole": base_val,
                  "val_loss_textbook_quadrupole": quad_val}
 
 
-def workload_learned(ctx, net, training, log, tree, eps, theta, scheds, sample, a_dir, reps):
+def workload_learned(ctx, net, training, log, tree, eps, theta, scheds, sample, a_dir, reps, near_ratio=0.0):
     """Plain, textbook-quadrupole and learned force on the benchmark workload
     itself, over opening angles around its own (plain at and below it, the
     corrections at and above it), each mode with its own cached schedule
     (``scheds[mode]``: the plain force's, or the corrected step's, whose best
     group size differs).  Each step (correction + force) is captured in one
-    graph and replayed; errors are against the direct sums of the sample."""
+    graph and replayed; errors are against the direct sums of the sample.
+    near_ratio > 0: the learned step corrects only the near cells (walks that
+    list them first)."""
     import torch
     import paper_1206_1199_amd as otoo
     from paper_1206_1199_amd import learned
-    thetas = {"plain": [round(theta - 0.1, 2), round(theta - 0.05, 2), theta],
-              "quad": [theta, round(theta + 0.1, 2)],
-              "learned": [theta, round(theta + 0.05, 2), round(theta + 0.1, 2), round(theta + 0.15, 2)]}
+    steps = lambda lo, hi: [round(theta + 0.05 * k, 2) for k in range(lo, hi + 1)]
+    thetas = {"plain": steps(-2, 0), "quad": steps(-2, 1), "learned": steps(0, 6)}
     old = ctx.tuning()
     rows = []
     try:
@@ -266,7 +279,8 @@ def workload_learned(ctx, net, training, log, tree, eps, theta, scheds, sample, 
             ctx.set_tuning(chunk=sc["chunk"], blocks_per_cu=sc["blocks_per_cu"], lpt=sc["lpt"], tile=sc["tile"])
             mode_id = otoo.GROUP_CHUNK if sc["group_mode"] == "chunk" else otoo.GROUP_CELL
             for th in thetas[mode]:
-                lists = tree.walk(theta=th, g_max=sc["g_max"], group_mode=mode_id)
+                lists = tree.walk(theta=th, g_max=sc["g_max"], group_mode=mode_id,
+                                  near_ratio=near_ratio if mode == "learned" else 0.0)
                 d, _, _ = learned.device_tree_arrays(tree, lists)
                 out = ctx.outputs(d.n)
                 gc = torch.empty((d.n_groups, otoo.CORR_STRIDE), dtype=torch.float32, device="cuda:0")
@@ -303,13 +317,16 @@ def learned_comparison(ctx, net, training, log, timing_reps):
     """Compare, on a held-out Plummer sphere (N = 2^20, seed 3, eps 0.005),
     plain theta = 0.5, plain at the largest theta with median error <= 1e-3,
     the textbook quadrupole and the learned correction, all timed per force
-    evaluation with the best of a few schedules per setting."""
+    evaluation with the best of a few schedules per setting.  A network
+    trained on near pairs corrects the near cells of walks that list them
+    first (near ratio = its training gate)."""
     import torch
     import synth
     import paper_1206_1199_amd as otoo
     from paper_1206_1199_amd import learned
     eps = 0.005
     gate = training["gate"]
+    near_ratio = gate if training.get("pairs") == "near" else 0.0
     pos, m = synth.plummer(1 << 20, seed=3)
     tree = otoo.Tree(pos, m, n_crit=16)
     perm, pos32, mass32, cm = tree.export(12)
@@ -333,8 +350,8 @@ def learned_comparison(ctx, net, training, log, timing_reps):
         ctx.check()
         return e0.elapsed_time(e1) / timing_reps
 
-    def run(theta, modes, g_max):
-        lists = tree.walk(theta=theta, g_max=g_max)
+    def run(theta, modes, g_max, near_ratio=0.0):
+        lists = tree.walk(theta=theta, g_max=g_max, near_ratio=near_ratio)
         d, _, _ = learned.device_tree_arrays(tree, lists)
         out = ctx.outputs(d.n)
         gc = torch.empty((d.n_groups, otoo.CORR_STRIDE), dtype=torch.float32, device="cuda:0")
@@ -369,11 +386,10 @@ def learned_comparison(ctx, net, training, log, timing_reps):
         rows += run(th, ("plain",), 32)
     for th in (0.5, 0.7, 0.75, 0.8):
         rows += run(th, ("plain",), 64)
-    for th in (0.8, 0.9):
-        rows += run(th, ("quad", "learned"), 32)
-    for g_max in (64, 128):
-        for th in (0.8, 0.85, 0.9, 0.95, 1.0):
-            rows += run(th, ("quad", "learned"), g_max)
+    for g_max, ths in ((32, (0.8, 0.9)), (64, (0.8, 0.85, 0.9, 0.95, 1.0)), (128, (0.8, 0.85, 0.9, 0.95, 1.0))):
+        for th in ths:
+            rows += run(th, ("quad",), g_max)
+            rows += run(th, ("learned",), g_max, near_ratio)
     for r in rows:
         log(f"  {r['mode']:8s} g_max {r['g_max']:3d} theta {r['theta']:.2f}: {r['ms']:.3f} ms, "
             f"median err {r['median_err']:.2e}, pairs {r['pairs']}")
@@ -381,7 +397,7 @@ def learned_comparison(ctx, net, training, log, timing_reps):
     best = {mode: (min(ok(mode), key=lambda r: r["ms"]) if ok(mode) else None) for mode in ("plain", "quad", "learned")}
     plain05 = min((r for r in rows if r["mode"] == "plain" and r["theta"] == 0.5), key=lambda r: r["ms"])
     res = {"workload": "Plummer N=1048576 seed=3 eps=0.005 (held out), error vs direct sum on 4096 particles",
-           "gate": gate, "training": training, "plain_theta_0.5": plain05, "best_at_1e-3": best, "rows": rows}
+           "gate": gate, "learned_pairs": "near" if near_ratio > 0 else "all", "training": training, "plain_theta_0.5": plain05, "best_at_1e-3": best, "rows": rows}
     if best["learned"]:
         res["learned_speedup_vs_plain_theta_0.5"] = plain05["ms"] / best["learned"]["ms"]
         if best["plain"]:
@@ -591,7 +607,12 @@ def main():
     ap.add_argument("--cache", default="", help="autotune cache file (default: the package's)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction comparison on Plummer")
     ap.add_argument("--no-plummer", action="store_true", help="skip the Plummer 2^20 plain headline")
-    ap.add_argument("--gate", type=float, default=0.4, help="learned correction: layers only where l/n >= gate")
+    ap.add_argument("--gate", type=float, default=0.4,
+                    help="learned correction: the near-cell ratio l/|COM - c_g| (pairs near), or the layers' "
+                         "l/n threshold (pairs all)")
+    ap.add_argument("--pairs", default="near", choices=["near", "all"],
+                    help="learned correction: network on the near cells only (walk lists them first; the far "
+                         "cells stay monopoles), or on every cell (gated, textbook quadrupole below the gate)")
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -623,12 +644,15 @@ def main():
     del pos
     ctx = otoo.Context(0)
 
+    near = args.pairs == "near"
+    near_ratio = args.gate if (mode == "learned" and near) else 0.0
     net, training, params = None, None, None
     if mode == "learned":
-        net, training = train_network(ctx, log, args.train_steps, gate=args.gate)
+        net, training = train_network(ctx, log, args.train_steps, gate=args.gate, near=near)
         params = net.get_params()[0]
 
-    key = at.cache_key(args.workload, mode)
+    sched_mode = mode if (mode != "learned" or near) else "learned-all"
+    key = at.cache_key(args.workload, sched_mode)
     cache_path = args.cache or at.DEFAULT_CACHE
     if args.autotune:
         grid = dict(at.GRID)
@@ -636,12 +660,12 @@ def main():
             grid["group"] = GROUPS[args.workload]
         kind = {"plain": -1, "quad": otoo.CORR_QUAD, "learned": otoo.CORR_MLP}[mode]
         best, table = at.autotune(tree, eps, theta, ctx, grid=grid, log=log, corr_kind=kind, net=net,
-                                  reps=args.autotune_reps)
+                                  reps=args.autotune_reps, near_ratio=near_ratio)
         at.save_cache(key, best, cache_path)
         sched = {k: best[k] for k in at.DEFAULT_SCHEDULE}
         source = "autotuned now" + ("" if mode == "plain" else f" ({mode} step)")
     else:
-        sched, source = at.cached_schedule(args.workload, 0, cache_path, mode=mode)
+        sched, source = at.cached_schedule(args.workload, 0, cache_path, mode=sched_mode)
     for k, v in (("g_max", args.g_max), ("group_mode", args.group_mode), ("chunk", args.chunk),
                  ("blocks_per_cu", args.blocks_per_cu), ("tile", args.tile)):
         if v:
@@ -654,7 +678,7 @@ def main():
 
     t2 = time.perf_counter()
     with marker("host walk"):
-        lists = tree.walk(theta=theta, g_max=sched["g_max"], group_mode=gmode)
+        lists = tree.walk(theta=theta, g_max=sched["g_max"], group_mode=gmode, near_ratio=near_ratio)
     t3 = time.perf_counter()
     perm, pos32, mass32, cm = tree.export(4 if mode == "plain" else 12)
     log(f"tree {1e3 * (t1 - t0):.0f} ms, walk {1e3 * (t3 - t2):.0f} ms: groups {lists.n_groups}, "
@@ -704,6 +728,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "correction": mode, "gate": args.gate if mode == "learned" else None,
+                   "corrected_pairs": ("near" if near else "all") if mode == "learned" else
+                   ("all" if mode == "quad" else None),
                    "n": int(len(m)), "groups": lists.n_groups, "list_entries": lists.n_entries,
                    "interactions": inter, "cell_pairs": n_pairs, "n_cells": tree.n_cells, "schedule": sched,
                    "schedule_source": source, "step": "correction pass + force in one captured graph"
@@ -768,7 +794,7 @@ def main():
             go = np.asarray(lists.group_off, np.int64)
             tgt = np.concatenate([np.arange(go[g], go[g + 1])[:4] for g in groups])
             base, (a_ref, p_ref) = cpu_baseline_corrected(pos32, mass32, lists, cm, eps, mode, params,
-                                                          args.gate, groups, tgt)
+                                                          0.0 if near else args.gate, groups, tgt)
             res["cpu_baseline"] = base
             ea, ep = rel_err(acc[tgt], a_ref), rel_err(pot[tgt], p_ref)
             res["accuracy"].update({"parity_acc_median": float(np.median(ea)), "parity_acc_max": float(ea.max()),
@@ -779,10 +805,12 @@ def main():
     torch.cuda.empty_cache()
     if mode == "learned" and not args.no_learned:   # the same comparison on the benchmark workload itself
         try:
+            has_quad = at.cache_key(args.workload, "quad") in at.load_cache(cache_path)
             scheds = {"plain": at.cached_schedule(args.workload, 0, cache_path)[0],
-                      "quad": sched, "learned": sched}
+                      "quad": at.cached_schedule(args.workload, 0, cache_path, mode="quad")[0] if has_quad else sched,
+                      "learned": sched}
             res["learned_workload"] = workload_learned(ctx, net, training, log, tree, eps, theta, scheds, sample,
-                                                       a_dir, reps)
+                                                       a_dir, reps, near_ratio)
         except Exception as e:  # the headline measurement stands on its own
             res["learned_workload"] = {"error": f"{type(e).__name__}: {e}"}
             log(f"workload comparison failed: {e}")
@@ -794,7 +822,7 @@ def main():
     if not args.no_learned:
         try:
             if net is None:
-                net, training = train_network(ctx, log, args.train_steps, gate=args.gate)
+                net, training = train_network(ctx, log, args.train_steps, gate=args.gate, near=near)
             res["learned"] = learned_comparison(ctx, net, training, log, reps)
         except Exception as e:  # the headline measurement stands on its own
             res["learned"] = {"error": f"{type(e).__name__}: {e}"}

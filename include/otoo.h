@@ -111,6 +111,10 @@ typedef struct {
     double m_limit;       /* ABSOLUTE: cells heavier than this are never accepted (INFINITY = off) */
     int32_t group_mode;   /* otoo_group_mode */
     int32_t g_max;        /* 1 .. OTOO_MAX_GROUP */
+    double near_ratio;    /* >= 0; > 0: each list's accepted cells are ordered near first -- those whose
+                             side l_c is at least near_ratio times the distance from their COM to the
+                             centre of the group's bounding box (FP64) -- then the others, each part
+                             ascending, and n_near counts the near ones; 0: no split (n_near = 0) */
 } otoo_walk_params;
 
 /* Interaction lists in CSR form, allocated by the library. */
@@ -123,6 +127,8 @@ typedef struct {
     int32_t* list_idx;      /* [n_entries]: j < n particle j, j >= n cell j - n */
     int32_t* n_cellent;     /* [n_groups]: the first n_cellent[g] entries of L_g are cells */
     float* group_box;       /* [n_groups][6]: bounding box lo xyz, hi xyz (FP32) */
+    int32_t* n_near;        /* [n_groups]: the first n_near[g] of those cells are the near ones
+                               (otoo_walk_params.near_ratio); all 0 without the split */
     void* impl;
 } otoo_lists;
 
@@ -487,7 +493,7 @@ int otoo_autotune(otoo_ctx* ctx, const otoo_tree* tree, const otoo_walk_params* 
  * or OTOO_CORR_MLP with the network mlp of this context) followed by the
  * force with that correction, captured on the context's stream; the cell
  * moments go with stride 12 and each group's cell-entry counts give the
- * pair offsets.  Larger groups cut the (group, cell) pairs the correction
+ * pair offsets (its near cells' counts when walk->near_ratio > 0).  Larger groups cut the (group, cell) pairs the correction
  * pays for and raise the interactions the force pays for, so the corrected
  * step has its own best group size.  corr_kind -1 is otoo_autotune.  The
  * context's tuning (net_kernel included) is restored afterwards.  EINVAL as

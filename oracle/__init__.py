@@ -101,9 +101,12 @@ def list_force(pos, mass, group_off, list_off, list_idx, cell_com, cell_mass, ep
                tgt=None, n_cellent=None, quad=None, expanded=False):
     """Interaction-list sums (see oracle.c).  Returns (acc[T,3], pot[T]).
 
-    With ``quad`` (one tensor per (group, cell) pair) the cells also act
-    through the quadrupole form, per target (``expanded=False``) or through a
-    second-order local expansion about the group's box centre (``expanded=True``).
+    With ``quad`` (one tensor per (group, cell) pair: the first
+    ``n_cellent[g]`` entries of each group's list, which must be cells) those
+    cells also act through the quadrupole form, per target
+    (``expanded=False``) or through a second-order local expansion about the
+    group's box centre (``expanded=True``); later cell entries act as
+    monopoles only.
     """
     lib = _load()
     pos = _f64(pos)

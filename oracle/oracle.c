@@ -194,10 +194,12 @@ static int64_t find_group(int64_t n_groups, const int64_t *group_off, int64_t i)
  * [group_off[g], group_off[g+1]) of particle indices; group g's list is
  * list_idx[list_off[g] .. list_off[g+1]).  Cells: cell_com[n_cells][3],
  * cell_mass[n_cells].  Optional quadrupole-form tensors: the first
- * n_cellent[g] entries of a group's list are its cells and the k-th of them
- * uses quad[(pair_off[g] + k) * 6 ...]; pass quad = NULL for monopole only.
- * Targets tgt[n_tgt] (NULL = all particles).  Returns 0, or -1 if an index
- * is out of range or a cell tensor is requested for a particle entry.
+ * n_cellent[g] entries of a group's list are cells that carry a tensor, the
+ * k-th of them quad[(pair_off[g] + k) * 6 ...]; cell entries after them
+ * (the far cells of a list whose near cells lead it) act as monopoles only;
+ * pass quad = NULL for monopole only.  Targets tgt[n_tgt] (NULL = all
+ * particles).  Returns 0, or -1 if an index is out of range or a cell
+ * tensor is requested for a particle entry.
  */
 int oracle_list_force(int64_t n, const double *pos, const double *mass,
                       int64_t n_groups, const int64_t *group_off,
@@ -231,14 +233,9 @@ int oracle_list_force(int64_t n, const double *pos, const double *mass,
             } else {
                 int64_t c = e - n;
                 pair_monopole(&pos[3 * i], &cell_com[3 * c], cell_mass[c], eps2, a, &phi);
-                if (quad) {
-                    if (kk >= n_cellent[g]) {
-                        bad = 1;
-                        continue;
-                    }
+                if (quad && kk < n_cellent[g])
                     pair_quadrupole(&pos[3 * i], &cell_com[3 * c], &quad[6 * (pair_off[g] + kk)],
                                     eps2, a, &phi);
-                }
             }
         }
         acc[3 * t + 0] = a[0];

@@ -25,6 +25,10 @@ to that box (0 inside).  Two acceptance criteria are provided:
             r_b = b_max/2 + sqrt(b_max^2/4 + sqrt(3 B2 / Delta)),
             and r_b = 2 * root side for cells heavier than m_limit (Sec. 3.3).
 An accepted cell is one list entry; an opened leaf contributes its particles.
+
+Near cells (the cells a learned correction is applied to; not in the paper):
+the accepted cells whose side is at least ``ratio`` times the distance from
+their COM to the centre of the group's bounding box.
 """
 from __future__ import annotations
 
@@ -181,3 +185,12 @@ def cell_groups(tree: Tree, g_max: int) -> list:
 
     visit(tree.root)
     return out
+
+
+def near_cells(cells: list, pos: np.ndarray, group_ids: np.ndarray, ratio: float) -> list:
+    """The accepted cells of a group that are near in the sense above:
+    side >= ratio * |COM - (lo + hi) / 2| with [lo, hi] the group's
+    bounding box, in FP64."""
+    p = np.asarray(pos, dtype=np.float64)[group_ids]
+    centre = 0.5 * (p.min(axis=0) + p.max(axis=0))
+    return [c for c in cells if c.side >= ratio * float(np.linalg.norm(c.com - centre))]

@@ -71,14 +71,16 @@ class OtooError(RuntimeError):
 
 class _WalkParams(ctypes.Structure):
     _fields_ = [("mac", ctypes.c_int32), ("theta", ctypes.c_double), ("delta", ctypes.c_double),
-                ("m_limit", ctypes.c_double), ("group_mode", ctypes.c_int32), ("g_max", ctypes.c_int32)]
+                ("m_limit", ctypes.c_double), ("group_mode", ctypes.c_int32), ("g_max", ctypes.c_int32),
+                ("near_ratio", ctypes.c_double)]
 
 
 class _Lists(ctypes.Structure):
     _fields_ = [("n_groups", ctypes.c_int32), ("n_entries", ctypes.c_int64), ("interactions", ctypes.c_int64),
                 ("group_off", ctypes.POINTER(ctypes.c_int32)), ("list_off", ctypes.POINTER(ctypes.c_int64)),
                 ("list_idx", ctypes.POINTER(ctypes.c_int32)), ("n_cellent", ctypes.POINTER(ctypes.c_int32)),
-                ("group_box", ctypes.POINTER(ctypes.c_float)), ("impl", ctypes.c_void_p)]
+                ("group_box", ctypes.POINTER(ctypes.c_float)), ("n_near", ctypes.POINTER(ctypes.c_int32)),
+                ("impl", ctypes.c_void_p)]
 
 
 class Tuning(ctypes.Structure):
@@ -185,6 +187,8 @@ class Lists:
     n_cellent: np.ndarray    # int32 [G]
     group_box: np.ndarray    # float32 [G, 6]
     interactions: int
+    n_near: np.ndarray = None   # int32 [G]: the near cells listed first (walks with near_ratio > 0)
+    near_ratio: float = 0.0
 
     @property
     def n_groups(self):
@@ -195,8 +199,15 @@ class Lists:
         return int(self.list_off[-1])
 
     @property
+    def n_pair(self):
+        """The (group, cell) pairs a cell correction covers, per group: the
+        near cells when the walk split them, else every cell entry (each
+        group's first entries)."""
+        return self.n_near if self.near_ratio > 0 else self.n_cellent
+
+    @property
     def pair_off(self):
-        return np.concatenate([[0], np.cumsum(self.n_cellent, dtype=np.int64)]).astype(np.int64)
+        return np.concatenate([[0], np.cumsum(self.n_pair, dtype=np.int64)]).astype(np.int64)
 
 
 class Tree:
@@ -256,12 +267,15 @@ class Tree:
         return nxt, more
 
     def walk(self, theta: float = 0.5, g_max: int | None = None, group_mode: int = GROUP_CHUNK, mac: int = MAC_BH,
-             delta: float = 0.01, m_limit: float = math.inf) -> Lists:
+             delta: float = 0.01, m_limit: float = math.inf, near_ratio: float = 0.0) -> Lists:
+        """Interaction lists; near_ratio > 0 lists each group's near cells
+        (side >= near_ratio x distance of the COM from the group's box centre)
+        first and makes them the lists' (group, cell) pairs."""
         p = _WalkParams(mac=mac, theta=theta, delta=delta, m_limit=m_limit, group_mode=group_mode,
-                        g_max=_g_max(g_max))
+                        g_max=_g_max(g_max), near_ratio=float(near_ratio))
         out = ctypes.POINTER(_Lists)()
         _check(lib().otoo_tree_walk(self._h, ctypes.byref(p), ctypes.byref(out)), "otoo_tree_walk")
-        return self._take_lists(out)
+        return self._take_lists(out, float(near_ratio))
 
     def n_groups(self, g_max: int | None = None, group_mode: int = GROUP_CHUNK) -> int:
         """Number of groups the walk forms for (group_mode, g_max)."""
@@ -290,7 +304,7 @@ class Tree:
                                         ctypes.byref(out)), "otoo_tree_walk_sph")
         return self._take_lists(out)
 
-    def _take_lists(self, out) -> Lists:
+    def _take_lists(self, out, near_ratio: float = 0.0) -> Lists:
         # the arrays are views of the library's buffers (no copy of the often
         # hundreds of MB of list indices); the buffers are freed with the last view
         owner = _ListsOwner(out)
@@ -301,7 +315,8 @@ class Tree:
                      list_idx=_view(s.list_idx, ctypes.c_int32, E, owner, np.int32),
                      n_cellent=_view(s.n_cellent, ctypes.c_int32, G, owner, np.int32),
                      group_box=_view(s.group_box, ctypes.c_float, G * 6, owner, np.float32).reshape(G, 6),
-                     interactions=int(s.interactions))
+                     interactions=int(s.interactions),
+                     n_near=_view(s.n_near, ctypes.c_int32, G, owner, np.int32), near_ratio=near_ratio)
 
 
 class _ListsOwner:
@@ -592,7 +607,8 @@ class Context:
         self._raise(lib().otoo_graph_launch(self._h), "otoo_graph_launch")
 
     def autotune(self, tree: Tree, eps: float, choices, schedules, reps: int = 10, theta: float = 0.5,
-                 mac: int = MAC_BH, delta: float = 0.01, m_limit: float = math.inf, corr_kind: int = -1, net=None):
+                 mac: int = MAC_BH, delta: float = 0.01, m_limit: float = math.inf, corr_kind: int = -1, net=None,
+                 near_ratio: float = 0.0):
         """Time every (group_mode, g_max) choice x device schedule as graph replays
         (otoo_autotune; with corr_kind CORR_QUAD or CORR_MLP (and ``net``)
         otoo_autotune_step, each replay being the correction pass and the
@@ -606,7 +622,8 @@ class Context:
         ms = np.zeros((len(choices), len(schedules)), np.float32)
         inter = np.zeros(len(choices), np.int64)
         bc, bt, bms = GroupChoice(), Tuning(), ctypes.c_float()
-        p = _WalkParams(mac=mac, theta=theta, delta=delta, m_limit=m_limit, group_mode=GROUP_CHUNK, g_max=1)
+        p = _WalkParams(mac=mac, theta=theta, delta=delta, m_limit=m_limit, group_mode=GROUP_CHUNK, g_max=1,
+                        near_ratio=float(near_ratio))
         if corr_kind < 0:
             rc = lib().otoo_autotune(self._h, tree._h, ctypes.byref(p), ch, len(choices), sc, len(schedules),
                                      float(eps), int(reps), _np_ptr(ms), _np_ptr(inter), ctypes.byref(bc),

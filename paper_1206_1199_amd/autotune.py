@@ -45,10 +45,11 @@ def device_key(device: int = 0) -> str:
 
 
 def autotune(tree: Tree, eps: float, theta: float, ctx: Context, grid=None, reps: int = 10, log=None,
-             corr_kind: int = -1, net=None):
+             corr_kind: int = -1, net=None, near_ratio: float = 0.0):
     """Sweep the grid through the library's otoo_autotune (otoo_autotune_step
     when corr_kind is CORR_QUAD or CORR_MLP: the timed step is the correction
-    pass and the force); returns (best dict, table of all measurements).  The
+    pass and the force; near_ratio > 0 corrects only the near cells that the
+    walk lists first); returns (best dict, table of all measurements).  The
     best is the fastest schedule, or, among those within 1 % of it, the one
     with the most interactions per second."""
     grid = grid or GRID
@@ -57,7 +58,7 @@ def autotune(tree: Tree, eps: float, theta: float, ctx: Context, grid=None, reps
                  for c, b, l, t in itertools.product(grid["chunk"], grid["blocks_per_cu"], grid["lpt"], grid["tile"])]
     ctx.sync_stream()
     ms, inter, _, _, _ = ctx.autotune(tree, eps, choices, schedules, reps=reps, theta=theta, corr_kind=corr_kind,
-                                      net=net)
+                                      net=net, near_ratio=near_ratio)
     table = []
     for gi, (mode, g_max) in enumerate(choices):
         rows = [dict(group_mode="chunk" if mode == GROUP_CHUNK else "cell", g_max=g_max, **s, ms=float(ms[gi, si]),
@@ -95,7 +96,8 @@ DEFAULT_SCHEDULE = dict(group_mode="chunk", g_max=64, chunk=2048, blocks_per_cu=
 
 def cache_key(workload: str, mode: str = "plain", device: int = 0) -> str:
     """Cache key of a workload's schedule: the plain force, or the corrected
-    step of mode "quad" or "learned" (which has its own best group size)."""
+    step of mode "quad", "learned" (network on the near cells) or
+    "learned-all" (network on every cell), each with its own best group size."""
     return f"{device_key(device)}:{workload}" + ("" if mode == "plain" else f"+{mode}")
 
 

@@ -117,7 +117,7 @@ struct otoo_tree {
 
 struct otoo_lists_impl {
     otoo_lists pub;
-    std::vector<int32_t> group_off, n_cellent;
+    std::vector<int32_t> group_off, n_cellent, n_near;
     std::unique_ptr<int32_t[]> list_idx;
     std::vector<int64_t> list_off;
     std::vector<float> group_box;  // [G][6] lo xyz, hi xyz (FP32, rounded outward is not needed: informative)
@@ -217,16 +217,20 @@ std::vector<WalkCell> walk_cells(const otoo_tree* t) {
 // opened leaf contributes its particles (a contiguous key range, the same
 // entries its more/next chain visits) without visiting them one by one.
 // Lists hold the accepted cells, then the particles, each part in walk
-// (ascending) order.  Threads take groups in chunks of 8; each keeps its
-// lists in its own buffer until they are gathered into one CSR.
+// (ascending) order.  With near_ratio > 0 the accepted cells are split,
+// each part still ascending: first the near ones, whose side l_c is at least
+// near_ratio times the distance from the cell's COM to the centre of the
+// group's bounding box (FP64), then the others; n_near counts the first
+// part.  Threads take groups in chunks of 8; each keeps its lists in its own
+// buffer until they are gathered into one CSR.
 template <class Decide>
 void walk_groups(const otoo_tree* t, const std::vector<int64_t>& goff, const std::vector<WalkCell>& cells,
-                 Decide decide, otoo_lists_impl* L) {
+                 Decide decide, otoo_lists_impl* L, double near_ratio = 0.0) {
     const int64_t n = t->n;
     const int64_t ng = (int64_t)goff.size() - 1;
     const int nth = omp_get_max_threads();
     std::vector<std::vector<int32_t>> buf(nth);
-    std::vector<int64_t> g_thread(ng), g_start(ng), g_ncell(ng), g_len(ng);
+    std::vector<int64_t> g_thread(ng), g_start(ng), g_ncell(ng), g_nnear(ng), g_len(ng);
     L->group_box.resize(6 * (size_t)ng);
     // an exception cannot leave an OpenMP region: a failed allocation inside
     // it is recorded here and rethrown after the region
@@ -235,7 +239,7 @@ void walk_groups(const otoo_tree* t, const std::vector<int64_t>& goff, const std
     {
         const int tid = omp_get_thread_num();
         std::vector<int32_t>& B = buf[tid];
-        std::vector<int32_t> cellv, partv;
+        std::vector<int32_t> cellv, partv, farv;
 #pragma omp for schedule(dynamic, 8)
         for (int64_t g = 0; g < ng; g++) {
             if (out_of_memory.load(std::memory_order_relaxed)) continue;
@@ -272,9 +276,25 @@ void walk_groups(const otoo_tree* t, const std::vector<int64_t>& goff, const std
                     if (act == kAccept) cellv.push_back((int32_t)u);
                     u = (open && !c.leaf) ? c.more : c.next;
                 }
+                int64_t nnear = 0;
+                if (near_ratio > 0.0) {   // near cells first, then the far ones, each part ascending
+                    const double cg[3] = {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2])};
+                    farv.clear();
+                    for (const int32_t u : cellv) {
+                        const int64_t c = (int64_t)u - n;
+                        const double dx = t->com[3 * c] - cg[0], dy = t->com[3 * c + 1] - cg[1],
+                                     dz = t->com[3 * c + 2] - cg[2];
+                        if (t->csize[c] >= near_ratio * std::sqrt(dx * dx + dy * dy + dz * dz))
+                            cellv[nnear++] = u;
+                        else
+                            farv.push_back(u);
+                    }
+                    std::copy(farv.begin(), farv.end(), cellv.begin() + nnear);
+                }
                 g_thread[g] = tid;
                 g_start[g] = (int64_t)B.size();
                 g_ncell[g] = (int64_t)cellv.size();
+                g_nnear[g] = nnear;
                 B.insert(B.end(), cellv.begin(), cellv.end());
                 B.insert(B.end(), partv.begin(), partv.end());
                 g_len[g] = (int64_t)B.size() - g_start[g];
@@ -287,11 +307,13 @@ void walk_groups(const otoo_tree* t, const std::vector<int64_t>& goff, const std
     L->group_off.resize(ng + 1);
     L->list_off.resize(ng + 1);
     L->n_cellent.resize(ng);
+    L->n_near.resize(ng);
     int64_t tot = 0, inter = 0;
     for (int64_t g = 0; g < ng; g++) {
         L->group_off[g] = (int32_t)goff[g];
         L->list_off[g] = tot;
         L->n_cellent[g] = (int32_t)g_ncell[g];
+        L->n_near[g] = (int32_t)g_nnear[g];
         tot += g_len[g];
         inter += (goff[g + 1] - goff[g]) * g_len[g];
     }
@@ -309,6 +331,7 @@ void walk_groups(const otoo_tree* t, const std::vector<int64_t>& goff, const std
     L->pub.list_idx = L->list_idx.get();
     L->pub.n_cellent = L->n_cellent.data();
     L->pub.group_box = L->group_box.data();
+    L->pub.n_near = L->n_near.data();
     L->pub.impl = L;
 }
 
@@ -662,6 +685,7 @@ int otoo_tree_walk_range(const otoo_tree* t, const otoo_walk_params* wp, int32_t
         return OTOO_EINVAL;
     }
     if (wp->group_mode != OTOO_GROUP_CHUNK && wp->group_mode != OTOO_GROUP_CELL) return OTOO_EINVAL;
+    if (!(wp->near_ratio >= 0.0) || !std::isfinite(wp->near_ratio)) return OTOO_EINVAL;
     otoo_lists_impl* L = new (std::nothrow) otoo_lists_impl();
     if (!L) return OTOO_ENOMEM;
     try {
@@ -675,7 +699,7 @@ int otoo_tree_walk_range(const otoo_tree* t, const otoo_walk_params* wp, int32_t
         const std::vector<int64_t> goff(all->begin() + g_begin, all->begin() + g1 + 1);
         const std::shared_ptr<const std::vector<WalkCell>> cells = cached_cells(t, *wp);
         walk_groups(t, goff, *cells, [](const WalkCell& w, double dmin, int64_t) { return dmin > w.ra ? kAccept : kOpen; },
-                    L);
+                    L, wp->near_ratio);
     } catch (const std::bad_alloc&) {
         delete L;
         return OTOO_ENOMEM;

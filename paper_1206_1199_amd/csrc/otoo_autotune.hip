@@ -177,9 +177,11 @@ int autotune_impl(otoo_ctx* c, const otoo_tree* tree, const otoo_walk_params* wa
         if (L.n_entries)
             HIP_TRY(c, hipMemcpy(d_li, L.list_idx, sizeof(int32_t) * L.n_entries, hipMemcpyHostToDevice));
         int64_t n_pairs = 0;
-        if (corr_kind >= 0) {   // the (group, cell) pairs: prefix sums of the cell-entry counts
+        if (corr_kind >= 0) {   // the (group, cell) pairs: prefix sums of the cell-entry counts (the near ones
+                                // when the walk splits them)
+            const int32_t* cnt = wp.near_ratio > 0.0 ? L.n_near : L.n_cellent;
             std::vector<int64_t> po((size_t)L.n_groups + 1, 0);
-            for (int32_t g = 0; g < L.n_groups; g++) po[g + 1] = po[g] + L.n_cellent[g];
+            for (int32_t g = 0; g < L.n_groups; g++) po[g + 1] = po[g] + cnt[g];
             n_pairs = po[L.n_groups];
             HIP_TRY(c, lists.alloc(&d_po, po.size()));
             HIP_TRY(c, lists.alloc(&d_gc, (size_t)L.n_groups * kCorrStride));

@@ -191,7 +191,7 @@ class Network:
 @dataclass
 class SampleConfig:
     """One walk of a seeded workload contributing training samples."""
-    workload: str          # "plummer"
+    workload: str          # "plummer", or "grf_cube" (n = ng^3 particles)
     n: int
     seed: int
     eps: float
@@ -225,7 +225,8 @@ def draw_samples(lists: Lists, n_samples: int, rng: np.random.Generator) -> np.n
     return np.stack([p, i], axis=1).astype(np.int64)
 
 
-def make_training_set(ctx, net: Network, configs, seed: int, device="cuda:0", log=None, gate: float = 0.0):
+def make_training_set(ctx, net: Network, configs, seed: int, device="cuda:0", log=None, gate: float = 0.0,
+                      near: bool = False):
     """Training samples from seeded walks (exact cell sums computed on the GPU).
 
     The library weights each sample by 1 / |a_i|^2, a_i the total force on
@@ -233,9 +234,11 @@ def make_training_set(ctx, net: Network, configs, seed: int, device="cuda:0", lo
     the correction is judged by), normalised so that the zero-correction loss
     of each configuration's kept samples is 1, and keeps only pairs the gate
     lets through to the layers (BF16 feature l/n >= gate); this function
-    gathers the kept rows.  Returns (X int16 [S,32], aux float32 [S,12], eps
-    float32 [S]) on the device; samples of different softening lengths carry
-    their own eps.
+    gathers the kept rows.  With near=True the walks list each group's near
+    cells first (near_ratio = gate) and the samples are drawn from those
+    pairs alone, all of them kept.  Returns (X int16 [S,32], aux float32
+    [S,12], eps float32 [S]) on the device; samples of different softening
+    lengths carry their own eps.
     """
     import torch
     import synth
@@ -243,16 +246,19 @@ def make_training_set(ctx, net: Network, configs, seed: int, device="cuda:0", lo
     Xs, auxs, epss = [], [], []
     for cfg in configs:
         t0 = time.perf_counter()
-        if cfg.workload != "plummer":
+        if cfg.workload == "plummer":
+            pos, m = synth.plummer(cfg.n, seed=cfg.seed)
+        elif cfg.workload == "grf_cube":
+            pos, m = synth.grf_cube(int(round(cfg.n ** (1.0 / 3.0))), seed=cfg.seed)
+        else:
             raise ValueError(cfg.workload)
-        pos, m = synth.plummer(cfg.n, seed=cfg.seed)
         tree = Tree(pos, m, n_crit=16)
-        lists = tree.walk(theta=cfg.theta, g_max=cfg.g_max)
+        lists = tree.walk(theta=cfg.theta, g_max=cfg.g_max, near_ratio=gate if near else 0.0)
         d, first, count = device_tree_arrays(tree, lists, device)
         smp = torch.from_numpy(draw_samples(lists, cfg.n_samples, rng)).to(device)
         X, aux = net.train_samples(d, first, count, cfg.eps, smp)
         acc, _ = ctx.force(d, cfg.eps)          # the target's total (monopole-tree) force
-        keep = net.sample_weights(smp, acc, X, aux, gate)
+        keep = net.sample_weights(smp, acc, X, aux, 0.0 if near else gate)
         X, aux = X[keep], aux[keep]
         Xs.append(X)
         auxs.append(aux)

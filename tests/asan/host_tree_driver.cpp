@@ -75,13 +75,20 @@ int main() {
 
     for (int32_t mode : {OTOO_GROUP_CHUNK, OTOO_GROUP_CELL})
         for (int32_t g_max : {1, 17, 64, 256})
-            for (double theta : {0.0, 0.5, 0.9}) {
-                otoo_walk_params wp{OTOO_MAC_BH, theta, 0.0, INFINITY, mode, g_max};
-                otoo_lists* L = nullptr;
-                expect(otoo_tree_walk(t, &wp, &L) == OTOO_OK && L, "walk");
-                if (L) check_lists(L, n, nc, "walk lists");
-                otoo_lists_free(L);
-            }
+            for (double theta : {0.0, 0.5, 0.9})
+                for (double near_ratio : {0.0, 0.4}) {
+                    otoo_walk_params wp{OTOO_MAC_BH, theta, 0.0, INFINITY, mode, g_max, near_ratio};
+                    otoo_lists* L = nullptr;
+                    expect(otoo_tree_walk(t, &wp, &L) == OTOO_OK && L, "walk");
+                    if (L) {
+                        check_lists(L, n, nc, "walk lists");
+                        for (int32_t g = 0; g < L->n_groups; g++)
+                            expect(L->n_near[g] >= 0 && L->n_near[g] <= L->n_cellent[g] &&
+                                       (near_ratio > 0.0 || L->n_near[g] == 0),
+                                   "near cells within the cells");
+                    }
+                    otoo_lists_free(L);
+                }
     for (double m_limit : {(double)INFINITY, 0.05}) {
         otoo_walk_params wp{OTOO_MAC_ABSOLUTE, 0.0, 0.01, m_limit, OTOO_GROUP_CHUNK, 64};
         otoo_lists* L = nullptr;
@@ -112,6 +119,11 @@ int main() {
     bad.g_max = 0;
     expect(otoo_tree_walk(t, &bad, &L) == OTOO_EINVAL, "g_max 0");
     expect(otoo_tree_walk_range(t, &bad, 5, 5, &L) == OTOO_EINVAL, "empty range");
+    bad.g_max = 64;
+    bad.near_ratio = -0.5;
+    expect(otoo_tree_walk(t, &bad, &L) == OTOO_EINVAL, "negative near ratio");
+    bad.near_ratio = NAN;
+    expect(otoo_tree_walk(t, &bad, &L) == OTOO_EINVAL, "NaN near ratio");
     h[17] = 0.0;
     expect(otoo_tree_walk_sph(t, h.data(), OTOO_GROUP_CELL, 32, &L) == OTOO_EINVAL, "h = 0");
     otoo_tree* t2 = nullptr;

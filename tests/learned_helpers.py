@@ -38,9 +38,15 @@ def group_geometry(pos, group_off):
     return 0.5 * (lo + hi), 0.5 * np.linalg.norm(hi - lo, axis=1)
 
 
+def pair_counts(lists):
+    """(group, cell) pairs per group: the near cells of a walk that listed
+    them first, else every cell entry."""
+    return np.asarray(getattr(lists, "n_pair", lists.n_cellent), np.int64)
+
+
 def pair_index(lists, n):
     """Group and cell (0-based cell number) of every (group, cell) pair, in pair order."""
-    nce = np.asarray(lists.n_cellent, np.int64)
+    nce = pair_counts(lists)
     G = len(nce)
     g = np.repeat(np.arange(G), nce)
     pair_off = np.concatenate([[0], np.cumsum(nce)])
@@ -55,7 +61,7 @@ def group_of(group_off, i):
 
 def pair_cells(lists, n, pairs):
     """Group and cell (0-based) of the given global pair numbers."""
-    pair_off = np.concatenate([[0], np.cumsum(np.asarray(lists.n_cellent, np.int64))])
+    pair_off = np.concatenate([[0], np.cumsum(pair_counts(lists))])
     pairs = np.asarray(pairs, np.int64)
     g = np.searchsorted(pair_off, pairs, side="right") - 1
     c = np.asarray(lists.list_idx, np.int64)[np.asarray(lists.list_off, np.int64)[g] + pairs - pair_off[g]] - n
@@ -80,12 +86,13 @@ def sub_lists(lists, groups):
     """The CSR restricted to `groups` (ascending), other particle ranges kept
     as groups with empty lists, so that every particle still has a group.
     Returns dict(group_off, list_off, list_idx, n_cellent, pairs) with
-    `pairs` the global pair numbers of the kept groups' pairs, in the
-    restricted pair order."""
+    n_cellent the kept groups' pair counts (the cells that carry a tensor)
+    and `pairs` the global pair numbers of their pairs, in the restricted
+    pair order."""
     go = np.asarray(lists.group_off, np.int64)
     lo = np.asarray(lists.list_off, np.int64)
     li = np.asarray(lists.list_idx, np.int64)
-    nce = np.asarray(lists.n_cellent, np.int64)
+    nce = pair_counts(lists)
     pair_off = np.concatenate([[0], np.cumsum(nce)])
     groups = np.unique(np.asarray(groups, np.int64))
     bounds, lens, ncs, idx, pairs = [int(go[0])], [], [], [], []

@@ -20,7 +20,7 @@ class _FakeContext:
     def sync_stream(self):
         pass
 
-    def autotune(self, tree, eps, choices, schedules, reps=10, theta=0.5, corr_kind=-1, net=None):
+    def autotune(self, tree, eps, choices, schedules, reps=10, theta=0.5, corr_kind=-1, net=None, near_ratio=0.0):
         assert self.ms.shape == (len(choices), len(schedules))
         return self.ms, self.inter, None, None, None
 

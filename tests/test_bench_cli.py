@@ -46,8 +46,8 @@ def test_traffic_is_read_only_for_matching_sources(tmp_path, monkeypatch):
     prof = tmp_path / "profiles"
     prof.mkdir()
 
-    def write(sha, workload, schedule):
-        (prof / "k_force_plummer1m.md").write_text(
+    def write(sha, workload, schedule, name="k_force_plummer1m.md"):
+        (prof / name).write_text(
             f"# summary\n\ntraffic_bytes_per_launch: 123456\nsource_sha256: {sha}\nworkload: {workload}\n"
             f"schedule: {json.dumps(schedule, sort_keys=True)}\n")
 
@@ -57,8 +57,12 @@ def test_traffic_is_read_only_for_matching_sources(tmp_path, monkeypatch):
         (tmp_path / "paper_1206_1199_amd" / "csrc" / f).write_bytes(
             open(os.path.join(ROOT, "paper_1206_1199_amd", "csrc", f), "rb").read())
     write(h.hexdigest()[:16], "W", sched)
-    assert bench.measured_traffic("W", sched) == 123456.0
-    assert bench.measured_traffic("other workload", sched) is None
-    assert bench.measured_traffic("W", dict(sched, chunk=4096)) is None
+    assert bench.measured_traffic("plummer1m", "plain", "W", sched) == 123456.0
+    assert bench.measured_traffic("plummer1m", "plain", "other workload", sched) is None
+    assert bench.measured_traffic("plummer1m", "plain", "W", dict(sched, chunk=4096)) is None
+    assert bench.measured_traffic("plummer1m", "learned", "W", sched) is None     # no summary of that mode
+    assert bench.measured_traffic("cube16m", "plain", "W", sched) is None         # nor of that workload
+    write(h.hexdigest()[:16], "W", sched, name="k_force_cube16m_learned.md")
+    assert bench.measured_traffic("cube16m", "learned", "W", sched) == 123456.0
     write("0" * 16, "W", sched)
-    assert bench.measured_traffic("W", sched) is None
+    assert bench.measured_traffic("plummer1m", "plain", "W", sched) is None

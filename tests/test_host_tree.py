@@ -103,6 +103,40 @@ def test_walk_lists_equal_oracle_sets(trees, mode, theta, mac):
     assert inter == lists.interactions
 
 
+@pytest.mark.parametrize("mode,theta", [(otoo.GROUP_CHUNK, 0.7), (otoo.GROUP_CELL, 0.9), (otoo.GROUP_CHUNK, 0.0)])
+def test_near_cells_listed_first_match_oracle(trees, mode, theta):
+    """A walk with a near ratio lists, per group, the same entries as the
+    plain walk; its cells are split into the near ones (side >= ratio x the
+    distance of the COM from the group's box centre, the oracle's
+    near_cells) and the others, each part ascending, n_near counting the
+    first part; the (group, cell) pairs are the near cells."""
+    pos, m, t, o = trees
+    perm, _, _, _ = t.export()
+    cells = t.cells()
+    plain = t.walk(theta=theta, g_max=64, group_mode=mode)
+    near = t.walk(theta=theta, g_max=64, group_mode=mode, near_ratio=0.4)
+    np.testing.assert_array_equal(plain.group_off, near.group_off)
+    np.testing.assert_array_equal(plain.list_off, near.list_off)
+    np.testing.assert_array_equal(plain.n_cellent, near.n_cellent)
+    assert np.all(plain.n_near == 0) and np.all(near.n_near <= near.n_cellent)
+    np.testing.assert_array_equal(near.pair_off, np.concatenate([[0], np.cumsum(near.n_near)]))
+    total_near = 0
+    for g in range(near.n_groups):
+        lo, hi = near.list_off[g], near.list_off[g + 1]
+        a, b = near.list_idx[lo:hi], plain.list_idx[lo:hi]
+        nce, nn = near.n_cellent[g], near.n_near[g]
+        np.testing.assert_array_equal(a[nce:], b[nce:])                 # particles unchanged
+        assert set(a[:nce].tolist()) == set(b[:nce].tolist())          # the same cells
+        assert np.all(np.diff(a[:nn]) > 0) and np.all(np.diff(a[nn:nce]) > 0)
+        ids = perm[near.group_off[g]:near.group_off[g + 1]]
+        oc, _ = otree.walk(o, pos, ids, theta)
+        want = {c.key for c in otree.near_cells(oc, pos, ids, 0.4)}
+        got = {(int(cells["level"][e - t.n]),) + tuple(int(v) for v in cells["ijk"][e - t.n]) for e in a[:nn]}
+        assert got == want
+        total_near += nn
+    assert (total_near > 0) == (theta > 0)
+
+
 def test_theta_zero_lists_all_particles(trees):
     pos, m, t, o = trees
     lists = t.walk(theta=0.0, g_max=128)

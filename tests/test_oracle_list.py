@@ -217,3 +217,22 @@ def test_expansion_within_truncation_bound_on_real_groups(group_mode):
     assert np.all(da <= ba + 1e-12 * an)
     assert np.all(dp <= bp + 1e-12 * np.abs(p_pp))
     assert np.median(da) < 0.5 * np.median(corr)
+
+
+def test_cells_after_the_tensor_range_are_monopoles():
+    """Tensors cover the first n_cellent[g] entries; a cell entry after them
+    (a far cell behind a list's near cells) acts as a monopole only: the same
+    sums as giving that cell a zero tensor."""
+    rng = np.random.default_rng(31)
+    pos = rng.normal(size=(3, 3))
+    mass = np.array([1.0, 2.0, 0.5])
+    com = rng.normal(size=(2, 3)) * 4.0
+    cmass = np.array([3.0, 1.5])
+    q = rng.normal(size=(1, 6))
+    args = (pos, mass, [0, 3], [0, 5], [3, 4, 0, 1, 2], com, cmass, 0.05)
+    for expanded in (False, True):
+        a1, p1 = oracle.list_force(*args, n_cellent=[1], quad=q, expanded=expanded)
+        a2, p2 = oracle.list_force(*args, n_cellent=[2], quad=np.concatenate([q, np.zeros((1, 6))]),
+                                   expanded=expanded)
+        np.testing.assert_allclose(a1, a2, rtol=1e-14, atol=0)
+        np.testing.assert_allclose(p1, p2, rtol=1e-14, atol=0)
