@@ -334,7 +334,7 @@ HELD_OUT = {
 # (case, pairs): bars on the learned median error as fractions of the plain
 # monopole's and of the textbook quadrupole's (on every cell) on the same lists
 GAIN_BARS = {
-    ("plummer16k", "all"): (0.8, 1.05), ("plummer256k", "all"): (0.8, 1.0),
+    ("plummer16k", "all"): (0.8, 1.02), ("plummer256k", "all"): (0.8, 0.95),
     ("cube64", "all"): (0.5, 0.5), ("cube128", "all"): (0.5, 0.5),
     ("plummer16k", "near"): (0.9, 1.5), ("plummer256k", "near"): (0.8, 1.05),
     ("cube64", "near"): (0.6, 0.65), ("cube128", "near"): (0.6, 0.65),
@@ -344,15 +344,17 @@ GAIN_BARS = {
 @pytest.mark.parametrize("pairs", ["all", "near"])
 @pytest.mark.parametrize("case", sorted(HELD_OUT))
 def test_training_reduces_loss_and_helps_forces(env, trained, trained_near, case, pairs):
-    """What the trained network gains on held-out inputs: a lower validation
-    loss than the plain monopole and the textbook quadrupole, and a median
-    force error against direct sums below the bars of GAIN_BARS.  On every
-    cell: at least 20 % below the plain monopole everywhere; on Plummer
-    spheres about the textbook quadrupole's (the network's inputs -- the
-    cells' second moments -- leave only the octupole and higher terms, which
-    it cannot see), on GRF cubes at most half of it (their cells carry little
-    quadrupole but regular higher moments that the network learns from the
-    geometry).  On the near cells alone (pairs "near": the network trained
+    """What the trained network gains on held-out inputs: a validation loss
+    (held-out Plummer pairs) below half the plain monopole's and at least
+    15 % below the textbook quadrupole's, and a median force error against
+    direct sums below the bars of GAIN_BARS.  On every cell: at least 20 %
+    below the plain monopole everywhere; on the 2^18 Plummer sphere at least
+    5 % below the textbook quadrupole, on the 2^14 sphere within 2 % of it
+    (the network's inputs -- the cells' second moments -- leave only the
+    octupole and higher terms, which it cannot see, and its per-pair gain
+    does not reach the median force error there); on GRF cubes at most half
+    of it (their cells carry little quadrupole but regular higher moments
+    that the network learns from the geometry).  On the near cells alone (pairs "near": the network trained
     on near pairs corrects only the cells of side >= 0.4 x their distance
     from the group's box centre, which the walk lists first; the far cells
     stay monopoles): on GRF cubes at most 65 % of the quadrupole on every
@@ -366,7 +368,7 @@ def test_training_reduces_loss_and_helps_forces(env, trained, trained_near, case
           f"{tr['base']:.4e}, textbook quadrupole {tr['quad']:.4e}", flush=True)
     assert tr["base"] == pytest.approx(1.0, rel=1e-5)      # the weights' normalisation
     assert tr["val"] < 0.5 * tr["base"]
-    assert tr["val"] < tr["quad"]
+    assert tr["val"] < 0.85 * tr["quad"]
     net = learned.Network(ctx)
     net.set_params(tr["params"])
     pos, m = getattr(synth, gen)(**kw)
