@@ -392,14 +392,19 @@ enum { kCorrPairs = 0, kCorrQuad = 1, kCorrMlp = 2 };
 
 // Work items of the per-wave correction kernels: the cell pairs of all
 // groups, in pair order (pair_off is their prefix sum), cut into items of
-// kCorrSeg pairs, taken statically by the waves.  A group whose pairs lie in
+// `seg` pairs, taken statically by the waves.  A group whose pairs lie in
 // one item writes its row of gcorr there; a group that straddles items leaves
 // a partial expansion in each: in slot R of its first item, and in slot L of
 // every later one.  k_corr_merge adds them in item order, so the result does
-// not depend on the schedule.
+// not depend on the schedule.  seg is kCorrSeg, halved down to kCorrSegMin
+// while there are fewer than four items per resident wave (small inputs
+// would otherwise leave most waves of the chip without an item); it follows
+// from the pair count and the kernels' occupancy alone.
 constexpr int kCorrSeg = 1024;
+constexpr int kCorrSegMin = 256;
 struct CorrPlan {
     int64_t n_items;
+    int32_t seg;     // pairs per item
     float* part_l;   // [n_items][kCorrStride]: 20 terms, centre xyz, pad
     float* part_r;   // [n_items][kCorrStride]
     float4* box;     // [n_groups]: box centre xyz and half-diagonal, -1 for a malformed group
@@ -781,7 +786,7 @@ __global__ __launch_bounds__(256) void k_corr_merge(CorrArgs a) {
             row[kCorrTerms + 3] = 0.f;
             continue;
         }
-        const int64_t i0 = p0 / kCorrSeg, i1 = (p1 - 1) / kCorrSeg;
+        const int64_t i0 = p0 / a.plan.seg, i1 = (p1 - 1) / a.plan.seg;
         if (i0 == i1) continue;   // written whole by its item
         const float* r = a.plan.part_r + (int64_t)kCorrStride * i0;
         float v[kCorrTerms];
@@ -887,8 +892,8 @@ __global__ __launch_bounds__(256) void k_corr_wave(CorrArgs a) {
     const float eps2 = a.eps * a.eps;
     const ItemRange ir = xcd_items(a.plan.n_items);
     for (int64_t it = ir.first; it < ir.end; it += ir.step) {
-        const int64_t q0 = it * kCorrSeg;
-        const int64_t q1 = q0 + kCorrSeg < a.n_pairs ? q0 + kCorrSeg : a.n_pairs;
+        const int64_t q0 = it * a.plan.seg;
+        const int64_t q1 = q0 + a.plan.seg < a.n_pairs ? q0 + a.plan.seg : a.n_pairs;
         for (int g = group_of_pair(a, q0); g < a.n_groups; g++) {
             int64_t p0, p1;
             pair_range(a, g, p0, p1);
@@ -968,9 +973,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     __syncthreads();
     const ItemRange ir = xcd_items(a.plan.n_items);
     for (int64_t it = ir.first; it < ir.end; it += ir.step)
-    for (int g = group_of_pair(a, it * kCorrSeg); g < a.n_groups; g++) {
-        const int64_t q0 = it * kCorrSeg;
-        const int64_t q1 = q0 + kCorrSeg < a.n_pairs ? q0 + kCorrSeg : a.n_pairs;
+    for (int g = group_of_pair(a, it * a.plan.seg); g < a.n_groups; g++) {
+        const int64_t q0 = it * a.plan.seg;
+        const int64_t q1 = q0 + a.plan.seg < a.n_pairs ? q0 + a.plan.seg : a.n_pairs;
         int64_t p0, p1;
         pair_range(a, g, p0, p1);
         if (p0 >= q1) break;
@@ -1099,7 +1104,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // The learned correction split into a network pass and an expansion pass,
 // so that neither carries the other's registers.
 //
-// k_corr_gnet: every wave takes the items of kCorrSeg pairs in turn (as the
+// k_corr_gnet: every wave takes the items of seg pairs in turn (as the
 // wave kernels do) and decides per pair whether the gate sends it through
 // the layers (features in range and finite, BF16 l/n at least the gate).
 // The pairs that go are appended to the wave's queue in LDS with their BF16
@@ -1258,9 +1263,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     int pend = 0;   // queued pairs, uniform within the wave
     const ItemRange ir = xcd_items(a.plan.n_items);
     for (int64_t it = ir.first; it < ir.end; it += ir.step)
-    for (int g = group_of_pair(a, it * kCorrSeg); g < a.n_groups; g++) {
-        const int64_t q0 = it * kCorrSeg;
-        const int64_t q1 = q0 + kCorrSeg < a.n_pairs ? q0 + kCorrSeg : a.n_pairs;
+    for (int g = group_of_pair(a, it * a.plan.seg); g < a.n_groups; g++) {
+        const int64_t q0 = it * a.plan.seg;
+        const int64_t q1 = q0 + a.plan.seg < a.n_pairs ? q0 + a.plan.seg : a.n_pairs;
         int64_t p0, p1;
         pair_range(a, g, p0, p1);
         if (p0 >= q1) break;
@@ -1348,8 +1353,8 @@ __global__ __launch_bounds__(256) void k_corr_apply(CorrArgs a, const float* __r
     const float eps2 = a.eps * a.eps;
     const ItemRange ir = xcd_items(a.plan.n_items);
     for (int64_t it = ir.first; it < ir.end; it += ir.step) {
-        const int64_t q0 = it * kCorrSeg;
-        const int64_t q1 = q0 + kCorrSeg < a.n_pairs ? q0 + kCorrSeg : a.n_pairs;
+        const int64_t q0 = it * a.plan.seg;
+        const int64_t q1 = q0 + a.plan.seg < a.n_pairs ? q0 + a.plan.seg : a.n_pairs;
         for (int g = group_of_pair(a, q0); g < a.n_groups; g++) {
             int64_t p0, p1;
             pair_range(a, g, p0, p1);
@@ -2252,24 +2257,10 @@ int otoo_correction(otoo_ctx* c, int32_t kind, otoo_mlp* m, int32_t n, const flo
         HIP_TRY(c, hipGetLastError());
         return OTOO_OK;
     }
-    // one wave per item of kCorrSeg pairs (items taken statically), then the rows of the groups
+    // one wave per item of seg pairs (items taken statically), then the rows of the groups
     // that straddle items or have no pairs
     CorrPlan& pl = ca.plan;
-    pl.n_items = (n_pairs + kCorrSeg - 1) / kCorrSeg;
-    const size_t part_bytes = align256(sizeof(float) * kCorrStride * (size_t)std::max<int64_t>(pl.n_items, 1));
-    const size_t box_bytes = align256(sizeof(float4) * (size_t)n_groups);
     const bool split = kind == OTOO_CORR_MLP && c->tune.net_kernel == 2;   // network pass + expansion pass
-    const size_t qbuf_bytes = split ? align256(sizeof(float) * kQRow * (size_t)std::max<int64_t>(n_pairs, 1)) : 0;
-    const size_t crec_bytes = split ? align256(2 * sizeof(uint4) * (size_t)std::max<int32_t>(n_cells, 1)) : 0;
-    int rc = ensure_corr_scratch(c, 2 * part_bytes + box_bytes + qbuf_bytes + crec_bytes);
-    if (rc) return rc;
-    pl.part_l = static_cast<float*>(c->corr_buf);
-    pl.part_r = reinterpret_cast<float*>(static_cast<char*>(c->corr_buf) + part_bytes);
-    pl.box = reinterpret_cast<float4*>(static_cast<char*>(c->corr_buf) + 2 * part_bytes);
-    float* qbuf = split ? reinterpret_cast<float*>(static_cast<char*>(c->corr_buf) + 2 * part_bytes + box_bytes)
-                        : nullptr;
-    pl.crec = split ? reinterpret_cast<uint4*>(static_cast<char*>(c->corr_buf) + 2 * part_bytes + box_bytes + qbuf_bytes)
-                    : nullptr;
     // resident workgroups per CU of each kernel (the same for every device of this build)
     static std::atomic<int> occ[5] = {0, 0, 0, 0, 0};
     auto resident = [&](int which, const void* fn, int& per_cu) -> int {
@@ -2287,12 +2278,29 @@ int otoo_correction(otoo_ctx* c, int32_t kind, otoo_mlp* m, int32_t n, const flo
                      : which == 2 ? reinterpret_cast<const void*>(&k_corr_net)
                                   : reinterpret_cast<const void*>(&k_corr_apply);
     int per_cu = 0, per_cu_net = 0;
-    rc = resident(which, fn, per_cu);
+    int rc = resident(which, fn, per_cu);
     if (rc) return rc;
     if (split) {
         rc = resident(4, reinterpret_cast<const void*>(&k_corr_gnet), per_cu_net);
         if (rc) return rc;
     }
+    const int64_t waves = 4LL * std::max(per_cu, per_cu_net) * c->num_cu;
+    pl.seg = kCorrSeg;
+    while (pl.seg > kCorrSegMin && (n_pairs + pl.seg - 1) / pl.seg < 4 * waves) pl.seg /= 2;
+    pl.n_items = (n_pairs + pl.seg - 1) / pl.seg;
+    const size_t part_bytes = align256(sizeof(float) * kCorrStride * (size_t)std::max<int64_t>(pl.n_items, 1));
+    const size_t box_bytes = align256(sizeof(float4) * (size_t)n_groups);
+    const size_t qbuf_bytes = split ? align256(sizeof(float) * kQRow * (size_t)std::max<int64_t>(n_pairs, 1)) : 0;
+    const size_t crec_bytes = split ? align256(2 * sizeof(uint4) * (size_t)std::max<int32_t>(n_cells, 1)) : 0;
+    rc = ensure_corr_scratch(c, 2 * part_bytes + box_bytes + qbuf_bytes + crec_bytes);
+    if (rc) return rc;
+    pl.part_l = static_cast<float*>(c->corr_buf);
+    pl.part_r = reinterpret_cast<float*>(static_cast<char*>(c->corr_buf) + part_bytes);
+    pl.box = reinterpret_cast<float4*>(static_cast<char*>(c->corr_buf) + 2 * part_bytes);
+    float* qbuf = split ? reinterpret_cast<float*>(static_cast<char*>(c->corr_buf) + 2 * part_bytes + box_bytes)
+                        : nullptr;
+    pl.crec = split ? reinterpret_cast<uint4*>(static_cast<char*>(c->corr_buf) + 2 * part_bytes + box_bytes + qbuf_bytes)
+                    : nullptr;
     hipLaunchKernelGGL(k_corr_box, dim3((unsigned)(((int64_t)n_groups + 3) / 4)), dim3(256), 0, c->stream, ca);
     const int64_t item_blocks = std::max<int64_t>((pl.n_items + 3) / 4, 1);
     const dim3 grid((unsigned)std::min<int64_t>((int64_t)per_cu * c->num_cu, item_blocks));
