@@ -30,6 +30,7 @@ import json
 import os
 import sys
 import time
+import types
 
 import numpy as np
 
@@ -579,6 +580,17 @@ def plain_headline(ctx, log, steps, warmup, reps):
     return res
 
 
+def workload_sample(workload, classes, perm, n):
+    """The accuracy sample in device order: 4096 particles, or 2048 per star
+    of the polytrope pair."""
+    import synth
+    seed = SAMPLE_SEED.get(workload, 100)
+    if "A" in classes:
+        ia, ib = np.flatnonzero(classes["A"][perm]), np.flatnonzero(classes["B"][perm])
+        return np.concatenate([ia[synth.sample_idx(len(ia), 2048, seed)], ib[synth.sample_idx(len(ib), 2048, seed)]])
+    return synth.sample_idx(n, 4096, seed=seed)
+
+
 def synth_sample(n, workload):
     import synth
     return synth.sample_idx(n, 4096, seed=SAMPLE_SEED.get(workload, 100))
@@ -610,6 +622,11 @@ def main():
     ap.add_argument("--gate", type=float, default=0.4,
                     help="learned correction: the near-cell ratio l/|COM - c_g| (pairs near), or the layers' "
                          "l/n threshold (pairs all)")
+    ap.add_argument("--near-ratio", type=float, default=0.0,
+                    help="learned correction on near cells: the near ratio (0: the autotuned one, else the gate)")
+    ap.add_argument("--err-target", type=float, default=0.0,
+                    help="autotune of the learned step: the median force error the tuned step must hold "
+                         "(0: the autotuner's default, 1e-3)")
     ap.add_argument("--pairs", default="near", choices=["near", "all"],
                     help="learned correction: network on the near cells only (walk lists them first; the far "
                          "cells stay monopoles), or on every cell (gated, textbook quadrupole below the gate)")
@@ -646,6 +663,8 @@ def main():
 
     near = args.pairs == "near"
     near_ratio = args.gate if (mode == "learned" and near) else 0.0
+    perm, pos32, mass32, cm = tree.export(4 if mode == "plain" else 12)
+    sample = workload_sample(args.workload, classes, perm, len(m))
     net, training, params = None, None, None
     if mode == "learned":
         net, training = train_network(ctx, log, args.train_steps, gate=args.gate, near=near)
@@ -659,13 +678,30 @@ def main():
         if args.workload in GROUPS:
             grid["group"] = GROUPS[args.workload]
         kind = {"plain": -1, "quad": otoo.CORR_QUAD, "learned": otoo.CORR_MLP}[mode]
-        best, table = at.autotune(tree, eps, theta, ctx, grid=grid, log=log, corr_kind=kind, net=net,
-                                  reps=args.autotune_reps, near_ratio=near_ratio)
+        if mode == "learned" and near:
+            # the near ratio is tuned with the schedule, under a bound on the step's median error
+            # at the accuracy sample (FP64 direct sums on the device)
+            ref = types.SimpleNamespace(pos=torch.from_numpy(pos32).to("cuda:0"),
+                                        mass=torch.from_numpy(mass32).to("cuda:0"))
+            a_ref, _ = direct_reference(ctx, ref, sample, eps)
+            del ref
+            ratios = (args.near_ratio,) if args.near_ratio > 0 else at.NEAR_RATIOS
+            best, table = at.autotune_learned(tree, eps, theta, ctx, net, sample, a_ref, ratios=ratios,
+                                              err_target=args.err_target or at.ERR_TARGET, grid=grid,
+                                              reps=args.autotune_reps, log=log)
+            near_ratio = best["near_ratio"]
+        else:
+            best, table = at.autotune(tree, eps, theta, ctx, grid=grid, log=log, corr_kind=kind, net=net,
+                                      reps=args.autotune_reps, near_ratio=near_ratio)
         at.save_cache(key, best, cache_path)
         sched = {k: best[k] for k in at.DEFAULT_SCHEDULE}
         source = "autotuned now" + ("" if mode == "plain" else f" ({mode} step)")
     else:
         sched, source = at.cached_schedule(args.workload, 0, cache_path, mode=sched_mode)
+        if mode == "learned" and near:
+            near_ratio = at.cached_near_ratio(args.workload, 0, cache_path, default=near_ratio)
+    if mode == "learned" and near and args.near_ratio > 0:
+        near_ratio = args.near_ratio
     for k, v in (("g_max", args.g_max), ("group_mode", args.group_mode), ("chunk", args.chunk),
                  ("blocks_per_cu", args.blocks_per_cu), ("tile", args.tile)):
         if v:
@@ -674,13 +710,12 @@ def main():
     if args.lpt >= 0:
         sched["lpt"] = args.lpt
     gmode = otoo.GROUP_CHUNK if sched["group_mode"] == "chunk" else otoo.GROUP_CELL
-    log(f"schedule ({source}): {sched}")
+    log(f"schedule ({source}): {sched}" + (f", near ratio {near_ratio}" if near_ratio > 0 else ""))
 
     t2 = time.perf_counter()
     with marker("host walk"):
         lists = tree.walk(theta=theta, g_max=sched["g_max"], group_mode=gmode, near_ratio=near_ratio)
     t3 = time.perf_counter()
-    perm, pos32, mass32, cm = tree.export(4 if mode == "plain" else 12)
     log(f"tree {1e3 * (t1 - t0):.0f} ms, walk {1e3 * (t3 - t2):.0f} ms: groups {lists.n_groups}, "
         f"entries {lists.n_entries}, interactions {lists.interactions}, cell pairs {int(lists.pair_off[-1])}")
 
@@ -728,6 +763,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "correction": mode, "gate": args.gate if mode == "learned" else None,
+                   "near_ratio": near_ratio if near_ratio > 0 else None,
                    "corrected_pairs": ("near" if near else "all") if mode == "learned" else
                    ("all" if mode == "quad" else None),
                    "n": int(len(m)), "groups": lists.n_groups, "list_entries": lists.n_entries,
@@ -752,14 +788,7 @@ def main():
     if training:
         res["training"] = training
     # accuracy of the tree force: FP64 direct sums on the device at a 4096-particle sample
-    import synth
-    seed = SAMPLE_SEED.get(args.workload, 100)
     cls = {k: v[perm] for k, v in classes.items()}          # masks in device order
-    if "A" in cls:    # 2048 sampled particles per star
-        ia, ib = np.flatnonzero(cls["A"]), np.flatnonzero(cls["B"])
-        sample = np.concatenate([ia[synth.sample_idx(len(ia), 2048, seed)], ib[synth.sample_idx(len(ib), 2048, seed)]])
-    else:
-        sample = synth.sample_idx(len(m), 4096, seed=seed)
     a_dir, p_dir = direct_reference(ctx, d, sample, eps)
     et, ept = rel_err(acc[sample], a_dir), rel_err(pot[sample], p_dir)
     res["accuracy"] = {"tree_acc_median_vs_direct": float(np.median(et)),
@@ -788,8 +817,11 @@ def main():
                 res["accuracy"][f"parity_acc_median_{k}"] = float(np.median(ea[mask]))
                 res["accuracy"][f"parity_acc_max_{k}"] = float(ea[mask].max())
         else:
-            # a bounded sample: every k-th group, about 1/256 of the work
-            step_g = max(1, lists.n_groups // 2048)
+            # a bounded sample: every k-th group, k chosen for about 12 s of oracle work on 16 threads
+            # (measured rates: about 6 us per (group, cell) pair for the FP64 network and its tensors,
+            # 3e8 interactions/s for the list sums)
+            est_s = 6e-6 * n_pairs + inter / 3e8
+            step_g = int(min(max(1, np.ceil(est_s / 12.0)), max(1, lists.n_groups // 256)))
             groups = np.arange(0, lists.n_groups, step_g, dtype=np.int64)
             go = np.asarray(lists.group_off, np.int64)
             tgt = np.concatenate([np.arange(go[g], go[g + 1])[:4] for g in groups])

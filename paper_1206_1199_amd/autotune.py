@@ -13,7 +13,7 @@ import itertools
 import json
 import os
 
-from . import GROUP_CELL, GROUP_CHUNK, Context, Tree
+from . import CORR_MLP, GROUP_CELL, GROUP_CHUNK, Context, Tree
 
 PACKAGE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
@@ -75,6 +75,69 @@ def autotune(tree: Tree, eps: float, theta: float, ctx: Context, grid=None, reps
     return best, table
 
 
+# near ratios the learned step is tuned over (the network is trained on pairs
+# of ratio >= 0.4, so each of these corrects a subset of its training pairs),
+# and the median force error the tuned step must hold
+NEAR_RATIOS = (0.4, 0.5, 0.6)
+ERR_TARGET = 1e-3
+
+
+def choose_near_ratio(rows, err_target: float = ERR_TARGET):
+    """Among rows (one per near ratio: its fastest schedule's "ms" and the
+    step's measured "median_err"), the fastest whose error is at most
+    err_target; if none is, the most accurate."""
+    ok = [r for r in rows if r["median_err"] <= err_target]
+    if ok:
+        return min(ok, key=lambda r: r["ms"])
+    return min(rows, key=lambda r: r["median_err"])
+
+
+def step_median_error(ctx: Context, tree: Tree, eps: float, theta: float, sched: dict, net, near_ratio: float,
+                      sample, a_ref) -> float:
+    """Median relative acceleration error, at the particles `sample` (device
+    order) against the reference accelerations a_ref [len(sample), 3], of one
+    learned step (correction of the near cells, then the force) with the
+    given schedule.  Leaves the context's tuning as it was."""
+    import numpy as np
+    import torch
+    from . import CORR_STRIDE
+    from .learned import device_tree_arrays
+    old = ctx.tuning()
+    try:
+        apply_schedule(ctx, sched)
+        lists = tree.walk(theta=theta, g_max=int(sched["g_max"]),
+                          group_mode=GROUP_CHUNK if sched["group_mode"] == "chunk" else GROUP_CELL,
+                          near_ratio=near_ratio)
+        d, _, _ = device_tree_arrays(tree, lists)
+        gc = torch.empty((d.n_groups, CORR_STRIDE), dtype=torch.float32, device=d.pos.device)
+        acc, _ = ctx.force(d, eps, gcorr=ctx.correction(d, CORR_MLP, eps, net=net, out=gc))
+        torch.cuda.synchronize()
+        ctx.check()
+        a = acc.cpu().numpy().astype(np.float64)[np.asarray(sample)]
+        ref = np.asarray(a_ref, np.float64)
+        return float(np.median(np.linalg.norm(a - ref, axis=1) / np.linalg.norm(ref, axis=1)))
+    finally:
+        ctx.set_tuning(chunk=old.chunk, blocks_per_cu=old.blocks_per_cu, lpt=old.lpt, tile=old.tile)
+
+
+def autotune_learned(tree: Tree, eps: float, theta: float, ctx: Context, net, sample, a_ref,
+                     ratios=NEAR_RATIOS, err_target: float = ERR_TARGET, grid=None, reps: int = 10, log=None):
+    """The learned step on near cells tuned with an accuracy bound: for each
+    near ratio the fastest group size and schedule (autotune with the
+    correction in the timed step), then the step's median error at the sample
+    with that schedule; the choice is choose_near_ratio's.  Returns (best
+    dict with near_ratio, median_err and err_target, rows of every ratio)."""
+    rows = []
+    for r in ratios:
+        best, _ = autotune(tree, eps, theta, ctx, grid=grid, reps=reps, log=log, corr_kind=CORR_MLP, net=net,
+                           near_ratio=r)
+        err = step_median_error(ctx, tree, eps, theta, best, net, r, sample, a_ref)
+        rows.append(dict(best, near_ratio=r, median_err=err))
+        if log:
+            log(f"  near ratio {r}: {best['group_mode']} {best['g_max']}, {best['ms']:.3f} ms, median error {err:.3e}")
+    return dict(choose_near_ratio(rows, err_target), err_target=err_target), rows
+
+
 def load_cache(path: str = DEFAULT_CACHE) -> dict:
     if os.path.exists(path):
         with open(path) as f:
@@ -116,6 +179,13 @@ def cached_schedule(workload: str, device: int = 0, path: str = DEFAULT_CACHE, m
         return sched, "defaults"
     sched.update({k: cached[k] for k in sched})
     return sched, source
+
+
+def cached_near_ratio(workload: str, device: int = 0, path: str = DEFAULT_CACHE, default: float = 0.4) -> float:
+    """The near ratio of the cached learned step (near cells) of this device
+    and workload, or `default`."""
+    cached = load_cache(path).get(cache_key(workload, "learned", device)) or {}
+    return float(cached.get("near_ratio", default))
 
 
 def apply_schedule(ctx: Context, sched: dict):

@@ -58,3 +58,27 @@ def test_corrected_step_has_its_own_cache_entry(tmp_path, monkeypatch):
     sched, source = at.cached_schedule("cube16m", path=path, mode="learned")
     assert sched == learned and source == "autotune cache (learned step)"
     assert at.cached_schedule("cube16m", path=path) == (plain, "autotune cache")
+
+
+def test_near_ratio_is_the_fastest_within_the_error_bound():
+    """The learned step's near ratio: the fastest of the ratios whose measured
+    median error holds the bound; with none holding it, the most accurate."""
+    rows = [dict(near_ratio=0.4, ms=10.5, median_err=4.5e-4), dict(near_ratio=0.5, ms=8.5, median_err=6.9e-4),
+            dict(near_ratio=0.6, ms=8.1, median_err=8.5e-4)]
+    assert at.choose_near_ratio(rows, 1e-3)["near_ratio"] == 0.6
+    assert at.choose_near_ratio(rows, 8e-4)["near_ratio"] == 0.5
+    assert at.choose_near_ratio(rows, 5e-4)["near_ratio"] == 0.4
+    assert at.choose_near_ratio(rows, 1e-4)["near_ratio"] == 0.4     # none holds it: the most accurate
+    assert at.choose_near_ratio(rows[::-1], 1e-3)["near_ratio"] == 0.6
+
+
+def test_learned_entry_carries_its_near_ratio(tmp_path, monkeypatch):
+    monkeypatch.setattr(at, "device_key", lambda device=0: "gfx950:256cu")
+    path = str(tmp_path / "cache.json")
+    assert at.cached_near_ratio("cube16m", path=path, default=0.4) == 0.4
+    entry = dict(group_mode="cell", g_max=256, chunk=16384, blocks_per_cu=6, lpt=0, tile=512, near_ratio=0.6,
+                 median_err=8.5e-4, err_target=1e-3)
+    at.save_cache(at.cache_key("cube16m", "learned"), entry, path)
+    assert at.cached_near_ratio("cube16m", path=path, default=0.4) == 0.6
+    sched, _ = at.cached_schedule("cube16m", path=path, mode="learned")
+    assert "near_ratio" not in sched and sched["g_max"] == 256

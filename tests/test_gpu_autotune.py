@@ -70,3 +70,35 @@ def test_rejected_schedule_leaves_tuning_unchanged(setup):
         ctx.autotune(tree, 0.01, [(otoo.GROUP_CHUNK, otoo.MAX_GROUP + 1)], SCHEDULES[:1], reps=1)
     assert e.value.code == otoo.EINVAL
     assert ctx.tuning().as_dict() == before
+
+
+def test_learned_step_tuned_under_an_error_bound(setup):
+    """autotune_learned: for each near ratio the fastest schedule of the
+    learned step, the step's median error at the sample measured with it
+    (against FP64 direct sums of the oracle), and the fastest ratio within the
+    bound; a bound no ratio meets gives the most accurate one."""
+    from paper_1206_1199_amd import autotune as at
+    from paper_1206_1199_amd import learned
+    ctx, tree = setup
+    before = ctx.tuning().as_dict()
+    net = learned.Network(ctx)
+    net.set_params(learned.init_params(5))   # untrained: its errors differ between ratios all the same
+    net.set_gate(0.0)
+    _, pos32, mass32, _ = tree.export(12)
+    sample = synth.sample_idx(len(mass32), 512, seed=9)
+    a_ref, _ = oracle.direct(pos32.astype(np.float64), mass32.astype(np.float64), float(np.float32(0.01)),
+                             tgt=sample)
+    # one group choice and schedule: each ratio's step, and so its error, is the same in both sweeps
+    grid = {"group": [(otoo.GROUP_CHUNK, 64)], "chunk": [2048], "blocks_per_cu": [8], "lpt": [1], "tile": [256]}
+    ratios = (0.4, 0.6)
+    best, rows = at.autotune_learned(tree, 0.01, 0.8, ctx, net, sample, a_ref, ratios=ratios, err_target=1.0,
+                                     grid=grid, reps=2)
+    assert [r["near_ratio"] for r in rows] == list(ratios)
+    for r in rows:
+        assert r["median_err"] == pytest.approx(
+            at.step_median_error(ctx, tree, 0.01, 0.8, r, net, r["near_ratio"], sample, a_ref), rel=1e-6)
+    assert best["near_ratio"] == min(rows, key=lambda r: r["ms"])["near_ratio"] and best["err_target"] == 1.0
+    strict, _ = at.autotune_learned(tree, 0.01, 0.8, ctx, net, sample, a_ref, ratios=ratios, err_target=0.0,
+                                    grid=grid, reps=2)
+    assert strict["near_ratio"] == min(rows, key=lambda r: r["median_err"])["near_ratio"]
+    assert ctx.tuning().as_dict() == before
