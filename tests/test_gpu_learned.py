@@ -528,21 +528,36 @@ def test_learned_cube_16m_captured(env, trained):
 
 
 def test_learned_cube_16m_near_captured(env, trained_near):
-    """The benchmark's default step: the GRF cube of 256^3 particles (seed 4,
-    eps 1e-3, opening angle 0.7, groups of 128), the network trained on near
-    pairs correcting the near cells, correction and force captured in one
-    graph and replayed; 2048 targets of 256 sampled groups."""
+    """The benchmark's default step in the launch configuration it is timed
+    in: the GRF cube of 256^3 particles (seed 4, eps 1e-3, opening angle
+    0.7), the learned step's cached schedule and near ratio (group size and
+    mode, chunk, workgroups, tile), the network trained on near pairs
+    correcting the near cells, correction and force captured in one graph
+    and replayed; 2048 targets of 256 sampled groups."""
+    from paper_1206_1199_amd import autotune as at
     ctx = env["ctx"]
     net = learned.Network(ctx)
     net.set_params(trained_near["params"])
+    sched, _ = at.cached_schedule("cube16m", mode="learned")
+    ratio = at.cached_near_ratio("cube16m", default=trained_near["gate"])
+    assert ratio >= trained_near["gate"]
+    print(f"schedule {sched}, near ratio {ratio}", flush=True)
     pos, m = synth.grf_cube(256, seed=4)
     tree = otoo.Tree(pos, m, n_crit=16)
     del pos, m
-    lists, pos32, mass32, cm, acc, pot = _corrected_on(ctx, tree, 0.7, 128, 1e-3, "mlp", net=net, capture=True,
-                                                       near_ratio=trained_near["gate"])
+    old = ctx.tuning()
+    at.apply_schedule(ctx, sched)
+    try:
+        lists, pos32, mass32, cm, acc, pot = _corrected_on(
+            ctx, tree, 0.7, sched["g_max"], 1e-3, "mlp", net=net, capture=True, near_ratio=ratio,
+            group_mode=otoo.GROUP_CHUNK if sched["group_mode"] == "chunk" else otoo.GROUP_CELL)
+    finally:
+        ctx.set_tuning(chunk=old.chunk, blocks_per_cu=old.blocks_per_cu, lpt=old.lpt, tile=old.tile)
+    assert 0 < int(lists.pair_off[-1]) < int(np.sum(lists.n_cellent))
     groups, tgt = sample_groups(lists, 256, 8, seed=14)
     compare(acc, pot, pos32, mass32, lists, cm, 1e-3, tgt, groups, "mlp", trained_near["params"], 0.0,
-            med_bar=2e-5, p99_bar=2e-4, label="learned on near cells, cube 2^24 theta 0.7 (graph replay)")
+            med_bar=2e-5, p99_bar=2e-4, label=f"learned on near cells (ratio {ratio}), cube 2^24 theta 0.7 "
+                                                f"(graph replay)")
     torch.cuda.empty_cache()
 
 
