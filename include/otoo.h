@@ -187,8 +187,8 @@ int otoo_set_stream(otoo_ctx* ctx, void* hip_stream);
 const char* otoo_last_error(const otoo_ctx* ctx);
 
 /* Kernel schedule knobs (the autotuner's search space).  A zero chunk,
- * blocks_per_cu or tile keeps the current value; lpt, debug_validate and
- * net_kernel are taken as given. */
+ * blocks_per_cu or tile keeps the current value; lpt, debug_validate,
+ * net_kernel and corr_chunks are taken as given. */
 typedef struct {
     int32_t chunk;        /* list entries per work item (a long list is split into items); >= 64 */
     int32_t blocks_per_cu;/* persistent workgroups per compute unit, 1..16 */
@@ -198,6 +198,9 @@ typedef struct {
     int32_t net_kernel;   /* learned correction kernel: 0 fused, registers-resident; 1 fused, LDS-staged;
                              2 (default) a network pass writing the gated pairs' tensors, then the
                              expansion pass */
+    int32_t corr_chunks;  /* the two passes of net_kernel 2: 0 (default) by the pairs' density (pair-parallel
+                             chunks of 64 pairs across groups when there are fewer than 32 pairs per group,
+                             else one group at a time), 1 one group at a time, 2 pair-parallel chunks */
 } otoo_tuning;
 int otoo_set_tuning(otoo_ctx* ctx, const otoo_tuning* tuning);
 int otoo_get_tuning(const otoo_ctx* ctx, otoo_tuning* tuning);

@@ -85,7 +85,8 @@ class _Lists(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32), ("lpt", ctypes.c_int32),
-                ("debug_validate", ctypes.c_int32), ("tile", ctypes.c_int32), ("net_kernel", ctypes.c_int32)]
+                ("debug_validate", ctypes.c_int32), ("tile", ctypes.c_int32), ("net_kernel", ctypes.c_int32),
+                ("corr_chunks", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -465,11 +466,13 @@ class Context:
         s = torch.cuda.current_stream(self.device)
         self._raise(lib().otoo_set_stream(self._h, ctypes.c_void_p(s.cuda_stream)), "otoo_set_stream")
 
-    def set_tuning(self, chunk=0, blocks_per_cu=0, lpt=None, debug_validate=None, tile=0, net_kernel=None):
+    def set_tuning(self, chunk=0, blocks_per_cu=0, lpt=None, debug_validate=None, tile=0, net_kernel=None,
+                   corr_chunks=None):
         cur = self.tuning()
         t = Tuning(chunk=chunk, blocks_per_cu=blocks_per_cu, lpt=cur.lpt if lpt is None else int(lpt),
                    debug_validate=cur.debug_validate if debug_validate is None else int(debug_validate), tile=tile,
-                   net_kernel=cur.net_kernel if net_kernel is None else int(net_kernel))
+                   net_kernel=cur.net_kernel if net_kernel is None else int(net_kernel),
+                   corr_chunks=cur.corr_chunks if corr_chunks is None else int(corr_chunks))
         self._raise(lib().otoo_set_tuning(self._h, ctypes.byref(t)), "otoo_set_tuning")
 
     def set_scratch_limit(self, max_bytes: int = 0):

@@ -194,6 +194,7 @@ int autotune_impl(otoo_ctx* c, const otoo_tree* tree, const otoo_walk_params* wa
             otoo_tuning t = schedules[si];
             t.debug_validate = 0;
             t.net_kernel = tg.saved.net_kernel;
+            t.corr_chunks = tg.saved.corr_chunks;
             c->tune = tg.saved;   // a zero field means the caller's value, not the previous schedule's
             rc = otoo_set_tuning(c, &t);
             if (rc) return rc;

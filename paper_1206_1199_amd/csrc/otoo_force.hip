@@ -993,12 +993,14 @@ int otoo_set_tuning(otoo_ctx* c, const otoo_tuning* t) {
     if (t->blocks_per_cu) nt.blocks_per_cu = t->blocks_per_cu;
     if (t->tile) nt.tile = t->tile;
     nt.net_kernel = t->net_kernel;
+    nt.corr_chunks = t->corr_chunks;
     nt.lpt = t->lpt ? 1 : 0;
     nt.debug_validate = t->debug_validate ? 1 : 0;
     if (nt.chunk < 64 || nt.chunk > (1 << 28)) return fail(c, OTOO_EINVAL, "chunk must be in 64..2^28");
     if (nt.blocks_per_cu < 1 || nt.blocks_per_cu > 16) return fail(c, OTOO_EINVAL, "blocks_per_cu must be in 1..16");
     if (nt.tile != 256 && nt.tile != 512 && nt.tile != 1024) return fail(c, OTOO_EINVAL, "tile must be 256, 512 or 1024");
     if (nt.net_kernel < 0 || nt.net_kernel > 2) return fail(c, OTOO_EINVAL, "net_kernel must be 0, 1 or 2");
+    if (nt.corr_chunks < 0 || nt.corr_chunks > 2) return fail(c, OTOO_EINVAL, "corr_chunks must be 0, 1 or 2");
     c->tune = nt;
     return OTOO_OK;
 }

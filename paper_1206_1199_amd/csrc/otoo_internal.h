@@ -172,7 +172,7 @@ struct otoo_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
-    otoo_tuning tune{1024, 8, 1, 0, 256, 2};
+    otoo_tuning tune{1024, 8, 1, 0, 256, 2, 0};
     int num_cu = 0;
     size_t scratch_cap = 0;   // largest scratch buffer allowed (0: no cap)
     // bumped whenever a scratch buffer of the context (or of a network bound

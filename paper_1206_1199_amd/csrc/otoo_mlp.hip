@@ -405,6 +405,7 @@ constexpr int kCorrSegMin = 256;
 struct CorrPlan {
     int64_t n_items;
     int32_t seg;     // pairs per item
+    int32_t chunked; // two-pass learned correction: pair-parallel chunks (sparse pairs), else one group at a time
     float* part_l;   // [n_items][kCorrStride]: 20 terms, centre xyz, pad
     float* part_r;   // [n_items][kCorrStride]
     float4* box;     // [n_groups]: box centre xyz and half-diagonal, -1 for a malformed group
@@ -716,7 +717,7 @@ __global__ __launch_bounds__(256) void k_corr_box(CorrArgs a) {
     }
 }
 
-// Group g's box from k_corr_box (wave-uniform); false for a malformed group.
+// Group g's box from k_corr_box; false for a malformed group.
 __device__ __forceinline__ bool group_box(const CorrArgs& a, int g, float& cx, float& cy, float& cz, float& h) {
     const float4 b = a.plan.box[g];
     cx = b.x;
@@ -767,6 +768,32 @@ __device__ __forceinline__ float* corr_target(const CorrArgs& a, int g, int64_t 
     if (p0 >= q0 && p1 <= q1) return a.gcorr + (int64_t)kCorrStride * g;   // whole group
     if (p0 < q0) return a.plan.part_l + (int64_t)kCorrStride * it;         // continues from an earlier item
     return a.plan.part_r + (int64_t)kCorrStride * it;                        // starts here, continues later
+}
+
+// The groups of the pairs of chunk [c0, c1) (c1 - c0 <= 64): map[j] is the
+// group of pair c0 + j.  The wave's lanes take 64 consecutive groups from
+// gcur (wave-uniform, the group of pair c0) at a time, and each writes its
+// group into map[] at the chunk positions of its pairs; groups without pairs
+// in the chunk write nothing.  On return gcur is the group of pair c1 - 1,
+// from which the next chunk's groups start.
+__device__ __forceinline__ void chunk_groups(const CorrArgs& a, int lane, int64_t c0, int64_t c1, int& gcur,
+                                             int* map) {
+    map[lane] = gcur;   // a valid group for every slot (malformed pair offsets leave slots unwritten)
+    __builtin_amdgcn_wave_barrier();
+    for (;;) {
+        const int g = gcur + lane;
+        int64_t p0 = a.n_pairs, p1 = a.n_pairs;
+        if (g < a.n_groups) pair_range(a, g, p0, p1);
+        const int64_t lo = p0 > c0 ? p0 : c0, hi = p1 < c1 ? p1 : c1;
+        for (int64_t p = lo; p < hi; p++) map[p - c0] = g;
+        // the run covers the chunk once its last group ends at or after c1
+        const int64_t last = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)p1 >> 32), 63) << 32) |
+                                       (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)p1, 63));
+        if (last >= c1 || gcur + 64 >= a.n_groups) break;
+        gcur += 64;
+    }
+    __builtin_amdgcn_wave_barrier();
+    gcur = __builtin_amdgcn_readfirstlane(map[c1 - 1 - c0]);
 }
 
 // Rows of the groups that straddle items (partials added in item order) and
@@ -1195,7 +1222,17 @@ struct GnetQueue {
     alignas(16) uint16_t x[kGQ][16];   // BF16 features 0..11, then zeros (the first 16 of the K = 32 inputs)
     float sc[kGQ];
     int64_t p[kGQ];
+    int map[64];                       // chunked passes: the group of each pair of the chunk
 };
+
+// The network inputs of a pair as queued: its features in BF16 (the pair's
+// own six, then the cell's normalised second moments), zeros after them.
+__device__ __forceinline__ void pack_inputs(const float fe[6], const CellRec& r, uint4& x0, uint4& x1) {
+    x0 = make_uint4((uint32_t)f2bf(fe[0]) | ((uint32_t)f2bf(fe[1]) << 16),
+                    (uint32_t)f2bf(fe[2]) | ((uint32_t)f2bf(fe[3]) << 16),
+                    (uint32_t)f2bf(fe[4]) | ((uint32_t)f2bf(fe[5]) << 16), r.s[0]);
+    x1 = make_uint4(r.s[1], r.s[2], 0u, 0u);
+}
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_corr_gnet(CorrArgs a, float* __restrict__ qbuf) {
     __shared__ float sb[NH + NH + NOUTP];
@@ -1219,7 +1256,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     __syncthreads();
 
     // the network on queue slots [0, cnt)
-    auto run_net = [&](int cnt) {
+    auto run_net = [&](int cnt) __attribute__((always_inline)) {
 #pragma unroll
         for (int tau = 0; tau < 4; tau++) {
             const int slot = tau * 16 + r16;
@@ -1261,67 +1298,107 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     };
 
     int pend = 0;   // queued pairs, uniform within the wave
-    const ItemRange ir = xcd_items(a.plan.n_items);
-    for (int64_t it = ir.first; it < ir.end; it += ir.step)
-    for (int g = group_of_pair(a, it * a.plan.seg); g < a.n_groups; g++) {
-        const int64_t q0 = it * a.plan.seg;
-        const int64_t q1 = q0 + a.plan.seg < a.n_pairs ? q0 + a.plan.seg : a.n_pairs;
-        int64_t p0, p1;
-        pair_range(a, g, p0, p1);
-        if (p0 >= q1) break;
-        const int64_t a0 = p0 > q0 ? p0 : q0, a1 = p1 < q1 ? p1 : q1;
-        if (a1 <= a0) continue;   // no pairs of this group in the item
-        float cx, cy, cz, h;
-        if (!group_box(a, g, cx, cy, cz, h)) continue;   // flagged by k_corr_box
-        int64_t lb, le;
-        list_range(a.list_off, a.n_entries, g, lb, le);
-        const int64_t k0 = a0 - p0, k1 = (a1 - p0) < (le - lb) ? (a1 - p0) : (le - lb);
-        for (int64_t base = k0; base < k1; base += 64) {
-            const int64_t k = base + lane;
-            bool gated = false;
-            float fe[6];
-            CellRec r{};
-            if (k < k1) {
-                const int64_t c = (int64_t)a.list_idx[lb + k] - a.n;   // a bad entry is flagged by k_corr_apply
-                if (c >= 0 && c < a.n_cells) {
-                    r = load_cell_rec(a.plan.crec, c);
-                    if (rec_features(cx, cy, cz, h, r, a.eps, fe)) gated = bf_round(fe[3]) >= a.gate;
-                }
+    // the pair of this lane (global pair number p, its BF16 inputs x0 | x1
+    // and scale sc) joins the queue if `gated`; a full batch runs the network
+    auto offer = [&](bool gated, uint4 x0, uint4 x1, float sc, int64_t p) __attribute__((always_inline)) {
+        const uint64_t mask = __ballot(gated);
+        if (gated) {
+            const int slot = pend + __popcll(mask & ((1ull << lane) - 1ull));   // pend < 64
+            uint4* dst = reinterpret_cast<uint4*>(Q.x[slot]);
+            dst[0] = x0;
+            dst[1] = x1;
+            Q.sc[slot] = sc;
+            Q.p[slot] = p;
+        }
+        pend += __popcll(mask);
+        __builtin_amdgcn_wave_barrier();
+        if (pend >= 64) {
+            run_net(64);
+            const int rest = pend - 64;   // < 64, moved from [64, pend) to the front
+            uint4 x0 = {}, x1 = {};
+            float s = 0.f;
+            int64_t pp = 0;
+            if (lane < rest) {
+                x0 = reinterpret_cast<const uint4*>(Q.x[64 + lane])[0];
+                x1 = reinterpret_cast<const uint4*>(Q.x[64 + lane])[1];
+                s = Q.sc[64 + lane];
+                pp = Q.p[64 + lane];
             }
-            const uint64_t mask = __ballot(gated);
-            if (gated) {
-                const int slot = pend + __popcll(mask & ((1ull << lane) - 1ull));   // pend < 64
-                uint4* dst = reinterpret_cast<uint4*>(Q.x[slot]);
-                dst[0] = make_uint4((uint32_t)f2bf(fe[0]) | ((uint32_t)f2bf(fe[1]) << 16),
-                                    (uint32_t)f2bf(fe[2]) | ((uint32_t)f2bf(fe[3]) << 16),
-                                    (uint32_t)f2bf(fe[4]) | ((uint32_t)f2bf(fe[5]) << 16), r.s[0]);
-                dst[1] = make_uint4(r.s[1], r.s[2], 0u, 0u);
-                Q.sc[slot] = r.sc;
-                Q.p[slot] = p0 + k;
-            }
-            pend += __popcll(mask);
             __builtin_amdgcn_wave_barrier();
-            if (pend >= 64) {
-                run_net(64);
-                const int rest = pend - 64;   // < 64, moved from [64, pend) to the front
+            if (lane < rest) {
+                reinterpret_cast<uint4*>(Q.x[lane])[0] = x0;
+                reinterpret_cast<uint4*>(Q.x[lane])[1] = x1;
+                Q.sc[lane] = s;
+                Q.p[lane] = pp;
+            }
+            __builtin_amdgcn_wave_barrier();
+            pend = rest;
+        }
+    };
+    const ItemRange ir = xcd_items(a.plan.n_items);
+    if (a.plan.chunked) {
+        // pair-parallel: chunks of 64 consecutive pairs, each lane with its own group
+        for (int64_t it = ir.first; it < ir.end; it += ir.step) {
+            const int64_t q0 = it * a.plan.seg;
+            const int64_t q1 = q0 + a.plan.seg < a.n_pairs ? q0 + a.plan.seg : a.n_pairs;
+            int gcur = group_of_pair(a, q0);
+            for (int64_t c0 = q0; c0 < q1; c0 += 64) {
+                const int64_t c1 = c0 + 64 < q1 ? c0 + 64 : q1;
+                chunk_groups(a, lane, c0, c1, gcur, Q.map);
+                const int64_t p = c0 + lane;
+                bool gated = false;
+                float fe[6];
+                CellRec r{};
+                if (p < c1) {
+                    const int g = Q.map[lane];
+                    int64_t p0, p1, lb, le;
+                    pair_range(a, g, p0, p1);
+                    list_range(a.list_off, a.n_entries, g, lb, le);
+                    float cx, cy, cz, h;
+                    const int64_t k = p - p0;
+                    if (group_box(a, g, cx, cy, cz, h) && k >= 0 && k < le - lb) {
+                        const int64_t c = (int64_t)a.list_idx[lb + k] - a.n;   // a bad entry is flagged by k_corr_apply
+                        if (c >= 0 && c < a.n_cells) {
+                            r = load_cell_rec(a.plan.crec, c);
+                            if (rec_features(cx, cy, cz, h, r, a.eps, fe)) gated = bf_round(fe[3]) >= a.gate;
+                        }
+                    }
+                }
                 uint4 x0 = {}, x1 = {};
-                float s = 0.f;
-                int64_t pp = 0;
-                if (lane < rest) {
-                    x0 = reinterpret_cast<const uint4*>(Q.x[64 + lane])[0];
-                    x1 = reinterpret_cast<const uint4*>(Q.x[64 + lane])[1];
-                    s = Q.sc[64 + lane];
-                    pp = Q.p[64 + lane];
+                if (gated) pack_inputs(fe, r, x0, x1);
+                offer(gated, x0, x1, r.sc, p);
+            }
+        }
+    } else {
+        for (int64_t it = ir.first; it < ir.end; it += ir.step)
+        for (int g = group_of_pair(a, it * a.plan.seg); g < a.n_groups; g++) {
+            const int64_t q0 = it * a.plan.seg;
+            const int64_t q1 = q0 + a.plan.seg < a.n_pairs ? q0 + a.plan.seg : a.n_pairs;
+            int64_t p0, p1;
+            pair_range(a, g, p0, p1);
+            if (p0 >= q1) break;
+            const int64_t a0 = p0 > q0 ? p0 : q0, a1 = p1 < q1 ? p1 : q1;
+            if (a1 <= a0) continue;   // no pairs of this group in the item
+            float cx, cy, cz, h;
+            if (!group_box(a, g, cx, cy, cz, h)) continue;   // flagged by k_corr_box
+            int64_t lb, le;
+            list_range(a.list_off, a.n_entries, g, lb, le);
+            const int64_t k0 = a0 - p0, k1 = (a1 - p0) < (le - lb) ? (a1 - p0) : (le - lb);
+            for (int64_t base = k0; base < k1; base += 64) {
+                const int64_t k = base + lane;
+                bool gated = false;
+                float fe[6];
+                CellRec r{};
+                if (k < k1) {
+                    const int64_t c = (int64_t)a.list_idx[lb + k] - a.n;   // a bad entry is flagged by k_corr_apply
+                    if (c >= 0 && c < a.n_cells) {
+                        r = load_cell_rec(a.plan.crec, c);
+                        if (rec_features(cx, cy, cz, h, r, a.eps, fe)) gated = bf_round(fe[3]) >= a.gate;
+                    }
                 }
-                __builtin_amdgcn_wave_barrier();
-                if (lane < rest) {
-                    reinterpret_cast<uint4*>(Q.x[lane])[0] = x0;
-                    reinterpret_cast<uint4*>(Q.x[lane])[1] = x1;
-                    Q.sc[lane] = s;
-                    Q.p[lane] = pp;
-                }
-                __builtin_amdgcn_wave_barrier();
-                pend = rest;
+                uint4 x0 = {}, x1 = {};
+                if (gated) pack_inputs(fe, r, x0, x1);
+                offer(gated, x0, x1, r.sc, p0 + k);
             }
         }
     }
@@ -1344,6 +1421,8 @@ __device__ __forceinline__ ApCell load_ap_cell(const CorrArgs& a, CorrEntry en, 
 
 struct ApList {
     float4 com[kApList];   // COM xyz, the pair's offset from the item segment's first pair (as float bits)
+    int map[64];           // chunked pass: the group of each pair of the chunk
+    float carry[kCorrTerms];   // chunked pass: the open group's sum over the item's earlier chunks
 };
 
 __global__ __launch_bounds__(256) void k_corr_apply(CorrArgs a, const float* __restrict__ qbuf) {
@@ -1352,6 +1431,98 @@ __global__ __launch_bounds__(256) void k_corr_apply(CorrArgs a, const float* __r
     ApList& L = sl[w];
     const float eps2 = a.eps * a.eps;
     const ItemRange ir = xcd_items(a.plan.n_items);
+    if (a.plan.chunked) {
+        // pair-parallel: chunks of 64 consecutive pairs, each lane with its own group; the lanes'
+        // expansion terms are summed per group by a segmented scan across the wave, a group that
+        // continues into the next chunk is carried over, and each group's sum over the item goes
+        // where corr_target puts it
+        bool bad = false;
+        for (int64_t it = ir.first; it < ir.end; it += ir.step) {
+            const int64_t q0 = it * a.plan.seg;
+            const int64_t q1 = q0 + a.plan.seg < a.n_pairs ? q0 + a.plan.seg : a.n_pairs;
+            int gcur = group_of_pair(a, q0);
+            int carry_g = -1;   // uniform
+            for (int64_t c0 = q0; c0 < q1; c0 += 64) {
+                const int64_t c1 = c0 + 64 < q1 ? c0 + 64 : q1;
+                chunk_groups(a, lane, c0, c1, gcur, L.map);
+                const int64_t p = c0 + lane;
+                const bool act = p < c1;
+                const int g = act ? L.map[lane] : -1;
+                float f[kCorrTerms];
+#pragma unroll
+                for (int k = 0; k < kCorrTerms; k++) f[k] = 0.f;
+                float cx = 0.f, cy = 0.f, cz = 0.f, h = 0.f;
+                int64_t p0 = 0, p1 = 0;
+                if (act) {
+                    pair_range(a, g, p0, p1);
+                    const bool ok = group_box(a, g, cx, cy, cz, h);
+                    int64_t lb, le;
+                    list_range(a.list_off, a.n_entries, g, lb, le);
+                    const int64_t k = p - p0;   // the group's cells lead its list
+                    if (ok && a.n_cells > 0 && k >= 0 && k < le - lb) {
+                        const int64_t c = (int64_t)a.list_idx[lb + k] - a.n;
+                        if (c >= 0 && c < a.n_cells) {
+                            const CellRec r = load_cell_rec(a.plan.crec, c);
+                            float fe[6];
+                            if (rec_features(cx, cy, cz, h, r, a.eps, fe)) {
+                                if (bf_round(fe[3]) >= a.gate) {
+                                    const float* row = qbuf + (int64_t)kQRow * p;
+                                    const float4 r0 = *reinterpret_cast<const float4*>(row);
+                                    const float2 r1 = *reinterpret_cast<const float2*>(row + 4);
+                                    const float Qv[6] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y};
+                                    quad_expand_add(cx - r.com[0], cy - r.com[1], cz - r.com[2], Qv, eps2, f);
+                                } else {
+                                    float o[NOUT];
+#pragma unroll
+                                    for (int m = 0; m < NOUT; m++) o[m] = 3.f * rec_s(r, m);
+                                    expand_outputs(o, r.sc, cx - r.com[0], cy - r.com[1], cz - r.com[2], eps2, f);
+                                }
+                            }
+                        } else {
+                            bad = true;
+                        }
+                    }
+                }
+                if (lane == 0 && carry_g >= 0 && g == carry_g) {
+#pragma unroll
+                    for (int k = 0; k < kCorrTerms; k++) f[k] += L.carry[k];
+                }
+                // segmented inclusive scan: the lanes of one group are contiguous.  Every lane
+                // takes part in each shuffle (a permute reads nothing from a lane that is off)
+                const int g_prev = __shfl(g, lane > 0 ? lane - 1 : 0);
+                const bool head = (lane == 0) | (g != g_prev);
+                const uint64_t heads = __ballot(head);
+                const int first = 63 - __clzll(heads & ((2ull << lane) - 1ull));
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int src = lane >= d ? lane - d : 0;
+#pragma unroll
+                    for (int k = 0; k < kCorrTerms; k++) {
+                        const float v = __shfl(f[k], src);
+                        if (lane - d >= first) f[k] += v;
+                    }
+                }
+                const bool seg_last = lane == 63 || ((heads >> (lane + 1)) & 1ull);
+                const int64_t end = p1 < q1 ? p1 : q1;   // one past the group's last pair in this item
+                const bool cont = act && seg_last && end > c1;
+                const uint64_t cm = __ballot(cont);
+                __builtin_amdgcn_wave_barrier();
+                if (cont) {
+#pragma unroll
+                    for (int k = 0; k < kCorrTerms; k++) L.carry[k] = f[k];
+                }
+                carry_g = cm ? __builtin_amdgcn_readlane(g, (int)(c1 - c0 - 1)) : -1;
+                if (act && seg_last && !cont) {
+                    float4* o4 = reinterpret_cast<float4*>(corr_target(a, g, it, p0, p1, q0, q1));
+#pragma unroll
+                    for (int k = 0; k < 5; k++) o4[k] = make_float4(f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]);
+                    o4[5] = make_float4(cx, cy, cz, 0.f);
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        if (bad) atomicOr(a.err, kErrIndex);
+        return;
+    }
     for (int64_t it = ir.first; it < ir.end; it += ir.step) {
         const int64_t q0 = it * a.plan.seg;
         const int64_t q1 = q0 + a.plan.seg < a.n_pairs ? q0 + a.plan.seg : a.n_pairs;
@@ -2288,6 +2459,8 @@ int otoo_correction(otoo_ctx* c, int32_t kind, otoo_mlp* m, int32_t n, const flo
     pl.seg = kCorrSeg;
     while (pl.seg > kCorrSegMin && (n_pairs + pl.seg - 1) / pl.seg < 4 * waves) pl.seg /= 2;
     pl.n_items = (n_pairs + pl.seg - 1) / pl.seg;
+    // sparse pairs (few per group, e.g. the nearest cells only): pair-parallel chunks
+    pl.chunked = split && (c->tune.corr_chunks == 2 || (c->tune.corr_chunks == 0 && n_pairs < 32LL * n_groups));
     const size_t part_bytes = align256(sizeof(float) * kCorrStride * (size_t)std::max<int64_t>(pl.n_items, 1));
     const size_t box_bytes = align256(sizeof(float4) * (size_t)n_groups);
     const size_t qbuf_bytes = split ? align256(sizeof(float) * kQRow * (size_t)std::max<int64_t>(n_pairs, 1)) : 0;

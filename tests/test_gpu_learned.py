@@ -400,8 +400,9 @@ def test_training_reduces_loss_and_helps_forces(env, trained, trained_near, case
     assert e_l <= bar_q * e_q
 
 
-@pytest.mark.parametrize("net_kernel,gate", [(0, 0.0), (1, 0.0), (2, 0.0), (0, 0.4), (1, 0.4), (2, 0.4)])
-def test_fused_learned_correction_matches_oracle(env, net_kernel, gate):
+@pytest.mark.parametrize("net_kernel,gate,chunks", [(0, 0.0, 0), (1, 0.0, 0), (2, 0.0, 1), (2, 0.0, 2), (0, 0.4, 0),
+                                                    (1, 0.4, 0), (2, 0.4, 1), (2, 0.4, 2)])
+def test_fused_learned_correction_matches_oracle(env, net_kernel, gate, chunks):
     """The fused per-group learned correction (register-resident network, or
     the LDS-staged one) and the force, against the oracle's list force with
     the oracle network's tensors: element by element against the expanded
@@ -410,20 +411,20 @@ def test_fused_learned_correction_matches_oracle(env, net_kernel, gate):
     ctx, net, d, lists, cm, pos32, mass32 = (env[k] for k in ("ctx", "net", "d", "lists", "cm", "pos32", "mass32"))
     net.set_params(env["params"])
     old = ctx.tuning()
-    ctx.set_tuning(net_kernel=net_kernel)
+    ctx.set_tuning(net_kernel=net_kernel, corr_chunks=chunks)
     net.set_gate(gate)
     try:
         gc = ctx.correction(d, otoo.CORR_MLP, EPS, net=net)
     finally:
         ctx.set_tuning(chunk=old.chunk, blocks_per_cu=old.blocks_per_cu, lpt=old.lpt, tile=old.tile,
-                       net_kernel=old.net_kernel)
+                       net_kernel=old.net_kernel, corr_chunks=old.corr_chunks)
         net.set_gate(0.0)
     acc, pot = ctx.force(d, EPS, gcorr=gc)
     torch.cuda.synchronize()
     ctx.check()
     groups, tgt = sample_groups(lists, lists.n_groups, 16, seed=7)
     compare(acc.cpu().numpy(), pot.cpu().numpy(), pos32, mass32, lists, cm, EPS, tgt, groups, "mlp", env["params"],
-            gate, med_bar=2e-5, p99_bar=2e-4, label=f"learned 16k kernel {net_kernel} gate {gate}")
+            gate, med_bar=2e-5, p99_bar=2e-4, label=f"learned 16k kernel {net_kernel} gate {gate} chunks {chunks}")
 
 
 def _corrected_on(ctx, tree, theta, g_max, eps, kind, net=None, group_mode=otoo.GROUP_CHUNK, capture=False,
@@ -451,29 +452,36 @@ def _corrected_on(ctx, tree, theta, g_max, eps, kind, net=None, group_mode=otoo.
     return lists, pos32, mass32, cm, out[0].cpu().numpy(), out[1].cpu().numpy()
 
 
-@pytest.mark.parametrize("kind,net_kernel", [("mlp", 0), ("mlp", 1), ("mlp", 2), ("quad", 2)])
-def test_near_pairs_match_oracle(env, kind, net_kernel):
+@pytest.mark.parametrize("kind,net_kernel,chunks,ratio", [("mlp", 0, 0, 0.4), ("mlp", 1, 0, 0.4), ("mlp", 2, 1, 0.4),
+                                                          ("mlp", 2, 2, 0.4), ("mlp", 2, 0, 0.6), ("quad", 2, 0, 0.4)])
+def test_near_pairs_match_oracle(env, kind, net_kernel, chunks, ratio):
     """Walks that list each group's near cells first (ratio 0.4) and make
     them the (group, cell) pairs: the correction covers those cells alone
     and the far cells, and the particles, enter as monopoles.  The device's
     correction and force against the oracle's list force with tensors on the
-    near cells only, every group of the 16k Plummer sphere at theta 0.7."""
+    near cells only, every group of the 16k Plummer sphere at theta 0.7.
+    The two-pass correction runs one group at a time (chunks 1) or in
+    pair-parallel chunks across groups (chunks 2; chosen by itself for the
+    sparse pairs of ratio 0.6)."""
     ctx, net, tree = env["ctx"], env["net"], env["tree"]
     net.set_params(env["params"])
     old = ctx.tuning()
-    ctx.set_tuning(net_kernel=net_kernel)
+    ctx.set_tuning(net_kernel=net_kernel, corr_chunks=chunks)
     try:
-        lists, pos32, mass32, cm, acc, pot = _corrected_on(ctx, tree, 0.7, 64, EPS, kind, net=net, near_ratio=0.4)
+        lists, pos32, mass32, cm, acc, pot = _corrected_on(ctx, tree, 0.7, 64, EPS, kind, net=net,
+                                                           near_ratio=ratio)
     finally:
         ctx.set_tuning(chunk=old.chunk, blocks_per_cu=old.blocks_per_cu, lpt=old.lpt, tile=old.tile,
-                       net_kernel=old.net_kernel)
+                       net_kernel=old.net_kernel, corr_chunks=old.corr_chunks)
+    if chunks == 0 and kind == "mlp" and ratio == 0.6:   # the automatic choice there is the chunked pass
+        assert int(lists.pair_off[-1]) < 32 * lists.n_groups
     n_near, n_cellent = np.asarray(lists.n_near), np.asarray(lists.n_cellent)
     assert np.all(n_near <= n_cellent) and 0 < n_near.sum() < n_cellent.sum()
     assert int(lists.pair_off[-1]) == n_near.sum()
     groups, tgt = sample_groups(lists, lists.n_groups, 8, seed=21)
     compare(acc, pot, pos32, mass32, lists, cm, EPS, tgt, groups, kind, env["params"] if kind == "mlp" else None,
             0.0, med_bar=2e-5 if kind == "mlp" else 1e-6, p99_bar=2e-4 if kind == "mlp" else 1e-5,
-            label=f"{kind} on near cells, kernel {net_kernel}")
+            label=f"{kind} on near cells (ratio {ratio}), kernel {net_kernel}, chunks {chunks}")
 
 
 @pytest.mark.parametrize("n,theta,g_max", [(16384, 0.8, 64), (1 << 20, 0.9, 128)])
@@ -562,12 +570,13 @@ def test_learned_cube_16m_near_captured(env, trained_near):
 
 
 @pytest.mark.parametrize("gate", [0.0, 0.3])
-@pytest.mark.parametrize("net_kernel", [0, 1, 2])
-def test_queue_rounds_on_long_lists(env, gate, net_kernel):
+@pytest.mark.parametrize("net_kernel,chunks", [(0, 0), (1, 0), (2, 1), (2, 2)])
+def test_queue_rounds_on_long_lists(env, gate, net_kernel, chunks):
     """Groups of 256 at theta 0.5 hold thousands of cells, so the register-
     resident kernel's queue of gated pairs runs many rounds and carries a
-    remainder between them (and the LDS-staged kernel many chunks).  Each
-    group's expansion terms {A, Phi, J, H} and centre, against the oracle's
+    remainder between them (and the LDS-staged kernel many chunks; the
+    pair-parallel two-pass kernels carry a group's sum from chunk to chunk
+    and split it between items).  Each group's expansion terms {A, Phi, J, H} and centre, against the oracle's
     sums over the group's cells of the quadrupole-form field derivatives of
     the oracle network's tensors (oracle.quad_derivs at the box centre), term
     by term: within the tensors' BF16 allowance carried through each term,
@@ -584,12 +593,12 @@ def test_queue_rounds_on_long_lists(env, gate, net_kernel):
     old = ctx.tuning()
     net.set_gate(gate)
     try:
-        ctx.set_tuning(net_kernel=net_kernel)
+        ctx.set_tuning(net_kernel=net_kernel, corr_chunks=chunks)
         gc = ctx.correction(d, otoo.CORR_MLP, EPS, net=net).cpu().numpy().astype(np.float64)
     finally:
         net.set_gate(0.0)
         ctx.set_tuning(chunk=old.chunk, blocks_per_cu=old.blocks_per_cu, lpt=old.lpt, tile=old.tile,
-                       net_kernel=old.net_kernel)
+                       net_kernel=old.net_kernel, corr_chunks=old.corr_chunks)
     ctx.check()
     rng = np.random.default_rng(17)
     groups = np.sort(rng.choice(lists.n_groups, 24, replace=False))
