@@ -819,8 +819,8 @@ def main():
         else:
             # a bounded sample: every k-th group, k chosen for about 12 s of oracle work on 16 threads
             # (measured rates: about 6 us per (group, cell) pair for the FP64 network and its tensors,
-            # 3e8 interactions/s for the list sums)
-            est_s = 6e-6 * n_pairs + inter / 3e8
+            # 8e8 interactions/s for the list sums)
+            est_s = 6e-6 * n_pairs + inter / 8e8
             step_g = int(min(max(1, np.ceil(est_s / 12.0)), max(1, lists.n_groups // 256)))
             groups = np.arange(0, lists.n_groups, step_g, dtype=np.int64)
             go = np.asarray(lists.group_off, np.int64)
