@@ -320,7 +320,7 @@ def learned_comparison(ctx, net, training, log, timing_reps):
     the textbook quadrupole and the learned correction, all timed per force
     evaluation with the best of a few schedules per setting.  A network
     trained on near pairs corrects the near cells of walks that list them
-    first (near ratio = its training gate)."""
+    first, at near ratio = its training gate and at 0.6."""
     import torch
     import synth
     import paper_1206_1199_amd as otoo
@@ -377,7 +377,8 @@ def learned_comparison(ctx, net, training, log, timing_reps):
                     ctx.force(d, eps, out=out)
             ms = timed(step)
             err = rel_err(out[0].cpu().numpy()[sample], a_dir)
-            rows.append(dict(mode=mode, theta=theta, g_max=g_max, ms=ms, interactions=lists.interactions,
+            rows.append(dict(mode=mode, theta=theta, g_max=g_max, near_ratio=near_ratio, ms=ms,
+                             interactions=lists.interactions,
                              pairs=d.n_pairs, median_err=float(np.median(err)),
                              p99_err=float(np.quantile(err, 0.99)), schedule=best_s))
         return rows
@@ -390,10 +391,12 @@ def learned_comparison(ctx, net, training, log, timing_reps):
     for g_max, ths in ((32, (0.8, 0.9)), (64, (0.8, 0.85, 0.9, 0.95, 1.0)), (128, (0.8, 0.85, 0.9, 0.95, 1.0))):
         for th in ths:
             rows += run(th, ("quad",), g_max)
-            rows += run(th, ("learned",), g_max, near_ratio)
+            for ratio in ((near_ratio, 0.6) if near_ratio > 0 else (0.0,)):   # the training ratio, and 0.6
+                rows += run(th, ("learned",), g_max, ratio)
     for r in rows:
-        log(f"  {r['mode']:8s} g_max {r['g_max']:3d} theta {r['theta']:.2f}: {r['ms']:.3f} ms, "
-            f"median err {r['median_err']:.2e}, pairs {r['pairs']}")
+        log(f"  {r['mode']:8s} g_max {r['g_max']:3d} theta {r['theta']:.2f}"
+            + (f" ratio {r['near_ratio']:.2f}" if r["near_ratio"] > 0 else "")
+            + f": {r['ms']:.3f} ms, median err {r['median_err']:.2e}, pairs {r['pairs']}")
     ok = lambda mode: [r for r in rows if r["mode"] == mode and r["median_err"] <= 1e-3]
     best = {mode: (min(ok(mode), key=lambda r: r["ms"]) if ok(mode) else None) for mode in ("plain", "quad", "learned")}
     plain05 = min((r for r in rows if r["mode"] == "plain" and r["theta"] == 0.5), key=lambda r: r["ms"])
