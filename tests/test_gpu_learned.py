@@ -661,3 +661,40 @@ def test_captured_correction_and_force_replay_matches_eager(env):
         ctx.check()
     finally:
         net.set_gate(0.0)
+
+
+@pytest.mark.parametrize("chunks", [1, 2])
+def test_malformed_pair_entries_are_reported(env, chunks):
+    """A (group, cell) pair whose list entry is out of range, or a particle,
+    is skipped by the two-pass learned correction (one group at a time or in
+    pair-parallel chunks) and reported by otoo_check; the flag clears, and
+    the same context then corrects valid lists as before."""
+    ctx, net, d, lists = env["ctx"], env["net"], env["d"], env["lists"]
+    net.set_params(env["params"])
+    lo = np.asarray(lists.list_off, np.int64)
+    old = ctx.tuning()
+    ctx.set_tuning(net_kernel=2, corr_chunks=chunks)
+    try:
+        ref = ctx.correction(d, otoo.CORR_MLP, EPS, net=net).clone()
+        torch.cuda.synchronize()
+        ctx.check()
+        for g, value in ((3, d.n + d.n_cells + 7), (17, 0)):     # out of range; a particle where a cell is due
+            bad = d.list_idx.clone()
+            bad[int(lo[g])] = value
+            d_bad = otoo.DeviceLists(d.pos, d.mass, d.group_off, d.list_off, bad, d.cell_mom, d.pair_off,
+                                     d.n_entries, d.interactions)
+            gc = ctx.correction(d_bad, otoo.CORR_MLP, EPS, net=net)
+            torch.cuda.synchronize()
+            with pytest.raises(otoo.OtooError):
+                ctx.check()
+            ctx.check()                                         # flag cleared
+            others = np.ones(d.n_groups, bool)
+            others[g] = False
+            assert torch.equal(gc[torch.from_numpy(others).cuda()], ref[torch.from_numpy(others).cuda()])
+        again = ctx.correction(d, otoo.CORR_MLP, EPS, net=net)
+        torch.cuda.synchronize()
+        ctx.check()
+        assert torch.equal(again, ref)
+    finally:
+        ctx.set_tuning(chunk=old.chunk, blocks_per_cu=old.blocks_per_cu, lpt=old.lpt, tile=old.tile,
+                       net_kernel=old.net_kernel, corr_chunks=old.corr_chunks)
