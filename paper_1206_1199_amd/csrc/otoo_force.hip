@@ -377,15 +377,56 @@ __device__ __forceinline__ void pair_mono(float xi, float yi, float zi, float4 s
     ph += mr;
 }
 
+constexpr int kPadRows = 64;   // zero-mass records after each LDS tile
+
+// The wave parts of a group of ng targets that does not divide the
+// workgroup: part j takes n[j] consecutive targets and splits each tile into
+// S = 64 / n[j] slices, so it runs about TILE / S rows.  The largest part,
+// c = 64 / (64 / ceil(ng / 4)) targets, keeps the longest row count to that
+// of a workgroup-wide layout; as many parts as fit take c targets, the rest
+// of the targets goes to the remaining parts in the largest counts 64 / S
+// that fit, and the last part takes what is left.  Scalar code, per item.
+__device__ __forceinline__ void part_counts(int ng, int (&n)[4]) {
+    const int c = 64 / (64 / ((ng + 3) >> 2));
+    const int nfull = ng / c;                // at most 4
+    int r = ng - nfull * c;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        if (j < nfull) {
+            n[j] = c;
+        } else if (j == 3) {
+            n[j] = r;
+        } else {
+            n[j] = r > 0 ? 64 / (64 / (r + 1) + 1) : 0;   // largest 64 / S <= r
+            r -= n[j];
+        }
+    }
+}
+
+// Wave rows of a full tile: the parts, and the workgroup-wide layout with
+// S = 256 / ng slices (the waves whose lanes are all past S ng skip the tile).
+template <int TILE>
+__device__ __forceinline__ bool use_parts(int ng) {
+    if (kBlock % ng == 0) return false;
+    const int S = kBlock / ng;
+    if (S > kPadRows + 1) return true;       // its last slice would run past the zero records
+    int n[4];
+    part_counts(ng, n);
+    int part_rows = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) part_rows += n[j] > 0 ? (TILE + 64 / n[j] - 1) / (64 / n[j]) : 0;
+    const int shared_rows = ((S * ng + 63) >> 6) * ((TILE + S - 1) / S);
+    return part_rows < shared_rows;
+}
+
 // One work item as every thread of the workgroup sees it.  The values are
 // the same in every lane (loads of one address); readfirstlane keeps them,
 // and the control of the tile loop, in scalar registers (integer division
 // and 64-bit compares run on the vector unit).
 struct ItemGeo {
     int g, k, g0, ng;
-    int S;             // slices: lanes are (target, slice)
-    int rows_full;     // rows of a full tile per slice
-    int tstride;       // entries per tile, a multiple of S
+    int S;             // slices of the workgroup-wide layout, 256 / ng
+    bool shared;       // lanes (t mod ng, t / ng) across the workgroup, else wave parts
     int clen;          // entries of this item (at most one chunk)
     int64_t nch;       // items of the group's list
     const int32_t* idx;   // the item's entries, idx[0 .. clen)
@@ -411,8 +452,7 @@ __device__ __forceinline__ bool decode_item(const ForceArgs& a, int q, ItemGeo& 
     m.clen = __builtin_amdgcn_readfirstlane(rest <= 0 ? 0 : (rest < a.chunk ? (int)rest : a.chunk));
     m.idx = a.list_idx + cb;
     m.S = __builtin_amdgcn_readfirstlane(kBlock / m.ng);
-    m.rows_full = __builtin_amdgcn_readfirstlane(TILE / m.S);
-    m.tstride = m.S * m.rows_full;
+    m.shared = !use_parts<TILE>(m.ng);
     return true;
 }
 
@@ -423,13 +463,13 @@ __device__ __forceinline__ bool decode_item(const ForceArgs& a, int q, ItemGeo& 
 // source-record loads for those indices (absent entries are zero mass).
 // Waiting for an index load right after issuing it would also wait for every
 // load issued before it (the vector memory counter drains in order).
-template <int L>
+template <int TILE, int L>
 __device__ __forceinline__ void load_idx(const ItemGeo& m, int t, int base, int32_t (&j)[L], bool (&has)[L]) {
 #pragma unroll
     for (int l = 0; l < L; l++) {
         const int te = t + l * kBlock;
         const int e = base + te;
-        has[l] = te < m.tstride && e < m.clen;
+        has[l] = te < TILE && e < m.clen;
         j[l] = has[l] ? m.idx[e] : 0;
     }
 }
@@ -449,12 +489,14 @@ __device__ __forceinline__ void load_src(const ForceArgs& a, const int32_t (&j)[
     }
 }
 
-// TILE list entries are staged in LDS per tile (TILE / kBlock per thread).
+// TILE list entries are staged in LDS per tile (TILE / kBlock per thread),
+// followed by kPadRows zero-mass records that the last slice of a target may
+// run into.
 template <int TILE>
 __device__ __forceinline__ void force_items(const ForceArgs& a) {
     constexpr int L = TILE / kBlock;
     static_assert(L * kBlock == TILE && L >= 1, "tile must be a multiple of the workgroup");
-    __shared__ float4 tile[2][TILE];
+    __shared__ float4 tile[2][TILE + kPadRows];
     __shared__ int s_q;
     const int t = threadIdx.x;
     const int64_t n_items = uniform64(a.meta->n_items < a.item_cap ? a.meta->n_items : a.item_cap);
@@ -470,16 +512,49 @@ __device__ __forceinline__ void force_items(const ForceArgs& a) {
             if (t == 0) atomicOr(a.err, kErrGroup);
             continue;
         }
-        const int g = m.g, k = m.k, g0 = m.g0, ng = m.ng, S = m.S;
+        const int g = m.g, k = m.k, g0 = m.g0, ng = m.ng;
         const int64_t nch = m.nch;
 
-        // Lanes are (target i, slice sl): S slices split each tile into S
-        // contiguous runs of `rows` entries, padded with zero-mass entries, so
-        // every lane runs the same uniform trip count.
-        const int i = t % ng;
-        const int sl = t / ng;
-        const bool active = sl < S;
-        const bool wave_busy = (t & ~63) < S * ng;    // some lane of this wave is active
+        // Lanes are (target i, slice sl): the nsl slices of a target split
+        // each tile into nsl contiguous runs of `rows` entries, padded with
+        // zero-mass entries, so every lane of a wave runs the same trip count.
+        // Workgroup-wide, S = 256 / ng slices (thread t: target t mod ng,
+        // slice t / ng); or, where that leaves more lanes idle, each wave
+        // takes its own part of the targets (part_counts), the parts rotated
+        // over the waves from item to item.  The slices of a target sit
+        // sstride threads apart.
+        int i, sl, nsl, sstride;
+        bool active, wave_busy;
+        if (m.shared) {
+            i = t % ng;
+            sl = t / ng;
+            nsl = m.S;
+            sstride = ng;
+            active = sl < nsl;
+            wave_busy = (t & ~63) < nsl * ng;    // some lane of this wave is active
+            if (!active) sl = 0;
+        } else {
+            const int pw = (__builtin_amdgcn_readfirstlane(t >> 6) + q) & 3;
+            int cnt[4];
+            part_counts(ng, cnt);
+            int pb = 0, pn = 0;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                if (j < pw) pb += cnt[j];
+                if (j == pw) pn = cnt[j];
+            }
+            pb = __builtin_amdgcn_readfirstlane(pb);
+            pn = __builtin_amdgcn_readfirstlane(pn);
+            const int lane = t & 63;
+            nsl = pn > 0 ? 64 / pn : 1;
+            sstride = pn;
+            wave_busy = pn > 0;
+            sl = pn > 0 ? lane / pn : 0;
+            active = wave_busy && sl < nsl;
+            i = active ? pb + lane - sl * pn : 0;
+            if (!active) sl = 0;
+        }
+        const int rows_full = (TILE + nsl - 1) / nsl;
         const float4 xi = a.src[g0 + i];
 
         float s_ax = 0.f, s_ay = 0.f, s_az = 0.f, s_ph = 0.f;
@@ -489,26 +564,27 @@ __device__ __forceinline__ void force_items(const ForceArgs& a) {
         float4 pre[L];
         int32_t jn[L];
         bool has[L];
-        load_idx(m, t, 0, jn, has);
+        load_idx<TILE>(m, t, 0, jn, has);
         load_src(a, jn, has, pre);
-        load_idx(m, t, m.tstride, jn, has);
+        load_idx<TILE>(m, t, TILE, jn, has);
         int buf = 0;
-        for (int tb = 0; tb < m.clen; tb += m.tstride) {
-            const int tl = (m.clen - tb) < m.tstride ? (m.clen - tb) : m.tstride;
-            const int rows = tl == m.tstride ? m.rows_full : __builtin_amdgcn_readfirstlane((tl + S - 1) / S);
+        for (int tb = 0; tb < m.clen; tb += TILE) {
+            const int tl = (m.clen - tb) < TILE ? (m.clen - tb) : TILE;
+            const int rows = tl == TILE ? rows_full : (tl + nsl - 1) / nsl;
 #pragma unroll
             for (int l = 0; l < L; l++) tile[buf][t + l * kBlock] = pre[l];
+            if (t < kPadRows) tile[buf][TILE + t] = make_float4(0.f, 0.f, 0.f, 0.f);
             __syncthreads();
             // the next tile's records (its indices arrived during the previous
             // tile) and the indices of the tile after it load while this tile
             // is summed
-            if (tb + m.tstride < m.clen) {
+            if (tb + TILE < m.clen) {
                 load_src(a, jn, has, pre);
-                load_idx(m, t, tb + 2 * m.tstride, jn, has);
+                load_idx<TILE>(m, t, tb + 2 * TILE, jn, has);
             }
             float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
             if (wave_busy) {
-                const float4* tp = tile[buf] + (active ? sl : 0) * rows;
+                const float4* tp = tile[buf] + sl * rows;
 #pragma unroll 8
                 for (int mm = 0; mm < rows; mm++) pair_mono(xi.x, xi.y, xi.z, tp[mm], a.eps2, ax, ay, az, ph);
             }
@@ -522,7 +598,8 @@ __device__ __forceinline__ void force_items(const ForceArgs& a) {
 
         // combine the j-slices of each target (fixed slice order)
         float* red = reinterpret_cast<float*>(&tile[0][0]);  // >= 2 * 256 float4 = 8 floats per thread
-        if (S > 1) {
+        const bool lead = active && sl == 0;
+        if (!m.shared || m.S > 1) {
             red[8 * t + 0] = s_ax;
             red[8 * t + 1] = s_ay;
             red[8 * t + 2] = s_az;
@@ -532,9 +609,9 @@ __device__ __forceinline__ void force_items(const ForceArgs& a) {
             red[8 * t + 6] = c_az;
             red[8 * t + 7] = c_ph;
             __syncthreads();
-            if (t < ng) {
-                for (int s = 1; s < S; s++) {
-                    const float* r = red + 8 * (s * ng + t);
+            if (lead) {
+                for (int s = 1; s < nsl; s++) {
+                    const float* r = red + 8 * (t + s * sstride);
                     kahan_add(s_ax, c_ax, r[0] + r[4]);
                     kahan_add(s_ay, c_ay, r[1] + r[5]);
                     kahan_add(s_az, c_az, r[2] + r[6]);
@@ -542,8 +619,8 @@ __device__ __forceinline__ void force_items(const ForceArgs& a) {
                 }
             }
         }
-        if (t < ng) {
-            const int p = g0 + t;
+        if (lead) {
+            const int p = g0 + i;
             if (nch == 1) {
                 float ax = s_ax + c_ax, ay = s_ay + c_ay, az = s_az + c_az;
                 const float self = xi.w * __builtin_amdgcn_rsqf(a.eps2);
@@ -554,7 +631,7 @@ __device__ __forceinline__ void force_items(const ForceArgs& a) {
                 a.out_acc[3 * p + 2] = az;
                 a.out_pot[p] = phi;
             } else {
-                const int64_t row = a.part_base[g] + (int64_t)k * ng + t;
+                const int64_t row = a.part_base[g] + (int64_t)k * ng + i;
                 if (row >= 0 && row < a.part_cap) {
                     a.partial[2 * row] = make_float4(s_ax, s_ay, s_az, s_ph);
                     a.partial[2 * row + 1] = make_float4(c_ax, c_ay, c_az, c_ph);
@@ -574,7 +651,7 @@ __device__ __forceinline__ void force_items(const ForceArgs& a) {
 // workgroups per CU by their 32 KB of LDS.
 template <int TILE>
 struct ForceWaves {
-    static constexpr int value = TILE == 512 ? 6 : 1;
+    static constexpr int value = TILE == 1024 ? 1 : 7;
 };
 
 template <int TILE>

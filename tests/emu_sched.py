@@ -7,10 +7,13 @@ for ``otoo_force``:
 - a longest-first order by cost class floor(log2(n_g * item length)), with
   the order inside a class left to the device;
 - partial rows for the groups split into several items, in group order;
-- the FP32 arithmetic of one item: lanes (target, slice), S = 256 // n_g
-  slices, tiles of S * (tile // S) entries split into S contiguous runs and
-  padded with zero-mass entries, a per-tile FP32 sum per lane added with
-  Kahan compensation across tiles, the slices combined in slice order;
+- the FP32 arithmetic of one item: lanes (target, slice); S = 256 // n_g
+  slices of every target, or, where that idles more lanes, up to four wave
+  parts of n targets with 64 // n slices each (``lane_parts``); tiles of
+  ``tile`` entries, each split into a target's S contiguous runs of
+  ceil(len / S) entries padded with zero-mass entries, a per-tile FP32 sum
+  per lane added with Kahan compensation across tiles, the slices combined in
+  slice order;
 - the merge of a split group's rows in item order (FP32 Kahan for the
   acceleration, FP64 for the potential) and the removal of the self pair.
 
@@ -99,18 +102,50 @@ def _rsq(x):
     return (1.0 / np.sqrt(x.astype(F64))).astype(F32)
 
 
-def item_sums(src, xi, idx, eps2, tile):
-    """(sum, comp) [n_g, 4] of one item: acc xyz and the potential sum
-    Σ m / r, for targets xi [n_g, 3] (FP32) against the entries idx of the
-    source table src [*, 4] (FP32 x, y, z, m)."""
-    ng = xi.shape[0]
+def wave_parts(ng: int):
+    """The four wave parts (first target, count) of a group of ng targets that
+    does not divide the workgroup, in the documented rule: the largest part
+    holds c = 64 // (64 // ceil(ng / 4)) targets; as many parts as fit take c,
+    the rest goes to the remaining parts as the largest count 64 // S that
+    fits, and the last part takes what is left."""
+    c = 64 // (64 // -(-ng // 4))
+    nfull = ng // c
+    rest = ng - nfull * c
+    counts = [c] * nfull
+    for j in range(nfull, 4):
+        if j == 3:
+            take = rest
+        else:
+            take = 64 // (64 // (rest + 1) + 1) if rest > 0 else 0
+        counts.append(take)
+        rest -= take
+    firsts = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    return [(int(b), int(n)) for b, n in zip(firsts, counts)]
+
+
+def lane_parts(ng: int, tile: int):
+    """(targets, S) per part.  Workgroup-wide: all ng targets with
+    S = 256 // ng slices, the waves whose lanes all lie past S ng idle; used
+    when ng divides 256, or when it runs no more wave rows per full tile than
+    the wave parts (and its last slice ends within 64 records of the tile).
+    Else the wave parts, n targets with 64 // n slices each."""
     S = BLOCK // ng
-    T = S * (tile // S)
-    eps2 = F32(eps2)
+    parts = [(np.arange(b, b + n), 64 // n) for b, n in wave_parts(ng) if n > 0]
+    if BLOCK % ng == 0:
+        return [(np.arange(ng), S)]
+    part_rows = sum(-(-tile // Sp) for _, Sp in parts)
+    shared_rows = -(-(S * ng) // 64) * -(-tile // S)
+    if S <= 65 and shared_rows <= part_rows:
+        return [(np.arange(ng), S)]
+    return parts
+
+
+def _part_sums(src, xi, idx, eps2, tile, S):
+    ng = xi.shape[0]
     s_acc = np.zeros((S, ng, 4), F32)
     c_acc = np.zeros((S, ng, 4), F32)
-    for tb in range(0, len(idx), T):
-        tl = min(len(idx) - tb, T)
+    for tb in range(0, len(idx), tile):
+        tl = min(len(idx) - tb, tile)
         rows = -(-tl // S)
         run = np.zeros((S * rows, 4), F32)      # zero-mass padding
         run[:tl] = src[idx[tb:tb + tl]]
@@ -135,6 +170,19 @@ def item_sums(src, xi, idx, eps2, tile):
     s, c = s_acc[0], c_acc[0]
     for sl in range(1, S):
         s, c = _kahan(s, c, (s_acc[sl] + c_acc[sl]).astype(F32))
+    return s, c
+
+
+def item_sums(src, xi, idx, eps2, tile):
+    """(sum, comp) [n_g, 4] of one item: acc xyz and the potential sum
+    Σ m / r, for targets xi [n_g, 3] (FP32) against the entries idx of the
+    source table src [*, 4] (FP32 x, y, z, m)."""
+    ng = xi.shape[0]
+    eps2 = F32(eps2)
+    s = np.zeros((ng, 4), F32)
+    c = np.zeros((ng, 4), F32)
+    for tg, S in lane_parts(ng, tile):
+        s[tg], c[tg] = _part_sums(src, xi[tg], idx, eps2, tile, S)
     return s, c
 
 

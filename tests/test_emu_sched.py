@@ -151,3 +151,41 @@ def test_compensated_tiles_keep_long_lists_accurate():
           f"one running sum: acc {np.median(na):.2e}, pot {np.median(npot):.2e}")
     assert np.median(ea) <= 5e-7 and np.median(ep) <= 1e-7
     assert np.median(na) >= 10 * np.median(ea) and np.median(npot) >= 10 * np.median(ep)
+
+
+@pytest.mark.parametrize("tile", [256, 512, 1024])
+def test_lane_layout_covers_each_target_and_entry_once(tile):
+    """Every group size 1..256: the parts hold each target once, at most 64
+    targets a wave part, the slices of a target cover a tile's entries once,
+    and the rows a slice reads stay within the tile and its 64 zero records.
+    The layout chosen never runs more wave rows per full tile than the
+    workgroup-wide one, its longest part no more rows than that layout with
+    ceil(ng / 4) targets a wave, and from 33 targets on it issues at most
+    14 % more rows than ng / 64 per entry."""
+    worse = 0
+    for ng in range(1, 257):
+        parts = emu.lane_parts(ng, tile)
+        tg = np.concatenate([p for p, _ in parts])
+        assert np.array_equal(np.sort(tg), np.arange(ng))
+        if len(parts) > 1 or emu.BLOCK % ng:
+            assert len(emu.wave_parts(ng)) == 4
+        if len(parts) > 1:
+            assert all(len(p) <= 64 and S == 64 // len(p) for p, S in parts)
+        for _, S in parts:
+            for tl in (1, tile - 1, tile):
+                rows = -(-tl // S)
+                assert S * rows >= tl and S * rows <= tile + 64
+                cover = np.zeros(S * rows, np.int64)
+                for sl in range(S):
+                    cover[sl * rows:(sl + 1) * rows] += 1
+                assert np.all(cover == 1)
+        S0 = emu.BLOCK // ng
+        shared = -(-(S0 * ng) // 64) * -(-tile // S0)
+        issued = sum(-(-tile // S) * (-(-len(p) * S // 64)) for p, S in parts)
+        assert issued <= shared or (S0 > 65 and len(parts) > 1)
+        ws = 64 // -(-ng // 4)
+        assert max(-(-tile // S) for _, S in parts) <= -(-tile // min(ws, S0))
+        if ng >= 33:
+            assert issued <= 1.14 * tile * ng / 64, ng
+        worse += issued < shared
+    assert worse > 100     # most sizes that do not divide 256 gain

@@ -185,6 +185,60 @@ def test_tiny_inputs(ctx, n, tile):
     _assert_parity(acc, pot, a_ref, p_ref, f"n={n}")
 
 
+def _all_group_sizes(seed):
+    """Groups of every size 1..256 in shuffled order, each list holding the
+    group's own particles, other particles and cells: lengths drawn around
+    the tile boundaries and up to about four 512-entry tiles."""
+    rng = synth.rng_for(seed)
+    sizes = np.arange(1, 257)
+    rng.shuffle(sizes)
+    group_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    n = int(group_off[-1])
+    pos, m = synth.plummer(n, seed=seed)
+    pos32, mass32 = pos.astype(np.float32), m.astype(np.float32)
+    n_cells = 700
+    com = pos32[rng.integers(0, n, n_cells)] + rng.normal(0, 0.05, (n_cells, 3)).astype(np.float32)
+    cm = np.concatenate([com, rng.uniform(1e-4, 1e-2, (n_cells, 1))], axis=1).astype(np.float32)
+    special = np.array([0, 1, 63, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 1536])
+    lists, offs = [], [0]
+    for g in range(256):
+        g0, g1 = int(group_off[g]), int(group_off[g + 1])
+        extra = int(special[rng.integers(0, len(special))]) if g % 2 else int(rng.integers(0, 2100))
+        n_cell = int(rng.integers(0, extra + 1))
+        others = rng.choice(np.concatenate([np.arange(0, g0), np.arange(g1, n)]), extra - n_cell, replace=False)
+        idx = np.concatenate([n + rng.choice(n_cells, n_cell), np.arange(g0, g1), others]).astype(np.int32)
+        lists.append(idx)
+        offs.append(offs[-1] + len(idx))
+    return pos32, mass32, cm, group_off, np.array(offs, np.int64), np.concatenate(lists)
+
+
+@pytest.mark.parametrize("tile,chunk", [(256, 1 << 20), (512, 1 << 20), (1024, 1 << 20), (512, 300)])
+def test_every_group_size(ctx, tile, chunk):
+    """Every group size 1..256: sizes that divide the workgroup spread each
+    target's slices over all its threads, the others mostly take per-wave
+    parts of the targets (each part with its own slice count, the parts
+    rotating over the waves from item to item); ragged last tiles, empty
+    slices and (chunk 300) lists split into several items all meet the bar."""
+    pos32, mass32, cm, group_off, list_off, list_idx = _all_group_sizes(41)
+    dev = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to("cuda:0")
+    G = len(group_off) - 1
+    ng = np.diff(group_off).astype(np.int64)
+    d = otoo.DeviceLists(pos=dev(pos32, np.float32), mass=dev(mass32, np.float32),
+                         group_off=dev(group_off, np.int32), list_off=dev(list_off, np.int64),
+                         list_idx=dev(list_idx, np.int32), cell_mom=dev(cm, np.float32),
+                         pair_off=dev(np.zeros(G + 1), np.int64), n_entries=int(list_off[-1]),
+                         interactions=int((ng * np.diff(list_off)).sum()), pair_count=0)
+    ctx.set_tuning(chunk=chunk, tile=tile, lpt=1)
+    try:
+        acc, pot = _gpu(ctx, d, 0.01)
+    finally:
+        ctx.set_tuning(chunk=1024, tile=256)
+    a_ref, p_ref = oracle.list_force(pos32.astype(np.float64), mass32.astype(np.float64), group_off, list_off,
+                                     list_idx, cm[:, :3].astype(np.float64), cm[:, 3].astype(np.float64),
+                                     float(np.float32(0.01)))
+    _assert_parity(acc, pot, a_ref, p_ref, f"every group size, tile {tile} chunk {chunk}")
+
+
 def test_malformed_lists_are_reported(ctx):
     pos, m = synth.plummer(1000, seed=6)
     t, lists, pos32, mass32, cm, d = _setup(pos, m, 0.5, 64)
