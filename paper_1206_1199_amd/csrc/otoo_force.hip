@@ -330,7 +330,7 @@ __device__ __forceinline__ void apply_corr(const float* __restrict__ gc, float x
 
 struct ForceArgs {
     const float4* src;
-    int64_t n_src;
+    int32_t n_src;            // records in src, clamped to the int32 range of the list entries
     int32_t n;
     const int32_t* group_off;
     const int64_t* list_off;
@@ -377,7 +377,7 @@ __device__ __forceinline__ void pair_mono(float xi, float yi, float zi, float4 s
     ph += mr;
 }
 
-constexpr int kPadRows = 64;   // zero-mass records after each LDS tile
+constexpr int kPadRows = 128;  // zero-mass records after each LDS tile
 
 // The wave parts of a group of ng targets that does not divide the
 // workgroup: part j takes n[j] consecutive targets and splits each tile into
@@ -385,12 +385,11 @@ constexpr int kPadRows = 64;   // zero-mass records after each LDS tile
 // c = 64 / (64 / ceil(ng / 4)) targets, keeps the longest row count to that
 // of a workgroup-wide layout; as many parts as fit take c targets, the rest
 // of the targets goes to the remaining parts in the largest counts 64 / S
-// that fit, and the last part takes what is left.  Scalar code, per item.
-__device__ __forceinline__ void part_counts(int ng, int (&n)[4]) {
+// that fit, and the last part takes what is left.
+__host__ __device__ constexpr void part_counts(int ng, int (&n)[4]) {
     const int c = 64 / (64 / ((ng + 3) >> 2));
     const int nfull = ng / c;                // at most 4
     int r = ng - nfull * c;
-#pragma unroll
     for (int j = 0; j < 4; j++) {
         if (j < nfull) {
             n[j] = c;
@@ -403,20 +402,61 @@ __device__ __forceinline__ void part_counts(int ng, int (&n)[4]) {
     }
 }
 
-// Wave rows of a full tile: the parts, and the workgroup-wide layout with
-// S = 256 / ng slices (the waves whose lanes are all past S ng skip the tile).
-template <int TILE>
-__device__ __forceinline__ bool use_parts(int ng) {
+// Wave rows of a full tile of `tile` entries: the parts, and the
+// workgroup-wide layout with S = 256 / ng slices (the waves whose lanes are
+// all past S ng skip the tile).  The parts are used where they run fewer
+// rows, and always past 64 slices (whose last slice would run past the zero
+// records).
+__host__ __device__ constexpr bool use_parts(int ng, int tile) {
     if (kBlock % ng == 0) return false;
     const int S = kBlock / ng;
-    if (S > kPadRows + 1) return true;       // its last slice would run past the zero records
-    int n[4];
+    if (S > 64) return true;
+    int n[4] = {0, 0, 0, 0};
     part_counts(ng, n);
     int part_rows = 0;
-#pragma unroll
-    for (int j = 0; j < 4; j++) part_rows += n[j] > 0 ? (TILE + 64 / n[j] - 1) / (64 / n[j]) : 0;
-    const int shared_rows = ((S * ng + 63) >> 6) * ((TILE + S - 1) / S);
+    for (int j = 0; j < 4; j++) part_rows += n[j] > 0 ? (tile + 64 / n[j] - 1) / (64 / n[j]) : 0;
+    const int shared_rows = ((S * ng + 63) >> 6) * ((tile + S - 1) / S);
     return part_rows < shared_rows;
+}
+
+// The lane layout of each group size, fixed at compile time so that items
+// decode it with one scalar load instead of integer divisions on the vector
+// unit: the part counts, the workgroup-wide slice count 256 / ng, and (bit
+// t of `parts`) whether tiles of 256 << t entries use the parts.
+struct GroupLayout {
+    uint8_t n[4];
+    uint16_t S;
+    uint8_t parts;
+    uint8_t pad;
+};
+struct LayoutTable {
+    GroupLayout e[kBlock + 1];
+};
+constexpr LayoutTable make_layouts() {
+    LayoutTable t{};
+    for (int ng = 1; ng <= kBlock; ng++) {
+        int n[4] = {0, 0, 0, 0};
+        part_counts(ng, n);
+        GroupLayout& e = t.e[ng];
+        for (int j = 0; j < 4; j++) e.n[j] = (uint8_t)n[j];
+        e.S = (uint16_t)(kBlock / ng);
+        e.parts = (uint8_t)((use_parts(ng, 256) ? 1 : 0) | (use_parts(ng, 512) ? 2 : 0) |
+                            (use_parts(ng, 1024) ? 4 : 0));
+    }
+    return t;
+}
+__constant__ LayoutTable kLayouts = make_layouts();
+
+template <int TILE>
+constexpr int tile_bit() {
+    return TILE == 256 ? 1 : (TILE == 512 ? 2 : 4);
+}
+
+// floor(x / d) for 0 <= x <= 2048 and 1 <= d <= 256 through the reciprocal:
+// (x + 1/2) / d lies at least 1 / (2 d) >= 2^-9 from an integer, and the
+// error of the product stays below 2049 x 2^-22 < 2^-10.
+__device__ __forceinline__ int div_small(int x, int d) {
+    return (int)(((float)x + 0.5f) * __builtin_amdgcn_rcpf((float)d));
 }
 
 // One work item as every thread of the workgroup sees it.  The values are
@@ -427,6 +467,7 @@ struct ItemGeo {
     int g, k, g0, ng;
     int S;             // slices of the workgroup-wide layout, 256 / ng
     bool shared;       // lanes (t mod ng, t / ng) across the workgroup, else wave parts
+    const GroupLayout* ly;   // the group size's layout
     int clen;          // entries of this item (at most one chunk)
     int64_t nch;       // items of the group's list
     const int32_t* idx;   // the item's entries, idx[0 .. clen)
@@ -451,8 +492,10 @@ __device__ __forceinline__ bool decode_item(const ForceArgs& a, int q, ItemGeo& 
     const int64_t rest = le - cb;
     m.clen = __builtin_amdgcn_readfirstlane(rest <= 0 ? 0 : (rest < a.chunk ? (int)rest : a.chunk));
     m.idx = a.list_idx + cb;
-    m.S = __builtin_amdgcn_readfirstlane(kBlock / m.ng);
-    m.shared = !use_parts<TILE>(m.ng);
+    const GroupLayout& ly = kLayouts.e[m.ng];
+    m.S = ly.S;
+    m.shared = (ly.parts & tile_bit<TILE>()) == 0;
+    m.ly = &ly;
     return true;
 }
 
@@ -491,7 +534,8 @@ __device__ __forceinline__ void load_src(const ForceArgs& a, const int32_t (&j)[
 
 // TILE list entries are staged in LDS per tile (TILE / kBlock per thread),
 // followed by kPadRows zero-mass records that the last slice of a target may
-// run into.
+// run into (a target's S <= 64 slices of at most ceil(TILE / S) + 1 rows end
+// before TILE + 2 S - 1).
 template <int TILE>
 __device__ __forceinline__ void force_items(const ForceArgs& a) {
     constexpr int L = TILE / kBlock;
@@ -526,8 +570,8 @@ __device__ __forceinline__ void force_items(const ForceArgs& a) {
         int i, sl, nsl, sstride;
         bool active, wave_busy;
         if (m.shared) {
-            i = t % ng;
-            sl = t / ng;
+            sl = div_small(t, ng);
+            i = t - sl * ng;
             nsl = m.S;
             sstride = ng;
             active = sl < nsl;
@@ -535,26 +579,30 @@ __device__ __forceinline__ void force_items(const ForceArgs& a) {
             if (!active) sl = 0;
         } else {
             const int pw = (__builtin_amdgcn_readfirstlane(t >> 6) + q) & 3;
-            int cnt[4];
-            part_counts(ng, cnt);
             int pb = 0, pn = 0;
 #pragma unroll
             for (int j = 0; j < 4; j++) {
-                if (j < pw) pb += cnt[j];
-                if (j == pw) pn = cnt[j];
+                const int cj = m.ly->n[j];
+                if (j < pw) pb += cj;
+                if (j == pw) pn = cj;
             }
             pb = __builtin_amdgcn_readfirstlane(pb);
             pn = __builtin_amdgcn_readfirstlane(pn);
             const int lane = t & 63;
-            nsl = pn > 0 ? 64 / pn : 1;
+            nsl = pn > 0 ? div_small(64, pn) : 1;
             sstride = pn;
             wave_busy = pn > 0;
-            sl = pn > 0 ? lane / pn : 0;
+            sl = pn > 0 ? div_small(lane, pn) : 0;
             active = wave_busy && sl < nsl;
             i = active ? pb + lane - sl * pn : 0;
             if (!active) sl = 0;
         }
-        const int rows_full = (TILE + nsl - 1) / nsl;
+        // Where one wave reads several slices, an odd row count puts their
+        // records in different LDS banks (slices of 2^k rows of 16 bytes
+        // start in the same bank and serialise the read).  The 128 and 256
+        // slices of groups of 2 and 1 keep exact rows.
+        const bool skew = m.shared ? (ng & 63) != 0 && nsl <= 64 : nsl > 1;
+        const int rows_full = div_small(TILE + nsl - 1, nsl) | (skew ? 1 : 0);
         const float4 xi = a.src[g0 + i];
 
         float s_ax = 0.f, s_ay = 0.f, s_az = 0.f, s_ph = 0.f;
@@ -570,7 +618,7 @@ __device__ __forceinline__ void force_items(const ForceArgs& a) {
         int buf = 0;
         for (int tb = 0; tb < m.clen; tb += TILE) {
             const int tl = (m.clen - tb) < TILE ? (m.clen - tb) : TILE;
-            const int rows = tl == TILE ? rows_full : (tl + nsl - 1) / nsl;
+            const int rows = tl == TILE ? rows_full : div_small(tl + nsl - 1, nsl) | (skew ? 1 : 0);
 #pragma unroll
             for (int l = 0; l < L; l++) tile[buf][t + l * kBlock] = pre[l];
             if (t < kPadRows) tile[buf][TILE + t] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -921,7 +969,7 @@ int enqueue(otoo_ctx* c, const Call& a, bool allow_timing, void* buf) {
     }
     ForceArgs fa;
     fa.src = src;
-    fa.n_src = n_src;
+    fa.n_src = (int32_t)std::min<int64_t>(n_src, INT32_MAX);
     fa.n = a.n;
     fa.group_off = a.group_off;
     fa.list_off = a.list_off;

@@ -11,7 +11,8 @@ for ``otoo_force``:
   slices of every target, or, where that idles more lanes, up to four wave
   parts of n targets with 64 // n slices each (``lane_parts``); tiles of
   ``tile`` entries, each split into a target's S contiguous runs of
-  ceil(len / S) entries padded with zero-mass entries, a per-tile FP32 sum
+  ceil(len / S) entries (made odd where one wave reads several slices)
+  padded with zero-mass entries, a per-tile FP32 sum
   per lane added with Kahan compensation across tiles, the slices combined in
   slice order;
 - the merge of a split group's rows in item order (FP32 Kahan for the
@@ -127,7 +128,7 @@ def lane_parts(ng: int, tile: int):
     """(targets, S) per part.  Workgroup-wide: all ng targets with
     S = 256 // ng slices, the waves whose lanes all lie past S ng idle; used
     when ng divides 256, or when it runs no more wave rows per full tile than
-    the wave parts (and its last slice ends within 64 records of the tile).
+    the wave parts (and has at most 64 slices).
     Else the wave parts, n targets with 64 // n slices each."""
     S = BLOCK // ng
     parts = [(np.arange(b, b + n), 64 // n) for b, n in wave_parts(ng) if n > 0]
@@ -135,18 +136,25 @@ def lane_parts(ng: int, tile: int):
         return [(np.arange(ng), S)]
     part_rows = sum(-(-tile // Sp) for _, Sp in parts)
     shared_rows = -(-(S * ng) // 64) * -(-tile // S)
-    if S <= 65 and shared_rows <= part_rows:
+    if S <= 64 and shared_rows <= part_rows:
         return [(np.arange(ng), S)]
     return parts
 
 
-def _part_sums(src, xi, idx, eps2, tile, S):
+def slice_rows(tl: int, S: int, skew: bool) -> int:
+    """Rows of each of S slices covering tl entries; odd where one wave reads
+    several slices (their LDS records then start in different banks)."""
+    rows = -(-tl // S)
+    return rows | 1 if skew else rows
+
+
+def _part_sums(src, xi, idx, eps2, tile, S, skew):
     ng = xi.shape[0]
     s_acc = np.zeros((S, ng, 4), F32)
     c_acc = np.zeros((S, ng, 4), F32)
     for tb in range(0, len(idx), tile):
         tl = min(len(idx) - tb, tile)
-        rows = -(-tl // S)
+        rows = slice_rows(tl, S, skew)
         run = np.zeros((S * rows, 4), F32)      # zero-mass padding
         run[:tl] = src[idx[tb:tb + tl]]
         run = run.reshape(S, rows, 4)            # slice s: entries s*rows .. (s+1)*rows - 1
@@ -181,8 +189,12 @@ def item_sums(src, xi, idx, eps2, tile):
     eps2 = F32(eps2)
     s = np.zeros((ng, 4), F32)
     c = np.zeros((ng, 4), F32)
-    for tg, S in lane_parts(ng, tile):
-        s[tg], c[tg] = _part_sums(src, xi[tg], idx, eps2, tile, S)
+    parts = lane_parts(ng, tile)
+    for tg, S in parts:
+        # one wave reads several slices: parts with S > 1, or a workgroup-wide
+        # layout whose slices do not end on wave boundaries
+        skew = S > 1 if len(parts) > 1 or BLOCK % ng else ng % 64 != 0 and S <= 64
+        s[tg], c[tg] = _part_sums(src, xi[tg], idx, eps2, tile, S, skew)
     return s, c
 
 

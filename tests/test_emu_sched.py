@@ -157,7 +157,8 @@ def test_compensated_tiles_keep_long_lists_accurate():
 def test_lane_layout_covers_each_target_and_entry_once(tile):
     """Every group size 1..256: the parts hold each target once, at most 64
     targets a wave part, the slices of a target cover a tile's entries once,
-    and the rows a slice reads stay within the tile and its 64 zero records.
+    and the rows a slice reads (odd where several slices share a wave) stay
+    within the tile and its 128 zero records.
     The layout chosen never runs more wave rows per full tile than the
     workgroup-wide one, its longest part no more rows than that layout with
     ceil(ng / 4) targets a wave, and from 33 targets on it issues at most
@@ -172,9 +173,11 @@ def test_lane_layout_covers_each_target_and_entry_once(tile):
         if len(parts) > 1:
             assert all(len(p) <= 64 and S == 64 // len(p) for p, S in parts)
         for _, S in parts:
+            skew = S > 1 if len(parts) > 1 or emu.BLOCK % ng else ng % 64 != 0 and S <= 64
+            assert S <= 64 or not skew
             for tl in (1, tile - 1, tile):
-                rows = -(-tl // S)
-                assert S * rows >= tl and S * rows <= tile + 64
+                rows = emu.slice_rows(tl, S, skew)
+                assert S * rows >= tl and S * rows <= tile + 128
                 cover = np.zeros(S * rows, np.int64)
                 for sl in range(S):
                     cover[sl * rows:(sl + 1) * rows] += 1
@@ -182,10 +185,23 @@ def test_lane_layout_covers_each_target_and_entry_once(tile):
         S0 = emu.BLOCK // ng
         shared = -(-(S0 * ng) // 64) * -(-tile // S0)
         issued = sum(-(-tile // S) * (-(-len(p) * S // 64)) for p, S in parts)
-        assert issued <= shared or (S0 > 65 and len(parts) > 1)
+        assert issued <= shared or (S0 > 64 and len(parts) > 1)
         ws = 64 // -(-ng // 4)
         assert max(-(-tile // S) for _, S in parts) <= -(-tile // min(ws, S0))
         if ng >= 33:
             assert issued <= 1.14 * tile * ng / 64, ng
         worse += issued < shared
     assert worse > 100     # most sizes that do not divide 256 gain
+
+
+def test_small_division_through_the_reciprocal():
+    """The force kernel divides lane, slice and row counts (0 <= x <= 2048,
+    1 <= d <= 256) as floor((x + 1/2) * rcp(d)) in FP32; exact for a
+    reciprocal within one ulp either side of 1 / d."""
+    x = np.arange(0, 2049, dtype=np.float32)[:, None]
+    d = np.arange(1, 257, dtype=np.float32)[None, :]
+    r0 = (np.float32(1.0) / d).astype(np.float32)
+    want = np.arange(0, 2049)[:, None] // np.arange(1, 257)[None, :]
+    for r in (r0, np.nextafter(r0, np.float32(0)), np.nextafter(r0, np.float32(1))):
+        q = np.floor(((x + np.float32(0.5)).astype(np.float32) * r).astype(np.float32)).astype(np.int64)
+        assert np.array_equal(q, want)
