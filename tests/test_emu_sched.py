@@ -102,6 +102,25 @@ def test_emulated_schedule_meets_parity_bar(plummer4k, chunk, tile):
     assert np.median(ep) <= MED_TOL and ep.max() <= MAX_TOL
 
 
+def test_emulated_wave_parts_meet_parity_bar():
+    """Cell groups of many sizes (wave parts with their odd rows, and
+    workgroup-wide layouts) meet the bar."""
+    pos, m = synth.plummer(3000, 8)
+    t = otoo.Tree(pos, m, n_crit=16)
+    L = t.walk(theta=0.6, g_max=100, group_mode=otoo.GROUP_CELL)
+    _, p32, m32, cm = t.export(4)
+    sizes = np.diff(L.group_off)
+    assert any(len(emu.lane_parts(int(g), 512)) > 1 for g in sizes)
+    eps = 0.01
+    a_ref, p_ref = oracle.list_force(p32.astype(np.float64), m32.astype(np.float64), L.group_off, L.list_off,
+                                     L.list_idx, cm[:, :3].astype(np.float64), cm[:, 3].astype(np.float64),
+                                     float(np.float32(eps)))
+    acc, pot = emu.force(p32, m32, L.group_off, L.list_off, L.list_idx, eps, 1 << 20, 512, cell_mom=cm)
+    ea, ep = oracle.rel_err(acc, a_ref), oracle.rel_err(pot, p_ref)
+    assert np.median(ea) <= MED_TOL and ea.max() <= MAX_TOL
+    assert np.median(ep) <= MED_TOL and ep.max() <= MAX_TOL
+
+
 def test_processing_order_does_not_change_results(plummer4k):
     p32, m32, cm, L, eps, _ = plummer4k
     chunk = 256
@@ -173,7 +192,8 @@ def test_lane_layout_covers_each_target_and_entry_once(tile):
         if len(parts) > 1:
             assert all(len(p) <= 64 and S == 64 // len(p) for p, S in parts)
         for _, S in parts:
-            skew = S > 1 if len(parts) > 1 or emu.BLOCK % ng else ng % 64 != 0 and S <= 64
+            wave_parts_used = len(parts) > 1 or (emu.BLOCK % ng != 0 and S != emu.BLOCK // ng)
+            skew = S > 1 if wave_parts_used else ng % 64 != 0 and S <= 64
             assert S <= 64 or not skew
             for tl in (1, tile - 1, tile):
                 rows = emu.slice_rows(tl, S, skew)
