@@ -462,11 +462,15 @@ enum otoo_corr_kind {
  * (Sec. 2).  The work is cut into items of 1024 consecutive (group, cell)
  * pairs in pair order; a group whose pairs span several items has its item
  * sums added in item order, so results do not depend on how the work is
- * scheduled.  Device pointers; asynchronous; mlp only for OTOO_CORR_MLP;
+ * scheduled.  group_box [n_groups][6] (lo xyz, hi xyz, FP32) may give each
+ * group's bounding box as the walk returns it (the extremes of the group's
+ * positions, identical to those of the FP32 pos); NULL has the pass find
+ * them in pos.  Device pointers; asynchronous; mlp only for OTOO_CORR_MLP;
  * cell_stride 12 for QUAD and MLP (the second-moment tensor).  The context
  * keeps scratch for the item sums (grown on demand). */
 int otoo_correction(otoo_ctx* ctx, int32_t kind, otoo_mlp* mlp, int32_t n, const float* pos, int32_t n_groups,
-                    const int32_t* group_off, int64_t n_entries, const int64_t* list_off, const int32_t* list_idx,
+                    const int32_t* group_off, const float* group_box, int64_t n_entries, const int64_t* list_off,
+                    const int32_t* list_idx,
                     int64_t n_pairs, const int64_t* pair_off, int32_t n_cells, const float* cell_mom,
                     int32_t cell_stride, float eps, const float* corr, float* gcorr);
 

@@ -142,7 +142,7 @@ def lib():
         "otoo_scratch_generation": ([P, ctypes.POINTER(I64)], I32),
         "otoo_force": ([P, I32, P, P, I32, P, I64, P, P, I32, P, I32, F, P, P, P], I32),
         "otoo_force_noalloc": ([P, I32, P, P, I32, P, I64, P, P, I32, P, I32, F, P, P, P], I32),
-        "otoo_correction": ([P, I32, P, I32, P, I32, P, I64, P, P, I64, P, I32, P, I32, F, P, P], I32),
+        "otoo_correction": ([P, I32, P, I32, P, I32, P, P, I64, P, P, I64, P, I32, P, I32, F, P, P], I32),
         "otoo_quad_exact": ([P, I32, I32, I64, P, P, I64, P, I32, P, I32, P], I32),
         "otoo_direct": ([P, I32, P, P, I32, P, F, P, P], I32),
         "otoo_sph_sum": ([P, I32, P, P, P, I32, P, I64, P, P, P], I32),
@@ -356,6 +356,7 @@ class DeviceLists:
     n_entries: int
     interactions: int
     pair_count: int = -1   # pair_off[-1] known on the host (-1: read it from the device)
+    group_box: "object" = None   # float32 [G, 6] lo xyz, hi xyz from the walk (None: found on the device)
 
     @property
     def n(self):
@@ -383,7 +384,8 @@ class DeviceLists:
                    list_off=t(lists.list_off, np.int64),
                    list_idx=t(lists.list_idx if lists.n_entries else np.zeros(1, np.int32), np.int32),
                    cell_mom=t(cm, np.float32)[:len(cell_mom)], pair_off=t(lists.pair_off, np.int64),
-                   n_entries=lists.n_entries, interactions=lists.interactions, pair_count=int(lists.pair_off[-1]))
+                   n_entries=lists.n_entries, interactions=lists.interactions, pair_count=int(lists.pair_off[-1]),
+                   group_box=t(lists.group_box, np.float32))
 
 
 def _lists_on_device(cls, pos, mass, cell_mom, lists: Lists):
@@ -547,7 +549,8 @@ class Context:
         g = out if out is not None else torch.empty((d.n_groups, CORR_STRIDE), dtype=torch.float32,
                                                     device=f"cuda:{self.device}")
         self._raise(lib().otoo_correction(self._h, int(kind), net._h if net is not None else None, d.n, _tptr(d.pos),
-                                          d.n_groups, _tptr(d.group_off), int(d.n_entries), _tptr(d.list_off),
+                                          d.n_groups, _tptr(d.group_off), _tptr(d.group_box), int(d.n_entries),
+                                          _tptr(d.list_off),
                                           _tptr(d.list_idx), d.n_pairs, _tptr(d.pair_off), d.n_cells,
                                           _tptr(d.cell_mom) if d.n_cells else None, int(d.cell_mom.shape[1]),
                                           float(eps), _tptr(corr), _tptr(g)), "otoo_correction")

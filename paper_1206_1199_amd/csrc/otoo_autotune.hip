@@ -67,6 +67,7 @@ struct StepArgs {
     int64_t n_entries, n_pairs;
     const float *pos, *mass, *cm;
     const int32_t *go, *li;
+    const float* gb;   // the walk's group boxes
     const int64_t *lo, *po;
     float eps;
     float* gcorr;
@@ -76,7 +77,8 @@ struct StepArgs {
 
 int step_enqueue(otoo_ctx* c, const StepArgs& s) {
     if (s.corr_kind >= 0) {
-        const int rc = otoo_correction(c, s.corr_kind, s.mlp, s.n, s.pos, s.n_groups, s.go, s.n_entries, s.lo, s.li,
+        const int rc = otoo_correction(c, s.corr_kind, s.mlp, s.n, s.pos, s.n_groups, s.go, s.gb, s.n_entries, s.lo,
+                                       s.li,
                                        s.n_pairs, s.po, s.n_cells, s.cm, s.stride, s.eps, nullptr, s.gcorr);
         if (rc) return rc;
     }
@@ -168,7 +170,7 @@ int autotune_impl(otoo_ctx* c, const otoo_tree* tree, const otoo_walk_params* wa
         DeviceBufs lists{c->stream, {}};
         int32_t *d_go, *d_li;
         int64_t *d_lo, *d_po = nullptr;
-        float* d_gc = nullptr;
+        float *d_gc = nullptr, *d_gb = nullptr;
         HIP_TRY(c, lists.alloc(&d_go, (size_t)L.n_groups + 1));
         HIP_TRY(c, lists.alloc(&d_lo, (size_t)L.n_groups + 1));
         HIP_TRY(c, lists.alloc(&d_li, (size_t)L.n_entries));
@@ -185,11 +187,13 @@ int autotune_impl(otoo_ctx* c, const otoo_tree* tree, const otoo_walk_params* wa
             n_pairs = po[L.n_groups];
             HIP_TRY(c, lists.alloc(&d_po, po.size()));
             HIP_TRY(c, lists.alloc(&d_gc, (size_t)L.n_groups * kCorrStride));
+            HIP_TRY(c, lists.alloc(&d_gb, (size_t)L.n_groups * 6));
             HIP_TRY(c, hipMemcpy(d_po, po.data(), sizeof(int64_t) * po.size(), hipMemcpyHostToDevice));
+            HIP_TRY(c, hipMemcpy(d_gb, L.group_box, sizeof(float) * 6 * (size_t)L.n_groups, hipMemcpyHostToDevice));
         }
         const StepArgs sa{corr_kind, mlp,  (int32_t)n, L.n_groups, (int32_t)n_cells, stride, L.n_entries, n_pairs,
-                          d_pos,     d_mass, d_cm,   d_go,        d_li,             d_lo,   d_po,        eps,
-                          d_gc,      d_acc,  d_pot};
+                          d_pos,     d_mass, d_cm,   d_go,        d_li,             d_gb,   d_lo,        d_po,
+                          eps,       d_gc,   d_acc,  d_pot};
         for (int32_t si = 0; si < n_schedules; si++) {
             otoo_tuning t = schedules[si];
             t.debug_validate = 0;

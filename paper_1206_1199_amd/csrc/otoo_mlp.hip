@@ -8,7 +8,8 @@
 // network's tensor the textbook quadrupole plus a learned correction, and a
 // gate on l/|d| limits the layers to near cells.
 //
-//   k_corr_box      bounding box of each group (the expansion centre)
+//   k_corr_box      bounding box of each group (the expansion centre), or
+//                   k_corr_box_given from the boxes the walk returns
 //   k_corr_net      per item of consecutive cell pairs: features, gated
 //                   network (register-resident, v_mfma_f32_16x16x32_bf16)
 //                   and the local expansion
@@ -417,6 +418,7 @@ struct CorrArgs {
     const float* pos;
     int32_t n_groups;
     const int32_t* group_off;
+    const float* gbox;        // [n_groups][6] lo xyz, hi xyz, or NULL (found in pos)
     const int64_t* list_off;
     int64_t n_entries;
     const int32_t* list_idx;
@@ -676,6 +678,16 @@ __device__ __forceinline__ float wave_max(float v) {
     return wave_reduce(v, -INFINITY, [](float x, float y) { return fmaxf(x, y); });
 }
 
+// Centre and half-diagonal of the box [lo, hi].
+__device__ __forceinline__ void box_centre(const float lo[3], const float hi[3], float& cx, float& cy, float& cz,
+                                           float& h) {
+    cx = 0.5f * (lo[0] + hi[0]);
+    cy = 0.5f * (lo[1] + hi[1]);
+    cz = 0.5f * (lo[2] + hi[2]);
+    const float ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
+    h = 0.5f * sqrtf(ex * ex + ey * ey + ez * ez);
+}
+
 // Geometry of group g for one wave: centre and half-diagonal of the
 // bounding box of its particles; false for a malformed group.
 __device__ __forceinline__ bool wave_group_box(const CorrArgs& a, int g, int lane, float& cx, float& cy, float& cz,
@@ -695,11 +707,7 @@ __device__ __forceinline__ bool wave_group_box(const CorrArgs& a, int g, int lan
         lo[k] = wave_min(lo[k]);
         hi[k] = wave_max(hi[k]);
     }
-    cx = 0.5f * (lo[0] + hi[0]);
-    cy = 0.5f * (lo[1] + hi[1]);
-    cz = 0.5f * (lo[2] + hi[2]);
-    const float ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
-    h = 0.5f * sqrtf(ex * ex + ey * ey + ez * ez);
+    box_centre(lo, hi, cx, cy, cz, h);
     return ok;
 }
 
@@ -715,6 +723,21 @@ __global__ __launch_bounds__(256) void k_corr_box(CorrArgs a) {
         a.plan.box[g] = make_float4(cx, cy, cz, ok ? h : -1.f);
         if (!ok) atomicOr(a.err, kErrGroup);
     }
+}
+
+// The same from the boxes the walk returns: one thread per group.
+__global__ __launch_bounds__(256) void k_corr_box_given(CorrArgs a) {
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= a.n_groups) return;
+    const int g0 = a.group_off[g];
+    const int ng = a.group_off[g + 1] - g0;
+    const bool ok = ng >= 1 && ng <= kBlock && g0 >= 0 && g0 + ng <= a.n;
+    const float lo[3] = {a.gbox[6 * g], a.gbox[6 * g + 1], a.gbox[6 * g + 2]};
+    const float hi[3] = {a.gbox[6 * g + 3], a.gbox[6 * g + 4], a.gbox[6 * g + 5]};
+    float cx, cy, cz, h;
+    box_centre(lo, hi, cx, cy, cz, h);
+    a.plan.box[g] = make_float4(cx, cy, cz, ok ? h : -1.f);
+    if (!ok) atomicOr(a.err, kErrGroup);
 }
 
 // Group g's box from k_corr_box; false for a malformed group.
@@ -2398,7 +2421,8 @@ int otoo_mlp_infer(otoo_mlp* m, int32_t n, const float* pos, int32_t n_groups, c
 }
 
 int otoo_correction(otoo_ctx* c, int32_t kind, otoo_mlp* m, int32_t n, const float* pos, int32_t n_groups,
-                    const int32_t* group_off, int64_t n_entries, const int64_t* list_off, const int32_t* list_idx,
+                    const int32_t* group_off, const float* group_box, int64_t n_entries, const int64_t* list_off,
+                    const int32_t* list_idx,
                     int64_t n_pairs, const int64_t* pair_off, int32_t n_cells, const float* cell_mom,
                     int32_t cell_stride, float eps, const float* corr, float* gcorr) {
     if (!c) return OTOO_EINVAL;
@@ -2419,7 +2443,7 @@ int otoo_correction(otoo_ctx* c, int32_t kind, otoo_mlp* m, int32_t n, const flo
         if (!m || m->ctx != c) return fail(c, OTOO_EINVAL, "a network of this context is required");
         if (!m->has_params) return fail(c, OTOO_EINVAL, "no parameters loaded");
     }
-    CorrArgs ca{n,        pos,     n_groups, group_off, list_off, n_entries, list_idx,
+    CorrArgs ca{n,        pos,     n_groups, group_off, group_box, list_off, n_entries, list_idx,
                 pair_off, n_pairs, n_cells,  cell_mom,  cell_stride, eps,   corr,
                 m ? m->wbf : nullptr, m ? m->master : nullptr, m ? m->gate : 0.f, gcorr, c->errflag, CorrPlan{}};
     if (kind == OTOO_CORR_MLP && c->tune.net_kernel == 1) {   // one workgroup per group, LDS-staged network
@@ -2474,7 +2498,11 @@ int otoo_correction(otoo_ctx* c, int32_t kind, otoo_mlp* m, int32_t n, const flo
                         : nullptr;
     pl.crec = split ? reinterpret_cast<uint4*>(static_cast<char*>(c->corr_buf) + 2 * part_bytes + box_bytes + qbuf_bytes)
                     : nullptr;
-    hipLaunchKernelGGL(k_corr_box, dim3((unsigned)(((int64_t)n_groups + 3) / 4)), dim3(256), 0, c->stream, ca);
+    if (group_box)
+        hipLaunchKernelGGL(k_corr_box_given, dim3((unsigned)(((int64_t)n_groups + 255) / 256)), dim3(256), 0,
+                           c->stream, ca);
+    else
+        hipLaunchKernelGGL(k_corr_box, dim3((unsigned)(((int64_t)n_groups + 3) / 4)), dim3(256), 0, c->stream, ca);
     const int64_t item_blocks = std::max<int64_t>((pl.n_items + 3) / 4, 1);
     const dim3 grid((unsigned)std::min<int64_t>((int64_t)per_cu * c->num_cu, item_blocks));
     if (which == 0) {

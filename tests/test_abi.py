@@ -31,8 +31,8 @@ def test_null_context_and_bad_arguments_return_einval():
     lib = otoo.lib()
     assert lib.otoo_force(None, 1, None, None, 1, None, 0, None, None, 0, None, 4, 0.1, None, None,
                           None) == otoo.EINVAL
-    assert lib.otoo_correction(None, 1, None, 1, None, 1, None, 0, None, None, 0, None, 0, None, 12, 0.1, None,
-                               None) == otoo.EINVAL
+    assert lib.otoo_correction(None, 1, None, 1, None, 1, None, None, 0, None, None, 0, None, 0, None, 12, 0.1,
+                               None, None) == otoo.EINVAL
     assert lib.otoo_quad_exact(None, 1, 1, 0, None, None, 0, None, 0, None, 12, None) == otoo.EINVAL
     assert lib.otoo_direct(None, 1, None, None, 0, None, 0.1, None, None) == otoo.EINVAL
     assert lib.otoo_sph_sum(None, 1, None, None, None, 1, None, 0, None, None, None) == otoo.EINVAL

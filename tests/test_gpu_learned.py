@@ -452,6 +452,31 @@ def _corrected_on(ctx, tree, theta, g_max, eps, kind, net=None, group_mode=otoo.
     return lists, pos32, mass32, cm, out[0].cpu().numpy(), out[1].cpu().numpy()
 
 
+@pytest.mark.parametrize("kind,chunks", [("mlp", 1), ("mlp", 2), ("quad", 0)])
+def test_walk_boxes_give_the_same_correction(env, kind, chunks):
+    """The correction pass given the walk's group boxes (one thread per group)
+    and finding them in the positions (one wave per group) produce the same
+    bits: the boxes' corners are the extremes of the same FP32 positions."""
+    import dataclasses
+    ctx, net, tree = env["ctx"], env["net"], env["tree"]
+    net.set_params(env["params"])
+    old = ctx.tuning()
+    ctx.set_tuning(net_kernel=2, corr_chunks=chunks)
+    try:
+        lists = tree.walk(theta=0.7, g_max=100, group_mode=otoo.GROUP_CELL, near_ratio=0.5)
+        d, _, _ = learned.device_tree_arrays(tree, lists)
+        assert d.group_box is not None and tuple(d.group_box.shape) == (lists.n_groups, 6)
+        corr_kind = otoo.CORR_MLP if kind == "mlp" else otoo.CORR_QUAD
+        given = ctx.correction(d, corr_kind, EPS, net=net)
+        found = ctx.correction(dataclasses.replace(d, group_box=None), corr_kind, EPS, net=net)
+        torch.cuda.synchronize()
+        ctx.check()
+    finally:
+        ctx.set_tuning(**old.as_dict())
+    assert torch.isfinite(given).all()
+    assert torch.equal(given, found)
+
+
 @pytest.mark.parametrize("kind,net_kernel,chunks,ratio", [("mlp", 0, 0, 0.4), ("mlp", 1, 0, 0.4), ("mlp", 2, 1, 0.4),
                                                           ("mlp", 2, 2, 0.4), ("mlp", 2, 0, 0.6), ("quad", 2, 0, 0.4)])
 def test_near_pairs_match_oracle(env, kind, net_kernel, chunks, ratio):
