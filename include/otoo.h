@@ -200,7 +200,9 @@ typedef struct {
                              expansion pass */
     int32_t corr_chunks;  /* the two passes of net_kernel 2: 0 (default) by the pairs' density (pair-parallel
                              chunks of 64 pairs across groups when there are fewer than 32 pairs per group,
-                             else one group at a time), 1 one group at a time, 2 pair-parallel chunks */
+                             or fewer than 128 when items of 256 pairs would give the resident waves fewer
+                             than four each; else one group at a time), 1 one group at a time, 2
+                             pair-parallel chunks */
 } otoo_tuning;
 int otoo_set_tuning(otoo_ctx* ctx, const otoo_tuning* tuning);
 int otoo_get_tuning(const otoo_ctx* ctx, otoo_tuning* tuning);

@@ -2483,8 +2483,11 @@ int otoo_correction(otoo_ctx* c, int32_t kind, otoo_mlp* m, int32_t n, const flo
     pl.seg = kCorrSeg;
     while (pl.seg > kCorrSegMin && (n_pairs + pl.seg - 1) / pl.seg < 4 * waves) pl.seg /= 2;
     pl.n_items = (n_pairs + pl.seg - 1) / pl.seg;
-    // sparse pairs (few per group, e.g. the nearest cells only): pair-parallel chunks
-    pl.chunked = split && (c->tune.corr_chunks == 2 || (c->tune.corr_chunks == 0 && n_pairs < 32LL * n_groups));
+    // pair-parallel chunks for sparse pairs (fewer than 32 per group, e.g. the nearest cells only), and
+    // for fewer than 128 per group when even items of kCorrSegMin pairs leave waves without four items
+    const bool underfull = (n_pairs + kCorrSegMin - 1) / kCorrSegMin < 4 * waves;
+    const bool sparse = n_pairs < 32LL * n_groups || (underfull && n_pairs < 128LL * n_groups);
+    pl.chunked = split && (c->tune.corr_chunks == 2 || (c->tune.corr_chunks == 0 && sparse));
     const size_t part_bytes = align256(sizeof(float) * kCorrStride * (size_t)std::max<int64_t>(pl.n_items, 1));
     const size_t box_bytes = align256(sizeof(float4) * (size_t)n_groups);
     const size_t qbuf_bytes = split ? align256(sizeof(float) * kQRow * (size_t)std::max<int64_t>(n_pairs, 1)) : 0;
