@@ -78,7 +78,7 @@ def autotune(tree: Tree, eps: float, theta: float, ctx: Context, grid=None, reps
 # near ratios the learned step is tuned over (the network is trained on pairs
 # of ratio >= 0.4, so each of these corrects a subset of its training pairs),
 # and the median force error the tuned step must hold
-NEAR_RATIOS = (0.4, 0.5, 0.55, 0.6, 0.65)
+NEAR_RATIOS = (0.4, 0.5, 0.55, 0.6, 0.62, 0.65)
 ERR_TARGET = 1e-3
 
 
