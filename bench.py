@@ -258,15 +258,15 @@ def train_network(ctx, log, train_steps, gate=0.4, near=True):
                  "val_loss_textbook_quadrupole": quad_val}
 
 
-def workload_learned(ctx, net, training, log, tree, eps, theta, scheds, sample, a_dir, reps, near_ratio=0.0):
+def workload_learned(ctx, net, training, log, tree, eps, theta, scheds, sample, a_dir, reps, near_ratios=(0.0,)):
     """Plain, textbook-quadrupole and learned force on the benchmark workload
     itself, over opening angles around its own (plain at and below it, the
     corrections at and above it), each mode with its own cached schedule
     (``scheds[mode]``: the plain force's, or the corrected step's, whose best
     group size differs).  Each step (correction + force) is captured in one
     graph and replayed; errors are against the direct sums of the sample.
-    near_ratio > 0: the learned step corrects only the near cells (walks that
-    list them first)."""
+    near_ratios (> 0): the learned step corrects only the near cells (walks
+    that list them first), at each of these ratios."""
     import torch
     import paper_1206_1199_amd as otoo
     from paper_1206_1199_amd import learned
@@ -279,9 +279,8 @@ def workload_learned(ctx, net, training, log, tree, eps, theta, scheds, sample, 
             sc = scheds[mode]
             ctx.set_tuning(chunk=sc["chunk"], blocks_per_cu=sc["blocks_per_cu"], lpt=sc["lpt"], tile=sc["tile"])
             mode_id = otoo.GROUP_CHUNK if sc["group_mode"] == "chunk" else otoo.GROUP_CELL
-            for th in thetas[mode]:
-                lists = tree.walk(theta=th, g_max=sc["g_max"], group_mode=mode_id,
-                                  near_ratio=near_ratio if mode == "learned" else 0.0)
+            for th, near_ratio in [(th, r) for th in thetas[mode] for r in (near_ratios if mode == "learned" else (0.0,))]:
+                lists = tree.walk(theta=th, g_max=sc["g_max"], group_mode=mode_id, near_ratio=near_ratio)
                 d, _, _ = learned.device_tree_arrays(tree, lists)
                 out = ctx.outputs(d.n)
                 gc = torch.empty((d.n_groups, otoo.CORR_STRIDE), dtype=torch.float32, device="cuda:0")
@@ -298,9 +297,11 @@ def workload_learned(ctx, net, training, log, tree, eps, theta, scheds, sample, 
                 ctx.check()
                 err = rel_err(out[0].cpu().numpy()[sample], a_dir)
                 rows.append(dict(mode=mode, theta=th, group_mode=sc["group_mode"], g_max=sc["g_max"],
-                                 ms=e0.elapsed_time(e1) / reps, interactions=lists.interactions, pairs=d.n_pairs,
+                                 near_ratio=near_ratio, ms=e0.elapsed_time(e1) / reps,
+                                 interactions=lists.interactions, pairs=d.n_pairs,
                                  median_err=float(np.median(err)), p99_err=float(np.quantile(err, 0.99))))
-                log(f"  {mode:8s} theta {th:.2f} {sc['group_mode']} {sc['g_max']} (graph replay): "
+                log(f"  {mode:8s} theta {th:.2f} {sc['group_mode']} {sc['g_max']}"
+                    + (f" ratio {near_ratio:.2f}" if near_ratio > 0 else "") + " (graph replay): "
                     f"{rows[-1]['ms']:.3f} ms, median err {rows[-1]['median_err']:.2e}")
                 del g, d, out, gc
                 torch.cuda.empty_cache()
@@ -844,8 +845,10 @@ def main():
             scheds = {"plain": at.cached_schedule(args.workload, 0, cache_path)[0],
                       "quad": at.cached_schedule(args.workload, 0, cache_path, mode="quad")[0] if has_quad else sched,
                       "learned": sched}
+            # the step's own ratio, and 0.6, which holds the error bound to larger opening angles
+            ratios = tuple(sorted({near_ratio, 0.6})) if near_ratio > 0 else (0.0,)
             res["learned_workload"] = workload_learned(ctx, net, training, log, tree, eps, theta, scheds, sample,
-                                                       a_dir, reps, near_ratio)
+                                                       a_dir, reps, ratios)
         except Exception as e:  # the headline measurement stands on its own
             res["learned_workload"] = {"error": f"{type(e).__name__}: {e}"}
             log(f"workload comparison failed: {e}")
