@@ -405,8 +405,8 @@ __host__ __device__ constexpr void part_counts(int ng, int (&n)[4]) {
 // Wave rows of a full tile of `tile` entries: the parts, and the
 // workgroup-wide layout with S = 256 / ng slices (the waves whose lanes are
 // all past S ng skip the tile).  The parts are used where they run fewer
-// rows, and always past 64 slices (whose last slice would run past the zero
-// records).
+// rows, and always where the workgroup-wide layout would have more than 64
+// slices (its last slice would run past the zero records).
 __host__ __device__ constexpr bool use_parts(int ng, int tile) {
     if (kBlock % ng == 0) return false;
     const int S = kBlock / ng;
@@ -692,11 +692,10 @@ __device__ __forceinline__ void force_items(const ForceArgs& a) {
     }
 }
 
-// Waves per SIMD the compiler is asked to fit: at 512-entry tiles the
-// default register budget (87 VGPRs) allows five; a budget for six gives
-// seven (72 VGPRs, no spills), which hides more of the per-item load chain.
-// 256-entry tiles already fit seven; 1024-entry tiles are held to four
-// workgroups per CU by their 32 KB of LDS.
+// Waves per SIMD the compiler is asked to fit: seven at 256- and 512-entry
+// tiles (at most 72 VGPRs, no spills; the default budget gave five at
+// 512-entry tiles, and seven hide more of the per-item load chain).
+// 1024-entry tiles are held to four workgroups per CU by their 36 KB of LDS.
 template <int TILE>
 struct ForceWaves {
     static constexpr int value = TILE == 1024 ? 1 : 7;
