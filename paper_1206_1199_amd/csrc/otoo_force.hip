@@ -519,6 +519,12 @@ __device__ __forceinline__ void load_idx(const ItemGeo& m, int t, int base, int3
 template <int L>
 __device__ __forceinline__ void load_src(const ForceArgs& a, const int32_t (&j)[L], const bool (&has)[L],
                                          float4 (&pre)[L]) {
+    // Every load in flight here is an index load (the previous records were
+    // stored to LDS): wait for them in every lane before the branches.  A
+    // wait left inside a branch that a wave may skip makes the compiler wait
+    // again before the index registers are reloaded, after these record
+    // loads are issued, and so for the records as well.
+    __builtin_amdgcn_s_waitcnt(0xF70);   // vmcnt(0); expcnt and lgkmcnt not waited for
 #pragma unroll
     for (int l = 0; l < L; l++) {
         pre[l] = make_float4(0.f, 0.f, 0.f, 0.f);
