@@ -11,7 +11,7 @@ network, per-group local expansion) and the force (pack, schedule, force
 kernel, reduction) -- captured in one graph and replayed with every input
 resident in HBM.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload cube16m]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 10] [--workload cube16m]
                     [--mode plain|quad|learned] [--autotune] [--no-learned]
                     [--no-cpu-baseline] [--no-plummer]
 
@@ -607,7 +607,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="cube16m", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="", choices=["", "plain", "quad", "learned"],
                     help="force evaluated per step (default: learned for the cube, plain otherwise)")
