@@ -284,6 +284,21 @@ int otoo_force_noalloc(otoo_ctx* ctx, int32_t n, const float* pos, const float* 
 int otoo_force_plan(int32_t n, int32_t n_groups, int64_t n_entries, int32_t n_cells, int32_t chunk,
                     int32_t workgroups, int64_t* scratch_bytes);
 
+/* The lanes the force kernel gives a group of ng targets (1 .. OTOO_MAX_GROUP)
+ * at tile depth `tile` (256, 512 or 1024 list entries), for tests and tools;
+ * host only, no context.  The kernel's workgroup is 256 threads in four
+ * waves of 64.
+ *   *wave_parts  0: every target has 256 / ng slices across the workgroup
+ *                (thread t: target t mod ng, slice t / ng), parts[0] =
+ *                256 / ng and parts[1..3] = 0;
+ *                1: each wave takes its own part of the targets, parts[j] =
+ *                the size of part j (consecutive targets, in order; 0 for an
+ *                idle part), each part with 64 / parts[j] slices of a tile.
+ * Sizes that divide 256 use the first layout; the others use the parts
+ * where these run fewer wave rows per full tile (and whenever 256 / ng
+ * exceeds 64).  EINVAL for ng or tile out of range or NULL pointers. */
+int otoo_group_layout(int32_t ng, int32_t tile, int32_t* wave_parts, int32_t* parts);
+
 /* Generation of the context's device scratch: a counter raised every time
  * the context allocates a scratch buffer anew (force, SPH and correction
  * scratch, and the per-group geometry of a network bound to it).  A graph

@@ -101,7 +101,8 @@ EXPORTED = [
     "otoo_tree_links", "otoo_tree_walk", "otoo_tree_groups", "otoo_tree_walk_range", "otoo_tree_walk_sph", "otoo_lists_free", "otoo_create", "otoo_destroy",
     "otoo_set_stream", "otoo_last_error", "otoo_set_tuning", "otoo_get_tuning", "otoo_force", "otoo_force_noalloc",
     "otoo_check", "otoo_enable_timing", "otoo_last_timing", "otoo_graph_capture", "otoo_graph_launch",
-    "otoo_autotune", "otoo_autotune_step", "otoo_set_scratch_limit", "otoo_force_plan", "otoo_scratch_generation",
+    "otoo_autotune", "otoo_autotune_step", "otoo_set_scratch_limit", "otoo_force_plan", "otoo_group_layout",
+    "otoo_scratch_generation",
     "otoo_quad_exact", "otoo_correction", "otoo_direct", "otoo_sph_sum", "otoo_mlp_num_params", "otoo_mlp_create", "otoo_mlp_destroy", "otoo_mlp_set_params", "otoo_mlp_set_gate",
     "otoo_mlp_get_params", "otoo_mlp_save", "otoo_mlp_load", "otoo_mlp_forward", "otoo_mlp_infer",
     "otoo_mlp_train_samples", "otoo_mlp_sample_weights", "otoo_mlp_backward", "otoo_mlp_train_step",
@@ -139,6 +140,7 @@ def lib():
         "otoo_get_tuning": ([P, ctypes.POINTER(Tuning)], I32),
         "otoo_set_scratch_limit": ([P, I64], I32),
         "otoo_force_plan": ([I32, I32, I64, I32, I32, I32, ctypes.POINTER(I64)], I32),
+        "otoo_group_layout": ([I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)], I32),
         "otoo_scratch_generation": ([P, ctypes.POINTER(I64)], I32),
         "otoo_force": ([P, I32, P, P, I32, P, I64, P, P, I32, P, I32, F, P, P, P], I32),
         "otoo_force_noalloc": ([P, I32, P, P, I32, P, I64, P, P, I32, P, I32, F, P, P, P], I32),
@@ -412,6 +414,16 @@ def force_plan(n: int, n_groups: int, n_entries: int, n_cells: int, chunk: int, 
                                ctypes.byref(b))
     _check(rc, "otoo_force_plan")
     return b.value
+
+
+def group_layout(ng: int, tile: int):
+    """The force kernel's lanes for a group of ng targets at tile depth
+    ``tile`` (host only): (False, [256 // ng, 0, 0, 0]) for slices across the
+    workgroup, or (True, [part sizes of the four waves])."""
+    wp = ctypes.c_int32()
+    parts = (ctypes.c_int32 * 4)()
+    _check(lib().otoo_group_layout(int(ng), int(tile), ctypes.byref(wp), parts), "otoo_group_layout")
+    return bool(wp.value), list(parts)
 
 
 class CapturedGraph:

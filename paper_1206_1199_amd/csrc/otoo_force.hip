@@ -1157,6 +1157,17 @@ int otoo_force_plan(int32_t n, int32_t n_groups, int64_t n_entries, int32_t n_ce
     return OTOO_OK;
 }
 
+int otoo_group_layout(int32_t ng, int32_t tile, int32_t* wave_parts, int32_t* parts) {
+    if (ng < 1 || ng > kBlock || (tile != 256 && tile != 512 && tile != 1024) || !wave_parts || !parts)
+        return OTOO_EINVAL;
+    static constexpr LayoutTable kHostLayouts = make_layouts();   // the table the kernel reads
+    const GroupLayout& e = kHostLayouts.e[ng];
+    const int bit = tile == 256 ? 1 : (tile == 512 ? 2 : 4);
+    *wave_parts = (e.parts & bit) ? 1 : 0;
+    for (int j = 0; j < 4; j++) parts[j] = *wave_parts ? e.n[j] : (j == 0 ? e.S : 0);
+    return OTOO_OK;
+}
+
 int otoo_scratch_generation(const otoo_ctx* c, int64_t* gen) {
     if (!c || !gen) return OTOO_EINVAL;
     *gen = c->scratch_gen;

@@ -225,3 +225,22 @@ def test_small_division_through_the_reciprocal():
     for r in (r0, np.nextafter(r0, np.float32(0)), np.nextafter(r0, np.float32(1))):
         q = np.floor(((x + np.float32(0.5)).astype(np.float32) * r).astype(np.float32)).astype(np.int64)
         assert np.array_equal(q, want)
+
+
+@pytest.mark.parametrize("tile", [256, 512, 1024])
+def test_library_layout_matches_the_model(tile):
+    """The layout table compiled into the force kernel (read back through
+    otoo_group_layout, host only) gives every group size the layout of the
+    model above: the same wave parts, or the same workgroup-wide slices."""
+    for ng in range(1, 257):
+        wave_parts, parts = otoo.group_layout(ng, tile)
+        model = emu.lane_parts(ng, tile)
+        model_parts = len(model) > 1 or (emu.BLOCK % ng != 0 and model[0][1] != emu.BLOCK // ng)
+        assert wave_parts == model_parts, ng
+        if wave_parts:
+            assert parts == [n for _, n in emu.wave_parts(ng)], ng
+        else:
+            assert parts == [emu.BLOCK // ng, 0, 0, 0], ng
+    for bad in ((0, tile), (257, tile), (64, 300)):
+        with pytest.raises(otoo.OtooError):
+            otoo.group_layout(*bad)
