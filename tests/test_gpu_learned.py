@@ -542,6 +542,27 @@ def test_learned_plummer_1m(env, trained, theta, g_max):
             med_bar=2e-5, p99_bar=2e-4, label=f"learned Plummer 2^20 theta {theta} g_max {g_max}")
 
 
+@pytest.mark.parametrize("theta,g_max,ratio", [(0.85, 64, 0.6), (0.9, 128, 0.5)])
+def test_learned_plummer_1m_near(env, trained_near, theta, g_max, ratio):
+    """The near-cell learned step on the held-out Plummer sphere 2^20 in the
+    settings the benchmark compares: at ratio 0.6 and groups of 64 (44 pairs
+    per group, too few in all to fill the chip one group at a time, so the
+    pass takes the pair-parallel chunks) and at ratio 0.5 with groups of 128
+    (one group at a time); 2048 targets of 256 sampled groups against the
+    oracle with the network's tensors on the near cells."""
+    ctx = env["ctx"]
+    net = learned.Network(ctx)
+    net.set_params(trained_near["params"])
+    pos, m = synth.plummer(1 << 20, seed=3)
+    tree = otoo.Tree(pos, m, n_crit=16)
+    lists, pos32, mass32, cm, acc, pot = _corrected_on(ctx, tree, theta, g_max, 0.005, "mlp", net=net,
+                                                       near_ratio=ratio)
+    assert int(lists.pair_off[-1]) == int(np.asarray(lists.n_near).sum()) > 0
+    groups, tgt = sample_groups(lists, 256, 8, seed=14)
+    compare(acc, pot, pos32, mass32, lists, cm, 0.005, tgt, groups, "mlp", trained_near["params"], 0.0,
+            med_bar=2e-5, p99_bar=2e-4, label=f"learned near cells Plummer 2^20 theta {theta} ratio {ratio}")
+
+
 def test_learned_cube_16m_captured(env, trained):
     """The largest single-GPU case: the GRF cube of 256^3 particles (seed 4,
     eps 1e-3, opening angle 0.7, groups of 32), learned correction and force
